@@ -1,0 +1,194 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+This module only *prepares inputs*: closed surface meshes shaped like the
+paper's scatterers (a sphere, Sec. 3.1; the paper's optimised shapes are
+replaced by a cube), random densities, incidence directions, admittances and
+observation points.  It contains none of the boundary-element arithmetic
+(no kernels, quadrature, tree or solver) so that the oracle and the HIP
+library stay independent of each other.
+
+Conventions
+-----------
+* Meshes are ``(V, T)``: ``V`` float64 ``(n_vert, 3)``, ``T`` int32
+  ``(n_tri, 3)``, triangles ordered counter-clockwise when seen from the
+  fluid, i.e. the right-hand normal points out of the scatterer, matching the
+  paper's normal that is exterior with respect to the scatterer (Sec. 2.1).
+* Random numbers come from ``numpy.random.default_rng(seed)`` (PCG64) and are
+  drawn in a fixed order: densities (real block, then imaginary block), then
+  directions, then admittances, then observation points, then element picks.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "icosphere", "cube_surface", "complex_normal", "unit_directions",
+    "Workload", "workload", "WORKLOADS",
+]
+
+
+# --------------------------------------------------------------------------
+# meshes
+# --------------------------------------------------------------------------
+def _orient_outward(V: np.ndarray, T: np.ndarray, inside: np.ndarray) -> np.ndarray:
+    """Flip triangles whose right-hand normal points towards ``inside``."""
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    nrm = np.cross(b - a, c - a)
+    cen = (a + b + c) / 3.0
+    flip = np.einsum("ij,ij->i", nrm, cen - inside) < 0
+    T = T.copy()
+    T[flip, 1], T[flip, 2] = T[flip, 2].copy(), T[flip, 1].copy()
+    return T
+
+
+def _icosahedron():
+    g = (1.0 + math.sqrt(5.0)) / 2.0
+    pts = []
+    for s1 in (-1.0, 1.0):
+        for s2 in (-1.0, 1.0):
+            pts.append((s1, s2 * g, 0.0))
+            pts.append((0.0, s1, s2 * g))
+            pts.append((s2 * g, 0.0, s1))
+    V = np.array(pts, dtype=np.float64)
+    # faces = triples of mutually adjacent vertices (edge length 2 before scaling)
+    d2 = ((V[:, None, :] - V[None, :, :]) ** 2).sum(-1)
+    adj = np.abs(d2 - 4.0) < 1e-9
+    faces = []
+    n = len(V)
+    for i in range(n):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            for k in range(j + 1, n):
+                if adj[i, k] and adj[j, k]:
+                    faces.append((i, j, k))
+    assert len(faces) == 20
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    T = np.array(faces, dtype=np.int64)
+    return V, T
+
+
+def icosphere(level: int, radius: float = 1.0):
+    """Unit icosahedron refined ``level`` times by 4-way midpoint splits,
+    new vertices pushed to the sphere.  ``n_tri = 20 * 4**level``."""
+    V, T = _icosahedron()
+    T = _orient_outward(V, T, np.zeros(3))
+    verts = [tuple(v) for v in V]
+    for _ in range(level):
+        cache: dict = {}
+
+        def mid(i, j):
+            key = (i, j) if i < j else (j, i)
+            if key not in cache:
+                m = np.add(verts[i], verts[j]) * 0.5
+                m = m / np.linalg.norm(m)
+                cache[key] = len(verts)
+                verts.append(tuple(m))
+            return cache[key]
+
+        newT = []
+        for a, b, c in T:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            newT += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        T = np.array(newT, dtype=np.int64)
+    V = np.array(verts, dtype=np.float64) * radius
+    return V, T.astype(np.int32)
+
+
+def cube_surface(n: int = 64, half: float = 1.0):
+    """Surface of the cube ``[-half, half]^3``; each face is an ``n x n`` grid
+    of squares, each split along its (i,j)->(i+1,j+1) diagonal.
+    ``n_tri = 12 n^2``, ``n_vert = 6 n^2 + 2``."""
+    index: dict = {}
+    verts = []
+
+    def vid(ijk):
+        if ijk not in index:
+            index[ijk] = len(verts)
+            verts.append(ijk)
+        return index[ijk]
+
+    tris = []
+    for axis in range(3):
+        for side in (0, n):
+            u_ax, v_ax = [a for a in range(3) if a != axis]
+            for i in range(n):
+                for j in range(n):
+                    def P(ii, jj):
+                        c = [0, 0, 0]
+                        c[axis] = side
+                        c[u_ax] = ii
+                        c[v_ax] = jj
+                        return vid(tuple(c))
+                    p00, p10, p11, p01 = P(i, j), P(i + 1, j), P(i + 1, j + 1), P(i, j + 1)
+                    tris.append((p00, p10, p11))
+                    tris.append((p00, p11, p01))
+    V = (np.array(verts, dtype=np.float64) * (2.0 * half / n)) - half
+    T = np.array(tris, dtype=np.int64)
+    T = _orient_outward(V, T, np.zeros(3))
+    return V, T.astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# random inputs
+# --------------------------------------------------------------------------
+def complex_normal(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Complex vector with Re and Im ~ N(0,1); real block drawn first."""
+    re = rng.standard_normal(n)
+    im = rng.standard_normal(n)
+    return re + 1j * im
+
+
+def unit_directions(rng: np.random.Generator, m: int) -> np.ndarray:
+    """``m`` directions uniform on the unit sphere (normalised Gaussians)."""
+    g = rng.standard_normal((m, 3))
+    return g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def admittance(rng: np.random.Generator, n: int, hi: float = 0.5) -> np.ndarray:
+    """Per-element complex admittance, Re and Im independently U[0, hi]."""
+    re = rng.uniform(0.0, hi, n)
+    im = rng.uniform(0.0, hi, n)
+    return re + 1j * im
+
+
+# --------------------------------------------------------------------------
+# the five workloads (sizes, wavenumbers and seeds)
+# --------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    mesh: str              # "ico<level>" or "cube<n>"
+    k: float
+    seed: int
+    order: int | None = None     # fixed expansion order, None = chosen from tolerance
+    leaf_cap: int = 32
+    tol: float = 1e-6
+    extra: dict = field(default_factory=dict)
+
+    def mesh_arrays(self):
+        if self.mesh.startswith("ico"):
+            return icosphere(int(self.mesh[3:]))
+        if self.mesh.startswith("cube"):
+            return cube_surface(int(self.mesh[4:]))
+        raise ValueError(self.mesh)
+
+    @property
+    def alpha(self) -> complex:
+        """Burton-Miller coupling i/k."""
+        return 1j / self.k
+
+
+WORKLOADS = {
+    "sphere1280_k1": Workload("sphere1280_k1", "ico3", 1.0, 1, order=8, leaf_cap=32),
+    "sphere20480_k4": Workload("sphere20480_k4", "ico5", 4.0, 2),
+    "sphere81920_k8": Workload("sphere81920_k8", "ico6", 8.0, 3),
+    "cube49152_k6": Workload("cube49152_k6", "cube64", 6.0, 4),
+}
+
+
+def workload(name: str) -> Workload:
+    return WORKLOADS[name]
