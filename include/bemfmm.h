@@ -1,0 +1,214 @@
+/*
+ * bemfmm.h - C ABI of the MI355X (gfx950) FMM-accelerated Burton-Miller
+ * collocation boundary-element library.
+ *
+ * What is computed
+ * ----------------
+ * The paper (Isakari, Kondo, Takahashi, Matsumoto, "A level-set-based
+ * topology optimisation for acoustic-elastic coupled problems with a fast
+ * BEM-FEM solver") solves the boundary integral equation of Sec. 2.3
+ * (Eq. danseibie2) for the 3-D Helmholtz kernel G = exp(ik|x|)/(4 pi |x|),
+ * discretised with piecewise-constant triangles and collocation; its acoustic
+ * block is I/2 - D (Eq. renritupu), applied by an FMM inside every GMRES
+ * iteration (solver step 2(c), Sec. 2.3).  This library applies the
+ * Burton-Miller combination of that equation with its normal derivative,
+ *
+ *     y = (I/2 - K - alpha H) p + (S + alpha K' + (alpha/2) I) q,
+ *
+ * where, for element j and collocation point x_i (centroid of element i),
+ * S_ij = int_j G, K_ij = int_j dG/dn_y, K'_ij = int_j dG/dn_x and
+ * H_ij = finite-part int_j d2G/dn_x dn_y; n is the unit normal pointing into
+ * the fluid.  alpha = 0 gives the paper's own operator I/2 - D (D = K) with
+ * S applied to q = dp/dn.  Regular pairs use the 3-point degree-2 triangle
+ * rule; pairs with |x_i - c_j| < eta * (longest edge of j) are integrated
+ * accurately; self terms use closed edge reductions.
+ *
+ * Conventions
+ * -----------
+ * - Vectors are DEVICE pointers to contiguous complex128 (interleaved re, im,
+ *   the PyTorch layout), in the caller's element order; nrhs columns are
+ *   stored one after the other with stride n_tri.  The caller owns them.
+ * - Mesh arrays in bem_problem are HOST pointers, copied at plan creation.
+ * - Calls are ordered on the given HIP stream (hipStream_t passed as void*,
+ *   NULL = the default stream).  Matvecs are asynchronous; solves
+ *   synchronise before returning.
+ * - Errors: every call returns a bem_status; on failure bem_last_error()
+ *   returns a thread-local message.  Invalid input is rejected before any
+ *   kernel launch.  No call allocates on behalf of the caller except
+ *   bem_plan_create.
+ * - A plan may hold several problems (meshes / wavenumbers); `prob` selects
+ *   one.  The tree, lists, near-field coefficients and translation
+ *   operators of a problem are built once and reused by forward and adjoint
+ *   products and solves (the paper reuses them between its state and
+ *   adjoint solves, Sec. 2.5, steps 6-7).
+ * - Thread safety: calls on the same plan must not overlap.
+ */
+#ifndef BEMFMM_H
+#define BEMFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bem_plan bem_plan; /* opaque */
+
+typedef enum {
+  BEM_OK = 0,
+  BEM_E_INVALID = -1,   /* bad argument or mesh; nothing was launched        */
+  BEM_E_OOM = -2,       /* device allocation failed                          */
+  BEM_E_HIP = -3,       /* a HIP runtime call failed                         */
+  BEM_E_NOCONV = -4,    /* GMRES hit max_iter; x holds the last iterate      */
+  BEM_E_BREAKDOWN = -5, /* GMRES breakdown without convergence               */
+  BEM_E_NAN = -6        /* NaN/Inf met in a solve                            */
+} bem_status;
+
+/* Arithmetic of the far field, near field and their corrections.  Vectors
+ * at the boundary are complex128 in both cases; the self (diagonal) terms
+ * and the I/2, alpha/2 identities are always applied in float64. */
+typedef enum { BEM_C128 = 0, BEM_C64 = 1 } bem_prec;
+
+typedef struct {
+  const double* vert;  /* host, n_vert x 3, row-major                       */
+  int64_t n_vert;
+  const int32_t* tri;  /* host, n_tri x 3, counter-clockwise seen from the
+                          fluid (right-hand normal into the fluid)         */
+  int64_t n_tri;
+  double k;            /* wavenumber, > 0                                   */
+  double alpha_re;     /* Burton-Miller coupling alpha (i/k typical; 0 =    */
+  double alpha_im;     /*   the paper's conventional equation)              */
+  double near_eta;     /* near-pair radius factor eta (<= 0 -> 2)           */
+  int32_t leaf_cap;    /* uniform leaf level = smallest level >= 2 whose
+                          fullest leaf holds <= leaf_cap elements (<=0->64) */
+  int32_t leaf_level;  /* > 0 forces the leaf level instead                 */
+  int32_t order64;     /* expansion order of the float64 far field, or <=0:
+                          chosen per level from the wavenumber             */
+  int32_t order32;     /* same for the float32 far field                   */
+} bem_problem;
+
+typedef struct {
+  double tol;          /* relative residual ||b - A x|| / ||b|| target       */
+  int32_t restart;     /* GMRES restart length m (<= 0 -> 50)                */
+  int32_t max_iter;    /* total Arnoldi steps (<= 0 -> 2000)                 */
+  int32_t mode;        /* 0: float64 operator throughout;
+                          1: mixed precision - inner GMRES on the float32
+                             operator, outer residuals and corrections in
+                             float64 (iterative refinement)                 */
+  double inner_tol;    /* mode 1: relative tolerance of each inner solve
+                          (<= 0 -> 1e-4)                                    */
+  int32_t use_x0;      /* nonzero: x holds the initial guess on entry       */
+} bem_gmres_opts;
+
+typedef struct {
+  int32_t iterations;  /* Arnoldi steps (all precisions)                     */
+  int32_t matvec64;    /* float64 operator applications                     */
+  int32_t matvec32;    /* float32 operator applications                     */
+  int32_t restarts;    /* GMRES restarts (mode 0) / refinement steps (mode 1)*/
+  double resid;        /* final true relative residual (float64 operator)   */
+  int32_t converged;
+  int32_t n_hist;      /* entries written to hist                           */
+  double hist[512];    /* residual estimates per Arnoldi step (truncated)   */
+} bem_gmres_info;
+
+typedef struct {
+  int64_t n_tri;
+  int32_t leaf_level;
+  int32_t n_leaves;
+  int64_t n_near;          /* near pairs (off-diagonal accurate entries)     */
+  int64_t n_p2p_pairs;     /* (target, source element) pairs in the U lists */
+  int64_t n_m2l[22];       /* multipole-to-local pairs per level             */
+  int32_t order64[22];     /* expansion order per level                      */
+  int32_t order32[22];
+  double box_size[22];
+  int64_t device_bytes;    /* device memory held by this problem             */
+} bem_plan_stats;
+
+/* Build a plan for n_probs problems.  Uploads the meshes and runs, on the
+ * device: element geometry and quadrature points, Morton keys and a stable
+ * radix sort, the uniform-depth octree and its U/V lists, the near-pair
+ * list with accurate near-singular integrals and self terms, and the
+ * translation, multipole and local operators in float64 and float32.
+ * Rejects NULL pointers, n_tri < 1, indices out of range, non-finite
+ * coordinates, zero-area triangles, k <= 0 (BEM_E_INVALID). */
+int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_plan** out);
+int bem_plan_destroy(bem_plan* plan);
+int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* stats);
+
+/* y = (I/2 - K - alpha H) p + (S + alpha K' + (alpha/2) I) q  (Burton-Miller
+ * combination of the boundary integral equation of Sec. 2.3).  p or q may
+ * be NULL (treated as zero); y must not alias p or q.  nrhs >= 1 columns. */
+int bem_fmm_matvec(bem_plan* plan, int prob, int prec, const void* p, const void* q,
+                   void* y, int nrhs, void* stream);
+
+/* Exact algebraic adjoint of bem_fmm_matvec (same tree, near field and
+ * operators, conjugate-transposed):  u = (I/2 - K - alpha H)^H y,
+ * w = (S + alpha K' + (alpha/2) I)^H y.  u or w may be NULL. */
+int bem_fmm_matvec_adjoint(bem_plan* plan, int prob, int prec, const void* y, void* u,
+                           void* w, int nrhs, void* stream);
+
+/* Solve A(sigma) x = b by restarted GMRES (the paper's iterative solver,
+ * Sec. 2.3 step 2 and Sec. 3), with A(sigma) = (I/2 - K - alpha H) +
+ * (S + alpha K' + (alpha/2) I) diag(sigma).  sigma (device complex128,
+ * n_tri) may be NULL (rigid scatterer, q = 0).  adjoint != 0 solves
+ * A(sigma)^H x = b instead.  x0 = 0 unless opts->use_x0.  Exit on the true
+ * relative residual recomputed with the float64 operator.  Synchronises. */
+int bem_gmres_solve(bem_plan* plan, int prob, const void* sigma, int adjoint, const void* b,
+                    void* x, const bem_gmres_opts* opts, bem_gmres_info* info, void* stream);
+
+/* Right-hand side of a plane wave exp(i k d.x) of unit amplitude:
+ * b_i = p_inc(x_i) + alpha dp_inc/dn(x_i) (device complex128 out). */
+int bem_plane_wave_rhs(bem_plan* plan, int prob, const double* dir3, void* b, void* stream);
+
+/* Field at exterior points by the integral representation (solver step 5,
+ * Sec. 2.3): out_m = inc_m + sum_j [int_j dG/dn_y p_j - int_j G q_j] with the
+ * 3-point rule, inc_m = exp(i k d.x_m) if dir3 != NULL else 0.  pts: device
+ * float64 n_pts x 3; p, q, out device complex128 (q may be NULL). */
+int bem_eval_field(bem_plan* plan, int prob, const void* p, const void* q, const double* pts,
+                   int n_pts, const double* dir3, void* out, void* stream);
+
+/* Adjoint of bem_eval_field's boundary part: rp_j = sum_m conj(int_j dG/dn_y
+ * (x_m)) c_m, rq_j = -sum_m conj(int_j G(x_m)) c_m.  rq may be NULL. */
+int bem_eval_field_adjoint(bem_plan* plan, int prob, const double* pts, int n_pts,
+                           const void* c, void* rp, void* rq, void* stream);
+
+/* Objective J = sum_m |p(x_m)|^2 of the plane-wave problem with admittance
+ * boundary q = sigma p, sigma = -i k beta (beta device complex128, n_tri),
+ * and its gradient grad_e = dJ/dRe(beta_e) + i dJ/dIm(beta_e) by the discrete
+ * adjoint: one forward solve, one adjoint solve (conjugate-transposed FMM
+ * operator), one adjoint product.  grad may be NULL (objective only).
+ * p_out (may be NULL) receives the boundary pressure.  Synchronises. */
+int bem_objective_grad(bem_plan* plan, int prob, const void* beta, const double* dir3,
+                       const double* pts, int n_pts, const bem_gmres_opts* opts, double* J,
+                       void* grad, void* p_out, bem_gmres_info* info_fwd,
+                       bem_gmres_info* info_adj, void* stream);
+
+/* Morton keys (uint64, caller order) and the sorted permutation (int32:
+ * sorted position -> caller index) of a problem, copied to device buffers
+ * the caller owns (n_tri entries each; either may be NULL). */
+int bem_tree_export(bem_plan* plan, int prob, void* keys, void* perm, void* stream);
+
+/* Leaf boxes: box keys (uint64, level-L keys) and [start, end) ranges in
+ * sorted order; device buffers of n_leaves entries (any may be NULL). */
+int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, void* end,
+                      void* stream);
+
+/* Stage timing with HIP events recorded on the call's stream.  After
+ * bem_profile_start, every product records an event pair around each stage;
+ * bem_profile_stop synchronises and returns, per slot, the summed
+ * milliseconds and the number of timed stage executions.  Slot =
+ * stage + 8 * (float32 ? 1 : 0) + 16 * (adjoint ? 1 : 0), stage: 0 gather,
+ * 1 P2P, 2 P2M (adjoint: L2P^H), 3 M2M, 4 M2L, 5 L2L, 6 finish (L2P, near
+ * corrections, diagonal, scatter).  ms and calls hold BEM_PROFILE_SLOTS
+ * entries (host). */
+#define BEM_PROFILE_SLOTS 32
+int bem_profile_start(bem_plan* plan, int prob);
+int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls);
+
+const char* bem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEMFMM_H */

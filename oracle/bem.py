@@ -208,6 +208,9 @@ def point_triangle_distance(x, A, B, C):
     return np.where(inside, np.abs(h), edge)
 
 
+NEAR_WORKERS = None   # process count for near integrals (None: all cores, max 16)
+
+
 def _near_chunk(args):
     return near_integrals(*args[:7], tol=args[7])
 
@@ -217,7 +220,7 @@ def near_integrals_parallel(x, nx, A, B, C, ny, k, tol=1e-13, workers=None, chun
     pair is integrated independently)."""
     M = len(x)
     if workers is None:
-        workers = min(len(os.sched_getaffinity(0)), 16)
+        workers = NEAR_WORKERS or min(len(os.sched_getaffinity(0)), 16)
     if M <= chunk or workers <= 1:
         return near_integrals(x, nx, A, B, C, ny, k, tol=tol)
     jobs = [(x[s:s + chunk], nx[s:s + chunk], A[s:s + chunk], B[s:s + chunk], C[s:s + chunk],

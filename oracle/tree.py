@@ -15,7 +15,10 @@ reading the GPU path must reproduce bit for bit:
 * elements sorted stably by (key, original index);
 * the box of a point at level l is key >> 3 (21 - l); all leaves sit at one
   level L (uniform depth), chosen as the smallest L >= 2 whose fullest leaf
-  holds at most ``leaf_cap`` elements (at most level 21);
+  holds at most ``leaf_cap`` elements (at most level 21), but no finer than
+  the largest level l >= 2 whose box side h_l = 2 R0 / 2^l exceeds
+  eta * (longest element edge), so that near pairs lie in adjacent leaves
+  whenever the mesh allows it;
 * lists, per level l >= 2, over non-empty boxes only:
   colleagues(b)  = boxes at level l with max_a |i_a(b) - i_a(c)| <= 1;
   V(b)           = children of colleagues(parent(b)) that are not
@@ -95,12 +98,20 @@ def choose_leaf_level(sorted_keys, leaf_cap: int) -> int:
 class Tree:
     """Uniform-depth octree over Morton-sorted elements."""
 
-    def __init__(self, cen: np.ndarray, leaf_cap: int = 32, leaf_level: int | None = None):
+    def __init__(self, cen: np.ndarray, leaf_cap: int = 32, leaf_level: int | None = None,
+                 ell_max: float | None = None, eta: float = 2.0):
         self.keys = morton_keys(cen)
         self.perm = sort_order(self.keys)
         sk = [self.keys[i] for i in self.perm]
         self.sorted_keys = sk
-        self.L = choose_leaf_level(sk, leaf_cap) if leaf_level is None else leaf_level
+        self.L = choose_leaf_level(sk, leaf_cap) if leaf_level is None else max(2, leaf_level)
+        if ell_max is not None:
+            _, _, R0 = bounding_cube(cen)
+            L_near = 2
+            for l in range(2, NBITS + 1):
+                if 2.0 * R0 / float(1 << l) > eta * ell_max:
+                    L_near = l
+            self.L = min(self.L, L_near)
         # boxes per level: sorted unique box keys
         self.boxes = {}
         for l in range(0, self.L + 1):

@@ -1,0 +1,371 @@
+"""Python binding of libbemfmm (the MI355X FMM Burton-Miller BEM library).
+
+Argument marshalling only: every numerical step runs in the HIP kernels of
+``_lib/libbemfmm.so`` (built by ``paper_1606_02383_amd.build``).  PyTorch
+supplies device memory and the current HIP stream.  Importing this module
+does not touch the GPU; the first call loads the library and raises if it is
+missing or was built without the GPU code.
+
+Vectors are complex128 CUDA (HIP) tensors of length n_tri in the caller's
+element order; the library reads and writes them in place on the current
+stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = ["Plan", "Problem", "GmresOptions", "ObjectiveJ", "load_library", "LIB_PATH",
+           "BEM_C128", "BEM_C64"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libbemfmm.so")
+BEM_C128 = 0
+BEM_C64 = 1
+
+STATUS = {0: "BEM_OK", -1: "BEM_E_INVALID", -2: "BEM_E_OOM", -3: "BEM_E_HIP",
+          -4: "BEM_E_NOCONV", -5: "BEM_E_BREAKDOWN", -6: "BEM_E_NAN"}
+
+EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm_matvec",
+           "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_plane_wave_rhs", "bem_eval_field",
+           "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
+           "bem_leaves_export", "bem_profile_start", "bem_profile_stop", "bem_last_error"]
+
+STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish"]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("vert", ctypes.POINTER(ctypes.c_double)), ("n_vert", ctypes.c_int64),
+                ("tri", ctypes.POINTER(ctypes.c_int32)), ("n_tri", ctypes.c_int64),
+                ("k", ctypes.c_double), ("alpha_re", ctypes.c_double),
+                ("alpha_im", ctypes.c_double), ("near_eta", ctypes.c_double),
+                ("leaf_cap", ctypes.c_int32), ("leaf_level", ctypes.c_int32),
+                ("order64", ctypes.c_int32), ("order32", ctypes.c_int32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("use_x0", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("matvec64", ctypes.c_int32),
+                ("matvec32", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("resid", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("n_hist", ctypes.c_int32), ("hist", ctypes.c_double * 512)]
+
+    def as_dict(self):
+        return dict(iterations=self.iterations, matvec64=self.matvec64, matvec32=self.matvec32,
+                    restarts=self.restarts, resid=self.resid, converged=bool(self.converged),
+                    hist=list(self.hist[:self.n_hist]))
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_tri", ctypes.c_int64), ("leaf_level", ctypes.c_int32),
+                ("n_leaves", ctypes.c_int32), ("n_near", ctypes.c_int64),
+                ("n_p2p_pairs", ctypes.c_int64), ("n_m2l", ctypes.c_int64 * 22),
+                ("order64", ctypes.c_int32 * 22), ("order32", ctypes.c_int32 * 22),
+                ("box_size", ctypes.c_double * 22), ("device_bytes", ctypes.c_int64)]
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbemfmm.so (after torch, so that one HIP runtime is shared)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    import torch  # noqa: F401  (loads the HIP runtime first)
+    if not os.path.exists(path):
+        raise RuntimeError(f"libbemfmm.so not found at {path}; run paper_1606_02383_amd.build")
+    lib = ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    lib.bem_plan_create.argtypes = [ctypes.POINTER(_Problem), i32, vp, ctypes.POINTER(vp)]
+    lib.bem_plan_destroy.argtypes = [vp]
+    lib.bem_plan_get_stats.argtypes = [vp, i32, ctypes.POINTER(_Stats)]
+    lib.bem_fmm_matvec.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp]
+    lib.bem_fmm_matvec_adjoint.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp]
+    lib.bem_gmres_solve.argtypes = [vp, i32, vp, i32, vp, vp, ctypes.POINTER(_Opts),
+                                    ctypes.POINTER(_Info), vp]
+    lib.bem_plane_wave_rhs.argtypes = [vp, i32, dp, vp, vp]
+    lib.bem_eval_field.argtypes = [vp, i32, vp, vp, vp, i32, dp, vp, vp]
+    lib.bem_eval_field_adjoint.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
+    lib.bem_objective_grad.argtypes = [vp, i32, vp, dp, dp, i32, ctypes.POINTER(_Opts), dp, vp,
+                                       vp, ctypes.POINTER(_Info), ctypes.POINTER(_Info), vp]
+    lib.bem_tree_export.argtypes = [vp, i32, vp, vp, vp]
+    lib.bem_leaves_export.argtypes = [vp, i32, vp, vp, vp, vp]
+    lib.bem_profile_start.argtypes = [vp, i32]
+    lib.bem_profile_stop.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int32)]
+    lib.bem_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "bem_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+class BemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != 0:
+        raise BemError(code, _LIB.bem_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Problem:
+    """One mesh + wavenumber.  V (n_vert, 3) float64, T (n_tri, 3) int32,
+    triangles counter-clockwise seen from the fluid."""
+    V: np.ndarray
+    T: np.ndarray
+    k: float
+    alpha: complex | None = None     # default i/k
+    near_eta: float = 2.0
+    leaf_cap: int = 64
+    leaf_level: int = 0
+    order64: int = 0
+    order32: int = 0
+
+
+@dataclass
+class GmresOptions:
+    tol: float = 1e-6
+    restart: int = 50
+    max_iter: int = 2000
+    mode: int = 0              # 0 float64, 1 float32 inner + float64 refinement
+    inner_tol: float = 1e-4
+    use_x0: bool = False
+
+    def c(self):
+        return _Opts(self.tol, self.restart, self.max_iter, self.mode, self.inner_tol,
+                     int(self.use_x0))
+
+
+class Plan:
+    """A built plan (tree, lists, near field, operators) for one or more problems."""
+
+    def __init__(self, problems):
+        import torch
+        lib = load_library()
+        if isinstance(problems, Problem):
+            problems = [problems]
+        self._keep = []
+        arr = (_Problem * len(problems))()
+        for i, p in enumerate(problems):
+            V = np.ascontiguousarray(p.V, dtype=np.float64)
+            T = np.ascontiguousarray(p.T, dtype=np.int32)
+            self._keep += [V, T]
+            a = (1j / p.k) if p.alpha is None else complex(p.alpha)
+            arr[i] = _Problem(V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), V.shape[0],
+                              T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), T.shape[0],
+                              float(p.k), a.real, a.imag, float(p.near_eta), int(p.leaf_cap),
+                              int(p.leaf_level), int(p.order64), int(p.order32))
+        self.problems = list(problems)
+        self.n = [int(np.asarray(p.T).shape[0]) for p in problems]
+        h = ctypes.c_void_p()
+        _check(lib.bem_plan_create(arr, len(problems), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _LIB.bem_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- helpers
+    def _vec(self, prob, nrhs=1):
+        import torch
+        shape = (self.n[prob],) if nrhs == 1 else (nrhs, self.n[prob])
+        return torch.empty(shape, dtype=torch.complex128, device=self.device)
+
+    def _in(self, t, prob):
+        import torch
+        if t is None:
+            return None
+        t = torch.as_tensor(t).to(device=self.device, dtype=torch.complex128).contiguous()
+        if t.shape[-1] != self.n[prob]:
+            raise ValueError(f"vector length {t.shape[-1]} != n_tri {self.n[prob]}")
+        return t
+
+    def stats(self, prob=0):
+        st = _Stats()
+        _check(_LIB.bem_plan_get_stats(self._h, prob, ctypes.byref(st)))
+        L = st.leaf_level
+        return dict(n_tri=st.n_tri, leaf_level=L, n_leaves=st.n_leaves, n_near=st.n_near,
+                    n_p2p_pairs=st.n_p2p_pairs, n_m2l=list(st.n_m2l[:L + 1]),
+                    order64=list(st.order64[:L + 1]), order32=list(st.order32[:L + 1]),
+                    box_size=list(st.box_size[:L + 1]), device_bytes=st.device_bytes)
+
+    # ---- products
+    def matvec(self, p, q=None, prec=BEM_C128, prob=0, out=None):
+        """y = (I/2 - K - alpha H) p + (S + alpha K' + alpha/2 I) q."""
+        p, q = self._in(p, prob), self._in(q, prob)
+        nrhs = 1 if p.dim() == 1 else p.shape[0]
+        y = out if out is not None else self._vec(prob, nrhs)
+        _check(_LIB.bem_fmm_matvec(self._h, prob, prec, _ptr(p), _ptr(q), _ptr(y), nrhs, _stream()))
+        return y
+
+    def matvec_adjoint(self, y, prec=BEM_C128, prob=0):
+        """(u, w) = ((I/2 - K - alpha H)^H y, (S + alpha K' + alpha/2 I)^H y)."""
+        y = self._in(y, prob)
+        nrhs = 1 if y.dim() == 1 else y.shape[0]
+        u, w = self._vec(prob, nrhs), self._vec(prob, nrhs)
+        _check(_LIB.bem_fmm_matvec_adjoint(self._h, prob, prec, _ptr(y), _ptr(u), _ptr(w), nrhs,
+                                           _stream()))
+        return u, w
+
+    def solve(self, b, sigma=None, adjoint=False, opts: GmresOptions | None = None, prob=0, x0=None):
+        """GMRES on A(sigma) = (I/2 - K - alpha H) + (S + alpha K' + alpha/2 I) diag(sigma)."""
+        opts = opts or GmresOptions()
+        b, sigma = self._in(b, prob), self._in(sigma, prob)
+        x = self._vec(prob) if x0 is None else self._in(x0, prob).clone()
+        if x0 is not None:
+            opts = GmresOptions(**{**opts.__dict__, "use_x0": True})
+        info = _Info()
+        o = opts.c()
+        code = _LIB.bem_gmres_solve(self._h, prob, _ptr(sigma), int(adjoint), _ptr(b), _ptr(x),
+                                    ctypes.byref(o), ctypes.byref(info), _stream())
+        d = info.as_dict()
+        if code not in (0, -4):
+            _check(code)
+        d["status"] = STATUS.get(code, code)
+        return x, d
+
+    def plane_wave_rhs(self, direction, prob=0):
+        d = np.ascontiguousarray(direction, dtype=np.float64)
+        b = self._vec(prob)
+        _check(_LIB.bem_plane_wave_rhs(self._h, prob, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       _ptr(b), _stream()))
+        return b
+
+    def eval_field(self, p, q, pts, direction=None, prob=0):
+        import torch
+        p, q = self._in(p, prob), self._in(q, prob)
+        pts = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64)).to(self.device)
+        out = torch.empty(pts.shape[0], dtype=torch.complex128, device=self.device)
+        dptr = None
+        if direction is not None:
+            d = np.ascontiguousarray(direction, dtype=np.float64)
+            self._keep.append(d)
+            dptr = d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(_LIB.bem_eval_field(self._h, prob, _ptr(p), _ptr(q),
+                                   ctypes.cast(pts.data_ptr(), ctypes.POINTER(ctypes.c_double)),
+                                   pts.shape[0], dptr, _ptr(out), _stream()))
+        return out
+
+    def eval_field_adjoint(self, pts, c, prob=0):
+        import torch
+        pts = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64)).to(self.device)
+        c = torch.as_tensor(c).to(device=self.device, dtype=torch.complex128).contiguous()
+        rp, rq = self._vec(prob), self._vec(prob)
+        _check(_LIB.bem_eval_field_adjoint(self._h, prob,
+                                           ctypes.cast(pts.data_ptr(), ctypes.POINTER(ctypes.c_double)),
+                                           pts.shape[0], _ptr(c), _ptr(rp), _ptr(rq), _stream()))
+        return rp, rq
+
+    def objective_grad(self, beta, direction, pts, opts: GmresOptions | None = None, prob=0,
+                       need_grad=True):
+        """J = sum |p(x_m)|^2 for the admittance problem and dJ/dRe(beta) + i dJ/dIm(beta)."""
+        opts = opts or GmresOptions(tol=1e-10)
+        beta = self._in(beta, prob)
+        d = np.ascontiguousarray(direction, dtype=np.float64)
+        P = np.ascontiguousarray(pts, dtype=np.float64)
+        J = ctypes.c_double()
+        grad = self._vec(prob) if need_grad else None
+        pout = self._vec(prob)
+        fi, ai = _Info(), _Info()
+        o = opts.c()
+        _check(_LIB.bem_objective_grad(self._h, prob, _ptr(beta),
+                                       d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), P.shape[0],
+                                       ctypes.byref(o), ctypes.byref(J), _ptr(grad), _ptr(pout),
+                                       ctypes.byref(fi), ctypes.byref(ai), _stream()))
+        return J.value, grad, pout, fi.as_dict(), ai.as_dict()
+
+    def profile_start(self, prob=0):
+        _check(_LIB.bem_profile_start(self._h, prob))
+
+    def profile_stop(self, prob=0):
+        """{(stage, 'f64'|'f32', 'fwd'|'adj'): (total ms, executions)}"""
+        ms = (ctypes.c_double * 32)()
+        calls = (ctypes.c_int32 * 32)()
+        _check(_LIB.bem_profile_stop(self._h, prob, ms, calls))
+        out = {}
+        for slot in range(32):
+            if calls[slot]:
+                st = STAGES[slot % 8] if slot % 8 < len(STAGES) else str(slot % 8)
+                key = (st, "f32" if (slot // 8) % 2 else "f64", "adj" if slot >= 16 else "fwd")
+                out[key] = (ms[slot], calls[slot])
+        return out
+
+    def tree_export(self, prob=0):
+        import torch
+        keys = torch.empty(self.n[prob], dtype=torch.int64, device=self.device)
+        perm = torch.empty(self.n[prob], dtype=torch.int32, device=self.device)
+        _check(_LIB.bem_tree_export(self._h, prob, _ptr(keys), _ptr(perm), _stream()))
+        return keys, perm
+
+    def leaves_export(self, prob=0):
+        import torch
+        nl = self.stats(prob)["n_leaves"]
+        keys = torch.empty(nl, dtype=torch.int64, device=self.device)
+        s = torch.empty(nl, dtype=torch.int32, device=self.device)
+        e = torch.empty(nl, dtype=torch.int32, device=self.device)
+        _check(_LIB.bem_leaves_export(self._h, prob, _ptr(keys), _ptr(s), _ptr(e), _stream()))
+        return keys, s, e
+
+
+def _objective_function():
+    import torch
+
+    class ObjectiveJ(torch.autograd.Function):
+        """J(beta) = sum_m |p(x_m)|^2 for the plane-wave admittance problem;
+        backward is the discrete adjoint (conjugate-transposed FMM solve)."""
+
+        @staticmethod
+        def forward(ctx, beta, plan, direction, pts, opts=None, prob=0):
+            J, grad, _, _, _ = plan.objective_grad(beta.detach(), direction, pts, opts, prob)
+            ctx.save_for_backward(grad)
+            return torch.tensor(J, dtype=torch.float64, device=beta.device)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (grad,) = ctx.saved_tensors
+            return gout * grad, None, None, None, None, None
+
+    return ObjectiveJ
+
+
+class _Lazy:
+    def __init__(self):
+        self._cls = None
+
+    def apply(self, *a, **k):
+        if self._cls is None:
+            self._cls = _objective_function()
+        return self._cls.apply(*a, **k)
+
+
+ObjectiveJ = _Lazy()

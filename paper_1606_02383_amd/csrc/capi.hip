@@ -1,0 +1,275 @@
+// C ABI: argument checks, plan lifecycle and dispatch.  Every numerical step
+// runs in the device kernels of the other translation units.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/bemfmm.h"
+#include "plan.h"
+
+namespace bemfmm {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int objective_grad(Problem& P, const c64* beta, const double* dir, const double* pts_host,
+                   int n_pts, const bem_gmres_opts* opts, double* J, c64* grad, c64* p_out,
+                   bem_gmres_info* info_f, bem_gmres_info* info_a, hipStream_t s);
+
+static void destroy_problem(Problem* P) {
+  if (!P) return;
+  release_workspace(*P);
+  for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
+  P->ev_pool.clear();
+  P->arena.release();
+  delete P;
+}
+
+}  // namespace bemfmm
+
+using namespace bemfmm;
+
+struct bem_plan {
+  std::vector<Problem*> probs;
+};
+
+static int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+static Problem* get_prob(bem_plan* plan, int prob) {
+  if (!plan || prob < 0 || prob >= (int)plan->probs.size()) return nullptr;
+  return plan->probs[prob];
+}
+
+extern "C" {
+
+const char* bem_last_error(void) { return g_last_error.c_str(); }
+
+int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_plan** out) {
+  if (!out) return fail(BEM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!probs || n_probs < 1) return fail(BEM_E_INVALID, "no problems given");
+  for (int i = 0; i < n_probs; ++i) {
+    const bem_problem& q = probs[i];
+    if (!q.vert || !q.tri) return fail(BEM_E_INVALID, "NULL mesh array");
+    if (q.n_tri < 1 || q.n_vert < 3) return fail(BEM_E_INVALID, "empty mesh");
+    if (q.n_tri > (int64_t)1 << 28) return fail(BEM_E_INVALID, "mesh too large");
+    if (!(q.k > 0.0) || !std::isfinite(q.k)) return fail(BEM_E_INVALID, "wavenumber must be > 0");
+    if (!std::isfinite(q.alpha_re) || !std::isfinite(q.alpha_im))
+      return fail(BEM_E_INVALID, "non-finite alpha");
+    for (int64_t t = 0; t < 3 * q.n_tri; ++t)
+      if (q.tri[t] < 0 || q.tri[t] >= q.n_vert)
+        return fail(BEM_E_INVALID, "triangle vertex index out of range");
+    for (int64_t t = 0; t < 3 * q.n_vert; ++t)
+      if (!std::isfinite(q.vert[t])) return fail(BEM_E_INVALID, "non-finite vertex coordinate");
+    if (q.order64 > 40 || q.order32 > 40) return fail(BEM_E_INVALID, "expansion order > 40");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  bem_plan* plan = new bem_plan();
+  for (int i = 0; i < n_probs; ++i) {
+    const bem_problem& q = probs[i];
+    Problem* P = new Problem();
+    plan->probs.push_back(P);
+    P->n = q.n_tri;
+    P->k = q.k;
+    P->alpha = mk(q.alpha_re, q.alpha_im);
+    P->eta = q.near_eta > 0 ? q.near_eta : 2.0;
+    P->leaf_cap = q.leaf_cap > 0 ? q.leaf_cap : 64;
+    P->leaf_level_req = q.leaf_level;
+    P->order64_req = q.order64;
+    P->order32_req = q.order32;
+    int r = build_geometry_and_tree(*P, q.vert, q.n_vert, q.tri, s);
+    if (!r) r = build_near_field(*P, s);
+    if (!r) r = build_operators(*P, s);
+    if (r) {
+      for (Problem* pp : plan->probs) destroy_problem(pp);
+      delete plan;
+      return r;
+    }
+  }
+  *out = plan;
+  return BEM_OK;
+}
+
+int bem_plan_destroy(bem_plan* plan) {
+  if (!plan) return BEM_OK;
+  for (Problem* P : plan->probs) destroy_problem(P);
+  delete plan;
+  return BEM_OK;
+}
+
+int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
+  Problem* P = get_prob((bem_plan*)plan, prob);
+  if (!P || !st) return fail(BEM_E_INVALID, "bad plan, problem index or stats pointer");
+  std::memset(st, 0, sizeof(*st));
+  st->n_tri = P->n;
+  st->leaf_level = P->L;
+  st->n_leaves = P->nbox[P->L];
+  st->n_near = P->n_near;
+  st->n_p2p_pairs = P->n_p2p_pairs;
+  for (int l = 0; l <= MAX_LEVEL; ++l) {
+    st->n_m2l[l] = P->n_m2l[l];
+    st->order64[l] = P->f64.order[l];
+    st->order32[l] = P->f32.order[l];
+    st->box_size[l] = P->h[l];
+  }
+  st->device_bytes = P->arena.bytes;
+  return BEM_OK;
+}
+
+int bem_fmm_matvec(bem_plan* plan, int prob, int prec, const void* p, const void* q, void* y,
+                   int nrhs, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  if (!y) return fail(BEM_E_INVALID, "y is NULL");
+  if (y == p || y == q) return fail(BEM_E_INVALID, "y aliases an input");
+  if (nrhs < 1) return fail(BEM_E_INVALID, "nrhs < 1");
+  if (prec != BEM_C128 && prec != BEM_C64) return fail(BEM_E_INVALID, "bad precision");
+  hipStream_t s = (hipStream_t)stream;
+  for (int c = 0; c < nrhs; ++c) {
+    const c64* pc = p ? (const c64*)p + (int64_t)c * P->n : nullptr;
+    const c64* qc = q ? (const c64*)q + (int64_t)c * P->n : nullptr;
+    c64* yc = (c64*)y + (int64_t)c * P->n;
+    int r = (prec == BEM_C128) ? fmm_apply<double>(*P, P->f64, pc, qc, yc, s)
+                               : fmm_apply<float>(*P, P->f32, pc, qc, yc, s);
+    if (r) return r;
+  }
+  return BEM_OK;
+}
+
+int bem_fmm_matvec_adjoint(bem_plan* plan, int prob, int prec, const void* y, void* u, void* w,
+                           int nrhs, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  if (!y) return fail(BEM_E_INVALID, "y is NULL");
+  if (!u && !w) return fail(BEM_E_INVALID, "both outputs NULL");
+  if (u == y || w == y) return fail(BEM_E_INVALID, "output aliases the input");
+  if (nrhs < 1) return fail(BEM_E_INVALID, "nrhs < 1");
+  if (prec != BEM_C128 && prec != BEM_C64) return fail(BEM_E_INVALID, "bad precision");
+  hipStream_t s = (hipStream_t)stream;
+  for (int c = 0; c < nrhs; ++c) {
+    const c64* yc = (const c64*)y + (int64_t)c * P->n;
+    c64* uc = u ? (c64*)u + (int64_t)c * P->n : nullptr;
+    c64* wc = w ? (c64*)w + (int64_t)c * P->n : nullptr;
+    int r = (prec == BEM_C128) ? fmm_apply_adjoint<double>(*P, P->f64, yc, uc, wc, s)
+                               : fmm_apply_adjoint<float>(*P, P->f32, yc, uc, wc, s);
+    if (r) return r;
+  }
+  return BEM_OK;
+}
+
+int bem_gmres_solve(bem_plan* plan, int prob, const void* sigma, int adjoint, const void* b,
+                    void* x, const bem_gmres_opts* opts, bem_gmres_info* info, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  if (!b || !x || !opts) return fail(BEM_E_INVALID, "NULL b, x or opts");
+  if (b == x) return fail(BEM_E_INVALID, "x aliases b");
+  if (!(opts->tol > 0.0)) return fail(BEM_E_INVALID, "tol must be > 0");
+  if (opts->mode != 0 && opts->mode != 1) return fail(BEM_E_INVALID, "bad mode");
+  int m = opts->restart > 0 ? opts->restart : 50;
+  if (m > 500) return fail(BEM_E_INVALID, "restart > 500");
+  int mi = opts->max_iter > 0 ? opts->max_iter : 2000;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return gmres_solve(*P, (const c64*)sigma, adjoint, (const c64*)b, (c64*)x, opts->tol, m, mi,
+                     opts->mode, opts->inner_tol, opts->use_x0, info, (hipStream_t)stream);
+}
+
+int bem_plane_wave_rhs(bem_plan* plan, int prob, const double* dir3, void* b, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !dir3 || !b) return fail(BEM_E_INVALID, "bad arguments");
+  return plane_wave_rhs(*P, dir3, (c64*)b, (hipStream_t)stream);
+}
+
+int bem_eval_field(bem_plan* plan, int prob, const void* p, const void* q, const double* pts,
+                   int n_pts, const double* dir3, void* out, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !p || !pts || !out || n_pts < 0) return fail(BEM_E_INVALID, "bad arguments");
+  return eval_field(*P, (const c64*)p, (const c64*)q, pts, n_pts, dir3, (c64*)out,
+                    (hipStream_t)stream);
+}
+
+int bem_eval_field_adjoint(bem_plan* plan, int prob, const double* pts, int n_pts, const void* c,
+                           void* rp, void* rq, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !pts || !c || !rp || n_pts < 0) return fail(BEM_E_INVALID, "bad arguments");
+  return eval_field_adjoint(*P, pts, n_pts, (const c64*)c, (c64*)rp, (c64*)rq,
+                            (hipStream_t)stream);
+}
+
+int bem_objective_grad(bem_plan* plan, int prob, const void* beta, const double* dir3,
+                       const double* pts, int n_pts, const bem_gmres_opts* opts, double* J,
+                       void* grad, void* p_out, bem_gmres_info* info_fwd,
+                       bem_gmres_info* info_adj, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !beta || !dir3 || !pts || n_pts < 1 || !opts || !J)
+    return fail(BEM_E_INVALID, "bad arguments");
+  if (!(opts->tol > 0.0)) return fail(BEM_E_INVALID, "tol must be > 0");
+  if (info_fwd) std::memset(info_fwd, 0, sizeof(*info_fwd));
+  if (info_adj) std::memset(info_adj, 0, sizeof(*info_adj));
+  return objective_grad(*P, (const c64*)beta, dir3, pts, n_pts, opts, J, (c64*)grad, (c64*)p_out,
+                        info_fwd, info_adj, (hipStream_t)stream);
+}
+
+int bem_tree_export(bem_plan* plan, int prob, void* keys, void* perm, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  hipStream_t s = (hipStream_t)stream;
+  if (keys)
+    BEM_HIP_TRY(hipMemcpyAsync(keys, P->keys_orig, sizeof(uint64_t) * P->n,
+                               hipMemcpyDeviceToDevice, s));
+  if (perm)
+    BEM_HIP_TRY(hipMemcpyAsync(perm, P->perm, sizeof(int) * P->n, hipMemcpyDeviceToDevice, s));
+  return BEM_OK;
+}
+
+int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, void* end,
+                      void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  hipStream_t s = (hipStream_t)stream;
+  int nl = P->nbox[P->L];
+  if (box_keys)
+    BEM_HIP_TRY(hipMemcpyAsync(box_keys, P->box_keys[P->L], sizeof(uint64_t) * nl,
+                               hipMemcpyDeviceToDevice, s));
+  if (start)
+    BEM_HIP_TRY(hipMemcpyAsync(start, P->box_start[P->L], sizeof(int) * nl,
+                               hipMemcpyDeviceToDevice, s));
+  if (end)
+    BEM_HIP_TRY(hipMemcpyAsync(end, P->box_start[P->L] + 1, sizeof(int) * nl,
+                               hipMemcpyDeviceToDevice, s));
+  return BEM_OK;
+}
+
+int bem_profile_start(bem_plan* plan, int prob) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  P->prof_on = true;
+  P->ev_used = 0;
+  P->ev_slot.clear();
+  return BEM_OK;
+}
+
+int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !ms || !calls) return fail(BEM_E_INVALID, "bad arguments");
+  for (int t = 0; t < PROF_SLOTS; ++t) {
+    ms[t] = 0.0;
+    calls[t] = 0;
+  }
+  for (int i = 0; i < P->ev_used; ++i) {
+    BEM_HIP_TRY(hipEventSynchronize(P->ev_pool[2 * i + 1]));
+    float t = 0.f;
+    BEM_HIP_TRY(hipEventElapsedTime(&t, P->ev_pool[2 * i], P->ev_pool[2 * i + 1]));
+    int slot = P->ev_slot[i];
+    ms[slot] += t;
+    calls[slot] += 1;
+  }
+  P->prof_on = false;
+  P->ev_used = 0;
+  P->ev_slot.clear();
+  return BEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,752 @@
+// Far-field operators, built once per plan in float64 on the device.
+//
+// The paper applies its BEM blocks with a low-frequency FMM (Sec. 2.3) whose
+// formulas it does not give; this is our own design from the published
+// spherical-wave expansion of the Helmholtz kernel.  With orthonormal
+// spherical harmonics Y_n^m (Condon-Shortley phase), regular and singular
+// wave functions R_n^m(v) = j_n(k|v|) Y_n^m(v^), S_n^m(v) = h_n(k|v|) Y_n^m(v^)
+// (h_n = j_n + i y_n, outgoing for the exp(-i omega t) convention of
+// Sec. 2.1), the kernel G = exp(ikr)/(4 pi r) separates as
+//     G(x - y) = ik sum_nm S_n^m(x - c) conj(R_n^m(y - c)),  |y-c| < |x-c|.
+// Translations follow from the plane-wave integral of R_n^m and the Gaunt
+// coefficients g(n,m; n',m'; l) = int Y_n^m conj(Y_n'^m') conj(Y_l^(m-m')):
+//     F_n^m(r + t) = sum_n'm' (F|R)_{n'm',nm}(t) R_n'^m'(r),
+//     (F|R)_{n'm',nm}(t) = sum_l 4 pi i^(n'+l-n) F_l^(m-m')(t) g(n,m;n',m';l)
+// with F = S for multipole-to-local (|r| < |t|) and F = R for local-to-local;
+// the multipole-to-multipole matrix equals the regular one.  Gradients use
+// the l = 1 terms of the same formula.  Gaunt coefficients are integrated
+// exactly by Gauss-Legendre quadrature in cos(theta).
+//
+// Coefficients are scaled per level so that every stored number is O(1) in
+// float32: with f_n = (k h_l)^n / (2n+1)!! (h_l the box side), multipoles are
+// kept as M_n / f_n and locals as L_n f_n.
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "plan.h"
+
+namespace bemfmm {
+
+#define ARENA_ALLOC(arena, ptr, count)                                              \
+  do {                                                                              \
+    int _r = (arena).alloc((void**)&(ptr), sizeof(*(ptr)) * (size_t)(count));      \
+    if (_r) return _r;                                                              \
+  } while (0)
+
+void gauss_legendre(int m, std::vector<double>& t, std::vector<double>& w);
+int build_vlist(Problem& P, int l, int** dst, int** src, int** code, int* npairs,
+                DevArena& scratch, hipStream_t s);
+
+constexpr double FOUR_PI = 12.566370614359172;
+constexpr int MAXP = 40;         // largest supported expansion order
+constexpr int MAXL = 2 * MAXP + 2;
+
+__host__ __device__ __forceinline__ int cidx(int n, int m) { return n * n + n + m; }
+
+// Theta_n^m(x), 0 <= m <= n <= nmax, normalised associated Legendre functions
+// with Condon-Shortley phase (Y_n^m = Theta_n^m(cos t) exp(i m phi)), written
+// to out[n*(nmax+1) + m].  Standard three-term recurrences.
+__device__ void theta_table(int nmax, double x, double* out, int stride) {
+  double s = sqrt(fmax(0.0, 1.0 - x * x));
+  double tmm = 0.28209479177387814;  // 1/sqrt(4 pi)
+  for (int m = 0; m <= nmax; ++m) {
+    if (m > 0) tmm = -sqrt((2.0 * m + 1.0) / (2.0 * m)) * s * tmm;
+    out[m * stride + m] = tmm;
+    if (m < nmax) {
+      double t1 = sqrt(2.0 * m + 3.0) * x * tmm;
+      out[(m + 1) * stride + m] = t1;
+      double t0 = tmm;
+      for (int n = m + 2; n <= nmax; ++n) {
+        double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+        double b = sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+        double t2 = a * (x * t1 - b * t0);
+        out[n * stride + m] = t2;
+        t0 = t1;
+        t1 = t2;
+      }
+    }
+  }
+}
+
+// spherical Bessel j_n(x), n = 0..nmax, by downward (Miller) recurrence of
+// the scaled values jt_n = j_n (2n+1)!! / x^n, normalised by j_0 = sin x / x;
+// returns j_n in out.
+__device__ void sph_jn(int nmax, double x, double* out) {
+  if (x == 0.0) {
+    out[0] = 1.0;
+    for (int n = 1; n <= nmax; ++n) out[n] = 0.0;
+    return;
+  }
+  int top = nmax + 24 + (int)(1.5 * x);
+  double x2 = x * x;
+  double jp1 = 1.0 - x2 / (2.0 * (2 * top + 5)), jn = 1.0 - x2 / (2.0 * (2 * top + 3));
+  // jt_{n-1} = jt_n - jt_{n+1} x^2 / ((2n+1)(2n+3))
+  for (int n = top; n >= 1; --n) {
+    double jm1 = jn - jp1 * x2 / ((2.0 * n + 1.0) * (2.0 * n + 3.0));
+    jp1 = jn;
+    jn = jm1;
+    if (n - 1 <= nmax) out[n - 1] = jm1;
+  }
+  // normalise on j_0 or j_1, whichever is larger (they never vanish together)
+  double j0 = (fabs(x) < 1e-4) ? 1.0 - x2 / 6.0 + x2 * x2 / 120.0 : sin(x) / x;
+  double scale;
+  if (nmax >= 1 && fabs(x) > 1.0) {
+    double j1 = (sin(x) / x - cos(x)) / x;
+    scale = (fabs(j0) >= fabs(j1)) ? j0 / out[0] : j1 / (out[1] * x / 3.0);
+  } else {
+    scale = j0 / out[0];
+  }
+  double f = 1.0;  // x^n / (2n+1)!!
+  for (int n = 0; n <= nmax; ++n) {
+    if (n > 0) f *= x / (2.0 * n + 1.0);
+    out[n] *= scale * f;
+  }
+}
+
+// spherical Bessel y_n(x), upward recurrence (stable for y)
+__device__ void sph_yn(int nmax, double x, double* out) {
+  double sn = sin(x), cs = cos(x);
+  out[0] = -cs / x;
+  if (nmax >= 1) out[1] = -cs / (x * x) - sn / x;
+  for (int n = 1; n < nmax; ++n) out[n + 1] = (2.0 * n + 1.0) / x * out[n] - out[n - 1];
+}
+
+// All R_n^m (sing = 0) or S_n^m (sing = 1) at v for n <= nmax, into out
+// (complex, cidx order).  tmp: >= (nmax+1)^2 + 2(nmax+1) doubles.
+__device__ void wave_functions(int nmax, double k, double vx, double vy, double vz, int sing,
+                               c64* out, double* tmp) {
+  double r = sqrt(vx * vx + vy * vy + vz * vz);
+  double ct = (r > 0.0) ? vz / r : 1.0;
+  double rxy = sqrt(vx * vx + vy * vy);
+  double cp = (rxy > 0.0) ? vx / rxy : 1.0, sp = (rxy > 0.0) ? vy / rxy : 0.0;
+  double* th = tmp;                          // (nmax+1)^2
+  double* jr = tmp + (nmax + 1) * (nmax + 1);  // nmax+1
+  double* yr = jr + (nmax + 1);
+  theta_table(nmax, ct, th, nmax + 1);
+  sph_jn(nmax, k * r, jr);
+  if (sing) sph_yn(nmax, k * r, yr);
+  double er = 1.0, ei = 0.0;  // exp(i m phi)
+  for (int m = 0; m <= nmax; ++m) {
+    if (m > 0) {
+      double t = er * cp - ei * sp;
+      ei = er * sp + ei * cp;
+      er = t;
+    }
+    double sgn = (m & 1) ? -1.0 : 1.0;
+    for (int n = m; n <= nmax; ++n) {
+      double t = th[n * (nmax + 1) + m];
+      c64 rad = sing ? mk(jr[n], yr[n]) : mk(jr[n], 0.0);
+      c64 y = mk(t * er, t * ei);
+      out[cidx(n, m)] = cmul(rad, y);
+      if (m > 0) {
+        // Y_n^-m = (-1)^m conj(Y_n^m)
+        c64 yneg = mk(sgn * t * er, -sgn * t * ei);
+        out[cidx(n, -m)] = cmul(rad, yneg);
+      }
+    }
+  }
+}
+
+// Gaunt table: for input (n,m) (n <= pin) and output (n',m') (n' <= pout),
+// gt[(in * Pout + out) * J + j] = g(n,m; n',m'; l) with l = |n-n'| + 2j,
+// j < J = min(pin,pout)+1 (zero where |m-m'| > l or l > lmax).
+// th: Theta tables at the K Gauss nodes, th[(q*(tmax+1) + l)*(tmax+1) + mu],
+// tmax = max(pin, pout, lmax).
+__global__ void k_gaunt(int pin, int pout, int lmax, int tmax, int K,
+                        const double* __restrict__ gw, const double* __restrict__ th,
+                        double* __restrict__ gt) {
+  int Pin = (pin + 1) * (pin + 1), Pout = (pout + 1) * (pout + 1);
+  int J = min(pin, pout) + 1;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)Pin * Pout) return;
+  int in = (int)(t / Pout), out = (int)(t % Pout);
+  int n = (int)sqrt((double)in);
+  while (n * n > in) --n;
+  while ((n + 1) * (n + 1) <= in) ++n;
+  int m = in - n * n - n;
+  int n2 = (int)sqrt((double)out);
+  while (n2 * n2 > out) --n2;
+  while ((n2 + 1) * (n2 + 1) <= out) ++n2;
+  int m2 = out - n2 * n2 - n2;
+  int mu = m - m2;
+  int L1 = tmax + 1;
+  for (int j = 0; j < J; ++j) {
+    int l = abs(n - n2) + 2 * j;
+    double val = 0.0;
+    if (l <= n + n2 && l <= lmax && abs(mu) <= l) {
+      for (int q = 0; q < K; ++q) {
+        const double* T = th + (int64_t)q * L1 * L1;
+        double a = T[n * L1 + abs(m)] * ((m < 0 && (m & 1)) ? -1.0 : 1.0);
+        double b = T[n2 * L1 + abs(m2)] * ((m2 < 0 && (m2 & 1)) ? -1.0 : 1.0);
+        double c = T[l * L1 + abs(mu)] * ((mu < 0 && (mu & 1)) ? -1.0 : 1.0);
+        val += gw[q] * a * b * c;
+      }
+      val *= 6.283185307179586;  // 2 pi from the phi integral
+    }
+    gt[t * J + j] = val;
+  }
+}
+
+__global__ void k_theta_nodes(int lmax, int K, const double* __restrict__ gx,
+                              double* __restrict__ th) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= K) return;
+  theta_table(lmax, gx[q], th + (int64_t)q * (lmax + 1) * (lmax + 1), lmax + 1);
+}
+
+// F_l^mu(t_g) for each group vector, l <= lmax: out[g * (lmax+1)^2 + cidx(l,mu)]
+__global__ void k_group_waves(int ngroups, const double* __restrict__ tv, double k, int lmax,
+                              int sing, c64* __restrict__ out, double* __restrict__ tmp) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups) return;
+  int L1 = lmax + 1;
+  wave_functions(lmax, k, tv[3 * g], tv[3 * g + 1], tv[3 * g + 2], sing, out + (int64_t)g * L1 * L1,
+                 tmp + (int64_t)g * (L1 * L1 + 2 * L1));
+}
+
+// Translation matrices, one per group: mats[g][out][in] (row-major),
+//   T = sum_l 4 pi i^(n'+l-n) F_l^(m-m')(t_g) g(n,m;n',m';l),
+// times the level scaling rs[out] * cs[in].
+template <typename R>
+__global__ void k_translation(int ngroups, int pin, int pout, int lmax,
+                              const c64* __restrict__ F, const double* __restrict__ gt,
+                              const double* __restrict__ rs, const double* __restrict__ cs,
+                              cplx<R>* __restrict__ mats) {
+  int Pin = (pin + 1) * (pin + 1), Pout = (pout + 1) * (pout + 1);
+  int J = min(pin, pout) + 1;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t per = (int64_t)Pin * Pout;
+  if (t >= per * ngroups) return;
+  int g = (int)(t / per);
+  int64_t e = t % per;
+  int out = (int)(e / Pin), in = (int)(e % Pin);
+  int n = (int)sqrt((double)in);
+  while (n * n > in) --n;
+  while ((n + 1) * (n + 1) <= in) ++n;
+  int m = in - n * n - n;
+  int n2 = (int)sqrt((double)out);
+  while (n2 * n2 > out) --n2;
+  while ((n2 + 1) * (n2 + 1) <= out) ++n2;
+  int m2 = out - n2 * n2 - n2;
+  int mu = m - m2;
+  const c64* Fg = F + (int64_t)g * (lmax + 1) * (lmax + 1);
+  const double* G = gt + ((int64_t)in * Pout + out) * J;
+  c64 acc = mk(0.0, 0.0);
+  for (int j = 0; j < J; ++j) {
+    int l = abs(n - n2) + 2 * j;
+    if (l > n + n2 || l > lmax || abs(mu) > l) continue;
+    double gv = G[j];
+    if (gv == 0.0) continue;
+    c64 f = Fg[cidx(l, mu)];
+    int e4 = (n2 + l - n) & 3;  // i^e
+    c64 ie = (e4 == 0) ? mk(1.0, 0.0) : (e4 == 1) ? mk(0.0, 1.0) : (e4 == 2) ? mk(-1.0, 0.0) : mk(0.0, -1.0);
+    acc = cadd(acc, cscale(cmul(ie, f), FOUR_PI * gv));
+  }
+  acc = cscale(acc, rs[out] * cs[in]);
+  mats[t] = mk((R)acc.re, (R)acc.im);
+}
+
+// Directional derivative coefficients: for unit vector d,
+//   d . grad R_n^m = sum_{s=+-1, mu} gc[(cidx(n,m)*2 + (s>0))*3 + mu+1] c_mu(d) R_{n+s}^{m-mu}
+// with c_0 = sqrt(3/4pi) d_z, c_{+1} = -sqrt(3/8pi)(d_x + i d_y),
+// c_{-1} = sqrt(3/8pi)(d_x - i d_y); gc holds 4 pi i^(n'+1-n) (k/3) g(n,m;n',m';1).
+__device__ __forceinline__ c64 cmu(int mu, double dx, double dy, double dz) {
+  if (mu == 0) return mk(0.4886025119029199 * dz, 0.0);
+  if (mu == 1) return mk(-0.3454941494713355 * dx, -0.3454941494713355 * dy);
+  return mk(0.3454941494713355 * dx, -0.3454941494713355 * dy);
+}
+
+// Per element (sorted order) P2M columns and L2P row at leaf centre c:
+//  p2m[e][c][1] (q column) = ik/f_n * (A/3) sum_q conj(R_n^m(y_q - c))
+//  p2m[e][c][0] (p column) = -ik/f_n * (A/3) sum_q conj(n_e . grad R_n^m(y_q - c))
+//  l2p[e][c]               = (R_n^m + alpha n_e . grad R_n^m)(x_e - c) / f_n
+// Rbuf: per thread scratch for (p+2)^2 wave functions of 4 points.
+template <typename R>
+__global__ void k_p2m_l2p(const double* __restrict__ g, int64_t n, int64_t e0, int64_t ne,
+                          const int* __restrict__ elem_leaf, const uint64_t* __restrict__ lkeys,
+                          int L, const double* __restrict__ lo, double hL, double k, double alr,
+                          double ali, int p, const double* __restrict__ gc,
+                          const double* __restrict__ finv, c64* __restrict__ Rbuf,
+                          double* __restrict__ tmpbuf, cplx<R>* __restrict__ p2m,
+                          cplx<R>* __restrict__ l2p) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ne) return;
+  int64_t e = e0 + t;
+  int P1 = (p + 2) * (p + 2), P = (p + 1) * (p + 1);
+  c64* Rb = Rbuf + t * 4 * P1;
+  double* tmp = tmpbuf + t * ((p + 2) * (p + 2) + 2 * (p + 2));
+  uint64_t key = lkeys[elem_leaf[e]];
+  double c[3];
+  uint32_t ix = 0, iy = 0, iz = 0;
+  for (int b = 0; b < L; ++b) {
+    ix |= (uint32_t)((key >> (3 * b + 2)) & 1) << b;
+    iy |= (uint32_t)((key >> (3 * b + 1)) & 1) << b;
+    iz |= (uint32_t)((key >> (3 * b)) & 1) << b;
+  }
+  c[0] = lo[0] + (ix + 0.5) * hL;
+  c[1] = lo[1] + (iy + 0.5) * hL;
+  c[2] = lo[2] + (iz + 0.5) * hL;
+  for (int q = 0; q < 3; ++q) {
+    double vx = g[(GEO_QX0 + 3 * q) * n + e] - c[0];
+    double vy = g[(GEO_QX0 + 3 * q + 1) * n + e] - c[1];
+    double vz = g[(GEO_QX0 + 3 * q + 2) * n + e] - c[2];
+    wave_functions(p + 1, k, vx, vy, vz, 0, Rb + q * P1, tmp);
+  }
+  wave_functions(p + 1, k, g[GEO_CX * n + e] - c[0], g[GEO_CY * n + e] - c[1],
+                 g[GEO_CZ * n + e] - c[2], 0, Rb + 3 * P1, tmp);
+  double nx = g[GEO_NX * n + e], ny = g[GEO_NY * n + e], nz = g[GEO_NZ * n + e];
+  double w3 = g[GEO_AREA * n + e] / 3.0;
+  c64 cm[3] = {cmu(-1, nx, ny, nz), cmu(0, nx, ny, nz), cmu(1, nx, ny, nz)};
+  c64 al = mk(alr, ali);
+  for (int nn = 0; nn <= p; ++nn) {
+    for (int m = -nn; m <= nn; ++m) {
+      int ci = cidx(nn, m);
+      c64 sq = mk(0.0, 0.0), sp = mk(0.0, 0.0), rt = mk(0.0, 0.0), gt = mk(0.0, 0.0);
+      for (int pt = 0; pt < 4; ++pt) {
+        const c64* Rv = Rb + pt * P1;
+        c64 grad = mk(0.0, 0.0);
+        for (int sgn = 0; sgn < 2; ++sgn) {
+          int n2 = sgn ? nn + 1 : nn - 1;
+          if (n2 < 0) continue;
+          for (int mu = -1; mu <= 1; ++mu) {
+            int m2 = m - mu;
+            if (abs(m2) > n2) continue;
+            const double* gg = gc + ((int64_t)(ci * 2 + sgn) * 3 + (mu + 1)) * 2;
+            c64 coef = mk(gg[0], gg[1]);
+            grad = cadd(grad, cmul(cmul(coef, cm[mu + 1]), Rv[cidx(n2, m2)]));
+          }
+        }
+        if (pt < 3) {
+          sq = cadd(sq, cconj(Rv[ci]));
+          sp = cadd(sp, cconj(grad));
+        } else {
+          rt = Rv[ci];
+          gt = grad;
+        }
+      }
+      double fi = finv[nn];  // 1 / f_n
+      c64 ik = mk(0.0, k);
+      c64 aq = cscale(cmul(ik, sq), w3 * fi);
+      c64 ap = cscale(cmul(ik, sp), -w3 * fi);
+      c64 b = cscale(cadd(rt, cmul(al, gt)), fi);
+      p2m[(e * P + ci) * 2 + 0] = mk((R)ap.re, (R)ap.im);
+      p2m[(e * P + ci) * 2 + 1] = mk((R)aq.re, (R)aq.im);
+      l2p[e * P + ci] = mk((R)b.re, (R)b.im);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+struct GauntSet {
+  double* d = nullptr;
+  int pin = 0, pout = 0, lmax = 0;
+};
+
+static int make_gaunt(int pin, int pout, int lmax, GauntSet& G, DevArena& scratch, hipStream_t s) {
+  int K = (pin + pout + lmax) / 2 + 2;
+  int tmax = std::max(std::max(pin, pout), lmax);
+  std::vector<double> gx, gw;
+  gauss_legendre(K, gx, gw);
+  double *dgx, *dgw, *th;
+  ARENA_ALLOC(scratch, dgx, K);
+  ARENA_ALLOC(scratch, dgw, K);
+  ARENA_ALLOC(scratch, th, (int64_t)K * (tmax + 1) * (tmax + 1));
+  BEM_HIP_TRY(hipMemcpyAsync(dgx, gx.data(), sizeof(double) * K, hipMemcpyHostToDevice, s));
+  BEM_HIP_TRY(hipMemcpyAsync(dgw, gw.data(), sizeof(double) * K, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_theta_nodes, dim3(ceil_div(K, 64)), dim3(64), 0, s, tmax, K, dgx, th);
+  BEM_LAUNCH_CHECK();
+  int64_t Pin = (pin + 1) * (pin + 1), Pout = (pout + 1) * (pout + 1);
+  int J = std::min(pin, pout) + 1;
+  ARENA_ALLOC(scratch, G.d, Pin * Pout * J);
+  hipLaunchKernelGGL(k_gaunt, dim3(ceil_div(Pin * Pout, 128)), dim3(128), 0, s, pin, pout, lmax,
+                     tmax, K, dgw, th, G.d);
+  BEM_LAUNCH_CHECK();
+  G.pin = pin;
+  G.pout = pout;
+  G.lmax = lmax;
+  return 0;
+}
+
+// scaling vector per coefficient: f_n^power, f_n = (k h)^n / (2n+1)!!
+static std::vector<double> coef_scale(int p, double kh, int power) {
+  std::vector<double> f(p + 1), out((p + 1) * (p + 1));
+  double v = 1.0;
+  for (int nn = 0; nn <= p; ++nn) {
+    if (nn > 0) v *= kh / (2.0 * nn + 1.0);
+    f[nn] = v;
+  }
+  for (int nn = 0; nn <= p; ++nn)
+    for (int m = -nn; m <= nn; ++m) out[cidx(nn, m)] = (power > 0) ? f[nn] : 1.0 / f[nn];
+  return out;
+}
+
+template <typename R>
+static int make_translations(Problem& P, int ngroups, const std::vector<double>& tvec, int sing,
+                             int pin, int pout, const std::vector<double>& rs,
+                             const std::vector<double>& cs, cplx<R>** mats, DevArena& scratch,
+                             hipStream_t s) {
+  int lmax = pin + pout;
+  GauntSet G;
+  int r = make_gaunt(pin, pout, lmax, G, scratch, s);
+  if (r) return r;
+  int L1 = lmax + 1;
+  double *dtv, *tmp, *drs, *dcs;
+  c64* F;
+  ARENA_ALLOC(scratch, dtv, 3 * ngroups);
+  ARENA_ALLOC(scratch, F, (int64_t)ngroups * L1 * L1);
+  ARENA_ALLOC(scratch, tmp, (int64_t)ngroups * (L1 * L1 + 2 * L1));
+  ARENA_ALLOC(scratch, drs, rs.size());
+  ARENA_ALLOC(scratch, dcs, cs.size());
+  BEM_HIP_TRY(hipMemcpyAsync(dtv, tvec.data(), sizeof(double) * 3 * ngroups, hipMemcpyHostToDevice, s));
+  BEM_HIP_TRY(hipMemcpyAsync(drs, rs.data(), sizeof(double) * rs.size(), hipMemcpyHostToDevice, s));
+  BEM_HIP_TRY(hipMemcpyAsync(dcs, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_group_waves, dim3(ceil_div(ngroups, 64)), dim3(64), 0, s, ngroups, dtv,
+                     P.k, lmax, sing, F, tmp);
+  BEM_LAUNCH_CHECK();
+  int64_t Pin = (pin + 1) * (pin + 1), Pout = (pout + 1) * (pout + 1);
+  ARENA_ALLOC(P.arena, *mats, Pin * Pout * ngroups);
+  int64_t tot = Pin * Pout * ngroups;
+  hipLaunchKernelGGL(k_translation<R>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, ngroups, pin,
+                     pout, lmax, F, G.d, drs, dcs, *mats);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+static int auto_order(double k, double h, int req, int base, int extra) {
+  if (req > 0) return std::min(req, MAXP);
+  double d = sqrt(3.0) * h;
+  int p = (int)ceil(k * d) + extra;
+  return std::min(std::max(p, base), MAXP);
+}
+
+// Tiles of a grouped op: (group, first pair, pair count, first row)
+static void make_tiles(const std::vector<int>& gstart, int rows, int CT, int RT,
+                       std::vector<int>& tg, std::vector<int>& tp0, std::vector<int>& tnp,
+                       std::vector<int>& tr0) {
+  int ng = (int)gstart.size() - 1;
+  for (int gi = 0; gi < ng; ++gi) {
+    int a = gstart[gi], b = gstart[gi + 1];
+    for (int p0 = a; p0 < b; p0 += CT)
+      for (int r0 = 0; r0 < rows; r0 += RT) {
+        tg.push_back(gi);
+        tp0.push_back(p0);
+        tnp.push_back(std::min(CT, b - p0));
+        tr0.push_back(r0);
+      }
+  }
+}
+
+constexpr int GEMM_CT = 32;
+constexpr int GEMM_RT = 64;
+
+__global__ void k_group_starts(const int* __restrict__ code, int np, int ngroups,
+                               int* __restrict__ cnt) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < np) atomicAdd(&cnt[code[t]], 1);
+}
+
+__global__ void k_sort_keys(const int* __restrict__ code, const int* __restrict__ dst, int np,
+                            int dbits, uint64_t* __restrict__ keys, int* __restrict__ idx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  keys[t] = ((uint64_t)code[t] << dbits) | (uint64_t)dst[t];
+  idx[t] = t;
+}
+
+__global__ void k_permute3(const int* __restrict__ idx, int np, const int* __restrict__ a,
+                           const int* __restrict__ b, const int* __restrict__ c,
+                           int* __restrict__ ao, int* __restrict__ bo, int* __restrict__ co) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  int i = idx[t];
+  ao[t] = a[i];
+  bo[t] = b[i];
+  co[t] = c[i];
+}
+
+__global__ void k_octant_pairs(const uint64_t* __restrict__ ckeys, const int* __restrict__ parent,
+                               int nbox, int* __restrict__ dst, int* __restrict__ src,
+                               int* __restrict__ code) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nbox) return;
+  dst[c] = parent[c];
+  src[c] = c;
+  code[c] = (int)(ckeys[c] & 7);
+}
+
+// Group (dst, src, code) pairs by code (stable by dst), upload tiles for the
+// forward and adjoint directions.  code < ngroups.
+template <typename R>
+static int finish_grouped(GroupedOp<R>& op, int* d0, int* s0, int* c0, int np, int ngroups,
+                          const std::vector<int>& slot_of_group, DevArena& arena,
+                          DevArena& scratch, hipStream_t s) {
+  op.n_pairs = np;
+  int dbits = 1;
+  while ((1 << dbits) < 1 << 30 && (1 << dbits) <= np + 1) ++dbits;
+  dbits = 30;
+  uint64_t* keys;
+  int* idx;
+  ARENA_ALLOC(scratch, keys, np);
+  ARENA_ALLOC(scratch, idx, np);
+  if (np > 0) {
+    hipLaunchKernelGGL(k_sort_keys, dim3(ceil_div(np, 256)), dim3(256), 0, s, c0, d0, np, dbits,
+                       keys, idx);
+    BEM_LAUNCH_CHECK();
+    int nbits = dbits + 10;
+    int r = sort_pairs_u64(keys, idx, np, nbits, scratch, s);
+    if (r) return r;
+  }
+  int* code_sorted;
+  ARENA_ALLOC(arena, op.pair_dst, np);
+  ARENA_ALLOC(arena, op.pair_src, np);
+  ARENA_ALLOC(scratch, code_sorted, np);
+  if (np > 0) {
+    hipLaunchKernelGGL(k_permute3, dim3(ceil_div(np, 256)), dim3(256), 0, s, idx, np, d0, s0, c0,
+                       op.pair_dst, op.pair_src, code_sorted);
+    BEM_LAUNCH_CHECK();
+  }
+  int* gcnt;
+  ARENA_ALLOC(scratch, gcnt, ngroups);
+  BEM_HIP_TRY(hipMemsetAsync(gcnt, 0, sizeof(int) * ngroups, s));
+  if (np > 0) {
+    hipLaunchKernelGGL(k_group_starts, dim3(ceil_div(np, 256)), dim3(256), 0, s, code_sorted, np,
+                       ngroups, gcnt);
+    BEM_LAUNCH_CHECK();
+  }
+  std::vector<int> hcnt(ngroups);
+  BEM_HIP_TRY(hipMemcpyAsync(hcnt.data(), gcnt, sizeof(int) * ngroups, hipMemcpyDeviceToHost, s));
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int> gstart(ngroups + 1, 0);
+  for (int g = 0; g < ngroups; ++g) gstart[g + 1] = gstart[g] + hcnt[g];
+  std::vector<int> tg, tp0, tnp, tr0, ta, tap0, tanp, tar0;
+  make_tiles(gstart, op.rows, GEMM_CT, GEMM_RT, tg, tp0, tnp, tr0);
+  make_tiles(gstart, op.cols, GEMM_CT, GEMM_RT, ta, tap0, tanp, tar0);
+  op.n_tiles = (int)tg.size();
+  op.n_tiles_adj = (int)ta.size();
+  ARENA_ALLOC(arena, op.tile_group, op.n_tiles);
+  ARENA_ALLOC(arena, op.tile_pair0, op.n_tiles);
+  ARENA_ALLOC(arena, op.tile_npairs, op.n_tiles);
+  ARENA_ALLOC(arena, op.tile_row0, op.n_tiles);
+  ARENA_ALLOC(arena, op.tile_group_adj, op.n_tiles_adj);
+  ARENA_ALLOC(arena, op.tile_pair0_adj, op.n_tiles_adj);
+  ARENA_ALLOC(arena, op.tile_npairs_adj, op.n_tiles_adj);
+  ARENA_ALLOC(arena, op.tile_row0_adj, op.n_tiles_adj);
+  ARENA_ALLOC(arena, op.group_slot, ngroups);
+  auto up = [&](int* d, const std::vector<int>& h) -> int {
+    if (!h.empty())
+      BEM_HIP_TRY(hipMemcpyAsync(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
+    return 0;
+  };
+  int r = 0;
+  if ((r = up(op.tile_group, tg)) || (r = up(op.tile_pair0, tp0)) || (r = up(op.tile_npairs, tnp)) ||
+      (r = up(op.tile_row0, tr0)) || (r = up(op.tile_group_adj, ta)) ||
+      (r = up(op.tile_pair0_adj, tap0)) || (r = up(op.tile_npairs_adj, tanp)) ||
+      (r = up(op.tile_row0_adj, tar0)) || (r = up(op.group_slot, slot_of_group)))
+    return r;
+  op.pair_dst_adj = op.pair_src;
+  op.pair_src_adj = op.pair_dst;
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+template <typename R>
+static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena& scratch,
+                           hipStream_t s) {
+  const int L = P.L;
+  const double k = P.k;
+  for (int l = 2; l <= L; ++l) {
+    D.order[l] = is64 ? auto_order(k, P.h[l], P.order64_req, 12, 8)
+                      : auto_order(k, P.h[l], P.order32_req, 7, 3);
+    D.ncoef[l] = (D.order[l] + 1) * (D.order[l] + 1);
+    ARENA_ALLOC(P.arena, D.M[l], (int64_t)P.nbox[l] * D.ncoef[l]);
+    ARENA_ALLOC(P.arena, D.Lc[l], (int64_t)P.nbox[l] * D.ncoef[l]);
+  }
+  // ---- M2L: one matrix per offset present at each level ----
+  for (int l = 2; l <= L; ++l) {
+    int *d0, *s0, *c0, np = 0;
+    int r = build_vlist(P, l, &d0, &s0, &c0, &np, scratch, s);
+    if (r) return r;
+    P.n_m2l[l] = np;
+    int p = D.order[l];
+    // present offsets
+    std::vector<int> hc(np);
+    if (np) BEM_HIP_TRY(hipMemcpyAsync(hc.data(), c0, sizeof(int) * np, hipMemcpyDeviceToHost, s));
+    BEM_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int> slot(N_OFFSETS, -1);
+    std::vector<double> tv;
+    int ns = 0;
+    for (int c : hc)
+      if (slot[c] < 0) slot[c] = 0;
+    for (int c = 0; c < N_OFFSETS; ++c)
+      if (slot[c] == 0) {
+        slot[c] = ns++;
+        int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
+        tv.push_back(dx * P.h[l]);
+        tv.push_back(dy * P.h[l]);
+        tv.push_back(dz * P.h[l]);
+      }
+    GroupedOp<R>& op = D.m2l[l];
+    op.rows = op.cols = D.ncoef[l];
+    op.n_slots = ns;
+    if (ns > 0) {
+      // L~ = f_n' (S|R) M~ f_n  (locals times f, multipoles over f)
+      std::vector<double> rs = coef_scale(p, k * P.h[l], +1), cs = coef_scale(p, k * P.h[l], +1);
+      r = make_translations<R>(P, ns, tv, 1, p, p, rs, cs, &op.mats, scratch, s);
+      if (r) return r;
+    }
+    r = finish_grouped<R>(op, d0, s0, c0, np, N_OFFSETS, slot, P.arena, scratch, s);
+    if (r) return r;
+  }
+  // ---- M2M (child level l -> parent l-1) and L2L (l-1 -> l), l >= 3 ----
+  for (int l = 3; l <= L; ++l) {
+    int nb = P.nbox[l];
+    int *d0, *s0, *c0;
+    ARENA_ALLOC(scratch, d0, nb);
+    ARENA_ALLOC(scratch, s0, nb);
+    ARENA_ALLOC(scratch, c0, nb);
+    hipLaunchKernelGGL(k_octant_pairs, dim3(ceil_div(nb, 256)), dim3(256), 0, s, P.box_keys[l],
+                       P.box_parent[l], nb, d0, s0, c0);
+    BEM_LAUNCH_CHECK();
+    int pc = D.order[l], pp = D.order[l - 1];
+    std::vector<int> slot(8);
+    std::vector<double> tv_m2m, tv_l2l;
+    for (int o = 0; o < 8; ++o) {
+      slot[o] = o;
+      // child centre minus parent centre = (+-1/2 h_l per axis)
+      double ox = (((o >> 2) & 1) ? 0.5 : -0.5) * P.h[l];
+      double oy = (((o >> 1) & 1) ? 0.5 : -0.5) * P.h[l];
+      double oz = ((o & 1) ? 0.5 : -0.5) * P.h[l];
+      tv_m2m.push_back(-ox);  // parent - child
+      tv_m2m.push_back(-oy);
+      tv_m2m.push_back(-oz);
+      tv_l2l.push_back(ox);  // child - parent
+      tv_l2l.push_back(oy);
+      tv_l2l.push_back(oz);
+    }
+    // M~_par = (1/f^(l-1)_n') (R|R) f^(l)_n M~_child
+    GroupedOp<R>& mm = D.m2m[l];
+    mm.rows = D.ncoef[l - 1];
+    mm.cols = D.ncoef[l];
+    mm.n_slots = 8;
+    std::vector<double> rs = coef_scale(pp, k * P.h[l - 1], -1), cs = coef_scale(pc, k * P.h[l], +1);
+    int r = make_translations<R>(P, 8, tv_m2m, 0, pc, pp, rs, cs, &mm.mats, scratch, s);
+    if (r) return r;
+    r = finish_grouped<R>(mm, d0, s0, c0, nb, 8, slot, P.arena, scratch, s);
+    if (r) return r;
+    // L~_child = f^(l)_n' (R|R) (1/f^(l-1)_n) L~_par ; pairs (dst child, src parent)
+    GroupedOp<R>& ll = D.l2l[l];
+    ll.rows = D.ncoef[l];
+    ll.cols = D.ncoef[l - 1];
+    ll.n_slots = 8;
+    rs = coef_scale(pc, k * P.h[l], +1);
+    cs = coef_scale(pp, k * P.h[l - 1], -1);
+    r = make_translations<R>(P, 8, tv_l2l, 0, pp, pc, rs, cs, &ll.mats, scratch, s);
+    if (r) return r;
+    r = finish_grouped<R>(ll, s0, d0, c0, nb, 8, slot, P.arena, scratch, s);
+    if (r) return r;
+  }
+  // ---- P2M and L2P per element ----
+  {
+    int p = D.order[L];
+    int P1 = (p + 2) * (p + 2);
+    int Pc = (p + 1) * (p + 1);
+    // derivative coefficients from the l = 1 Gaunt terms (output order p+1)
+    GauntSet G1;
+    int r = make_gaunt(p, p + 1, 1, G1, scratch, s);
+    if (r) return r;
+    int J = std::min(p, p + 1) + 1;
+    std::vector<double> hg((size_t)Pc * P1 * J);
+    BEM_HIP_TRY(hipMemcpyAsync(hg.data(), G1.d, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, s));
+    BEM_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<double> gc((size_t)Pc * 2 * 3 * 2, 0.0);
+    for (int nn = 0; nn <= p; ++nn)
+      for (int m = -nn; m <= nn; ++m)
+        for (int sg = 0; sg < 2; ++sg) {
+          int n2 = sg ? nn + 1 : nn - 1;
+          if (n2 < 0) continue;
+          for (int mu = -1; mu <= 1; ++mu) {
+            int m2 = m - mu;
+            if (abs(m2) > n2) continue;
+            // l = 1 = |nn - n2| + 2j -> j = 0
+            double gv = hg[((size_t)cidx(nn, m) * P1 + cidx(n2, m2)) * J + 0];
+            std::complex<double> ie = std::pow(std::complex<double>(0, 1), (n2 + 1 - nn) & 3);
+            std::complex<double> cf = ie * (FOUR_PI * gv * k / 3.0);
+            size_t o = ((size_t)(cidx(nn, m) * 2 + sg) * 3 + (mu + 1)) * 2;
+            gc[o] = cf.real();
+            gc[o + 1] = cf.imag();
+          }
+        }
+    double *dgc, *dfinv, *dlo;
+    ARENA_ALLOC(scratch, dgc, gc.size());
+    ARENA_ALLOC(scratch, dfinv, p + 1);
+    ARENA_ALLOC(scratch, dlo, 3);
+    std::vector<double> finv(p + 1);
+    double v = 1.0;
+    for (int nn = 0; nn <= p; ++nn) {
+      if (nn > 0) v *= k * P.h[L] / (2.0 * nn + 1.0);
+      finv[nn] = 1.0 / v;
+    }
+    BEM_HIP_TRY(hipMemcpyAsync(dgc, gc.data(), sizeof(double) * gc.size(), hipMemcpyHostToDevice, s));
+    BEM_HIP_TRY(hipMemcpyAsync(dfinv, finv.data(), sizeof(double) * (p + 1), hipMemcpyHostToDevice, s));
+    BEM_HIP_TRY(hipMemcpyAsync(dlo, P.lo, sizeof(double) * 3, hipMemcpyHostToDevice, s));
+    ARENA_ALLOC(P.arena, D.p2m, (int64_t)P.n * Pc * 2);
+    ARENA_ALLOC(P.arena, D.l2p, (int64_t)P.n * Pc);
+    int64_t chunk = 16384;
+    c64* Rbuf;
+    double* tmpb;
+    ARENA_ALLOC(scratch, Rbuf, chunk * 4 * P1);
+    ARENA_ALLOC(scratch, tmpb, chunk * (P1 + 2 * (p + 2)));
+    for (int64_t e0 = 0; e0 < P.n; e0 += chunk) {
+      int64_t ne = std::min(chunk, P.n - e0);
+      hipLaunchKernelGGL(k_p2m_l2p<R>, dim3(ceil_div(ne, 64)), dim3(64), 0, s, P.geo, P.n, e0, ne,
+                         P.elem_leaf, P.box_keys[L], L, dlo, P.h[L], k, P.alpha.re, P.alpha.im, p,
+                         dgc, dfinv, Rbuf, tmpb, D.p2m, D.l2p);
+      BEM_LAUNCH_CHECK();
+    }
+    BEM_HIP_TRY(hipStreamSynchronize(s));
+  }
+  return 0;
+}
+
+__global__ void k_geo_to_float(const double* __restrict__ g, int64_t cnt, float* __restrict__ f) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < cnt) f[i] = (float)g[i];
+}
+
+int build_operators(Problem& P, hipStream_t s) {
+  DevArena scratch;
+  struct Guard {
+    DevArena& a;
+    ~Guard() { a.release(); }
+  } guard{scratch};
+  if (P.L >= 2) {
+    int r = build_precision<double>(P, P.f64, true, scratch, s);
+    if (r) return r;
+    scratch.release();
+    r = build_precision<float>(P, P.f32, false, scratch, s);
+    if (r) return r;
+  }
+  // float geometry copy and work vectors
+  int64_t cnt = (int64_t)GEO_COUNT * P.n;
+  ARENA_ALLOC(P.arena, P.f32.geo, cnt);
+  hipLaunchKernelGGL(k_geo_to_float, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, P.geo, cnt, P.f32.geo);
+  BEM_LAUNCH_CHECK();
+  P.f64.geo = P.geo;
+  ARENA_ALLOC(P.arena, P.f64.ps, P.n);
+  ARENA_ALLOC(P.arena, P.f64.qs, P.n);
+  ARENA_ALLOC(P.arena, P.f64.ys, P.n);
+  ARENA_ALLOC(P.arena, P.f64.ys2, P.n);
+  ARENA_ALLOC(P.arena, P.f32.ps, P.n);
+  ARENA_ALLOC(P.arena, P.f32.qs, P.n);
+  ARENA_ALLOC(P.arena, P.f32.ys, P.n);
+  ARENA_ALLOC(P.arena, P.f32.ys2, P.n);
+  ARENA_ALLOC(P.arena, P.p64s, P.n);
+  ARENA_ALLOC(P.arena, P.q64s, P.n);
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+}  // namespace bemfmm

@@ -1,0 +1,174 @@
+// Internal plan state shared by the translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace bemfmm {
+
+constexpr int NBITS = 21;        // Morton bits per axis
+constexpr int MAX_LEVEL = 21;
+constexpr int N_OFFSETS = 343;   // 7^3 translation-vector slots, (dx+3)*49+(dy+3)*7+(dz+3)
+constexpr int NEAR_RULE = 8;     // near-singular rule: 8 x 8 collapsed Gauss points
+constexpr int SELF_RULE = 64;    // self terms: Gauss points per edge angle
+
+// Device allocation registry: every buffer a problem owns.
+struct DevArena {
+  std::vector<void*> ptrs;
+  int64_t bytes = 0;
+  int alloc(void** p, size_t n);  // returns 0 or BEM_E_OOM
+  void release();
+};
+
+// A grouped gather-GEMM-scatter job: for pair t in group g,
+//   dst[pair_dst[t]] += op_g * src[pair_src[t]]
+// op_g is a (rows x cols) complex matrix, row-major.  Tiles enumerate
+// (group, first pair, first row) blocks.
+template <typename R>
+struct GroupedOp {
+  int rows = 0, cols = 0;          // output / input coefficient counts
+  int n_pairs = 0, n_tiles = 0;
+  int* pair_dst = nullptr;         // device, grouped by g, ascending dst within g
+  int* pair_src = nullptr;
+  int* tile_group = nullptr;       // device, per tile
+  int* tile_pair0 = nullptr;
+  int* tile_npairs = nullptr;
+  int* tile_row0 = nullptr;
+  int* group_slot = nullptr;       // device: group id -> matrix slot
+  cplx<R>* mats = nullptr;         // device: n_slots x rows x cols
+  int n_slots = 0;
+  // adjoint: dst/src swapped, op conjugate-transposed (rows <-> cols)
+  int n_tiles_adj = 0;
+  int* tile_group_adj = nullptr;
+  int* tile_pair0_adj = nullptr;
+  int* tile_npairs_adj = nullptr;
+  int* tile_row0_adj = nullptr;
+  int* pair_dst_adj = nullptr;     // pairs regrouped for the adjoint (dst = old src)
+  int* pair_src_adj = nullptr;
+};
+
+template <typename R>
+struct PrecisionData {
+  std::array<int, MAX_LEVEL + 1> order{};   // p_l
+  std::array<int, MAX_LEVEL + 1> ncoef{};   // (p_l + 1)^2
+  std::array<cplx<R>*, MAX_LEVEL + 1> M{};  // multipole (box-major, ncoef per box)
+  std::array<cplx<R>*, MAX_LEVEL + 1> Lc{}; // local
+  std::array<GroupedOp<R>, MAX_LEVEL + 1> m2l{};
+  std::array<GroupedOp<R>, MAX_LEVEL + 1> m2m{};  // level l -> l-1 (index l)
+  std::array<GroupedOp<R>, MAX_LEVEL + 1> l2l{};  // level l-1 -> l (index l)
+  cplx<R>* p2m = nullptr;   // n x ncoef_L x 2 (columns: p, q), sorted order
+  cplx<R>* l2p = nullptr;   // n x ncoef_L
+  // near-field corrections (accurate - 3-point rule), CSR by target and
+  // CSC by source (both sorted order)
+  cplx<R>* near_cp = nullptr;
+  cplx<R>* near_cq = nullptr;
+  cplx<R>* neart_cp = nullptr;
+  cplx<R>* neart_cq = nullptr;
+  // work vectors (sorted order)
+  cplx<R>* ps = nullptr;
+  cplx<R>* qs = nullptr;
+  cplx<R>* ys = nullptr;
+  cplx<R>* ys2 = nullptr;
+  // float geometry (sorted order) for the direct near field
+  R* geo = nullptr;         // SoA, see GEO_* offsets
+};
+
+// SoA geometry layout offsets (multiples of n)
+enum {
+  GEO_CX = 0, GEO_CY, GEO_CZ, GEO_NX, GEO_NY, GEO_NZ, GEO_AREA, GEO_ELL,
+  GEO_QX0, GEO_QY0, GEO_QZ0, GEO_QX1, GEO_QY1, GEO_QZ1, GEO_QX2, GEO_QY2, GEO_QZ2,
+  GEO_AX, GEO_AY, GEO_AZ, GEO_BX, GEO_BY, GEO_BZ, GEO_CXV, GEO_CYV, GEO_CZV,
+  GEO_COUNT
+};
+
+struct Problem {
+  int64_t n = 0;
+  double k = 0;
+  c64 alpha{0, 0};
+  double eta = 2.0;
+  int leaf_cap = 64, leaf_level_req = 0, order64_req = 0, order32_req = 0;
+  DevArena arena;
+  // geometry, sorted order, float64 SoA (GEO_COUNT x n)
+  double* geo = nullptr;
+  int* perm = nullptr;            // sorted position -> caller index
+  uint64_t* keys_orig = nullptr;  // Morton keys in caller order
+  uint64_t* keys_sorted = nullptr;
+  // bounding cube
+  double lo[3]{}, R0 = 0, scale = 0, ell_max = 0;
+  // tree
+  int L = 0;
+  std::array<int, MAX_LEVEL + 1> nbox{};
+  std::array<uint64_t*, MAX_LEVEL + 1> box_keys{};
+  std::array<int*, MAX_LEVEL + 1> box_start{};   // first sorted element (nbox+1 entries)
+  std::array<int*, MAX_LEVEL + 1> box_parent{};
+  std::array<double, MAX_LEVEL + 1> h{};          // box side per level
+  std::array<int64_t, MAX_LEVEL + 1> n_m2l{};
+  int* elem_leaf = nullptr;                        // sorted element -> leaf
+  int* u_ptr = nullptr;                            // leaf U lists (CSR)
+  int* u_idx = nullptr;
+  int64_t n_u = 0, n_p2p_pairs = 0;
+  // near field (sorted order)
+  int64_t n_near = 0;
+  int* near_ptr = nullptr;   // n + 1
+  int* near_col = nullptr;
+  int* neart_ptr = nullptr;  // n + 1
+  int* neart_row = nullptr;
+  c64* diag_p = nullptr;     // 1/2 - alpha H_ii
+  c64* diag_q = nullptr;     // S_ii + alpha/2
+  PrecisionData<double> f64;
+  PrecisionData<float> f32;
+  // float64 input copies for the diagonal (sorted order)
+  c64* p64s = nullptr;
+  c64* q64s = nullptr;
+  // solver workspace (Krylov basis etc.), owned, see solver.hip
+  void* solver_ws = nullptr;
+  // stage profiling with HIP events (off unless enabled)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_slot;   // slot of each recorded (start, end) pair
+  int ev_used = 0;
+};
+
+// profiling slots: stage + 8 * precision (0: float64, 1: float32) + 16 * adjoint
+enum { ST_GATHER = 0, ST_P2P, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_FINISH, ST_COUNT };
+constexpr int PROF_SLOTS = 32;
+int prof_begin(Problem& P, hipStream_t s);                 // returns event index or -1
+int prof_end(Problem& P, int idx, int slot, hipStream_t s);
+
+struct Plan {
+  std::vector<Problem*> probs;
+};
+
+// ---- host entry points implemented in the .hip translation units ----
+int build_geometry_and_tree(Problem& P, const double* vert, int64_t n_vert, const int32_t* tri,
+                            hipStream_t s);
+int build_near_field(Problem& P, hipStream_t s);
+int build_operators(Problem& P, hipStream_t s);
+template <typename R>
+int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* y,
+              hipStream_t s);
+template <typename R>
+int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64* w,
+                      hipStream_t s);
+int sort_pairs_u64(uint64_t* keys, int* vals, int n, int nbits, DevArena& scratch,
+                   hipStream_t s);
+int exclusive_scan(const int* in, int* out, int n, int* total, DevArena& scratch, hipStream_t s);
+
+// solver helpers
+int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x,
+                double tol, int restart, int max_iter, int mode, double inner_tol, int use_x0,
+                void* info, hipStream_t s);
+int plane_wave_rhs(Problem& P, const double* d, c64* b, hipStream_t s);
+int eval_field(Problem& P, const c64* p, const c64* q, const double* pts, int n_pts,
+               const double* d, c64* out, hipStream_t s);
+int eval_field_adjoint(Problem& P, const double* pts, int n_pts, const c64* c, c64* rp,
+                       c64* rq, hipStream_t s);
+void release_workspace(Problem& P);
+
+}  // namespace bemfmm

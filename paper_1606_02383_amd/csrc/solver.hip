@@ -1,0 +1,724 @@
+// GMRES(m) in float64 on device vectors, mixed-precision iterative
+// refinement, plane-wave right-hand sides, the field representation at
+// exterior points, and the objective J = sum |p(x_m)|^2 with its
+// discrete-adjoint gradient.
+//
+// GMRES is the paper's iterative solver (Sec. 2.3 step 2; Sec. 3, tolerance
+// there 1e-5).  Arnoldi uses classical Gram-Schmidt with one
+// re-orthogonalisation (CGS2): two multi-dot and two multi-update kernels per
+// step instead of 2(j+1) launches; reductions are deterministic two-stage
+// sums.  The small Hessenberg least-squares problem (Givens rotations) is
+// solved on the host from one (j+2)-entry column per step.  The exit test
+// is the true relative residual ||b - A x|| / ||b|| recomputed with the
+// float64 operator.
+#include <cmath>
+#include <complex>
+#include <functional>
+#include <vector>
+
+#include "../../include/bemfmm.h"
+#include "plan.h"
+
+namespace bemfmm {
+
+#define ARENA_ALLOC(arena, ptr, count)                                              \
+  do {                                                                              \
+    int _r = (arena).alloc((void**)&(ptr), sizeof(*(ptr)) * (size_t)(count));      \
+    if (_r) return _r;                                                              \
+  } while (0)
+
+constexpr int RED_BLOCKS = 128;
+constexpr int RED_THREADS = 256;
+
+// partial[k * RED_BLOCKS + bx] = sum_{i in block bx} conj(V_k[i]) w[i]
+__global__ void k_multidot_partial(const c64* __restrict__ V, int64_t ld, int64_t n,
+                                   const c64* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double sr[RED_THREADS], si[RED_THREADS];
+  int kvec = blockIdx.y;
+  const c64* v = V + kvec * ld;
+  double ar = 0, ai = 0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n;
+       i += (int64_t)RED_BLOCKS * RED_THREADS) {
+    c64 a = v[i], b = w[i];
+    ar += a.re * b.re + a.im * b.im;
+    ai += a.re * b.im - a.im * b.re;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * (kvec * RED_BLOCKS + blockIdx.x)] = sr[0];
+    partial[2 * (kvec * RED_BLOCKS + blockIdx.x) + 1] = si[0];
+  }
+}
+
+// out[k] (+)= sum_bx partial[k][bx]   (accumulate != 0 adds to out)
+__global__ void k_multidot_final(const double* __restrict__ partial, int nk,
+                                 c64* __restrict__ out, int accumulate) {
+  __shared__ double sr[RED_BLOCKS], si[RED_BLOCKS];
+  int kvec = blockIdx.x;
+  int t = threadIdx.x;
+  sr[t] = partial[2 * (kvec * RED_BLOCKS + t)];
+  si[t] = partial[2 * (kvec * RED_BLOCKS + t) + 1];
+  __syncthreads();
+  for (int s = RED_BLOCKS / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      sr[t] += sr[t + s];
+      si[t] += si[t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (accumulate) {
+      out[kvec].re += sr[0];
+      out[kvec].im += si[0];
+    } else {
+      out[kvec] = mk(sr[0], si[0]);
+    }
+  }
+}
+
+// w -= sum_k V_k h_k
+__global__ void k_multiupdate(const c64* __restrict__ V, int64_t ld, int64_t n, int nk,
+                              const c64* __restrict__ h, c64* __restrict__ w) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  c64 acc = w[i];
+  for (int kk = 0; kk < nk; ++kk) {
+    c64 v = V[kk * ld + i], c = h[kk];
+    acc.re -= v.re * c.re - v.im * c.im;
+    acc.im -= v.re * c.im + v.im * c.re;
+  }
+  w[i] = acc;
+}
+
+// dst = src / |h|  where h = out[0] holds ||w||^2 in its real part
+__global__ void k_normalise(const c64* __restrict__ src, int64_t n, const c64* __restrict__ nrm2,
+                            c64* __restrict__ dst) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = sqrt(nrm2[0].re);
+  double inv = (s > 0.0) ? 1.0 / s : 0.0;
+  dst[i] = mk(src[i].re * inv, src[i].im * inv);
+}
+
+// x += sum_k V_k y_k
+__global__ void k_combine(const c64* __restrict__ V, int64_t ld, int64_t n, int nk,
+                          const c64* __restrict__ y, c64* __restrict__ x) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  c64 acc = x[i];
+  for (int kk = 0; kk < nk; ++kk) cfma(acc, V[kk * ld + i], y[kk]);
+  x[i] = acc;
+}
+
+// r = b - a
+__global__ void k_sub(const c64* __restrict__ b, const c64* __restrict__ a, int64_t n,
+                      c64* __restrict__ r) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) r[i] = csub(b[i], a[i]);
+}
+
+// out = s * v (elementwise), conj_s conjugates s
+__global__ void k_diag_mul(const c64* __restrict__ sg, const c64* __restrict__ v, int64_t n,
+                           int conj_s, c64* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  c64 s = sg[i];
+  if (conj_s) s.im = -s.im;
+  out[i] = cmul(s, v[i]);
+}
+
+// out = a + conj(s) * b
+__global__ void k_add_conj_diag(const c64* __restrict__ a, const c64* __restrict__ sg,
+                                const c64* __restrict__ b, int64_t n, c64* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  c64 r = a[i];
+  cfmac(r, sg[i], b[i]);
+  out[i] = r;
+}
+
+__global__ void k_copy(const c64* __restrict__ a, int64_t n, c64* __restrict__ b) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void k_axpy(const c64* __restrict__ a, int64_t n, c64* __restrict__ b) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = cadd(b[i], a[i]);
+}
+
+__global__ void k_set_zero(c64* __restrict__ a, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = mk(0.0, 0.0);
+}
+
+__global__ void k_scale(c64* __restrict__ a, int64_t n, double s) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = cscale(a[i], s);
+}
+
+struct Workspace {
+  DevArena arena;
+  int64_t n = 0;
+  int m = 0;
+  c64* V = nullptr;     // (m+1) x n
+  c64* w = nullptr;
+  c64* t1 = nullptr;
+  c64* t2 = nullptr;
+  c64* t3 = nullptr;
+  c64* r = nullptr;
+  c64* d = nullptr;
+  c64* rr = nullptr;
+  c64* h = nullptr;     // m+2
+  c64* h2 = nullptr;
+  c64* y = nullptr;
+  double* partial = nullptr;
+  int ensure(int64_t n_, int m_) {
+    if (n_ == n && m_ <= m) return 0;
+    arena.release();
+    n = n_;
+    m = m_;
+    ARENA_ALLOC(arena, V, (int64_t)(m + 1) * n);
+    ARENA_ALLOC(arena, w, n);
+    ARENA_ALLOC(arena, t1, n);
+    ARENA_ALLOC(arena, t2, n);
+    ARENA_ALLOC(arena, t3, n);
+    ARENA_ALLOC(arena, r, n);
+    ARENA_ALLOC(arena, d, n);
+    ARENA_ALLOC(arena, rr, n);
+    ARENA_ALLOC(arena, h, m + 2);
+    ARENA_ALLOC(arena, h2, m + 2);
+    ARENA_ALLOC(arena, y, m + 2);
+    ARENA_ALLOC(arena, partial, 2 * (int64_t)RED_BLOCKS * (m + 2));
+    return 0;
+  }
+};
+
+static Workspace& workspace_for(Problem& P) {
+  if (!P.solver_ws) P.solver_ws = new Workspace();
+  return *(Workspace*)P.solver_ws;
+}
+
+// dots out[k] = V_k^H w for k < nk
+static int multidot(Workspace& W, const c64* V, int64_t ld, int64_t n, int nk, const c64* w,
+                    c64* out, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(k_multidot_partial, dim3(RED_BLOCKS, nk), dim3(RED_THREADS), 0, s, V, ld, n, w,
+                     W.partial);
+  BEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_multidot_final, dim3(nk), dim3(RED_BLOCKS), 0, s, W.partial, nk, out,
+                     accumulate);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+static int norm2(Workspace& W, const c64* v, int64_t n, double* out, hipStream_t s) {
+  int r = multidot(W, v, n, n, 1, v, W.h2, 0, s);
+  if (r) return r;
+  c64 h;
+  BEM_HIP_TRY(hipMemcpyAsync(&h, W.h2, sizeof(c64), hipMemcpyDeviceToHost, s));
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  *out = sqrt(h.re);
+  return 0;
+}
+
+typedef std::function<int(const c64*, c64*)> ApplyFn;
+
+struct GmresStats {
+  int iters = 0, restarts = 0;
+  double est = 0;
+  std::vector<double> hist;
+};
+
+// GMRES(m) on apply, x in/out; stops when the (estimated, then recomputed
+// with `apply`) residual <= atol or after max_iter steps.
+// Returns 0, or BEM_E_NOCONV / BEM_E_NAN / BEM_E_BREAKDOWN / error.
+static int gmres_core(Workspace& W, const ApplyFn& apply, const c64* b, c64* x, int64_t n,
+                      double atol, int m, int max_iter, bool x_is_zero, GmresStats& st,
+                      hipStream_t s) {
+  const int nb = ceil_div(n, 256);
+  double beta = 0;
+  int r;
+  // r = b - A x
+  if (x_is_zero) {
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, b, n, W.r);
+    BEM_LAUNCH_CHECK();
+  } else {
+    if ((r = apply(x, W.t1))) return r;
+    hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, s, b, W.t1, n, W.r);
+    BEM_LAUNCH_CHECK();
+  }
+  if ((r = norm2(W, W.r, n, &beta, s))) return r;
+  st.est = beta;
+  if (!std::isfinite(beta)) return -6;
+  if (beta <= atol) return 0;
+  std::vector<std::complex<double>> H((m + 1) * m), cs(m), sn(m), g(m + 1);
+  std::vector<c64> hcol(2 * m + 4);
+  while (st.iters < max_iter) {
+    // V_0 = r / beta
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, W.r, n, W.V);
+    BEM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, s, W.V, n, 1.0 / beta);
+    BEM_LAUNCH_CHECK();
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    bool done = false;
+    for (int j = 0; j < m && st.iters < max_iter; ++j) {
+      if ((r = apply(W.V + (int64_t)j * n, W.w))) return r;
+      ++st.iters;
+      // CGS2
+      if ((r = multidot(W, W.V, n, n, j + 1, W.w, W.h, 0, s))) return r;
+      hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, s, W.V, n, n, j + 1, W.h, W.w);
+      BEM_LAUNCH_CHECK();
+      if ((r = multidot(W, W.V, n, n, j + 1, W.w, W.h2, 0, s))) return r;
+      hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, s, W.V, n, n, j + 1, W.h2, W.w);
+      BEM_LAUNCH_CHECK();
+      if ((r = multidot(W, W.w, n, n, 1, W.w, W.h2 + j + 1, 0, s))) return r;
+      hipLaunchKernelGGL(k_normalise, dim3(nb), dim3(256), 0, s, W.w, n, W.h2 + j + 1,
+                         W.V + (int64_t)(j + 1) * n);
+      BEM_LAUNCH_CHECK();
+      BEM_HIP_TRY(hipMemcpyAsync(hcol.data(), W.h, sizeof(c64) * (j + 1), hipMemcpyDeviceToHost, s));
+      BEM_HIP_TRY(hipMemcpyAsync(hcol.data() + j + 1, W.h2, sizeof(c64) * (j + 2),
+                                 hipMemcpyDeviceToHost, s));
+      BEM_HIP_TRY(hipStreamSynchronize(s));
+      // h = first pass + second pass; h_{j+1} = ||w||
+      std::vector<std::complex<double>> col(j + 2);
+      for (int i = 0; i <= j; ++i)
+        col[i] = std::complex<double>(hcol[i].re + hcol[j + 1 + i].re, hcol[i].im + hcol[j + 1 + i].im);
+      double hn = sqrt(hcol[j + 1 + j + 1].re);
+      col[j + 1] = hn;
+      if (!std::isfinite(hn)) return -6;
+      for (int i = 0; i < j; ++i) {
+        std::complex<double> t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -std::conj(sn[i]) * col[i] + std::conj(cs[i]) * col[i + 1];
+        col[i] = t;
+      }
+      double den = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
+      if (den == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        cs[j] = std::conj(col[j]) / den;
+        sn[j] = std::conj(col[j + 1]) / den;
+      }
+      col[j] = cs[j] * col[j] + sn[j] * col[j + 1];
+      col[j + 1] = 0.0;
+      g[j + 1] = -std::conj(sn[j]) * g[j];
+      g[j] = cs[j] * g[j];
+      for (int i = 0; i <= j; ++i) H[i * m + j] = col[i];
+      jend = j + 1;
+      st.est = std::abs(g[j + 1]);
+      st.hist.push_back(st.est);
+      if (st.est <= atol || hn == 0.0) {
+        done = true;
+        break;
+      }
+    }
+    // y = H^-1 g (upper triangular)
+    std::vector<std::complex<double>> yv(jend);
+    for (int i = jend - 1; i >= 0; --i) {
+      std::complex<double> acc = g[i];
+      for (int kk = i + 1; kk < jend; ++kk) acc -= H[i * m + kk] * yv[kk];
+      if (std::abs(H[i * m + i]) == 0.0) return -5;
+      yv[i] = acc / H[i * m + i];
+    }
+    std::vector<c64> yh(jend);
+    for (int i = 0; i < jend; ++i) yh[i] = mk(yv[i].real(), yv[i].imag());
+    BEM_HIP_TRY(hipMemcpyAsync(W.y, yh.data(), sizeof(c64) * jend, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, W.V, n, n, jend, W.y, x);
+    BEM_LAUNCH_CHECK();
+    // recompute the residual with the operator
+    if ((r = apply(x, W.t1))) return r;
+    hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, s, b, W.t1, n, W.r);
+    BEM_LAUNCH_CHECK();
+    if ((r = norm2(W, W.r, n, &beta, s))) return r;
+    st.est = beta;
+    if (!std::isfinite(beta)) return -6;
+    if (beta <= atol) return 0;
+    ++st.restarts;
+    (void)done;
+  }
+  return -4;
+}
+
+int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x, double tol,
+                int restart, int max_iter, int mode, double inner_tol, int use_x0, void* info_v,
+                hipStream_t s) {
+  bem_gmres_info* info = (bem_gmres_info*)info_v;
+  const int64_t n = P.n;
+  const int nb = ceil_div(n, 256);
+  Workspace& W = workspace_for(P);
+  int r = W.ensure(n, restart);
+  if (r) return r;
+  int mv64 = 0, mv32 = 0;
+  // operator application in a given precision, writes out = A v (or A^H v)
+  auto make_apply = [&](bool f32) -> ApplyFn {
+    return [&, f32](const c64* v, c64* out) -> int {
+      int rr;
+      if (!adjoint) {
+        const c64* q = nullptr;
+        if (sigma) {
+          hipLaunchKernelGGL(k_diag_mul, dim3(nb), dim3(256), 0, s, sigma, v, n, 0, W.t3);
+          BEM_LAUNCH_CHECK();
+          q = W.t3;
+        }
+        rr = f32 ? fmm_apply<float>(P, P.f32, v, q, out, s) : fmm_apply<double>(P, P.f64, v, q, out, s);
+        if (rr) return rr;
+      } else {
+        c64* wv = sigma ? W.t3 : nullptr;
+        rr = f32 ? fmm_apply_adjoint<float>(P, P.f32, v, out, wv, s)
+                 : fmm_apply_adjoint<double>(P, P.f64, v, out, wv, s);
+        if (rr) return rr;
+        if (sigma) {
+          hipLaunchKernelGGL(k_add_conj_diag, dim3(nb), dim3(256), 0, s, out, sigma, W.t3, n, out);
+          BEM_LAUNCH_CHECK();
+        }
+      }
+      if (f32)
+        ++mv32;
+      else
+        ++mv64;
+      return 0;
+    };
+  };
+  ApplyFn A64 = make_apply(false), A32 = make_apply(true);
+  double bn = 0;
+  if ((r = norm2(W, b, n, &bn, s))) return r;
+  GmresStats st;
+  int status = 0;
+  if (!use_x0) {
+    hipLaunchKernelGGL(k_set_zero, dim3(nb), dim3(256), 0, s, x, n);
+    BEM_LAUNCH_CHECK();
+  }
+  double resid = 0;
+  if (bn == 0.0) {
+    hipLaunchKernelGGL(k_set_zero, dim3(nb), dim3(256), 0, s, x, n);
+    BEM_LAUNCH_CHECK();
+  } else if (mode == 0) {
+    status = gmres_core(W, A64, b, x, n, tol * bn, restart, max_iter, !use_x0, st, s);
+    resid = st.est / bn;
+  } else {
+    // iterative refinement: outer float64 residual, inner float32 operator
+    c64* rvec = W.rr;
+    c64* dvec = W.d;
+    int outer = 0;
+    status = -4;
+    bool xzero = !use_x0;
+    while (outer < 30 && st.iters < max_iter) {
+      if (xzero) {
+        hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, b, n, rvec);
+        BEM_LAUNCH_CHECK();
+      } else {
+        if ((r = A64(x, W.t1))) return r;
+        hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, s, b, W.t1, n, rvec);
+        BEM_LAUNCH_CHECK();
+      }
+      double rn = 0;
+      if ((r = norm2(W, rvec, n, &rn, s))) return r;
+      resid = rn / bn;
+      st.hist.push_back(rn);
+      if (!std::isfinite(rn)) {
+        status = -6;
+        break;
+      }
+      if (resid <= tol) {
+        status = 0;
+        break;
+      }
+      GmresStats in;
+      in.iters = 0;
+      hipLaunchKernelGGL(k_set_zero, dim3(nb), dim3(256), 0, s, dvec, n);
+      BEM_LAUNCH_CHECK();
+      double itol = inner_tol > 0 ? inner_tol : 1e-4;
+      int ist = gmres_core(W, A32, rvec, dvec, n, itol * rn, restart, max_iter - st.iters, true,
+                           in, s);
+      st.iters += in.iters;
+      for (double h : in.hist) st.hist.push_back(h);
+      if (ist && ist != -4) {
+        status = ist;
+        break;
+      }
+      hipLaunchKernelGGL(k_axpy, dim3(nb), dim3(256), 0, s, dvec, n, x);
+      BEM_LAUNCH_CHECK();
+      xzero = false;
+      ++outer;
+      st.restarts = outer;
+    }
+  }
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  if (info) {
+    info->iterations = st.iters;
+    info->matvec64 = mv64;
+    info->matvec32 = mv32;
+    info->restarts = st.restarts;
+    info->resid = resid;
+    info->converged = (status == 0);
+    int nh = std::min((int)st.hist.size(), 512);
+    info->n_hist = nh;
+    for (int i = 0; i < nh; ++i) info->hist[i] = st.hist[i] / (bn > 0 ? bn : 1.0);
+  }
+  if (status == -4) set_error("GMRES did not reach the tolerance within max_iter");
+  if (status == -5) set_error("GMRES breakdown");
+  if (status == -6) set_error("NaN or Inf met in GMRES");
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// right-hand side, field representation, objective
+// ---------------------------------------------------------------------------
+__global__ void k_plane_wave(const double* __restrict__ g, int64_t n, const int* __restrict__ perm,
+                             double k, double alr, double ali, double dx, double dy, double dz,
+                             c64* __restrict__ b) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double ph = k * (dx * g[GEO_CX * n + i] + dy * g[GEO_CY * n + i] + dz * g[GEO_CZ * n + i]);
+  double dn = dx * g[GEO_NX * n + i] + dy * g[GEO_NY * n + i] + dz * g[GEO_NZ * n + i];
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  c64 e = mk(cs, sn);
+  // 1 + alpha * i k d.n
+  c64 f = mk(1.0 - ali * k * dn, alr * k * dn);
+  b[perm[i]] = cmul(e, f);
+}
+
+int plane_wave_rhs(Problem& P, const double* d, c64* b, hipStream_t s) {
+  double nrm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  if (!(nrm > 0)) {
+    set_error("zero incidence direction");
+    return -1;
+  }
+  hipLaunchKernelGGL(k_plane_wave, dim3(ceil_div(P.n, 256)), dim3(256), 0, s, P.geo, P.n, P.perm,
+                     P.k, P.alpha.re, P.alpha.im, d[0] / nrm, d[1] / nrm, d[2] / nrm, b);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+constexpr double INV4PI = 0.07957747154594767;
+
+// one block per point: out_m = inc + sum_j sum_q w [G_y p_j - G q_j]
+__global__ void k_eval_field(const double* __restrict__ g, int64_t n, const int* __restrict__ perm,
+                             const c64* __restrict__ p, const c64* __restrict__ q,
+                             const double* __restrict__ pts, double k, int has_inc, double dx,
+                             double dy, double dz, c64* __restrict__ out) {
+  __shared__ double sr[256], si[256];
+  int m = blockIdx.x;
+  double x0 = pts[3 * m], x1 = pts[3 * m + 1], x2 = pts[3 * m + 2];
+  double ar = 0, ai = 0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    int o = perm[j];
+    c64 pj = p[o], qj = q ? q[o] : mk(0.0, 0.0);
+    double w = g[GEO_AREA * n + j] / 3.0 * INV4PI;
+    double nyx = g[GEO_NX * n + j], nyy = g[GEO_NY * n + j], nyz = g[GEO_NZ * n + j];
+    for (int qq = 0; qq < 3; ++qq) {
+      double rx = x0 - g[(GEO_QX0 + 3 * qq) * n + j];
+      double ry = x1 - g[(GEO_QX0 + 3 * qq + 1) * n + j];
+      double rz = x2 - g[(GEO_QX0 + 3 * qq + 2) * n + j];
+      double r = sqrt(rx * rx + ry * ry + rz * rz), u = 1.0 / r;
+      double sn, cs;
+      sincos(k * r, &sn, &cs);
+      c64 G = mk(cs * u * w, sn * u * w);
+      // G_y = -G (ik - u) u (rv.n_y)
+      double rny = rx * nyx + ry * nyy + rz * nyz;
+      c64 Gy = cscale(cmul(G, mk(-u, k)), -u * rny);
+      c64 v = csub(cmul(Gy, pj), cmul(G, qj));
+      ar += v.re;
+      ai += v.im;
+    }
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sr[threadIdx.x] += sr[threadIdx.x + st];
+      si[threadIdx.x] += si[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    c64 v = mk(sr[0], si[0]);
+    if (has_inc) {
+      double sn, cs;
+      sincos(k * (dx * x0 + dy * x1 + dz * x2), &sn, &cs);
+      v = cadd(v, mk(cs, sn));
+    }
+    out[m] = v;
+  }
+}
+
+// rp_j = sum_m conj(Khat_mj) c_m,  rq_j = -sum_m conj(Shat_mj) c_m
+__global__ void k_eval_field_adj(const double* __restrict__ g, int64_t n,
+                                 const int* __restrict__ perm, const double* __restrict__ pts,
+                                 int npts, double k, const c64* __restrict__ c,
+                                 c64* __restrict__ rp, c64* __restrict__ rq) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double w = g[GEO_AREA * n + j] / 3.0 * INV4PI;
+  double nyx = g[GEO_NX * n + j], nyy = g[GEO_NY * n + j], nyz = g[GEO_NZ * n + j];
+  c64 ap = mk(0.0, 0.0), aq = mk(0.0, 0.0);
+  for (int m = 0; m < npts; ++m) {
+    c64 K = mk(0.0, 0.0), S = mk(0.0, 0.0);
+    for (int qq = 0; qq < 3; ++qq) {
+      double rx = pts[3 * m] - g[(GEO_QX0 + 3 * qq) * n + j];
+      double ry = pts[3 * m + 1] - g[(GEO_QX0 + 3 * qq + 1) * n + j];
+      double rz = pts[3 * m + 2] - g[(GEO_QX0 + 3 * qq + 2) * n + j];
+      double r = sqrt(rx * rx + ry * ry + rz * rz), u = 1.0 / r;
+      double sn, cs;
+      sincos(k * r, &sn, &cs);
+      c64 G = mk(cs * u * w, sn * u * w);
+      double rny = rx * nyx + ry * nyy + rz * nyz;
+      K = cadd(K, cscale(cmul(G, mk(-u, k)), -u * rny));
+      S = cadd(S, G);
+    }
+    cfmac(ap, K, c[m]);
+    cfmac(aq, S, c[m]);
+  }
+  int o = perm[j];
+  rp[o] = ap;
+  if (rq) rq[o] = mk(-aq.re, -aq.im);
+}
+
+int eval_field(Problem& P, const c64* p, const c64* q, const double* pts, int n_pts,
+               const double* d, c64* out, hipStream_t s) {
+  if (n_pts <= 0) return 0;
+  double dx = 0, dy = 0, dz = 0;
+  if (d) {
+    double nrm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(nrm > 0)) {
+      set_error("zero incidence direction");
+      return -1;
+    }
+    dx = d[0] / nrm;
+    dy = d[1] / nrm;
+    dz = d[2] / nrm;
+  }
+  hipLaunchKernelGGL(k_eval_field, dim3(n_pts), dim3(256), 0, s, P.geo, P.n, P.perm, p, q, pts,
+                     P.k, d ? 1 : 0, dx, dy, dz, out);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+int eval_field_adjoint(Problem& P, const double* pts, int n_pts, const c64* c, c64* rp, c64* rq,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_eval_field_adj, dim3(ceil_div(P.n, 128)), dim3(128), 0, s, P.geo, P.n,
+                     P.perm, pts, n_pts, P.k, c, rp, rq);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+// sigma = -i k beta
+__global__ void k_sigma(const c64* __restrict__ beta, int64_t n, double k, c64* __restrict__ sg) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) sg[i] = mk(k * beta[i].im, -k * beta[i].re);
+}
+
+// J = sum |p_obs|^2 (one block)
+__global__ void k_objective(const c64* __restrict__ pobs, int npts, double* __restrict__ J) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0;
+    for (int m = 0; m < npts; ++m) s += pobs[m].re * pobs[m].re + pobs[m].im * pobs[m].im;
+    *J = s;
+  }
+}
+
+// rhs = rp + conj(sigma) rq
+__global__ void k_adj_rhs(const c64* __restrict__ rp, const c64* __restrict__ rq,
+                          const c64* __restrict__ sg, int64_t n, c64* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  c64 v = rp[i];
+  cfmac(v, sg[i], rq[i]);
+  out[i] = v;
+}
+
+// g = -conj(w) + conj(rq);  grad = 2 Re(-i k g p) + i 2 Re(k g p)
+__global__ void k_grad(const c64* __restrict__ w, const c64* __restrict__ rq,
+                       const c64* __restrict__ p, int64_t n, double k, c64* __restrict__ grad) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  c64 gg = mk(-w[i].re + rq[i].re, w[i].im - rq[i].im);
+  c64 gp = cmul(gg, p[i]);
+  // -i k gp = k (gp.im - i gp.re) -> real part k gp.im
+  grad[i] = mk(2.0 * k * gp.im, 2.0 * k * gp.re);
+}
+
+int objective_grad(Problem& P, const c64* beta, const double* dir, const double* pts_host,
+                   int n_pts, const bem_gmres_opts* opts, double* J, c64* grad, c64* p_out,
+                   bem_gmres_info* info_f, bem_gmres_info* info_a, hipStream_t s) {
+  const int64_t n = P.n;
+  const int nb = ceil_div(n, 256);
+  DevArena tmp;
+  struct G {
+    DevArena& a;
+    ~G() { a.release(); }
+  } guard{tmp};
+  c64 *sg, *b, *p, *q, *pobs, *rp, *rq, *rhs, *mu, *u, *w;
+  double *pts, *dJ;
+  ARENA_ALLOC(tmp, sg, n);
+  ARENA_ALLOC(tmp, b, n);
+  ARENA_ALLOC(tmp, p, n);
+  ARENA_ALLOC(tmp, q, n);
+  ARENA_ALLOC(tmp, pobs, n_pts);
+  ARENA_ALLOC(tmp, rp, n);
+  ARENA_ALLOC(tmp, rq, n);
+  ARENA_ALLOC(tmp, rhs, n);
+  ARENA_ALLOC(tmp, mu, n);
+  ARENA_ALLOC(tmp, u, n);
+  ARENA_ALLOC(tmp, w, n);
+  ARENA_ALLOC(tmp, pts, 3 * n_pts);
+  ARENA_ALLOC(tmp, dJ, 1);
+  BEM_HIP_TRY(hipMemcpyAsync(pts, pts_host, sizeof(double) * 3 * n_pts, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_sigma, dim3(nb), dim3(256), 0, s, beta, n, P.k, sg);
+  BEM_LAUNCH_CHECK();
+  int r = plane_wave_rhs(P, dir, b, s);
+  if (r) return r;
+  bem_gmres_opts o = *opts;
+  r = gmres_solve(P, sg, 0, b, p, o.tol, o.restart > 0 ? o.restart : 50,
+                  o.max_iter > 0 ? o.max_iter : 2000, o.mode, o.inner_tol, 0, info_f, s);
+  if (r) return r;
+  hipLaunchKernelGGL(k_diag_mul, dim3(nb), dim3(256), 0, s, sg, p, n, 0, q);
+  BEM_LAUNCH_CHECK();
+  if ((r = eval_field(P, p, q, pts, n_pts, dir, pobs, s))) return r;
+  hipLaunchKernelGGL(k_objective, dim3(1), dim3(64), 0, s, pobs, n_pts, dJ);
+  BEM_LAUNCH_CHECK();
+  BEM_HIP_TRY(hipMemcpyAsync(J, dJ, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (p_out) {
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, p, n, p_out);
+    BEM_LAUNCH_CHECK();
+  }
+  if (grad) {
+    // conj(rhs_T) = rp + conj(sigma) rq with rp, rq from c = p_obs
+    if ((r = eval_field_adjoint(P, pts, n_pts, pobs, rp, rq, s))) return r;
+    hipLaunchKernelGGL(k_adj_rhs, dim3(nb), dim3(256), 0, s, rp, rq, sg, n, rhs);
+    BEM_LAUNCH_CHECK();
+    r = gmres_solve(P, sg, 1, rhs, mu, o.tol, o.restart > 0 ? o.restart : 50,
+                    o.max_iter > 0 ? o.max_iter : 2000, o.mode, o.inner_tol, 0, info_a, s);
+    if (r) return r;
+    // w = Mq^H mu (float64 adjoint product)
+    if ((r = fmm_apply_adjoint<double>(P, P.f64, mu, u, w, s))) return r;
+    hipLaunchKernelGGL(k_grad, dim3(nb), dim3(256), 0, s, w, rq, p, n, P.k, grad);
+    BEM_LAUNCH_CHECK();
+  }
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+void release_workspace(Problem& P) {
+  if (P.solver_ws) {
+    Workspace* W = (Workspace*)P.solver_ws;
+    W->arena.release();
+    delete W;
+    P.solver_ws = nullptr;
+  }
+}
+
+}  // namespace bemfmm

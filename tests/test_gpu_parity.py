@@ -1,0 +1,204 @@
+"""GPU parity tests: the HIP library (through its C ABI) against the CPU oracle.
+
+Sizes: the 1280-element sphere at k = 1 (every element compared), plus
+smaller and ragged meshes; the large workloads are covered in
+test_gpu_scale.py on sampled rows.
+"""
+import numpy as np
+import pytest
+
+from oracle import bem as obem
+from oracle import mie, solve
+from oracle import tree as otree
+from workloads import complex_normal, cube_surface, icosphere, unit_directions
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1606_02383_amd as bem
+    bem.load_library()
+    return bem
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def sphere1280():
+    V, T = icosphere(3)
+    g = obem.Geometry(V, T)
+    k = 1.0
+    Mp, Mq = obem.bm_blocks(g, k, 1j / k)
+    return V, T, g, k, Mp, Mq
+
+
+@pytest.fixture(scope="module")
+def plan1280(sphere1280):
+    bem = _lib()
+    V, T, g, k, Mp, Mq = sphere1280
+    _log("plan: sphere 1280, k=1, auto orders")
+    return bem.Plan(bem.Problem(V, T, k, leaf_cap=32))
+
+
+def test_tree_bit_exact_sphere1280(sphere1280, plan1280):
+    V, T, g, k, _, _ = sphere1280
+    _log("case: tree bit-exact sphere1280")
+    keys, perm = plan1280.tree_export()
+    keys = keys.cpu().numpy().astype(np.uint64)
+    perm = perm.cpu().numpy()
+    t = otree.Tree(g.cen, leaf_cap=32, ell_max=float(g.ell.max()))
+    assert [int(x) for x in keys] == t.keys
+    assert perm.tolist() == t.perm
+    st = plan1280.stats()
+    assert st["leaf_level"] == t.L
+    lk, ls, le = plan1280.leaves_export()
+    assert [int(x) for x in lk.cpu().numpy()] == t.boxes[t.L]
+    assert ls.cpu().numpy().tolist() == t.leaf_start
+    assert le.cpu().numpy().tolist() == t.leaf_end
+
+
+@pytest.mark.parametrize("mesh", ["cube6", "ico2"])
+def test_tree_bit_exact_small(mesh):
+    bem = _lib()
+    V, T = cube_surface(6) if mesh == "cube6" else icosphere(2)
+    _log(f"case: tree bit-exact {mesh}")
+    plan = bem.Plan(bem.Problem(V, T, 2.0, leaf_cap=8))
+    keys, perm = plan.tree_export()
+    gg = obem.Geometry(V, T)
+    t = otree.Tree(gg.cen, leaf_cap=8, ell_max=float(gg.ell.max()))
+    assert [int(x) for x in keys.cpu().numpy().astype(np.uint64)] == t.keys
+    assert perm.cpu().numpy().tolist() == t.perm
+    lk, ls, le = plan.leaves_export()
+    assert [int(x) for x in lk.cpu().numpy()] == t.boxes[t.L]
+    assert ls.cpu().numpy().tolist() == t.leaf_start
+
+
+def test_matvec_f64_sphere1280(sphere1280, plan1280):
+    import torch
+    _, T, g, k, Mp, Mq = sphere1280
+    rng = np.random.default_rng(1)
+    p = complex_normal(rng, len(T))
+    q = complex_normal(rng, len(T))
+    _log("case: matvec f64 sphere1280")
+    y = plan1280.matvec(torch.from_numpy(p), torch.from_numpy(q)).cpu().numpy()
+    ref = Mp @ p + Mq @ q
+    err = _rel(y, ref)
+    _log(f"  rel-L2 err {err:.3e}")
+    assert err < 1e-6
+    # rigid: q = None
+    y0 = plan1280.matvec(torch.from_numpy(p)).cpu().numpy()
+    assert _rel(y0, Mp @ p) < 1e-6
+
+
+def test_matvec_f32_sphere1280(sphere1280, plan1280):
+    import torch
+    _, T, g, k, Mp, Mq = sphere1280
+    rng = np.random.default_rng(1)
+    p = complex_normal(rng, len(T))
+    q = complex_normal(rng, len(T))
+    _log("case: matvec f32 sphere1280")
+    y = plan1280.matvec(torch.from_numpy(p), torch.from_numpy(q), prec=1).cpu().numpy()
+    err = _rel(y, Mp @ p + Mq @ q)
+    _log(f"  rel-L2 err {err:.3e}")
+    assert err < 1e-4
+
+
+def test_fixed_order8_sphere1280(sphere1280):
+    """The 1280-element workload's fixed order p = 8, leaf <= 32: report the error."""
+    import torch
+    bem = _lib()
+    V, T, g, k, Mp, Mq = sphere1280
+    _log("case: order 8 sphere1280")
+    plan = bem.Plan(bem.Problem(V, T, k, leaf_cap=32, order64=8, order32=8))
+    rng = np.random.default_rng(1)
+    p = complex_normal(rng, len(T))
+    q = complex_normal(rng, len(T))
+    y = plan.matvec(torch.from_numpy(p), torch.from_numpy(q)).cpu().numpy()
+    err = _rel(y, Mp @ p + Mq @ q)
+    _log(f"  p=8 rel-L2 err {err:.3e}")
+    assert err < 1e-4
+
+
+def test_adjoint_sphere1280(sphere1280, plan1280):
+    import torch
+    _, T, g, k, Mp, Mq = sphere1280
+    rng = np.random.default_rng(2)
+    yv = complex_normal(rng, len(T))
+    _log("case: adjoint f64 sphere1280")
+    u, w = plan1280.matvec_adjoint(torch.from_numpy(yv))
+    u, w = u.cpu().numpy(), w.cpu().numpy()
+    assert _rel(u, Mp.conj().T @ yv) < 1e-6
+    assert _rel(w, Mq.conj().T @ yv) < 1e-6
+    u32, w32 = plan1280.matvec_adjoint(torch.from_numpy(yv), prec=1)
+    assert _rel(u32.cpu().numpy(), Mp.conj().T @ yv) < 1e-4
+    assert _rel(w32.cpu().numpy(), Mq.conj().T @ yv) < 1e-4
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_adjoint_dot_product(plan1280, prec):
+    """<A x, y> = <x, A^H y> for the FMM operator itself (exact transpose)."""
+    import torch
+    n = plan1280.n[0]
+    rng = np.random.default_rng(3)
+    p, q, yv = (complex_normal(rng, n) for _ in range(3))
+    _log(f"case: adjoint dot product prec={prec}")
+    Ax = plan1280.matvec(torch.from_numpy(p), torch.from_numpy(q), prec=prec).cpu().numpy()
+    u, w = plan1280.matvec_adjoint(torch.from_numpy(yv), prec=prec)
+    lhs = np.vdot(yv, Ax)
+    rhs = np.vdot(u.cpu().numpy(), p) + np.vdot(w.cpu().numpy(), q)
+    rel = abs(lhs - rhs) / abs(lhs)
+    _log(f"  dot-test rel {rel:.3e}")
+    assert rel < (1e-12 if prec == 0 else 1e-5)
+
+
+def test_gmres_sphere1280_against_lu_and_mie(sphere1280, plan1280):
+    import torch
+    V, T, g, k, Mp, Mq = sphere1280
+    bem = _lib()
+    d = np.array([0.0, 0.0, 1.0])
+    _log("case: gmres sphere1280")
+    b = plan1280.plane_wave_rhs(d)
+    b_ref = obem.plane_wave_rhs(g, k, 1j / k, d)
+    assert _rel(b.cpu().numpy(), b_ref) < 1e-14
+    x, info = plan1280.solve(b, opts=bem.GmresOptions(tol=1e-10, restart=50))
+    _log(f"  iters {info['iterations']} resid {info['resid']:.2e}")
+    assert info["converged"] and info["resid"] <= 1e-10
+    x_lu = np.linalg.solve(Mp, b_ref)
+    assert _rel(x.cpu().numpy(), x_lu) < 1e-5
+    ref = mie.surface_pressure(k, g.cen[:, 2] / np.linalg.norm(g.cen, axis=1))
+    assert _rel(x.cpu().numpy(), ref) < 0.01
+    # mixed precision refinement reaches the same float64 residual
+    x2, info2 = plan1280.solve(b, opts=bem.GmresOptions(tol=1e-8, mode=1, inner_tol=1e-4))
+    _log(f"  IR iters {info2['iterations']} mv32 {info2['matvec32']} mv64 {info2['matvec64']} "
+         f"resid {info2['resid']:.2e}")
+    assert info2["converged"] and info2["resid"] <= 1e-8
+    assert info2["matvec32"] > 0
+    assert _rel(x2.cpu().numpy(), x_lu) < 1e-5
+
+
+def test_eval_field_against_oracle(sphere1280, plan1280):
+    import torch
+    V, T, g, k, Mp, Mq = sphere1280
+    rng = np.random.default_rng(5)
+    p = complex_normal(rng, len(T))
+    q = complex_normal(rng, len(T))
+    pts = 3.0 * unit_directions(rng, 8)
+    d = np.array([0.0, 0.6, 0.8])
+    _log("case: eval field")
+    got = plan1280.eval_field(torch.from_numpy(p), torch.from_numpy(q), pts, d).cpu().numpy()
+    ref = solve.represent(g, k, pts, p, q, d)
+    assert _rel(got, ref) < 1e-13
+    c = complex_normal(rng, 8)
+    rp, rq = plan1280.eval_field_adjoint(pts, torch.from_numpy(c))
+    Kh, Sh = solve.represent_blocks(g, k, pts)
+    assert _rel(rp.cpu().numpy(), Kh.conj().T @ c) < 1e-13
+    assert _rel(rq.cpu().numpy(), -(Sh.conj().T @ c)) < 1e-13
