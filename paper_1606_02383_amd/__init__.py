@@ -171,7 +171,7 @@ class Plan:
             V = np.ascontiguousarray(p.V, dtype=np.float64)
             T = np.ascontiguousarray(p.T, dtype=np.int32)
             self._keep += [V, T]
-            a = (1j / p.k) if p.alpha is None else complex(p.alpha)
+            a = (1j / p.k if p.k else 0j) if p.alpha is None else complex(p.alpha)
             arr[i] = _Problem(V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), V.shape[0],
                               T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), T.shape[0],
                               float(p.k), a.real, a.imag, float(p.near_eta), int(p.leaf_cap),

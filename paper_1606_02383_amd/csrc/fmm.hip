@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(P2P_THREADS)
     k_p2p(const R* __restrict__ geo, int64_t n, const int* __restrict__ bstart,
           const int* __restrict__ u_ptr, const int* __restrict__ u_idx,
           const cplx<R>* __restrict__ ps, const cplx<R>* __restrict__ qs, R k, R alr, R ali,
-          cplx<R>* __restrict__ ys) {
+          int all_src, cplx<R>* __restrict__ ys) {
   __shared__ R s_q[9][P2P_CHUNK];
   __shared__ R s_n[3][P2P_CHUNK];
   __shared__ R s_w[P2P_CHUNK];
@@ -130,16 +130,23 @@ __global__ void __launch_bounds__(P2P_THREADS)
   const int u0 = u_ptr[b], nu = u_ptr[b + 1] - u0;
   if (tid == 0) {
     int acc = 0;
-    for (int t = 0; t < nu; ++t) {
-      int nb = u_idx[u0 + t];
-      s_nb[t] = bstart[nb];
-      s_pre[t] = acc;
-      acc += bstart[nb + 1] - bstart[nb];
+    if (all_src) {  // every element is a source (direct sum)
+      s_nb[0] = 0;
+      s_pre[0] = 0;
+      acc = (int)n;
+    } else {
+      for (int t = 0; t < nu; ++t) {
+        int nb = u_idx[u0 + t];
+        s_nb[t] = bstart[nb];
+        s_pre[t] = acc;
+        acc += bstart[nb + 1] - bstart[nb];
+      }
     }
-    s_pre[nu] = acc;
+    s_pre[all_src ? 1 : nu] = acc;
   }
   __syncthreads();
-  const int total = s_pre[nu];
+  const int total = s_pre[all_src ? 1 : nu];
+  const int nseg = all_src ? 1 : nu;
   for (int tg = 0; tg < nT; tg += P2P_THREADS) {
     const int nTg = min(P2P_THREADS, nT - tg);
     const int nsl = P2P_THREADS / nTg;
@@ -161,7 +168,7 @@ __global__ void __launch_bounds__(P2P_THREADS)
       __syncthreads();
       for (int v = tid; v < cnt; v += P2P_THREADS) {
         int gv = c0 + v, t = 0;
-        while (t + 1 < nu && s_pre[t + 1] <= gv) ++t;
+        while (t + 1 < nseg && s_pre[t + 1] <= gv) ++t;
         int j = s_nb[t] + (gv - s_pre[t]);
         for (int c = 0; c < 9; ++c) s_q[c][v] = geo[(GEO_QX0 + c) * n + j];
         s_n[0][v] = geo[GEO_NX * n + j];
@@ -211,8 +218,8 @@ template <typename R>
 __global__ void __launch_bounds__(P2P_THREADS)
     k_p2p_adj(const R* __restrict__ geo, int64_t n, const int* __restrict__ bstart,
               const int* __restrict__ u_ptr, const int* __restrict__ u_idx,
-              const cplx<R>* __restrict__ ysrt, R k, R alr, R ali, cplx<R>* __restrict__ us,
-              cplx<R>* __restrict__ ws) {
+              const cplx<R>* __restrict__ ysrt, R k, R alr, R ali, int all_src,
+              cplx<R>* __restrict__ us, cplx<R>* __restrict__ ws) {
   __shared__ R s_x[6][P2P_CHUNK];
   __shared__ R s_y[2][P2P_CHUNK];
   __shared__ int s_id[P2P_CHUNK];
@@ -223,16 +230,23 @@ __global__ void __launch_bounds__(P2P_THREADS)
   const int u0 = u_ptr[b], nu = u_ptr[b + 1] - u0;
   if (tid == 0) {
     int acc = 0;
-    for (int t = 0; t < nu; ++t) {
-      int nb = u_idx[u0 + t];
-      s_nb[t] = bstart[nb];
-      s_pre[t] = acc;
-      acc += bstart[nb + 1] - bstart[nb];
+    if (all_src) {  // every element is a source (direct sum)
+      s_nb[0] = 0;
+      s_pre[0] = 0;
+      acc = (int)n;
+    } else {
+      for (int t = 0; t < nu; ++t) {
+        int nb = u_idx[u0 + t];
+        s_nb[t] = bstart[nb];
+        s_pre[t] = acc;
+        acc += bstart[nb + 1] - bstart[nb];
+      }
     }
-    s_pre[nu] = acc;
+    s_pre[all_src ? 1 : nu] = acc;
   }
   __syncthreads();
-  const int total = s_pre[nu];
+  const int total = s_pre[all_src ? 1 : nu];
+  const int nseg = all_src ? 1 : nu;
   for (int tg = 0; tg < nT; tg += P2P_THREADS) {
     const int nTg = min(P2P_THREADS, nT - tg);
     const int nsl = P2P_THREADS / nTg;
@@ -253,7 +267,7 @@ __global__ void __launch_bounds__(P2P_THREADS)
       __syncthreads();
       for (int v = tid; v < cnt; v += P2P_THREADS) {
         int gv = c0 + v, t = 0;
-        while (t + 1 < nu && s_pre[t + 1] <= gv) ++t;
+        while (t + 1 < nseg && s_pre[t + 1] <= gv) ++t;
         int i = s_nb[t] + (gv - s_pre[t]);
         s_x[0][v] = geo[GEO_CX * n + i];
         s_x[1][v] = geo[GEO_CY * n + i];
@@ -329,10 +343,39 @@ __global__ void k_leaf_accumulate(const int* __restrict__ bstart, int ncoef,
 }
 
 // ---------------------------------------------------------------------------
-// grouped gather-GEMM-scatter:  dst[pair_dst] += op_g src[pair_src]
-// (ADJ: op_g conjugate-transposed).  Tile 64 rows x 32 pairs, k-step 16.
+// grouped gather-GEMM-scatter on the matrix cores:
+//   dst[pair_dst] += op_g src[pair_src]      (ADJ: op_g conjugate-transposed)
+// Workgroup tile: 64 output rows x 64 pairs; four waves, each 32 x 32.  The
+// complex product runs as four real 16x16x4 MFMA products per 16x16 block:
+//   C_re += A_re B_re - A_im B_im,   C_im += A_re B_im + A_im B_re.
+// Operands are staged through LDS, 16 complex k per stage; output columns are
+// accumulated with atomics (pairs of one group never share a destination, but
+// different groups do).
+// MFMA 16x16x4 operand layout (wave64): A[m][k] from lane m + 16 k, B[k][n]
+// from lane n + 16 k.  Output D[m][n] sits in lane n + 16 j, element e, with
+// m = 4 j + e for the float32 instruction and m = 4 e + j for the float64
+// one (both measured on gfx950).
 // ---------------------------------------------------------------------------
-constexpr int G_RT = 64, G_CT = 32, G_KT = 16;
+template <typename R>
+struct MfmaOp;
+template <>
+struct MfmaOp<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int j, int e) { return 4 * j + e; }
+};
+template <>
+struct MfmaOp<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int j, int e) { return 4 * e + j; }
+};
+
+constexpr int G_RT = 64, G_CT = 64, G_KC = 16, G_LD = G_KC + 1;
 
 template <typename R, bool ADJ, int KIND>
 __global__ void __launch_bounds__(256)
@@ -341,9 +384,10 @@ __global__ void __launch_bounds__(256)
                    const int* __restrict__ tile_row0, const int* __restrict__ group_slot,
                    const cplx<R>* __restrict__ mats, const int* __restrict__ pair_dst,
                    const int* __restrict__ pair_src, const cplx<R>* __restrict__ src,
-                   cplx<R>* __restrict__ dst) {
-  __shared__ R a_re[G_KT][G_RT], a_im[G_KT][G_RT];
-  __shared__ R b_re[G_KT][G_CT], b_im[G_KT][G_CT];
+                   cplx<R>* __restrict__ dst, cplx<R>* __restrict__ cbuf) {
+  typedef typename MfmaOp<R>::v4 v4;
+  __shared__ R a_re[G_RT * G_LD], a_im[G_RT * G_LD];
+  __shared__ R b_re[G_CT * G_LD], b_im[G_CT * G_LD];
   __shared__ int s_src[G_CT], s_dst[G_CT];
   const int tile = blockIdx.x, tid = threadIdx.x;
   const int grp = tile_group[tile], p0 = tile_pair0[tile], np = tile_npairs[tile];
@@ -356,13 +400,19 @@ __global__ void __launch_bounds__(256)
     s_src[tid] = (tid < np) ? pair_src[p0 + tid] : -1;
     s_dst[tid] = (tid < np) ? pair_dst[p0 + tid] : -1;
   }
-  const int ty = tid / 16, tx = tid % 16;
-  cplx<R> acc[4][2];
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  v4 cr[2][2], ci[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = mk<R>(0, 0);
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = v4{0, 0, 0, 0};
+      ci[a][b] = v4{0, 0, 0, 0};
+    }
   __syncthreads();
-  for (int k0 = 0; k0 < in_cols; k0 += G_KT) {
-    // A tile: A[kk][rr] = op(r0 + rr, k0 + kk)
+  for (int k0 = 0; k0 < in_cols; k0 += G_KC) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       int e = tid + 256 * q;
@@ -371,8 +421,8 @@ __global__ void __launch_bounds__(256)
         rr = e % G_RT;
         kk = e / G_RT;
       } else {
-        kk = e % G_KT;
-        rr = e / G_KT;
+        kk = e % G_KC;
+        rr = e / G_KC;
       }
       int r = r0 + rr, c = k0 + kk;
       cplx<R> v = mk<R>(0, 0);
@@ -384,50 +434,79 @@ __global__ void __launch_bounds__(256)
           v = M[(int64_t)r * mat_cols + c];
         }
       }
-      a_re[kk][rr] = v.re;
-      a_im[kk][rr] = v.im;
+      a_re[rr * G_LD + kk] = v.re;
+      a_im[rr * G_LD + kk] = v.im;
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < 4; ++q) {
       int e = tid + 256 * q;
-      int kk = e % G_KT, cc = e / G_KT;
+      int kk = e % G_KC, cc = e / G_KC;
       int c = k0 + kk;
       cplx<R> v = mk<R>(0, 0);
       if (cc < np && c < in_cols) v = src[(int64_t)s_src[cc] * in_cols + c];
-      b_re[kk][cc] = v.re;
-      b_im[kk][cc] = v.im;
+      b_re[cc * G_LD + kk] = v.re;
+      b_im[cc * G_LD + kk] = v.im;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < G_KT; ++kk) {
-      R ar[4], ai[4], br[2], bi[2];
+    for (int ks = 0; ks < G_KC; ks += 4) {
+      R ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ar[i] = a_re[kk][ty * 4 + i];
-        ai[i] = a_im[kk][ty * 4 + i];
+      for (int rb = 0; rb < 2; ++rb) {
+        int row = wr * 32 + rb * 16 + li;
+        ar[rb] = a_re[row * G_LD + ks + lk];
+        ai[rb] = a_im[row * G_LD + ks + lk];
+        nai[rb] = -ai[rb];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        br[j] = b_re[kk][tx * 2 + j];
-        bi[j] = b_im[kk][tx * 2 + j];
+      for (int cb = 0; cb < 2; ++cb) {
+        int col = wc * 32 + cb * 16 + li;
+        br[cb] = b_re[col * G_LD + ks + lk];
+        bi[cb] = b_im[col * G_LD + ks + lk];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j].re += ar[i] * br[j] - ai[i] * bi[j];
-          acc[i][j].im += ar[i] * bi[j] + ai[i] * br[j];
+        for (int cb = 0; cb < 2; ++cb) {
+          cr[rb][cb] = MfmaOp<R>::mma(ar[rb], br[cb], cr[rb][cb]);
+          cr[rb][cb] = MfmaOp<R>::mma(nai[rb], bi[cb], cr[rb][cb]);
+          ci[rb][cb] = MfmaOp<R>::mma(ar[rb], bi[cb], ci[rb][cb]);
+          ci[rb][cb] = MfmaOp<R>::mma(ai[rb], br[cb], ci[rb][cb]);
         }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      int r = r0 + ty * 4 + i, cc = tx * 2 + j;
-      if (r < out_rows && cc < np) atomic_cadd(&dst[(int64_t)s_dst[cc] * out_rows + r], acc[i][j]);
-    }
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int row = r0 + wr * 32 + rb * 16 + MfmaOp<R>::row(lk, e);
+        int cc = wc * 32 + cb * 16 + li;
+        if (row < out_rows && cc < np) {
+          cplx<R> v = mk<R>(cr[rb][cb][e], ci[rb][cb][e]);
+          if (cbuf)  // per-pair output, reduced per destination afterwards
+            cbuf[(int64_t)(p0 + cc) * out_rows + row] = v;
+          else
+            atomic_cadd(&dst[(int64_t)s_dst[cc] * out_rows + row], v);
+        }
+      }
+}
+
+// dst[b][c] (+)= sum over the pairs t of box b of cbuf[t][c]  (pairs listed
+// per box in a fixed order: deterministic, no atomics)
+template <typename R>
+__global__ void k_pair_reduce(int ncoef, const int* __restrict__ ptr, const int* __restrict__ pairs,
+                              const cplx<R>* __restrict__ cbuf, int accumulate,
+                              cplx<R>* __restrict__ dst) {
+  const int b = blockIdx.x;
+  const int t0 = ptr[b], t1 = ptr[b + 1];
+  for (int c = threadIdx.x; c < ncoef; c += blockDim.x) {
+    cplx<R> acc = accumulate ? dst[(int64_t)b * ncoef + c] : mk<R>(0, 0);
+    for (int t = t0; t < t1; ++t) acc = cadd(acc, cbuf[(int64_t)pairs[t] * ncoef + c]);
+    dst[(int64_t)b * ncoef + c] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -552,21 +631,33 @@ int prof_end(Problem& P, int idx, int slot, hipStream_t s) {
 // host drivers
 // ---------------------------------------------------------------------------
 // KIND only separates the kernel names (0 M2L, 1 M2M, 2 L2L) for profilers
+// With cbuf (and the op's per-destination pair lists) the product is
+// written per pair and then reduced per destination box, replacing dst
+// (accumulate = 0) or adding to it; without, it is accumulated atomically.
 template <typename R, int KIND>
 static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, cplx<R>* dst,
-                          hipStream_t s) {
+                          hipStream_t s, cplx<R>* cbuf = nullptr, int accumulate = 0) {
   int nt = adj ? op.n_tiles_adj : op.n_tiles;
-  if (nt == 0) return 0;
-  if (adj)
-    hipLaunchKernelGGL((k_grouped_gemm<R, true, KIND>), dim3(nt), dim3(256), 0, s, op.rows,
-                       op.cols, op.tile_group_adj, op.tile_pair0_adj, op.tile_npairs_adj,
-                       op.tile_row0_adj, op.group_slot, op.mats, op.pair_dst_adj, op.pair_src_adj,
-                       src, dst);
-  else
-    hipLaunchKernelGGL((k_grouped_gemm<R, false, KIND>), dim3(nt), dim3(256), 0, s, op.rows,
-                       op.cols, op.tile_group, op.tile_pair0, op.tile_npairs, op.tile_row0,
-                       op.group_slot, op.mats, op.pair_dst, op.pair_src, src, dst);
-  BEM_LAUNCH_CHECK();
+  if (nt > 0) {
+    if (adj)
+      hipLaunchKernelGGL((k_grouped_gemm<R, true, KIND>), dim3(nt), dim3(256), 0, s, op.rows,
+                         op.cols, op.tile_group_adj, op.tile_pair0_adj, op.tile_npairs_adj,
+                         op.tile_row0_adj, op.group_slot, op.mats, op.pair_dst_adj,
+                         op.pair_src_adj, src, dst, cbuf);
+    else
+      hipLaunchKernelGGL((k_grouped_gemm<R, false, KIND>), dim3(nt), dim3(256), 0, s, op.rows,
+                         op.cols, op.tile_group, op.tile_pair0, op.tile_npairs, op.tile_row0,
+                         op.group_slot, op.mats, op.pair_dst, op.pair_src, src, dst, cbuf);
+    BEM_LAUNCH_CHECK();
+  }
+  if (cbuf && (adj ? op.n_red_adj : op.n_red) > 0) {
+    int nb = adj ? op.n_red_adj : op.n_red;
+    int nco = adj ? op.cols : op.rows;
+    hipLaunchKernelGGL(k_pair_reduce<R>, dim3(nb), dim3(nco >= 128 ? 128 : 64), 0, s, nco,
+                       adj ? op.red_ptr_adj : op.red_ptr, adj ? op.red_pairs_adj : op.red_pairs,
+                       (const cplx<R>*)cbuf, accumulate, dst);
+    BEM_LAUNCH_CHECK();
+  }
   return 0;
 }
 
@@ -594,10 +685,18 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
   const int nleaf = P.nbox[L];
   PROF_BEGIN(e1);
   hipLaunchKernelGGL(k_p2p<R>, dim3(nleaf), dim3(P2P_THREADS), 0, s, (const R*)D.geo, n,
-                     P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr, ali, D.ys);
+                     P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr, ali, (int)P.direct,
+                     D.ys);
   BEM_LAUNCH_CHECK();
   PROF_END(e1, ST_P2P);
   int r = 0;
+  if (P.direct) {
+    hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
+                       P.elem_leaf, 0, D.l2p, D.Lc[L], P.near_ptr, P.near_col, D.near_cp,
+                       D.near_cq, D.ps, D.qs, D.ys, P.diag_p, P.diag_q, P.p64s, P.q64s, y);
+    BEM_LAUNCH_CHECK();
+    return 0;
+  }
   PROF_BEGIN(e2);
   hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(nleaf), dim3(128), 0, s, P.box_start[L],
                      D.ncoef[L], D.p2m, D.ps, D.qs, 0, D.M[L]);
@@ -609,11 +708,9 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
     if ((r = launch_grouped<R, 1>(D.m2m[l], false, D.M[l], D.M[l - 1], s))) return r;
   }
   PROF_END(e3, ST_M2M);
-  for (int l = 2; l <= L; ++l)
-    if ((r = zero<R>(D.Lc[l], (int64_t)P.nbox[l] * D.ncoef[l], s))) return r;
   PROF_BEGIN(e4);
   for (int l = 2; l <= L; ++l)
-    if ((r = launch_grouped<R, 0>(D.m2l[l], false, D.M[l], D.Lc[l], s))) return r;
+    if ((r = launch_grouped<R, 0>(D.m2l[l], false, D.M[l], D.Lc[l], s, D.cbuf, 0))) return r;
   PROF_END(e4, ST_M2L);
   PROF_BEGIN(e5);
   for (int l = 3; l <= L; ++l)
@@ -654,10 +751,18 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   const int nleaf = P.nbox[L];
   PROF_BEGIN(e1);
   hipLaunchKernelGGL(k_p2p_adj<R>, dim3(nleaf), dim3(P2P_THREADS), 0, s, (const R*)D.geo, n,
-                     P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali, D.ys, D.ys2);
+                     P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali, (int)P.direct, D.ys,
+                     D.ys2);
   BEM_LAUNCH_CHECK();
   PROF_END(e1, ST_P2P);
   int r = 0;
+  if (P.direct) {
+    hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
+                       P.elem_leaf, 0, D.p2m, D.M[L], P.neart_ptr, P.neart_row, D.neart_cp,
+                       D.neart_cq, D.ps, D.ys, D.ys2, P.diag_p, P.diag_q, P.p64s, u, w);
+    BEM_LAUNCH_CHECK();
+    return 0;
+  }
   // adjoint locals (L2P^H) in Lc, adjoint multipoles in M
   PROF_BEGIN(e2);
   hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(nleaf), dim3(128), 0, s, P.box_start[L],
@@ -670,11 +775,9 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
     if ((r = launch_grouped<R, 2>(D.l2l[l], true, D.Lc[l], D.Lc[l - 1], s))) return r;
   }
   PROF_END(e5, ST_L2L);
-  for (int l = 2; l <= L; ++l)
-    if ((r = zero<R>(D.M[l], (int64_t)P.nbox[l] * D.ncoef[l], s))) return r;
   PROF_BEGIN(e4);
   for (int l = 2; l <= L; ++l)
-    if ((r = launch_grouped<R, 0>(D.m2l[l], true, D.Lc[l], D.M[l], s))) return r;
+    if ((r = launch_grouped<R, 0>(D.m2l[l], true, D.Lc[l], D.M[l], s, D.cbuf, 0))) return r;
   PROF_END(e4, ST_M2L);
   PROF_BEGIN(e3);
   for (int l = 3; l <= L; ++l)

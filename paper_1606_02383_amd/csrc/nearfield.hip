@@ -379,7 +379,7 @@ int build_near_field(Problem& P, hipStream_t s) {
   const int* bstart = P.box_start[P.L];
   int nb = ceil_div(n, 128);
   int total = 0, total_t = 0;
-  const int brute = (P.h[P.L] > P.eta * P.ell_max) ? 0 : 1;
+  const int brute = P.direct ? 1 : 0;
   if (brute && n > 200000) {
     set_error("mesh too coarse for its size: elements wider than the finest usable leaf");
     return -1;

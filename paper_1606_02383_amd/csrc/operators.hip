@@ -439,7 +439,7 @@ static void make_tiles(const std::vector<int>& gstart, int rows, int CT, int RT,
   }
 }
 
-constexpr int GEMM_CT = 32;
+constexpr int GEMM_CT = 64;
 constexpr int GEMM_RT = 64;
 
 __global__ void k_group_starts(const int* __restrict__ code, int np, int ngroups,
@@ -552,6 +552,65 @@ static int finish_grouped(GroupedOp<R>& op, int* d0, int* s0, int* c0, int np, i
   return 0;
 }
 
+__global__ void k_count_boxes(const int* __restrict__ box, int np, int* __restrict__ cnt) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < np) atomicAdd(&cnt[box[t]], 1);
+}
+
+__global__ void k_keys_from_box(const int* __restrict__ box, int np, uint64_t* __restrict__ keys,
+                                int* __restrict__ idx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  keys[t] = (uint64_t)box[t];
+  idx[t] = t;
+}
+
+// CSR lists of pair indices per box (ascending pair index within a box), by
+// destination (forward) and by source (adjoint).
+static int pairs_by_box(const int* box, int np, int nbox, int** ptr_out, int** pairs_out,
+                        DevArena& arena, DevArena& scratch, hipStream_t s) {
+  int *cnt, *ptr, *pairs;
+  uint64_t* keys;
+  ARENA_ALLOC(scratch, cnt, nbox);
+  ARENA_ALLOC(arena, ptr, nbox + 1);
+  ARENA_ALLOC(arena, pairs, np);
+  ARENA_ALLOC(scratch, keys, np);
+  BEM_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int) * nbox, s));
+  if (np > 0) {
+    hipLaunchKernelGGL(k_count_boxes, dim3(ceil_div(np, 256)), dim3(256), 0, s, box, np, cnt);
+    BEM_LAUNCH_CHECK();
+  }
+  int total = 0;
+  int r = exclusive_scan(cnt, ptr, nbox, &total, scratch, s);
+  if (r) return r;
+  BEM_HIP_TRY(hipMemcpyAsync(ptr + nbox, &total, sizeof(int), hipMemcpyHostToDevice, s));
+  if (np > 0) {
+    hipLaunchKernelGGL(k_keys_from_box, dim3(ceil_div(np, 256)), dim3(256), 0, s, box, np, keys,
+                       pairs);
+    BEM_LAUNCH_CHECK();
+    int nbits = 1;
+    while ((1 << nbits) <= nbox) ++nbits;
+    r = sort_pairs_u64(keys, pairs, np, nbits, scratch, s);
+    if (r) return r;
+  }
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  *ptr_out = ptr;
+  *pairs_out = pairs;
+  return 0;
+}
+
+template <typename R>
+static int build_reduce_lists(GroupedOp<R>& op, int nbox, DevArena& arena, DevArena& scratch,
+                              hipStream_t s) {
+  int r = pairs_by_box(op.pair_dst, op.n_pairs, nbox, &op.red_ptr, &op.red_pairs, arena, scratch, s);
+  if (r) return r;
+  r = pairs_by_box(op.pair_src, op.n_pairs, nbox, &op.red_ptr_adj, &op.red_pairs_adj, arena,
+                   scratch, s);
+  if (r) return r;
+  op.n_red = op.n_red_adj = nbox;
+  return 0;
+}
+
 template <typename R>
 static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena& scratch,
                            hipStream_t s) {
@@ -565,6 +624,7 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     ARENA_ALLOC(P.arena, D.Lc[l], (int64_t)P.nbox[l] * D.ncoef[l]);
   }
   // ---- M2L: one matrix per offset present at each level ----
+  int64_t cbuf_count = 0;
   for (int l = 2; l <= L; ++l) {
     int *d0, *s0, *c0, np = 0;
     int r = build_vlist(P, l, &d0, &s0, &c0, &np, scratch, s);
@@ -598,6 +658,10 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
       if (r) return r;
     }
     r = finish_grouped<R>(op, d0, s0, c0, np, N_OFFSETS, slot, P.arena, scratch, s);
+    if (r) return r;
+    r = build_reduce_lists<R>(op, P.nbox[l], P.arena, scratch, s);
+    if (r) return r;
+    cbuf_count = std::max(cbuf_count, (int64_t)np * D.ncoef[l]);
     if (r) return r;
   }
   // ---- M2M (child level l -> parent l-1) and L2L (l-1 -> l), l >= 3 ----
@@ -648,6 +712,7 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     r = finish_grouped<R>(ll, s0, d0, c0, nb, 8, slot, P.arena, scratch, s);
     if (r) return r;
   }
+  ARENA_ALLOC(P.arena, D.cbuf, cbuf_count);
   // ---- P2M and L2P per element ----
   {
     int p = D.order[L];
@@ -722,7 +787,7 @@ int build_operators(Problem& P, hipStream_t s) {
     DevArena& a;
     ~Guard() { a.release(); }
   } guard{scratch};
-  if (P.L >= 2) {
+  if (P.L >= 2 && !P.direct) {
     int r = build_precision<double>(P, P.f64, true, scratch, s);
     if (r) return r;
     scratch.release();

@@ -51,6 +51,13 @@ struct GroupedOp {
   int* tile_row0_adj = nullptr;
   int* pair_dst_adj = nullptr;     // pairs regrouped for the adjoint (dst = old src)
   int* pair_src_adj = nullptr;
+  // per-destination pair lists (CSR over destination boxes) for the
+  // atomic-free two-phase product; *_adj lists pairs by source box
+  int n_red = 0, n_red_adj = 0;
+  int* red_ptr = nullptr;
+  int* red_pairs = nullptr;
+  int* red_ptr_adj = nullptr;
+  int* red_pairs_adj = nullptr;
 };
 
 template <typename R>
@@ -62,6 +69,7 @@ struct PrecisionData {
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2l{};
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2m{};  // level l -> l-1 (index l)
   std::array<GroupedOp<R>, MAX_LEVEL + 1> l2l{};  // level l-1 -> l (index l)
+  cplx<R>* cbuf = nullptr;  // per-pair products of the largest M2L level
   cplx<R>* p2m = nullptr;   // n x ncoef_L x 2 (columns: p, q), sorted order
   cplx<R>* l2p = nullptr;   // n x ncoef_L
   // near-field corrections (accurate - 3-point rule), CSR by target and
@@ -103,6 +111,7 @@ struct Problem {
   double lo[3]{}, R0 = 0, scale = 0, ell_max = 0;
   // tree
   int L = 0;
+  bool direct = false;  // leaves not wider than the near radius: direct sum, no far field
   std::array<int, MAX_LEVEL + 1> nbox{};
   std::array<uint64_t*, MAX_LEVEL + 1> box_keys{};
   std::array<int*, MAX_LEVEL + 1> box_start{};   // first sorted element (nbox+1 entries)

@@ -651,6 +651,7 @@ int build_geometry_and_tree(Problem& P, const double* vert, int64_t n_vert, cons
   }
   if (L > L_near) L = L_near;
   P.L = L;
+  P.direct = !(P.h[L] > P.eta * P.ell_max);
 
   // boxes of every level 0..L and parents
   std::vector<int*> elem_box(L + 1, nullptr);
