@@ -86,6 +86,10 @@ def main():
     ap.add_argument("--workload", default="sphere81920_k8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for hardware-counter passes: 3 float32 and 3 float64 "
+                         "products, then one elementwise kernel over 512 MiB in / 512 MiB out "
+                         "(the byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -110,6 +114,16 @@ def main():
     log(f"[bench] plan built in {t_plan:.2f} s; leaf level {st['leaf_level']}, "
         f"orders f64 {st['order64'][2:]} f32 {st['order32'][2:]}, m2l pairs {st['n_m2l'][2:]}")
     b = plan.plane_wave_rhs(d)
+    if args.counters:
+        for prec in (1, 0):
+            for _ in range(3):
+                plan.matvec(b, prec=prec)
+        x = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        log("[bench] counters run done")
+        return
     opts64 = bem.GmresOptions(tol=wl.tol, restart=50, mode=0)
     optsir = bem.GmresOptions(tol=wl.tol, restart=50, mode=1, inner_tol=args.inner_tol)
 
@@ -165,8 +179,9 @@ def main():
     L = st["leaf_level"]
     flops_m2l = sum(8.0 * st["n_m2l"][l] * (st["order32"][l] + 1) ** 4 for l in range(2, L + 1))
     n_lvl = max(1, L - 1)
-    # per kernel launch (one launch per level): mean work / mean duration
-    per_launch_ms = m2l_ms / max(1, m2l_calls) / n_lvl
+    # one M2L GEMM launch per level per matvec: mean work / mean duration
+    n_mv = max(1, m2l_calls // n_lvl)
+    per_launch_ms = m2l_ms / max(1, m2l_calls)
     achieved = (flops_m2l / n_lvl) / (per_launch_ms / 1e3) if per_launch_ms > 0 else 0.0
     roofline = {"kernel": "k_grouped_gemm<float,false,0> (M2L, float32)", "bound": "mfma",
                 "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,

@@ -33,7 +33,7 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
            "bem_leaves_export", "bem_profile_start", "bem_profile_stop", "bem_last_error"]
 
-STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish"]
+STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce"]
 
 
 class _Problem(ctypes.Structure):

@@ -21,6 +21,9 @@ static void destroy_problem(Problem* P) {
   release_workspace(*P);
   for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
   P->ev_pool.clear();
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+  if (P->side) (void)hipStreamDestroy(P->side);
   P->arena.release();
   delete P;
 }

@@ -389,7 +389,12 @@ __global__ void __launch_bounds__(256)
   __shared__ R a_re[G_RT * G_LD], a_im[G_RT * G_LD];
   __shared__ R b_re[G_CT * G_LD], b_im[G_CT * G_LD];
   __shared__ int s_src[G_CT], s_dst[G_CT];
-  const int tile = blockIdx.x, tid = threadIdx.x;
+  // XCD-aware order: workgroups go to the 8 XCDs round-robin (block b on XCD
+  // b % 8), so give each XCD a contiguous range of tiles; consecutive tiles
+  // share their group's matrix, which then stays in that XCD's L2.
+  const int nt = gridDim.x, xcd = blockIdx.x & 7, slot_in_xcd = blockIdx.x >> 3;
+  const int tile = xcd * (nt >> 3) + min(xcd, nt & 7) + slot_in_xcd;
+  const int tid = threadIdx.x;
   const int grp = tile_group[tile], p0 = tile_pair0[tile], np = tile_npairs[tile];
   const int r0 = tile_row0[tile];
   const int slot = group_slot[grp];
@@ -496,16 +501,29 @@ __global__ void __launch_bounds__(256)
 
 // dst[b][c] (+)= sum over the pairs t of box b of cbuf[t][c]  (pairs listed
 // per box in a fixed order: deterministic, no atomics)
+// 256 threads per box: 4 slices of 64 coefficients, each slice sums every
+// fourth pair, then the slices are added in a fixed order.
 template <typename R>
-__global__ void k_pair_reduce(int ncoef, const int* __restrict__ ptr, const int* __restrict__ pairs,
-                              const cplx<R>* __restrict__ cbuf, int accumulate,
-                              cplx<R>* __restrict__ dst) {
+__global__ void __launch_bounds__(256)
+    k_pair_reduce(int ncoef, const int* __restrict__ ptr, const int* __restrict__ pairs,
+                  const cplx<R>* __restrict__ cbuf, int accumulate, cplx<R>* __restrict__ dst) {
+  __shared__ cplx<R> part[4][64];
   const int b = blockIdx.x;
   const int t0 = ptr[b], t1 = ptr[b + 1];
-  for (int c = threadIdx.x; c < ncoef; c += blockDim.x) {
-    cplx<R> acc = accumulate ? dst[(int64_t)b * ncoef + c] : mk<R>(0, 0);
-    for (int t = t0; t < t1; ++t) acc = cadd(acc, cbuf[(int64_t)pairs[t] * ncoef + c]);
-    dst[(int64_t)b * ncoef + c] = acc;
+  const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncoef; c0 += 64) {
+    const int c = c0 + lane;
+    cplx<R> acc = mk<R>(0, 0);
+    if (c < ncoef)
+      for (int t = t0 + slice; t < t1; t += 4) acc = cadd(acc, cbuf[(int64_t)pairs[t] * ncoef + c]);
+    part[slice][lane] = acc;
+    __syncthreads();
+    if (slice == 0 && c < ncoef) {
+      cplx<R> s = accumulate ? dst[(int64_t)b * ncoef + c] : mk<R>(0, 0);
+      s = cadd(s, cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane])));
+      dst[(int64_t)b * ncoef + c] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -636,9 +654,11 @@ int prof_end(Problem& P, int idx, int slot, hipStream_t s) {
 // (accumulate = 0) or adding to it; without, it is accumulated atomically.
 template <typename R, int KIND>
 static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, cplx<R>* dst,
-                          hipStream_t s, cplx<R>* cbuf = nullptr, int accumulate = 0) {
+                          hipStream_t s, cplx<R>* cbuf = nullptr, int accumulate = 0,
+                          Problem* prof = nullptr) {
   int nt = adj ? op.n_tiles_adj : op.n_tiles;
   if (nt > 0) {
+    int evg = prof ? prof_begin(*prof, s) : -1;
     if (adj)
       hipLaunchKernelGGL((k_grouped_gemm<R, true, KIND>), dim3(nt), dim3(256), 0, s, op.rows,
                          op.cols, op.tile_group_adj, op.tile_pair0_adj, op.tile_npairs_adj,
@@ -649,14 +669,23 @@ static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, 
                          op.cols, op.tile_group, op.tile_pair0, op.tile_npairs, op.tile_row0,
                          op.group_slot, op.mats, op.pair_dst, op.pair_src, src, dst, cbuf);
     BEM_LAUNCH_CHECK();
+    if (prof) {
+      int pr = prof_end(*prof, evg, ST_M2L + 8 * (sizeof(R) == 4) + 16 * (adj ? 1 : 0), s);
+      if (pr) return pr;
+    }
   }
   if (cbuf && (adj ? op.n_red_adj : op.n_red) > 0) {
     int nb = adj ? op.n_red_adj : op.n_red;
     int nco = adj ? op.cols : op.rows;
-    hipLaunchKernelGGL(k_pair_reduce<R>, dim3(nb), dim3(nco >= 128 ? 128 : 64), 0, s, nco,
+    int ev = prof ? prof_begin(*prof, s) : -1;
+    hipLaunchKernelGGL(k_pair_reduce<R>, dim3(nb), dim3(256), 0, s, nco,
                        adj ? op.red_ptr_adj : op.red_ptr, adj ? op.red_pairs_adj : op.red_pairs,
                        (const cplx<R>*)cbuf, accumulate, dst);
     BEM_LAUNCH_CHECK();
+    if (prof) {
+      int pr = prof_end(*prof, ev, ST_M2L_RED + 8 * (sizeof(R) == 4) + 16 * (adj ? 1 : 0), s);
+      if (pr) return pr;
+    }
   }
   return 0;
 }
@@ -683,12 +712,22 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
-  PROF_BEGIN(e1);
-  hipLaunchKernelGGL(k_p2p<R>, dim3(nleaf), dim3(P2P_THREADS), 0, s, (const R*)D.geo, n,
-                     P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr, ali, (int)P.direct,
-                     D.ys);
-  BEM_LAUNCH_CHECK();
-  PROF_END(e1, ST_P2P);
+  // the near field runs on the side stream, concurrently with the far field
+  hipStream_t sn = P.direct ? s : P.side;
+  if (!P.direct) {
+    BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
+    BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
+  }
+  {
+    int e1 = prof_begin(P, sn);
+    hipLaunchKernelGGL(k_p2p<R>, dim3(nleaf), dim3(P2P_THREADS), 0, sn, (const R*)D.geo, n,
+                       P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr, ali, (int)P.direct,
+                       D.ys);
+    BEM_LAUNCH_CHECK();
+    int pr = prof_end(P, e1, ST_P2P + 8 * (sizeof(R) == 4), sn);
+    if (pr) return pr;
+  }
+  if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
   int r = 0;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
@@ -708,14 +747,14 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
     if ((r = launch_grouped<R, 1>(D.m2m[l], false, D.M[l], D.M[l - 1], s))) return r;
   }
   PROF_END(e3, ST_M2M);
-  PROF_BEGIN(e4);
   for (int l = 2; l <= L; ++l)
-    if ((r = launch_grouped<R, 0>(D.m2l[l], false, D.M[l], D.Lc[l], s, D.cbuf, 0))) return r;
-  PROF_END(e4, ST_M2L);
+    if ((r = launch_grouped<R, 0>(D.m2l[l], false, D.M[l], D.Lc[l], s, D.cbuf, 0,
+                                  P.prof_on ? &P : nullptr))) return r;
   PROF_BEGIN(e5);
   for (int l = 3; l <= L; ++l)
     if ((r = launch_grouped<R, 2>(D.l2l[l], false, D.Lc[l - 1], D.Lc[l], s))) return r;
   PROF_END(e5, ST_L2L);
+  BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);
   hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
                      P.elem_leaf, D.ncoef[L], D.l2p, D.Lc[L], P.near_ptr, P.near_col, D.near_cp,
@@ -749,12 +788,21 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
-  PROF_BEGIN(e1);
-  hipLaunchKernelGGL(k_p2p_adj<R>, dim3(nleaf), dim3(P2P_THREADS), 0, s, (const R*)D.geo, n,
-                     P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali, (int)P.direct, D.ys,
-                     D.ys2);
-  BEM_LAUNCH_CHECK();
-  PROF_END(e1, ST_P2P);
+  hipStream_t sn = P.direct ? s : P.side;
+  if (!P.direct) {
+    BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
+    BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
+  }
+  {
+    int e1 = prof_begin(P, sn);
+    hipLaunchKernelGGL(k_p2p_adj<R>, dim3(nleaf), dim3(P2P_THREADS), 0, sn, (const R*)D.geo, n,
+                       P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali, (int)P.direct, D.ys,
+                       D.ys2);
+    BEM_LAUNCH_CHECK();
+    int pr = prof_end(P, e1, ST_P2P + 8 * (sizeof(R) == 4) + 16, sn);
+    if (pr) return pr;
+  }
+  if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
   int r = 0;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
@@ -775,14 +823,14 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
     if ((r = launch_grouped<R, 2>(D.l2l[l], true, D.Lc[l], D.Lc[l - 1], s))) return r;
   }
   PROF_END(e5, ST_L2L);
-  PROF_BEGIN(e4);
   for (int l = 2; l <= L; ++l)
-    if ((r = launch_grouped<R, 0>(D.m2l[l], true, D.Lc[l], D.M[l], s, D.cbuf, 0))) return r;
-  PROF_END(e4, ST_M2L);
+    if ((r = launch_grouped<R, 0>(D.m2l[l], true, D.Lc[l], D.M[l], s, D.cbuf, 0,
+                                  P.prof_on ? &P : nullptr))) return r;
   PROF_BEGIN(e3);
   for (int l = 3; l <= L; ++l)
     if ((r = launch_grouped<R, 1>(D.m2m[l], true, D.M[l - 1], D.M[l], s))) return r;
   PROF_END(e3, ST_M2M);
+  BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);
   hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
                      P.elem_leaf, D.ncoef[L], D.p2m, D.M[L], P.neart_ptr, P.neart_row,

@@ -810,6 +810,9 @@ int build_operators(Problem& P, hipStream_t s) {
   ARENA_ALLOC(P.arena, P.f32.ys2, P.n);
   ARENA_ALLOC(P.arena, P.p64s, P.n);
   ARENA_ALLOC(P.arena, P.q64s, P.n);
+  BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
+  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
   BEM_HIP_TRY(hipStreamSynchronize(s));
   return 0;
 }

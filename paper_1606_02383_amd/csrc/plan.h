@@ -137,6 +137,10 @@ struct Problem {
   c64* q64s = nullptr;
   // solver workspace (Krylov basis etc.), owned, see solver.hip
   void* solver_ws = nullptr;
+  // second stream (default priority) for the direct near field, which runs
+  // concurrently with the far-field chain; fork/join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // stage profiling with HIP events (off unless enabled)
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
@@ -145,7 +149,7 @@ struct Problem {
 };
 
 // profiling slots: stage + 8 * precision (0: float64, 1: float32) + 16 * adjoint
-enum { ST_GATHER = 0, ST_P2P, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_FINISH, ST_COUNT };
+enum { ST_GATHER = 0, ST_P2P, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_FINISH, ST_M2L_RED, ST_COUNT };
 constexpr int PROF_SLOTS = 32;
 int prof_begin(Problem& P, hipStream_t s);                 // returns event index or -1
 int prof_end(Problem& P, int idx, int slot, hipStream_t s);
