@@ -24,6 +24,9 @@ static void destroy_problem(Problem* P) {
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   if (P->side) (void)hipStreamDestroy(P->side);
+  if (P->ev_fork2) (void)hipEventDestroy(P->ev_fork2);
+  if (P->ev_join2) (void)hipEventDestroy(P->ev_join2);
+  if (P->side2) (void)hipStreamDestroy(P->side2);
   P->arena.release();
   delete P;
 }

@@ -491,10 +491,15 @@ __global__ void __launch_bounds__(256)
         int cc = wc * 32 + cb * 16 + li;
         if (row < out_rows && cc < np) {
           cplx<R> v = mk<R>(cr[rb][cb][e], ci[rb][cb][e]);
-          if (cbuf)  // per-pair output, reduced per destination afterwards
+          if (cbuf) {  // per-pair output, reduced per destination afterwards
             cbuf[(int64_t)(p0 + cc) * out_rows + row] = v;
-          else
+          } else if ((KIND == 2 && !ADJ) || (KIND == 1 && ADJ)) {
+            // parent -> child: every child is the destination of exactly one pair
+            cplx<R>* d = &dst[(int64_t)s_dst[cc] * out_rows + row];
+            *d = cadd(*d, v);
+          } else {
             atomic_cadd(&dst[(int64_t)s_dst[cc] * out_rows + row], v);
+          }
         }
       }
 }
@@ -741,18 +746,28 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
                      D.ncoef[L], D.p2m, D.ps, D.qs, 0, D.M[L]);
   BEM_LAUNCH_CHECK();
   PROF_END(e2, ST_P2M);
+  // leaf-level M2L on its own stream: needs only the leaf multipoles
+  BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
+  BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
+  if ((r = launch_grouped<R, 0>(D.m2l[L], false, D.M[L], D.Lc[L], P.side2, D.cbufL, 0,
+                                P.prof_on ? &P : nullptr)))
+    return r;
+  BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   PROF_BEGIN(e3);
   for (int l = L; l >= 3; --l) {
     if ((r = zero<R>(D.M[l - 1], (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s))) return r;
     if ((r = launch_grouped<R, 1>(D.m2m[l], false, D.M[l], D.M[l - 1], s))) return r;
   }
   PROF_END(e3, ST_M2M);
-  for (int l = 2; l <= L; ++l)
+  for (int l = 2; l < L; ++l)
     if ((r = launch_grouped<R, 0>(D.m2l[l], false, D.M[l], D.Lc[l], s, D.cbuf, 0,
                                   P.prof_on ? &P : nullptr))) return r;
   PROF_BEGIN(e5);
-  for (int l = 3; l <= L; ++l)
+  for (int l = 3; l <= L; ++l) {
+    if (l == L) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
     if ((r = launch_grouped<R, 2>(D.l2l[l], false, D.Lc[l - 1], D.Lc[l], s))) return r;
+  }
+  if (L < 3) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
   PROF_END(e5, ST_L2L);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);
@@ -817,18 +832,28 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
                      D.ncoef[L], D.l2p, D.ps, (const cplx<R>*)nullptr, 1, D.Lc[L]);
   BEM_LAUNCH_CHECK();
   PROF_END(e2, ST_P2M);
+  // leaf-level M2L^H on its own stream: needs only the leaf adjoint locals
+  BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
+  BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
+  if ((r = launch_grouped<R, 0>(D.m2l[L], true, D.Lc[L], D.M[L], P.side2, D.cbufL, 0,
+                                P.prof_on ? &P : nullptr)))
+    return r;
+  BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   PROF_BEGIN(e5);
   for (int l = L; l >= 3; --l) {
     if ((r = zero<R>(D.Lc[l - 1], (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s))) return r;
     if ((r = launch_grouped<R, 2>(D.l2l[l], true, D.Lc[l], D.Lc[l - 1], s))) return r;
   }
   PROF_END(e5, ST_L2L);
-  for (int l = 2; l <= L; ++l)
+  for (int l = 2; l < L; ++l)
     if ((r = launch_grouped<R, 0>(D.m2l[l], true, D.Lc[l], D.M[l], s, D.cbuf, 0,
                                   P.prof_on ? &P : nullptr))) return r;
   PROF_BEGIN(e3);
-  for (int l = 3; l <= L; ++l)
+  for (int l = 3; l <= L; ++l) {
+    if (l == L) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
     if ((r = launch_grouped<R, 1>(D.m2m[l], true, D.M[l - 1], D.M[l], s))) return r;
+  }
+  if (L < 3) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
   PROF_END(e3, ST_M2M);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);

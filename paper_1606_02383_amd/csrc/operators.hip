@@ -661,7 +661,10 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     if (r) return r;
     r = build_reduce_lists<R>(op, P.nbox[l], P.arena, scratch, s);
     if (r) return r;
-    cbuf_count = std::max(cbuf_count, (int64_t)np * D.ncoef[l]);
+    if (l < L)
+      cbuf_count = std::max(cbuf_count, (int64_t)np * D.ncoef[l]);
+    else
+      ARENA_ALLOC(P.arena, D.cbufL, (int64_t)np * D.ncoef[l]);
     if (r) return r;
   }
   // ---- M2M (child level l -> parent l-1) and L2L (l-1 -> l), l >= 3 ----
@@ -811,6 +814,9 @@ int build_operators(Problem& P, hipStream_t s) {
   ARENA_ALLOC(P.arena, P.p64s, P.n);
   ARENA_ALLOC(P.arena, P.q64s, P.n);
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+  BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side2, hipStreamNonBlocking));
+  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_fork2, hipEventDisableTiming));
+  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_join2, hipEventDisableTiming));
   BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
   BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
   BEM_HIP_TRY(hipStreamSynchronize(s));

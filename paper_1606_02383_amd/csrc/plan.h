@@ -69,7 +69,8 @@ struct PrecisionData {
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2l{};
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2m{};  // level l -> l-1 (index l)
   std::array<GroupedOp<R>, MAX_LEVEL + 1> l2l{};  // level l-1 -> l (index l)
-  cplx<R>* cbuf = nullptr;  // per-pair products of the largest M2L level
+  cplx<R>* cbuf = nullptr;   // per-pair M2L products, levels below the leaf level
+  cplx<R>* cbufL = nullptr;  // per-pair M2L products, leaf level (own stream)
   cplx<R>* p2m = nullptr;   // n x ncoef_L x 2 (columns: p, q), sorted order
   cplx<R>* l2p = nullptr;   // n x ncoef_L
   // near-field corrections (accurate - 3-point rule), CSR by target and
@@ -141,6 +142,9 @@ struct Problem {
   // concurrently with the far-field chain; fork/join events
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // third stream: the leaf-level M2L (the largest) overlaps the coarser levels
+  hipStream_t side2 = nullptr;
+  hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
   // stage profiling with HIP events (off unless enabled)
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;

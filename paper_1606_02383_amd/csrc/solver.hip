@@ -438,7 +438,10 @@ int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x,
       in.iters = 0;
       hipLaunchKernelGGL(k_set_zero, dim3(nb), dim3(256), 0, s, dvec, n);
       BEM_LAUNCH_CHECK();
+      // ask the inner solve only for the reduction still needed (with a
+      // factor-2 margin), never tighter than inner_tol
       double itol = inner_tol > 0 ? inner_tol : 1e-4;
+      itol = std::max(itol, 0.5 * tol * bn / rn);
       int ist = gmres_core(W, A32, rvec, dvec, n, itol * rn, restart, max_iter - st.iters, true,
                            in, s);
       st.iters += in.iters;
