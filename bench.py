@@ -69,6 +69,21 @@ def cpu_baseline(V, T, k, seed, target_s=15.0):
 _G = None
 
 
+def measured_traffic():
+    """HBM bytes per float32 M2L launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "m2l_counters.json")
+    try:
+        meta = json.load(open(path))
+        src = open(os.path.join(ROOT, meta["kernel_source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != meta.get("kernel_source_sha256"):
+        return None
+    return meta.get("bytes_per_launch")
+
+
 def _cpu_rows(rows):
     import os as _os
     _os.environ["OMP_NUM_THREADS"] = "1"
@@ -186,7 +201,7 @@ def main():
     roofline = {"kernel": "k_grouped_gemm<float,false,0> (M2L, float32)", "bound": "mfma",
                 "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 4),
-                "traffic": None,
+                "traffic": measured_traffic(),
                 "flops_per_matvec": flops_m2l, "launches_per_matvec": n_lvl,
                 "avg_launch_ms": round(per_launch_ms, 5)}
 
