@@ -81,7 +81,10 @@ typedef struct {
   double near_eta;     /* near-pair radius factor eta (<= 0 -> 2)           */
   int32_t leaf_cap;    /* uniform leaf level = smallest level >= 2 whose
                           fullest leaf holds <= leaf_cap elements (<=0->64) */
-  int32_t leaf_level;  /* > 0 forces the leaf level instead                 */
+  int32_t leaf_level;  /* > 0 forces the leaf level instead; < 0 tunes it:
+                          the occupancy-rule level and its two neighbours
+                          are built and timed on a float32 product at plan
+                          creation, and the fastest is kept              */
   int32_t order64;     /* expansion order of the float64 far field, or <=0:
                           chosen per level from the wavenumber             */
   int32_t order32;     /* same for the float32 far field                   */
@@ -122,6 +125,8 @@ typedef struct {
   int32_t order32[22];
   double box_size[22];
   int64_t device_bytes;    /* device memory held by this problem             */
+  double tuned_ms;         /* leaf_level < 0: float32 product time (ms) of the
+                              kept leaf level; 0 otherwise                   */
 } bem_plan_stats;
 
 /* Build a plan for n_probs problems.  Uploads the meshes and runs, on the
@@ -155,6 +160,24 @@ int bem_fmm_matvec_adjoint(bem_plan* plan, int prob, int prec, const void* y, vo
  * relative residual recomputed with the float64 operator.  Synchronises. */
 int bem_gmres_solve(bem_plan* plan, int prob, const void* sigma, int adjoint, const void* b,
                     void* x, const bem_gmres_opts* opts, bem_gmres_info* info, void* stream);
+
+/* Batched solves: n_sys systems, system i being problem probs[i] with
+ * sigma[i] (may be NULL, or sigma itself NULL for all rigid), adjoint[i]
+ * (NULL = all forward), right-hand side b[i] and solution x[i] (device
+ * complex128, distinct x).  probs, sigma, adjoint, b, x and infos are HOST
+ * arrays (of device pointers).  All systems advance in lockstep, one float64
+ * residual or one Arnoldi step per system per tick, with one host
+ * synchronisation per tick; systems of different problems run concurrently
+ * on per-problem streams, systems of one problem share its stream.  Same
+ * options and exit test as bem_gmres_solve (mode 1: GMRES(m) on the float32
+ * operator inside each refinement step, restarted from the float64 residual).
+ * Returns BEM_OK when every system converged, else the first failing status;
+ * infos[i] (may be NULL) reports each system.  Ordered after prior work on
+ * `stream`; synchronises before returning. */
+int bem_gmres_solve_batch(bem_plan* plan, int n_sys, const int32_t* probs,
+                          const void* const* sigma, const int32_t* adjoint, const void* const* b,
+                          void* const* x, const bem_gmres_opts* opts, bem_gmres_info* infos,
+                          void* stream);
 
 /* Right-hand side of a plane wave exp(i k d.x) of unit amplitude:
  * b_i = p_inc(x_i) + alpha dp_inc/dn(x_i) (device complex128 out). */

@@ -29,7 +29,8 @@ STATUS = {0: "BEM_OK", -1: "BEM_E_INVALID", -2: "BEM_E_OOM", -3: "BEM_E_HIP",
           -4: "BEM_E_NOCONV", -5: "BEM_E_BREAKDOWN", -6: "BEM_E_NAN"}
 
 EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm_matvec",
-           "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_plane_wave_rhs", "bem_eval_field",
+           "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
+           "bem_plane_wave_rhs", "bem_eval_field",
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
            "bem_leaves_export", "bem_profile_start", "bem_profile_stop", "bem_last_error"]
 
@@ -68,7 +69,8 @@ class _Stats(ctypes.Structure):
                 ("n_leaves", ctypes.c_int32), ("n_near", ctypes.c_int64),
                 ("n_p2p_pairs", ctypes.c_int64), ("n_m2l", ctypes.c_int64 * 22),
                 ("order64", ctypes.c_int32 * 22), ("order32", ctypes.c_int32 * 22),
-                ("box_size", ctypes.c_double * 22), ("device_bytes", ctypes.c_int64)]
+                ("box_size", ctypes.c_double * 22), ("device_bytes", ctypes.c_int64),
+                ("tuned_ms", ctypes.c_double)]
 
 
 _LIB = None
@@ -91,6 +93,10 @@ def load_library(path: str = LIB_PATH):
     lib.bem_fmm_matvec_adjoint.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp]
     lib.bem_gmres_solve.argtypes = [vp, i32, vp, i32, vp, vp, ctypes.POINTER(_Opts),
                                     ctypes.POINTER(_Info), vp]
+    lib.bem_gmres_solve_batch.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                          ctypes.POINTER(_Opts), ctypes.POINTER(_Info), vp]
     lib.bem_plane_wave_rhs.argtypes = [vp, i32, dp, vp, vp]
     lib.bem_eval_field.argtypes = [vp, i32, vp, vp, vp, i32, dp, vp, vp]
     lib.bem_eval_field_adjoint.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
@@ -138,7 +144,7 @@ class Problem:
     alpha: complex | None = None     # default i/k
     near_eta: float = 2.0
     leaf_cap: int = 64
-    leaf_level: int = 0
+    leaf_level: int = 0              # > 0 forced, < 0 tuned at plan creation
     order64: int = 0
     order32: int = 0
 
@@ -216,7 +222,8 @@ class Plan:
         return dict(n_tri=st.n_tri, leaf_level=L, n_leaves=st.n_leaves, n_near=st.n_near,
                     n_p2p_pairs=st.n_p2p_pairs, n_m2l=list(st.n_m2l[:L + 1]),
                     order64=list(st.order64[:L + 1]), order32=list(st.order32[:L + 1]),
-                    box_size=list(st.box_size[:L + 1]), device_bytes=st.device_bytes)
+                    box_size=list(st.box_size[:L + 1]), device_bytes=st.device_bytes,
+                    tuned_ms=st.tuned_ms)
 
     # ---- products
     def matvec(self, p, q=None, prec=BEM_C128, prob=0, out=None):
@@ -252,6 +259,37 @@ class Plan:
             _check(code)
         d["status"] = STATUS.get(code, code)
         return x, d
+
+    def solve_batch(self, systems, opts: GmresOptions | None = None):
+        """Lockstep batched solves.  systems: list of dicts with keys
+        'prob', 'b' and optional 'sigma', 'adjoint'.  Returns (xs, infos)."""
+        opts = opts or GmresOptions()
+        ns = len(systems)
+        probs = (ctypes.c_int32 * ns)()
+        adj = (ctypes.c_int32 * ns)()
+        sg = (ctypes.c_void_p * ns)()
+        bs = (ctypes.c_void_p * ns)()
+        xs_p = (ctypes.c_void_p * ns)()
+        keep, xs = [], []
+        for i, s in enumerate(systems):
+            pr = int(s.get("prob", 0))
+            b = self._in(s["b"], pr)
+            sigma = self._in(s.get("sigma"), pr)
+            x = self._vec(pr)
+            keep += [b, sigma]
+            xs.append(x)
+            probs[i] = pr
+            adj[i] = int(bool(s.get("adjoint", False)))
+            sg[i] = sigma.data_ptr() if sigma is not None else None
+            bs[i] = b.data_ptr()
+            xs_p[i] = x.data_ptr()
+        infos = (_Info * ns)()
+        o = opts.c()
+        code = _LIB.bem_gmres_solve_batch(self._h, ns, probs, sg, adj, bs, xs_p, ctypes.byref(o),
+                                          infos, _stream())
+        if code not in (0, -4):
+            _check(code)
+        return xs, [infos[i].as_dict() for i in range(ns)]
 
     def plane_wave_rhs(self, direction, prob=0):
         d = np.ascontiguousarray(direction, dtype=np.float64)

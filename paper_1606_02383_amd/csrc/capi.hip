@@ -15,6 +15,10 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 int objective_grad(Problem& P, const c64* beta, const double* dir, const double* pts_host,
                    int n_pts, const bem_gmres_opts* opts, double* J, c64* grad, c64* p_out,
                    bem_gmres_info* info_f, bem_gmres_info* info_a, hipStream_t s);
+int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjoint,
+                      const std::vector<const c64*>& sigma, const std::vector<const c64*>& b,
+                      const std::vector<c64*>& x, double tol, int m, int max_iter, int mode,
+                      double inner_tol, int use_x0, bem_gmres_info* infos, hipStream_t caller);
 
 static void destroy_problem(Problem* P) {
   if (!P) return;
@@ -27,6 +31,7 @@ static void destroy_problem(Problem* P) {
   if (P->ev_fork2) (void)hipEventDestroy(P->ev_fork2);
   if (P->ev_join2) (void)hipEventDestroy(P->ev_join2);
   if (P->side2) (void)hipStreamDestroy(P->side2);
+  if (P->bstream) (void)hipStreamDestroy(P->bstream);
   P->arena.release();
   delete P;
 }
@@ -47,6 +52,79 @@ static int fail(int code, const std::string& msg) {
 static Problem* get_prob(bem_plan* plan, int prob) {
   if (!plan || prob < 0 || prob >= (int)plan->probs.size()) return nullptr;
   return plan->probs[prob];
+}
+
+// Mean time of one float32 product of a built problem (HIP events).
+static int time_f32_product(Problem& P, hipStream_t s, float* ms) {
+  c64* v = nullptr;
+  c64* y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (v) (void)hipFree(v);
+    if (y) (void)hipFree(y);
+  };
+  int r = 0;
+  auto check = [&](hipError_t e) {
+    if (e != hipSuccess && !r) {
+      set_error(std::string("HIP error '") + hipGetErrorString(e) + "' in the leaf-level tuner");
+      r = -3;
+    }
+    return r == 0;
+  };
+  if (check(hipMalloc((void**)&v, sizeof(c64) * P.n)) &&
+      check(hipMalloc((void**)&y, sizeof(c64) * P.n)) &&
+      check(hipMemsetAsync(v, 0, sizeof(c64) * P.n, s)) && check(hipEventCreate(&e0)) &&
+      check(hipEventCreate(&e1))) {
+    r = fmm_apply<float>(P, P.f32, v, nullptr, y, s);  // warm-up
+    if (!r) check(hipEventRecord(e0, s));
+    for (int t = 0; t < 5 && !r; ++t) r = fmm_apply<float>(P, P.f32, v, nullptr, y, s);
+    float t = 0.f;
+    if (!r && check(hipEventRecord(e1, s)) && check(hipEventSynchronize(e1)) &&
+        check(hipEventElapsedTime(&t, e0, e1)))
+      *ms = t / 5.0f;
+  }
+  cleanup();
+  return r;
+}
+
+// Autotuner: the leaf level chosen by the occupancy rule and its two
+// neighbours (within [2, finest level allowed by the near radius]) are built
+// and timed on a float32 product; the fastest plan is kept.
+template <typename Build>
+static int autotune_leaf_level(const bem_problem& q, Build& build_one, Problem** best,
+                               hipStream_t s) {
+  Problem* cur = *best;
+  float best_ms = 0.f;
+  int r = time_f32_product(*cur, s, &best_ms);
+  if (r) return r;
+  const int L0 = cur->L;
+  for (int L : {L0 - 1, L0 + 1}) {
+    if (L < 2) continue;
+    Problem* cand = nullptr;
+    r = build_one(q, L, &cand);
+    if (r) return r;
+    if (cand->L != L || cand->direct) {  // level capped by the near radius
+      destroy_problem(cand);
+      continue;
+    }
+    float ms = 0.f;
+    r = time_f32_product(*cand, s, &ms);
+    if (r) {
+      destroy_problem(cand);
+      return r;
+    }
+    if (ms < best_ms) {
+      destroy_problem(*best);
+      *best = cand;
+      best_ms = ms;
+    } else {
+      destroy_problem(cand);
+    }
+  }
+  (*best)->tuned_ms = best_ms;
+  return 0;
 }
 
 extern "C" {
@@ -74,26 +152,37 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
   }
   hipStream_t s = (hipStream_t)stream;
   bem_plan* plan = new bem_plan();
-  for (int i = 0; i < n_probs; ++i) {
-    const bem_problem& q = probs[i];
+  auto build_one = [&](const bem_problem& q, int leaf_level, Problem** outp) -> int {
     Problem* P = new Problem();
-    plan->probs.push_back(P);
     P->n = q.n_tri;
     P->k = q.k;
     P->alpha = mk(q.alpha_re, q.alpha_im);
     P->eta = q.near_eta > 0 ? q.near_eta : 2.0;
     P->leaf_cap = q.leaf_cap > 0 ? q.leaf_cap : 64;
-    P->leaf_level_req = q.leaf_level;
+    P->leaf_level_req = leaf_level;
     P->order64_req = q.order64;
     P->order32_req = q.order32;
     int r = build_geometry_and_tree(*P, q.vert, q.n_vert, q.tri, s);
     if (!r) r = build_near_field(*P, s);
     if (!r) r = build_operators(*P, s);
     if (r) {
+      destroy_problem(P);
+      return r;
+    }
+    *outp = P;
+    return 0;
+  };
+  for (int i = 0; i < n_probs; ++i) {
+    const bem_problem& q = probs[i];
+    Problem* P = nullptr;
+    int r = build_one(q, q.leaf_level > 0 ? q.leaf_level : 0, &P);
+    if (!r && q.leaf_level < 0 && !P->direct) r = autotune_leaf_level(q, build_one, &P, s);
+    if (r) {
       for (Problem* pp : plan->probs) destroy_problem(pp);
       delete plan;
       return r;
     }
+    plan->probs.push_back(P);
   }
   *out = plan;
   return BEM_OK;
@@ -122,6 +211,7 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
     st->box_size[l] = P->h[l];
   }
   st->device_bytes = P->arena.bytes;
+  st->tuned_ms = P->tuned_ms;
   return BEM_OK;
 }
 
@@ -180,6 +270,36 @@ int bem_gmres_solve(bem_plan* plan, int prob, const void* sigma, int adjoint, co
   if (info) std::memset(info, 0, sizeof(*info));
   return gmres_solve(*P, (const c64*)sigma, adjoint, (const c64*)b, (c64*)x, opts->tol, m, mi,
                      opts->mode, opts->inner_tol, opts->use_x0, info, (hipStream_t)stream);
+}
+
+int bem_gmres_solve_batch(bem_plan* plan, int n_sys, const int32_t* probs,
+                          const void* const* sigma, const int32_t* adjoint, const void* const* b,
+                          void* const* x, const bem_gmres_opts* opts, bem_gmres_info* infos,
+                          void* stream) {
+  if (!plan || n_sys < 1 || !probs || !b || !x || !opts)
+    return fail(BEM_E_INVALID, "bad batch arguments");
+  if (!(opts->tol > 0.0)) return fail(BEM_E_INVALID, "tol must be > 0");
+  if (opts->mode != 0 && opts->mode != 1) return fail(BEM_E_INVALID, "bad mode");
+  int m = opts->restart > 0 ? opts->restart : 50;
+  if (m > 500) return fail(BEM_E_INVALID, "restart > 500");
+  int mi = opts->max_iter > 0 ? opts->max_iter : 2000;
+  std::vector<Problem*> ps(n_sys);
+  std::vector<int> adj(n_sys);
+  std::vector<const c64*> sg(n_sys), bb(n_sys);
+  std::vector<c64*> xx(n_sys);
+  for (int i = 0; i < n_sys; ++i) {
+    ps[i] = get_prob(plan, probs[i]);
+    if (!ps[i]) return fail(BEM_E_INVALID, "bad problem index in batch");
+    if (!b[i] || !x[i] || b[i] == x[i]) return fail(BEM_E_INVALID, "bad b/x in batch");
+    for (int j = 0; j < i; ++j)
+      if (x[j] == x[i]) return fail(BEM_E_INVALID, "two systems share one solution vector");
+    adj[i] = adjoint ? adjoint[i] : 0;
+    sg[i] = sigma ? (const c64*)sigma[i] : nullptr;
+    bb[i] = (const c64*)b[i];
+    xx[i] = (c64*)x[i];
+  }
+  return gmres_solve_batch(ps, adj, sg, bb, xx, opts->tol, m, mi, opts->mode, opts->inner_tol,
+                           opts->use_x0, infos, (hipStream_t)stream);
 }
 
 int bem_plane_wave_rhs(bem_plan* plan, int prob, const double* dir3, void* b, void* stream) {

@@ -815,6 +815,7 @@ int build_operators(Problem& P, hipStream_t s) {
   ARENA_ALLOC(P.arena, P.q64s, P.n);
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side2, hipStreamNonBlocking));
+  BEM_HIP_TRY(hipStreamCreateWithFlags(&P.bstream, hipStreamNonBlocking));
   BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_fork2, hipEventDisableTiming));
   BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_join2, hipEventDisableTiming));
   BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));

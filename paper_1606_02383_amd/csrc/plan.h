@@ -112,6 +112,7 @@ struct Problem {
   double lo[3]{}, R0 = 0, scale = 0, ell_max = 0;
   // tree
   int L = 0;
+  float tuned_ms = 0.f;  // autotuner: float32 product time of the kept leaf level
   bool direct = false;  // leaves not wider than the near radius: direct sum, no far field
   std::array<int, MAX_LEVEL + 1> nbox{};
   std::array<uint64_t*, MAX_LEVEL + 1> box_keys{};
@@ -144,6 +145,8 @@ struct Problem {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // third stream: the leaf-level M2L (the largest) overlaps the coarser levels
   hipStream_t side2 = nullptr;
+  // stream of this problem inside batched solves (problems run concurrently)
+  hipStream_t bstream = nullptr;
   hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
   // stage profiling with HIP events (off unless enabled)
   bool prof_on = false;

@@ -15,6 +15,8 @@
 #include <complex>
 #include <functional>
 #include <vector>
+#include <algorithm>
+#include <cstring>
 
 #include "../../include/bemfmm.h"
 #include "plan.h"
@@ -722,6 +724,288 @@ void release_workspace(Problem& P) {
     delete W;
     P.solver_ws = nullptr;
   }
+}
+
+// ---------------------------------------------------------------------------
+// batched solves: many systems (problem, sigma, direction, rhs) advance in
+// lockstep.  Every tick issues, for each active system, either a float64
+// residual or one Arnoldi step on its problem's stream (systems of one problem
+// share that stream and its product workspaces; different problems run
+// concurrently), then synchronises once and does the small host-side work
+// (norms, Givens rotations, decisions) for all systems.
+// ---------------------------------------------------------------------------
+struct BatchSys {
+  Problem* P = nullptr;
+  int adjoint = 0;
+  const c64* sigma = nullptr;
+  const c64* b = nullptr;
+  c64* x = nullptr;
+  Workspace W;
+  hipStream_t s = nullptr;
+  int state = 0;  // 0 outer residual, 1 Arnoldi, 2 done
+  bool first = true;
+  double bn = 0, rn = 0, atol = 0, beta = 0;
+  int j = 0, iters = 0, mv64 = 0, mv32 = 0, outer = 0, status = -4;
+  std::vector<std::complex<double>> H, cs, sn, g;
+  std::vector<double> hist;
+  c64* hbuf = nullptr;  // pinned host mirror of the scalars read back per tick
+};
+
+static int batch_apply(BatchSys& S, bool f32, const c64* v, c64* out) {
+  Problem& P = *S.P;
+  const int64_t n = P.n;
+  const int nb = ceil_div(n, 256);
+  hipStream_t s = S.s;
+  int rr;
+  if (!S.adjoint) {
+    const c64* q = nullptr;
+    if (S.sigma) {
+      hipLaunchKernelGGL(k_diag_mul, dim3(nb), dim3(256), 0, s, S.sigma, v, n, 0, S.W.t3);
+      BEM_LAUNCH_CHECK();
+      q = S.W.t3;
+    }
+    rr = f32 ? fmm_apply<float>(P, P.f32, v, q, out, s) : fmm_apply<double>(P, P.f64, v, q, out, s);
+    if (rr) return rr;
+  } else {
+    c64* wv = S.sigma ? S.W.t3 : nullptr;
+    rr = f32 ? fmm_apply_adjoint<float>(P, P.f32, v, out, wv, s)
+             : fmm_apply_adjoint<double>(P, P.f64, v, out, wv, s);
+    if (rr) return rr;
+    if (S.sigma) {
+      hipLaunchKernelGGL(k_add_conj_diag, dim3(nb), dim3(256), 0, s, out, S.sigma, S.W.t3, n, out);
+      BEM_LAUNCH_CHECK();
+    }
+  }
+  if (f32)
+    ++S.mv32;
+  else
+    ++S.mv64;
+  return 0;
+}
+
+int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjoint,
+                      const std::vector<const c64*>& sigma, const std::vector<const c64*>& b,
+                      const std::vector<c64*>& x, double tol, int m, int max_iter, int mode,
+                      double inner_tol, int use_x0, bem_gmres_info* infos, hipStream_t caller) {
+  const int ns = (int)probs.size();
+  std::vector<BatchSys> sys(ns);
+  c64* hpin = nullptr;
+  BEM_HIP_TRY(hipHostMalloc((void**)&hpin, sizeof(c64) * (size_t)ns * (2 * m + 4)));
+  struct PinGuard {
+    c64* p;
+    ~PinGuard() { (void)hipHostFree(p); }
+  } pin{hpin};
+  hipEvent_t start;
+  BEM_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t e;
+    ~EvGuard() { (void)hipEventDestroy(e); }
+  } evg{start};
+  BEM_HIP_TRY(hipEventRecord(start, caller));
+  std::vector<hipStream_t> streams;
+  for (int i = 0; i < ns; ++i) {
+    BatchSys& S = sys[i];
+    S.P = probs[i];
+    S.adjoint = adjoint[i];
+    S.sigma = sigma[i];
+    S.b = b[i];
+    S.x = x[i];
+    S.s = S.P->bstream;
+    S.hbuf = hpin + (size_t)i * (2 * m + 4);
+    if (std::find(streams.begin(), streams.end(), S.s) == streams.end()) {
+      streams.push_back(S.s);
+      BEM_HIP_TRY(hipStreamWaitEvent(S.s, start, 0));
+    }
+    int r = S.W.ensure(S.P->n, m);
+    if (r) return r;
+    S.H.assign((size_t)(m + 1) * m, 0.0);
+    S.cs.assign(m, 0.0);
+    S.sn.assign(m, 0.0);
+    S.g.assign(m + 1, 0.0);
+    S.first = !use_x0;
+  }
+  // norms of the right-hand sides
+  for (auto& S : sys) {
+    int r = multidot(S.W, S.b, S.P->n, S.P->n, 1, S.b, S.W.h2, 0, S.s);
+    if (r) return r;
+    BEM_HIP_TRY(hipMemcpyAsync(S.hbuf, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, S.s));
+    if (S.first) {
+      hipLaunchKernelGGL(k_set_zero, dim3(ceil_div(S.P->n, 256)), dim3(256), 0, S.s, S.x, S.P->n);
+      BEM_LAUNCH_CHECK();
+    }
+  }
+  for (hipStream_t st : streams) BEM_HIP_TRY(hipStreamSynchronize(st));
+  for (auto& S : sys) {
+    S.bn = sqrt(S.hbuf[0].re);
+    if (!std::isfinite(S.bn)) {
+      S.status = -6;
+      S.state = 2;
+    } else if (S.bn == 0.0) {
+      S.status = 0;
+      S.state = 2;
+    }
+  }
+  for (int tick = 0; tick < 100000; ++tick) {
+    bool any = false;
+    // issue
+    for (auto& S : sys) {
+      if (S.state == 2) continue;
+      any = true;
+      const int64_t n = S.P->n;
+      const int nb = ceil_div(n, 256);
+      int r = 0;
+      if (S.state == 0) {
+        if (S.first) {
+          hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, S.s, S.b, n, S.W.r);
+          BEM_LAUNCH_CHECK();
+        } else {
+          if ((r = batch_apply(S, false, S.x, S.W.t1))) return r;
+          hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, S.s, S.b, S.W.t1, n, S.W.r);
+          BEM_LAUNCH_CHECK();
+        }
+        if ((r = multidot(S.W, S.W.r, n, n, 1, S.W.r, S.W.h2, 0, S.s))) return r;
+        BEM_HIP_TRY(hipMemcpyAsync(S.hbuf, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, S.s));
+      } else {
+        const int j = S.j;
+        if ((r = batch_apply(S, mode == 1, S.W.V + (int64_t)j * n, S.W.w))) return r;
+        if ((r = multidot(S.W, S.W.V, n, n, j + 1, S.W.w, S.W.h, 0, S.s))) return r;
+        hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, S.s, S.W.V, n, n, j + 1, S.W.h,
+                           S.W.w);
+        BEM_LAUNCH_CHECK();
+        if ((r = multidot(S.W, S.W.V, n, n, j + 1, S.W.w, S.W.h2, 0, S.s))) return r;
+        hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, S.s, S.W.V, n, n, j + 1, S.W.h2,
+                           S.W.w);
+        BEM_LAUNCH_CHECK();
+        if ((r = multidot(S.W, S.W.w, n, n, 1, S.W.w, S.W.h2 + j + 1, 0, S.s))) return r;
+        hipLaunchKernelGGL(k_normalise, dim3(nb), dim3(256), 0, S.s, S.W.w, n, S.W.h2 + j + 1,
+                           S.W.V + (int64_t)(j + 1) * n);
+        BEM_LAUNCH_CHECK();
+        BEM_HIP_TRY(hipMemcpyAsync(S.hbuf, S.W.h, sizeof(c64) * (j + 1), hipMemcpyDeviceToHost, S.s));
+        BEM_HIP_TRY(hipMemcpyAsync(S.hbuf + j + 1, S.W.h2, sizeof(c64) * (j + 2),
+                                   hipMemcpyDeviceToHost, S.s));
+      }
+    }
+    if (!any) break;
+    for (hipStream_t st : streams) BEM_HIP_TRY(hipStreamSynchronize(st));
+    // host decisions
+    for (auto& S : sys) {
+      if (S.state == 2) continue;
+      const int64_t n = S.P->n;
+      const int nb = ceil_div(n, 256);
+      if (S.state == 0) {
+        S.first = false;
+        S.rn = sqrt(S.hbuf[0].re);
+        S.hist.push_back(S.rn / S.bn);
+        if (!std::isfinite(S.rn)) {
+          S.status = -6;
+          S.state = 2;
+          continue;
+        }
+        if (S.rn <= tol * S.bn) {
+          S.status = 0;
+          S.state = 2;
+          continue;
+        }
+        if (S.iters >= max_iter || (mode == 1 && S.outer >= 30)) {
+          S.status = -4;
+          S.state = 2;
+          continue;
+        }
+        double itol = (mode == 1) ? std::max(inner_tol > 0 ? inner_tol : 1e-4, 0.5 * tol * S.bn / S.rn)
+                                  : tol * S.bn / S.rn;
+        S.atol = itol * S.rn;
+        S.beta = S.rn;
+        hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, S.s, S.W.r, n, S.W.V);
+        BEM_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, S.s, S.W.V, n, 1.0 / S.beta);
+        BEM_LAUNCH_CHECK();
+        std::fill(S.g.begin(), S.g.end(), 0.0);
+        S.g[0] = S.beta;
+        S.j = 0;
+        S.state = 1;
+      } else {
+        const int j = S.j;
+        std::vector<std::complex<double>> col(j + 2);
+        for (int i = 0; i <= j; ++i)
+          col[i] = std::complex<double>(S.hbuf[i].re + S.hbuf[j + 1 + i].re,
+                                        S.hbuf[i].im + S.hbuf[j + 1 + i].im);
+        double hn = sqrt(S.hbuf[j + 1 + j + 1].re);
+        col[j + 1] = hn;
+        ++S.iters;
+        if (!std::isfinite(hn)) {
+          S.status = -6;
+          S.state = 2;
+          continue;
+        }
+        for (int i = 0; i < j; ++i) {
+          std::complex<double> t = S.cs[i] * col[i] + S.sn[i] * col[i + 1];
+          col[i + 1] = -std::conj(S.sn[i]) * col[i] + std::conj(S.cs[i]) * col[i + 1];
+          col[i] = t;
+        }
+        double den = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
+        if (den == 0.0) {
+          S.cs[j] = 1.0;
+          S.sn[j] = 0.0;
+        } else {
+          S.cs[j] = std::conj(col[j]) / den;
+          S.sn[j] = std::conj(col[j + 1]) / den;
+        }
+        col[j] = S.cs[j] * col[j] + S.sn[j] * col[j + 1];
+        S.g[j + 1] = -std::conj(S.sn[j]) * S.g[j];
+        S.g[j] = S.cs[j] * S.g[j];
+        for (int i = 0; i <= j; ++i) S.H[i * m + j] = col[i];
+        double est = std::abs(S.g[j + 1]);
+        S.hist.push_back(est / S.bn);
+        if (est <= S.atol || hn == 0.0 || j + 1 == m || S.iters >= max_iter) {
+          int jend = j + 1;
+          std::vector<std::complex<double>> yv(jend);
+          for (int i = jend - 1; i >= 0; --i) {
+            std::complex<double> acc = S.g[i];
+            for (int kk = i + 1; kk < jend; ++kk) acc -= S.H[i * m + kk] * yv[kk];
+            if (std::abs(S.H[i * m + i]) == 0.0) {
+              acc = 0.0;
+              yv[i] = 0.0;
+              continue;
+            }
+            yv[i] = acc / S.H[i * m + i];
+          }
+          for (int i = 0; i < jend; ++i) S.hbuf[m + 1 + i] = mk(yv[i].real(), yv[i].imag());
+          BEM_HIP_TRY(hipMemcpyAsync(S.W.y, S.hbuf + m + 1, sizeof(c64) * jend,
+                                     hipMemcpyHostToDevice, S.s));
+          hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, S.s, S.W.V, n, n, jend, S.W.y, S.x);
+          BEM_LAUNCH_CHECK();
+          ++S.outer;
+          S.state = 0;
+        } else {
+          S.j = j + 1;
+        }
+      }
+    }
+  }
+  // join the caller's stream
+  for (hipStream_t st : streams) BEM_HIP_TRY(hipStreamSynchronize(st));
+  int worst = 0;
+  for (int i = 0; i < ns; ++i) {
+    BatchSys& S = sys[i];
+    if (infos) {
+      bem_gmres_info* info = infos + i;
+      std::memset(info, 0, sizeof(*info));
+      info->iterations = S.iters;
+      info->matvec64 = S.mv64;
+      info->matvec32 = S.mv32;
+      info->restarts = S.outer;
+      info->resid = (S.bn > 0) ? S.rn / S.bn : 0.0;
+      info->converged = S.status == 0;
+      int nh = std::min((int)S.hist.size(), 512);
+      info->n_hist = nh;
+      for (int t = 0; t < nh; ++t) info->hist[t] = S.hist[t];
+    }
+    if (S.status != 0 && worst == 0) worst = S.status;
+    S.W.arena.release();
+  }
+  if (worst == -4) set_error("some systems of the batch did not converge (see infos)");
+  if (worst == -6) set_error("NaN or Inf met in a system of the batch");
+  return worst;
 }
 
 }  // namespace bemfmm

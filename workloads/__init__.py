@@ -190,5 +190,23 @@ WORKLOADS = {
 }
 
 
+# mixed-mesh batch: 16 state solves and the 16 matching adjoint solves
+BATCH_LEVELS = (4, 5, 6)
+BATCH_KS = (2.0, 4.0, 8.0)
+
+
+def batch32(seed: int = 5):
+    """State solve s = 0..15 runs on icosphere level ``[4,5,6][s mod 3]`` at
+    ``k = [2,4,8][(s div 3) mod 3]`` with a seeded incidence direction; the
+    adjoint solve s reuses its mesh and k.  Returns ``(cases, obs)`` with
+    cases = [(level, k, direction)] and 8 observation points on the
+    radius-3 sphere."""
+    rng = np.random.default_rng(seed)
+    dirs = unit_directions(rng, 16)
+    obs = 3.0 * unit_directions(rng, 8)
+    cases = [(BATCH_LEVELS[s % 3], BATCH_KS[(s // 3) % 3], dirs[s]) for s in range(16)]
+    return cases, obs
+
+
 def workload(name: str) -> Workload:
     return WORKLOADS[name]
