@@ -32,11 +32,20 @@ namespace bemfmm {
 constexpr int RED_BLOCKS = 128;
 constexpr int RED_THREADS = 256;
 
-// partial[k * RED_BLOCKS + bx] = sum_{i in block bx} conj(V_k[i]) w[i]
-__global__ void k_multidot_partial(const c64* __restrict__ V, int64_t ld, int64_t n,
-                                   const c64* __restrict__ w, double* __restrict__ partial) {
-  __shared__ double sr[RED_THREADS], si[RED_THREADS];
-  int kvec = blockIdx.y;
+// Fixed-order sum over a wavefront: lane l holds v; every lane gets the total.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// partial[k][bx] = sum over block bx of conj(V_k[i]) w[i], k < gridDim.y
+// (complex, interleaved re/im).  The final sums are formed by the kernel
+// that consumes them (fold_dots), so no grid-wide synchronisation is needed.
+__global__ void __launch_bounds__(RED_THREADS)
+    k_multidot_partial(const c64* __restrict__ V, int64_t ld, int64_t n,
+                       const c64* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double sr[RED_THREADS / 64], si[RED_THREADS / 64];
+  const int kvec = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const c64* v = V + kvec * ld;
   double ar = 0, ai = 0;
   for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n;
@@ -45,70 +54,115 @@ __global__ void k_multidot_partial(const c64* __restrict__ V, int64_t ld, int64_
     ar += a.re * b.re + a.im * b.im;
     ai += a.re * b.im - a.im * b.re;
   }
-  sr[threadIdx.x] = ar;
-  si[threadIdx.x] = ai;
-  __syncthreads();
-  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sr[threadIdx.x] += sr[threadIdx.x + s];
-      si[threadIdx.x] += si[threadIdx.x + s];
-    }
-    __syncthreads();
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if (lane == 0) {
+    sr[wave] = ar;
+    si[wave] = ai;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    partial[2 * (kvec * RED_BLOCKS + blockIdx.x)] = sr[0];
-    partial[2 * (kvec * RED_BLOCKS + blockIdx.x) + 1] = si[0];
+    partial[2 * (kvec * RED_BLOCKS + blockIdx.x)] = (sr[0] + sr[1]) + (sr[2] + sr[3]);
+    partial[2 * (kvec * RED_BLOCKS + blockIdx.x) + 1] = (si[0] + si[1]) + (si[2] + si[3]);
   }
 }
 
-// out[k] (+)= sum_bx partial[k][bx]   (accumulate != 0 adds to out)
-__global__ void k_multidot_final(const double* __restrict__ partial, int nk,
-                                 c64* __restrict__ out, int accumulate) {
-  __shared__ double sr[RED_BLOCKS], si[RED_BLOCKS];
-  int kvec = blockIdx.x;
-  int t = threadIdx.x;
-  sr[t] = partial[2 * (kvec * RED_BLOCKS + t)];
-  si[t] = partial[2 * (kvec * RED_BLOCKS + t) + 1];
+// hs[k] = sum_bx partial[k][bx] for k < nk into shared memory, in a fixed
+// order (every block of the caller gets bit-identical values); block 0
+// also stores them to out.  Wave q handles k = q, q + 4, ...
+__device__ __forceinline__ void fold_dots(const double* __restrict__ partial, int nk, c64* hs,
+                                          c64* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = wave; k < nk; k += 4) {
+    const double* pk = partial + 2 * (int64_t)k * RED_BLOCKS;
+    double r = pk[2 * lane] + pk[2 * (lane + 64)];
+    double m = pk[2 * lane + 1] + pk[2 * (lane + 64) + 1];
+    r = wave_sum(r);
+    m = wave_sum(m);
+    if (lane == 0) {
+      hs[k] = mk(r, m);
+      if (out && blockIdx.x == 0) out[k] = mk(r, m);
+    }
+  }
   __syncthreads();
-  for (int s = RED_BLOCKS / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      sr[t] += sr[t + s];
-      si[t] += si[t + s];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    if (accumulate) {
-      out[kvec].re += sr[0];
-      out[kvec].im += si[0];
-    } else {
-      out[kvec] = mk(sr[0], si[0]);
-    }
-  }
 }
 
-// w -= sum_k V_k h_k
-__global__ void k_multiupdate(const c64* __restrict__ V, int64_t ld, int64_t n, int nk,
-                              const c64* __restrict__ h, c64* __restrict__ w) {
+// w -= sum_k V_k h_k with h_k folded from the dot partials (h stored to
+// hout by block 0); with nrm_partial != null also the block partials of
+// ||w||^2 after the update.  nk <= MAX_NK.
+constexpr int MAX_NK = 512;
+__global__ void __launch_bounds__(256)
+    k_multiupdate(const c64* __restrict__ V, int64_t ld, int64_t n, int nk,
+                  const double* __restrict__ partial, c64* __restrict__ hout,
+                  c64* __restrict__ w, double* __restrict__ nrm_partial) {
+  __shared__ c64 hs[MAX_NK];
+  __shared__ double sw[4];
+  fold_dots(partial, nk, hs, hout);
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  c64 acc = w[i];
-  for (int kk = 0; kk < nk; ++kk) {
-    c64 v = V[kk * ld + i], c = h[kk];
-    acc.re -= v.re * c.re - v.im * c.im;
-    acc.im -= v.re * c.im + v.im * c.re;
+  double sq = 0;
+  if (i < n) {
+    c64 acc = w[i];
+    for (int kk = 0; kk < nk; ++kk) {
+      c64 v = V[kk * ld + i], c = hs[kk];
+      acc.re -= v.re * c.re - v.im * c.im;
+      acc.im -= v.re * c.im + v.im * c.re;
+    }
+    w[i] = acc;
+    sq = acc.re * acc.re + acc.im * acc.im;
   }
-  w[i] = acc;
+  if (!nrm_partial) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  sq = wave_sum(sq);
+  if (lane == 0) sw[wave] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) nrm_partial[blockIdx.x] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
 }
 
-// dst = src / |h|  where h = out[0] holds ||w||^2 in its real part
-__global__ void k_normalise(const c64* __restrict__ src, int64_t n, const c64* __restrict__ nrm2,
-                            c64* __restrict__ dst) {
+// V_{j+1} = w / ||w||, ||w||^2 folded from the n_part block partials.
+// Block 0 stores ||w||^2 to nrm_out and writes the step's Hessenberg column
+// to col (host memory): col[i] = h1[i] + h2[i] for i <= j, col[j+1] = ||w||^2.
+__global__ void __launch_bounds__(256)
+    k_normalise(const c64* __restrict__ src, int64_t n, const double* __restrict__ nrm_partial,
+                int n_part, c64* __restrict__ dst, c64* __restrict__ nrm_out,
+                const c64* __restrict__ h1, const c64* __restrict__ h2, int j,
+                c64* __restrict__ col) {
+  __shared__ double s_nrm;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave == 0) {
+    double t = 0;
+    for (int b = lane; b < n_part; b += 64) t += nrm_partial[b];
+    t = wave_sum(t);
+    if (lane == 0) s_nrm = t;
+  }
+  __syncthreads();
+  const double nrm2 = s_nrm;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0 && nrm_out) *nrm_out = mk(nrm2, 0.0);
+    if (col) {
+      for (int t = threadIdx.x; t <= j + 1; t += blockDim.x)
+        col[t] = (t <= j) ? cadd(h1[t], h2[t]) : mk(nrm2, 0.0);
+      __threadfence_system();
+    }
+  }
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double s = sqrt(nrm2[0].re);
+  double s = sqrt(nrm2);
   double inv = (s > 0.0) ? 1.0 / s : 0.0;
   dst[i] = mk(src[i].re * inv, src[i].im * inv);
+}
+
+// out[k] = sum_bx partial[k][bx]  (one wave per k; same order as fold_dots)
+__global__ void k_multidot_final(const double* __restrict__ partial, int nk,
+                                 c64* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x;
+  if (k >= nk) return;
+  const double* pk = partial + 2 * (int64_t)k * RED_BLOCKS;
+  double r = pk[2 * lane] + pk[2 * (lane + 64)];
+  double m = pk[2 * lane + 1] + pk[2 * (lane + 64) + 1];
+  r = wave_sum(r);
+  m = wave_sum(m);
+  if (lane == 0) out[k] = mk(r, m);
 }
 
 // x += sum_k V_k y_k
@@ -183,10 +237,14 @@ struct Workspace {
   c64* h = nullptr;     // m+2
   c64* h2 = nullptr;
   c64* y = nullptr;
-  double* partial = nullptr;
+  double* partial = nullptr;   // RED_BLOCKS x (m+2) complex block partials
+  double* partial2 = nullptr;  // one per 256-element block
+  c64* hcol = nullptr;         // pinned host: 2 slots x (m+2) Hessenberg columns
+  c64* hscal = nullptr;        // pinned host: scalars read back (norms)
+  hipEvent_t ev[2] = {nullptr, nullptr};
   int ensure(int64_t n_, int m_) {
     if (n_ == n && m_ <= m) return 0;
-    arena.release();
+    release();
     n = n_;
     m = m_;
     ARENA_ALLOC(arena, V, (int64_t)(m + 1) * n);
@@ -201,7 +259,22 @@ struct Workspace {
     ARENA_ALLOC(arena, h2, m + 2);
     ARENA_ALLOC(arena, y, m + 2);
     ARENA_ALLOC(arena, partial, 2 * (int64_t)RED_BLOCKS * (m + 2));
+    ARENA_ALLOC(arena, partial2, ceil_div(n, 256) + 1);
+    BEM_HIP_TRY(hipHostMalloc((void**)&hcol, sizeof(c64) * 2 * (m + 2), hipHostMallocDefault));
+    BEM_HIP_TRY(hipHostMalloc((void**)&hscal, sizeof(c64) * 4, hipHostMallocDefault));
+    for (auto& e : ev) BEM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return 0;
+  }
+  void release() {
+    arena.release();
+    if (hcol) (void)hipHostFree(hcol);
+    if (hscal) (void)hipHostFree(hscal);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    hcol = hscal = nullptr;
+    ev[0] = ev[1] = nullptr;
+    n = 0;
+    m = 0;
   }
 };
 
@@ -210,25 +283,53 @@ static Workspace& workspace_for(Problem& P) {
   return *(Workspace*)P.solver_ws;
 }
 
-// dots out[k] = V_k^H w for k < nk
+// dots out[k] = V_k^H w for k < nk (partials, then one fixed-order fold)
 static int multidot(Workspace& W, const c64* V, int64_t ld, int64_t n, int nk, const c64* w,
-                    c64* out, int accumulate, hipStream_t s) {
-  hipLaunchKernelGGL(k_multidot_partial, dim3(RED_BLOCKS, nk), dim3(RED_THREADS), 0, s, V, ld, n, w,
-                     W.partial);
+                    c64* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_multidot_partial, dim3(RED_BLOCKS, nk), dim3(RED_THREADS), 0, s, V, ld, n,
+                     w, W.partial);
   BEM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_multidot_final, dim3(nk), dim3(RED_BLOCKS), 0, s, W.partial, nk, out,
-                     accumulate);
+  hipLaunchKernelGGL(k_multidot_final, dim3(nk), dim3(64), 0, s, W.partial, nk, out);
   BEM_LAUNCH_CHECK();
   return 0;
 }
 
+// ||v|| read back to the host (synchronises the stream)
 static int norm2(Workspace& W, const c64* v, int64_t n, double* out, hipStream_t s) {
-  int r = multidot(W, v, n, n, 1, v, W.h2, 0, s);
+  int r = multidot(W, v, n, n, 1, v, W.h2, s);
   if (r) return r;
-  c64 h;
-  BEM_HIP_TRY(hipMemcpyAsync(&h, W.h2, sizeof(c64), hipMemcpyDeviceToHost, s));
+  BEM_HIP_TRY(hipMemcpyAsync(W.hscal, W.h2, sizeof(c64), hipMemcpyDeviceToHost, s));
   BEM_HIP_TRY(hipStreamSynchronize(s));
-  *out = sqrt(h.re);
+  *out = sqrt(W.hscal[0].re);
+  return 0;
+}
+
+// Orthogonalisation of one Arnoldi step (w = A V_j on entry), CGS2:
+//   h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, V_{j+1} = w / ||w||
+// in five launches (each update folds the preceding dot partials itself);
+// the column (h1 + h2, ||w||^2) lands in host slot `slot` of W.hcol and
+// W.ev[slot] is recorded after it.
+static int arnoldi_orth(Workspace& W, int64_t n, int j, int slot, hipStream_t s) {
+  const int nb = ceil_div(n, 256);
+  const int nk = j + 1;
+  if (nk > MAX_NK) return -1;
+  hipLaunchKernelGGL(k_multidot_partial, dim3(RED_BLOCKS, nk), dim3(RED_THREADS), 0, s, W.V,
+                     (int64_t)n, n, W.w, W.partial);
+  BEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, s, W.V, (int64_t)n, n, nk,
+                     W.partial, W.h, W.w, (double*)nullptr);
+  BEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_multidot_partial, dim3(RED_BLOCKS, nk), dim3(RED_THREADS), 0, s, W.V,
+                     (int64_t)n, n, W.w, W.partial);
+  BEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, s, W.V, (int64_t)n, n, nk,
+                     W.partial, W.h2, W.w, W.partial2);
+  BEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_normalise, dim3(nb), dim3(256), 0, s, W.w, n, W.partial2, nb,
+                     W.V + (int64_t)(j + 1) * n, W.h2 + j + 1, W.h, W.h2, j,
+                     W.hcol + slot * (W.m + 2));
+  BEM_LAUNCH_CHECK();
+  BEM_HIP_TRY(hipEventRecord(W.ev[slot], s));
   return 0;
 }
 
@@ -243,6 +344,12 @@ struct GmresStats {
 // GMRES(m) on apply, x in/out; stops when the (estimated, then recomputed
 // with `apply`) residual <= atol or after max_iter steps.
 // Returns 0, or BEM_E_NOCONV / BEM_E_NAN / BEM_E_BREAKDOWN / error.
+//
+// The host runs one Arnoldi step behind the device: step j + 1 is queued
+// before the host waits for the Hessenberg column of step j, so the device
+// does not idle while the host applies the Givens rotations.  When the
+// residual trend says step j is likely the last of the cycle, the host waits
+// instead of queueing a step that would be thrown away.
 static int gmres_core(Workspace& W, const ApplyFn& apply, const c64* b, c64* x, int64_t n,
                       double atol, int m, int max_iter, bool x_is_zero, GmresStats& st,
                       hipStream_t s) {
@@ -263,7 +370,14 @@ static int gmres_core(Workspace& W, const ApplyFn& apply, const c64* b, c64* x, 
   if (!std::isfinite(beta)) return -6;
   if (beta <= atol) return 0;
   std::vector<std::complex<double>> H((m + 1) * m), cs(m), sn(m), g(m + 1);
-  std::vector<c64> hcol(2 * m + 4);
+  const int ld = W.m + 2;
+  // queue step j: w = A V_j, orthogonalise, column to slot j & 1
+  auto issue = [&](int j) -> int {
+    int rr = apply(W.V + (int64_t)j * n, W.w);
+    if (rr) return rr;
+    ++st.iters;
+    return arnoldi_orth(W, n, j, j & 1, s);
+  };
   while (st.iters < max_iter) {
     // V_0 = r / beta
     hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, W.r, n, W.V);
@@ -273,32 +387,28 @@ static int gmres_core(Workspace& W, const ApplyFn& apply, const c64* b, c64* x, 
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jend = 0;
-    bool done = false;
-    for (int j = 0; j < m && st.iters < max_iter; ++j) {
-      if ((r = apply(W.V + (int64_t)j * n, W.w))) return r;
-      ++st.iters;
-      // CGS2
-      if ((r = multidot(W, W.V, n, n, j + 1, W.w, W.h, 0, s))) return r;
-      hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, s, W.V, n, n, j + 1, W.h, W.w);
-      BEM_LAUNCH_CHECK();
-      if ((r = multidot(W, W.V, n, n, j + 1, W.w, W.h2, 0, s))) return r;
-      hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, s, W.V, n, n, j + 1, W.h2, W.w);
-      BEM_LAUNCH_CHECK();
-      if ((r = multidot(W, W.w, n, n, 1, W.w, W.h2 + j + 1, 0, s))) return r;
-      hipLaunchKernelGGL(k_normalise, dim3(nb), dim3(256), 0, s, W.w, n, W.h2 + j + 1,
-                         W.V + (int64_t)(j + 1) * n);
-      BEM_LAUNCH_CHECK();
-      BEM_HIP_TRY(hipMemcpyAsync(hcol.data(), W.h, sizeof(c64) * (j + 1), hipMemcpyDeviceToHost, s));
-      BEM_HIP_TRY(hipMemcpyAsync(hcol.data() + j + 1, W.h2, sizeof(c64) * (j + 2),
-                                 hipMemcpyDeviceToHost, s));
-      BEM_HIP_TRY(hipStreamSynchronize(s));
-      // h = first pass + second pass; h_{j+1} = ||w||
+    if ((r = issue(0))) return r;
+    bool queued_next = false;  // step j + 1 already queued
+    double est_prev = beta, est_prev2 = 0.0;
+    for (int j = 0; j < m; ++j) {
+      // speculate on step j + 1 unless the trend predicts convergence at j
+      const bool room = (j + 1 < m) && (st.iters < max_iter);
+      const double pred = (est_prev2 > 0.0) ? est_prev * (est_prev / est_prev2) : est_prev;
+      queued_next = false;
+      if (room && pred > atol) {
+        if ((r = issue(j + 1))) return r;
+        queued_next = true;
+      }
+      BEM_HIP_TRY(hipEventSynchronize(W.ev[j & 1]));
+      const c64* hc = W.hcol + (j & 1) * ld;
       std::vector<std::complex<double>> col(j + 2);
-      for (int i = 0; i <= j; ++i)
-        col[i] = std::complex<double>(hcol[i].re + hcol[j + 1 + i].re, hcol[i].im + hcol[j + 1 + i].im);
-      double hn = sqrt(hcol[j + 1 + j + 1].re);
+      for (int i = 0; i <= j; ++i) col[i] = std::complex<double>(hc[i].re, hc[i].im);
+      double hn = sqrt(hc[j + 1].re);
       col[j + 1] = hn;
-      if (!std::isfinite(hn)) return -6;
+      if (!std::isfinite(hn)) {
+        BEM_HIP_TRY(hipStreamSynchronize(s));
+        return -6;
+      }
       for (int i = 0; i < j; ++i) {
         std::complex<double> t = cs[i] * col[i] + sn[i] * col[i + 1];
         col[i + 1] = -std::conj(sn[i]) * col[i] + std::conj(cs[i]) * col[i + 1];
@@ -320,9 +430,13 @@ static int gmres_core(Workspace& W, const ApplyFn& apply, const c64* b, c64* x, 
       jend = j + 1;
       st.est = std::abs(g[j + 1]);
       st.hist.push_back(st.est);
-      if (st.est <= atol || hn == 0.0) {
-        done = true;
-        break;
+      est_prev2 = est_prev;
+      est_prev = st.est;
+      if (st.est <= atol || hn == 0.0) break;
+      if (!queued_next) {
+        if (!room) break;
+        if ((r = issue(j + 1))) return r;
+        queued_next = true;
       }
     }
     // y = H^-1 g (upper triangular)
@@ -330,12 +444,17 @@ static int gmres_core(Workspace& W, const ApplyFn& apply, const c64* b, c64* x, 
     for (int i = jend - 1; i >= 0; --i) {
       std::complex<double> acc = g[i];
       for (int kk = i + 1; kk < jend; ++kk) acc -= H[i * m + kk] * yv[kk];
-      if (std::abs(H[i * m + i]) == 0.0) return -5;
+      if (std::abs(H[i * m + i]) == 0.0) {
+        BEM_HIP_TRY(hipStreamSynchronize(s));
+        return -5;
+      }
       yv[i] = acc / H[i * m + i];
     }
-    std::vector<c64> yh(jend);
-    for (int i = 0; i < jend; ++i) yh[i] = mk(yv[i].real(), yv[i].imag());
-    BEM_HIP_TRY(hipMemcpyAsync(W.y, yh.data(), sizeof(c64) * jend, hipMemcpyHostToDevice, s));
+    // the host column slots are reused by the next cycle: let the queued
+    // (possibly speculative) step land first
+    BEM_HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < jend; ++i) W.hcol[i] = mk(yv[i].real(), yv[i].imag());
+    BEM_HIP_TRY(hipMemcpyAsync(W.y, W.hcol, sizeof(c64) * jend, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, W.V, n, n, jend, W.y, x);
     BEM_LAUNCH_CHECK();
     // recompute the residual with the operator
@@ -347,7 +466,6 @@ static int gmres_core(Workspace& W, const ApplyFn& apply, const c64* b, c64* x, 
     if (!std::isfinite(beta)) return -6;
     if (beta <= atol) return 0;
     ++st.restarts;
-    (void)done;
   }
   return -4;
 }
@@ -720,7 +838,7 @@ int objective_grad(Problem& P, const c64* beta, const double* dir, const double*
 void release_workspace(Problem& P) {
   if (P.solver_ws) {
     Workspace* W = (Workspace*)P.solver_ws;
-    W->arena.release();
+    W->release();
     delete W;
     P.solver_ws = nullptr;
   }
@@ -748,7 +866,6 @@ struct BatchSys {
   int j = 0, iters = 0, mv64 = 0, mv32 = 0, outer = 0, status = -4;
   std::vector<std::complex<double>> H, cs, sn, g;
   std::vector<double> hist;
-  c64* hbuf = nullptr;  // pinned host mirror of the scalars read back per tick
 };
 
 static int batch_apply(BatchSys& S, bool f32, const c64* v, c64* out) {
@@ -789,12 +906,12 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
                       double inner_tol, int use_x0, bem_gmres_info* infos, hipStream_t caller) {
   const int ns = (int)probs.size();
   std::vector<BatchSys> sys(ns);
-  c64* hpin = nullptr;
-  BEM_HIP_TRY(hipHostMalloc((void**)&hpin, sizeof(c64) * (size_t)ns * (2 * m + 4)));
-  struct PinGuard {
-    c64* p;
-    ~PinGuard() { (void)hipHostFree(p); }
-  } pin{hpin};
+  struct SysGuard {  // every exit path frees the per-system workspaces
+    std::vector<BatchSys>& v;
+    ~SysGuard() {
+      for (auto& S : v) S.W.release();
+    }
+  } sys_guard{sys};
   hipEvent_t start;
   BEM_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
   struct EvGuard {
@@ -811,7 +928,6 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
     S.b = b[i];
     S.x = x[i];
     S.s = S.P->bstream;
-    S.hbuf = hpin + (size_t)i * (2 * m + 4);
     if (std::find(streams.begin(), streams.end(), S.s) == streams.end()) {
       streams.push_back(S.s);
       BEM_HIP_TRY(hipStreamWaitEvent(S.s, start, 0));
@@ -826,9 +942,9 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
   }
   // norms of the right-hand sides
   for (auto& S : sys) {
-    int r = multidot(S.W, S.b, S.P->n, S.P->n, 1, S.b, S.W.h2, 0, S.s);
+    int r = multidot(S.W, S.b, S.P->n, S.P->n, 1, S.b, S.W.h2, S.s);
     if (r) return r;
-    BEM_HIP_TRY(hipMemcpyAsync(S.hbuf, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, S.s));
+    BEM_HIP_TRY(hipMemcpyAsync(S.W.hscal, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, S.s));
     if (S.first) {
       hipLaunchKernelGGL(k_set_zero, dim3(ceil_div(S.P->n, 256)), dim3(256), 0, S.s, S.x, S.P->n);
       BEM_LAUNCH_CHECK();
@@ -836,7 +952,7 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
   }
   for (hipStream_t st : streams) BEM_HIP_TRY(hipStreamSynchronize(st));
   for (auto& S : sys) {
-    S.bn = sqrt(S.hbuf[0].re);
+    S.bn = sqrt(S.W.hscal[0].re);
     if (!std::isfinite(S.bn)) {
       S.status = -6;
       S.state = 2;
@@ -863,26 +979,12 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
           hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, S.s, S.b, S.W.t1, n, S.W.r);
           BEM_LAUNCH_CHECK();
         }
-        if ((r = multidot(S.W, S.W.r, n, n, 1, S.W.r, S.W.h2, 0, S.s))) return r;
-        BEM_HIP_TRY(hipMemcpyAsync(S.hbuf, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, S.s));
+        if ((r = multidot(S.W, S.W.r, n, n, 1, S.W.r, S.W.h2, S.s))) return r;
+        BEM_HIP_TRY(hipMemcpyAsync(S.W.hscal, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, S.s));
       } else {
         const int j = S.j;
         if ((r = batch_apply(S, mode == 1, S.W.V + (int64_t)j * n, S.W.w))) return r;
-        if ((r = multidot(S.W, S.W.V, n, n, j + 1, S.W.w, S.W.h, 0, S.s))) return r;
-        hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, S.s, S.W.V, n, n, j + 1, S.W.h,
-                           S.W.w);
-        BEM_LAUNCH_CHECK();
-        if ((r = multidot(S.W, S.W.V, n, n, j + 1, S.W.w, S.W.h2, 0, S.s))) return r;
-        hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, S.s, S.W.V, n, n, j + 1, S.W.h2,
-                           S.W.w);
-        BEM_LAUNCH_CHECK();
-        if ((r = multidot(S.W, S.W.w, n, n, 1, S.W.w, S.W.h2 + j + 1, 0, S.s))) return r;
-        hipLaunchKernelGGL(k_normalise, dim3(nb), dim3(256), 0, S.s, S.W.w, n, S.W.h2 + j + 1,
-                           S.W.V + (int64_t)(j + 1) * n);
-        BEM_LAUNCH_CHECK();
-        BEM_HIP_TRY(hipMemcpyAsync(S.hbuf, S.W.h, sizeof(c64) * (j + 1), hipMemcpyDeviceToHost, S.s));
-        BEM_HIP_TRY(hipMemcpyAsync(S.hbuf + j + 1, S.W.h2, sizeof(c64) * (j + 2),
-                                   hipMemcpyDeviceToHost, S.s));
+        if ((r = arnoldi_orth(S.W, n, j, 0, S.s))) return r;
       }
     }
     if (!any) break;
@@ -894,7 +996,7 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
       const int nb = ceil_div(n, 256);
       if (S.state == 0) {
         S.first = false;
-        S.rn = sqrt(S.hbuf[0].re);
+        S.rn = sqrt(S.W.hscal[0].re);
         S.hist.push_back(S.rn / S.bn);
         if (!std::isfinite(S.rn)) {
           S.status = -6;
@@ -927,9 +1029,8 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
         const int j = S.j;
         std::vector<std::complex<double>> col(j + 2);
         for (int i = 0; i <= j; ++i)
-          col[i] = std::complex<double>(S.hbuf[i].re + S.hbuf[j + 1 + i].re,
-                                        S.hbuf[i].im + S.hbuf[j + 1 + i].im);
-        double hn = sqrt(S.hbuf[j + 1 + j + 1].re);
+          col[i] = std::complex<double>(S.W.hcol[i].re, S.W.hcol[i].im);
+        double hn = sqrt(S.W.hcol[j + 1].re);
         col[j + 1] = hn;
         ++S.iters;
         if (!std::isfinite(hn)) {
@@ -969,8 +1070,9 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
             }
             yv[i] = acc / S.H[i * m + i];
           }
-          for (int i = 0; i < jend; ++i) S.hbuf[m + 1 + i] = mk(yv[i].real(), yv[i].imag());
-          BEM_HIP_TRY(hipMemcpyAsync(S.W.y, S.hbuf + m + 1, sizeof(c64) * jend,
+          c64* yh = S.W.hcol + (S.W.m + 2);
+          for (int i = 0; i < jend; ++i) yh[i] = mk(yv[i].real(), yv[i].imag());
+          BEM_HIP_TRY(hipMemcpyAsync(S.W.y, yh, sizeof(c64) * jend,
                                      hipMemcpyHostToDevice, S.s));
           hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, S.s, S.W.V, n, n, jend, S.W.y, S.x);
           BEM_LAUNCH_CHECK();
@@ -1001,7 +1103,6 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
       for (int t = 0; t < nh; ++t) info->hist[t] = S.hist[t];
     }
     if (S.status != 0 && worst == 0) worst = S.status;
-    S.W.arena.release();
   }
   if (worst == -4) set_error("some systems of the batch did not converge (see infos)");
   if (worst == -6) set_error("NaN or Inf met in a system of the batch");
