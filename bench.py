@@ -272,20 +272,27 @@ def main():
     plan.solve(b, opts=optsir)
     prof = plan.profile_stop()
     stages = {f"{k[0]}_{k[1]}_{k[2]}": round(v[0] / v[1], 4) for k, v in prof.items()}
-    m2l_ms, m2l_calls = prof.get(("m2l", "f32", "fwd"), (0.0, 0))
+    # dominant kernel: the leaf-level float32 M2L GEMM (one launch per
+    # product); algorithmic flops per launch = 8 (p_L + 1)^4 per M2L pair
     L = st["leaf_level"]
-    flops_m2l = sum(8.0 * st["n_m2l"][l] * (st["order32"][l] + 1) ** 4 for l in range(2, L + 1))
-    n_lvl = max(1, L - 1)
-    # one M2L GEMM launch per level per matvec: mean work / mean duration
-    n_mv = max(1, m2l_calls // n_lvl)
-    per_launch_ms = m2l_ms / max(1, m2l_calls)
-    achieved = (flops_m2l / n_lvl) / (per_launch_ms / 1e3) if per_launch_ms > 0 else 0.0
-    roofline = {"kernel": "k_grouped_gemm<float,false,0> (M2L, float32)", "bound": "mfma",
+    leaf_ms, leaf_calls = prof.get(("m2l_leaf", "f32", "fwd"), (0.0, 0))
+    flops_leaf = 8.0 * st["n_m2l"][L] * (st["order32"][L] + 1) ** 4
+    per_launch_ms = leaf_ms / max(1, leaf_calls)
+    achieved = flops_leaf / (per_launch_ms / 1e3) if per_launch_ms > 0 else 0.0
+    coarse_ms, coarse_calls = prof.get(("m2l", "f32", "fwd"), (0.0, 0))
+    flops_coarse = sum(8.0 * st["n_m2l"][l] * (st["order32"][l] + 1) ** 4 for l in range(2, L))
+    coarse_launch_ms = coarse_ms / max(1, coarse_calls)
+    roofline = {"kernel": f"k_grouped_gemm<float,{st['m2l_tile32'][L]},false,0> "
+                          f"(leaf-level M2L, float32)", "bound": "mfma",
                 "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 4),
                 "traffic": measured_traffic(),
-                "flops_per_matvec": flops_m2l, "launches_per_matvec": n_lvl,
-                "avg_launch_ms": round(per_launch_ms, 5)}
+                "flops_per_launch": flops_leaf, "avg_launch_ms": round(per_launch_ms, 5),
+                "launches": leaf_calls,
+                "coarse_levels_m2l": {"flops_per_launch": flops_coarse,
+                                      "avg_launch_ms": round(coarse_launch_ms, 5),
+                                      "tflops": round(flops_coarse / max(coarse_launch_ms, 1e-9)
+                                                      / 1e9, 3)}}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -85,9 +85,10 @@ typedef struct {
                           the occupancy-rule level and its two neighbours
                           are built and timed on a float32 product at plan
                           creation, and the fastest is kept              */
-  int32_t order64;     /* expansion order of the float64 far field, or <=0:
-                          chosen per level from the wavenumber             */
-  int32_t order32;     /* same for the float32 far field                   */
+  int32_t order64;     /* expansion order of the float64 far field: > 0
+                          fixed; 0: per level ceil(k sqrt(3) h) + 8, at
+                          least 12; < 0: the same with minimum -order64    */
+  int32_t order32;     /* same for the float32 far field (+3, at least 7)  */
 } bem_problem;
 
 typedef struct {
@@ -127,6 +128,7 @@ typedef struct {
   int64_t device_bytes;    /* device memory held by this problem             */
   double tuned_ms;         /* leaf_level < 0: float32 product time (ms) of the
                               kept leaf level; 0 otherwise                   */
+  int32_t m2l_tile32[22];  /* pairs per tile of the float32 M2L per level   */
 } bem_plan_stats;
 
 /* Build a plan for n_probs problems.  Uploads the meshes and runs, on the
@@ -220,11 +222,12 @@ int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, voi
  * bem_profile_start, every product records an event pair around each stage;
  * bem_profile_stop synchronises and returns, per slot, the summed
  * milliseconds and the number of timed stage executions.  Slot =
- * stage + 8 * (float32 ? 1 : 0) + 16 * (adjoint ? 1 : 0), stage: 0 gather,
- * 1 P2P, 2 P2M (adjoint: L2P^H), 3 M2M, 4 M2L, 5 L2L, 6 finish (L2P, near
- * corrections, diagonal, scatter).  ms and calls hold BEM_PROFILE_SLOTS
- * entries (host). */
-#define BEM_PROFILE_SLOTS 32
+ * stage + 16 * (float32 ? 1 : 0) + 32 * (adjoint ? 1 : 0), stage: 0 gather,
+ * 1 P2P, 2 P2M (adjoint: L2P^H), 3 M2M, 4 M2L of the levels above the
+ * leaves (merged launch), 5 L2L, 6 finish (L2P, near corrections, diagonal,
+ * scatter), 7 reduction of 4, 8 M2L of the leaf level, 9 reduction of 8.
+ * ms and calls hold BEM_PROFILE_SLOTS entries (host). */
+#define BEM_PROFILE_SLOTS 64
 int bem_profile_start(bem_plan* plan, int prob);
 int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls);
 

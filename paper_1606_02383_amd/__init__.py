@@ -34,7 +34,9 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
            "bem_leaves_export", "bem_profile_start", "bem_profile_stop", "bem_last_error"]
 
-STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce"]
+STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
+          "m2l_leaf_reduce"]
+PROFILE_SLOTS = 64
 
 
 class _Problem(ctypes.Structure):
@@ -70,7 +72,7 @@ class _Stats(ctypes.Structure):
                 ("n_p2p_pairs", ctypes.c_int64), ("n_m2l", ctypes.c_int64 * 22),
                 ("order64", ctypes.c_int32 * 22), ("order32", ctypes.c_int32 * 22),
                 ("box_size", ctypes.c_double * 22), ("device_bytes", ctypes.c_int64),
-                ("tuned_ms", ctypes.c_double)]
+                ("tuned_ms", ctypes.c_double), ("m2l_tile32", ctypes.c_int32 * 22)]
 
 
 _LIB = None
@@ -223,7 +225,7 @@ class Plan:
                     n_p2p_pairs=st.n_p2p_pairs, n_m2l=list(st.n_m2l[:L + 1]),
                     order64=list(st.order64[:L + 1]), order32=list(st.order32[:L + 1]),
                     box_size=list(st.box_size[:L + 1]), device_bytes=st.device_bytes,
-                    tuned_ms=st.tuned_ms)
+                    tuned_ms=st.tuned_ms, m2l_tile32=list(st.m2l_tile32[:L + 1]))
 
     # ---- products
     def matvec(self, p, q=None, prec=BEM_C128, prob=0, out=None):
@@ -347,14 +349,14 @@ class Plan:
 
     def profile_stop(self, prob=0):
         """{(stage, 'f64'|'f32', 'fwd'|'adj'): (total ms, executions)}"""
-        ms = (ctypes.c_double * 32)()
-        calls = (ctypes.c_int32 * 32)()
+        ms = (ctypes.c_double * PROFILE_SLOTS)()
+        calls = (ctypes.c_int32 * PROFILE_SLOTS)()
         _check(_LIB.bem_profile_stop(self._h, prob, ms, calls))
         out = {}
-        for slot in range(32):
+        for slot in range(PROFILE_SLOTS):
             if calls[slot]:
-                st = STAGES[slot % 8] if slot % 8 < len(STAGES) else str(slot % 8)
-                key = (st, "f32" if (slot // 8) % 2 else "f64", "adj" if slot >= 16 else "fwd")
+                st = STAGES[slot % 16] if slot % 16 < len(STAGES) else str(slot % 16)
+                key = (st, "f32" if (slot // 16) % 2 else "f64", "adj" if slot >= 32 else "fwd")
                 out[key] = (ms[slot], calls[slot])
         return out
 

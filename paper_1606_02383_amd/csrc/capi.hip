@@ -212,6 +212,7 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
   }
   st->device_bytes = P->arena.bytes;
   st->tuned_ms = P->tuned_ms;
+  for (int l = 0; l < 22; ++l) st->m2l_tile32[l] = (l <= P->L) ? P->f32.m2l[l].ct : 0;
   return BEM_OK;
 }
 

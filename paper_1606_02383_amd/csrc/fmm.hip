@@ -28,67 +28,126 @@
 
 namespace bemfmm {
 
-constexpr float INV_4PI_F = 0.07957747154594767f;
 constexpr double INV_4PI_D = 0.07957747154594767;
 
+// e^{i k r}: float32 uses the hardware sine/cosine, which take the phase in
+// turns (k r / 2 pi; here a few radians at most, absolute error ~1e-6, far
+// below the float32 operator's tolerance); float64 the library sincos.
 template <typename R>
-__device__ __forceinline__ void sincos_r(R x, R* s, R* c);
+__device__ __forceinline__ void phase(R r, R k, R k_turns, R* s, R* c);
 template <>
-__device__ __forceinline__ void sincos_r<float>(float x, float* s, float* c) {
-  sincosf(x, s, c);
+__device__ __forceinline__ void phase<float>(float r, float, float k_turns, float* s, float* c) {
+  const float t = r * k_turns;
+  *s = __builtin_amdgcn_sinf(t);
+  *c = __builtin_amdgcn_cosf(t);
 }
 template <>
-__device__ __forceinline__ void sincos_r<double>(double x, double* s, double* c) {
-  sincos(x, s, c);
+__device__ __forceinline__ void phase<double>(double r, double k, double, double* s, double* c) {
+  sincos(k * r, s, c);
 }
+// 1/sqrt(x) for x well inside the normal range (squared distances between
+// distinct rule points and collocation points)
 template <typename R>
 __device__ __forceinline__ R rsqrt_r(R x);
 template <>
 __device__ __forceinline__ float rsqrt_r<float>(float x) {
-  return rsqrtf(x);
+  return __builtin_amdgcn_rsqf(x);
 }
 template <>
 __device__ __forceinline__ double rsqrt_r<double>(double x) {
   return 1.0 / sqrt(x);
 }
 
-// kernel coefficients (cp, cq) of one (target, source point) pair; w
-// includes the rule weight and 1/(4 pi).
-template <typename R>
-__device__ __forceinline__ void bm_pair(R xx, R xy, R xz, R nxx, R nxy, R nxz, R yx, R yy, R yz,
-                                        R nyx, R nyy, R nyz, R w, R k, R alr, R ali,
-                                        cplx<R>& cp, cplx<R>& cq) {
-  R rx = xx - yx, ry = xy - yy, rz = xz - yz;
-  R r2 = rx * rx + ry * ry + rz * rz;
-  R u = rsqrt_r<R>(r2);
-  R r = r2 * u;
-  R sn, cs;
-  sincos_r<R>(k * r, &sn, &cs);
-  R gs = w * u;
-  cplx<R> G = mk<R>(cs * gs, sn * gs);
-  R u2 = u * u;
-  cplx<R> a1 = mk<R>(-u2, k * u);
-  cplx<R> a2 = mk<R>(R(3) * u2 - k * k, R(-3) * k * u);
-  R rnx = rx * nxx + ry * nxy + rz * nxz;
-  R rny = rx * nyx + ry * nyy + rz * nyz;
-  R nn = nxx * nyx + nxy * nyy + nxz * nyz;
-  cplx<R> al = mk<R>(alr, ali);
-  // a1 * (rny + alpha nn) + alpha a2 rnx rny u^2
-  cplx<R> t1 = cmul(a1, mk<R>(rny + alr * nn, ali * nn));
-  cplx<R> t2 = cmul(al, cscale(a2, rnx * rny * u2));
-  cp = cmul(G, cadd(t1, t2));
-  cplx<R> t3 = cmul(al, cscale(a1, rnx));
-  cq = cmul(G, mk<R>(R(1) + t3.re, t3.im));
+// Burton-Miller coefficients (sp, sq) of a target point x (normal n_x)
+// against one source element, summed over the element's three rule points
+// y_q, without the per-point weight (rule weight x area / (4 pi), the same
+// for the three points; the callers apply it).  With r = x - y_q, u = 1/|r|,
+// G = e^{ikr} u, a1 = (-u^2, k u), a2 = (3 u^2 - k^2, -3 k u):
+//   p coefficient  G [a1 (r.n_y + alpha n_x.n_y) + alpha a2 (r.n_x)(r.n_y) u^2]
+//                  (-dG/dn_y - alpha d2G/dn_x dn_y)
+//   q coefficient  G [1 + alpha a1 (r.n_x)]       (G + alpha dG/dn_x)
+// The element is flat, so r.n_y = x.n_y - d with d = y_q.n_y the same for its
+// three points; n_x.n_y is shared too: both are formed once per element.
+// IMAG: alpha purely imaginary (alpha = i/k, the usual coupling), which
+// drops the alpha_re products.
+template <typename R, bool IMAG>
+__device__ __forceinline__ void bm_elem(R xx, R xy, R xz, R nxx, R nxy, R nxz, const R* yq,
+                                        R nyx, R nyy, R nyz, R d, R k, R k_turns, R alr, R ali,
+                                        cplx<R>& sp, cplx<R>& sq) {
+  const R nn = nxx * nyx + nxy * nyy + nxz * nyz;
+  const R rny = xx * nyx + xy * nyy + xz * nyz - d;
+  const R c1r = IMAG ? rny : rny + alr * nn, c1i = ali * nn;  // rny + alpha nn
+  const R k2 = k * k, m3k = R(-3) * k;
+  R spr = 0, spi = 0, sqr = 0, sqi = 0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const R rx = xx - yq[3 * q], ry = xy - yq[3 * q + 1], rz = xz - yq[3 * q + 2];
+    const R r2 = rx * rx + ry * ry + rz * rz;
+    const R u = rsqrt_r<R>(r2);
+    const R r = r2 * u;
+    R sn, cs;
+    phase<R>(r, k, k_turns, &sn, &cs);
+    const R Gr = cs * u, Gi = sn * u;
+    const R u2 = u * u;
+    const R a1r = -u2, a1i = k * u;
+    const R rnx = rx * nxx + ry * nxy + rz * nxz;
+    // a2 rnx rny u^2 = (t, v) with a2 = (3 u^2 - k^2, -3 k u)
+    const R sc = rnx * rny * u2;
+    const R t = (R(3) * u2 - k2) * sc, v = m3k * u * sc;
+    // f = a1 (rny + alpha nn) + alpha (t, v);  g = 1 + alpha a1 rnx
+    R fr = a1r * c1r - a1i * c1i, fi = a1r * c1i + a1i * c1r;
+    R gr, gi;
+    if (IMAG) {
+      fr -= ali * v;
+      fi += ali * t;
+      const R ar = ali * rnx;
+      gr = R(1) - a1i * ar;
+      gi = a1r * ar;
+    } else {
+      fr += alr * t - ali * v;
+      fi += alr * v + ali * t;
+      gr = R(1) + (alr * a1r - ali * a1i) * rnx;
+      gi = (alr * a1i + ali * a1r) * rnx;
+    }
+    spr += Gr * fr - Gi * fi;
+    spi += Gr * fi + Gi * fr;
+    sqr += Gr * gr - Gi * gi;
+    sqi += Gr * gi + Gi * gr;
+  }
+  sp = mk<R>(spr, spi);
+  sq = mk<R>(sqr, sqi);
 }
 
 // ---------------------------------------------------------------------------
 // gather / scatter
 // ---------------------------------------------------------------------------
+// Buffers cleared by the first kernel of a product (targets of atomic
+// accumulation further down the chain), folded into it to save launches.
+constexpr int MAX_ZERO = 8;
+template <typename R>
+struct ZeroList {
+  int n;
+  cplx<R>* ptr[MAX_ZERO];
+  int64_t cnt[MAX_ZERO];
+};
+
+template <typename R>
+__device__ __forceinline__ void zero_list(const ZeroList<R>& z) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+#pragma unroll
+  for (int q = 0; q < MAX_ZERO; ++q) {
+    if (q >= z.n) break;
+    for (int64_t i = gid; i < z.cnt[q]; i += gsz) z.ptr[q][i] = mk<R>(R(0), R(0));
+  }
+}
+
 template <typename R>
 __global__ void k_gather_in(const c64* __restrict__ p, const c64* __restrict__ q,
                             const int* __restrict__ perm, int64_t n, cplx<R>* __restrict__ ps,
                             cplx<R>* __restrict__ qs, c64* __restrict__ p64,
-                            c64* __restrict__ q64) {
+                            c64* __restrict__ q64, const ZeroList<R> zl) {
+  zero_list(zl);
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   int o = perm[i];
@@ -112,19 +171,19 @@ __global__ void k_zero(cplx<R>* __restrict__ a, int64_t cnt) {
 constexpr int P2P_THREADS = 256;
 constexpr int P2P_CHUNK = 128;
 
-template <typename R>
+template <typename R, bool IMAG>
 __global__ void __launch_bounds__(P2P_THREADS)
     k_p2p(const R* __restrict__ geo, int64_t n, const int* __restrict__ bstart,
           const int* __restrict__ u_ptr, const int* __restrict__ u_idx,
           const cplx<R>* __restrict__ ps, const cplx<R>* __restrict__ qs, R k, R alr, R ali,
           int all_src, cplx<R>* __restrict__ ys) {
   __shared__ R s_q[9][P2P_CHUNK];
-  __shared__ R s_n[3][P2P_CHUNK];
-  __shared__ R s_w[P2P_CHUNK];
+  __shared__ R s_n[4][P2P_CHUNK];  // normal and plane offset y . n
   __shared__ R s_pq[4][P2P_CHUNK];
   __shared__ int s_id[P2P_CHUNK];
   __shared__ int s_nb[28], s_pre[28];
   __shared__ cplx<R> s_red[P2P_THREADS];
+  const R k_turns = k * R(0.15915494309189535);  // k / (2 pi)
   const int b = blockIdx.x, tid = threadIdx.x;
   const int t0 = bstart[b], nT = bstart[b + 1] - t0;
   const int u0 = u_ptr[b], nu = u_ptr[b + 1] - u0;
@@ -171,31 +230,30 @@ __global__ void __launch_bounds__(P2P_THREADS)
         while (t + 1 < nseg && s_pre[t + 1] <= gv) ++t;
         int j = s_nb[t] + (gv - s_pre[t]);
         for (int c = 0; c < 9; ++c) s_q[c][v] = geo[(GEO_QX0 + c) * n + j];
-        s_n[0][v] = geo[GEO_NX * n + j];
-        s_n[1][v] = geo[GEO_NY * n + j];
-        s_n[2][v] = geo[GEO_NZ * n + j];
-        s_w[v] = geo[GEO_AREA * n + j] * R(1.0 / 3.0) * R(INV_4PI_D);
+        const R nx = geo[GEO_NX * n + j], ny = geo[GEO_NY * n + j], nz = geo[GEO_NZ * n + j];
+        s_n[0][v] = nx;
+        s_n[1][v] = ny;
+        s_n[2][v] = nz;
+        s_n[3][v] = s_q[0][v] * nx + s_q[1][v] * ny + s_q[2][v] * nz;
+        // densities times the per-point weight (rule weight x area / (4 pi))
+        const R wj = geo[GEO_AREA * n + j] * R(1.0 / 3.0) * R(INV_4PI_D);
         cplx<R> pv = ps[j], qv = qs[j];
-        s_pq[0][v] = pv.re;
-        s_pq[1][v] = pv.im;
-        s_pq[2][v] = qv.re;
-        s_pq[3][v] = qv.im;
+        s_pq[0][v] = wj * pv.re;
+        s_pq[1][v] = wj * pv.im;
+        s_pq[2][v] = wj * qv.re;
+        s_pq[3][v] = wj * qv.im;
         s_id[v] = j;
       }
       __syncthreads();
       if (active) {
         for (int v = sl; v < cnt; v += nsl) {
           if (s_id[v] == i) continue;
-          cplx<R> sp = mk<R>(0, 0), sq = mk<R>(0, 0);
+          R yq[9];
 #pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            cplx<R> cp, cq;
-            bm_pair<R>(xx, xy, xz, nxx, nxy, nxz, s_q[3 * q][v], s_q[3 * q + 1][v],
-                       s_q[3 * q + 2][v], s_n[0][v], s_n[1][v], s_n[2][v], s_w[v], k, alr, ali,
-                       cp, cq);
-            sp = cadd(sp, cp);
-            sq = cadd(sq, cq);
-          }
+          for (int c = 0; c < 9; ++c) yq[c] = s_q[c][v];
+          cplx<R> sp, sq;
+          bm_elem<R, IMAG>(xx, xy, xz, nxx, nxy, nxz, yq, s_n[0][v], s_n[1][v], s_n[2][v],
+                           s_n[3][v], k, k_turns, alr, ali, sp, sq);
           cfma(acc, sp, mk<R>(s_pq[0][v], s_pq[1][v]));
           cfma(acc, sq, mk<R>(s_pq[2][v], s_pq[3][v]));
         }
@@ -214,7 +272,7 @@ __global__ void __launch_bounds__(P2P_THREADS)
 
 // Adjoint P2P: one block per leaf of output elements j; iterates over the
 // target elements i of the U list:  u_j += conj(cp_ij) y_i,  w_j += conj(cq_ij) y_i.
-template <typename R>
+template <typename R, bool IMAG>
 __global__ void __launch_bounds__(P2P_THREADS)
     k_p2p_adj(const R* __restrict__ geo, int64_t n, const int* __restrict__ bstart,
               const int* __restrict__ u_ptr, const int* __restrict__ u_idx,
@@ -225,6 +283,7 @@ __global__ void __launch_bounds__(P2P_THREADS)
   __shared__ int s_id[P2P_CHUNK];
   __shared__ int s_nb[28], s_pre[28];
   __shared__ cplx<R> s_red[2][P2P_THREADS];
+  const R k_turns = k * R(0.15915494309189535);  // k / (2 pi)
   const int b = blockIdx.x, tid = threadIdx.x;
   const int t0 = bstart[b], nT = bstart[b + 1] - t0;
   const int u0 = u_ptr[b], nu = u_ptr[b + 1] - u0;
@@ -253,14 +312,14 @@ __global__ void __launch_bounds__(P2P_THREADS)
     const bool active = tid < nTg * nsl;
     const int ti = tid % nTg, sl = tid / nTg;
     const int j = t0 + tg + ti;
-    R q[9], nyx = 0, nyy = 0, nyz = 0, w = 0;
+    R q[9], nyx = 0, nyy = 0, nyz = 0;
     for (int c = 0; c < 9; ++c) q[c] = active ? geo[(GEO_QX0 + c) * n + j] : R(0);
     if (active) {
       nyx = geo[GEO_NX * n + j];
       nyy = geo[GEO_NY * n + j];
       nyz = geo[GEO_NZ * n + j];
-      w = geo[GEO_AREA * n + j] * R(1.0 / 3.0) * R(INV_4PI_D);
     }
+    const R dj = q[0] * nyx + q[1] * nyy + q[2] * nyz;  // plane offset of element j
     cplx<R> au = mk<R>(0, 0), aw = mk<R>(0, 0);
     for (int c0 = 0; c0 < total; c0 += P2P_CHUNK) {
       const int cnt = min(P2P_CHUNK, total - c0);
@@ -284,16 +343,9 @@ __global__ void __launch_bounds__(P2P_THREADS)
       if (active) {
         for (int v = sl; v < cnt; v += nsl) {
           if (s_id[v] == j) continue;
-          cplx<R> sp = mk<R>(0, 0), sq = mk<R>(0, 0);
-#pragma unroll
-          for (int qq = 0; qq < 3; ++qq) {
-            cplx<R> cp, cq;
-            bm_pair<R>(s_x[0][v], s_x[1][v], s_x[2][v], s_x[3][v], s_x[4][v], s_x[5][v],
-                       q[3 * qq], q[3 * qq + 1], q[3 * qq + 2], nyx, nyy, nyz, w, k, alr, ali,
-                       cp, cq);
-            sp = cadd(sp, cp);
-            sq = cadd(sq, cq);
-          }
+          cplx<R> sp, sq;
+          bm_elem<R, IMAG>(s_x[0][v], s_x[1][v], s_x[2][v], s_x[3][v], s_x[4][v], s_x[5][v], q,
+                           nyx, nyy, nyz, dj, k, k_turns, alr, ali, sp, sq);
           cplx<R> yv = mk<R>(s_y[0][v], s_y[1][v]);
           cfmac(au, sp, yv);
           cfmac(aw, sq, yv);
@@ -310,8 +362,10 @@ __global__ void __launch_bounds__(P2P_THREADS)
         su = cadd(su, s_red[0][q2 * nTg + tid]);
         sw = cadd(sw, s_red[1][q2 * nTg + tid]);
       }
-      us[t0 + tg + tid] = su;
-      ws[t0 + tg + tid] = sw;
+      // per-point weight of element j (rule weight x area / (4 pi))
+      const R wj = geo[GEO_AREA * n + t0 + tg + tid] * R(1.0 / 3.0) * R(INV_4PI_D);
+      us[t0 + tg + tid] = cscale(su, wj);
+      ws[t0 + tg + tid] = cscale(sw, wj);
     }
   }
 }
@@ -321,36 +375,74 @@ __global__ void __launch_bounds__(P2P_THREADS)
 // leaf's elements.  mode 0: M[b][c] = sum_e A[e][c][0] p_e + A[e][c][1] q_e;
 // mode 1: M[b][c] = sum_e conj(B[e][c]) y_e.
 // ---------------------------------------------------------------------------
+// two adjacent complex values in one wide load (16-byte aligned pair)
+__device__ __forceinline__ void load_pair(const cplx<float>* p, cplx<float>& a, cplx<float>& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a = mk<float>(v.x, v.y);
+  b = mk<float>(v.z, v.w);
+}
+__device__ __forceinline__ void load_pair(const cplx<double>* p, cplx<double>& a,
+                                          cplx<double>& b) {
+  const double2 u = reinterpret_cast<const double2*>(p)[0];
+  const double2 v = reinterpret_cast<const double2*>(p)[1];
+  a = mk<double>(u.x, u.y);
+  b = mk<double>(v.x, v.y);
+}
+
+// Per-leaf accumulation over the leaf's elements e:
+//   mode 0 (P2M):     out[b][c] = sum_e mat[e][c][0] a_e + mat[e][c][1] bvec_e
+//   mode 1 (L2P^H):   out[b][c] = sum_e conj(mat[e][c]) a_e
+// One 256-thread block per leaf: lane l of slice q handles coefficients
+// l, l + 64, ... over the elements e0 + q, e0 + q + 4, ...; the four slices
+// are added in a fixed order.
 template <typename R>
-__global__ void k_leaf_accumulate(const int* __restrict__ bstart, int ncoef,
-                                  const cplx<R>* __restrict__ mat, const cplx<R>* __restrict__ a,
-                                  const cplx<R>* __restrict__ bvec, int mode,
-                                  cplx<R>* __restrict__ out) {
+__global__ void __launch_bounds__(256)
+    k_leaf_accumulate(const int* __restrict__ bstart, int ncoef, const cplx<R>* __restrict__ mat,
+                      const cplx<R>* __restrict__ a, const cplx<R>* __restrict__ bvec, int mode,
+                      cplx<R>* __restrict__ out) {
+  __shared__ cplx<R> part[4][64];
   const int b = blockIdx.x;
   const int e0 = bstart[b], e1 = bstart[b + 1];
-  for (int c = threadIdx.x; c < ncoef; c += blockDim.x) {
+  const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncoef; c0 += 64) {
+    const int c = c0 + lane;
     cplx<R> acc = mk<R>(0, 0);
-    for (int e = e0; e < e1; ++e) {
-      if (mode == 0) {
-        cfma(acc, mat[((int64_t)e * ncoef + c) * 2], a[e]);
-        cfma(acc, mat[((int64_t)e * ncoef + c) * 2 + 1], bvec[e]);
-      } else {
-        cfmac(acc, mat[(int64_t)e * ncoef + c], a[e]);
+    if (c < ncoef) {
+      for (int e = e0 + sl; e < e1; e += 4) {
+        if (mode == 0) {
+          cplx<R> mp, mq;
+          load_pair(mat + ((int64_t)e * ncoef + c) * 2, mp, mq);
+          cfma(acc, mp, a[e]);
+          cfma(acc, mq, bvec[e]);
+        } else {
+          cfmac(acc, mat[(int64_t)e * ncoef + c], a[e]);
+        }
       }
     }
-    out[(int64_t)b * ncoef + c] = acc;
+    part[sl][lane] = acc;
+    __syncthreads();
+    if (sl == 0 && c < ncoef)
+      out[(int64_t)b * ncoef + c] =
+          cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
 // grouped gather-GEMM-scatter on the matrix cores:
-//   dst[pair_dst] += op_g src[pair_src]      (ADJ: op_g conjugate-transposed)
-// Workgroup tile: 64 output rows x 64 pairs; four waves, each 32 x 32.  The
-// complex product runs as four real 16x16x4 MFMA products per 16x16 block:
-//   C_re += A_re B_re - A_im B_im,   C_im += A_re B_im + A_im B_re.
-// Operands are staged through LDS, 16 complex k per stage; output columns are
-// accumulated with atomics (pairs of one group never share a destination, but
-// different groups do).
+//   dst[pair_dst] (+)= op_g src[pair_src]      (ADJ: op_g conjugate-transposed)
+// Workgroup tile: 64 output rows x CT pairs (CT = 16, 32, 64 or 128; 8 waves
+// for 128, else 4), operands staged through LDS in 16-wide k chunks, double
+// buffered: the global loads of chunk c + 1 are in flight while chunk c runs
+// on the matrix cores.  Complex products:
+//   float32: three real products per block (P1 = Ar Br, P2 = Ai Bi,
+//            P3 = (Ar + Ai)(Br + Bi); C = (P1 - P2, P3 - P1 - P2)), with the
+//            sums (Ar + Ai), (Br + Bi) formed once when staging;
+//   float64: four real products (C_re = Ar Br - Ai Bi, C_im = Ar Bi + Ai Br).
+// The output tile is staged in LDS and written as whole coefficient rows per
+// pair (contiguous), either to the per-pair buffer, or added into the
+// destination (plain read-modify-write where every destination of the launch
+// receives one pair, else atomically).
 // MFMA 16x16x4 operand layout (wave64): A[m][k] from lane m + 16 k, B[k][n]
 // from lane n + 16 k.  Output D[m][n] sits in lane n + 16 j, element e, with
 // m = 4 j + e for the float32 instruction and m = 4 e + j for the float64
@@ -375,61 +467,127 @@ struct MfmaOp<double> {
   __device__ static __forceinline__ int row(int j, int e) { return 4 * e + j; }
 };
 
-constexpr int G_RT = 64, G_CT = 64, G_KC = 16, G_LD = G_KC + 1;
+constexpr int G_RT = 64, G_KC = 16, G_LD = G_KC + 1;
 
-template <typename R, bool ADJ, int KIND>
-__global__ void __launch_bounds__(256)
-    k_grouped_gemm(int mat_rows, int mat_cols, const int* __restrict__ tile_group,
-                   const int* __restrict__ tile_pair0, const int* __restrict__ tile_npairs,
-                   const int* __restrict__ tile_row0, const int* __restrict__ group_slot,
-                   const cplx<R>* __restrict__ mats, const int* __restrict__ pair_dst,
-                   const int* __restrict__ pair_src, const cplx<R>* __restrict__ src,
-                   cplx<R>* __restrict__ dst, cplx<R>* __restrict__ cbuf) {
+template <int CT>
+struct TileShape {
+  static constexpr int NW = (CT == 128) ? 8 : 4;         // waves
+  static constexpr int WR = (NW == 8) ? 2 : (CT >= 32 ? 2 : 4);  // wave rows
+  static constexpr int WC = NW / WR;                     // wave columns
+  static constexpr int RB = G_RT / WR / 16;              // 16x16 blocks per wave
+  static constexpr int CB = CT / WC / 16;
+};
+
+// One grouped product of a launch (a launch may cover several levels, each
+// with its own operator, tiles, input and output; tiles of job q are the
+// launch's tiles tile0[q] .. tile0[q + 1] - 1).
+template <typename R>
+struct GemmJobDev {
+  int mat_rows, mat_cols;
+  const int* tile_group;
+  const int* tile_pair0;
+  const int* tile_npairs;
+  const int* tile_row0;
+  const int* group_slot;
+  const int* pair_dst;
+  const int* pair_src;
+  const cplx<R>* mats;
+  const cplx<R>* src;
+  cplx<R>* dst;
+  cplx<R>* cbuf;
+};
+constexpr int MAX_JOBS = 8;
+template <typename R>
+struct GemmBatch {
+  int n;
+  int tile0[MAX_JOBS + 1];
+  GemmJobDev<R> job[MAX_JOBS];
+};
+
+// the job of a (workgroup-uniform) index, selected without dynamic indexing
+// of the kernel argument
+template <typename T, int N>
+__device__ __forceinline__ T select_job(const T (&arr)[N], int q) {
+  T v = arr[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i)
+    if (i == q) v = arr[i];
+  return v;
+}
+
+// KIND: 0 M2L (per-pair output), 1 M2M, 2 L2L (the latter two add into dst)
+template <typename R, int CT, bool ADJ, int KIND>
+__global__ void __launch_bounds__(64 * TileShape<CT>::NW)
+    k_grouped_gemm(const GemmBatch<R> batch) {
   typedef typename MfmaOp<R>::v4 v4;
-  __shared__ R a_re[G_RT * G_LD], a_im[G_RT * G_LD];
-  __shared__ R b_re[G_CT * G_LD], b_im[G_CT * G_LD];
-  __shared__ int s_src[G_CT], s_dst[G_CT];
+  typedef TileShape<CT> S;
+  constexpr bool M3 = sizeof(R) == 4;
+  constexpr int NP = M3 ? 3 : 2;  // LDS planes: re, im (, re + im)
+  constexpr int NT = 64 * S::NW;
+  constexpr int PA = (G_RT * G_KC) / NT, PB = (CT * G_KC + NT - 1) / NT;
+  constexpr int A_SZ = 2 * NP * G_RT * G_LD, B_SZ = 2 * NP * CT * G_LD;
+  constexpr int OLD = G_RT + 1;  // staged output [pair][row], padded
+  constexpr int MAIN = (A_SZ + B_SZ) * (int)sizeof(R);
+  constexpr int OUTB = CT * OLD * 2 * (int)sizeof(R);
+  __shared__ __attribute__((aligned(16))) char smem[MAIN > OUTB ? MAIN : OUTB];
+  __shared__ int s_src[CT], s_dst[CT];
+  R* As = (R*)smem;
+  R* Bs = As + A_SZ;
   // XCD-aware order: workgroups go to the 8 XCDs round-robin (block b on XCD
   // b % 8), so give each XCD a contiguous range of tiles; consecutive tiles
   // share their group's matrix, which then stays in that XCD's L2.
   const int nt = gridDim.x, xcd = blockIdx.x & 7, slot_in_xcd = blockIdx.x >> 3;
-  const int tile = xcd * (nt >> 3) + min(xcd, nt & 7) + slot_in_xcd;
+  const int gtile = xcd * (nt >> 3) + min(xcd, nt & 7) + slot_in_xcd;
+  int q = 0;
+#pragma unroll
+  for (int i = 1; i < MAX_JOBS; ++i)
+    if (i < batch.n && gtile >= batch.tile0[i]) q = i;
+  const GemmJobDev<R> J = select_job(batch.job, q);
+  const int tile = gtile - select_job(batch.tile0, q);
+  const int mat_rows = J.mat_rows, mat_cols = J.mat_cols;
+  const int* __restrict__ pair_src = J.pair_src;
+  const cplx<R>* __restrict__ src = J.src;
+  cplx<R>* __restrict__ dst = J.dst;
+  cplx<R>* __restrict__ cbuf = J.cbuf;
   const int tid = threadIdx.x;
-  const int grp = tile_group[tile], p0 = tile_pair0[tile], np = tile_npairs[tile];
-  const int r0 = tile_row0[tile];
-  const int slot = group_slot[grp];
+  const int grp = J.tile_group[tile], p0 = J.tile_pair0[tile], np = J.tile_npairs[tile];
+  const int r0 = J.tile_row0[tile];
+  const int slot = J.group_slot[grp];
   const int out_rows = ADJ ? mat_cols : mat_rows;  // rows of the effective op
   const int in_cols = ADJ ? mat_rows : mat_cols;
-  const cplx<R>* M = mats + (int64_t)slot * mat_rows * mat_cols;
-  if (tid < G_CT) {
-    s_src[tid] = (tid < np) ? pair_src[p0 + tid] : -1;
-    s_dst[tid] = (tid < np) ? pair_dst[p0 + tid] : -1;
+  const cplx<R>* M = J.mats + (int64_t)slot * mat_rows * mat_cols;
+  for (int t = tid; t < CT; t += NT) {
+    s_src[t] = (t < np) ? pair_src[p0 + t] : -1;
+    s_dst[t] = (t < np) ? J.pair_dst[p0 + t] : -1;
   }
-  const int wave = tid >> 6, lane = tid & 63;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int li = lane & 15, lk = lane >> 4;
-  v4 cr[2][2], ci[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      cr[a][b] = v4{0, 0, 0, 0};
-      ci[a][b] = v4{0, 0, 0, 0};
-    }
   __syncthreads();
-  for (int k0 = 0; k0 < in_cols; k0 += G_KC) {
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave / S::WC, wc = wave % S::WC;
+  const int li = lane & 15, lk = lane >> 4;
+  v4 c0[S::RB][S::CB], c1[S::RB][S::CB], c2[S::RB][S::CB];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = tid + 256 * q;
+  for (int a = 0; a < S::RB; ++a)
+#pragma unroll
+    for (int b = 0; b < S::CB; ++b) {
+      c0[a][b] = v4{0, 0, 0, 0};
+      c1[a][b] = v4{0, 0, 0, 0};
+      c2[a][b] = v4{0, 0, 0, 0};
+    }
+  cplx<R> ra[PA], rb[PB];
+  // global -> registers for the chunk starting at k0
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      const int e = tid + NT * q;
       int kk, rr;
-      if (ADJ) {
+      if (ADJ) {  // consecutive threads walk a stored row (contiguous)
         rr = e % G_RT;
         kk = e / G_RT;
       } else {
         kk = e % G_KC;
         rr = e / G_KC;
       }
-      int r = r0 + rr, c = k0 + kk;
+      const int r = r0 + rr, c = k0 + kk;
       cplx<R> v = mk<R>(0, 0);
       if (r < out_rows && c < in_cols) {
         if (ADJ) {
@@ -439,69 +597,120 @@ __global__ void __launch_bounds__(256)
           v = M[(int64_t)r * mat_cols + c];
         }
       }
-      a_re[rr * G_LD + kk] = v.re;
-      a_im[rr * G_LD + kk] = v.im;
+      ra[q] = v;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = tid + 256 * q;
-      int kk = e % G_KC, cc = e / G_KC;
-      int c = k0 + kk;
-      cplx<R> v = mk<R>(0, 0);
-      if (cc < np && c < in_cols) v = src[(int64_t)s_src[cc] * in_cols + c];
-      b_re[cc * G_LD + kk] = v.re;
-      b_im[cc * G_LD + kk] = v.im;
+    for (int q = 0; q < PB; ++q) {
+      const int e = tid + NT * q;
+      const int kk = e % G_KC, cc = e / G_KC, c = k0 + kk;
+      rb[q] = (cc < np && c < in_cols) ? src[(int64_t)s_src[cc] * in_cols + c] : mk<R>(0, 0);
     }
-    __syncthreads();
+  };
+  // registers -> LDS buffer buf
+  auto store = [&](int buf) {
+    R* A0 = As + (buf * NP) * G_RT * G_LD;
+    R* B0 = Bs + (buf * NP) * CT * G_LD;
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      const int e = tid + NT * q;
+      const int kk = ADJ ? e / G_RT : e % G_KC, rr = ADJ ? e % G_RT : e / G_KC;
+      A0[rr * G_LD + kk] = ra[q].re;
+      A0[G_RT * G_LD + rr * G_LD + kk] = ra[q].im;
+      if (M3) A0[2 * G_RT * G_LD + rr * G_LD + kk] = ra[q].re + ra[q].im;
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int e = tid + NT * q;
+      const int kk = e % G_KC, cc = e / G_KC;
+      if (cc < CT) {
+        B0[cc * G_LD + kk] = rb[q].re;
+        B0[CT * G_LD + cc * G_LD + kk] = rb[q].im;
+        if (M3) B0[2 * CT * G_LD + cc * G_LD + kk] = rb[q].re + rb[q].im;
+      }
+    }
+  };
+  const int nchunk = (in_cols + G_KC - 1) / G_KC;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) load((ch + 1) * G_KC);
+    const R* A0 = As + (buf * NP) * G_RT * G_LD;
+    const R* B0 = Bs + (buf * NP) * CT * G_LD;
 #pragma unroll
     for (int ks = 0; ks < G_KC; ks += 4) {
-      R ar[2], ai[2], nai[2], br[2], bi[2];
+      R a0[S::RB], a1[S::RB], a2[S::RB], b0[S::CB], b1[S::CB], b2[S::CB];
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        int row = wr * 32 + rb * 16 + li;
-        ar[rb] = a_re[row * G_LD + ks + lk];
-        ai[rb] = a_im[row * G_LD + ks + lk];
-        nai[rb] = -ai[rb];
+      for (int i = 0; i < S::RB; ++i) {
+        const int o = (wr * (G_RT / S::WR) + i * 16 + li) * G_LD + ks + lk;
+        a0[i] = A0[o];
+        a1[i] = A0[G_RT * G_LD + o];
+        if (M3) a2[i] = A0[2 * G_RT * G_LD + o];
       }
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        int col = wc * 32 + cb * 16 + li;
-        br[cb] = b_re[col * G_LD + ks + lk];
-        bi[cb] = b_im[col * G_LD + ks + lk];
+      for (int j = 0; j < S::CB; ++j) {
+        const int o = (wc * (CT / S::WC) + j * 16 + li) * G_LD + ks + lk;
+        b0[j] = B0[o];
+        b1[j] = B0[CT * G_LD + o];
+        if (M3) b2[j] = B0[2 * CT * G_LD + o];
       }
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int i = 0; i < S::RB; ++i)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          cr[rb][cb] = MfmaOp<R>::mma(ar[rb], br[cb], cr[rb][cb]);
-          cr[rb][cb] = MfmaOp<R>::mma(nai[rb], bi[cb], cr[rb][cb]);
-          ci[rb][cb] = MfmaOp<R>::mma(ar[rb], bi[cb], ci[rb][cb]);
-          ci[rb][cb] = MfmaOp<R>::mma(ai[rb], br[cb], ci[rb][cb]);
-        }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int row = r0 + wr * 32 + rb * 16 + MfmaOp<R>::row(lk, e);
-        int cc = wc * 32 + cb * 16 + li;
-        if (row < out_rows && cc < np) {
-          cplx<R> v = mk<R>(cr[rb][cb][e], ci[rb][cb][e]);
-          if (cbuf) {  // per-pair output, reduced per destination afterwards
-            cbuf[(int64_t)(p0 + cc) * out_rows + row] = v;
-          } else if ((KIND == 2 && !ADJ) || (KIND == 1 && ADJ)) {
-            // parent -> child: every child is the destination of exactly one pair
-            cplx<R>* d = &dst[(int64_t)s_dst[cc] * out_rows + row];
-            *d = cadd(*d, v);
+        for (int j = 0; j < S::CB; ++j) {
+          if (M3) {
+            c0[i][j] = MfmaOp<R>::mma(a0[i], b0[j], c0[i][j]);
+            c1[i][j] = MfmaOp<R>::mma(a1[i], b1[j], c1[i][j]);
+            c2[i][j] = MfmaOp<R>::mma(a2[i], b2[j], c2[i][j]);
           } else {
-            atomic_cadd(&dst[(int64_t)s_dst[cc] * out_rows + row], v);
+            c0[i][j] = MfmaOp<R>::mma(a0[i], b0[j], c0[i][j]);
+            c0[i][j] = MfmaOp<R>::mma(-a1[i], b1[j], c0[i][j]);
+            c1[i][j] = MfmaOp<R>::mma(a0[i], b1[j], c1[i][j]);
+            c1[i][j] = MfmaOp<R>::mma(a1[i], b0[j], c1[i][j]);
           }
         }
+    }
+    if (ch + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
+  }
+  // stage the tile [pair][row] in LDS (the operand buffers are free now)
+  R* Os = (R*)smem;
+#pragma unroll
+  for (int i = 0; i < S::RB; ++i)
+#pragma unroll
+    for (int j = 0; j < S::CB; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = wr * (G_RT / S::WR) + i * 16 + MfmaOp<R>::row(lk, e);
+        const int cc = wc * (CT / S::WC) + j * 16 + li;
+        R re, im;
+        if (M3) {
+          re = c0[i][j][e] - c1[i][j][e];
+          im = c2[i][j][e] - c0[i][j][e] - c1[i][j][e];
+        } else {
+          re = c0[i][j][e];
+          im = c1[i][j][e];
+        }
+        Os[(cc * OLD + row) * 2] = re;
+        Os[(cc * OLD + row) * 2 + 1] = im;
       }
+  __syncthreads();
+  const int nrow = min(G_RT, out_rows - r0);
+  for (int t = tid; t < CT * G_RT; t += NT) {
+    const int cc = t / G_RT, row = t % G_RT;
+    if (cc >= np || row >= nrow) continue;
+    const cplx<R> v = mk<R>(Os[(cc * OLD + row) * 2], Os[(cc * OLD + row) * 2 + 1]);
+    if (KIND == 0) {  // per-pair output, reduced per destination afterwards
+      cbuf[(int64_t)(p0 + cc) * out_rows + r0 + row] = v;
+    } else if ((KIND == 2 && !ADJ) || (KIND == 1 && ADJ)) {
+      // parent -> child: every child is the destination of exactly one pair
+      cplx<R>* d = &dst[(int64_t)s_dst[cc] * out_rows + r0 + row];
+      *d = cadd(*d, v);
+    } else {
+      atomic_cadd(&dst[(int64_t)s_dst[cc] * out_rows + r0 + row], v);
+    }
+  }
 }
 
 // dst[b][c] (+)= sum over the pairs t of box b of cbuf[t][c]  (pairs listed
@@ -509,35 +718,60 @@ __global__ void __launch_bounds__(256)
 // 256 threads per box: 4 slices of 64 coefficients, each slice sums every
 // fourth pair, then the slices are added in a fixed order.
 template <typename R>
+struct RedJobDev {
+  int ncoef;
+  const int* ptr;
+  const int* pairs;
+  const cplx<R>* cbuf;
+  cplx<R>* dst;
+};
+template <typename R>
+struct RedBatch {
+  int n;
+  int box0[MAX_JOBS + 1];
+  RedJobDev<R> job[MAX_JOBS];
+};
+
+template <typename R>
 __global__ void __launch_bounds__(256)
-    k_pair_reduce(int ncoef, const int* __restrict__ ptr, const int* __restrict__ pairs,
-                  const cplx<R>* __restrict__ cbuf, int accumulate, cplx<R>* __restrict__ dst) {
+    k_pair_reduce(const RedBatch<R> batch, int accumulate) {
   __shared__ cplx<R> part[4][64];
-  const int b = blockIdx.x;
-  const int t0 = ptr[b], t1 = ptr[b + 1];
+  int q = 0;
+#pragma unroll
+  for (int i = 1; i < MAX_JOBS; ++i)
+    if (i < batch.n && (int)blockIdx.x >= batch.box0[i]) q = i;
+  const RedJobDev<R> J = select_job(batch.job, q);
+  const int b = blockIdx.x - select_job(batch.box0, q);
+  const int ncoef = J.ncoef;
+  const int t0 = J.ptr[b], t1 = J.ptr[b + 1];
   const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
   for (int c0 = 0; c0 < ncoef; c0 += 64) {
     const int c = c0 + lane;
     cplx<R> acc = mk<R>(0, 0);
     if (c < ncoef)
-      for (int t = t0 + slice; t < t1; t += 4) acc = cadd(acc, cbuf[(int64_t)pairs[t] * ncoef + c]);
+      for (int t = t0 + slice; t < t1; t += 4)
+        acc = cadd(acc, J.cbuf[(int64_t)J.pairs[t] * ncoef + c]);
     part[slice][lane] = acc;
     __syncthreads();
     if (slice == 0 && c < ncoef) {
-      cplx<R> s = accumulate ? dst[(int64_t)b * ncoef + c] : mk<R>(0, 0);
+      cplx<R> s = accumulate ? J.dst[(int64_t)b * ncoef + c] : mk<R>(0, 0);
       s = cadd(s, cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane])));
-      dst[(int64_t)b * ncoef + c] = s;
+      J.dst[(int64_t)b * ncoef + c] = s;
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// finish: one wavefront per element
+// finish: 16 lanes per element (4 elements per wavefront).  Lane l handles
+// local-expansion coefficients l, l + 16, ... and near-list entries l,
+// l + 16, ...; the 16 partial sums are combined by shuffles in a fixed order.
 // ---------------------------------------------------------------------------
+constexpr int FIN_LANES = 16;
+
 template <typename R>
-__device__ __forceinline__ R wave_reduce(R v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+__device__ __forceinline__ R group_sum16(R v) {
+  for (int off = FIN_LANES / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, FIN_LANES);
   return v;
 }
 
@@ -551,23 +785,24 @@ __global__ void __launch_bounds__(256)
              const cplx<R>* __restrict__ ys, const c64* __restrict__ dp,
              const c64* __restrict__ dq, const c64* __restrict__ p64,
              const c64* __restrict__ q64, c64* __restrict__ y) {
-  int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
-  if (i >= n) return;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / FIN_LANES;
+  const int l = threadIdx.x % FIN_LANES;
   cplx<R> acc = mk<R>(0, 0);
-  if (ncoef > 0) {
-    const cplx<R>* Bi = l2p + i * ncoef;
-    const cplx<R>* Lb = Lc + (int64_t)elem_leaf[i] * ncoef;
-    for (int c = lane; c < ncoef; c += 64) cfma(acc, Bi[c], Lb[c]);
+  if (i < n) {  // whole 16-lane groups are in or out: the shuffles stay inside a group
+    if (ncoef > 0) {
+      const cplx<R>* Bi = l2p + i * ncoef;
+      const cplx<R>* Lb = Lc + (int64_t)elem_leaf[i] * ncoef;
+      for (int c = l; c < ncoef; c += FIN_LANES) cfma(acc, Bi[c], Lb[c]);
+    }
+    for (int t = near_ptr[i] + l; t < near_ptr[i + 1]; t += FIN_LANES) {
+      const int j = near_col[t];
+      cfma(acc, ncp[t], ps[j]);
+      cfma(acc, ncq[t], qs[j]);
+    }
   }
-  for (int t = near_ptr[i] + lane; t < near_ptr[i + 1]; t += 64) {
-    int j = near_col[t];
-    cfma(acc, ncp[t], ps[j]);
-    cfma(acc, ncq[t], qs[j]);
-  }
-  acc.re = wave_reduce(acc.re);
-  acc.im = wave_reduce(acc.im);
-  if (lane == 0) {
+  acc.re = group_sum16(acc.re);
+  acc.im = group_sum16(acc.im);
+  if (i < n && l == 0) {
     cplx<R> s = cadd(acc, ys[i]);
     c64 out = mk((double)s.re, (double)s.im);
     cfma(out, dp[i], p64[i]);
@@ -586,28 +821,31 @@ __global__ void __launch_bounds__(256)
                  const cplx<R>* __restrict__ ws, const c64* __restrict__ dp,
                  const c64* __restrict__ dq, const c64* __restrict__ y64, c64* __restrict__ u,
                  c64* __restrict__ w) {
-  int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
-  if (j >= n) return;
+  const int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / FIN_LANES;
+  const int l = threadIdx.x % FIN_LANES;
   cplx<R> au = mk<R>(0, 0), aw = mk<R>(0, 0);
-  if (ncoef > 0) {
-    const cplx<R>* Aj = p2m + j * ncoef * 2;
-    const cplx<R>* Mb = Mc + (int64_t)elem_leaf[j] * ncoef;
-    for (int c = lane; c < ncoef; c += 64) {
-      cfmac(au, Aj[2 * c], Mb[c]);
-      cfmac(aw, Aj[2 * c + 1], Mb[c]);
+  if (j < n) {
+    if (ncoef > 0) {
+      const cplx<R>* Aj = p2m + j * ncoef * 2;
+      const cplx<R>* Mb = Mc + (int64_t)elem_leaf[j] * ncoef;
+      for (int c = l; c < ncoef; c += FIN_LANES) {
+        cplx<R> ap, aq;
+        load_pair(Aj + 2 * c, ap, aq);
+        cfmac(au, ap, Mb[c]);
+        cfmac(aw, aq, Mb[c]);
+      }
+    }
+    for (int t = tptr[j] + l; t < tptr[j + 1]; t += FIN_LANES) {
+      cplx<R> yv = ysrt[trow[t]];
+      cfmac(au, tcp[t], yv);
+      cfmac(aw, tcq[t], yv);
     }
   }
-  for (int t = tptr[j] + lane; t < tptr[j + 1]; t += 64) {
-    cplx<R> yv = ysrt[trow[t]];
-    cfmac(au, tcp[t], yv);
-    cfmac(aw, tcq[t], yv);
-  }
-  au.re = wave_reduce(au.re);
-  au.im = wave_reduce(au.im);
-  aw.re = wave_reduce(aw.re);
-  aw.im = wave_reduce(aw.im);
-  if (lane == 0) {
+  au.re = group_sum16(au.re);
+  au.im = group_sum16(au.im);
+  aw.re = group_sum16(aw.re);
+  aw.im = group_sum16(aw.im);
+  if (j < n && l == 0) {
     cplx<R> su = cadd(au, us[j]), sw = cadd(aw, ws[j]);
     c64 ou = mk((double)su.re, (double)su.im), ow = mk((double)sw.re, (double)sw.im);
     cfmac(ou, dp[j], y64[j]);
@@ -646,53 +884,171 @@ int prof_end(Problem& P, int idx, int slot, hipStream_t s) {
 #define PROF_BEGIN(var) int var = prof_begin(P, s)
 #define PROF_END(var, stage)                                                  \
   do {                                                                        \
-    int _pr = prof_end(P, var, (stage) + 8 * (sizeof(R) == 4) + 16 * ADJ_FLAG, s); \
+    int _pr = prof_end(P, var, prof_slot(stage, sizeof(R) == 4, ADJ_FLAG), s); \
     if (_pr) return _pr;                                                      \
   } while (0)
 
 // ---------------------------------------------------------------------------
 // host drivers
 // ---------------------------------------------------------------------------
-// KIND only separates the kernel names (0 M2L, 1 M2M, 2 L2L) for profilers
-// With cbuf (and the op's per-destination pair lists) the product is
-// written per pair and then reduced per destination box, replacing dst
-// (accumulate = 0) or adding to it; without, it is accumulated atomically.
+// KIND: 0 M2L (per-pair output into cbuf, then reduced per destination box,
+// replacing dst (accumulate = 0) or adding to it), 1 M2M, 2 L2L (added into
+// dst).  One launch covers up to MAX_JOBS grouped products with the same
+// pair-tile width (chosen at plan time; it selects the instantiation).
+template <typename R>
+struct GemmJob {
+  const GroupedOp<R>* op;
+  const cplx<R>* src;
+  cplx<R>* dst;
+  cplx<R>* cbuf;  // M2L: this job's per-pair output
+};
+
+template <typename R, int CT, bool ADJ, int KIND>
+static void launch_gemm(const GemmBatch<R>& b, int nt, hipStream_t s) {
+  hipLaunchKernelGGL((k_grouped_gemm<R, CT, ADJ, KIND>), dim3(nt), dim3(64 * TileShape<CT>::NW), 0,
+                     s, b);
+}
+
+template <typename R, bool ADJ, int KIND>
+static int launch_gemm_ct(const GemmBatch<R>& b, int ct, int nt, hipStream_t s) {
+  switch (ct) {
+    case 16: launch_gemm<R, 16, ADJ, KIND>(b, nt, s); break;
+    case 32: launch_gemm<R, 32, ADJ, KIND>(b, nt, s); break;
+    case 64: launch_gemm<R, 64, ADJ, KIND>(b, nt, s); break;
+    case 128:
+      if constexpr (sizeof(R) == 4) {
+        launch_gemm<R, 128, ADJ, KIND>(b, nt, s);
+        break;
+      } else {
+        set_error("128-pair tiles are float32 only");
+        return -1;
+      }
+    default: set_error("bad pair-tile width"); return -1;
+  }
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
 template <typename R, int KIND>
-static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, cplx<R>* dst,
-                          hipStream_t s, cplx<R>* cbuf = nullptr, int accumulate = 0,
-                          Problem* prof = nullptr) {
-  int nt = adj ? op.n_tiles_adj : op.n_tiles;
+static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStream_t s,
+                               int accumulate = 0, Problem* prof = nullptr,
+                               int st_gemm = ST_M2L) {
+  if (nj <= 0) return 0;
+  if (nj > MAX_JOBS) {
+    set_error("too many grouped products in one launch");
+    return -1;
+  }
+  GemmBatch<R> b{};
+  RedBatch<R> rb{};
+  b.n = rb.n = nj;
+  int nt = 0, nbox = 0, ct = 0;
+  for (int q = 0; q < nj; ++q) {
+    const GroupedOp<R>& op = *jobs[q].op;
+    if (KIND == 0 && !jobs[q].cbuf) {
+      set_error("multipole-to-local product without its per-pair buffer");
+      return -1;
+    }
+    const int jct = adj ? op.ct_adj : op.ct;
+    if (q > 0 && jct != ct) {
+      set_error("grouped products of one launch differ in tile width");
+      return -1;
+    }
+    ct = jct;
+    GemmJobDev<R>& J = b.job[q];
+    J.mat_rows = op.rows;
+    J.mat_cols = op.cols;
+    J.tile_group = adj ? op.tile_group_adj : op.tile_group;
+    J.tile_pair0 = adj ? op.tile_pair0_adj : op.tile_pair0;
+    J.tile_npairs = adj ? op.tile_npairs_adj : op.tile_npairs;
+    J.tile_row0 = adj ? op.tile_row0_adj : op.tile_row0;
+    J.group_slot = op.group_slot;
+    J.pair_dst = adj ? op.pair_dst_adj : op.pair_dst;
+    J.pair_src = adj ? op.pair_src_adj : op.pair_src;
+    J.mats = op.mats;
+    J.src = jobs[q].src;
+    J.dst = jobs[q].dst;
+    J.cbuf = jobs[q].cbuf;
+    b.tile0[q] = nt;
+    nt += adj ? op.n_tiles_adj : op.n_tiles;
+    RedJobDev<R>& RJ = rb.job[q];
+    RJ.ncoef = adj ? op.cols : op.rows;
+    RJ.ptr = adj ? op.red_ptr_adj : op.red_ptr;
+    RJ.pairs = adj ? op.red_pairs_adj : op.red_pairs;
+    RJ.cbuf = jobs[q].cbuf;
+    RJ.dst = jobs[q].dst;
+    rb.box0[q] = nbox;
+    nbox += adj ? op.n_red_adj : op.n_red;
+  }
+  b.tile0[nj] = nt;
+  rb.box0[nj] = nbox;
   if (nt > 0) {
     int evg = prof ? prof_begin(*prof, s) : -1;
-    if (adj)
-      hipLaunchKernelGGL((k_grouped_gemm<R, true, KIND>), dim3(nt), dim3(256), 0, s, op.rows,
-                         op.cols, op.tile_group_adj, op.tile_pair0_adj, op.tile_npairs_adj,
-                         op.tile_row0_adj, op.group_slot, op.mats, op.pair_dst_adj,
-                         op.pair_src_adj, src, dst, cbuf);
-    else
-      hipLaunchKernelGGL((k_grouped_gemm<R, false, KIND>), dim3(nt), dim3(256), 0, s, op.rows,
-                         op.cols, op.tile_group, op.tile_pair0, op.tile_npairs, op.tile_row0,
-                         op.group_slot, op.mats, op.pair_dst, op.pair_src, src, dst, cbuf);
-    BEM_LAUNCH_CHECK();
+    int r = adj ? launch_gemm_ct<R, true, KIND>(b, ct, nt, s)
+                : launch_gemm_ct<R, false, KIND>(b, ct, nt, s);
+    if (r) return r;
     if (prof) {
-      int pr = prof_end(*prof, evg, ST_M2L + 8 * (sizeof(R) == 4) + 16 * (adj ? 1 : 0), s);
+      int pr = prof_end(*prof, evg, prof_slot(st_gemm, sizeof(R) == 4, adj), s);
       if (pr) return pr;
     }
   }
-  if (cbuf && (adj ? op.n_red_adj : op.n_red) > 0) {
-    int nb = adj ? op.n_red_adj : op.n_red;
-    int nco = adj ? op.cols : op.rows;
+  // the reduction also runs with no tiles: it then clears the destinations
+  if (KIND == 0 && nbox > 0) {
     int ev = prof ? prof_begin(*prof, s) : -1;
-    hipLaunchKernelGGL(k_pair_reduce<R>, dim3(nb), dim3(256), 0, s, nco,
-                       adj ? op.red_ptr_adj : op.red_ptr, adj ? op.red_pairs_adj : op.red_pairs,
-                       (const cplx<R>*)cbuf, accumulate, dst);
+    hipLaunchKernelGGL(k_pair_reduce<R>, dim3(nbox), dim3(256), 0, s, rb, accumulate);
     BEM_LAUNCH_CHECK();
     if (prof) {
-      int pr = prof_end(*prof, ev, ST_M2L_RED + 8 * (sizeof(R) == 4) + 16 * (adj ? 1 : 0), s);
+      const int st_red = st_gemm == ST_M2L_LEAF ? ST_M2L_LEAF_RED : ST_M2L_RED;
+      int pr = prof_end(*prof, ev, prof_slot(st_red, sizeof(R) == 4, adj), s);
       if (pr) return pr;
     }
   }
   return 0;
+}
+
+template <typename R, int KIND>
+static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, cplx<R>* dst,
+                          hipStream_t s, cplx<R>* cbuf = nullptr, int accumulate = 0,
+                          Problem* prof = nullptr, int st_gemm = ST_M2L) {
+  GemmJob<R> j{&op, src, dst, cbuf};
+  return launch_grouped_jobs<R, KIND>(&j, 1, adj, s, accumulate, prof, st_gemm);
+}
+
+// M2L of the levels 2 .. L-1 (all inputs ready once the upward pass is done):
+// consecutive levels with the same pair-tile width share a launch (up to
+// MAX_JOBS levels), each level keeping the width chosen for it
+template <typename R>
+static int launch_coarse_m2l(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t s) {
+  const int L = P.L;
+  int l = 2;
+  while (l < L) {
+    GemmJob<R> jobs[MAX_JOBS];
+    int nj = 0;
+    const int ct = adj ? D.m2l[l].ct_adj : D.m2l[l].ct;
+    for (; l < L && nj < MAX_JOBS && (adj ? D.m2l[l].ct_adj : D.m2l[l].ct) == ct; ++l, ++nj) {
+      jobs[nj].op = &D.m2l[l];
+      jobs[nj].src = adj ? D.Lc[l] : D.M[l];
+      jobs[nj].dst = adj ? D.M[l] : D.Lc[l];
+      jobs[nj].cbuf = D.cbuf + D.cbuf_off[l];
+    }
+    int r = launch_grouped_jobs<R, 0>(jobs, nj, adj, s, 0, P.prof_on ? &P : nullptr);
+    if (r) return r;
+  }
+  return 0;
+}
+
+// the parent-level expansions accumulated atomically in the chain (M for the
+// forward upward pass, L for the adjoint one), cleared by the gather kernel
+template <typename R>
+static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, bool adj) {
+  ZeroList<R> z{};
+  z.n = 0;
+  if (P.direct) return z;
+  for (int l = P.L - 1; l >= 2 && z.n < MAX_ZERO; --l) {
+    z.ptr[z.n] = adj ? D.Lc[l] : D.M[l];
+    z.cnt[z.n] = (int64_t)P.nbox[l] * D.ncoef[l];
+    ++z.n;
+  }
+  return z;
 }
 
 template <typename R>
@@ -713,7 +1069,7 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
   int nb = ceil_div(n, 256);
   PROF_BEGIN(e0);
   hipLaunchKernelGGL(k_gather_in<R>, dim3(nb), dim3(256), 0, s, p, q, P.perm, n, D.ps, D.qs,
-                     P.p64s, P.q64s);
+                     P.p64s, P.q64s, chain_zero_list(P, D, false));
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
@@ -725,24 +1081,29 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
   }
   {
     int e1 = prof_begin(P, sn);
-    hipLaunchKernelGGL(k_p2p<R>, dim3(nleaf), dim3(P2P_THREADS), 0, sn, (const R*)D.geo, n,
-                       P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr, ali, (int)P.direct,
-                       D.ys);
+    if (P.alpha.re == 0.0)
+      hipLaunchKernelGGL((k_p2p<R, true>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
+                         (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr,
+                         ali, (int)P.direct, D.ys);
+    else
+      hipLaunchKernelGGL((k_p2p<R, false>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
+                         (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr,
+                         ali, (int)P.direct, D.ys);
     BEM_LAUNCH_CHECK();
-    int pr = prof_end(P, e1, ST_P2P + 8 * (sizeof(R) == 4), sn);
+    int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, false), sn);
     if (pr) return pr;
   }
   if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
   int r = 0;
   if (P.direct) {
-    hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
+    hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
                        P.elem_leaf, 0, D.l2p, D.Lc[L], P.near_ptr, P.near_col, D.near_cp,
                        D.near_cq, D.ps, D.qs, D.ys, P.diag_p, P.diag_q, P.p64s, P.q64s, y);
     BEM_LAUNCH_CHECK();
     return 0;
   }
   PROF_BEGIN(e2);
-  hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(nleaf), dim3(128), 0, s, P.box_start[L],
+  hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(nleaf), dim3(256), 0, s, P.box_start[L],
                      D.ncoef[L], D.p2m, D.ps, D.qs, 0, D.M[L]);
   BEM_LAUNCH_CHECK();
   PROF_END(e2, ST_P2M);
@@ -750,18 +1111,19 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
   BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
   BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   if ((r = launch_grouped<R, 0>(D.m2l[L], false, D.M[L], D.Lc[L], P.side2, D.cbufL, 0,
-                                P.prof_on ? &P : nullptr)))
+                                P.prof_on ? &P : nullptr, ST_M2L_LEAF)))
     return r;
   BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   PROF_BEGIN(e3);
   for (int l = L; l >= 3; --l) {
-    if ((r = zero<R>(D.M[l - 1], (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s))) return r;
+    // parents beyond the gather kernel's clear list
+    if (l - 1 < L - MAX_ZERO &&
+        (r = zero<R>(D.M[l - 1], (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s)))
+      return r;
     if ((r = launch_grouped<R, 1>(D.m2m[l], false, D.M[l], D.M[l - 1], s))) return r;
   }
   PROF_END(e3, ST_M2M);
-  for (int l = 2; l < L; ++l)
-    if ((r = launch_grouped<R, 0>(D.m2l[l], false, D.M[l], D.Lc[l], s, D.cbuf, 0,
-                                  P.prof_on ? &P : nullptr))) return r;
+  if ((r = launch_coarse_m2l<R>(P, D, false, s))) return r;
   PROF_BEGIN(e5);
   for (int l = 3; l <= L; ++l) {
     if (l == L) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
@@ -771,7 +1133,7 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
   PROF_END(e5, ST_L2L);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);
-  hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
+  hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
                      P.elem_leaf, D.ncoef[L], D.l2p, D.Lc[L], P.near_ptr, P.near_col, D.near_cp,
                      D.near_cq, D.ps, D.qs, D.ys, P.diag_p, P.diag_q, P.p64s, P.q64s, y);
   BEM_LAUNCH_CHECK();
@@ -781,7 +1143,9 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
 
 template <typename R>
 __global__ void k_gather_adj(const c64* __restrict__ y, const int* __restrict__ perm, int64_t n,
-                             cplx<R>* __restrict__ ys, c64* __restrict__ y64) {
+                             cplx<R>* __restrict__ ys, c64* __restrict__ y64,
+                             const ZeroList<R> zl) {
+  zero_list(zl);
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   c64 a = y[perm[i]];
@@ -799,7 +1163,8 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   int nb = ceil_div(n, 256);
   // sorted input in D.ps, P.p64s; P2P results in D.ys (u) and D.ys2 (w)
   PROF_BEGIN(e0);
-  hipLaunchKernelGGL(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, y, P.perm, n, D.ps, P.p64s);
+  hipLaunchKernelGGL(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, y, P.perm, n, D.ps, P.p64s,
+                     chain_zero_list(P, D, true));
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
@@ -810,17 +1175,22 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   }
   {
     int e1 = prof_begin(P, sn);
-    hipLaunchKernelGGL(k_p2p_adj<R>, dim3(nleaf), dim3(P2P_THREADS), 0, sn, (const R*)D.geo, n,
-                       P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali, (int)P.direct, D.ys,
-                       D.ys2);
+    if (P.alpha.re == 0.0)
+      hipLaunchKernelGGL((k_p2p_adj<R, true>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
+                         (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali,
+                         (int)P.direct, D.ys, D.ys2);
+    else
+      hipLaunchKernelGGL((k_p2p_adj<R, false>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
+                         (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali,
+                         (int)P.direct, D.ys, D.ys2);
     BEM_LAUNCH_CHECK();
-    int pr = prof_end(P, e1, ST_P2P + 8 * (sizeof(R) == 4) + 16, sn);
+    int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, true), sn);
     if (pr) return pr;
   }
   if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
   int r = 0;
   if (P.direct) {
-    hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
+    hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
                        P.elem_leaf, 0, D.p2m, D.M[L], P.neart_ptr, P.neart_row, D.neart_cp,
                        D.neart_cq, D.ps, D.ys, D.ys2, P.diag_p, P.diag_q, P.p64s, u, w);
     BEM_LAUNCH_CHECK();
@@ -828,7 +1198,7 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   }
   // adjoint locals (L2P^H) in Lc, adjoint multipoles in M
   PROF_BEGIN(e2);
-  hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(nleaf), dim3(128), 0, s, P.box_start[L],
+  hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(nleaf), dim3(256), 0, s, P.box_start[L],
                      D.ncoef[L], D.l2p, D.ps, (const cplx<R>*)nullptr, 1, D.Lc[L]);
   BEM_LAUNCH_CHECK();
   PROF_END(e2, ST_P2M);
@@ -836,18 +1206,18 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
   BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   if ((r = launch_grouped<R, 0>(D.m2l[L], true, D.Lc[L], D.M[L], P.side2, D.cbufL, 0,
-                                P.prof_on ? &P : nullptr)))
+                                P.prof_on ? &P : nullptr, ST_M2L_LEAF)))
     return r;
   BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   PROF_BEGIN(e5);
   for (int l = L; l >= 3; --l) {
-    if ((r = zero<R>(D.Lc[l - 1], (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s))) return r;
+    if (l - 1 < L - MAX_ZERO &&
+        (r = zero<R>(D.Lc[l - 1], (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s)))
+      return r;
     if ((r = launch_grouped<R, 2>(D.l2l[l], true, D.Lc[l], D.Lc[l - 1], s))) return r;
   }
   PROF_END(e5, ST_L2L);
-  for (int l = 2; l < L; ++l)
-    if ((r = launch_grouped<R, 0>(D.m2l[l], true, D.Lc[l], D.M[l], s, D.cbuf, 0,
-                                  P.prof_on ? &P : nullptr))) return r;
+  if ((r = launch_coarse_m2l<R>(P, D, true, s))) return r;
   PROF_BEGIN(e3);
   for (int l = 3; l <= L; ++l) {
     if (l == L) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
@@ -857,7 +1227,7 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   PROF_END(e3, ST_M2M);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);
-  hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * 64, 256)), dim3(256), 0, s, n, P.perm,
+  hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
                      P.elem_leaf, D.ncoef[L], D.p2m, D.M[L], P.neart_ptr, P.neart_row,
                      D.neart_cp, D.neart_cq, D.ps, D.ys, D.ys2, P.diag_p, P.diag_q, P.p64s, u, w);
   BEM_LAUNCH_CHECK();

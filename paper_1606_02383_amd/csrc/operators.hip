@@ -415,8 +415,11 @@ static int make_translations(Problem& P, int ngroups, const std::vector<double>&
   return 0;
 }
 
+// Expansion order of a level: ceil(k sqrt(3) h) + extra, at least `base`;
+// req > 0 fixes it, req < 0 replaces the minimum by -req.
 static int auto_order(double k, double h, int req, int base, int extra) {
   if (req > 0) return std::min(req, MAXP);
+  if (req < 0) base = -req;
   double d = sqrt(3.0) * h;
   int p = (int)ceil(k * d) + extra;
   return std::min(std::max(p, base), MAXP);
@@ -439,8 +442,25 @@ static void make_tiles(const std::vector<int>& gstart, int rows, int CT, int RT,
   }
 }
 
-constexpr int GEMM_CT = 64;
-constexpr int GEMM_RT = 64;
+constexpr int GEMM_RT = 64;  // output rows per tile
+
+// Pair-tile width of a grouped product: the widest of the supported widths
+// (128 is float32 only) that still gives at least ~4 tiles per compute unit,
+// else the narrowest.  Narrow tiles keep sparse groups (few pairs per
+// translation vector, coarse levels) from multiplying mostly-zero columns
+// and spread small launches over more compute units.
+static int pick_pair_tile(const std::vector<int>& gstart, int rows, bool f32) {
+  const int widths[4] = {128, 64, 32, 16};
+  const int row_tiles = (rows + GEMM_RT - 1) / GEMM_RT;
+  for (int w : widths) {
+    if (w == 128 && !f32) continue;
+    int64_t tiles = 0;
+    for (size_t g = 0; g + 1 < gstart.size(); ++g)
+      tiles += (int64_t)((gstart[g + 1] - gstart[g] + w - 1) / w) * row_tiles;
+    if (tiles >= 1024) return w;
+  }
+  return 16;
+}
 
 __global__ void k_group_starts(const int* __restrict__ code, int np, int ngroups,
                                int* __restrict__ cnt) {
@@ -482,7 +502,7 @@ __global__ void k_octant_pairs(const uint64_t* __restrict__ ckeys, const int* __
 template <typename R>
 static int finish_grouped(GroupedOp<R>& op, int* d0, int* s0, int* c0, int np, int ngroups,
                           const std::vector<int>& slot_of_group, DevArena& arena,
-                          DevArena& scratch, hipStream_t s) {
+                          DevArena& scratch, hipStream_t s, int force_ct = 0) {
   op.n_pairs = np;
   int dbits = 1;
   while ((1 << dbits) < 1 << 30 && (1 << dbits) <= np + 1) ++dbits;
@@ -522,8 +542,10 @@ static int finish_grouped(GroupedOp<R>& op, int* d0, int* s0, int* c0, int np, i
   std::vector<int> gstart(ngroups + 1, 0);
   for (int g = 0; g < ngroups; ++g) gstart[g + 1] = gstart[g] + hcnt[g];
   std::vector<int> tg, tp0, tnp, tr0, ta, tap0, tanp, tar0;
-  make_tiles(gstart, op.rows, GEMM_CT, GEMM_RT, tg, tp0, tnp, tr0);
-  make_tiles(gstart, op.cols, GEMM_CT, GEMM_RT, ta, tap0, tanp, tar0);
+  op.ct = force_ct ? force_ct : pick_pair_tile(gstart, op.rows, sizeof(R) == 4);
+  op.ct_adj = force_ct ? force_ct : pick_pair_tile(gstart, op.cols, sizeof(R) == 4);
+  make_tiles(gstart, op.rows, op.ct, GEMM_RT, tg, tp0, tnp, tr0);
+  make_tiles(gstart, op.cols, op.ct_adj, GEMM_RT, ta, tap0, tanp, tar0);
   op.n_tiles = (int)tg.size();
   op.n_tiles_adj = (int)ta.size();
   ARENA_ALLOC(arena, op.tile_group, op.n_tiles);
@@ -661,11 +683,12 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     if (r) return r;
     r = build_reduce_lists<R>(op, P.nbox[l], P.arena, scratch, s);
     if (r) return r;
-    if (l < L)
-      cbuf_count = std::max(cbuf_count, (int64_t)np * D.ncoef[l]);
-    else
+    if (l < L) {
+      D.cbuf_off[l] = cbuf_count;
+      cbuf_count += (int64_t)np * D.ncoef[l];
+    } else {
       ARENA_ALLOC(P.arena, D.cbufL, (int64_t)np * D.ncoef[l]);
-    if (r) return r;
+    }
   }
   // ---- M2M (child level l -> parent l-1) and L2L (l-1 -> l), l >= 3 ----
   for (int l = 3; l <= L; ++l) {
@@ -816,10 +839,13 @@ int build_operators(Problem& P, hipStream_t s) {
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side2, hipStreamNonBlocking));
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.bstream, hipStreamNonBlocking));
-  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_fork2, hipEventDisableTiming));
-  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_join2, hipEventDisableTiming));
-  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
-  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
+  // fork/join events order work between this device's streams only: a
+  // device-scope release suffices (no system-scope cache write-back)
+  const unsigned evf = hipEventDisableTiming | hipEventReleaseToDevice;
+  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_fork2, evf));
+  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_join2, evf));
+  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_fork, evf));
+  BEM_HIP_TRY(hipEventCreateWithFlags(&P.ev_join, evf));
   BEM_HIP_TRY(hipStreamSynchronize(s));
   return 0;
 }

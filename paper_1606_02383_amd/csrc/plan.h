@@ -29,11 +29,12 @@ struct DevArena {
 // A grouped gather-GEMM-scatter job: for pair t in group g,
 //   dst[pair_dst[t]] += op_g * src[pair_src[t]]
 // op_g is a (rows x cols) complex matrix, row-major.  Tiles enumerate
-// (group, first pair, first row) blocks.
+// (group, first pair, first row) blocks of up to ct pairs x 64 rows.
 template <typename R>
 struct GroupedOp {
   int rows = 0, cols = 0;          // output / input coefficient counts
   int n_pairs = 0, n_tiles = 0;
+  int ct = 64, ct_adj = 64;        // pairs per tile (16, 32, 64 or 128)
   int* pair_dst = nullptr;         // device, grouped by g, ascending dst within g
   int* pair_src = nullptr;
   int* tile_group = nullptr;       // device, per tile
@@ -70,6 +71,7 @@ struct PrecisionData {
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2m{};  // level l -> l-1 (index l)
   std::array<GroupedOp<R>, MAX_LEVEL + 1> l2l{};  // level l-1 -> l (index l)
   cplx<R>* cbuf = nullptr;   // per-pair M2L products, levels below the leaf level
+  std::array<int64_t, MAX_LEVEL + 1> cbuf_off{};  // offset of each level's pairs in cbuf
   cplx<R>* cbufL = nullptr;  // per-pair M2L products, leaf level (own stream)
   cplx<R>* p2m = nullptr;   // n x ncoef_L x 2 (columns: p, q), sorted order
   cplx<R>* l2p = nullptr;   // n x ncoef_L
@@ -155,9 +157,13 @@ struct Problem {
   int ev_used = 0;
 };
 
-// profiling slots: stage + 8 * precision (0: float64, 1: float32) + 16 * adjoint
-enum { ST_GATHER = 0, ST_P2P, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_FINISH, ST_M2L_RED, ST_COUNT };
-constexpr int PROF_SLOTS = 32;
+// profiling slots: stage + 16 * precision (0: float64, 1: float32) + 32 * adjoint
+enum {
+  ST_GATHER = 0, ST_P2P, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_FINISH, ST_M2L_RED,
+  ST_M2L_LEAF, ST_M2L_LEAF_RED, ST_COUNT
+};
+constexpr int PROF_SLOTS = 64;
+constexpr int prof_slot(int stage, bool f32, bool adj) { return stage + 16 * f32 + 32 * adj; }
 int prof_begin(Problem& P, hipStream_t s);                 // returns event index or -1
 int prof_end(Problem& P, int idx, int slot, hipStream_t s);
 

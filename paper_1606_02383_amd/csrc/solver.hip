@@ -913,7 +913,7 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
     }
   } sys_guard{sys};
   hipEvent_t start;
-  BEM_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  BEM_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming | hipEventReleaseToDevice));
   struct EvGuard {
     hipEvent_t e;
     ~EvGuard() { (void)hipEventDestroy(e); }
