@@ -209,7 +209,8 @@ def main():
     t_plan = time.perf_counter() - t0
     st = plan.stats()
     log(f"[bench] plan built in {t_plan:.2f} s; leaf level {st['leaf_level']}, "
-        f"orders f64 {st['order64'][2:]} f32 {st['order32'][2:]}, m2l pairs {st['n_m2l'][2:]}")
+        f"orders f64 {st['order64'][2:]} f32 {st['order32'][2:]}, m2l pairs {st['n_m2l'][2:]}, "
+        f"P2P pairs {st['n_p2p_pairs']}, schedule f64/f32 {st['schedule']}")
     b = plan.plane_wave_rhs(d)
     if args.counters:
         for prec in (1, 0):
@@ -312,7 +313,7 @@ def main():
         "config": {"workload": wl.name, "n_tri": len(T), "k": wl.k, "alpha": "i/k",
                    "rhs": "plane wave, seeded direction", "tol": wl.tol,
                    "solver": "GMRES(50), float32 inner / float64 refinement",
-                   "inner_tol": args.inner_tol, "leaf_level": L,
+                   "inner_tol": args.inner_tol, "leaf_level": L, "schedule": st["schedule"],
                    "order32": st["order32"][2:], "order64": st["order64"][2:]},
         "f64_gmres": {"matvecs": info64["matvec64"], "ms": t64_solve * 1e3,
                       "matvecs_per_s": info64["matvec64"] / t64_solve},

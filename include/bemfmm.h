@@ -129,6 +129,12 @@ typedef struct {
   double tuned_ms;         /* leaf_level < 0: float32 product time (ms) of the
                               kept leaf level; 0 otherwise                   */
   int32_t m2l_tile32[22];  /* pairs per tile of the float32 M2L per level   */
+  int32_t schedule[2];     /* stream schedule of the float64 / float32
+                              products, chosen by timing at plan creation:
+                              0 leaf-level M2L beside the upward pass, 1 it
+                              before the upward pass, 2 as 1 with the near
+                              field started after it, 3 as 0 with the near
+                              field started after the upward pass           */
 } bem_plan_stats;
 
 /* Build a plan for n_probs problems.  Uploads the meshes and runs, on the
@@ -217,6 +223,13 @@ int bem_tree_export(bem_plan* plan, int prob, void* keys, void* perm, void* stre
  * sorted order; device buffers of n_leaves entries (any may be NULL). */
 int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, void* end,
                       void* stream);
+
+/* Overrides the stream schedule of problem `prob` for precision prec
+ * (BEM_C128 / BEM_C64), see bem_plan_stats.schedule.  The schedule orders
+ * the same kernels differently on the problem's streams; products agree up
+ * to the rounding of the atomic parent accumulations.  BEM_E_INVALID for a
+ * bad index, precision or schedule (0..3). */
+int bem_plan_set_schedule(bem_plan* plan, int prob, int prec, int schedule);
 
 /* Stage timing with HIP events recorded on the call's stream.  After
  * bem_profile_start, every product records an event pair around each stage;

@@ -32,7 +32,8 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
            "bem_plane_wave_rhs", "bem_eval_field",
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
-           "bem_leaves_export", "bem_profile_start", "bem_profile_stop", "bem_last_error"]
+           "bem_leaves_export", "bem_plan_set_schedule", "bem_profile_start",
+           "bem_profile_stop", "bem_last_error"]
 
 STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
           "m2l_leaf_reduce"]
@@ -72,7 +73,8 @@ class _Stats(ctypes.Structure):
                 ("n_p2p_pairs", ctypes.c_int64), ("n_m2l", ctypes.c_int64 * 22),
                 ("order64", ctypes.c_int32 * 22), ("order32", ctypes.c_int32 * 22),
                 ("box_size", ctypes.c_double * 22), ("device_bytes", ctypes.c_int64),
-                ("tuned_ms", ctypes.c_double), ("m2l_tile32", ctypes.c_int32 * 22)]
+                ("tuned_ms", ctypes.c_double), ("m2l_tile32", ctypes.c_int32 * 22),
+                ("schedule", ctypes.c_int32 * 2)]
 
 
 _LIB = None
@@ -106,6 +108,7 @@ def load_library(path: str = LIB_PATH):
                                        vp, ctypes.POINTER(_Info), ctypes.POINTER(_Info), vp]
     lib.bem_tree_export.argtypes = [vp, i32, vp, vp, vp]
     lib.bem_leaves_export.argtypes = [vp, i32, vp, vp, vp, vp]
+    lib.bem_plan_set_schedule.argtypes = [vp, i32, i32, i32]
     lib.bem_profile_start.argtypes = [vp, i32]
     lib.bem_profile_stop.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int32)]
     lib.bem_last_error.restype = ctypes.c_char_p
@@ -225,7 +228,8 @@ class Plan:
                     n_p2p_pairs=st.n_p2p_pairs, n_m2l=list(st.n_m2l[:L + 1]),
                     order64=list(st.order64[:L + 1]), order32=list(st.order32[:L + 1]),
                     box_size=list(st.box_size[:L + 1]), device_bytes=st.device_bytes,
-                    tuned_ms=st.tuned_ms, m2l_tile32=list(st.m2l_tile32[:L + 1]))
+                    tuned_ms=st.tuned_ms, m2l_tile32=list(st.m2l_tile32[:L + 1]),
+                    schedule=list(st.schedule))
 
     # ---- products
     def matvec(self, p, q=None, prec=BEM_C128, prob=0, out=None):
@@ -343,6 +347,10 @@ class Plan:
                                        ctypes.byref(o), ctypes.byref(J), _ptr(grad), _ptr(pout),
                                        ctypes.byref(fi), ctypes.byref(ai), _stream()))
         return J.value, grad, pout, fi.as_dict(), ai.as_dict()
+
+    def set_schedule(self, schedule, prec=BEM_C128, prob=0):
+        """Override the stream schedule chosen at plan creation (0..3)."""
+        _check(_LIB.bem_plan_set_schedule(self._h, prob, prec, int(schedule)))
 
     def profile_start(self, prob=0):
         _check(_LIB.bem_profile_start(self._h, prob))

@@ -54,8 +54,8 @@ static Problem* get_prob(bem_plan* plan, int prob) {
   return plan->probs[prob];
 }
 
-// Mean time of one float32 product of a built problem (HIP events).
-static int time_f32_product(Problem& P, hipStream_t s, float* ms) {
+// Mean time of one product of a built problem (HIP events), float32 or float64.
+static int time_product(Problem& P, bool f32, hipStream_t s, float* ms) {
   c64* v = nullptr;
   c64* y = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -77,9 +77,13 @@ static int time_f32_product(Problem& P, hipStream_t s, float* ms) {
       check(hipMalloc((void**)&y, sizeof(c64) * P.n)) &&
       check(hipMemsetAsync(v, 0, sizeof(c64) * P.n, s)) && check(hipEventCreate(&e0)) &&
       check(hipEventCreate(&e1))) {
-    r = fmm_apply<float>(P, P.f32, v, nullptr, y, s);  // warm-up
+    auto apply = [&]() {
+      return f32 ? fmm_apply<float>(P, P.f32, v, nullptr, y, s)
+                 : fmm_apply<double>(P, P.f64, v, nullptr, y, s);
+    };
+    r = apply();  // warm-up
     if (!r) check(hipEventRecord(e0, s));
-    for (int t = 0; t < 5 && !r; ++t) r = fmm_apply<float>(P, P.f32, v, nullptr, y, s);
+    for (int t = 0; t < 5 && !r; ++t) r = apply();
     float t = 0.f;
     if (!r && check(hipEventRecord(e1, s)) && check(hipEventSynchronize(e1)) &&
         check(hipEventElapsedTime(&t, e0, e1)))
@@ -92,12 +96,34 @@ static int time_f32_product(Problem& P, hipStream_t s, float* ms) {
 // Autotuner: the leaf level chosen by the occupancy rule and its two
 // neighbours (within [2, finest level allowed by the near radius]) are built
 // and timed on a float32 product; the fastest plan is kept.
+// Stream schedule per precision: each candidate is timed on the problem's
+// own products and the fastest kept (the products' results do not depend on
+// the schedule).
+static int tune_schedule(Problem& P, hipStream_t s) {
+  for (int prec = 0; prec < 2; ++prec) {
+    int best = 0;
+    float best_ms = 0.f;
+    for (int c = 0; c < SCHED_COUNT; ++c) {
+      P.sched[prec] = c;
+      float ms = 0.f;
+      int r = time_product(P, prec == 1, s, &ms);
+      if (r) return r;
+      if (c == 0 || ms < best_ms) {
+        best = c;
+        best_ms = ms;
+      }
+    }
+    P.sched[prec] = best;
+  }
+  return 0;
+}
+
 template <typename Build>
 static int autotune_leaf_level(const bem_problem& q, Build& build_one, Problem** best,
                                hipStream_t s) {
   Problem* cur = *best;
   float best_ms = 0.f;
-  int r = time_f32_product(*cur, s, &best_ms);
+  int r = time_product(*cur, true, s, &best_ms);
   if (r) return r;
   const int L0 = cur->L;
   for (int L : {L0 - 1, L0 + 1}) {
@@ -110,7 +136,7 @@ static int autotune_leaf_level(const bem_problem& q, Build& build_one, Problem**
       continue;
     }
     float ms = 0.f;
-    r = time_f32_product(*cand, s, &ms);
+    r = time_product(*cand, true, s, &ms);
     if (r) {
       destroy_problem(cand);
       return r;
@@ -177,6 +203,7 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
     Problem* P = nullptr;
     int r = build_one(q, q.leaf_level > 0 ? q.leaf_level : 0, &P);
     if (!r && q.leaf_level < 0 && !P->direct) r = autotune_leaf_level(q, build_one, &P, s);
+    if (!r && !P->direct) r = tune_schedule(*P, s);
     if (r) {
       for (Problem* pp : plan->probs) destroy_problem(pp);
       delete plan;
@@ -213,6 +240,8 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
   st->device_bytes = P->arena.bytes;
   st->tuned_ms = P->tuned_ms;
   for (int l = 0; l < 22; ++l) st->m2l_tile32[l] = (l <= P->L) ? P->f32.m2l[l].ct : 0;
+  st->schedule[0] = P->sched[0];
+  st->schedule[1] = P->sched[1];
   return BEM_OK;
 }
 
@@ -366,6 +395,15 @@ int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, voi
   if (end)
     BEM_HIP_TRY(hipMemcpyAsync(end, P->box_start[P->L] + 1, sizeof(int) * nl,
                                hipMemcpyDeviceToDevice, s));
+  return BEM_OK;
+}
+
+int bem_plan_set_schedule(bem_plan* plan, int prob, int prec, int schedule) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  if (prec != BEM_C128 && prec != BEM_C64) return fail(BEM_E_INVALID, "bad precision");
+  if (schedule < 0 || schedule >= SCHED_COUNT) return fail(BEM_E_INVALID, "bad schedule");
+  P->sched[prec == BEM_C64 ? 1 : 0] = schedule;
   return BEM_OK;
 }
 

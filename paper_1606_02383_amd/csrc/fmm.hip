@@ -1073,13 +1073,14 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
+  const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   // the near field runs on the side stream, concurrently with the far field
-  hipStream_t sn = P.direct ? s : P.side;
-  if (!P.direct) {
-    BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
-    BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
-  }
-  {
+  auto launch_p2p = [&]() -> int {
+    hipStream_t sn = P.direct ? s : P.side;
+    if (!P.direct) {
+      BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
+      BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
+    }
     int e1 = prof_begin(P, sn);
     if (P.alpha.re == 0.0)
       hipLaunchKernelGGL((k_p2p<R, true>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
@@ -1092,9 +1093,12 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
     BEM_LAUNCH_CHECK();
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, false), sn);
     if (pr) return pr;
-  }
-  if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
+    if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
+    return 0;
+  };
   int r = 0;
+  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
+  if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
                        P.elem_leaf, 0, D.l2p, D.Lc[L], P.near_ptr, P.near_col, D.near_cp,
@@ -1107,13 +1111,19 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
                      D.ncoef[L], D.p2m, D.ps, D.qs, 0, D.M[L]);
   BEM_LAUNCH_CHECK();
   PROF_END(e2, ST_P2M);
-  // leaf-level M2L on its own stream: needs only the leaf multipoles
-  BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
-  BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
-  if ((r = launch_grouped<R, 0>(D.m2l[L], false, D.M[L], D.Lc[L], P.side2, D.cbufL, 0,
+  // leaf-level M2L (needs only the leaf multipoles): on its own stream
+  // (SCHED_CONCURRENT), or on this stream before the upward pass
+  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP;
+  hipStream_t sl = leaf_side ? P.side2 : s;
+  if (leaf_side) {
+    BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
+    BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
+  }
+  if ((r = launch_grouped<R, 0>(D.m2l[L], false, D.M[L], D.Lc[L], sl, D.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF)))
     return r;
-  BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
+  if (leaf_side) BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
+  if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e3);
   for (int l = L; l >= 3; --l) {
     // parents beyond the gather kernel's clear list
@@ -1123,13 +1133,14 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
     if ((r = launch_grouped<R, 1>(D.m2m[l], false, D.M[l], D.M[l - 1], s))) return r;
   }
   PROF_END(e3, ST_M2M);
+  if (sched == SCHED_P2P_AFTER_UP && (r = launch_p2p())) return r;
   if ((r = launch_coarse_m2l<R>(P, D, false, s))) return r;
   PROF_BEGIN(e5);
   for (int l = 3; l <= L; ++l) {
-    if (l == L) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
+    if (l == L && leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
     if ((r = launch_grouped<R, 2>(D.l2l[l], false, D.Lc[l - 1], D.Lc[l], s))) return r;
   }
-  if (L < 3) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
+  if (L < 3 && leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
   PROF_END(e5, ST_L2L);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);
@@ -1168,12 +1179,13 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
-  hipStream_t sn = P.direct ? s : P.side;
-  if (!P.direct) {
-    BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
-    BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
-  }
-  {
+  const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
+  auto launch_p2p = [&]() -> int {
+    hipStream_t sn = P.direct ? s : P.side;
+    if (!P.direct) {
+      BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
+      BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
+    }
     int e1 = prof_begin(P, sn);
     if (P.alpha.re == 0.0)
       hipLaunchKernelGGL((k_p2p_adj<R, true>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
@@ -1186,9 +1198,12 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
     BEM_LAUNCH_CHECK();
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, true), sn);
     if (pr) return pr;
-  }
-  if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
+    if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
+    return 0;
+  };
   int r = 0;
+  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
+  if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
                        P.elem_leaf, 0, D.p2m, D.M[L], P.neart_ptr, P.neart_row, D.neart_cp,
@@ -1202,13 +1217,19 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
                      D.ncoef[L], D.l2p, D.ps, (const cplx<R>*)nullptr, 1, D.Lc[L]);
   BEM_LAUNCH_CHECK();
   PROF_END(e2, ST_P2M);
-  // leaf-level M2L^H on its own stream: needs only the leaf adjoint locals
-  BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
-  BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
-  if ((r = launch_grouped<R, 0>(D.m2l[L], true, D.Lc[L], D.M[L], P.side2, D.cbufL, 0,
+  // leaf-level M2L^H (needs only the leaf adjoint locals): own stream or
+  // this one, as in the forward product
+  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP;
+  hipStream_t sl = leaf_side ? P.side2 : s;
+  if (leaf_side) {
+    BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
+    BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
+  }
+  if ((r = launch_grouped<R, 0>(D.m2l[L], true, D.Lc[L], D.M[L], sl, D.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF)))
     return r;
-  BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
+  if (leaf_side) BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
+  if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e5);
   for (int l = L; l >= 3; --l) {
     if (l - 1 < L - MAX_ZERO &&
@@ -1217,13 +1238,14 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
     if ((r = launch_grouped<R, 2>(D.l2l[l], true, D.Lc[l], D.Lc[l - 1], s))) return r;
   }
   PROF_END(e5, ST_L2L);
+  if (sched == SCHED_P2P_AFTER_UP && (r = launch_p2p())) return r;
   if ((r = launch_coarse_m2l<R>(P, D, true, s))) return r;
   PROF_BEGIN(e3);
   for (int l = 3; l <= L; ++l) {
-    if (l == L) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
+    if (l == L && leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
     if ((r = launch_grouped<R, 1>(D.m2m[l], true, D.M[l - 1], D.M[l], s))) return r;
   }
-  if (L < 3) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
+  if (L < 3 && leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
   PROF_END(e3, ST_M2M);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);

@@ -115,6 +115,9 @@ struct Problem {
   // tree
   int L = 0;
   float tuned_ms = 0.f;  // autotuner: float32 product time of the kept leaf level
+  // stream schedule of the products per precision (0 float64, 1 float32),
+  // chosen by timing at plan creation
+  std::array<int, 2> sched{{0, 0}};
   bool direct = false;  // leaves not wider than the near radius: direct sum, no far field
   std::array<int, MAX_LEVEL + 1> nbox{};
   std::array<uint64_t*, MAX_LEVEL + 1> box_keys{};
@@ -166,6 +169,19 @@ constexpr int PROF_SLOTS = 64;
 constexpr int prof_slot(int stage, bool f32, bool adj) { return stage + 16 * f32 + 32 * adj; }
 int prof_begin(Problem& P, hipStream_t s);                 // returns event index or -1
 int prof_end(Problem& P, int idx, int slot, hipStream_t s);
+
+// Stream schedules of one product (the near field P2P always runs on the
+// side stream, concurrently with the far field):
+//   SCHED_CONCURRENT  leaf-level M2L on a third stream, beside the upward pass
+//   SCHED_LEAF_SERIAL leaf-level M2L on the main stream before the upward pass
+//   SCHED_LEAF_FIRST  as SCHED_LEAF_SERIAL, with P2P started after it
+//   SCHED_P2P_AFTER_UP as SCHED_CONCURRENT, with P2P started after the
+//                     upward pass (whose small launches then do not wait
+//                     for compute units behind it)
+enum {
+  SCHED_CONCURRENT = 0, SCHED_LEAF_SERIAL = 1, SCHED_LEAF_FIRST = 2, SCHED_P2P_AFTER_UP = 3,
+  SCHED_COUNT
+};
 
 struct Plan {
   std::vector<Problem*> probs;
