@@ -210,7 +210,9 @@ def main():
     st = plan.stats()
     log(f"[bench] plan built in {t_plan:.2f} s; leaf level {st['leaf_level']}, "
         f"orders f64 {st['order64'][2:]} f32 {st['order32'][2:]}, m2l pairs {st['n_m2l'][2:]}, "
-        f"P2P pairs {st['n_p2p_pairs']}, schedule f64/f32 {st['schedule']}")
+        f"P2P pairs {st['n_p2p_pairs']}, schedule f64/f32 {st['schedule']}, "
+        f"P2P grid {st['p2p_grid']}, leaf M2L grid {st['m2l_grid']}, "
+        f"direct depth {st['direct_depth']}")
     b = plan.plane_wave_rhs(d)
     if args.counters:
         for prec in (1, 0):

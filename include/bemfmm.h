@@ -135,6 +135,13 @@ typedef struct {
                               before the upward pass, 2 as 1 with the near
                               field started after it, 3 as 0 with the near
                               field started after the upward pass           */
+  int32_t p2p_grid[2];     /* near-field workgroups (float64 / float32): 0 one
+                              per leaf, else a grid-stride launch of that
+                              many (chosen with the schedule)               */
+  int32_t m2l_grid[2];     /* leaf-level M2L workgroups, same convention    */
+  int32_t direct_depth[2]; /* levels above the leaves reached by direct
+                              leaf <-> ancestor translations in one launch
+                              (0: level-by-level chains); chosen by timing  */
 } bem_plan_stats;
 
 /* Build a plan for n_probs problems.  Uploads the meshes and runs, on the
@@ -224,12 +231,15 @@ int bem_tree_export(bem_plan* plan, int prob, void* keys, void* perm, void* stre
 int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, void* end,
                       void* stream);
 
-/* Overrides the stream schedule of problem `prob` for precision prec
- * (BEM_C128 / BEM_C64), see bem_plan_stats.schedule.  The schedule orders
- * the same kernels differently on the problem's streams; products agree up
- * to the rounding of the atomic parent accumulations.  BEM_E_INVALID for a
- * bad index, precision or schedule (0..3). */
-int bem_plan_set_schedule(bem_plan* plan, int prob, int prec, int schedule);
+/* Overrides the choices made by timing at plan creation for problem `prob`
+ * and precision prec (BEM_C128 / BEM_C64), see bem_plan_stats: stream
+ * schedule (0..3), near-field and leaf-level M2L grids (0: one workgroup per
+ * leaf / tile, else a grid-stride launch of that many) and direct
+ * translation depth (0 .. the depth built).  A negative value keeps the
+ * current choice.  Products agree up to rounding whatever the choice.
+ * BEM_E_INVALID for a bad index, precision or value. */
+int bem_plan_set_tuning(bem_plan* plan, int prob, int prec, int schedule, int p2p_grid,
+                        int m2l_grid, int direct_depth);
 
 /* Stage timing with HIP events recorded on the call's stream.  After
  * bem_profile_start, every product records an event pair around each stage;

@@ -32,7 +32,7 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
            "bem_plane_wave_rhs", "bem_eval_field",
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
-           "bem_leaves_export", "bem_plan_set_schedule", "bem_profile_start",
+           "bem_leaves_export", "bem_plan_set_tuning", "bem_profile_start",
            "bem_profile_stop", "bem_last_error"]
 
 STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
@@ -74,7 +74,8 @@ class _Stats(ctypes.Structure):
                 ("order64", ctypes.c_int32 * 22), ("order32", ctypes.c_int32 * 22),
                 ("box_size", ctypes.c_double * 22), ("device_bytes", ctypes.c_int64),
                 ("tuned_ms", ctypes.c_double), ("m2l_tile32", ctypes.c_int32 * 22),
-                ("schedule", ctypes.c_int32 * 2)]
+                ("schedule", ctypes.c_int32 * 2), ("p2p_grid", ctypes.c_int32 * 2),
+                ("m2l_grid", ctypes.c_int32 * 2), ("direct_depth", ctypes.c_int32 * 2)]
 
 
 _LIB = None
@@ -108,7 +109,7 @@ def load_library(path: str = LIB_PATH):
                                        vp, ctypes.POINTER(_Info), ctypes.POINTER(_Info), vp]
     lib.bem_tree_export.argtypes = [vp, i32, vp, vp, vp]
     lib.bem_leaves_export.argtypes = [vp, i32, vp, vp, vp, vp]
-    lib.bem_plan_set_schedule.argtypes = [vp, i32, i32, i32]
+    lib.bem_plan_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32, i32]
     lib.bem_profile_start.argtypes = [vp, i32]
     lib.bem_profile_stop.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int32)]
     lib.bem_last_error.restype = ctypes.c_char_p
@@ -229,7 +230,8 @@ class Plan:
                     order64=list(st.order64[:L + 1]), order32=list(st.order32[:L + 1]),
                     box_size=list(st.box_size[:L + 1]), device_bytes=st.device_bytes,
                     tuned_ms=st.tuned_ms, m2l_tile32=list(st.m2l_tile32[:L + 1]),
-                    schedule=list(st.schedule))
+                    schedule=list(st.schedule), p2p_grid=list(st.p2p_grid),
+                    m2l_grid=list(st.m2l_grid), direct_depth=list(st.direct_depth))
 
     # ---- products
     def matvec(self, p, q=None, prec=BEM_C128, prob=0, out=None):
@@ -348,9 +350,11 @@ class Plan:
                                        ctypes.byref(fi), ctypes.byref(ai), _stream()))
         return J.value, grad, pout, fi.as_dict(), ai.as_dict()
 
-    def set_schedule(self, schedule, prec=BEM_C128, prob=0):
-        """Override the stream schedule chosen at plan creation (0..3)."""
-        _check(_LIB.bem_plan_set_schedule(self._h, prob, prec, int(schedule)))
+    def set_tuning(self, prec=BEM_C128, prob=0, schedule=-1, p2p_grid=-1, m2l_grid=-1,
+                   direct_depth=-1):
+        """Override the choices timed at plan creation (negative: keep)."""
+        _check(_LIB.bem_plan_set_tuning(self._h, prob, prec, int(schedule), int(p2p_grid),
+                                        int(m2l_grid), int(direct_depth)))
 
     def profile_start(self, prob=0):
         _check(_LIB.bem_profile_start(self._h, prob))

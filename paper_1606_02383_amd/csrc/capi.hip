@@ -99,21 +99,67 @@ static int time_product(Problem& P, bool f32, hipStream_t s, float* ms) {
 // Stream schedule per precision: each candidate is timed on the problem's
 // own products and the fastest kept (the products' results do not depend on
 // the schedule).
+// Then, for the kept schedule, the grids of the two large launches that run
+// beside the far-field chain: the near field (one workgroup per leaf, or a
+// grid-stride launch of 2 or 4 per compute unit) and the leaf-level M2L (one
+// per tile, or 1 or 2 per compute unit).
+// A candidate replaces the current choice only when more than 2% faster
+// (timings of a few products vary by about that much).
 static int tune_schedule(Problem& P, hipStream_t s) {
+  int dev = 0, ncu = 0;
+  BEM_HIP_TRY(hipGetDevice(&dev));
+  BEM_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const float gain = 0.98f;
   for (int prec = 0; prec < 2; ++prec) {
+    const int nd_max = prec == 1 ? P.f32.n_direct : P.f64.n_direct;
     int best = 0;
     float best_ms = 0.f;
+    P.p2p_cap[prec] = 0;
+    P.m2l_cap[prec] = 0;
+    P.ndir[prec] = 0;
     for (int c = 0; c < SCHED_COUNT; ++c) {
       P.sched[prec] = c;
       float ms = 0.f;
       int r = time_product(P, prec == 1, s, &ms);
       if (r) return r;
-      if (c == 0 || ms < best_ms) {
+      if (c == 0 || ms < gain * best_ms) {
         best = c;
         best_ms = ms;
       }
     }
     P.sched[prec] = best;
+    // direct leaf <-> ancestor translations instead of the chains
+    if (nd_max > 0) {
+      P.ndir[prec] = nd_max;
+      float ms = 0.f;
+      int r = time_product(P, prec == 1, s, &ms);
+      if (r) return r;
+      if (ms < gain * best_ms)
+        best_ms = ms;
+      else
+        P.ndir[prec] = 0;
+    }
+    // near-field grid x leaf-level M2L grid (one or two workgroups per CU)
+    int best_p = 0, best_m = 0;
+    P.m2l_cap[prec] = 0;
+    for (int pm : {0, 2, 4})
+      for (int mm : {0, 1, 2}) {
+        if (pm == 0 && mm == 0) continue;  // timed above
+        const int pc = pm * ncu, mc = mm * ncu;
+        if (pc >= P.nbox[P.L]) continue;
+        P.p2p_cap[prec] = pc;
+        P.m2l_cap[prec] = mc;
+        float ms = 0.f;
+        int r = time_product(P, prec == 1, s, &ms);
+        if (r) return r;
+        if (ms < gain * best_ms) {
+          best_p = pc;
+          best_m = mc;
+          best_ms = ms;
+        }
+      }
+    P.p2p_cap[prec] = best_p;
+    P.m2l_cap[prec] = best_m;
   }
   return 0;
 }
@@ -242,6 +288,12 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
   for (int l = 0; l < 22; ++l) st->m2l_tile32[l] = (l <= P->L) ? P->f32.m2l[l].ct : 0;
   st->schedule[0] = P->sched[0];
   st->schedule[1] = P->sched[1];
+  st->p2p_grid[0] = P->p2p_cap[0];
+  st->p2p_grid[1] = P->p2p_cap[1];
+  st->m2l_grid[0] = P->m2l_cap[0];
+  st->m2l_grid[1] = P->m2l_cap[1];
+  st->direct_depth[0] = P->ndir[0];
+  st->direct_depth[1] = P->ndir[1];
   return BEM_OK;
 }
 
@@ -398,12 +450,19 @@ int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, voi
   return BEM_OK;
 }
 
-int bem_plan_set_schedule(bem_plan* plan, int prob, int prec, int schedule) {
+int bem_plan_set_tuning(bem_plan* plan, int prob, int prec, int schedule, int p2p_grid,
+                        int m2l_grid, int direct_depth) {
   Problem* P = get_prob(plan, prob);
   if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
   if (prec != BEM_C128 && prec != BEM_C64) return fail(BEM_E_INVALID, "bad precision");
-  if (schedule < 0 || schedule >= SCHED_COUNT) return fail(BEM_E_INVALID, "bad schedule");
-  P->sched[prec == BEM_C64 ? 1 : 0] = schedule;
+  const int i = prec == BEM_C64 ? 1 : 0;
+  const int nd_max = i ? P->f32.n_direct : P->f64.n_direct;
+  if (schedule >= SCHED_COUNT) return fail(BEM_E_INVALID, "bad schedule");
+  if (direct_depth > nd_max) return fail(BEM_E_INVALID, "direct depth beyond the one built");
+  if (schedule >= 0) P->sched[i] = schedule;
+  if (p2p_grid >= 0) P->p2p_cap[i] = p2p_grid;
+  if (m2l_grid >= 0) P->m2l_cap[i] = m2l_grid;
+  if (direct_depth >= 0) P->ndir[i] = direct_depth;
   return BEM_OK;
 }
 

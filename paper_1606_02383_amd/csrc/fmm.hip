@@ -24,6 +24,8 @@
 // with a1 = iku - u^2 and a2 = 3u^2 - k^2 - 3iku.
 #include <cmath>
 
+#include <algorithm>
+
 #include "plan.h"
 
 namespace bemfmm {
@@ -176,7 +178,7 @@ __global__ void __launch_bounds__(P2P_THREADS)
     k_p2p(const R* __restrict__ geo, int64_t n, const int* __restrict__ bstart,
           const int* __restrict__ u_ptr, const int* __restrict__ u_idx,
           const cplx<R>* __restrict__ ps, const cplx<R>* __restrict__ qs, R k, R alr, R ali,
-          int all_src, cplx<R>* __restrict__ ys) {
+          int all_src, int nleaf, cplx<R>* __restrict__ ys) {
   __shared__ R s_q[9][P2P_CHUNK];
   __shared__ R s_n[4][P2P_CHUNK];  // normal and plane offset y . n
   __shared__ R s_pq[4][P2P_CHUNK];
@@ -184,7 +186,10 @@ __global__ void __launch_bounds__(P2P_THREADS)
   __shared__ int s_nb[28], s_pre[28];
   __shared__ cplx<R> s_red[P2P_THREADS];
   const R k_turns = k * R(0.15915494309189535);  // k / (2 pi)
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  // grid-stride over the leaves (the grid may be capped below the leaf count)
+  for (int b = blockIdx.x; b < nleaf; b += gridDim.x) {
+  __syncthreads();  // the previous leaf no longer reads the shared arrays
   const int t0 = bstart[b], nT = bstart[b + 1] - t0;
   const int u0 = u_ptr[b], nu = u_ptr[b + 1] - u0;
   if (tid == 0) {
@@ -268,6 +273,7 @@ __global__ void __launch_bounds__(P2P_THREADS)
       ys[t0 + tg + tid] = s;
     }
   }
+  }
 }
 
 // Adjoint P2P: one block per leaf of output elements j; iterates over the
@@ -276,7 +282,7 @@ template <typename R, bool IMAG>
 __global__ void __launch_bounds__(P2P_THREADS)
     k_p2p_adj(const R* __restrict__ geo, int64_t n, const int* __restrict__ bstart,
               const int* __restrict__ u_ptr, const int* __restrict__ u_idx,
-              const cplx<R>* __restrict__ ysrt, R k, R alr, R ali, int all_src,
+              const cplx<R>* __restrict__ ysrt, R k, R alr, R ali, int all_src, int nleaf,
               cplx<R>* __restrict__ us, cplx<R>* __restrict__ ws) {
   __shared__ R s_x[6][P2P_CHUNK];
   __shared__ R s_y[2][P2P_CHUNK];
@@ -284,7 +290,10 @@ __global__ void __launch_bounds__(P2P_THREADS)
   __shared__ int s_nb[28], s_pre[28];
   __shared__ cplx<R> s_red[2][P2P_THREADS];
   const R k_turns = k * R(0.15915494309189535);  // k / (2 pi)
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  // grid-stride over the leaves (the grid may be capped below the leaf count)
+  for (int b = blockIdx.x; b < nleaf; b += gridDim.x) {
+  __syncthreads();  // the previous leaf no longer reads the shared arrays
   const int t0 = bstart[b], nT = bstart[b + 1] - t0;
   const int u0 = u_ptr[b], nu = u_ptr[b + 1] - u0;
   if (tid == 0) {
@@ -367,6 +376,7 @@ __global__ void __launch_bounds__(P2P_THREADS)
       us[t0 + tg + tid] = cscale(su, wj);
       ws[t0 + tg + tid] = cscale(sw, wj);
     }
+  }
   }
 }
 
@@ -500,6 +510,7 @@ constexpr int MAX_JOBS = 8;
 template <typename R>
 struct GemmBatch {
   int n;
+  int ntiles;  // tile0[n]: the grid strides over them (grid <= ntiles, multiple of 8)
   int tile0[MAX_JOBS + 1];
   GemmJobDev<R> job[MAX_JOBS];
 };
@@ -515,7 +526,8 @@ __device__ __forceinline__ T select_job(const T (&arr)[N], int q) {
   return v;
 }
 
-// KIND: 0 M2L (per-pair output), 1 M2M, 2 L2L (the latter two add into dst)
+// KIND: 0 M2L (per-pair output), 1 M2M, 2 L2L, 3 leaf -> ancestor, 4
+// ancestor -> leaf (the others add into dst)
 template <typename R, int CT, bool ADJ, int KIND>
 __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
     k_grouped_gemm(const GemmBatch<R> batch) {
@@ -536,7 +548,14 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
   // XCD-aware order: workgroups go to the 8 XCDs round-robin (block b on XCD
   // b % 8), so give each XCD a contiguous range of tiles; consecutive tiles
   // share their group's matrix, which then stays in that XCD's L2.
-  const int nt = gridDim.x, xcd = blockIdx.x & 7, slot_in_xcd = blockIdx.x >> 3;
+  // Tiles are visited with a grid stride (a capped grid keeps room on the
+  // compute units for work on other streams).  Virtual block vb =
+  // blockIdx + i * gridDim keeps the XCD of blockIdx as the grid is a
+  // multiple of 8 (or the whole tile count).
+  const int nt = batch.ntiles;
+  for (int vb = blockIdx.x; vb < nt; vb += gridDim.x) {
+  __syncthreads();  // the previous tile no longer reads the shared arrays
+  const int xcd = vb & 7, slot_in_xcd = vb >> 3;
   const int gtile = xcd * (nt >> 3) + min(xcd, nt & 7) + slot_in_xcd;
   int q = 0;
 #pragma unroll
@@ -710,6 +729,7 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
     } else {
       atomic_cadd(&dst[(int64_t)s_dst[cc] * out_rows + r0 + row], v);
     }
+  }
   }
 }
 
@@ -932,7 +952,7 @@ static int launch_gemm_ct(const GemmBatch<R>& b, int ct, int nt, hipStream_t s) 
 template <typename R, int KIND>
 static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStream_t s,
                                int accumulate = 0, Problem* prof = nullptr,
-                               int st_gemm = ST_M2L) {
+                               int st_gemm = ST_M2L, int grid_cap = 0) {
   if (nj <= 0) return 0;
   if (nj > MAX_JOBS) {
     set_error("too many grouped products in one launch");
@@ -980,11 +1000,13 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
     nbox += adj ? op.n_red_adj : op.n_red;
   }
   b.tile0[nj] = nt;
+  b.ntiles = nt;
   rb.box0[nj] = nbox;
   if (nt > 0) {
     int evg = prof ? prof_begin(*prof, s) : -1;
-    int r = adj ? launch_gemm_ct<R, true, KIND>(b, ct, nt, s)
-                : launch_gemm_ct<R, false, KIND>(b, ct, nt, s);
+    const int grid = (grid_cap > 0 && grid_cap < nt) ? (grid_cap & ~7) : nt;
+    int r = adj ? launch_gemm_ct<R, true, KIND>(b, ct, grid > 0 ? grid : nt, s)
+                : launch_gemm_ct<R, false, KIND>(b, ct, grid > 0 ? grid : nt, s);
     if (r) return r;
     if (prof) {
       int pr = prof_end(*prof, evg, prof_slot(st_gemm, sizeof(R) == 4, adj), s);
@@ -1008,9 +1030,9 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
 template <typename R, int KIND>
 static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, cplx<R>* dst,
                           hipStream_t s, cplx<R>* cbuf = nullptr, int accumulate = 0,
-                          Problem* prof = nullptr, int st_gemm = ST_M2L) {
+                          Problem* prof = nullptr, int st_gemm = ST_M2L, int grid_cap = 0) {
   GemmJob<R> j{&op, src, dst, cbuf};
-  return launch_grouped_jobs<R, KIND>(&j, 1, adj, s, accumulate, prof, st_gemm);
+  return launch_grouped_jobs<R, KIND>(&j, 1, adj, s, accumulate, prof, st_gemm, grid_cap);
 }
 
 // M2L of the levels 2 .. L-1 (all inputs ready once the upward pass is done):
@@ -1031,6 +1053,66 @@ static int launch_coarse_m2l(Problem& P, PrecisionData<R>& D, bool adj, hipStrea
       jobs[nj].cbuf = D.cbuf + D.cbuf_off[l];
     }
     int r = launch_grouped_jobs<R, 0>(jobs, nj, adj, s, 0, P.prof_on ? &P : nullptr);
+    if (r) return r;
+  }
+  return 0;
+}
+
+// Upward pass: leaf multipoles to the n_direct levels above in one launch
+// (KIND 3), then the level-by-level chain above them.  Adjoint: the mirror
+// image for the adjoint locals (direct L2L^H, then the L2L^H chain).
+template <typename R>
+static int upward_pass(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t s) {
+  const int L = P.L, nd = std::min(D.n_direct, P.ndir[sizeof(R) == 4]);
+  GemmJob<R> jobs[MAX_JOBS];
+  for (int d = 1; d <= nd; ++d) {
+    if (adj)
+      jobs[d - 1] = GemmJob<R>{&D.l2l_dir[d], D.Lc[L], D.Lc[L - d], nullptr};
+    else
+      jobs[d - 1] = GemmJob<R>{&D.m2m_dir[d], D.M[L], D.M[L - d], nullptr};
+  }
+  int r = 0;
+  if (nd > 0) {
+    r = adj ? launch_grouped_jobs<R, 4>(jobs, nd, true, s) : launch_grouped_jobs<R, 3>(jobs, nd, false, s);
+    if (r) return r;
+  }
+  for (int l = L - nd; l >= 3; --l) {
+    cplx<R>* par = adj ? D.Lc[l - 1] : D.M[l - 1];
+    // parents beyond the gather kernel's clear list
+    if (l - 1 < L - MAX_ZERO && (r = zero<R>(par, (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s)))
+      return r;
+    r = adj ? launch_grouped<R, 2>(D.l2l[l], true, D.Lc[l], par, s)
+            : launch_grouped<R, 1>(D.m2m[l], false, D.M[l], par, s);
+    if (r) return r;
+  }
+  return 0;
+}
+
+// Downward pass: the level-by-level chain down to level L - n_direct (totals
+// there), then all n_direct levels to the leaves in one launch (KIND 4,
+// after `leaf_ready`: the leaf-level M2L result is written on another
+// stream).  Adjoint: the mirror image (M2M^H chain, direct M2M^H).
+template <typename R>
+static int downward_pass(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t s,
+                         hipEvent_t leaf_ready) {
+  const int L = P.L, nd = std::min(D.n_direct, P.ndir[sizeof(R) == 4]);
+  int r = 0;
+  for (int l = 3; l <= L - nd; ++l) {
+    if (l == L && leaf_ready) BEM_HIP_TRY(hipStreamWaitEvent(s, leaf_ready, 0));
+    r = adj ? launch_grouped<R, 1>(D.m2m[l], true, D.M[l - 1], D.M[l], s)
+            : launch_grouped<R, 2>(D.l2l[l], false, D.Lc[l - 1], D.Lc[l], s);
+    if (r) return r;
+  }
+  if ((nd > 0 || L < 3) && leaf_ready) BEM_HIP_TRY(hipStreamWaitEvent(s, leaf_ready, 0));
+  if (nd > 0) {
+    GemmJob<R> jobs[MAX_JOBS];
+    for (int d = 1; d <= nd; ++d) {
+      if (adj)
+        jobs[d - 1] = GemmJob<R>{&D.m2m_dir[d], D.M[L - d], D.M[L], nullptr};
+      else
+        jobs[d - 1] = GemmJob<R>{&D.l2l_dir[d], D.Lc[L - d], D.Lc[L], nullptr};
+    }
+    r = adj ? launch_grouped_jobs<R, 3>(jobs, nd, true, s) : launch_grouped_jobs<R, 4>(jobs, nd, false, s);
     if (r) return r;
   }
   return 0;
@@ -1074,6 +1156,8 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
+  const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
+  const int p2p_grid = (cap > 0 && cap < nleaf) ? cap : nleaf;
   // the near field runs on the side stream, concurrently with the far field
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
@@ -1083,13 +1167,13 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
     }
     int e1 = prof_begin(P, sn);
     if (P.alpha.re == 0.0)
-      hipLaunchKernelGGL((k_p2p<R, true>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
+      hipLaunchKernelGGL((k_p2p<R, true>), dim3(p2p_grid), dim3(P2P_THREADS), 0, sn,
                          (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr,
-                         ali, (int)P.direct, D.ys);
+                         ali, (int)P.direct, nleaf, D.ys);
     else
-      hipLaunchKernelGGL((k_p2p<R, false>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
+      hipLaunchKernelGGL((k_p2p<R, false>), dim3(p2p_grid), dim3(P2P_THREADS), 0, sn,
                          (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr,
-                         ali, (int)P.direct, D.ys);
+                         ali, (int)P.direct, nleaf, D.ys);
     BEM_LAUNCH_CHECK();
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, false), sn);
     if (pr) return pr;
@@ -1120,27 +1204,18 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
     BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   }
   if ((r = launch_grouped<R, 0>(D.m2l[L], false, D.M[L], D.Lc[L], sl, D.cbufL, 0,
-                                P.prof_on ? &P : nullptr, ST_M2L_LEAF)))
+                                P.prof_on ? &P : nullptr, ST_M2L_LEAF,
+                                P.m2l_cap[sizeof(R) == 4])))
     return r;
   if (leaf_side) BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e3);
-  for (int l = L; l >= 3; --l) {
-    // parents beyond the gather kernel's clear list
-    if (l - 1 < L - MAX_ZERO &&
-        (r = zero<R>(D.M[l - 1], (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s)))
-      return r;
-    if ((r = launch_grouped<R, 1>(D.m2m[l], false, D.M[l], D.M[l - 1], s))) return r;
-  }
+  if ((r = upward_pass<R>(P, D, false, s))) return r;
   PROF_END(e3, ST_M2M);
   if (sched == SCHED_P2P_AFTER_UP && (r = launch_p2p())) return r;
   if ((r = launch_coarse_m2l<R>(P, D, false, s))) return r;
   PROF_BEGIN(e5);
-  for (int l = 3; l <= L; ++l) {
-    if (l == L && leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
-    if ((r = launch_grouped<R, 2>(D.l2l[l], false, D.Lc[l - 1], D.Lc[l], s))) return r;
-  }
-  if (L < 3 && leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
+  if ((r = downward_pass<R>(P, D, false, s, leaf_side ? P.ev_join2 : nullptr))) return r;
   PROF_END(e5, ST_L2L);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);
@@ -1180,6 +1255,8 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
+  const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
+  const int p2p_grid = (cap > 0 && cap < nleaf) ? cap : nleaf;
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
     if (!P.direct) {
@@ -1188,13 +1265,13 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
     }
     int e1 = prof_begin(P, sn);
     if (P.alpha.re == 0.0)
-      hipLaunchKernelGGL((k_p2p_adj<R, true>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
+      hipLaunchKernelGGL((k_p2p_adj<R, true>), dim3(p2p_grid), dim3(P2P_THREADS), 0, sn,
                          (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali,
-                         (int)P.direct, D.ys, D.ys2);
+                         (int)P.direct, nleaf, D.ys, D.ys2);
     else
-      hipLaunchKernelGGL((k_p2p_adj<R, false>), dim3(nleaf), dim3(P2P_THREADS), 0, sn,
+      hipLaunchKernelGGL((k_p2p_adj<R, false>), dim3(p2p_grid), dim3(P2P_THREADS), 0, sn,
                          (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali,
-                         (int)P.direct, D.ys, D.ys2);
+                         (int)P.direct, nleaf, D.ys, D.ys2);
     BEM_LAUNCH_CHECK();
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, true), sn);
     if (pr) return pr;
@@ -1226,26 +1303,18 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
     BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   }
   if ((r = launch_grouped<R, 0>(D.m2l[L], true, D.Lc[L], D.M[L], sl, D.cbufL, 0,
-                                P.prof_on ? &P : nullptr, ST_M2L_LEAF)))
+                                P.prof_on ? &P : nullptr, ST_M2L_LEAF,
+                                P.m2l_cap[sizeof(R) == 4])))
     return r;
   if (leaf_side) BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e5);
-  for (int l = L; l >= 3; --l) {
-    if (l - 1 < L - MAX_ZERO &&
-        (r = zero<R>(D.Lc[l - 1], (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s)))
-      return r;
-    if ((r = launch_grouped<R, 2>(D.l2l[l], true, D.Lc[l], D.Lc[l - 1], s))) return r;
-  }
+  if ((r = upward_pass<R>(P, D, true, s))) return r;
   PROF_END(e5, ST_L2L);
   if (sched == SCHED_P2P_AFTER_UP && (r = launch_p2p())) return r;
   if ((r = launch_coarse_m2l<R>(P, D, true, s))) return r;
   PROF_BEGIN(e3);
-  for (int l = 3; l <= L; ++l) {
-    if (l == L && leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
-    if ((r = launch_grouped<R, 1>(D.m2m[l], true, D.M[l - 1], D.M[l], s))) return r;
-  }
-  if (L < 3 && leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
+  if ((r = downward_pass<R>(P, D, true, s, leaf_side ? P.ev_join2 : nullptr))) return r;
   PROF_END(e3, ST_M2M);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);

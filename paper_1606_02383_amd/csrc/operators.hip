@@ -497,6 +497,23 @@ __global__ void k_octant_pairs(const uint64_t* __restrict__ ckeys, const int* __
   code[c] = (int)(ckeys[c] & 7);
 }
 
+// (ancestor at `depth` levels up, leaf, position code of the leaf inside the
+// ancestor: the low 3 depth bits of its Morton key)
+struct ParentChain {
+  const int* par[MAX_DIRECT];  // par[i]: parent index of the boxes of level L - i
+};
+__global__ void k_ancestor_pairs(const uint64_t* __restrict__ leaf_keys, const ParentChain pc,
+                                 int depth, int nleaf, int* __restrict__ dst,
+                                 int* __restrict__ src, int* __restrict__ code) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  int a = b;
+  for (int i = 0; i < depth; ++i) a = pc.par[i][a];
+  dst[b] = a;
+  src[b] = b;
+  code[b] = (int)(leaf_keys[b] & ((1ull << (3 * depth)) - 1));
+}
+
 // Group (dst, src, code) pairs by code (stable by dst), upload tiles for the
 // forward and adjoint directions.  code < ngroups.
 template <typename R>
@@ -737,6 +754,64 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     if (r) return r;
     r = finish_grouped<R>(ll, s0, d0, c0, nb, 8, slot, P.arena, scratch, s);
     if (r) return r;
+  }
+  // ---- direct translations between the leaves and the MAX_DIRECT levels
+  // above them (leaf -> ancestor for the upward pass, ancestor -> leaf for
+  // the downward one): one launch per pass instead of a chain of dependent
+  // level-by-level launches.  A depth is used while its 8^depth operators
+  // stay within DIRECT_BYTES; the levels above are chained. ----
+  D.n_direct = 0;
+  for (int d = 1; d <= MAX_DIRECT && L - d >= 2; ++d) {
+    const int a = L - d, ng = 1 << (3 * d), pL = D.order[L], pa = D.order[a];
+    const int64_t bytes = 2 * (int64_t)ng * D.ncoef[L] * D.ncoef[a] * (int64_t)sizeof(cplx<R>);
+    if (bytes > DIRECT_BYTES) break;
+    const int nb = P.nbox[L];
+    int *d0, *s0, *c0;
+    ARENA_ALLOC(scratch, d0, nb);
+    ARENA_ALLOC(scratch, s0, nb);
+    ARENA_ALLOC(scratch, c0, nb);
+    ParentChain pcn{};
+    for (int i = 0; i < d; ++i) pcn.par[i] = P.box_parent[L - i];
+    hipLaunchKernelGGL(k_ancestor_pairs, dim3(ceil_div(nb, 256)), dim3(256), 0, s, P.box_keys[L],
+                       pcn, d, nb, d0, s0, c0);
+    BEM_LAUNCH_CHECK();
+    std::vector<int> slot(ng);
+    std::vector<double> tv_up, tv_down;
+    for (int c = 0; c < ng; ++c) {
+      slot[c] = c;
+      // leaf centre minus ancestor centre: the steps from level a + 1 down
+      double o[3] = {0, 0, 0};
+      for (int i = 1; i <= d; ++i) {
+        const int dig = (c >> (3 * (d - i))) & 7;
+        for (int ax = 0; ax < 3; ++ax)
+          o[ax] += (((dig >> (2 - ax)) & 1) ? 0.5 : -0.5) * P.h[a + i];
+      }
+      for (int ax = 0; ax < 3; ++ax) {
+        tv_up.push_back(-o[ax]);   // ancestor - leaf
+        tv_down.push_back(o[ax]);  // leaf - ancestor
+      }
+    }
+    GroupedOp<R>& mu = D.m2m_dir[d];  // M~_anc += (1/f^(a)) (R|R) f^(L) M~_leaf
+    mu.rows = D.ncoef[a];
+    mu.cols = D.ncoef[L];
+    mu.n_slots = ng;
+    std::vector<double> rs = coef_scale(pa, k * P.h[a], -1), cs = coef_scale(pL, k * P.h[L], +1);
+    int r = make_translations<R>(P, ng, tv_up, 0, pL, pa, rs, cs, &mu.mats, scratch, s);
+    if (r) return r;
+    // few pairs per position code: 16-pair tiles (all depths share a launch)
+    r = finish_grouped<R>(mu, d0, s0, c0, nb, ng, slot, P.arena, scratch, s, 16);
+    if (r) return r;
+    GroupedOp<R>& ld = D.l2l_dir[d];  // L~_leaf += f^(L) (R|R) (1/f^(a)) L~_anc
+    ld.rows = D.ncoef[L];
+    ld.cols = D.ncoef[a];
+    ld.n_slots = ng;
+    rs = coef_scale(pL, k * P.h[L], +1);
+    cs = coef_scale(pa, k * P.h[a], -1);
+    r = make_translations<R>(P, ng, tv_down, 0, pa, pL, rs, cs, &ld.mats, scratch, s);
+    if (r) return r;
+    r = finish_grouped<R>(ld, s0, d0, c0, nb, ng, slot, P.arena, scratch, s, 16);
+    if (r) return r;
+    D.n_direct = d;
   }
   ARENA_ALLOC(P.arena, D.cbuf, cbuf_count);
   // ---- P2M and L2P per element ----

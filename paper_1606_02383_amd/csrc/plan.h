@@ -17,6 +17,8 @@ constexpr int MAX_LEVEL = 21;
 constexpr int N_OFFSETS = 343;   // 7^3 translation-vector slots, (dx+3)*49+(dy+3)*7+(dz+3)
 constexpr int NEAR_RULE = 8;     // near-singular rule: 8 x 8 collapsed Gauss points
 constexpr int SELF_RULE = 64;    // self terms: Gauss points per edge angle
+constexpr int MAX_DIRECT = 3;    // levels above the leaves reached by direct translations
+constexpr int64_t DIRECT_BYTES = int64_t(1) << 30;  // operator memory cap per direct depth
 
 // Device allocation registry: every buffer a problem owns.
 struct DevArena {
@@ -70,6 +72,10 @@ struct PrecisionData {
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2l{};
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2m{};  // level l -> l-1 (index l)
   std::array<GroupedOp<R>, MAX_LEVEL + 1> l2l{};  // level l-1 -> l (index l)
+  // direct translations leaf <-> level L - d for d = 1 .. n_direct (index d)
+  int n_direct = 0;
+  std::array<GroupedOp<R>, MAX_DIRECT + 1> m2m_dir{};  // leaf -> level L - d
+  std::array<GroupedOp<R>, MAX_DIRECT + 1> l2l_dir{};  // level L - d -> leaf
   cplx<R>* cbuf = nullptr;   // per-pair M2L products, levels below the leaf level
   std::array<int64_t, MAX_LEVEL + 1> cbuf_off{};  // offset of each level's pairs in cbuf
   cplx<R>* cbufL = nullptr;  // per-pair M2L products, leaf level (own stream)
@@ -118,6 +124,14 @@ struct Problem {
   // stream schedule of the products per precision (0 float64, 1 float32),
   // chosen by timing at plan creation
   std::array<int, 2> sched{{0, 0}};
+  // workgroups of the near-field kernel per precision (0: one per leaf; else
+  // a grid-stride launch of that many, leaving room for the far-field chain)
+  std::array<int, 2> p2p_cap{{0, 0}};
+  // workgroups of the leaf-level M2L launch (0: one per tile, else that many)
+  std::array<int, 2> m2l_cap{{0, 0}};
+  // depth of the direct leaf <-> ancestor translations used (<= n_direct of
+  // the precision; 0: level-by-level chains only)
+  std::array<int, 2> ndir{{0, 0}};
   bool direct = false;  // leaves not wider than the near radius: direct sum, no far field
   std::array<int, MAX_LEVEL + 1> nbox{};
   std::array<uint64_t*, MAX_LEVEL + 1> box_keys{};

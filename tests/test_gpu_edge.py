@@ -121,32 +121,48 @@ def test_multiple_rhs_columns():
         assert np.allclose(Y[c], y, rtol=0, atol=1e-12 * np.abs(y).max())
 
 
-def test_every_stream_schedule_gives_the_same_products():
-    """Each stream schedule runs the same kernels in another order; forward
-    and adjoint products agree to rounding (atomic parent sums)."""
+def test_every_tuning_choice_gives_the_same_products():
+    """Stream schedules, capped grids and direct leaf <-> ancestor
+    translations run the same arithmetic in another order or another
+    factorisation: forward and adjoint products agree to rounding and to the
+    expansion truncation."""
     import torch
     bem = _lib()
-    V, T = icosphere(4)
+    V, T = icosphere(5)
     plan = bem.Plan(bem.Problem(V, T, 4.0))
     st = plan.stats()
-    _log(f"case: stream schedules (tuned f64/f32 {st['schedule']})")
+    _log(f"case: tuning choices (tuned schedule {st['schedule']} grids {st['p2p_grid']} "
+         f"{st['m2l_grid']} direct {st['direct_depth']}, leaf level {st['leaf_level']})")
     assert all(0 <= c < 4 for c in st["schedule"])
     rng = np.random.default_rng(17)
     p = torch.from_numpy(complex_normal(rng, len(T)))
     q = torch.from_numpy(complex_normal(rng, len(T)))
     ref = {}
-    for sched in range(4):
-        for prec, tol in ((0, 1e-12), (1, 1e-5)):
-            plan.set_schedule(sched, prec=prec)
+    choices = [dict(schedule=c, p2p_grid=0, m2l_grid=0, direct_depth=0) for c in range(4)]
+    choices += [dict(schedule=0, p2p_grid=512, m2l_grid=256, direct_depth=0),
+                dict(schedule=3, p2p_grid=0, m2l_grid=0, direct_depth=3),
+                dict(schedule=1, p2p_grid=1024, m2l_grid=0, direct_depth=2)]
+    for ch in choices:
+        for prec in (0, 1):
+            ch2 = dict(ch)
+            # the depth built may be smaller on a shallow tree
+            built = 3 if st["leaf_level"] >= 5 else max(0, st["leaf_level"] - 2)
+            ch2["direct_depth"] = min(ch2["direct_depth"], built)
+            plan.set_tuning(prec=prec, **ch2)
             y = plan.matvec(p, q, prec=prec).cpu().numpy()
             u, w = plan.matvec_adjoint(p, prec=prec)
             u, w = u.cpu().numpy(), w.cpu().numpy()
             if prec not in ref:
-                ref[prec] = (y, u, w)
+                ref[prec] = (ch2["direct_depth"], (y, u, w))
                 continue
-            for a, b in zip((y, u, w), ref[prec]):
-                e = np.linalg.norm(a - b) / np.linalg.norm(b)
-                _log(f"  schedule {sched} prec {prec}: {e:.1e}")
-                assert e < tol
+            same = ch2["direct_depth"] == ref[prec][0]
+            # same factorisation: rounding only; other depth: truncation too
+            tol = (1e-12 if same else 1e-6) if prec == 0 else (1e-6 if same else 5e-5)
+            errs = [np.linalg.norm(a - b) / np.linalg.norm(b)
+                    for a, b in zip((y, u, w), ref[prec][1])]
+            _log(f"  {ch2} prec {prec}: {max(errs):.1e} (tol {tol:.0e})")
+            assert max(errs) < tol
     with pytest.raises(RuntimeError, match="INVALID"):
-        plan.set_schedule(4)
+        plan.set_tuning(schedule=4)
+    with pytest.raises(RuntimeError, match="INVALID"):
+        plan.set_tuning(direct_depth=9)
