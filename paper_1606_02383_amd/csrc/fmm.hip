@@ -26,6 +26,7 @@
 
 #include <algorithm>
 
+#include "phase64.h"
 #include "plan.h"
 
 namespace bemfmm {
@@ -34,7 +35,8 @@ constexpr double INV_4PI_D = 0.07957747154594767;
 
 // e^{i k r}: float32 uses the hardware sine/cosine, which take the phase in
 // turns (k r / 2 pi; here a few radians at most, absolute error ~1e-6, far
-// below the float32 operator's tolerance); float64 the library sincos.
+// below the float32 operator's tolerance); float64 the reduced Taylor
+// evaluation of phase64.h (error < 2e-16, branch-free).
 template <typename R>
 __device__ __forceinline__ void phase(R r, R k, R k_turns, R* s, R* c);
 template <>
@@ -45,7 +47,7 @@ __device__ __forceinline__ void phase<float>(float r, float, float k_turns, floa
 }
 template <>
 __device__ __forceinline__ void phase<double>(double r, double k, double, double* s, double* c) {
-  sincos(k * r, s, c);
+  sincos_reduced(k * r, s, c);
 }
 // 1/sqrt(x) for x well inside the normal range (squared distances between
 // distinct rule points and collocation points)
@@ -55,9 +57,14 @@ template <>
 __device__ __forceinline__ float rsqrt_r<float>(float x) {
   return __builtin_amdgcn_rsqf(x);
 }
+// float64: hardware estimate refined by two Newton steps
+// y <- y + (y/2)(1 - x y^2) (each doubles the correct bits)
 template <>
 __device__ __forceinline__ double rsqrt_r<double>(double x) {
-  return 1.0 / sqrt(x);
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
 }
 
 // Burton-Miller coefficients (sp, sq) of a target point x (normal n_x)

@@ -445,19 +445,22 @@ static void make_tiles(const std::vector<int>& gstart, int rows, int CT, int RT,
 constexpr int GEMM_RT = 64;  // output rows per tile
 
 // Pair-tile width of a grouped product: the widest of the supported widths
-// (128 is float32 only) that still gives at least ~4 tiles per compute unit,
-// else the narrowest.  Narrow tiles keep sparse groups (few pairs per
-// translation vector, coarse levels) from multiplying mostly-zero columns
-// and spread small launches over more compute units.
+// (128 is float32 only) that still gives at least ~4 tiles per compute unit
+// and fills its tiles at least half on average, else the narrowest.  Narrow
+// tiles keep sparse groups (few pairs per translation vector, coarse levels)
+// from multiplying mostly-zero columns and spread small launches over more
+// compute units.
 static int pick_pair_tile(const std::vector<int>& gstart, int rows, bool f32) {
   const int widths[4] = {128, 64, 32, 16};
   const int row_tiles = (rows + GEMM_RT - 1) / GEMM_RT;
   for (int w : widths) {
     if (w == 128 && !f32) continue;
-    int64_t tiles = 0;
-    for (size_t g = 0; g + 1 < gstart.size(); ++g)
-      tiles += (int64_t)((gstart[g + 1] - gstart[g] + w - 1) / w) * row_tiles;
-    if (tiles >= 1024) return w;
+    int64_t col_tiles = 0, pairs = 0;
+    for (size_t g = 0; g + 1 < gstart.size(); ++g) {
+      col_tiles += (gstart[g + 1] - gstart[g] + w - 1) / w;
+      pairs += gstart[g + 1] - gstart[g];
+    }
+    if (col_tiles * row_tiles >= 1024 && 2 * pairs >= col_tiles * w) return w;
   }
   return 16;
 }
