@@ -132,7 +132,7 @@ __device__ __forceinline__ void bm_elem(R xx, R xy, R xz, R nxx, R nxy, R nxz, c
 // ---------------------------------------------------------------------------
 // Buffers cleared by the first kernel of a product (targets of atomic
 // accumulation further down the chain), folded into it to save launches.
-constexpr int MAX_ZERO = 8;
+constexpr int MAX_ZERO = MAX_LEVEL;  // every level above the leaves
 template <typename R>
 struct ZeroList {
   int n;
@@ -168,11 +168,6 @@ __global__ void k_gather_in(const c64* __restrict__ p, const c64* __restrict__ q
   q64[i] = b;
 }
 
-template <typename R>
-__global__ void k_zero(cplx<R>* __restrict__ a, int64_t cnt) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < cnt) a[i] = mk<R>(R(0), R(0));
-}
 
 // ---------------------------------------------------------------------------
 // P2P: one block per leaf; sources of the U list staged in LDS in chunks
@@ -1084,10 +1079,7 @@ static int upward_pass(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t s)
     if (r) return r;
   }
   for (int l = L - nd; l >= 3; --l) {
-    cplx<R>* par = adj ? D.Lc[l - 1] : D.M[l - 1];
-    // parents beyond the gather kernel's clear list
-    if (l - 1 < L - MAX_ZERO && (r = zero<R>(par, (int64_t)P.nbox[l - 1] * D.ncoef[l - 1], s)))
-      return r;
+    cplx<R>* par = adj ? D.Lc[l - 1] : D.M[l - 1];  // cleared by the gather kernel
     r = adj ? launch_grouped<R, 2>(D.l2l[l], true, D.Lc[l], par, s)
             : launch_grouped<R, 1>(D.m2m[l], false, D.M[l], par, s);
     if (r) return r;
@@ -1140,13 +1132,6 @@ static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, bool adj) {
   return z;
 }
 
-template <typename R>
-static int zero(cplx<R>* a, int64_t cnt, hipStream_t s) {
-  if (cnt <= 0) return 0;
-  hipLaunchKernelGGL(k_zero<R>, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, a, cnt);
-  BEM_LAUNCH_CHECK();
-  return 0;
-}
 
 template <typename R>
 int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* y,

@@ -166,3 +166,37 @@ def test_every_tuning_choice_gives_the_same_products():
         plan.set_tuning(schedule=4)
     with pytest.raises(RuntimeError, match="INVALID"):
         plan.set_tuning(direct_depth=9)
+
+
+def test_deep_tree_hybrid_passes():
+    """327680-element sphere with leaf level 6 (four levels above the
+    leaves): the upward/downward passes mix direct translations (depth
+    1..3) with level chains above them; every depth must give the oracle's
+    rows, and the adjoint must pass the dot test."""
+    import torch
+    bem = _lib()
+    V, T = icosphere(7)
+    k = 2.0
+    plan = bem.Plan(bem.Problem(V, T, k, leaf_cap=16, leaf_level=6))
+    st = plan.stats()
+    _log(f"case: deep tree, n={len(T)}, leaf level {st['leaf_level']}")
+    assert st["leaf_level"] == 6
+    g = obem.Geometry(V, T)
+    rng = np.random.default_rng(6)
+    p, q = complex_normal(rng, len(T)), complex_normal(rng, len(T))
+    rows = np.sort(rng.choice(len(T), 16, replace=False))
+    ref = obem.matvec(g, k, 1j / k, p, q, rows=rows, block=16)
+    yv = complex_normal(rng, len(T))
+    for depth in (0, 1, 2, 3):
+        for prec, tol in ((0, 1e-6), (1, 1e-4)):
+            plan.set_tuning(prec=prec, direct_depth=depth)
+            y = plan.matvec(torch.from_numpy(p), torch.from_numpy(q), prec=prec).cpu().numpy()
+            e = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
+            u, w = plan.matvec_adjoint(torch.from_numpy(yv), prec=prec)
+            u, w = u.cpu().numpy(), w.cpu().numpy()
+            lhs = np.vdot(yv, y)
+            rhs = np.vdot(u, p) + np.vdot(w, q)
+            dot = abs(lhs - rhs) / abs(lhs)
+            _log(f"  depth {depth} prec {prec}: rows {e:.2e}, dot test {dot:.1e}")
+            assert e < tol
+            assert dot < (1e-12 if prec == 0 else 1e-5)
