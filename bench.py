@@ -118,7 +118,8 @@ def run_batch(args):
     for i, (lvl, k) in enumerate(combos):
         st = plan.stats(i)
         log(f"[bench] problem {i}: level {lvl} n={st['n_tri']} k={k} leaf level "
-            f"{st['leaf_level']} ({st['tuned_ms']:.3f} ms per float32 product)")
+            f"{st['leaf_level']} ({st['tuned_ms']:.3f} ms per float32 product), schedule "
+            f"{st['schedule']}, direct depth {st['direct_depth']}")
     log(f"[bench] plan of {len(combos)} problems built (with tuning) in {t_plan:.2f} s")
     opts = bem.GmresOptions(tol=1e-6, restart=50, mode=1, inner_tol=args.inner_tol)
     systems = []

@@ -127,6 +127,30 @@ __device__ __forceinline__ void bm_elem(R xx, R xy, R xz, R nxx, R nxy, R nxz, c
   sq = mk<R>(sqr, sqi);
 }
 
+// A launch may cover several problems or levels ("jobs", at most MAX_JOBS):
+// work item v belongs to the job q with first[q] <= v < first[q + 1].
+constexpr int MAX_JOBS = 8;
+
+// the job of a (workgroup-uniform) index, selected without dynamic indexing
+// of the kernel argument
+template <typename T, int N>
+__device__ __forceinline__ T select_job(const T (&arr)[N], int q) {
+  T v = arr[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i)
+    if (i == q) v = arr[i];
+  return v;
+}
+
+template <int N>
+__device__ __forceinline__ int job_of(const int (&first)[N], int njobs, int v) {
+  int q = 0;
+#pragma unroll
+  for (int i = 1; i < N - 1; ++i)
+    if (i < njobs && v >= first[i]) q = i;
+  return q;
+}
+
 // ---------------------------------------------------------------------------
 // gather / scatter
 // ---------------------------------------------------------------------------
@@ -175,23 +199,57 @@ __global__ void k_gather_in(const c64* __restrict__ p, const c64* __restrict__ q
 constexpr int P2P_THREADS = 256;
 constexpr int P2P_CHUNK = 128;
 
+// one problem's near field in a (possibly multi-problem) P2P launch; the
+// forward kernel reads ps, qs and writes ys, the adjoint one reads ps (the
+// sorted y) and writes ys, ys2 (u, w)
+template <typename R>
+struct P2PJobDev {
+  const R* geo;
+  int64_t n;
+  const int* bstart;
+  const int* u_ptr;
+  const int* u_idx;
+  const cplx<R>* ps;
+  const cplx<R>* qs;
+  cplx<R>* ys;
+  cplx<R>* ys2;
+  R k, alr, ali;
+  int all_src;
+};
+template <typename R>
+struct P2PBatch {
+  int n;      // jobs
+  int total;  // leaves of all jobs
+  int leaf0[MAX_JOBS + 1];
+  P2PJobDev<R> job[MAX_JOBS];
+};
+
 template <typename R, bool IMAG>
-__global__ void __launch_bounds__(P2P_THREADS)
-    k_p2p(const R* __restrict__ geo, int64_t n, const int* __restrict__ bstart,
-          const int* __restrict__ u_ptr, const int* __restrict__ u_idx,
-          const cplx<R>* __restrict__ ps, const cplx<R>* __restrict__ qs, R k, R alr, R ali,
-          int all_src, int nleaf, cplx<R>* __restrict__ ys) {
+__global__ void __launch_bounds__(P2P_THREADS) k_p2p(const P2PBatch<R> batch) {
   __shared__ R s_q[9][P2P_CHUNK];
   __shared__ R s_n[4][P2P_CHUNK];  // normal and plane offset y . n
   __shared__ R s_pq[4][P2P_CHUNK];
   __shared__ int s_id[P2P_CHUNK];
   __shared__ int s_nb[28], s_pre[28];
   __shared__ cplx<R> s_red[P2P_THREADS];
-  const R k_turns = k * R(0.15915494309189535);  // k / (2 pi)
   const int tid = threadIdx.x;
-  // grid-stride over the leaves (the grid may be capped below the leaf count)
-  for (int b = blockIdx.x; b < nleaf; b += gridDim.x) {
+  // grid-stride over the leaves of all jobs (the grid may be capped)
+  for (int vb = blockIdx.x; vb < batch.total; vb += gridDim.x) {
   __syncthreads();  // the previous leaf no longer reads the shared arrays
+  const int qj = job_of(batch.leaf0, batch.n, vb);
+  const P2PJobDev<R> J = select_job(batch.job, qj);
+  const int b = vb - select_job(batch.leaf0, qj);
+  const R* __restrict__ geo = J.geo;
+  const int64_t n = J.n;
+  const int* __restrict__ bstart = J.bstart;
+  const int* __restrict__ u_ptr = J.u_ptr;
+  const int* __restrict__ u_idx = J.u_idx;
+  const cplx<R>* __restrict__ ps = J.ps;
+  const cplx<R>* __restrict__ qs = J.qs;
+  cplx<R>* __restrict__ ys = J.ys;
+  const R k = J.k, alr = J.alr, ali = J.ali;
+  const int all_src = J.all_src;
+  const R k_turns = k * R(0.15915494309189535);  // k / (2 pi)
   const int t0 = bstart[b], nT = bstart[b + 1] - t0;
   const int u0 = u_ptr[b], nu = u_ptr[b + 1] - u0;
   if (tid == 0) {
@@ -281,21 +339,30 @@ __global__ void __launch_bounds__(P2P_THREADS)
 // Adjoint P2P: one block per leaf of output elements j; iterates over the
 // target elements i of the U list:  u_j += conj(cp_ij) y_i,  w_j += conj(cq_ij) y_i.
 template <typename R, bool IMAG>
-__global__ void __launch_bounds__(P2P_THREADS)
-    k_p2p_adj(const R* __restrict__ geo, int64_t n, const int* __restrict__ bstart,
-              const int* __restrict__ u_ptr, const int* __restrict__ u_idx,
-              const cplx<R>* __restrict__ ysrt, R k, R alr, R ali, int all_src, int nleaf,
-              cplx<R>* __restrict__ us, cplx<R>* __restrict__ ws) {
+__global__ void __launch_bounds__(P2P_THREADS) k_p2p_adj(const P2PBatch<R> batch) {
   __shared__ R s_x[6][P2P_CHUNK];
   __shared__ R s_y[2][P2P_CHUNK];
   __shared__ int s_id[P2P_CHUNK];
   __shared__ int s_nb[28], s_pre[28];
   __shared__ cplx<R> s_red[2][P2P_THREADS];
-  const R k_turns = k * R(0.15915494309189535);  // k / (2 pi)
   const int tid = threadIdx.x;
-  // grid-stride over the leaves (the grid may be capped below the leaf count)
-  for (int b = blockIdx.x; b < nleaf; b += gridDim.x) {
+  // grid-stride over the leaves of all jobs (the grid may be capped)
+  for (int vb = blockIdx.x; vb < batch.total; vb += gridDim.x) {
   __syncthreads();  // the previous leaf no longer reads the shared arrays
+  const int qj = job_of(batch.leaf0, batch.n, vb);
+  const P2PJobDev<R> J = select_job(batch.job, qj);
+  const int b = vb - select_job(batch.leaf0, qj);
+  const R* __restrict__ geo = J.geo;
+  const int64_t n = J.n;
+  const int* __restrict__ bstart = J.bstart;
+  const int* __restrict__ u_ptr = J.u_ptr;
+  const int* __restrict__ u_idx = J.u_idx;
+  const cplx<R>* __restrict__ ysrt = J.ps;
+  cplx<R>* __restrict__ us = J.ys;
+  cplx<R>* __restrict__ ws = J.ys2;
+  const R k = J.k, alr = J.alr, ali = J.ali;
+  const int all_src = J.all_src;
+  const R k_turns = k * R(0.15915494309189535);  // k / (2 pi)
   const int t0 = bstart[b], nT = bstart[b + 1] - t0;
   const int u0 = u_ptr[b], nu = u_ptr[b + 1] - u0;
   if (tid == 0) {
@@ -408,13 +475,33 @@ __device__ __forceinline__ void load_pair(const cplx<double>* p, cplx<double>& a
 // l, l + 64, ... over the elements e0 + q, e0 + q + 4, ...; the four slices
 // are added in a fixed order.
 template <typename R>
-__global__ void __launch_bounds__(256)
-    k_leaf_accumulate(const int* __restrict__ bstart, int ncoef, const cplx<R>* __restrict__ mat,
-                      const cplx<R>* __restrict__ a, const cplx<R>* __restrict__ bvec, int mode,
-                      cplx<R>* __restrict__ out) {
+struct LeafJobDev {
+  const int* bstart;
+  int ncoef;
+  const cplx<R>* mat;
+  const cplx<R>* a;
+  const cplx<R>* bvec;
+  cplx<R>* out;
+};
+template <typename R>
+struct LeafBatch {
+  int n, total;
+  int leaf0[MAX_JOBS + 1];
+  LeafJobDev<R> job[MAX_JOBS];
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_leaf_accumulate(const LeafBatch<R> batch, int mode) {
   __shared__ cplx<R> part[4][64];
-  const int b = blockIdx.x;
-  const int e0 = bstart[b], e1 = bstart[b + 1];
+  const int qj = job_of(batch.leaf0, batch.n, (int)blockIdx.x);
+  const LeafJobDev<R> J = select_job(batch.job, qj);
+  const int b = (int)blockIdx.x - select_job(batch.leaf0, qj);
+  const int ncoef = J.ncoef;
+  const cplx<R>* __restrict__ mat = J.mat;
+  const cplx<R>* __restrict__ a = J.a;
+  const cplx<R>* __restrict__ bvec = J.bvec;
+  cplx<R>* __restrict__ out = J.out;
+  const int e0 = J.bstart[b], e1 = J.bstart[b + 1];
   const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
   for (int c0 = 0; c0 < ncoef; c0 += 64) {
     const int c = c0 + lane;
@@ -508,7 +595,6 @@ struct GemmJobDev {
   cplx<R>* dst;
   cplx<R>* cbuf;
 };
-constexpr int MAX_JOBS = 8;
 template <typename R>
 struct GemmBatch {
   int n;
@@ -517,16 +603,6 @@ struct GemmBatch {
   GemmJobDev<R> job[MAX_JOBS];
 };
 
-// the job of a (workgroup-uniform) index, selected without dynamic indexing
-// of the kernel argument
-template <typename T, int N>
-__device__ __forceinline__ T select_job(const T (&arr)[N], int q) {
-  T v = arr[0];
-#pragma unroll
-  for (int i = 1; i < N; ++i)
-    if (i == q) v = arr[i];
-  return v;
-}
 
 // KIND: 0 M2L (per-pair output), 1 M2M, 2 L2L, 3 leaf -> ancestor, 4
 // ancestor -> leaf (the others add into dst)
@@ -1037,11 +1113,94 @@ static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, 
   return launch_grouped_jobs<R, KIND>(&j, 1, adj, s, accumulate, prof, st_gemm, grid_cap);
 }
 
+// near-field job of one problem (buffers X)
+template <typename R>
+static P2PJobDev<R> p2p_job(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X) {
+  P2PJobDev<R> j{};
+  j.geo = D.geo;
+  j.n = P.n;
+  j.bstart = P.box_start[P.L];
+  j.u_ptr = P.u_ptr;
+  j.u_idx = P.u_idx;
+  j.ps = X.ps;
+  j.qs = X.qs;
+  j.ys = X.ys;
+  j.ys2 = X.ys2;
+  j.k = (R)P.k;
+  j.alr = (R)P.alpha.re;
+  j.ali = (R)P.alpha.im;
+  j.all_src = P.direct ? 1 : 0;
+  return j;
+}
+
+// one P2P launch over up to MAX_JOBS problems (imag: all with alpha_re = 0);
+// grid_cap > 0 caps the grid (grid-stride over the leaves)
+template <typename R>
+static int launch_p2p_jobs(const P2PJobDev<R>* jobs, const int* nleaf, int nj, bool adj,
+                           bool imag, int grid_cap, hipStream_t s) {
+  if (nj <= 0) return 0;
+  if (nj > MAX_JOBS) {
+    set_error("too many near-field jobs in one launch");
+    return -1;
+  }
+  P2PBatch<R> b{};
+  b.n = nj;
+  int tot = 0;
+  for (int q = 0; q < nj; ++q) {
+    b.leaf0[q] = tot;
+    b.job[q] = jobs[q];
+    tot += nleaf[q];
+  }
+  b.leaf0[nj] = tot;
+  b.total = tot;
+  if (tot == 0) return 0;
+  const int grid = (grid_cap > 0 && grid_cap < tot) ? grid_cap : tot;
+  if (adj) {
+    if (imag)
+      hipLaunchKernelGGL((k_p2p_adj<R, true>), dim3(grid), dim3(P2P_THREADS), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_p2p_adj<R, false>), dim3(grid), dim3(P2P_THREADS), 0, s, b);
+  } else {
+    if (imag)
+      hipLaunchKernelGGL((k_p2p<R, true>), dim3(grid), dim3(P2P_THREADS), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_p2p<R, false>), dim3(grid), dim3(P2P_THREADS), 0, s, b);
+  }
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+// one leaf-accumulation launch (mode 0 P2M, 1 L2P^H) over up to MAX_JOBS problems
+template <typename R>
+static int launch_leaf_jobs(const LeafJobDev<R>* jobs, const int* nleaf, int nj, int mode,
+                            hipStream_t s) {
+  if (nj <= 0) return 0;
+  if (nj > MAX_JOBS) {
+    set_error("too many leaf jobs in one launch");
+    return -1;
+  }
+  LeafBatch<R> b{};
+  b.n = nj;
+  int tot = 0;
+  for (int q = 0; q < nj; ++q) {
+    b.leaf0[q] = tot;
+    b.job[q] = jobs[q];
+    tot += nleaf[q];
+  }
+  b.leaf0[nj] = tot;
+  b.total = tot;
+  if (tot == 0) return 0;
+  hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(tot), dim3(256), 0, s, b, mode);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
 // M2L of the levels 2 .. L-1 (all inputs ready once the upward pass is done):
 // consecutive levels with the same pair-tile width share a launch (up to
 // MAX_JOBS levels), each level keeping the width chosen for it
 template <typename R>
-static int launch_coarse_m2l(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t s) {
+static int launch_coarse_m2l(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj,
+                             hipStream_t s) {
   const int L = P.L;
   int l = 2;
   while (l < L) {
@@ -1050,9 +1209,9 @@ static int launch_coarse_m2l(Problem& P, PrecisionData<R>& D, bool adj, hipStrea
     const int ct = adj ? D.m2l[l].ct_adj : D.m2l[l].ct;
     for (; l < L && nj < MAX_JOBS && (adj ? D.m2l[l].ct_adj : D.m2l[l].ct) == ct; ++l, ++nj) {
       jobs[nj].op = &D.m2l[l];
-      jobs[nj].src = adj ? D.Lc[l] : D.M[l];
-      jobs[nj].dst = adj ? D.M[l] : D.Lc[l];
-      jobs[nj].cbuf = D.cbuf + D.cbuf_off[l];
+      jobs[nj].src = adj ? X.Lc[l] : X.M[l];
+      jobs[nj].dst = adj ? X.M[l] : X.Lc[l];
+      jobs[nj].cbuf = X.cbuf + D.cbuf_off[l];
     }
     int r = launch_grouped_jobs<R, 0>(jobs, nj, adj, s, 0, P.prof_on ? &P : nullptr);
     if (r) return r;
@@ -1064,14 +1223,15 @@ static int launch_coarse_m2l(Problem& P, PrecisionData<R>& D, bool adj, hipStrea
 // (KIND 3), then the level-by-level chain above them.  Adjoint: the mirror
 // image for the adjoint locals (direct L2L^H, then the L2L^H chain).
 template <typename R>
-static int upward_pass(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t s) {
+static int upward_pass(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj,
+                       hipStream_t s) {
   const int L = P.L, nd = std::min(D.n_direct, P.ndir[sizeof(R) == 4]);
   GemmJob<R> jobs[MAX_JOBS];
   for (int d = 1; d <= nd; ++d) {
     if (adj)
-      jobs[d - 1] = GemmJob<R>{&D.l2l_dir[d], D.Lc[L], D.Lc[L - d], nullptr};
+      jobs[d - 1] = GemmJob<R>{&D.l2l_dir[d], X.Lc[L], X.Lc[L - d], nullptr};
     else
-      jobs[d - 1] = GemmJob<R>{&D.m2m_dir[d], D.M[L], D.M[L - d], nullptr};
+      jobs[d - 1] = GemmJob<R>{&D.m2m_dir[d], X.M[L], X.M[L - d], nullptr};
   }
   int r = 0;
   if (nd > 0) {
@@ -1079,9 +1239,9 @@ static int upward_pass(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t s)
     if (r) return r;
   }
   for (int l = L - nd; l >= 3; --l) {
-    cplx<R>* par = adj ? D.Lc[l - 1] : D.M[l - 1];  // cleared by the gather kernel
-    r = adj ? launch_grouped<R, 2>(D.l2l[l], true, D.Lc[l], par, s)
-            : launch_grouped<R, 1>(D.m2m[l], false, D.M[l], par, s);
+    cplx<R>* par = adj ? X.Lc[l - 1] : X.M[l - 1];  // cleared by the gather kernel
+    r = adj ? launch_grouped<R, 2>(D.l2l[l], true, X.Lc[l], par, s)
+            : launch_grouped<R, 1>(D.m2m[l], false, X.M[l], par, s);
     if (r) return r;
   }
   return 0;
@@ -1092,14 +1252,14 @@ static int upward_pass(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t s)
 // after `leaf_ready`: the leaf-level M2L result is written on another
 // stream).  Adjoint: the mirror image (M2M^H chain, direct M2M^H).
 template <typename R>
-static int downward_pass(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t s,
-                         hipEvent_t leaf_ready) {
+static int downward_pass(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj,
+                         hipStream_t s, hipEvent_t leaf_ready) {
   const int L = P.L, nd = std::min(D.n_direct, P.ndir[sizeof(R) == 4]);
   int r = 0;
   for (int l = 3; l <= L - nd; ++l) {
     if (l == L && leaf_ready) BEM_HIP_TRY(hipStreamWaitEvent(s, leaf_ready, 0));
-    r = adj ? launch_grouped<R, 1>(D.m2m[l], true, D.M[l - 1], D.M[l], s)
-            : launch_grouped<R, 2>(D.l2l[l], false, D.Lc[l - 1], D.Lc[l], s);
+    r = adj ? launch_grouped<R, 1>(D.m2m[l], true, X.M[l - 1], X.M[l], s)
+            : launch_grouped<R, 2>(D.l2l[l], false, X.Lc[l - 1], X.Lc[l], s);
     if (r) return r;
   }
   if ((nd > 0 || L < 3) && leaf_ready) BEM_HIP_TRY(hipStreamWaitEvent(s, leaf_ready, 0));
@@ -1107,9 +1267,9 @@ static int downward_pass(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t 
     GemmJob<R> jobs[MAX_JOBS];
     for (int d = 1; d <= nd; ++d) {
       if (adj)
-        jobs[d - 1] = GemmJob<R>{&D.m2m_dir[d], D.M[L - d], D.M[L], nullptr};
+        jobs[d - 1] = GemmJob<R>{&D.m2m_dir[d], X.M[L - d], X.M[L], nullptr};
       else
-        jobs[d - 1] = GemmJob<R>{&D.l2l_dir[d], D.Lc[L - d], D.Lc[L], nullptr};
+        jobs[d - 1] = GemmJob<R>{&D.l2l_dir[d], X.Lc[L - d], X.Lc[L], nullptr};
     }
     r = adj ? launch_grouped_jobs<R, 3>(jobs, nd, true, s) : launch_grouped_jobs<R, 4>(jobs, nd, false, s);
     if (r) return r;
@@ -1120,12 +1280,12 @@ static int downward_pass(Problem& P, PrecisionData<R>& D, bool adj, hipStream_t 
 // the parent-level expansions accumulated atomically in the chain (M for the
 // forward upward pass, L for the adjoint one), cleared by the gather kernel
 template <typename R>
-static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, bool adj) {
+static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj) {
   ZeroList<R> z{};
   z.n = 0;
   if (P.direct) return z;
   for (int l = P.L - 1; l >= 2 && z.n < MAX_ZERO; --l) {
-    z.ptr[z.n] = adj ? D.Lc[l] : D.M[l];
+    z.ptr[z.n] = adj ? X.Lc[l] : X.M[l];
     z.cnt[z.n] = (int64_t)P.nbox[l] * D.ncoef[l];
     ++z.n;
   }
@@ -1134,22 +1294,21 @@ static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, bool adj) {
 
 
 template <typename R>
-int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* y,
-              hipStream_t s) {
+int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, const c64* q,
+                c64* y, hipStream_t s) {
   const int64_t n = P.n;
   const int L = P.L;
   const R k = (R)P.k, alr = (R)P.alpha.re, ali = (R)P.alpha.im;
   constexpr int ADJ_FLAG = 0;
   int nb = ceil_div(n, 256);
   PROF_BEGIN(e0);
-  hipLaunchKernelGGL(k_gather_in<R>, dim3(nb), dim3(256), 0, s, p, q, P.perm, n, D.ps, D.qs,
-                     P.p64s, P.q64s, chain_zero_list(P, D, false));
+  hipLaunchKernelGGL(k_gather_in<R>, dim3(nb), dim3(256), 0, s, p, q, P.perm, n, X.ps, X.qs,
+                     X.p64s, X.q64s, chain_zero_list(P, D, X, false));
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
-  const int p2p_grid = (cap > 0 && cap < nleaf) ? cap : nleaf;
   // the near field runs on the side stream, concurrently with the far field
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
@@ -1158,15 +1317,9 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
       BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
     }
     int e1 = prof_begin(P, sn);
-    if (P.alpha.re == 0.0)
-      hipLaunchKernelGGL((k_p2p<R, true>), dim3(p2p_grid), dim3(P2P_THREADS), 0, sn,
-                         (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr,
-                         ali, (int)P.direct, nleaf, D.ys);
-    else
-      hipLaunchKernelGGL((k_p2p<R, false>), dim3(p2p_grid), dim3(P2P_THREADS), 0, sn,
-                         (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, D.qs, k, alr,
-                         ali, (int)P.direct, nleaf, D.ys);
-    BEM_LAUNCH_CHECK();
+    const P2PJobDev<R> job = p2p_job(P, D, X);
+    int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, false, P.alpha.re == 0.0, cap, sn);
+    if (rr) return rr;
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, false), sn);
     if (pr) return pr;
     if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
@@ -1177,15 +1330,16 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
   if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
-                       P.elem_leaf, 0, D.l2p, D.Lc[L], P.near_ptr, P.near_col, D.near_cp,
-                       D.near_cq, D.ps, D.qs, D.ys, P.diag_p, P.diag_q, P.p64s, P.q64s, y);
+                       P.elem_leaf, 0, D.l2p, X.Lc[L], P.near_ptr, P.near_col, D.near_cp,
+                       D.near_cq, X.ps, X.qs, X.ys, P.diag_p, P.diag_q, X.p64s, X.q64s, y);
     BEM_LAUNCH_CHECK();
     return 0;
   }
   PROF_BEGIN(e2);
-  hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(nleaf), dim3(256), 0, s, P.box_start[L],
-                     D.ncoef[L], D.p2m, D.ps, D.qs, 0, D.M[L]);
-  BEM_LAUNCH_CHECK();
+  {
+    const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], D.p2m, X.ps, X.qs, X.M[L]};
+    if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, 0, s))) return r;
+  }
   PROF_END(e2, ST_P2M);
   // leaf-level M2L (needs only the leaf multipoles): on its own stream
   // (SCHED_CONCURRENT), or on this stream before the upward pass
@@ -1195,25 +1349,25 @@ int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* 
     BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
     BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   }
-  if ((r = launch_grouped<R, 0>(D.m2l[L], false, D.M[L], D.Lc[L], sl, D.cbufL, 0,
+  if ((r = launch_grouped<R, 0>(D.m2l[L], false, X.M[L], X.Lc[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
                                 P.m2l_cap[sizeof(R) == 4])))
     return r;
   if (leaf_side) BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e3);
-  if ((r = upward_pass<R>(P, D, false, s))) return r;
+  if ((r = upward_pass<R>(P, D, X, false, s))) return r;
   PROF_END(e3, ST_M2M);
   if (sched == SCHED_P2P_AFTER_UP && (r = launch_p2p())) return r;
-  if ((r = launch_coarse_m2l<R>(P, D, false, s))) return r;
+  if ((r = launch_coarse_m2l<R>(P, D, X, false, s))) return r;
   PROF_BEGIN(e5);
-  if ((r = downward_pass<R>(P, D, false, s, leaf_side ? P.ev_join2 : nullptr))) return r;
+  if ((r = downward_pass<R>(P, D, X, false, s, leaf_side ? P.ev_join2 : nullptr))) return r;
   PROF_END(e5, ST_L2L);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);
   hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
-                     P.elem_leaf, D.ncoef[L], D.l2p, D.Lc[L], P.near_ptr, P.near_col, D.near_cp,
-                     D.near_cq, D.ps, D.qs, D.ys, P.diag_p, P.diag_q, P.p64s, P.q64s, y);
+                     P.elem_leaf, D.ncoef[L], D.l2p, X.Lc[L], P.near_ptr, P.near_col, D.near_cp,
+                     D.near_cq, X.ps, X.qs, X.ys, P.diag_p, P.diag_q, X.p64s, X.q64s, y);
   BEM_LAUNCH_CHECK();
   PROF_END(e6, ST_FINISH);
   return 0;
@@ -1232,23 +1386,22 @@ __global__ void k_gather_adj(const c64* __restrict__ y, const int* __restrict__ 
 }
 
 template <typename R>
-int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64* w,
-                      hipStream_t s) {
+int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* y, c64* u,
+                        c64* w, hipStream_t s) {
   const int64_t n = P.n;
   const int L = P.L;
   const R k = (R)P.k, alr = (R)P.alpha.re, ali = (R)P.alpha.im;
   constexpr int ADJ_FLAG = 1;
   int nb = ceil_div(n, 256);
-  // sorted input in D.ps, P.p64s; P2P results in D.ys (u) and D.ys2 (w)
+  // sorted input in X.ps, X.p64s; P2P results in X.ys (u) and X.ys2 (w)
   PROF_BEGIN(e0);
-  hipLaunchKernelGGL(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, y, P.perm, n, D.ps, P.p64s,
-                     chain_zero_list(P, D, true));
+  hipLaunchKernelGGL(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, y, P.perm, n, X.ps, X.p64s,
+                     chain_zero_list(P, D, X, true));
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
-  const int p2p_grid = (cap > 0 && cap < nleaf) ? cap : nleaf;
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
     if (!P.direct) {
@@ -1256,15 +1409,9 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
       BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
     }
     int e1 = prof_begin(P, sn);
-    if (P.alpha.re == 0.0)
-      hipLaunchKernelGGL((k_p2p_adj<R, true>), dim3(p2p_grid), dim3(P2P_THREADS), 0, sn,
-                         (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali,
-                         (int)P.direct, nleaf, D.ys, D.ys2);
-    else
-      hipLaunchKernelGGL((k_p2p_adj<R, false>), dim3(p2p_grid), dim3(P2P_THREADS), 0, sn,
-                         (const R*)D.geo, n, P.box_start[L], P.u_ptr, P.u_idx, D.ps, k, alr, ali,
-                         (int)P.direct, nleaf, D.ys, D.ys2);
-    BEM_LAUNCH_CHECK();
+    const P2PJobDev<R> job = p2p_job(P, D, X);
+    int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, true, P.alpha.re == 0.0, cap, sn);
+    if (rr) return rr;
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, true), sn);
     if (pr) return pr;
     if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
@@ -1275,16 +1422,17 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
   if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
-                       P.elem_leaf, 0, D.p2m, D.M[L], P.neart_ptr, P.neart_row, D.neart_cp,
-                       D.neart_cq, D.ps, D.ys, D.ys2, P.diag_p, P.diag_q, P.p64s, u, w);
+                       P.elem_leaf, 0, D.p2m, X.M[L], P.neart_ptr, P.neart_row, D.neart_cp,
+                       D.neart_cq, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, u, w);
     BEM_LAUNCH_CHECK();
     return 0;
   }
   // adjoint locals (L2P^H) in Lc, adjoint multipoles in M
   PROF_BEGIN(e2);
-  hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(nleaf), dim3(256), 0, s, P.box_start[L],
-                     D.ncoef[L], D.l2p, D.ps, (const cplx<R>*)nullptr, 1, D.Lc[L]);
-  BEM_LAUNCH_CHECK();
+  {
+    const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], D.l2p, X.ps, nullptr, X.Lc[L]};
+    if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, 1, s))) return r;
+  }
   PROF_END(e2, ST_P2M);
   // leaf-level M2L^H (needs only the leaf adjoint locals): own stream or
   // this one, as in the forward product
@@ -1294,30 +1442,261 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
     BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
     BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   }
-  if ((r = launch_grouped<R, 0>(D.m2l[L], true, D.Lc[L], D.M[L], sl, D.cbufL, 0,
+  if ((r = launch_grouped<R, 0>(D.m2l[L], true, X.Lc[L], X.M[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
                                 P.m2l_cap[sizeof(R) == 4])))
     return r;
   if (leaf_side) BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e5);
-  if ((r = upward_pass<R>(P, D, true, s))) return r;
+  if ((r = upward_pass<R>(P, D, X, true, s))) return r;
   PROF_END(e5, ST_L2L);
   if (sched == SCHED_P2P_AFTER_UP && (r = launch_p2p())) return r;
-  if ((r = launch_coarse_m2l<R>(P, D, true, s))) return r;
+  if ((r = launch_coarse_m2l<R>(P, D, X, true, s))) return r;
   PROF_BEGIN(e3);
-  if ((r = downward_pass<R>(P, D, true, s, leaf_side ? P.ev_join2 : nullptr))) return r;
+  if ((r = downward_pass<R>(P, D, X, true, s, leaf_side ? P.ev_join2 : nullptr))) return r;
   PROF_END(e3, ST_M2M);
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   PROF_BEGIN(e6);
   hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
-                     P.elem_leaf, D.ncoef[L], D.p2m, D.M[L], P.neart_ptr, P.neart_row,
-                     D.neart_cp, D.neart_cq, D.ps, D.ys, D.ys2, P.diag_p, P.diag_q, P.p64s, u, w);
+                     P.elem_leaf, D.ncoef[L], D.p2m, X.M[L], P.neart_ptr, P.neart_row,
+                     D.neart_cp, D.neart_cq, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, u, w);
   BEM_LAUNCH_CHECK();
   PROF_END(e6, ST_FINISH);
   return 0;
 }
 
+// grouped launches of any number of jobs: by pair-tile width, MAX_JOBS at a time
+template <typename R, int KIND>
+static int launch_grouped_any(const std::vector<GemmJob<R>>& jobs, bool adj, hipStream_t s) {
+  for (int ct : {16, 32, 64, 128}) {
+    std::vector<GemmJob<R>> g;
+    for (const GemmJob<R>& j : jobs)
+      if ((adj ? j.op->ct_adj : j.op->ct) == ct) g.push_back(j);
+    for (size_t a = 0; a < g.size(); a += MAX_JOBS) {
+      const int nj = (int)std::min<size_t>(MAX_JOBS, g.size() - a);
+      int r = launch_grouped_jobs<R, KIND>(&g[a], nj, adj, s);
+      if (r) return r;
+    }
+  }
+  return 0;
+}
+
+// The batched product: the per-element stages (gather, finish) run per
+// item; every other stage is one launch (or one per tile width and
+// MAX_JOBS items) over all items, in the order of the single product
+// (near field and leaf-level M2L on the side streams when given).  Level
+// chains of problems with different depths are merged step by step from
+// the leaves.
+template <typename R>
+int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const BatchStreams& bs) {
+  int r = 0;
+  hipStream_t s = bs.main;
+  const bool sides = bs.side && bs.side2;
+  hipStream_t sn = sides ? bs.side : s, sl = sides ? bs.side2 : s;
+  // gathers (and the clears of the atomically accumulated expansions)
+  for (const BatchItem<R>& it : items) {
+    Problem& P = *it.P;
+    PrecisionData<R>& D = *it.D;
+    ExecBuf<R>& X = *it.X;
+    const int nb = ceil_div(P.n, 256);
+    if (adj)
+      hipLaunchKernelGGL(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, it.in, P.perm, P.n, X.ps,
+                         X.p64s, chain_zero_list(P, D, X, true));
+    else
+      hipLaunchKernelGGL(k_gather_in<R>, dim3(nb), dim3(256), 0, s, it.in, it.q, P.perm, P.n,
+                         X.ps, X.qs, X.p64s, X.q64s, chain_zero_list(P, D, X, false));
+    BEM_LAUNCH_CHECK();
+  }
+  // near field, by kind of alpha
+  if (sides) {
+    BEM_HIP_TRY(hipEventRecord(bs.ev[0], s));
+    BEM_HIP_TRY(hipStreamWaitEvent(sn, bs.ev[0], 0));
+  }
+  for (int imag = 0; imag < 2; ++imag) {
+    std::vector<P2PJobDev<R>> jobs;
+    std::vector<int> nl;
+    for (const BatchItem<R>& it : items)
+      if ((it.P->alpha.re == 0.0) == (imag == 1)) {
+        jobs.push_back(p2p_job(*it.P, *it.D, *it.X));
+        nl.push_back(it.P->nbox[it.P->L]);
+      }
+    for (size_t a = 0; a < jobs.size(); a += MAX_JOBS) {
+      const int nj = (int)std::min<size_t>(MAX_JOBS, jobs.size() - a);
+      if ((r = launch_p2p_jobs<R>(&jobs[a], &nl[a], nj, adj, imag == 1, 0, sn))) return r;
+    }
+  }
+  if (sides) BEM_HIP_TRY(hipEventRecord(bs.ev[1], sn));
+  // far field of the items that have one
+  std::vector<const BatchItem<R>*> far;
+  for (const BatchItem<R>& it : items)
+    if (!it.P->direct) far.push_back(&it);
+  {
+    std::vector<LeafJobDev<R>> jobs;
+    std::vector<int> nl;
+    for (const BatchItem<R>* it : far) {
+      Problem& P = *it->P;
+      PrecisionData<R>& D = *it->D;
+      ExecBuf<R>& X = *it->X;
+      const int L = P.L;
+      if (adj)
+        jobs.push_back(LeafJobDev<R>{P.box_start[L], D.ncoef[L], D.l2p, X.ps, nullptr, X.Lc[L]});
+      else
+        jobs.push_back(LeafJobDev<R>{P.box_start[L], D.ncoef[L], D.p2m, X.ps, X.qs, X.M[L]});
+      nl.push_back(P.nbox[L]);
+    }
+    for (size_t a = 0; a < jobs.size(); a += MAX_JOBS) {
+      const int nj = (int)std::min<size_t>(MAX_JOBS, jobs.size() - a);
+      if ((r = launch_leaf_jobs<R>(&jobs[a], &nl[a], nj, adj ? 1 : 0, s))) return r;
+    }
+  }
+  // level chains only: merged across problems step by step they need few
+  // launches, while the direct operators (8^d per depth, mostly sparse
+  // groups) cost more than they save once launches are shared
+  auto nd_of = [](const BatchItem<R>*) { return 0; };
+  // leaf-level M2L
+  if (sides) {
+    BEM_HIP_TRY(hipEventRecord(bs.ev[2], s));
+    BEM_HIP_TRY(hipStreamWaitEvent(sl, bs.ev[2], 0));
+  }
+  {
+    std::vector<GemmJob<R>> jobs;
+    for (const BatchItem<R>* it : far) {
+      const int L = it->P->L;
+      ExecBuf<R>& X = *it->X;
+      jobs.push_back(GemmJob<R>{&it->D->m2l[L], adj ? X.Lc[L] : X.M[L], adj ? X.M[L] : X.Lc[L],
+                                X.cbufL});
+    }
+    if ((r = launch_grouped_any<R, 0>(jobs, adj, sl))) return r;
+  }
+  if (sides) BEM_HIP_TRY(hipEventRecord(bs.ev[3], sl));
+  // upward pass: direct translations, then the chains step by step
+  {
+    std::vector<GemmJob<R>> jobs;
+    int max_steps = 0;
+    for (const BatchItem<R>* it : far) {
+      const int L = it->P->L, nd = nd_of(it);
+      ExecBuf<R>& X = *it->X;
+      for (int d = 1; d <= nd; ++d)
+        jobs.push_back(adj ? GemmJob<R>{&it->D->l2l_dir[d], X.Lc[L], X.Lc[L - d], nullptr}
+                           : GemmJob<R>{&it->D->m2m_dir[d], X.M[L], X.M[L - d], nullptr});
+      max_steps = std::max(max_steps, L - nd - 2);
+    }
+    if (adj) {
+      if ((r = launch_grouped_any<R, 4>(jobs, true, s))) return r;
+    } else {
+      if ((r = launch_grouped_any<R, 3>(jobs, false, s))) return r;
+    }
+    for (int t = 0; t < max_steps; ++t) {
+      jobs.clear();
+      for (const BatchItem<R>* it : far) {
+        const int l = it->P->L - nd_of(it) - t;  // level l -> l - 1
+        if (l < 3) continue;
+        ExecBuf<R>& X = *it->X;
+        jobs.push_back(adj ? GemmJob<R>{&it->D->l2l[l], X.Lc[l], X.Lc[l - 1], nullptr}
+                           : GemmJob<R>{&it->D->m2m[l], X.M[l], X.M[l - 1], nullptr});
+      }
+      if (adj) {
+        if ((r = launch_grouped_any<R, 2>(jobs, true, s))) return r;
+      } else {
+        if ((r = launch_grouped_any<R, 1>(jobs, false, s))) return r;
+      }
+    }
+  }
+  // M2L of the levels above the leaves
+  {
+    std::vector<GemmJob<R>> jobs;
+    for (const BatchItem<R>* it : far) {
+      ExecBuf<R>& X = *it->X;
+      for (int l = 2; l < it->P->L; ++l)
+        jobs.push_back(GemmJob<R>{&it->D->m2l[l], adj ? X.Lc[l] : X.M[l],
+                                  adj ? X.M[l] : X.Lc[l], X.cbuf + it->D->cbuf_off[l]});
+    }
+    if ((r = launch_grouped_any<R, 0>(jobs, adj, s))) return r;
+  }
+  // downward pass (its last step writes the leaf level): the chains step
+  // by step, then the direct translations
+  if (sides) BEM_HIP_TRY(hipStreamWaitEvent(s, bs.ev[3], 0));
+  {
+    std::vector<GemmJob<R>> jobs;
+    int max_steps = 0;
+    for (const BatchItem<R>* it : far) max_steps = std::max(max_steps, it->P->L - nd_of(it) - 2);
+    for (int t = 0; t < max_steps; ++t) {
+      jobs.clear();
+      for (const BatchItem<R>* it : far) {
+        const int l = 3 + t;  // level l - 1 -> l
+        if (l > it->P->L - nd_of(it)) continue;
+        ExecBuf<R>& X = *it->X;
+        jobs.push_back(adj ? GemmJob<R>{&it->D->m2m[l], X.M[l - 1], X.M[l], nullptr}
+                           : GemmJob<R>{&it->D->l2l[l], X.Lc[l - 1], X.Lc[l], nullptr});
+      }
+      if (adj) {
+        if ((r = launch_grouped_any<R, 1>(jobs, true, s))) return r;
+      } else {
+        if ((r = launch_grouped_any<R, 2>(jobs, false, s))) return r;
+      }
+    }
+    jobs.clear();
+    for (const BatchItem<R>* it : far) {
+      const int L = it->P->L, nd = nd_of(it);
+      ExecBuf<R>& X = *it->X;
+      for (int d = 1; d <= nd; ++d)
+        jobs.push_back(adj ? GemmJob<R>{&it->D->m2m_dir[d], X.M[L - d], X.M[L], nullptr}
+                           : GemmJob<R>{&it->D->l2l_dir[d], X.Lc[L - d], X.Lc[L], nullptr});
+    }
+    if (adj) {
+      if ((r = launch_grouped_any<R, 3>(jobs, true, s))) return r;
+    } else {
+      if ((r = launch_grouped_any<R, 4>(jobs, false, s))) return r;
+    }
+  }
+  // finish per item
+  if (sides) BEM_HIP_TRY(hipStreamWaitEvent(s, bs.ev[1], 0));
+  for (const BatchItem<R>& it : items) {
+    Problem& P = *it.P;
+    PrecisionData<R>& D = *it.D;
+    ExecBuf<R>& X = *it.X;
+    const int64_t n = P.n;
+    const int L = P.L;
+    const int ncoef = P.direct ? 0 : D.ncoef[L];
+    if (adj)
+      hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n,
+                         P.perm, P.elem_leaf, ncoef, D.p2m, X.M[L], P.neart_ptr, P.neart_row,
+                         D.neart_cp, D.neart_cq, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s,
+                         it.out, it.out2);
+    else
+      hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n,
+                         P.perm, P.elem_leaf, ncoef, D.l2p, X.Lc[L], P.near_ptr, P.near_col,
+                         D.near_cp, D.near_cq, X.ps, X.qs, X.ys, P.diag_p, P.diag_q, X.p64s,
+                         X.q64s, it.out);
+    BEM_LAUNCH_CHECK();
+  }
+  return 0;
+}
+
+template <typename R>
+int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* y,
+              hipStream_t s) {
+  return fmm_apply_x<R>(P, D, D.X, p, q, y, s);
+}
+template <typename R>
+int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64* w,
+                      hipStream_t s) {
+  return fmm_apply_adjoint_x<R>(P, D, D.X, y, u, w, s);
+}
+
+template int fmm_apply_x<float>(Problem&, PrecisionData<float>&, ExecBuf<float>&, const c64*,
+                                const c64*, c64*, hipStream_t);
+template int fmm_apply_x<double>(Problem&, PrecisionData<double>&, ExecBuf<double>&, const c64*,
+                                 const c64*, c64*, hipStream_t);
+template int fmm_apply_adjoint_x<float>(Problem&, PrecisionData<float>&, ExecBuf<float>&,
+                                        const c64*, c64*, c64*, hipStream_t);
+template int fmm_apply_adjoint_x<double>(Problem&, PrecisionData<double>&, ExecBuf<double>&,
+                                         const c64*, c64*, c64*, hipStream_t);
+template int fmm_apply_batch<float>(const std::vector<BatchItem<float>>&, bool,
+                                    const BatchStreams&);
+template int fmm_apply_batch<double>(const std::vector<BatchItem<double>>&, bool,
+                                     const BatchStreams&);
 template int fmm_apply<float>(Problem&, PrecisionData<float>&, const c64*, const c64*, c64*,
                               hipStream_t);
 template int fmm_apply<double>(Problem&, PrecisionData<double>&, const c64*, const c64*, c64*,

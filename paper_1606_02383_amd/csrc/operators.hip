@@ -662,8 +662,6 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     D.order[l] = is64 ? auto_order(k, P.h[l], P.order64_req, 12, 8)
                       : auto_order(k, P.h[l], P.order32_req, 7, 3);
     D.ncoef[l] = (D.order[l] + 1) * (D.order[l] + 1);
-    ARENA_ALLOC(P.arena, D.M[l], (int64_t)P.nbox[l] * D.ncoef[l]);
-    ARENA_ALLOC(P.arena, D.Lc[l], (int64_t)P.nbox[l] * D.ncoef[l]);
   }
   // ---- M2L: one matrix per offset present at each level ----
   int64_t cbuf_count = 0;
@@ -707,7 +705,7 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
       D.cbuf_off[l] = cbuf_count;
       cbuf_count += (int64_t)np * D.ncoef[l];
     } else {
-      ARENA_ALLOC(P.arena, D.cbufL, (int64_t)np * D.ncoef[l]);
+      D.cbufL_count = (int64_t)np * D.ncoef[l];
     }
   }
   // ---- M2M (child level l -> parent l-1) and L2L (l-1 -> l), l >= 3 ----
@@ -816,7 +814,7 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     if (r) return r;
     D.n_direct = d;
   }
-  ARENA_ALLOC(P.arena, D.cbuf, cbuf_count);
+  D.cbuf_count = cbuf_count;
   // ---- P2M and L2P per element ----
   {
     int p = D.order[L];
@@ -885,6 +883,27 @@ __global__ void k_geo_to_float(const double* __restrict__ g, int64_t cnt, float*
   if (i < cnt) f[i] = (float)g[i];
 }
 
+template <typename R>
+int alloc_exec(const Problem& P, const PrecisionData<R>& D, ExecBuf<R>& X, DevArena& arena) {
+  for (int l = 2; l <= P.L; ++l) {
+    ARENA_ALLOC(arena, X.M[l], (int64_t)P.nbox[l] * D.ncoef[l]);
+    ARENA_ALLOC(arena, X.Lc[l], (int64_t)P.nbox[l] * D.ncoef[l]);
+  }
+  ARENA_ALLOC(arena, X.cbuf, D.cbuf_count);
+  ARENA_ALLOC(arena, X.cbufL, D.cbufL_count);
+  ARENA_ALLOC(arena, X.ps, P.n);
+  ARENA_ALLOC(arena, X.qs, P.n);
+  ARENA_ALLOC(arena, X.ys, P.n);
+  ARENA_ALLOC(arena, X.ys2, P.n);
+  ARENA_ALLOC(arena, X.p64s, P.n);
+  ARENA_ALLOC(arena, X.q64s, P.n);
+  return 0;
+}
+template int alloc_exec<float>(const Problem&, const PrecisionData<float>&, ExecBuf<float>&,
+                               DevArena&);
+template int alloc_exec<double>(const Problem&, const PrecisionData<double>&, ExecBuf<double>&,
+                                DevArena&);
+
 int build_operators(Problem& P, hipStream_t s) {
   DevArena scratch;
   struct Guard {
@@ -904,16 +923,11 @@ int build_operators(Problem& P, hipStream_t s) {
   hipLaunchKernelGGL(k_geo_to_float, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, P.geo, cnt, P.f32.geo);
   BEM_LAUNCH_CHECK();
   P.f64.geo = P.geo;
-  ARENA_ALLOC(P.arena, P.f64.ps, P.n);
-  ARENA_ALLOC(P.arena, P.f64.qs, P.n);
-  ARENA_ALLOC(P.arena, P.f64.ys, P.n);
-  ARENA_ALLOC(P.arena, P.f64.ys2, P.n);
-  ARENA_ALLOC(P.arena, P.f32.ps, P.n);
-  ARENA_ALLOC(P.arena, P.f32.qs, P.n);
-  ARENA_ALLOC(P.arena, P.f32.ys, P.n);
-  ARENA_ALLOC(P.arena, P.f32.ys2, P.n);
-  ARENA_ALLOC(P.arena, P.p64s, P.n);
-  ARENA_ALLOC(P.arena, P.q64s, P.n);
+  {
+    int r = alloc_exec<double>(P, P.f64, P.f64.X, P.arena);
+    if (!r) r = alloc_exec<float>(P, P.f32, P.f32.X, P.arena);
+    if (r) return r;
+  }
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side2, hipStreamNonBlocking));
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.bstream, hipStreamNonBlocking));

@@ -63,12 +63,29 @@ struct GroupedOp {
   int* red_pairs_adj = nullptr;
 };
 
+// Buffers that one product writes, for one precision: sorted densities and
+// their float64 copies, near-field sums, expansions per level and the
+// per-pair M2L outputs.  A problem holds one set; batched solves give every
+// further system of the same problem its own, so that their products can
+// share launches.
+template <typename R>
+struct ExecBuf {
+  std::array<cplx<R>*, MAX_LEVEL + 1> M{};   // multipole (box-major, ncoef per box)
+  std::array<cplx<R>*, MAX_LEVEL + 1> Lc{};  // local
+  cplx<R>* cbuf = nullptr;   // per-pair M2L products, levels below the leaf level
+  cplx<R>* cbufL = nullptr;  // per-pair M2L products, leaf level
+  cplx<R>* ps = nullptr;     // work vectors (sorted order)
+  cplx<R>* qs = nullptr;
+  cplx<R>* ys = nullptr;
+  cplx<R>* ys2 = nullptr;
+  c64* p64s = nullptr;       // float64 input copies for the diagonal (sorted order)
+  c64* q64s = nullptr;
+};
+
 template <typename R>
 struct PrecisionData {
   std::array<int, MAX_LEVEL + 1> order{};   // p_l
   std::array<int, MAX_LEVEL + 1> ncoef{};   // (p_l + 1)^2
-  std::array<cplx<R>*, MAX_LEVEL + 1> M{};  // multipole (box-major, ncoef per box)
-  std::array<cplx<R>*, MAX_LEVEL + 1> Lc{}; // local
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2l{};
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2m{};  // level l -> l-1 (index l)
   std::array<GroupedOp<R>, MAX_LEVEL + 1> l2l{};  // level l-1 -> l (index l)
@@ -76,9 +93,8 @@ struct PrecisionData {
   int n_direct = 0;
   std::array<GroupedOp<R>, MAX_DIRECT + 1> m2m_dir{};  // leaf -> level L - d
   std::array<GroupedOp<R>, MAX_DIRECT + 1> l2l_dir{};  // level L - d -> leaf
-  cplx<R>* cbuf = nullptr;   // per-pair M2L products, levels below the leaf level
   std::array<int64_t, MAX_LEVEL + 1> cbuf_off{};  // offset of each level's pairs in cbuf
-  cplx<R>* cbufL = nullptr;  // per-pair M2L products, leaf level (own stream)
+  int64_t cbuf_count = 0, cbufL_count = 0;        // sizes of the per-pair buffers
   cplx<R>* p2m = nullptr;   // n x ncoef_L x 2 (columns: p, q), sorted order
   cplx<R>* l2p = nullptr;   // n x ncoef_L
   // near-field corrections (accurate - 3-point rule), CSR by target and
@@ -87,13 +103,9 @@ struct PrecisionData {
   cplx<R>* near_cq = nullptr;
   cplx<R>* neart_cp = nullptr;
   cplx<R>* neart_cq = nullptr;
-  // work vectors (sorted order)
-  cplx<R>* ps = nullptr;
-  cplx<R>* qs = nullptr;
-  cplx<R>* ys = nullptr;
-  cplx<R>* ys2 = nullptr;
   // float geometry (sorted order) for the direct near field
   R* geo = nullptr;         // SoA, see GEO_* offsets
+  ExecBuf<R> X;             // the problem's own product buffers
 };
 
 // SoA geometry layout offsets (multiples of n)
@@ -153,9 +165,6 @@ struct Problem {
   c64* diag_q = nullptr;     // S_ii + alpha/2
   PrecisionData<double> f64;
   PrecisionData<float> f32;
-  // float64 input copies for the diagonal (sorted order)
-  c64* p64s = nullptr;
-  c64* q64s = nullptr;
   // solver workspace (Krylov basis etc.), owned, see solver.hip
   void* solver_ws = nullptr;
   // second stream (default priority) for the direct near field, which runs
@@ -207,11 +216,45 @@ int build_geometry_and_tree(Problem& P, const double* vert, int64_t n_vert, cons
 int build_near_field(Problem& P, hipStream_t s);
 int build_operators(Problem& P, hipStream_t s);
 template <typename R>
+int alloc_exec(const Problem& P, const PrecisionData<R>& D, ExecBuf<R>& X, DevArena& arena);
+template <typename R>
 int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* y,
               hipStream_t s);
 template <typename R>
 int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64* w,
                       hipStream_t s);
+// The same products into the given buffers (several executions of one
+// problem may be in flight with distinct buffers).
+template <typename R>
+int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, const c64* q,
+                c64* y, hipStream_t s);
+template <typename R>
+int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* y, c64* u,
+                        c64* w, hipStream_t s);
+
+// One product of a batch: forward y = A_p in + A_q q, or adjoint
+// (out, out2) = (A_p^H in, A_q^H in); items of one problem need distinct X.
+template <typename R>
+struct BatchItem {
+  Problem* P;
+  PrecisionData<R>* D;
+  ExecBuf<R>* X;
+  const c64* in;
+  const c64* q;  // forward only (may be null)
+  c64* out;
+  c64* out2;     // adjoint only (may be null)
+};
+// Streams of a batched product: the main chain on `main`; with `side` and
+// `side2` set, the near field runs on `side` and the leaf-level M2L on
+// `side2`, concurrently with the chain (fork/join events ev[0..3]).
+struct BatchStreams {
+  hipStream_t main = nullptr, side = nullptr, side2 = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+// All items' products (same precision and direction) with every stage
+// issued once for all of them.
+template <typename R>
+int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const BatchStreams& bs);
 int sort_pairs_u64(uint64_t* keys, int* vals, int n, int nbits, DevArena& scratch,
                    hipStream_t s);
 int exclusive_scan(const int* in, int* out, int n, int* total, DevArena& scratch, hipStream_t s);

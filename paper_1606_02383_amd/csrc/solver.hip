@@ -859,7 +859,11 @@ struct BatchSys {
   const c64* b = nullptr;
   c64* x = nullptr;
   Workspace W;
-  hipStream_t s = nullptr;
+  // product buffers: the problem's own for its first system, else these
+  ExecBuf<float> own32;
+  ExecBuf<double> own64;
+  ExecBuf<float>* X32 = nullptr;
+  ExecBuf<double>* X64 = nullptr;
   int state = 0;  // 0 outer residual, 1 Arnoldi, 2 done
   bool first = true;
   double bn = 0, rn = 0, atol = 0, beta = 0;
@@ -867,38 +871,6 @@ struct BatchSys {
   std::vector<std::complex<double>> H, cs, sn, g;
   std::vector<double> hist;
 };
-
-static int batch_apply(BatchSys& S, bool f32, const c64* v, c64* out) {
-  Problem& P = *S.P;
-  const int64_t n = P.n;
-  const int nb = ceil_div(n, 256);
-  hipStream_t s = S.s;
-  int rr;
-  if (!S.adjoint) {
-    const c64* q = nullptr;
-    if (S.sigma) {
-      hipLaunchKernelGGL(k_diag_mul, dim3(nb), dim3(256), 0, s, S.sigma, v, n, 0, S.W.t3);
-      BEM_LAUNCH_CHECK();
-      q = S.W.t3;
-    }
-    rr = f32 ? fmm_apply<float>(P, P.f32, v, q, out, s) : fmm_apply<double>(P, P.f64, v, q, out, s);
-    if (rr) return rr;
-  } else {
-    c64* wv = S.sigma ? S.W.t3 : nullptr;
-    rr = f32 ? fmm_apply_adjoint<float>(P, P.f32, v, out, wv, s)
-             : fmm_apply_adjoint<double>(P, P.f64, v, out, wv, s);
-    if (rr) return rr;
-    if (S.sigma) {
-      hipLaunchKernelGGL(k_add_conj_diag, dim3(nb), dim3(256), 0, s, out, S.sigma, S.W.t3, n, out);
-      BEM_LAUNCH_CHECK();
-    }
-  }
-  if (f32)
-    ++S.mv32;
-  else
-    ++S.mv64;
-  return 0;
-}
 
 int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjoint,
                       const std::vector<const c64*>& sigma, const std::vector<const c64*>& b,
@@ -912,14 +884,25 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
       for (auto& S : v) S.W.release();
     }
   } sys_guard{sys};
-  hipEvent_t start;
-  BEM_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming | hipEventReleaseToDevice));
-  struct EvGuard {
-    hipEvent_t e;
-    ~EvGuard() { (void)hipEventDestroy(e); }
-  } evg{start};
-  BEM_HIP_TRY(hipEventRecord(start, caller));
-  std::vector<hipStream_t> streams;
+  // every stage of the tick's products is launched once for all systems (on
+  // the caller's stream, near field and leaf-level M2L on two side streams)
+  BatchStreams bs;
+  bs.main = caller;
+  struct StreamGuard {
+    BatchStreams& b;
+    ~StreamGuard() {
+      for (auto& e : b.ev)
+        if (e) (void)hipEventDestroy(e);
+      if (b.side) (void)hipStreamDestroy(b.side);
+      if (b.side2) (void)hipStreamDestroy(b.side2);
+    }
+  } stream_guard{bs};
+  BEM_HIP_TRY(hipStreamCreateWithFlags(&bs.side, hipStreamNonBlocking));
+  BEM_HIP_TRY(hipStreamCreateWithFlags(&bs.side2, hipStreamNonBlocking));
+  for (auto& e : bs.ev)
+    BEM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventReleaseToDevice));
+  hipStream_t s = caller;
+  std::vector<Problem*> seen;
   for (int i = 0; i < ns; ++i) {
     BatchSys& S = sys[i];
     S.P = probs[i];
@@ -927,13 +910,18 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
     S.sigma = sigma[i];
     S.b = b[i];
     S.x = x[i];
-    S.s = S.P->bstream;
-    if (std::find(streams.begin(), streams.end(), S.s) == streams.end()) {
-      streams.push_back(S.s);
-      BEM_HIP_TRY(hipStreamWaitEvent(S.s, start, 0));
-    }
     int r = S.W.ensure(S.P->n, m);
     if (r) return r;
+    if (std::find(seen.begin(), seen.end(), S.P) == seen.end()) {
+      seen.push_back(S.P);
+      S.X32 = &S.P->f32.X;
+      S.X64 = &S.P->f64.X;
+    } else {  // a further system of the same problem: buffers of its own
+      if ((r = alloc_exec<float>(*S.P, S.P->f32, S.own32, S.W.arena))) return r;
+      if ((r = alloc_exec<double>(*S.P, S.P->f64, S.own64, S.W.arena))) return r;
+      S.X32 = &S.own32;
+      S.X64 = &S.own64;
+    }
     S.H.assign((size_t)(m + 1) * m, 0.0);
     S.cs.assign(m, 0.0);
     S.sn.assign(m, 0.0);
@@ -942,15 +930,15 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
   }
   // norms of the right-hand sides
   for (auto& S : sys) {
-    int r = multidot(S.W, S.b, S.P->n, S.P->n, 1, S.b, S.W.h2, S.s);
+    int r = multidot(S.W, S.b, S.P->n, S.P->n, 1, S.b, S.W.h2, s);
     if (r) return r;
-    BEM_HIP_TRY(hipMemcpyAsync(S.W.hscal, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, S.s));
+    BEM_HIP_TRY(hipMemcpyAsync(S.W.hscal, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, s));
     if (S.first) {
-      hipLaunchKernelGGL(k_set_zero, dim3(ceil_div(S.P->n, 256)), dim3(256), 0, S.s, S.x, S.P->n);
+      hipLaunchKernelGGL(k_set_zero, dim3(ceil_div(S.P->n, 256)), dim3(256), 0, s, S.x, S.P->n);
       BEM_LAUNCH_CHECK();
     }
   }
-  for (hipStream_t st : streams) BEM_HIP_TRY(hipStreamSynchronize(st));
+  BEM_HIP_TRY(hipStreamSynchronize(s));
   for (auto& S : sys) {
     S.bn = sqrt(S.W.hscal[0].re);
     if (!std::isfinite(S.bn)) {
@@ -963,32 +951,75 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
   }
   for (int tick = 0; tick < 100000; ++tick) {
     bool any = false;
-    // issue
-    for (auto& S : sys) {
+    // the tick's products: outer residuals (float64, of x) and Arnoldi steps
+    // (of V_j), grouped by precision and direction into batched products
+    std::vector<BatchItem<float>> it32[2];
+    std::vector<BatchItem<double>> it64[2];
+    std::vector<char> wants(ns, 0), is32(ns, 0);
+    for (int i = 0; i < ns; ++i) {
+      BatchSys& S = sys[i];
       if (S.state == 2) continue;
       any = true;
+      if (S.state == 0 && S.first) continue;  // r = b: no product
+      const int64_t n = S.P->n;
+      const int nb = ceil_div(n, 256);
+      const bool f32 = S.state == 1 && mode == 1;
+      const c64* vin = S.state == 0 ? S.x : S.W.V + (int64_t)S.j * n;
+      c64* vout = S.state == 0 ? S.W.t1 : S.W.w;
+      const c64* q = nullptr;
+      c64* out2 = nullptr;
+      if (!S.adjoint && S.sigma) {  // q = sigma v
+        hipLaunchKernelGGL(k_diag_mul, dim3(nb), dim3(256), 0, s, S.sigma, vin, n, 0, S.W.t3);
+        BEM_LAUNCH_CHECK();
+        q = S.W.t3;
+      }
+      if (S.adjoint && S.sigma) out2 = S.W.t3;
+      wants[i] = 1;
+      is32[i] = f32;
+      if (f32)
+        it32[S.adjoint].push_back(BatchItem<float>{S.P, &S.P->f32, S.X32, vin, q, vout, out2});
+      else
+        it64[S.adjoint].push_back(BatchItem<double>{S.P, &S.P->f64, S.X64, vin, q, vout, out2});
+    }
+    if (!any) break;
+    for (int a = 0; a < 2; ++a) {
+      int r = 0;
+      if (!it32[a].empty() && (r = fmm_apply_batch<float>(it32[a], a == 1, bs))) return r;
+      if (!it64[a].empty() && (r = fmm_apply_batch<double>(it64[a], a == 1, bs))) return r;
+    }
+    // per system: adjoint admittance term, then residual norm or orthogonalisation
+    for (int i = 0; i < ns; ++i) {
+      BatchSys& S = sys[i];
+      if (S.state == 2) continue;
       const int64_t n = S.P->n;
       const int nb = ceil_div(n, 256);
       int r = 0;
-      if (S.state == 0) {
-        if (S.first) {
-          hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, S.s, S.b, n, S.W.r);
-          BEM_LAUNCH_CHECK();
-        } else {
-          if ((r = batch_apply(S, false, S.x, S.W.t1))) return r;
-          hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, S.s, S.b, S.W.t1, n, S.W.r);
+      if (wants[i]) {
+        c64* vout = S.state == 0 ? S.W.t1 : S.W.w;
+        if (S.adjoint && S.sigma) {
+          hipLaunchKernelGGL(k_add_conj_diag, dim3(nb), dim3(256), 0, s, vout, S.sigma, S.W.t3,
+                             n, vout);
           BEM_LAUNCH_CHECK();
         }
-        if ((r = multidot(S.W, S.W.r, n, n, 1, S.W.r, S.W.h2, S.s))) return r;
-        BEM_HIP_TRY(hipMemcpyAsync(S.W.hscal, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, S.s));
+        if (is32[i])
+          ++S.mv32;
+        else
+          ++S.mv64;
+      }
+      if (S.state == 0) {
+        if (S.first) {
+          hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, S.b, n, S.W.r);
+        } else {
+          hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, s, S.b, S.W.t1, n, S.W.r);
+        }
+        BEM_LAUNCH_CHECK();
+        if ((r = multidot(S.W, S.W.r, n, n, 1, S.W.r, S.W.h2, s))) return r;
+        BEM_HIP_TRY(hipMemcpyAsync(S.W.hscal, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, s));
       } else {
-        const int j = S.j;
-        if ((r = batch_apply(S, mode == 1, S.W.V + (int64_t)j * n, S.W.w))) return r;
-        if ((r = arnoldi_orth(S.W, n, j, 0, S.s))) return r;
+        if ((r = arnoldi_orth(S.W, n, S.j, 0, s))) return r;
       }
     }
-    if (!any) break;
-    for (hipStream_t st : streams) BEM_HIP_TRY(hipStreamSynchronize(st));
+    BEM_HIP_TRY(hipStreamSynchronize(s));
     // host decisions
     for (auto& S : sys) {
       if (S.state == 2) continue;
@@ -1017,9 +1048,9 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
                                   : tol * S.bn / S.rn;
         S.atol = itol * S.rn;
         S.beta = S.rn;
-        hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, S.s, S.W.r, n, S.W.V);
+        hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, S.W.r, n, S.W.V);
         BEM_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, S.s, S.W.V, n, 1.0 / S.beta);
+        hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, s, S.W.V, n, 1.0 / S.beta);
         BEM_LAUNCH_CHECK();
         std::fill(S.g.begin(), S.g.end(), 0.0);
         S.g[0] = S.beta;
@@ -1073,8 +1104,8 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
           c64* yh = S.W.hcol + (S.W.m + 2);
           for (int i = 0; i < jend; ++i) yh[i] = mk(yv[i].real(), yv[i].imag());
           BEM_HIP_TRY(hipMemcpyAsync(S.W.y, yh, sizeof(c64) * jend,
-                                     hipMemcpyHostToDevice, S.s));
-          hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, S.s, S.W.V, n, n, jend, S.W.y, S.x);
+                                     hipMemcpyHostToDevice, s));
+          hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, S.W.V, n, n, jend, S.W.y, S.x);
           BEM_LAUNCH_CHECK();
           ++S.outer;
           S.state = 0;
@@ -1084,8 +1115,7 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
       }
     }
   }
-  // join the caller's stream
-  for (hipStream_t st : streams) BEM_HIP_TRY(hipStreamSynchronize(st));
+  BEM_HIP_TRY(hipStreamSynchronize(s));
   int worst = 0;
   for (int i = 0; i < ns; ++i) {
     BatchSys& S = sys[i];
