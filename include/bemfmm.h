@@ -99,8 +99,9 @@ typedef struct {
                           1: mixed precision - inner GMRES on the float32
                              operator, outer residuals and corrections in
                              float64 (iterative refinement)                 */
-  double inner_tol;    /* mode 1: relative tolerance of each inner solve
-                          (<= 0 -> 1e-4)                                    */
+  double inner_tol;    /* mode 1: relative residual reduction asked of the
+                          first inner solve (<= 0 -> 1e-3); later ones ask
+                          for half the reduction still needed, >= 1e-6      */
   int32_t use_x0;      /* nonzero: x holds the initial guess on entry       */
 } bem_gmres_opts;
 

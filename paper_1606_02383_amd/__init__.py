@@ -161,7 +161,7 @@ class GmresOptions:
     restart: int = 50
     max_iter: int = 2000
     mode: int = 0              # 0 float64, 1 float32 inner + float64 refinement
-    inner_tol: float = 1e-4
+    inner_tol: float = 1e-3
     use_x0: bool = False
 
     def c(self):

@@ -335,6 +335,17 @@ static int arnoldi_orth(Workspace& W, int64_t n, int j, int slot, hipStream_t s)
 
 typedef std::function<int(const c64*, c64*)> ApplyFn;
 
+// Relative residual reduction asked of the float32 inner solve at
+// refinement step `outer` (residual rn, right-hand side norm bn): the first
+// step asks for inner_tol, later ones for the reduction still needed to
+// reach tol with a factor-2 margin; never below 1e-6 (the float32 operator
+// is accurate to ~1e-5, so tighter inner targets only cost iterations).
+static double inner_target(int outer, double inner_tol, double tol, double bn, double rn) {
+  const double need = 0.5 * tol * bn / rn;
+  const double t = outer == 0 ? std::max(inner_tol > 0 ? inner_tol : 1e-3, need) : need;
+  return std::max(t, 1e-6);
+}
+
 struct GmresStats {
   int iters = 0, restarts = 0;
   double est = 0;
@@ -558,10 +569,7 @@ int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x,
       in.iters = 0;
       hipLaunchKernelGGL(k_set_zero, dim3(nb), dim3(256), 0, s, dvec, n);
       BEM_LAUNCH_CHECK();
-      // ask the inner solve only for the reduction still needed (with a
-      // factor-2 margin), never tighter than inner_tol
-      double itol = inner_tol > 0 ? inner_tol : 1e-4;
-      itol = std::max(itol, 0.5 * tol * bn / rn);
+      const double itol = inner_target(outer, inner_tol, tol, bn, rn);
       int ist = gmres_core(W, A32, rvec, dvec, n, itol * rn, restart, max_iter - st.iters, true,
                            in, s);
       st.iters += in.iters;
@@ -1044,8 +1052,8 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
           S.state = 2;
           continue;
         }
-        double itol = (mode == 1) ? std::max(inner_tol > 0 ? inner_tol : 1e-4, 0.5 * tol * S.bn / S.rn)
-                                  : tol * S.bn / S.rn;
+        const double itol = (mode == 1) ? inner_target(S.outer, inner_tol, tol, S.bn, S.rn)
+                                        : tol * S.bn / S.rn;
         S.atol = itol * S.rn;
         S.beta = S.rn;
         hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, S.W.r, n, S.W.V);
