@@ -157,30 +157,35 @@ __device__ __forceinline__ int job_of(const int (&first)[N], int njobs, int v) {
 // Buffers cleared by the first kernel of a product (targets of atomic
 // accumulation further down the chain), folded into it to save launches.
 constexpr int MAX_ZERO = MAX_LEVEL;  // every level above the leaves
-template <typename R>
+template <typename R, int NZ = MAX_ZERO>
 struct ZeroList {
   int n;
-  cplx<R>* ptr[MAX_ZERO];
-  int64_t cnt[MAX_ZERO];
+  cplx<R>* ptr[NZ];
+  int64_t cnt[NZ];
 };
 
-template <typename R>
-__device__ __forceinline__ void zero_list(const ZeroList<R>& z) {
-  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+// clears the listed buffers; thread gid of gsz threads takes entries gid,
+// gid + gsz, ...
+template <typename R, int NZ>
+__device__ __forceinline__ void zero_list(const ZeroList<R, NZ>& z, int64_t gid, int64_t gsz) {
 #pragma unroll
-  for (int q = 0; q < MAX_ZERO; ++q) {
+  for (int q = 0; q < NZ; ++q) {
     if (q >= z.n) break;
     for (int64_t i = gid; i < z.cnt[q]; i += gsz) z.ptr[q][i] = mk<R>(R(0), R(0));
   }
 }
+
+__device__ __forceinline__ int64_t grid_tid() {
+  return blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+}
+__device__ __forceinline__ int64_t grid_threads() { return (int64_t)gridDim.x * blockDim.x; }
 
 template <typename R>
 __global__ void k_gather_in(const c64* __restrict__ p, const c64* __restrict__ q,
                             const int* __restrict__ perm, int64_t n, cplx<R>* __restrict__ ps,
                             cplx<R>* __restrict__ qs, c64* __restrict__ p64,
                             c64* __restrict__ q64, const ZeroList<R> zl) {
-  zero_list(zl);
+  zero_list(zl, grid_tid(), grid_threads());
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   int o = perm[i];
@@ -873,18 +878,18 @@ __device__ __forceinline__ R group_sum16(R v) {
   return v;
 }
 
+// y[perm[i]] for element i (sorted order), lane l of its 16-lane group: far
+// field (L2P rows against the leaf's local expansion), near corrections, the
+// P2P sum ys and the float64 diagonal.  Every lane of a group calls it.
 template <typename R>
-__global__ void __launch_bounds__(256)
-    k_finish(int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
-             int ncoef, const cplx<R>* __restrict__ l2p, const cplx<R>* __restrict__ Lc,
-             const int* __restrict__ near_ptr, const int* __restrict__ near_col,
-             const cplx<R>* __restrict__ ncp, const cplx<R>* __restrict__ ncq,
-             const cplx<R>* __restrict__ ps, const cplx<R>* __restrict__ qs,
-             const cplx<R>* __restrict__ ys, const c64* __restrict__ dp,
-             const c64* __restrict__ dq, const c64* __restrict__ p64,
-             const c64* __restrict__ q64, c64* __restrict__ y) {
-  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / FIN_LANES;
-  const int l = threadIdx.x % FIN_LANES;
+__device__ __forceinline__ void finish_elem(
+    int64_t i, int l, int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
+    int ncoef, const cplx<R>* __restrict__ l2p, const cplx<R>* __restrict__ Lc,
+    const int* __restrict__ near_ptr, const int* __restrict__ near_col,
+    const cplx<R>* __restrict__ ncp, const cplx<R>* __restrict__ ncq,
+    const cplx<R>* __restrict__ ps, const cplx<R>* __restrict__ qs,
+    const cplx<R>* __restrict__ ys, const c64* __restrict__ dp, const c64* __restrict__ dq,
+    const c64* __restrict__ p64, const c64* __restrict__ q64, c64* __restrict__ y) {
   cplx<R> acc = mk<R>(0, 0);
   if (i < n) {  // whole 16-lane groups are in or out: the shuffles stay inside a group
     if (ncoef > 0) {
@@ -911,16 +916,30 @@ __global__ void __launch_bounds__(256)
 
 template <typename R>
 __global__ void __launch_bounds__(256)
-    k_finish_adj(int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
-                 int ncoef, const cplx<R>* __restrict__ p2m, const cplx<R>* __restrict__ Mc,
-                 const int* __restrict__ tptr, const int* __restrict__ trow,
-                 const cplx<R>* __restrict__ tcp, const cplx<R>* __restrict__ tcq,
-                 const cplx<R>* __restrict__ ysrt, const cplx<R>* __restrict__ us,
-                 const cplx<R>* __restrict__ ws, const c64* __restrict__ dp,
-                 const c64* __restrict__ dq, const c64* __restrict__ y64, c64* __restrict__ u,
-                 c64* __restrict__ w) {
-  const int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / FIN_LANES;
-  const int l = threadIdx.x % FIN_LANES;
+    k_finish(int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
+             int ncoef, const cplx<R>* __restrict__ l2p, const cplx<R>* __restrict__ Lc,
+             const int* __restrict__ near_ptr, const int* __restrict__ near_col,
+             const cplx<R>* __restrict__ ncp, const cplx<R>* __restrict__ ncq,
+             const cplx<R>* __restrict__ ps, const cplx<R>* __restrict__ qs,
+             const cplx<R>* __restrict__ ys, const c64* __restrict__ dp,
+             const c64* __restrict__ dq, const c64* __restrict__ p64,
+             const c64* __restrict__ q64, c64* __restrict__ y) {
+  finish_elem<R>(grid_tid() / FIN_LANES, threadIdx.x % FIN_LANES, n, perm, elem_leaf, ncoef, l2p,
+                 Lc, near_ptr, near_col, ncp, ncq, ps, qs, ys, dp, dq, p64, q64, y);
+}
+
+// u[perm[j]], w[perm[j]] of the adjoint for source element j (sorted
+// order): transposed P2M rows, transposed near corrections, the adjoint
+// P2P sums and the conjugated diagonal.  Every lane of a group calls it.
+template <typename R>
+__device__ __forceinline__ void finish_adj_elem(
+    int64_t j, int l, int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
+    int ncoef, const cplx<R>* __restrict__ p2m, const cplx<R>* __restrict__ Mc,
+    const int* __restrict__ tptr, const int* __restrict__ trow, const cplx<R>* __restrict__ tcp,
+    const cplx<R>* __restrict__ tcq, const cplx<R>* __restrict__ ysrt,
+    const cplx<R>* __restrict__ us, const cplx<R>* __restrict__ ws, const c64* __restrict__ dp,
+    const c64* __restrict__ dq, const c64* __restrict__ y64, c64* __restrict__ u,
+    c64* __restrict__ w) {
   cplx<R> au = mk<R>(0, 0), aw = mk<R>(0, 0);
   if (j < n) {
     if (ncoef > 0) {
@@ -952,6 +971,114 @@ __global__ void __launch_bounds__(256)
     if (u) u[o] = ou;
     if (w) w[o] = ow;
   }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_finish_adj(int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
+                 int ncoef, const cplx<R>* __restrict__ p2m, const cplx<R>* __restrict__ Mc,
+                 const int* __restrict__ tptr, const int* __restrict__ trow,
+                 const cplx<R>* __restrict__ tcp, const cplx<R>* __restrict__ tcq,
+                 const cplx<R>* __restrict__ ysrt, const cplx<R>* __restrict__ us,
+                 const cplx<R>* __restrict__ ws, const c64* __restrict__ dp,
+                 const c64* __restrict__ dq, const c64* __restrict__ y64, c64* __restrict__ u,
+                 c64* __restrict__ w) {
+  finish_adj_elem<R>(grid_tid() / FIN_LANES, threadIdx.x % FIN_LANES, n, perm, elem_leaf, ncoef,
+                     p2m, Mc, tptr, trow, tcp, tcq, ysrt, us, ws, dp, dq, y64, u, w);
+}
+
+// ---------------------------------------------------------------------------
+// Gather and finish of several products in one launch each (batched
+// product).  Job q owns blocks blk0[q] .. blk0[q + 1) - 1.
+// ---------------------------------------------------------------------------
+constexpr int BATCH_ZERO = 8;  // cleared levels per job in a batched gather
+
+template <typename R>
+struct GatherJobDev {
+  const c64* p;  // forward: p (user order) | adjoint: y
+  const c64* q;  // forward only, may be null
+  const int* perm;
+  int64_t n;
+  cplx<R>* ps;
+  cplx<R>* qs;
+  c64* p64;
+  c64* q64;
+  ZeroList<R, BATCH_ZERO> zl;
+};
+
+template <typename R>
+struct GatherBatch {
+  int n;
+  int blk0[MAX_JOBS + 1];
+  GatherJobDev<R> job[MAX_JOBS];
+};
+
+template <typename R, bool ADJ>
+__global__ void __launch_bounds__(256) k_gather_batch(const GatherBatch<R> batch) {
+  const int qj = job_of(batch.blk0, batch.n, (int)blockIdx.x);
+  const GatherJobDev<R> J = select_job(batch.job, qj);
+  const int b0 = select_job(batch.blk0, qj), b1 = select_job(batch.blk0, qj + 1);
+  const int64_t i = (int64_t)((int)blockIdx.x - b0) * blockDim.x + threadIdx.x;
+  zero_list(J.zl, i, (int64_t)(b1 - b0) * blockDim.x);
+  if (i >= J.n) return;
+  const int o = J.perm[i];
+  const c64 a = J.p ? J.p[o] : mk(0.0, 0.0);
+  J.ps[i] = mk<R>((R)a.re, (R)a.im);
+  J.p64[i] = a;
+  if (!ADJ) {
+    const c64 c = J.q ? J.q[o] : mk(0.0, 0.0);
+    J.qs[i] = mk<R>((R)c.re, (R)c.im);
+    J.q64[i] = c;
+  }
+}
+
+// forward: ex = L2P rows, Mx = leaf locals, near CSR by target, a/b = sorted
+// p/q, c = P2P sums, p64/q64 = float64 sorted p/q, out = y.
+// adjoint: ex = P2M rows, Mx = leaf multipoles, near CSC by source, a =
+// sorted y, b/c = P2P sums (u, w), p64 = float64 sorted y, out/out2 = u/w.
+template <typename R>
+struct FinJobDev {
+  int64_t n;
+  const int* perm;
+  const int* elem_leaf;
+  int ncoef;
+  const cplx<R>* ex;
+  const cplx<R>* Mx;
+  const int* nptr;
+  const int* nidx;
+  const cplx<R>* ncp;
+  const cplx<R>* ncq;
+  const cplx<R>* a;
+  const cplx<R>* b;
+  const cplx<R>* c;
+  const c64* dp;
+  const c64* dq;
+  const c64* p64;
+  const c64* q64;
+  c64* out;
+  c64* out2;
+};
+
+template <typename R>
+struct FinBatch {
+  int n;
+  int blk0[MAX_JOBS + 1];
+  FinJobDev<R> job[MAX_JOBS];
+};
+
+template <typename R, bool ADJ>
+__global__ void __launch_bounds__(256) k_finish_batch(const FinBatch<R> batch) {
+  const int qj = job_of(batch.blk0, batch.n, (int)blockIdx.x);
+  const FinJobDev<R> J = select_job(batch.job, qj);
+  const int64_t t = (int64_t)((int)blockIdx.x - select_job(batch.blk0, qj)) * blockDim.x +
+                    threadIdx.x;
+  const int l = threadIdx.x % FIN_LANES;
+  if (ADJ)
+    finish_adj_elem<R>(t / FIN_LANES, l, J.n, J.perm, J.elem_leaf, J.ncoef, J.ex, J.Mx, J.nptr,
+                       J.nidx, J.ncp, J.ncq, J.a, J.b, J.c, J.dp, J.dq, J.p64, J.out, J.out2);
+  else
+    finish_elem<R>(t / FIN_LANES, l, J.n, J.perm, J.elem_leaf, J.ncoef, J.ex, J.Mx, J.nptr,
+                   J.nidx, J.ncp, J.ncq, J.a, J.b, J.c, J.dp, J.dq, J.p64, J.q64, J.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1377,7 +1504,7 @@ template <typename R>
 __global__ void k_gather_adj(const c64* __restrict__ y, const int* __restrict__ perm, int64_t n,
                              cplx<R>* __restrict__ ys, c64* __restrict__ y64,
                              const ZeroList<R> zl) {
-  zero_list(zl);
+  zero_list(zl, grid_tid(), grid_threads());
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   c64 a = y[perm[i]];
@@ -1494,19 +1621,48 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
   hipStream_t s = bs.main;
   const bool sides = bs.side && bs.side2;
   hipStream_t sn = sides ? bs.side : s, sl = sides ? bs.side2 : s;
-  // gathers (and the clears of the atomically accumulated expansions)
-  for (const BatchItem<R>& it : items) {
-    Problem& P = *it.P;
-    PrecisionData<R>& D = *it.D;
-    ExecBuf<R>& X = *it.X;
-    const int nb = ceil_div(P.n, 256);
-    if (adj)
-      hipLaunchKernelGGL(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, it.in, P.perm, P.n, X.ps,
-                         X.p64s, chain_zero_list(P, D, X, true));
-    else
-      hipLaunchKernelGGL(k_gather_in<R>, dim3(nb), dim3(256), 0, s, it.in, it.q, P.perm, P.n,
-                         X.ps, X.qs, X.p64s, X.q64s, chain_zero_list(P, D, X, false));
-    BEM_LAUNCH_CHECK();
+  // gathers (and the clears of the atomically accumulated expansions), up
+  // to MAX_JOBS items per launch; an item with more cleared levels than a
+  // batched job holds gets a launch of its own
+  {
+    GatherBatch<R> gb{};
+    auto flush = [&]() -> int {
+      if (gb.n == 0) return 0;
+      if (adj)
+        hipLaunchKernelGGL((k_gather_batch<R, true>), dim3(gb.blk0[gb.n]), dim3(256), 0, s, gb);
+      else
+        hipLaunchKernelGGL((k_gather_batch<R, false>), dim3(gb.blk0[gb.n]), dim3(256), 0, s, gb);
+      BEM_LAUNCH_CHECK();
+      gb = GatherBatch<R>{};
+      return 0;
+    };
+    for (const BatchItem<R>& it : items) {
+      Problem& P = *it.P;
+      PrecisionData<R>& D = *it.D;
+      ExecBuf<R>& X = *it.X;
+      const int nb = ceil_div(P.n, 256);
+      const ZeroList<R> z = chain_zero_list(P, D, X, adj);
+      if (z.n > BATCH_ZERO) {
+        if (adj)
+          hipLaunchKernelGGL(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, it.in, P.perm, P.n, X.ps,
+                             X.p64s, z);
+        else
+          hipLaunchKernelGGL(k_gather_in<R>, dim3(nb), dim3(256), 0, s, it.in, it.q, P.perm, P.n,
+                             X.ps, X.qs, X.p64s, X.q64s, z);
+        BEM_LAUNCH_CHECK();
+        continue;
+      }
+      GatherJobDev<R>& J = gb.job[gb.n];
+      J = GatherJobDev<R>{it.in, adj ? nullptr : it.q, P.perm, P.n, X.ps, X.qs, X.p64s, X.q64s, {}};
+      J.zl.n = z.n;
+      for (int e = 0; e < z.n; ++e) {
+        J.zl.ptr[e] = z.ptr[e];
+        J.zl.cnt[e] = z.cnt[e];
+      }
+      gb.blk0[gb.n + 1] = gb.blk0[gb.n] + nb;
+      if (++gb.n == MAX_JOBS && (r = flush())) return r;
+    }
+    if ((r = flush())) return r;
   }
   // near field, by kind of alpha
   if (sides) {
@@ -1650,26 +1806,40 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
       if ((r = launch_grouped_any<R, 4>(jobs, false, s))) return r;
     }
   }
-  // finish per item
+  // finish, up to MAX_JOBS items per launch
   if (sides) BEM_HIP_TRY(hipStreamWaitEvent(s, bs.ev[1], 0));
-  for (const BatchItem<R>& it : items) {
-    Problem& P = *it.P;
-    PrecisionData<R>& D = *it.D;
-    ExecBuf<R>& X = *it.X;
-    const int64_t n = P.n;
-    const int L = P.L;
-    const int ncoef = P.direct ? 0 : D.ncoef[L];
-    if (adj)
-      hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n,
-                         P.perm, P.elem_leaf, ncoef, D.p2m, X.M[L], P.neart_ptr, P.neart_row,
-                         D.neart_cp, D.neart_cq, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s,
-                         it.out, it.out2);
-    else
-      hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n,
-                         P.perm, P.elem_leaf, ncoef, D.l2p, X.Lc[L], P.near_ptr, P.near_col,
-                         D.near_cp, D.near_cq, X.ps, X.qs, X.ys, P.diag_p, P.diag_q, X.p64s,
-                         X.q64s, it.out);
-    BEM_LAUNCH_CHECK();
+  {
+    FinBatch<R> fb{};
+    auto flush = [&]() -> int {
+      if (fb.n == 0) return 0;
+      if (adj)
+        hipLaunchKernelGGL((k_finish_batch<R, true>), dim3(fb.blk0[fb.n]), dim3(256), 0, s, fb);
+      else
+        hipLaunchKernelGGL((k_finish_batch<R, false>), dim3(fb.blk0[fb.n]), dim3(256), 0, s, fb);
+      BEM_LAUNCH_CHECK();
+      fb = FinBatch<R>{};
+      return 0;
+    };
+    for (const BatchItem<R>& it : items) {
+      Problem& P = *it.P;
+      PrecisionData<R>& D = *it.D;
+      ExecBuf<R>& X = *it.X;
+      const int L = P.L;
+      const int ncoef = P.direct ? 0 : D.ncoef[L];
+      if (adj)
+        fb.job[fb.n] = FinJobDev<R>{P.n, P.perm, P.elem_leaf, ncoef, D.p2m, X.M[L],
+                                    P.neart_ptr, P.neart_row, D.neart_cp, D.neart_cq, X.ps,
+                                    X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, nullptr, it.out,
+                                    it.out2};
+      else
+        fb.job[fb.n] = FinJobDev<R>{P.n, P.perm, P.elem_leaf, ncoef, D.l2p, X.Lc[L],
+                                    P.near_ptr, P.near_col, D.near_cp, D.near_cq, X.ps,
+                                    X.qs, X.ys, P.diag_p, P.diag_q, X.p64s, X.q64s, it.out,
+                                    nullptr};
+      fb.blk0[fb.n + 1] = fb.blk0[fb.n] + ceil_div(P.n * FIN_LANES, 256);
+      if (++fb.n == MAX_JOBS && (r = flush())) return r;
+    }
+    if ((r = flush())) return r;
   }
   return 0;
 }

@@ -38,17 +38,17 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// partial[k][bx] = sum over block bx of conj(V_k[i]) w[i], k < gridDim.y
-// (complex, interleaved re/im).  The final sums are formed by the kernel
-// that consumes them (fold_dots), so no grid-wide synchronisation is needed.
-__global__ void __launch_bounds__(RED_THREADS)
-    k_multidot_partial(const c64* __restrict__ V, int64_t ld, int64_t n,
-                       const c64* __restrict__ w, double* __restrict__ partial) {
+// Block bx's partial of conj(v)^H w (complex, interleaved re/im) into
+// out[0..1]; blocks stride the vector RED_BLOCKS apart.  The final sums are
+// formed by the kernel that consumes them (fold_dots), so no grid-wide
+// synchronisation is needed.
+__device__ __forceinline__ void dot_partial(const c64* __restrict__ v, int64_t n,
+                                            const c64* __restrict__ w, int bx,
+                                            double* __restrict__ out) {
   __shared__ double sr[RED_THREADS / 64], si[RED_THREADS / 64];
-  const int kvec = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const c64* v = V + kvec * ld;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double ar = 0, ai = 0;
-  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n;
+  for (int64_t i = bx * (int64_t)RED_THREADS + threadIdx.x; i < n;
        i += (int64_t)RED_BLOCKS * RED_THREADS) {
     c64 a = v[i], b = w[i];
     ar += a.re * b.re + a.im * b.im;
@@ -62,14 +62,23 @@ __global__ void __launch_bounds__(RED_THREADS)
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    partial[2 * (kvec * RED_BLOCKS + blockIdx.x)] = (sr[0] + sr[1]) + (sr[2] + sr[3]);
-    partial[2 * (kvec * RED_BLOCKS + blockIdx.x) + 1] = (si[0] + si[1]) + (si[2] + si[3]);
+    out[0] = (sr[0] + sr[1]) + (sr[2] + sr[3]);
+    out[1] = (si[0] + si[1]) + (si[2] + si[3]);
   }
 }
 
+// partial[k][bx] = sum over block bx of conj(V_k[i]) w[i], k < gridDim.y
+__global__ void __launch_bounds__(RED_THREADS)
+    k_multidot_partial(const c64* __restrict__ V, int64_t ld, int64_t n,
+                       const c64* __restrict__ w, double* __restrict__ partial) {
+  const int kvec = blockIdx.y;
+  dot_partial(V + kvec * ld, n, w, blockIdx.x, partial + 2 * (kvec * RED_BLOCKS + blockIdx.x));
+}
+
 // hs[k] = sum_bx partial[k][bx] for k < nk into shared memory, in a fixed
-// order (every block of the caller gets bit-identical values); block 0
-// also stores them to out.  Wave q handles k = q, q + 4, ...
+// order (every block of the caller gets bit-identical values); with out
+// non-null they are also stored there (the caller passes it to one block
+// only).  Wave q handles k = q, q + 4, ...
 __device__ __forceinline__ void fold_dots(const double* __restrict__ partial, int nk, c64* hs,
                                           c64* __restrict__ out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -81,7 +90,7 @@ __device__ __forceinline__ void fold_dots(const double* __restrict__ partial, in
     m = wave_sum(m);
     if (lane == 0) {
       hs[k] = mk(r, m);
-      if (out && blockIdx.x == 0) out[k] = mk(r, m);
+      if (out) out[k] = mk(r, m);
     }
   }
   __syncthreads();
@@ -89,16 +98,17 @@ __device__ __forceinline__ void fold_dots(const double* __restrict__ partial, in
 
 // w -= sum_k V_k h_k with h_k folded from the dot partials (h stored to
 // hout by block 0); with nrm_partial != null also the block partials of
-// ||w||^2 after the update.  nk <= MAX_NK.
+// ||w||^2 after the update.  nk <= MAX_NK; bx is the block's index within
+// the vector (256 entries per block).
 constexpr int MAX_NK = 512;
-__global__ void __launch_bounds__(256)
-    k_multiupdate(const c64* __restrict__ V, int64_t ld, int64_t n, int nk,
-                  const double* __restrict__ partial, c64* __restrict__ hout,
-                  c64* __restrict__ w, double* __restrict__ nrm_partial) {
+__device__ __forceinline__ void update_block(const c64* __restrict__ V, int64_t ld, int64_t n,
+                                             int nk, const double* __restrict__ partial,
+                                             c64* __restrict__ hout, c64* __restrict__ w,
+                                             double* __restrict__ nrm_partial, int bx) {
   __shared__ c64 hs[MAX_NK];
   __shared__ double sw[4];
-  fold_dots(partial, nk, hs, hout);
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  fold_dots(partial, nk, hs, bx == 0 ? hout : nullptr);
+  int64_t i = bx * (int64_t)blockDim.x + threadIdx.x;
   double sq = 0;
   if (i < n) {
     c64 acc = w[i];
@@ -115,17 +125,26 @@ __global__ void __launch_bounds__(256)
   sq = wave_sum(sq);
   if (lane == 0) sw[wave] = sq;
   __syncthreads();
-  if (threadIdx.x == 0) nrm_partial[blockIdx.x] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+  if (threadIdx.x == 0) nrm_partial[bx] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+}
+
+__global__ void __launch_bounds__(256)
+    k_multiupdate(const c64* __restrict__ V, int64_t ld, int64_t n, int nk,
+                  const double* __restrict__ partial, c64* __restrict__ hout,
+                  c64* __restrict__ w, double* __restrict__ nrm_partial) {
+  update_block(V, ld, n, nk, partial, hout, w, nrm_partial, blockIdx.x);
 }
 
 // V_{j+1} = w / ||w||, ||w||^2 folded from the n_part block partials.
 // Block 0 stores ||w||^2 to nrm_out and writes the step's Hessenberg column
 // to col (host memory): col[i] = h1[i] + h2[i] for i <= j, col[j+1] = ||w||^2.
-__global__ void __launch_bounds__(256)
-    k_normalise(const c64* __restrict__ src, int64_t n, const double* __restrict__ nrm_partial,
-                int n_part, c64* __restrict__ dst, c64* __restrict__ nrm_out,
-                const c64* __restrict__ h1, const c64* __restrict__ h2, int j,
-                c64* __restrict__ col) {
+__device__ __forceinline__ void normalise_block(const c64* __restrict__ src, int64_t n,
+                                                const double* __restrict__ nrm_partial,
+                                                int n_part, c64* __restrict__ dst,
+                                                c64* __restrict__ nrm_out,
+                                                const c64* __restrict__ h1,
+                                                const c64* __restrict__ h2, int j,
+                                                c64* __restrict__ col, int bx) {
   __shared__ double s_nrm;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (wave == 0) {
@@ -136,7 +155,7 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   const double nrm2 = s_nrm;
-  if (blockIdx.x == 0) {
+  if (bx == 0) {
     if (threadIdx.x == 0 && nrm_out) *nrm_out = mk(nrm2, 0.0);
     if (col) {
       for (int t = threadIdx.x; t <= j + 1; t += blockDim.x)
@@ -144,11 +163,92 @@ __global__ void __launch_bounds__(256)
       __threadfence_system();
     }
   }
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t i = bx * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = sqrt(nrm2);
   double inv = (s > 0.0) ? 1.0 / s : 0.0;
   dst[i] = mk(src[i].re * inv, src[i].im * inv);
+}
+
+__global__ void __launch_bounds__(256)
+    k_normalise(const c64* __restrict__ src, int64_t n, const double* __restrict__ nrm_partial,
+                int n_part, c64* __restrict__ dst, c64* __restrict__ nrm_out,
+                const c64* __restrict__ h1, const c64* __restrict__ h2, int j,
+                c64* __restrict__ col) {
+  normalise_block(src, n, nrm_partial, n_part, dst, nrm_out, h1, h2, j, col, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// The same CGS2 phases for several systems in one launch each (batched
+// solver).  Per-system vectors and scratch are fixed for a solve and sit in
+// a device table; the tick's jobs (system index and basis size) and their
+// block offsets are a kernel argument.  Each block finds its job by binary
+// search over the offsets and runs the single-system body on it.
+// ---------------------------------------------------------------------------
+constexpr int ORTH_MAX_JOBS = 64;
+
+struct OrthSysDev {
+  c64* V;  // (m + 1) x n basis, leading dimension n
+  c64* w;
+  int64_t n;
+  double* partial;   // RED_BLOCKS x (m + 2) complex dot partials
+  double* partial2;  // norm partials, one per 256-entry block
+  c64* h;
+  c64* h2;
+  c64* hcol;  // pinned host column (slot 0)
+};
+
+struct OrthTick {
+  int njobs;
+  int sys[ORTH_MAX_JOBS];
+  int kofs[ORTH_MAX_JOBS + 1];  // prefix sums of the basis sizes j + 1
+  int bofs[ORTH_MAX_JOBS + 1];  // prefix sums of ceil(n / 256)
+};
+
+// largest job a with ofs[a] <= x (ofs ascending, ofs[0] = 0)
+__device__ __forceinline__ int find_job(const int* ofs, int nj, int x) {
+  int lo = 0, hi = nj - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ofs[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// grid (RED_BLOCKS, kofs[njobs]): block row y is basis vector y - kofs[a]
+// of job a
+__global__ void __launch_bounds__(RED_THREADS)
+    k_orth_dots(const OrthSysDev* __restrict__ tab, const OrthTick t) {
+  const int a = find_job(t.kofs, t.njobs, blockIdx.y);
+  const OrthSysDev S = tab[t.sys[a]];
+  const int kvec = blockIdx.y - t.kofs[a];
+  dot_partial(S.V + kvec * S.n, S.n, S.w, blockIdx.x,
+              S.partial + 2 * (kvec * RED_BLOCKS + blockIdx.x));
+}
+
+// grid (bofs[njobs]); pass 0: w -= V h1 (h1 -> h); pass 1: w -= V h2
+// (h2 -> h2) and the norm partials
+__global__ void __launch_bounds__(256)
+    k_orth_update(const OrthSysDev* __restrict__ tab, const OrthTick t, int pass) {
+  const int a = find_job(t.bofs, t.njobs, blockIdx.x);
+  const OrthSysDev S = tab[t.sys[a]];
+  const int nk = t.kofs[a + 1] - t.kofs[a];
+  update_block(S.V, S.n, S.n, nk, S.partial, pass ? S.h2 : S.h, S.w,
+               pass ? S.partial2 : nullptr, blockIdx.x - t.bofs[a]);
+}
+
+// grid (bofs[njobs]): V_{j+1} = w / ||w|| and the Hessenberg column
+__global__ void __launch_bounds__(256)
+    k_orth_normalise(const OrthSysDev* __restrict__ tab, const OrthTick t) {
+  const int a = find_job(t.bofs, t.njobs, blockIdx.x);
+  const OrthSysDev S = tab[t.sys[a]];
+  const int j = t.kofs[a + 1] - t.kofs[a] - 1;
+  const int nb = t.bofs[a + 1] - t.bofs[a];
+  normalise_block(S.w, S.n, S.partial2, nb, S.V + (int64_t)(j + 1) * S.n, S.h2 + j + 1, S.h,
+                  S.h2, j, S.hcol, blockIdx.x - t.bofs[a]);
 }
 
 // out[k] = sum_bx partial[k][bx]  (one wave per k; same order as fold_dots)
@@ -860,6 +960,36 @@ void release_workspace(Problem& P) {
 // concurrently), then synchronises once and does the small host-side work
 // (norms, Givens rotations, decisions) for all systems.
 // ---------------------------------------------------------------------------
+// CGS2 step of every listed system (sys_idx[i] with basis size nk[i] and
+// length n[i]) in five launches per ORTH_MAX_JOBS systems; each column lands
+// in slot 0 of its system's pinned host buffer.
+static int orth_batch(const OrthSysDev* tab, const std::vector<int>& sys_idx,
+                      const std::vector<int>& nk, const std::vector<int64_t>& n,
+                      hipStream_t s) {
+  for (size_t a0 = 0; a0 < sys_idx.size(); a0 += ORTH_MAX_JOBS) {
+    OrthTick t{};
+    t.njobs = (int)std::min<size_t>(ORTH_MAX_JOBS, sys_idx.size() - a0);
+    for (int a = 0; a < t.njobs; ++a) {
+      if (nk[a0 + a] < 1 || nk[a0 + a] > MAX_NK) return -1;
+      t.sys[a] = sys_idx[a0 + a];
+      t.kofs[a + 1] = t.kofs[a] + nk[a0 + a];
+      t.bofs[a + 1] = t.bofs[a] + (int)ceil_div(n[a0 + a], 256);
+    }
+    const dim3 gd(RED_BLOCKS, t.kofs[t.njobs]), gb(t.bofs[t.njobs]);
+    hipLaunchKernelGGL(k_orth_dots, gd, dim3(RED_THREADS), 0, s, tab, t);
+    BEM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_orth_update, gb, dim3(256), 0, s, tab, t, 0);
+    BEM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_orth_dots, gd, dim3(RED_THREADS), 0, s, tab, t);
+    BEM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_orth_update, gb, dim3(256), 0, s, tab, t, 1);
+    BEM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_orth_normalise, gb, dim3(256), 0, s, tab, t);
+    BEM_LAUNCH_CHECK();
+  }
+  return 0;
+}
+
 struct BatchSys {
   Problem* P = nullptr;
   int adjoint = 0;
@@ -936,6 +1066,26 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
     S.g.assign(m + 1, 0.0);
     S.first = !use_x0;
   }
+  // device table of the per-system orthogonalisation operands
+  DevArena tab_arena;
+  struct ArenaGuard {
+    DevArena& a;
+    ~ArenaGuard() { a.release(); }
+  } tab_guard{tab_arena};
+  OrthSysDev* tab = nullptr;
+  {
+    int r = tab_arena.alloc((void**)&tab, sizeof(OrthSysDev) * ns);
+    if (r) return r;
+    std::vector<OrthSysDev> h(ns);
+    for (int i = 0; i < ns; ++i) {
+      Workspace& W = sys[i].W;
+      h[i] = OrthSysDev{W.V, W.w, W.n, W.partial, W.partial2, W.h, W.h2, W.hcol};
+    }
+    BEM_HIP_TRY(hipMemcpyAsync(tab, h.data(), sizeof(OrthSysDev) * ns, hipMemcpyHostToDevice, s));
+    BEM_HIP_TRY(hipStreamSynchronize(s));
+  }
+  std::vector<int> orth_sys, orth_nk;
+  std::vector<int64_t> orth_n;
   // norms of the right-hand sides
   for (auto& S : sys) {
     int r = multidot(S.W, S.b, S.P->n, S.P->n, 1, S.b, S.W.h2, s);
@@ -995,7 +1145,11 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
       if (!it32[a].empty() && (r = fmm_apply_batch<float>(it32[a], a == 1, bs))) return r;
       if (!it64[a].empty() && (r = fmm_apply_batch<double>(it64[a], a == 1, bs))) return r;
     }
-    // per system: adjoint admittance term, then residual norm or orthogonalisation
+    // per system: adjoint admittance term, then residual norm; the Arnoldi
+    // systems' orthogonalisation is merged into one set of launches
+    orth_sys.clear();
+    orth_nk.clear();
+    orth_n.clear();
     for (int i = 0; i < ns; ++i) {
       BatchSys& S = sys[i];
       if (S.state == 2) continue;
@@ -1024,8 +1178,14 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
         if ((r = multidot(S.W, S.W.r, n, n, 1, S.W.r, S.W.h2, s))) return r;
         BEM_HIP_TRY(hipMemcpyAsync(S.W.hscal, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, s));
       } else {
-        if ((r = arnoldi_orth(S.W, n, S.j, 0, s))) return r;
+        orth_sys.push_back(i);
+        orth_nk.push_back(S.j + 1);
+        orth_n.push_back(n);
       }
+    }
+    if (!orth_sys.empty()) {
+      int r = orth_batch(tab, orth_sys, orth_nk, orth_n, s);
+      if (r) return r;
     }
     BEM_HIP_TRY(hipStreamSynchronize(s));
     // host decisions
