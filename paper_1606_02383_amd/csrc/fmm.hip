@@ -835,6 +835,29 @@ struct RedBatch {
   RedJobDev<R> job[MAX_JOBS];
 };
 
+// Sum over t = t0 + slice, t0 + slice + 4, ... < t1 of cbuf[pairs[t] * ncoef + c],
+// added in ascending t.  Eight rows are loaded per step (out-of-range ones as
+// zero, which leaves the sum unchanged) so that their latencies overlap.
+template <typename R>
+__device__ __forceinline__ cplx<R> slice_sum(const int* __restrict__ pairs,
+                                             const cplx<R>* __restrict__ cbuf, int ncoef, int c,
+                                             int t0, int t1, int slice) {
+  constexpr int U = 8;
+  cplx<R> acc = mk<R>(0, 0);
+  for (int t = t0 + slice; t < t1; t += 4 * U) {
+    int p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) p[u] = t + 4 * u < t1 ? pairs[t + 4 * u] : -1;
+    cplx<R> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = p[u] >= 0 ? cbuf[(int64_t)p[u] * ncoef + c] : mk<R>(0, 0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = cadd(acc, v[u]);
+  }
+  return acc;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256)
     k_pair_reduce(const RedBatch<R> batch, int accumulate) {
@@ -850,10 +873,8 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
   for (int c0 = 0; c0 < ncoef; c0 += 64) {
     const int c = c0 + lane;
-    cplx<R> acc = mk<R>(0, 0);
-    if (c < ncoef)
-      for (int t = t0 + slice; t < t1; t += 4)
-        acc = cadd(acc, J.cbuf[(int64_t)J.pairs[t] * ncoef + c]);
+    const cplx<R> acc =
+        c < ncoef ? slice_sum<R>(J.pairs, J.cbuf, ncoef, c, t0, t1, slice) : mk<R>(0, 0);
     part[slice][lane] = acc;
     __syncthreads();
     if (slice == 0 && c < ncoef) {
@@ -879,8 +900,9 @@ __device__ __forceinline__ R group_sum16(R v) {
 }
 
 // y[perm[i]] for element i (sorted order), lane l of its 16-lane group: far
-// field (L2P rows against the leaf's local expansion), near corrections, the
-// P2P sum ys and the float64 diagonal.  Every lane of a group calls it.
+// field (L2P rows against the leaf's local expansion: Lc[elem_leaf[i]], or
+// Lc itself when elem_leaf is null), near corrections, the P2P sum ys and
+// the float64 diagonal.  Every lane of a group calls it.
 template <typename R>
 __device__ __forceinline__ void finish_elem(
     int64_t i, int l, int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
@@ -894,7 +916,7 @@ __device__ __forceinline__ void finish_elem(
   if (i < n) {  // whole 16-lane groups are in or out: the shuffles stay inside a group
     if (ncoef > 0) {
       const cplx<R>* Bi = l2p + i * ncoef;
-      const cplx<R>* Lb = Lc + (int64_t)elem_leaf[i] * ncoef;
+      const cplx<R>* Lb = elem_leaf ? Lc + (int64_t)elem_leaf[i] * ncoef : Lc;
       for (int c = l; c < ncoef; c += FIN_LANES) cfma(acc, Bi[c], Lb[c]);
     }
     for (int t = near_ptr[i] + l; t < near_ptr[i + 1]; t += FIN_LANES) {
@@ -929,8 +951,9 @@ __global__ void __launch_bounds__(256)
 }
 
 // u[perm[j]], w[perm[j]] of the adjoint for source element j (sorted
-// order): transposed P2M rows, transposed near corrections, the adjoint
-// P2P sums and the conjugated diagonal.  Every lane of a group calls it.
+// order): transposed P2M rows (against Mc[elem_leaf[j]], or Mc itself when
+// elem_leaf is null), transposed near corrections, the adjoint P2P sums and
+// the conjugated diagonal.  Every lane of a group calls it.
 template <typename R>
 __device__ __forceinline__ void finish_adj_elem(
     int64_t j, int l, int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
@@ -944,7 +967,7 @@ __device__ __forceinline__ void finish_adj_elem(
   if (j < n) {
     if (ncoef > 0) {
       const cplx<R>* Aj = p2m + j * ncoef * 2;
-      const cplx<R>* Mb = Mc + (int64_t)elem_leaf[j] * ncoef;
+      const cplx<R>* Mb = elem_leaf ? Mc + (int64_t)elem_leaf[j] * ncoef : Mc;
       for (int c = l; c < ncoef; c += FIN_LANES) {
         cplx<R> ap, aq;
         load_pair(Aj + 2 * c, ap, aq);
@@ -985,6 +1008,87 @@ __global__ void __launch_bounds__(256)
                  c64* __restrict__ w) {
   finish_adj_elem<R>(grid_tid() / FIN_LANES, threadIdx.x % FIN_LANES, n, perm, elem_leaf, ncoef,
                      p2m, Mc, tptr, trow, tcp, tcq, ysrt, us, ws, dp, dq, y64, u, w);
+}
+
+// ---------------------------------------------------------------------------
+// Leaf finish: one leaf box per block.  The leaf-level M2L reduction is
+// folded into the finish: the box's expansion = its part translated from
+// the level above (base, accumulated there onto a cleared buffer) + the sum
+// of its per-pair M2L results, formed in LDS (same order as k_pair_reduce,
+// so the values equal those of the separate reduction); then every element
+// of the leaf as in k_finish / k_finish_adj.
+// ---------------------------------------------------------------------------
+extern __shared__ double leaf_lds[];
+
+template <typename R>
+__device__ __forceinline__ void leaf_expansion(int b, int ncoef, const int* __restrict__ ptr,
+                                               const int* __restrict__ pairs,
+                                               const cplx<R>* __restrict__ cbuf,
+                                               const cplx<R>* __restrict__ base, cplx<R>* out) {
+  __shared__ cplx<R> part[4][64];
+  const int t0 = ptr[b], t1 = ptr[b + 1];
+  const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncoef; c0 += 64) {
+    const int c = c0 + lane;
+    const cplx<R> acc =
+        c < ncoef ? slice_sum<R>(pairs, cbuf, ncoef, c, t0, t1, slice) : mk<R>(0, 0);
+    part[slice][lane] = acc;
+    __syncthreads();
+    if (slice == 0 && c < ncoef)
+      out[c] = cadd(base[(int64_t)b * ncoef + c],
+                    cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane])));
+    __syncthreads();
+  }
+}
+
+// forward: y for the elements of leaf b (L2P against the leaf's locals)
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_leaf_finish(const int* __restrict__ bstart, int ncoef, const int* __restrict__ red_ptr,
+                  const int* __restrict__ red_pairs, const cplx<R>* __restrict__ cbuf,
+                  const cplx<R>* __restrict__ Lc, int64_t n, const int* __restrict__ perm,
+                  const cplx<R>* __restrict__ l2p, const int* __restrict__ near_ptr,
+                  const int* __restrict__ near_col, const cplx<R>* __restrict__ ncp,
+                  const cplx<R>* __restrict__ ncq, const cplx<R>* __restrict__ ps,
+                  const cplx<R>* __restrict__ qs, const cplx<R>* __restrict__ ys,
+                  const c64* __restrict__ dp, const c64* __restrict__ dq,
+                  const c64* __restrict__ p64, const c64* __restrict__ q64,
+                  c64* __restrict__ y) {
+  cplx<R>* Lf = reinterpret_cast<cplx<R>*>(leaf_lds);
+  const int b = blockIdx.x;
+  leaf_expansion<R>(b, ncoef, red_ptr, red_pairs, cbuf, Lc, Lf);
+  const int e0 = bstart[b], ne = bstart[b + 1] - e0;
+  const int g = threadIdx.x / FIN_LANES, l = threadIdx.x % FIN_LANES;
+  for (int e = 0; e < ne; e += 256 / FIN_LANES) {
+    const int64_t i = e + g < ne ? e0 + e + g : n;  // n: group idle this pass
+    finish_elem<R>(i, l, n, perm, nullptr, ncoef, l2p, Lf, near_ptr, near_col, ncp, ncq, ps, qs,
+                   ys, dp, dq, p64, q64, y);
+  }
+}
+
+// adjoint: u, w for the elements of leaf b (P2M^H against the leaf's
+// adjoint multipoles)
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_leaf_finish_adj(const int* __restrict__ bstart, int ncoef, const int* __restrict__ red_ptr,
+                      const int* __restrict__ red_pairs, const cplx<R>* __restrict__ cbuf,
+                      const cplx<R>* __restrict__ Mc, int64_t n, const int* __restrict__ perm,
+                      const cplx<R>* __restrict__ p2m, const int* __restrict__ tptr,
+                      const int* __restrict__ trow, const cplx<R>* __restrict__ tcp,
+                      const cplx<R>* __restrict__ tcq, const cplx<R>* __restrict__ ysrt,
+                      const cplx<R>* __restrict__ us, const cplx<R>* __restrict__ ws,
+                      const c64* __restrict__ dp, const c64* __restrict__ dq,
+                      const c64* __restrict__ y64, c64* __restrict__ u, c64* __restrict__ w) {
+  cplx<R>* Mf = reinterpret_cast<cplx<R>*>(leaf_lds);
+  const int b = blockIdx.x;
+  leaf_expansion<R>(b, ncoef, red_ptr, red_pairs, cbuf, Mc, Mf);
+  const int e0 = bstart[b], ne = bstart[b + 1] - e0;
+  const int g = threadIdx.x / FIN_LANES, l = threadIdx.x % FIN_LANES;
+  for (int e = 0; e < ne; e += 256 / FIN_LANES) {
+    const int64_t j = e + g < ne ? e0 + e + g : n;
+    finish_adj_elem<R>(j, l, n, perm, nullptr, ncoef, p2m, Mf, tptr, trow, tcp, tcq, ysrt, us, ws,
+                       dp, dq, y64, u, w);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1157,7 +1261,8 @@ static int launch_gemm_ct(const GemmBatch<R>& b, int ct, int nt, hipStream_t s) 
 template <typename R, int KIND>
 static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStream_t s,
                                int accumulate = 0, Problem* prof = nullptr,
-                               int st_gemm = ST_M2L, int grid_cap = 0) {
+                               int st_gemm = ST_M2L, int grid_cap = 0,
+                               bool run_reduce = true) {
   if (nj <= 0) return 0;
   if (nj > MAX_JOBS) {
     set_error("too many grouped products in one launch");
@@ -1219,7 +1324,7 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
     }
   }
   // the reduction also runs with no tiles: it then clears the destinations
-  if (KIND == 0 && nbox > 0) {
+  if (KIND == 0 && nbox > 0 && run_reduce) {
     int ev = prof ? prof_begin(*prof, s) : -1;
     hipLaunchKernelGGL(k_pair_reduce<R>, dim3(nbox), dim3(256), 0, s, rb, accumulate);
     BEM_LAUNCH_CHECK();
@@ -1235,9 +1340,45 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
 template <typename R, int KIND>
 static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, cplx<R>* dst,
                           hipStream_t s, cplx<R>* cbuf = nullptr, int accumulate = 0,
-                          Problem* prof = nullptr, int st_gemm = ST_M2L, int grid_cap = 0) {
+                          Problem* prof = nullptr, int st_gemm = ST_M2L, int grid_cap = 0,
+                          bool run_reduce = true) {
   GemmJob<R> j{&op, src, dst, cbuf};
-  return launch_grouped_jobs<R, KIND>(&j, 1, adj, s, accumulate, prof, st_gemm, grid_cap);
+  return launch_grouped_jobs<R, KIND>(&j, 1, adj, s, accumulate, prof, st_gemm, grid_cap,
+                                      run_reduce);
+}
+
+// The per-destination reductions of several M2L products (their GEMMs
+// launched with run_reduce = false), up to MAX_JOBS per launch.
+template <typename R>
+static int launch_reduce_jobs(const std::vector<GemmJob<R>>& jobs, bool adj, hipStream_t s,
+                              Problem* prof = nullptr, int st_red = ST_M2L_RED) {
+  for (size_t a = 0; a < jobs.size(); a += MAX_JOBS) {
+    const int nj = (int)std::min<size_t>(MAX_JOBS, jobs.size() - a);
+    RedBatch<R> rb{};
+    rb.n = nj;
+    int nbox = 0;
+    for (int q = 0; q < nj; ++q) {
+      const GroupedOp<R>& op = *jobs[a + q].op;
+      RedJobDev<R>& RJ = rb.job[q];
+      RJ.ncoef = adj ? op.cols : op.rows;
+      RJ.ptr = adj ? op.red_ptr_adj : op.red_ptr;
+      RJ.pairs = adj ? op.red_pairs_adj : op.red_pairs;
+      RJ.cbuf = jobs[a + q].cbuf;
+      RJ.dst = jobs[a + q].dst;
+      rb.box0[q] = nbox;
+      nbox += adj ? op.n_red_adj : op.n_red;
+    }
+    rb.box0[nj] = nbox;
+    if (nbox == 0) continue;
+    int ev = prof ? prof_begin(*prof, s) : -1;
+    hipLaunchKernelGGL(k_pair_reduce<R>, dim3(nbox), dim3(256), 0, s, rb, 0);
+    BEM_LAUNCH_CHECK();
+    if (prof) {
+      int pr = prof_end(*prof, ev, prof_slot(st_red, sizeof(R) == 4, adj), s);
+      if (pr) return pr;
+    }
+  }
+  return 0;
 }
 
 // near-field job of one problem (buffers X)
@@ -1329,6 +1470,7 @@ template <typename R>
 static int launch_coarse_m2l(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj,
                              hipStream_t s) {
   const int L = P.L;
+  std::vector<GemmJob<R>> all;
   int l = 2;
   while (l < L) {
     GemmJob<R> jobs[MAX_JOBS];
@@ -1339,11 +1481,13 @@ static int launch_coarse_m2l(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, boo
       jobs[nj].src = adj ? X.Lc[l] : X.M[l];
       jobs[nj].dst = adj ? X.M[l] : X.Lc[l];
       jobs[nj].cbuf = X.cbuf + D.cbuf_off[l];
+      all.push_back(jobs[nj]);
     }
-    int r = launch_grouped_jobs<R, 0>(jobs, nj, adj, s, 0, P.prof_on ? &P : nullptr);
+    int r = launch_grouped_jobs<R, 0>(jobs, nj, adj, s, 0, P.prof_on ? &P : nullptr, ST_M2L, 0,
+                                      false);
     if (r) return r;
   }
-  return 0;
+  return launch_reduce_jobs<R>(all, adj, s, P.prof_on ? &P : nullptr);
 }
 
 // Upward pass: leaf multipoles to the n_direct levels above in one launch
@@ -1375,21 +1519,20 @@ static int upward_pass(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj,
 }
 
 // Downward pass: the level-by-level chain down to level L - n_direct (totals
-// there), then all n_direct levels to the leaves in one launch (KIND 4,
-// after `leaf_ready`: the leaf-level M2L result is written on another
-// stream).  Adjoint: the mirror image (M2M^H chain, direct M2M^H).
+// there), then all n_direct levels to the leaves in one launch (KIND 4).
+// The leaf level receives only the translated part (onto a cleared buffer);
+// the leaf finish adds the leaf-level M2L.  Adjoint: the mirror image (M2M^H
+// chain, direct M2M^H).
 template <typename R>
 static int downward_pass(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj,
-                         hipStream_t s, hipEvent_t leaf_ready) {
+                         hipStream_t s) {
   const int L = P.L, nd = std::min(D.n_direct, P.ndir[sizeof(R) == 4]);
   int r = 0;
   for (int l = 3; l <= L - nd; ++l) {
-    if (l == L && leaf_ready) BEM_HIP_TRY(hipStreamWaitEvent(s, leaf_ready, 0));
     r = adj ? launch_grouped<R, 1>(D.m2m[l], true, X.M[l - 1], X.M[l], s)
             : launch_grouped<R, 2>(D.l2l[l], false, X.Lc[l - 1], X.Lc[l], s);
     if (r) return r;
   }
-  if ((nd > 0 || L < 3) && leaf_ready) BEM_HIP_TRY(hipStreamWaitEvent(s, leaf_ready, 0));
   if (nd > 0) {
     GemmJob<R> jobs[MAX_JOBS];
     for (int d = 1; d <= nd; ++d) {
@@ -1405,12 +1548,20 @@ static int downward_pass(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool ad
 }
 
 // the parent-level expansions accumulated atomically in the chain (M for the
-// forward upward pass, L for the adjoint one), cleared by the gather kernel
+// forward upward pass, L for the adjoint one), cleared by the gather kernel;
+// with leaf, also the leaf-level target of the downward pass (L forward, M
+// adjoint), whose M2L part the leaf finish adds
 template <typename R>
-static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj) {
+static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj,
+                                   bool leaf = false) {
   ZeroList<R> z{};
   z.n = 0;
   if (P.direct) return z;
+  if (leaf) {
+    z.ptr[z.n] = adj ? X.M[P.L] : X.Lc[P.L];
+    z.cnt[z.n] = (int64_t)P.nbox[P.L] * D.ncoef[P.L];
+    ++z.n;
+  }
   for (int l = P.L - 1; l >= 2 && z.n < MAX_ZERO; --l) {
     z.ptr[z.n] = adj ? X.Lc[l] : X.M[l];
     z.cnt[z.n] = (int64_t)P.nbox[l] * D.ncoef[l];
@@ -1419,6 +1570,20 @@ static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, ExecBuf<R>& 
   return z;
 }
 
+
+// Join before the finish: with the leaf-level M2L on the third stream, that
+// stream first waits for the near field, so the caller's stream waits on a
+// single event (each wait costs the caller's stream a few microseconds).
+static int join_side_streams(Problem& P, hipStream_t s, bool leaf_side) {
+  if (leaf_side) {
+    BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_join, 0));
+    BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
+    BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
+  } else {
+    BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
+  }
+  return 0;
+}
 
 template <typename R>
 int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, const c64* q,
@@ -1430,7 +1595,7 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   int nb = ceil_div(n, 256);
   PROF_BEGIN(e0);
   hipLaunchKernelGGL(k_gather_in<R>, dim3(nb), dim3(256), 0, s, p, q, P.perm, n, X.ps, X.qs,
-                     X.p64s, X.q64s, chain_zero_list(P, D, X, false));
+                     X.p64s, X.q64s, chain_zero_list(P, D, X, false, true));
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
@@ -1476,11 +1641,11 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
     BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
     BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   }
+  // (its per-destination sums are formed by the leaf finish)
   if ((r = launch_grouped<R, 0>(D.m2l[L], false, X.M[L], X.Lc[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
-                                P.m2l_cap[sizeof(R) == 4])))
+                                P.m2l_cap[sizeof(R) == 4], false)))
     return r;
-  if (leaf_side) BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e3);
   if ((r = upward_pass<R>(P, D, X, false, s))) return r;
@@ -1488,14 +1653,18 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   if (sched == SCHED_P2P_AFTER_UP && (r = launch_p2p())) return r;
   if ((r = launch_coarse_m2l<R>(P, D, X, false, s))) return r;
   PROF_BEGIN(e5);
-  if ((r = downward_pass<R>(P, D, X, false, s, leaf_side ? P.ev_join2 : nullptr))) return r;
+  if ((r = downward_pass<R>(P, D, X, false, s))) return r;
   PROF_END(e5, ST_L2L);
-  BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
+  if ((r = join_side_streams(P, s, leaf_side))) return r;
   PROF_BEGIN(e6);
-  hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
-                     P.elem_leaf, D.ncoef[L], D.l2p, X.Lc[L], P.near_ptr, P.near_col, D.near_cp,
-                     D.near_cq, X.ps, X.qs, X.ys, P.diag_p, P.diag_q, X.p64s, X.q64s, y);
-  BEM_LAUNCH_CHECK();
+  {
+    const GroupedOp<R>& op = D.m2l[L];
+    hipLaunchKernelGGL(k_leaf_finish<R>, dim3(nleaf), dim3(256), sizeof(cplx<R>) * D.ncoef[L], s,
+                       P.box_start[L], D.ncoef[L], op.red_ptr, op.red_pairs, X.cbufL, X.Lc[L], n,
+                       P.perm, D.l2p, P.near_ptr, P.near_col, D.near_cp, D.near_cq, X.ps, X.qs,
+                       X.ys, P.diag_p, P.diag_q, X.p64s, X.q64s, y);
+    BEM_LAUNCH_CHECK();
+  }
   PROF_END(e6, ST_FINISH);
   return 0;
 }
@@ -1523,7 +1692,7 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   // sorted input in X.ps, X.p64s; P2P results in X.ys (u) and X.ys2 (w)
   PROF_BEGIN(e0);
   hipLaunchKernelGGL(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, y, P.perm, n, X.ps, X.p64s,
-                     chain_zero_list(P, D, X, true));
+                     chain_zero_list(P, D, X, true, true));
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
@@ -1571,9 +1740,8 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   }
   if ((r = launch_grouped<R, 0>(D.m2l[L], true, X.Lc[L], X.M[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
-                                P.m2l_cap[sizeof(R) == 4])))
+                                P.m2l_cap[sizeof(R) == 4], false)))
     return r;
-  if (leaf_side) BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
   if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e5);
   if ((r = upward_pass<R>(P, D, X, true, s))) return r;
@@ -1581,14 +1749,18 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   if (sched == SCHED_P2P_AFTER_UP && (r = launch_p2p())) return r;
   if ((r = launch_coarse_m2l<R>(P, D, X, true, s))) return r;
   PROF_BEGIN(e3);
-  if ((r = downward_pass<R>(P, D, X, true, s, leaf_side ? P.ev_join2 : nullptr))) return r;
+  if ((r = downward_pass<R>(P, D, X, true, s))) return r;
   PROF_END(e3, ST_M2M);
-  BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
+  if ((r = join_side_streams(P, s, leaf_side))) return r;
   PROF_BEGIN(e6);
-  hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
-                     P.elem_leaf, D.ncoef[L], D.p2m, X.M[L], P.neart_ptr, P.neart_row,
-                     D.neart_cp, D.neart_cq, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, u, w);
-  BEM_LAUNCH_CHECK();
+  {
+    const GroupedOp<R>& op = D.m2l[L];
+    hipLaunchKernelGGL(k_leaf_finish_adj<R>, dim3(nleaf), dim3(256), sizeof(cplx<R>) * D.ncoef[L],
+                       s, P.box_start[L], D.ncoef[L], op.red_ptr_adj, op.red_pairs_adj, X.cbufL,
+                       X.M[L], n, P.perm, D.p2m, P.neart_ptr, P.neart_row, D.neart_cp,
+                       D.neart_cq, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, u, w);
+    BEM_LAUNCH_CHECK();
+  }
   PROF_END(e6, ST_FINISH);
   return 0;
 }
@@ -1602,11 +1774,12 @@ static int launch_grouped_any(const std::vector<GemmJob<R>>& jobs, bool adj, hip
       if ((adj ? j.op->ct_adj : j.op->ct) == ct) g.push_back(j);
     for (size_t a = 0; a < g.size(); a += MAX_JOBS) {
       const int nj = (int)std::min<size_t>(MAX_JOBS, g.size() - a);
-      int r = launch_grouped_jobs<R, KIND>(&g[a], nj, adj, s);
+      int r = launch_grouped_jobs<R, KIND>(&g[a], nj, adj, s, 0, nullptr, ST_M2L, 0, false);
       if (r) return r;
     }
   }
-  return 0;
+  // M2L: the per-destination reductions of every tile width in one pass
+  return KIND == 0 ? launch_reduce_jobs<R>(jobs, adj, s) : 0;
 }
 
 // The batched product: the per-element stages (gather, finish) run per
