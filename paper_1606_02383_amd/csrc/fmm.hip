@@ -220,6 +220,12 @@ struct P2PJobDev {
   cplx<R>* ys2;
   R k, alr, ali;
   int all_src;
+  // near-field corrections (accurate minus rule integrals): CSR by target
+  // element (forward) or by source element (adjoint)
+  const int* nptr;
+  const int* nidx;
+  const cplx<R>* ncp;
+  const cplx<R>* ncq;
 };
 template <typename R>
 struct P2PBatch {
@@ -329,6 +335,14 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p(const P2PBatch<R> batch) {
         }
       }
     }
+    if (active) {  // near-field corrections of target i, split over the slices
+      const int* __restrict__ nptr = J.nptr;
+      for (int t = nptr[i] + sl; t < nptr[i + 1]; t += nsl) {
+        const int j = J.nidx[t];
+        cfma(acc, J.ncp[t], ps[j]);
+        cfma(acc, J.ncq[t], qs[j]);
+      }
+    }
     __syncthreads();
     s_red[tid] = active ? acc : mk<R>(0, 0);
     __syncthreads();
@@ -349,7 +363,7 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p_adj(const P2PBatch<R> batch
   __shared__ R s_y[2][P2P_CHUNK];
   __shared__ int s_id[P2P_CHUNK];
   __shared__ int s_nb[28], s_pre[28];
-  __shared__ cplx<R> s_red[2][P2P_THREADS];
+  __shared__ cplx<R> s_red[4][P2P_THREADS];
   const int tid = threadIdx.x;
   // grid-stride over the leaves of all jobs (the grid may be capped)
   for (int vb = blockIdx.x; vb < batch.total; vb += gridDim.x) {
@@ -435,20 +449,34 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p_adj(const P2PBatch<R> batch
         }
       }
     }
+    // transposed near-field corrections of source j, split over the slices
+    cplx<R> cu = mk<R>(0, 0), cw = mk<R>(0, 0);
+    if (active) {
+      const int* __restrict__ nptr = J.nptr;
+      for (int t = nptr[j] + sl; t < nptr[j + 1]; t += nsl) {
+        const cplx<R> yv = ysrt[J.nidx[t]];
+        cfmac(cu, J.ncp[t], yv);
+        cfmac(cw, J.ncq[t], yv);
+      }
+    }
     __syncthreads();
     s_red[0][tid] = active ? au : mk<R>(0, 0);
     s_red[1][tid] = active ? aw : mk<R>(0, 0);
+    s_red[2][tid] = cu;
+    s_red[3][tid] = cw;
     __syncthreads();
     if (tid < nTg) {
-      cplx<R> su = mk<R>(0, 0), sw = mk<R>(0, 0);
+      cplx<R> su = mk<R>(0, 0), sw = mk<R>(0, 0), scu = mk<R>(0, 0), scw = mk<R>(0, 0);
       for (int q2 = 0; q2 < nsl; ++q2) {
         su = cadd(su, s_red[0][q2 * nTg + tid]);
         sw = cadd(sw, s_red[1][q2 * nTg + tid]);
+        scu = cadd(scu, s_red[2][q2 * nTg + tid]);
+        scw = cadd(scw, s_red[3][q2 * nTg + tid]);
       }
       // per-point weight of element j (rule weight x area / (4 pi))
       const R wj = geo[GEO_AREA * n + t0 + tg + tid] * R(1.0 / 3.0) * R(INV_4PI_D);
-      us[t0 + tg + tid] = cscale(su, wj);
-      ws[t0 + tg + tid] = cscale(sw, wj);
+      us[t0 + tg + tid] = cadd(cscale(su, wj), scu);
+      ws[t0 + tg + tid] = cadd(cscale(sw, wj), scw);
     }
   }
   }
@@ -901,8 +929,9 @@ __device__ __forceinline__ R group_sum16(R v) {
 
 // y[perm[i]] for element i (sorted order), lane l of its 16-lane group: far
 // field (L2P rows against the leaf's local expansion: Lc[elem_leaf[i]], or
-// Lc itself when elem_leaf is null), near corrections, the P2P sum ys and
-// the float64 diagonal.  Every lane of a group calls it.
+// Lc itself when elem_leaf is null), near corrections when near_ptr is
+// non-null (the products pass null: their P2P kernels apply them), the P2P
+// sum ys and the float64 diagonal.  Every lane of a group calls it.
 template <typename R>
 __device__ __forceinline__ void finish_elem(
     int64_t i, int l, int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
@@ -919,11 +948,12 @@ __device__ __forceinline__ void finish_elem(
       const cplx<R>* Lb = elem_leaf ? Lc + (int64_t)elem_leaf[i] * ncoef : Lc;
       for (int c = l; c < ncoef; c += FIN_LANES) cfma(acc, Bi[c], Lb[c]);
     }
-    for (int t = near_ptr[i] + l; t < near_ptr[i + 1]; t += FIN_LANES) {
-      const int j = near_col[t];
-      cfma(acc, ncp[t], ps[j]);
-      cfma(acc, ncq[t], qs[j]);
-    }
+    if (near_ptr)
+      for (int t = near_ptr[i] + l; t < near_ptr[i + 1]; t += FIN_LANES) {
+        const int j = near_col[t];
+        cfma(acc, ncp[t], ps[j]);
+        cfma(acc, ncq[t], qs[j]);
+      }
   }
   acc.re = group_sum16(acc.re);
   acc.im = group_sum16(acc.im);
@@ -952,7 +982,8 @@ __global__ void __launch_bounds__(256)
 
 // u[perm[j]], w[perm[j]] of the adjoint for source element j (sorted
 // order): transposed P2M rows (against Mc[elem_leaf[j]], or Mc itself when
-// elem_leaf is null), transposed near corrections, the adjoint P2P sums and
+// elem_leaf is null), transposed near corrections when tptr is non-null (the
+// products pass null: their P2P kernels apply them), the adjoint P2P sums and
 // the conjugated diagonal.  Every lane of a group calls it.
 template <typename R>
 __device__ __forceinline__ void finish_adj_elem(
@@ -975,11 +1006,12 @@ __device__ __forceinline__ void finish_adj_elem(
         cfmac(aw, aq, Mb[c]);
       }
     }
-    for (int t = tptr[j] + l; t < tptr[j + 1]; t += FIN_LANES) {
-      cplx<R> yv = ysrt[trow[t]];
-      cfmac(au, tcp[t], yv);
-      cfmac(aw, tcq[t], yv);
-    }
+    if (tptr)
+      for (int t = tptr[j] + l; t < tptr[j + 1]; t += FIN_LANES) {
+        cplx<R> yv = ysrt[trow[t]];
+        cfmac(au, tcp[t], yv);
+        cfmac(aw, tcq[t], yv);
+      }
   }
   au.re = group_sum16(au.re);
   au.im = group_sum16(au.im);
@@ -1383,7 +1415,7 @@ static int launch_reduce_jobs(const std::vector<GemmJob<R>>& jobs, bool adj, hip
 
 // near-field job of one problem (buffers X)
 template <typename R>
-static P2PJobDev<R> p2p_job(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X) {
+static P2PJobDev<R> p2p_job(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool adj) {
   P2PJobDev<R> j{};
   j.geo = D.geo;
   j.n = P.n;
@@ -1398,6 +1430,10 @@ static P2PJobDev<R> p2p_job(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X) {
   j.alr = (R)P.alpha.re;
   j.ali = (R)P.alpha.im;
   j.all_src = P.direct ? 1 : 0;
+  j.nptr = adj ? P.neart_ptr : P.near_ptr;
+  j.nidx = adj ? P.neart_row : P.near_col;
+  j.ncp = adj ? D.neart_cp : D.near_cp;
+  j.ncq = adj ? D.neart_cq : D.near_cq;
   return j;
 }
 
@@ -1609,7 +1645,7 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
       BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
     }
     int e1 = prof_begin(P, sn);
-    const P2PJobDev<R> job = p2p_job(P, D, X);
+    const P2PJobDev<R> job = p2p_job(P, D, X, false);
     int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, false, P.alpha.re == 0.0, cap, sn);
     if (rr) return rr;
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, false), sn);
@@ -1622,8 +1658,8 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
-                       P.elem_leaf, 0, D.l2p, X.Lc[L], P.near_ptr, P.near_col, D.near_cp,
-                       D.near_cq, X.ps, X.qs, X.ys, P.diag_p, P.diag_q, X.p64s, X.q64s, y);
+                       P.elem_leaf, 0, D.l2p, X.Lc[L], nullptr, nullptr, nullptr,
+                       nullptr, X.ps, X.qs, X.ys, P.diag_p, P.diag_q, X.p64s, X.q64s, y);
     BEM_LAUNCH_CHECK();
     return 0;
   }
@@ -1661,7 +1697,7 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
     const GroupedOp<R>& op = D.m2l[L];
     hipLaunchKernelGGL(k_leaf_finish<R>, dim3(nleaf), dim3(256), sizeof(cplx<R>) * D.ncoef[L], s,
                        P.box_start[L], D.ncoef[L], op.red_ptr, op.red_pairs, X.cbufL, X.Lc[L], n,
-                       P.perm, D.l2p, P.near_ptr, P.near_col, D.near_cp, D.near_cq, X.ps, X.qs,
+                       P.perm, D.l2p, nullptr, nullptr, nullptr, nullptr, X.ps, X.qs,
                        X.ys, P.diag_p, P.diag_q, X.p64s, X.q64s, y);
     BEM_LAUNCH_CHECK();
   }
@@ -1705,7 +1741,7 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
       BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
     }
     int e1 = prof_begin(P, sn);
-    const P2PJobDev<R> job = p2p_job(P, D, X);
+    const P2PJobDev<R> job = p2p_job(P, D, X, true);
     int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, true, P.alpha.re == 0.0, cap, sn);
     if (rr) return rr;
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, true), sn);
@@ -1718,8 +1754,8 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
-                       P.elem_leaf, 0, D.p2m, X.M[L], P.neart_ptr, P.neart_row, D.neart_cp,
-                       D.neart_cq, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, u, w);
+                       P.elem_leaf, 0, D.p2m, X.M[L], nullptr, nullptr, nullptr,
+                       nullptr, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, u, w);
     BEM_LAUNCH_CHECK();
     return 0;
   }
@@ -1757,8 +1793,8 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
     const GroupedOp<R>& op = D.m2l[L];
     hipLaunchKernelGGL(k_leaf_finish_adj<R>, dim3(nleaf), dim3(256), sizeof(cplx<R>) * D.ncoef[L],
                        s, P.box_start[L], D.ncoef[L], op.red_ptr_adj, op.red_pairs_adj, X.cbufL,
-                       X.M[L], n, P.perm, D.p2m, P.neart_ptr, P.neart_row, D.neart_cp,
-                       D.neart_cq, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, u, w);
+                       X.M[L], n, P.perm, D.p2m, nullptr, nullptr, nullptr,
+                       nullptr, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, u, w);
     BEM_LAUNCH_CHECK();
   }
   PROF_END(e6, ST_FINISH);
@@ -1847,7 +1883,7 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
     std::vector<int> nl;
     for (const BatchItem<R>& it : items)
       if ((it.P->alpha.re == 0.0) == (imag == 1)) {
-        jobs.push_back(p2p_job(*it.P, *it.D, *it.X));
+        jobs.push_back(p2p_job(*it.P, *it.D, *it.X, adj));
         nl.push_back(it.P->nbox[it.P->L]);
       }
     for (size_t a = 0; a < jobs.size(); a += MAX_JOBS) {
@@ -2001,12 +2037,12 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
       const int ncoef = P.direct ? 0 : D.ncoef[L];
       if (adj)
         fb.job[fb.n] = FinJobDev<R>{P.n, P.perm, P.elem_leaf, ncoef, D.p2m, X.M[L],
-                                    P.neart_ptr, P.neart_row, D.neart_cp, D.neart_cq, X.ps,
+                                    nullptr, nullptr, nullptr, nullptr, X.ps,
                                     X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, nullptr, it.out,
                                     it.out2};
       else
         fb.job[fb.n] = FinJobDev<R>{P.n, P.perm, P.elem_leaf, ncoef, D.l2p, X.Lc[L],
-                                    P.near_ptr, P.near_col, D.near_cp, D.near_cq, X.ps,
+                                    nullptr, nullptr, nullptr, nullptr, X.ps,
                                     X.qs, X.ys, P.diag_p, P.diag_q, X.p64s, X.q64s, it.out,
                                     nullptr};
       fb.blk0[fb.n + 1] = fb.blk0[fb.n] + ceil_div(P.n * FIN_LANES, 256);
