@@ -26,6 +26,8 @@
 
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "phase64.h"
 #include "plan.h"
 
@@ -149,6 +151,18 @@ __device__ __forceinline__ int job_of(const int (&first)[N], int njobs, int v) {
   for (int i = 1; i < N - 1; ++i)
     if (i < njobs && v >= first[i]) q = i;
   return q;
+}
+
+// Launch whose completion signals `done` (when non-null) as part of the
+// dispatch itself: fork and join points between streams then need no
+// separate event record (a marker that costs the stream an extra gap).
+template <typename... KArgs, typename... Args>
+static void launch_done(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds,
+                        hipStream_t s, hipEvent_t done, Args... args) {
+  if (done)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, nullptr, done, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
 }
 
 // ---------------------------------------------------------------------------
@@ -1265,20 +1279,21 @@ struct GemmJob {
 };
 
 template <typename R, int CT, bool ADJ, int KIND>
-static void launch_gemm(const GemmBatch<R>& b, int nt, hipStream_t s) {
-  hipLaunchKernelGGL((k_grouped_gemm<R, CT, ADJ, KIND>), dim3(nt), dim3(64 * TileShape<CT>::NW), 0,
-                     s, b);
+static void launch_gemm(const GemmBatch<R>& b, int nt, hipStream_t s, hipEvent_t done) {
+  launch_done(k_grouped_gemm<R, CT, ADJ, KIND>, dim3(nt), dim3(64 * TileShape<CT>::NW), 0, s,
+              done, b);
 }
 
 template <typename R, bool ADJ, int KIND>
-static int launch_gemm_ct(const GemmBatch<R>& b, int ct, int nt, hipStream_t s) {
+static int launch_gemm_ct(const GemmBatch<R>& b, int ct, int nt, hipStream_t s,
+                          hipEvent_t done = nullptr) {
   switch (ct) {
-    case 16: launch_gemm<R, 16, ADJ, KIND>(b, nt, s); break;
-    case 32: launch_gemm<R, 32, ADJ, KIND>(b, nt, s); break;
-    case 64: launch_gemm<R, 64, ADJ, KIND>(b, nt, s); break;
+    case 16: launch_gemm<R, 16, ADJ, KIND>(b, nt, s, done); break;
+    case 32: launch_gemm<R, 32, ADJ, KIND>(b, nt, s, done); break;
+    case 64: launch_gemm<R, 64, ADJ, KIND>(b, nt, s, done); break;
     case 128:
       if constexpr (sizeof(R) == 4) {
-        launch_gemm<R, 128, ADJ, KIND>(b, nt, s);
+        launch_gemm<R, 128, ADJ, KIND>(b, nt, s, done);
         break;
       } else {
         set_error("128-pair tiles are float32 only");
@@ -1294,8 +1309,16 @@ template <typename R, int KIND>
 static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStream_t s,
                                int accumulate = 0, Problem* prof = nullptr,
                                int st_gemm = ST_M2L, int grid_cap = 0,
-                               bool run_reduce = true) {
-  if (nj <= 0) return 0;
+                               bool run_reduce = true, hipEvent_t done = nullptr) {
+  // `done`: signalled by the GEMM launch (only with run_reduce = false)
+  if (done && run_reduce) {
+    set_error("completion event of a grouped product with its reduction");
+    return -1;
+  }
+  if (nj <= 0) {
+    if (done) BEM_HIP_TRY(hipEventRecord(done, s));
+    return 0;
+  }
   if (nj > MAX_JOBS) {
     set_error("too many grouped products in one launch");
     return -1;
@@ -1344,11 +1367,12 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
   b.tile0[nj] = nt;
   b.ntiles = nt;
   rb.box0[nj] = nbox;
+  if (nt == 0 && done) BEM_HIP_TRY(hipEventRecord(done, s));
   if (nt > 0) {
     int evg = prof ? prof_begin(*prof, s) : -1;
     const int grid = (grid_cap > 0 && grid_cap < nt) ? (grid_cap & ~7) : nt;
-    int r = adj ? launch_gemm_ct<R, true, KIND>(b, ct, grid > 0 ? grid : nt, s)
-                : launch_gemm_ct<R, false, KIND>(b, ct, grid > 0 ? grid : nt, s);
+    int r = adj ? launch_gemm_ct<R, true, KIND>(b, ct, grid > 0 ? grid : nt, s, done)
+                : launch_gemm_ct<R, false, KIND>(b, ct, grid > 0 ? grid : nt, s, done);
     if (r) return r;
     if (prof) {
       int pr = prof_end(*prof, evg, prof_slot(st_gemm, sizeof(R) == 4, adj), s);
@@ -1373,10 +1397,10 @@ template <typename R, int KIND>
 static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, cplx<R>* dst,
                           hipStream_t s, cplx<R>* cbuf = nullptr, int accumulate = 0,
                           Problem* prof = nullptr, int st_gemm = ST_M2L, int grid_cap = 0,
-                          bool run_reduce = true) {
+                          bool run_reduce = true, hipEvent_t done = nullptr) {
   GemmJob<R> j{&op, src, dst, cbuf};
   return launch_grouped_jobs<R, KIND>(&j, 1, adj, s, accumulate, prof, st_gemm, grid_cap,
-                                      run_reduce);
+                                      run_reduce, done);
 }
 
 // The per-destination reductions of several M2L products (their GEMMs
@@ -1441,8 +1465,11 @@ static P2PJobDev<R> p2p_job(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, bool
 // grid_cap > 0 caps the grid (grid-stride over the leaves)
 template <typename R>
 static int launch_p2p_jobs(const P2PJobDev<R>* jobs, const int* nleaf, int nj, bool adj,
-                           bool imag, int grid_cap, hipStream_t s) {
-  if (nj <= 0) return 0;
+                           bool imag, int grid_cap, hipStream_t s, hipEvent_t done = nullptr) {
+  if (nj <= 0) {
+    if (done) BEM_HIP_TRY(hipEventRecord(done, s));
+    return 0;
+  }
   if (nj > MAX_JOBS) {
     set_error("too many near-field jobs in one launch");
     return -1;
@@ -1457,18 +1484,21 @@ static int launch_p2p_jobs(const P2PJobDev<R>* jobs, const int* nleaf, int nj, b
   }
   b.leaf0[nj] = tot;
   b.total = tot;
-  if (tot == 0) return 0;
+  if (tot == 0) {
+    if (done) BEM_HIP_TRY(hipEventRecord(done, s));
+    return 0;
+  }
   const int grid = (grid_cap > 0 && grid_cap < tot) ? grid_cap : tot;
   if (adj) {
     if (imag)
-      hipLaunchKernelGGL((k_p2p_adj<R, true>), dim3(grid), dim3(P2P_THREADS), 0, s, b);
+      launch_done(k_p2p_adj<R, true>, dim3(grid), dim3(P2P_THREADS), 0, s, done, b);
     else
-      hipLaunchKernelGGL((k_p2p_adj<R, false>), dim3(grid), dim3(P2P_THREADS), 0, s, b);
+      launch_done(k_p2p_adj<R, false>, dim3(grid), dim3(P2P_THREADS), 0, s, done, b);
   } else {
     if (imag)
-      hipLaunchKernelGGL((k_p2p<R, true>), dim3(grid), dim3(P2P_THREADS), 0, s, b);
+      launch_done(k_p2p<R, true>, dim3(grid), dim3(P2P_THREADS), 0, s, done, b);
     else
-      hipLaunchKernelGGL((k_p2p<R, false>), dim3(grid), dim3(P2P_THREADS), 0, s, b);
+      launch_done(k_p2p<R, false>, dim3(grid), dim3(P2P_THREADS), 0, s, done, b);
   }
   BEM_LAUNCH_CHECK();
   return 0;
@@ -1477,8 +1507,11 @@ static int launch_p2p_jobs(const P2PJobDev<R>* jobs, const int* nleaf, int nj, b
 // one leaf-accumulation launch (mode 0 P2M, 1 L2P^H) over up to MAX_JOBS problems
 template <typename R>
 static int launch_leaf_jobs(const LeafJobDev<R>* jobs, const int* nleaf, int nj, int mode,
-                            hipStream_t s) {
-  if (nj <= 0) return 0;
+                            hipStream_t s, hipEvent_t done = nullptr) {
+  if (nj <= 0) {
+    if (done) BEM_HIP_TRY(hipEventRecord(done, s));
+    return 0;
+  }
   if (nj > MAX_JOBS) {
     set_error("too many leaf jobs in one launch");
     return -1;
@@ -1493,8 +1526,11 @@ static int launch_leaf_jobs(const LeafJobDev<R>* jobs, const int* nleaf, int nj,
   }
   b.leaf0[nj] = tot;
   b.total = tot;
-  if (tot == 0) return 0;
-  hipLaunchKernelGGL(k_leaf_accumulate<R>, dim3(tot), dim3(256), 0, s, b, mode);
+  if (tot == 0) {
+    if (done) BEM_HIP_TRY(hipEventRecord(done, s));
+    return 0;
+  }
+  launch_done(k_leaf_accumulate<R>, dim3(tot), dim3(256), 0, s, done, b, mode);
   BEM_LAUNCH_CHECK();
   return 0;
 }
@@ -1607,17 +1643,11 @@ static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, ExecBuf<R>& 
 }
 
 
-// Join before the finish: with the leaf-level M2L on the third stream, that
-// stream first waits for the near field, so the caller's stream waits on a
-// single event (each wait costs the caller's stream a few microseconds).
+// Join before the finish: the completion events of the near field and (on
+// the third stream) of the leaf-level M2L, both signalled by their launches.
 static int join_side_streams(Problem& P, hipStream_t s, bool leaf_side) {
-  if (leaf_side) {
-    BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_join, 0));
-    BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
-    BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
-  } else {
-    BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
-  }
+  BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
+  if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
   return 0;
 }
 
@@ -1629,32 +1659,35 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   const R k = (R)P.k, alr = (R)P.alpha.re, ali = (R)P.alpha.im;
   constexpr int ADJ_FLAG = 0;
   int nb = ceil_div(n, 256);
-  PROF_BEGIN(e0);
-  hipLaunchKernelGGL(k_gather_in<R>, dim3(nb), dim3(256), 0, s, p, q, P.perm, n, X.ps, X.qs,
-                     X.p64s, X.q64s, chain_zero_list(P, D, X, false, true));
-  BEM_LAUNCH_CHECK();
-  PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
+  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
+  // fork of the near field: signalled by the gather itself when the P2P
+  // follows it directly
+  const bool fork_at_gather = p2p_first && !P.direct;
+  PROF_BEGIN(e0);
+  launch_done(k_gather_in<R>, dim3(nb), dim3(256), 0, s, fork_at_gather ? P.ev_fork : nullptr, p,
+              q, P.perm, n, X.ps, X.qs, X.p64s, X.q64s, chain_zero_list(P, D, X, false, true));
+  BEM_LAUNCH_CHECK();
+  PROF_END(e0, ST_GATHER);
   // the near field runs on the side stream, concurrently with the far field
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
     if (!P.direct) {
-      BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
+      if (!fork_at_gather) BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
       BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
     }
     int e1 = prof_begin(P, sn);
     const P2PJobDev<R> job = p2p_job(P, D, X, false);
-    int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, false, P.alpha.re == 0.0, cap, sn);
+    int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, false, P.alpha.re == 0.0, cap, sn,
+                                P.direct ? nullptr : P.ev_join);
     if (rr) return rr;
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, false), sn);
     if (pr) return pr;
-    if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
     return 0;
   };
   int r = 0;
-  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
   if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
@@ -1663,24 +1696,24 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
     BEM_LAUNCH_CHECK();
     return 0;
   }
+  // leaf-level M2L (needs only the leaf multipoles): on its own stream
+  // (SCHED_CONCURRENT), or on this stream before the upward pass; the fork
+  // is signalled by the P2M launch
+  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP;
+  hipStream_t sl = leaf_side ? P.side2 : s;
   PROF_BEGIN(e2);
   {
     const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], D.p2m, X.ps, X.qs, X.M[L]};
-    if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, 0, s))) return r;
+    if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, 0, s, leaf_side ? P.ev_fork2 : nullptr)))
+      return r;
   }
   PROF_END(e2, ST_P2M);
-  // leaf-level M2L (needs only the leaf multipoles): on its own stream
-  // (SCHED_CONCURRENT), or on this stream before the upward pass
-  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP;
-  hipStream_t sl = leaf_side ? P.side2 : s;
-  if (leaf_side) {
-    BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
-    BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
-  }
+  if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   // (its per-destination sums are formed by the leaf finish)
   if ((r = launch_grouped<R, 0>(D.m2l[L], false, X.M[L], X.Lc[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
-                                P.m2l_cap[sizeof(R) == 4], false)))
+                                P.m2l_cap[sizeof(R) == 4], false,
+                                leaf_side ? P.ev_join2 : nullptr)))
     return r;
   if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e3);
@@ -1726,31 +1759,32 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   constexpr int ADJ_FLAG = 1;
   int nb = ceil_div(n, 256);
   // sorted input in X.ps, X.p64s; P2P results in X.ys (u) and X.ys2 (w)
-  PROF_BEGIN(e0);
-  hipLaunchKernelGGL(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, y, P.perm, n, X.ps, X.p64s,
-                     chain_zero_list(P, D, X, true, true));
-  BEM_LAUNCH_CHECK();
-  PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
+  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
+  const bool fork_at_gather = p2p_first && !P.direct;
+  PROF_BEGIN(e0);
+  launch_done(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, fork_at_gather ? P.ev_fork : nullptr, y,
+              P.perm, n, X.ps, X.p64s, chain_zero_list(P, D, X, true, true));
+  BEM_LAUNCH_CHECK();
+  PROF_END(e0, ST_GATHER);
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
     if (!P.direct) {
-      BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
+      if (!fork_at_gather) BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
       BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
     }
     int e1 = prof_begin(P, sn);
     const P2PJobDev<R> job = p2p_job(P, D, X, true);
-    int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, true, P.alpha.re == 0.0, cap, sn);
+    int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, true, P.alpha.re == 0.0, cap, sn,
+                                P.direct ? nullptr : P.ev_join);
     if (rr) return rr;
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, true), sn);
     if (pr) return pr;
-    if (!P.direct) BEM_HIP_TRY(hipEventRecord(P.ev_join, sn));
     return 0;
   };
   int r = 0;
-  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
   if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
@@ -1760,23 +1794,22 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
     return 0;
   }
   // adjoint locals (L2P^H) in Lc, adjoint multipoles in M
-  PROF_BEGIN(e2);
-  {
-    const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], D.l2p, X.ps, nullptr, X.Lc[L]};
-    if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, 1, s))) return r;
-  }
-  PROF_END(e2, ST_P2M);
   // leaf-level M2L^H (needs only the leaf adjoint locals): own stream or
   // this one, as in the forward product
   const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP;
   hipStream_t sl = leaf_side ? P.side2 : s;
-  if (leaf_side) {
-    BEM_HIP_TRY(hipEventRecord(P.ev_fork2, s));
-    BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
+  PROF_BEGIN(e2);
+  {
+    const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], D.l2p, X.ps, nullptr, X.Lc[L]};
+    if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, 1, s, leaf_side ? P.ev_fork2 : nullptr)))
+      return r;
   }
+  PROF_END(e2, ST_P2M);
+  if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   if ((r = launch_grouped<R, 0>(D.m2l[L], true, X.Lc[L], X.M[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
-                                P.m2l_cap[sizeof(R) == 4], false)))
+                                P.m2l_cap[sizeof(R) == 4], false,
+                                leaf_side ? P.ev_join2 : nullptr)))
     return r;
   if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
   PROF_BEGIN(e5);
