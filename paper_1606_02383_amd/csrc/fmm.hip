@@ -654,12 +654,15 @@ struct GemmBatch {
 // KIND: 0 M2L (per-pair output), 1 M2M, 2 L2L, 3 leaf -> ancestor, 4
 // ancestor -> leaf (the others add into dst)
 template <typename R, int CT, bool ADJ, int KIND>
-__global__ void __launch_bounds__(64 * TileShape<CT>::NW)
+__global__ void __launch_bounds__(64 * TileShape<CT>::NW, TileShape<CT>::NW == 4 ? 2 : 1)
     k_grouped_gemm(const GemmBatch<R> batch) {
   typedef typename MfmaOp<R>::v4 v4;
   typedef TileShape<CT> S;
-  constexpr bool M3 = sizeof(R) == 4;
-  constexpr int NP = M3 ? 3 : 2;  // LDS planes: re, im (, re + im)
+  // complex blocks as three real products (P1 = Ar Br, P2 = Ai Bi,
+  // P3 = (Ar + Ai)(Br + Bi)); float32 stages the sums as a third LDS plane,
+  // float64 (twice the LDS per value) forms them from the loaded operands
+  constexpr bool STAGE3 = sizeof(R) == 4;
+  constexpr int NP = STAGE3 ? 3 : 2;  // LDS planes: re, im (, re + im)
   constexpr int NT = 64 * S::NW;
   constexpr int PA = (G_RT * G_KC) / NT, PB = (CT * G_KC + NT - 1) / NT;
   constexpr int A_SZ = 2 * NP * G_RT * G_LD, B_SZ = 2 * NP * CT * G_LD;
@@ -760,7 +763,7 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
       const int kk = ADJ ? e / G_RT : e % G_KC, rr = ADJ ? e % G_RT : e / G_KC;
       A0[rr * G_LD + kk] = ra[q].re;
       A0[G_RT * G_LD + rr * G_LD + kk] = ra[q].im;
-      if (M3) A0[2 * G_RT * G_LD + rr * G_LD + kk] = ra[q].re + ra[q].im;
+      if (STAGE3) A0[2 * G_RT * G_LD + rr * G_LD + kk] = ra[q].re + ra[q].im;
     }
 #pragma unroll
     for (int q = 0; q < PB; ++q) {
@@ -769,7 +772,7 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
       if (cc < CT) {
         B0[cc * G_LD + kk] = rb[q].re;
         B0[CT * G_LD + cc * G_LD + kk] = rb[q].im;
-        if (M3) B0[2 * CT * G_LD + cc * G_LD + kk] = rb[q].re + rb[q].im;
+        if (STAGE3) B0[2 * CT * G_LD + cc * G_LD + kk] = rb[q].re + rb[q].im;
       }
     }
   };
@@ -790,29 +793,22 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
         const int o = (wr * (G_RT / S::WR) + i * 16 + li) * G_LD + ks + lk;
         a0[i] = A0[o];
         a1[i] = A0[G_RT * G_LD + o];
-        if (M3) a2[i] = A0[2 * G_RT * G_LD + o];
+        a2[i] = STAGE3 ? A0[2 * G_RT * G_LD + o] : a0[i] + a1[i];
       }
 #pragma unroll
       for (int j = 0; j < S::CB; ++j) {
         const int o = (wc * (CT / S::WC) + j * 16 + li) * G_LD + ks + lk;
         b0[j] = B0[o];
         b1[j] = B0[CT * G_LD + o];
-        if (M3) b2[j] = B0[2 * CT * G_LD + o];
+        b2[j] = STAGE3 ? B0[2 * CT * G_LD + o] : b0[j] + b1[j];
       }
 #pragma unroll
       for (int i = 0; i < S::RB; ++i)
 #pragma unroll
         for (int j = 0; j < S::CB; ++j) {
-          if (M3) {
-            c0[i][j] = MfmaOp<R>::mma(a0[i], b0[j], c0[i][j]);
-            c1[i][j] = MfmaOp<R>::mma(a1[i], b1[j], c1[i][j]);
-            c2[i][j] = MfmaOp<R>::mma(a2[i], b2[j], c2[i][j]);
-          } else {
-            c0[i][j] = MfmaOp<R>::mma(a0[i], b0[j], c0[i][j]);
-            c0[i][j] = MfmaOp<R>::mma(-a1[i], b1[j], c0[i][j]);
-            c1[i][j] = MfmaOp<R>::mma(a0[i], b1[j], c1[i][j]);
-            c1[i][j] = MfmaOp<R>::mma(a1[i], b0[j], c1[i][j]);
-          }
+          c0[i][j] = MfmaOp<R>::mma(a0[i], b0[j], c0[i][j]);
+          c1[i][j] = MfmaOp<R>::mma(a1[i], b1[j], c1[i][j]);
+          c2[i][j] = MfmaOp<R>::mma(a2[i], b2[j], c2[i][j]);
         }
     }
     if (ch + 1 < nchunk) store(buf ^ 1);
@@ -828,14 +824,8 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
       for (int e = 0; e < 4; ++e) {
         const int row = wr * (G_RT / S::WR) + i * 16 + MfmaOp<R>::row(lk, e);
         const int cc = wc * (CT / S::WC) + j * 16 + li;
-        R re, im;
-        if (M3) {
-          re = c0[i][j][e] - c1[i][j][e];
-          im = c2[i][j][e] - c0[i][j][e] - c1[i][j][e];
-        } else {
-          re = c0[i][j][e];
-          im = c1[i][j][e];
-        }
+        const R re = c0[i][j][e] - c1[i][j][e];
+        const R im = c2[i][j][e] - c0[i][j][e] - c1[i][j][e];
         Os[(cc * OLD + row) * 2] = re;
         Os[(cc * OLD + row) * 2 + 1] = im;
       }
