@@ -135,7 +135,9 @@ typedef struct {
                               0 leaf-level M2L beside the upward pass, 1 it
                               before the upward pass, 2 as 1 with the near
                               field started after it, 3 as 0 with the near
-                              field started after the upward pass           */
+                              field started after the upward pass, 4 as 0
+                              with the near field started after the leaf
+                              multipoles, behind the leaf-level M2L         */
   int32_t p2p_grid[2];     /* near-field workgroups (float64 / float32): 0 one
                               per leaf, else a grid-stride launch of that
                               many (chosen with the schedule)               */
@@ -234,7 +236,7 @@ int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, voi
 
 /* Overrides the choices made by timing at plan creation for problem `prob`
  * and precision prec (BEM_C128 / BEM_C64), see bem_plan_stats: stream
- * schedule (0..3), near-field and leaf-level M2L grids (0: one workgroup per
+ * schedule (0..4), near-field and leaf-level M2L grids (0: one workgroup per
  * leaf / tile, else a grid-stride launch of that many) and direct
  * translation depth (0 .. the depth built).  A negative value keeps the
  * current choice.  Products agree up to rounding whatever the choice.

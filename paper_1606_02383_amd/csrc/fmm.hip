@@ -1665,8 +1665,11 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
     if (!P.direct) {
-      if (!fork_at_gather) BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
-      BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
+      // behind the leaf M2L: forked by the P2M's completion event
+      hipEvent_t fork = sched == SCHED_LEAF_THEN_P2P ? P.ev_fork2 : P.ev_fork;
+      if (!fork_at_gather && sched != SCHED_LEAF_THEN_P2P)
+        BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
+      BEM_HIP_TRY(hipStreamWaitEvent(sn, fork, 0));
     }
     int e1 = prof_begin(P, sn);
     const P2PJobDev<R> job = p2p_job(P, D, X, false);
@@ -1689,7 +1692,8 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   // leaf-level M2L (needs only the leaf multipoles): on its own stream
   // (SCHED_CONCURRENT), or on this stream before the upward pass; the fork
   // is signalled by the P2M launch
-  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP;
+  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP ||
+                         sched == SCHED_LEAF_THEN_P2P;
   hipStream_t sl = leaf_side ? P.side2 : s;
   PROF_BEGIN(e2);
   {
@@ -1705,7 +1709,8 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
                                 P.m2l_cap[sizeof(R) == 4], false,
                                 leaf_side ? P.ev_join2 : nullptr)))
     return r;
-  if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
+  if ((sched == SCHED_LEAF_FIRST || sched == SCHED_LEAF_THEN_P2P) && (r = launch_p2p()))
+    return r;
   PROF_BEGIN(e3);
   if ((r = upward_pass<R>(P, D, X, false, s))) return r;
   PROF_END(e3, ST_M2M);
@@ -1762,8 +1767,11 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
     if (!P.direct) {
-      if (!fork_at_gather) BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
-      BEM_HIP_TRY(hipStreamWaitEvent(sn, P.ev_fork, 0));
+      // behind the leaf M2L: forked by the P2M's completion event
+      hipEvent_t fork = sched == SCHED_LEAF_THEN_P2P ? P.ev_fork2 : P.ev_fork;
+      if (!fork_at_gather && sched != SCHED_LEAF_THEN_P2P)
+        BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
+      BEM_HIP_TRY(hipStreamWaitEvent(sn, fork, 0));
     }
     int e1 = prof_begin(P, sn);
     const P2PJobDev<R> job = p2p_job(P, D, X, true);
@@ -1786,7 +1794,8 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   // adjoint locals (L2P^H) in Lc, adjoint multipoles in M
   // leaf-level M2L^H (needs only the leaf adjoint locals): own stream or
   // this one, as in the forward product
-  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP;
+  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP ||
+                         sched == SCHED_LEAF_THEN_P2P;
   hipStream_t sl = leaf_side ? P.side2 : s;
   PROF_BEGIN(e2);
   {
@@ -1801,7 +1810,8 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
                                 P.m2l_cap[sizeof(R) == 4], false,
                                 leaf_side ? P.ev_join2 : nullptr)))
     return r;
-  if (sched == SCHED_LEAF_FIRST && (r = launch_p2p())) return r;
+  if ((sched == SCHED_LEAF_FIRST || sched == SCHED_LEAF_THEN_P2P) && (r = launch_p2p()))
+    return r;
   PROF_BEGIN(e5);
   if ((r = upward_pass<R>(P, D, X, true, s))) return r;
   PROF_END(e5, ST_L2L);

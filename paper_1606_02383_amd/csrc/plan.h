@@ -201,9 +201,12 @@ int prof_end(Problem& P, int idx, int slot, hipStream_t s);
 //   SCHED_P2P_AFTER_UP as SCHED_CONCURRENT, with P2P started after the
 //                     upward pass (whose small launches then do not wait
 //                     for compute units behind it)
+//   SCHED_LEAF_THEN_P2P as SCHED_CONCURRENT, with P2P forked after the P2M,
+//                     behind the leaf-level M2L (whose workgroups then take
+//                     their place on the compute units first)
 enum {
   SCHED_CONCURRENT = 0, SCHED_LEAF_SERIAL = 1, SCHED_LEAF_FIRST = 2, SCHED_P2P_AFTER_UP = 3,
-  SCHED_COUNT
+  SCHED_LEAF_THEN_P2P = 4, SCHED_COUNT
 };
 
 struct Plan {
