@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cstring>
 
+#include <hip/hip_ext.h>
+
 #include "../../include/bemfmm.h"
 #include "plan.h"
 
@@ -408,7 +410,7 @@ static int norm2(Workspace& W, const c64* v, int64_t n, double* out, hipStream_t
 //   h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, V_{j+1} = w / ||w||
 // in five launches (each update folds the preceding dot partials itself);
 // the column (h1 + h2, ||w||^2) lands in host slot `slot` of W.hcol and
-// W.ev[slot] is recorded after it.
+// W.ev[slot] completes with the launch that writes it.
 static int arnoldi_orth(Workspace& W, int64_t n, int j, int slot, hipStream_t s) {
   const int nb = ceil_div(n, 256);
   const int nk = j + 1;
@@ -425,11 +427,12 @@ static int arnoldi_orth(Workspace& W, int64_t n, int j, int slot, hipStream_t s)
   hipLaunchKernelGGL(k_multiupdate, dim3(nb), dim3(256), 0, s, W.V, (int64_t)n, n, nk,
                      W.partial, W.h2, W.w, W.partial2);
   BEM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_normalise, dim3(nb), dim3(256), 0, s, W.w, n, W.partial2, nb,
-                     W.V + (int64_t)(j + 1) * n, W.h2 + j + 1, W.h, W.h2, j,
-                     W.hcol + slot * (W.m + 2));
+  // W.ev[slot] is signalled by this launch's completion (no separate event
+  // record, which would cost the stream a gap before the next product)
+  hipExtLaunchKernelGGL(k_normalise, dim3(nb), dim3(256), 0, s, nullptr, W.ev[slot], 0, W.w, n,
+                        W.partial2, nb, W.V + (int64_t)(j + 1) * n, W.h2 + j + 1, W.h, W.h2, j,
+                        W.hcol + slot * (W.m + 2));
   BEM_LAUNCH_CHECK();
-  BEM_HIP_TRY(hipEventRecord(W.ev[slot], s));
   return 0;
 }
 
