@@ -249,12 +249,18 @@ int bem_plan_set_tuning(bem_plan* plan, int prob, int prec, int schedule, int p2
  * bem_profile_stop synchronises and returns, per slot, the summed
  * milliseconds and the number of timed stage executions.  Slot =
  * stage + 16 * (float32 ? 1 : 0) + 32 * (adjoint ? 1 : 0), stage: 0 gather,
- * 1 P2P, 2 P2M (adjoint: L2P^H), 3 M2M, 4 M2L of the levels above the
- * leaves (merged launch), 5 L2L, 6 finish (L2P, near corrections, diagonal,
- * scatter), 7 reduction of 4, 8 M2L of the leaf level, 9 reduction of 8.
- * ms and calls hold BEM_PROFILE_SLOTS entries (host). */
+ * 1 P2P (with the near-field corrections), 2 P2M (adjoint: L2P^H), 3 M2M,
+ * 4 M2L of the levels above the leaves, 5 L2L, 6 leaf finish (sums of the
+ * leaf-level M2L, L2P, P2P sums, diagonal, scatter), 7 reduction of 4,
+ * 8 M2L of the leaf level, 9 unused (the reduction of 8 is part of 6).
+ * ms and calls hold BEM_PROFILE_SLOTS entries (host).
+ * bem_profile_leaf_m2l_start times only stage 8, with timing events attached
+ * to its launches (nothing is recorded on any stream between kernels), so a
+ * timed region keeps its schedule; bem_profile_stop ends either mode.
+ * BEM_E_INVALID for a bad plan, problem or output pointer. */
 #define BEM_PROFILE_SLOTS 64
 int bem_profile_start(bem_plan* plan, int prob);
+int bem_profile_leaf_m2l_start(bem_plan* plan, int prob);
 int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls);
 
 const char* bem_last_error(void);

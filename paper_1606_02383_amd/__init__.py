@@ -33,7 +33,7 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_plane_wave_rhs", "bem_eval_field",
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
            "bem_leaves_export", "bem_plan_set_tuning", "bem_profile_start",
-           "bem_profile_stop", "bem_last_error"]
+           "bem_profile_leaf_m2l_start", "bem_profile_stop", "bem_last_error"]
 
 STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
           "m2l_leaf_reduce"]
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH):
     lib.bem_leaves_export.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.bem_plan_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32, i32]
     lib.bem_profile_start.argtypes = [vp, i32]
+    lib.bem_profile_leaf_m2l_start.argtypes = [vp, i32]
     lib.bem_profile_stop.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int32)]
     lib.bem_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -356,8 +357,14 @@ class Plan:
         _check(_LIB.bem_plan_set_tuning(self._h, prob, prec, int(schedule), int(p2p_grid),
                                         int(m2l_grid), int(direct_depth)))
 
-    def profile_start(self, prob=0):
-        _check(_LIB.bem_profile_start(self._h, prob))
+    def profile_start(self, prob=0, leaf_m2l_only=False):
+        """Stage timing until profile_stop: every stage (event pairs on the
+        streams), or only the leaf-level M2L with events attached to its
+        launches (leaf_m2l_only; leaves the schedule of a timed region as is)."""
+        if leaf_m2l_only:
+            _check(_LIB.bem_profile_leaf_m2l_start(self._h, prob))
+        else:
+            _check(_LIB.bem_profile_start(self._h, prob))
 
     def profile_stop(self, prob=0):
         """{(stage, 'f64'|'f32', 'fwd'|'adj'): (total ms, executions)}"""

@@ -31,7 +31,6 @@ static void destroy_problem(Problem* P) {
   if (P->ev_fork2) (void)hipEventDestroy(P->ev_fork2);
   if (P->ev_join2) (void)hipEventDestroy(P->ev_join2);
   if (P->side2) (void)hipStreamDestroy(P->side2);
-  if (P->bstream) (void)hipStreamDestroy(P->bstream);
   P->arena.release();
   delete P;
 }
@@ -470,6 +469,24 @@ int bem_profile_start(bem_plan* plan, int prob) {
   Problem* P = get_prob(plan, prob);
   if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
   P->prof_on = true;
+  P->prof_leaf = false;
+  P->ev_used = 0;
+  P->ev_slot.clear();
+  return BEM_OK;
+}
+
+int bem_profile_leaf_m2l_start(bem_plan* plan, int prob) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  // enough event pairs for a few hundred products, created outside the
+  // region being timed
+  while (P->ev_pool.size() < 1024) {
+    hipEvent_t e;
+    BEM_HIP_TRY(hipEventCreate(&e));
+    P->ev_pool.push_back(e);
+  }
+  P->prof_on = false;
+  P->prof_leaf = true;
   P->ev_used = 0;
   P->ev_slot.clear();
   return BEM_OK;
@@ -491,6 +508,7 @@ int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls) {
     calls[slot] += 1;
   }
   P->prof_on = false;
+  P->prof_leaf = false;
   P->ev_used = 0;
   P->ev_slot.clear();
   return BEM_OK;

@@ -156,11 +156,12 @@ __device__ __forceinline__ int job_of(const int (&first)[N], int njobs, int v) {
 // Launch whose completion signals `done` (when non-null) as part of the
 // dispatch itself: fork and join points between streams then need no
 // separate event record (a marker that costs the stream an extra gap).
+// `start` (timing events only) brackets the launch for profiling.
 template <typename... KArgs, typename... Args>
 static void launch_done(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds,
-                        hipStream_t s, hipEvent_t done, Args... args) {
-  if (done)
-    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, nullptr, done, 0, args...);
+                        hipStream_t s, hipEvent_t start, hipEvent_t done, Args... args) {
+  if (done || start)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, start, done, 0, args...);
   else
     hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
 }
@@ -1246,6 +1247,36 @@ int prof_end(Problem& P, int idx, int slot, hipStream_t s) {
   return 0;
 }
 
+// a (start, end) event pair for a launch's own events, counted in `slot`
+int prof_pair(Problem& P, int slot) {
+  if ((int)P.ev_pool.size() < 2 * (P.ev_used + 1)) {
+    for (int t = 0; t < 64; ++t) {
+      hipEvent_t e;
+      BEM_HIP_TRY(hipEventCreate(&e));
+      P.ev_pool.push_back(e);
+    }
+  }
+  int idx = P.ev_used++;
+  if ((int)P.ev_slot.size() <= idx) P.ev_slot.resize(idx + 1);
+  P.ev_slot[idx] = slot;
+  return idx;
+}
+
+// the leaf-level M2L's launch events: (start, done) = a timing pair when the
+// leaf M2L alone is profiled, else (none, the join event when it runs on the
+// third stream)
+template <typename R>
+static void leaf_m2l_events(Problem& P, bool adj, bool leaf_side, hipEvent_t* start,
+                            hipEvent_t* done) {
+  *start = nullptr;
+  *done = leaf_side ? P.ev_join2 : nullptr;
+  if (!P.prof_leaf) return;
+  const int idx = prof_pair(P, prof_slot(ST_M2L_LEAF, sizeof(R) == 4, adj));
+  if (idx < 0) return;
+  *start = P.ev_pool[2 * idx];
+  *done = P.ev_pool[2 * idx + 1];
+}
+
 #define PROF_BEGIN(var) int var = prof_begin(P, s)
 #define PROF_END(var, stage)                                                  \
   do {                                                                        \
@@ -1269,21 +1300,22 @@ struct GemmJob {
 };
 
 template <typename R, int CT, bool ADJ, int KIND>
-static void launch_gemm(const GemmBatch<R>& b, int nt, hipStream_t s, hipEvent_t done) {
+static void launch_gemm(const GemmBatch<R>& b, int nt, hipStream_t s, hipEvent_t start,
+                        hipEvent_t done) {
   launch_done(k_grouped_gemm<R, CT, ADJ, KIND>, dim3(nt), dim3(64 * TileShape<CT>::NW), 0, s,
-              done, b);
+              start, done, b);
 }
 
 template <typename R, bool ADJ, int KIND>
 static int launch_gemm_ct(const GemmBatch<R>& b, int ct, int nt, hipStream_t s,
-                          hipEvent_t done = nullptr) {
+                          hipEvent_t done = nullptr, hipEvent_t start = nullptr) {
   switch (ct) {
-    case 16: launch_gemm<R, 16, ADJ, KIND>(b, nt, s, done); break;
-    case 32: launch_gemm<R, 32, ADJ, KIND>(b, nt, s, done); break;
-    case 64: launch_gemm<R, 64, ADJ, KIND>(b, nt, s, done); break;
+    case 16: launch_gemm<R, 16, ADJ, KIND>(b, nt, s, start, done); break;
+    case 32: launch_gemm<R, 32, ADJ, KIND>(b, nt, s, start, done); break;
+    case 64: launch_gemm<R, 64, ADJ, KIND>(b, nt, s, start, done); break;
     case 128:
       if constexpr (sizeof(R) == 4) {
-        launch_gemm<R, 128, ADJ, KIND>(b, nt, s, done);
+        launch_gemm<R, 128, ADJ, KIND>(b, nt, s, start, done);
         break;
       } else {
         set_error("128-pair tiles are float32 only");
@@ -1299,8 +1331,10 @@ template <typename R, int KIND>
 static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStream_t s,
                                int accumulate = 0, Problem* prof = nullptr,
                                int st_gemm = ST_M2L, int grid_cap = 0,
-                               bool run_reduce = true, hipEvent_t done = nullptr) {
-  // `done`: signalled by the GEMM launch (only with run_reduce = false)
+                               bool run_reduce = true, hipEvent_t done = nullptr,
+                               hipEvent_t start = nullptr) {
+  // `done`: signalled by the GEMM launch (only with run_reduce = false);
+  // `start`: timing event attached to the GEMM launch
   if (done && run_reduce) {
     set_error("completion event of a grouped product with its reduction");
     return -1;
@@ -1357,12 +1391,13 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
   b.tile0[nj] = nt;
   b.ntiles = nt;
   rb.box0[nj] = nbox;
+  if (nt == 0 && start) BEM_HIP_TRY(hipEventRecord(start, s));
   if (nt == 0 && done) BEM_HIP_TRY(hipEventRecord(done, s));
   if (nt > 0) {
     int evg = prof ? prof_begin(*prof, s) : -1;
     const int grid = (grid_cap > 0 && grid_cap < nt) ? (grid_cap & ~7) : nt;
-    int r = adj ? launch_gemm_ct<R, true, KIND>(b, ct, grid > 0 ? grid : nt, s, done)
-                : launch_gemm_ct<R, false, KIND>(b, ct, grid > 0 ? grid : nt, s, done);
+    int r = adj ? launch_gemm_ct<R, true, KIND>(b, ct, grid > 0 ? grid : nt, s, done, start)
+                : launch_gemm_ct<R, false, KIND>(b, ct, grid > 0 ? grid : nt, s, done, start);
     if (r) return r;
     if (prof) {
       int pr = prof_end(*prof, evg, prof_slot(st_gemm, sizeof(R) == 4, adj), s);
@@ -1387,10 +1422,11 @@ template <typename R, int KIND>
 static int launch_grouped(const GroupedOp<R>& op, bool adj, const cplx<R>* src, cplx<R>* dst,
                           hipStream_t s, cplx<R>* cbuf = nullptr, int accumulate = 0,
                           Problem* prof = nullptr, int st_gemm = ST_M2L, int grid_cap = 0,
-                          bool run_reduce = true, hipEvent_t done = nullptr) {
+                          bool run_reduce = true, hipEvent_t done = nullptr,
+                          hipEvent_t start = nullptr) {
   GemmJob<R> j{&op, src, dst, cbuf};
   return launch_grouped_jobs<R, KIND>(&j, 1, adj, s, accumulate, prof, st_gemm, grid_cap,
-                                      run_reduce, done);
+                                      run_reduce, done, start);
 }
 
 // The per-destination reductions of several M2L products (their GEMMs
@@ -1481,14 +1517,14 @@ static int launch_p2p_jobs(const P2PJobDev<R>* jobs, const int* nleaf, int nj, b
   const int grid = (grid_cap > 0 && grid_cap < tot) ? grid_cap : tot;
   if (adj) {
     if (imag)
-      launch_done(k_p2p_adj<R, true>, dim3(grid), dim3(P2P_THREADS), 0, s, done, b);
+      launch_done(k_p2p_adj<R, true>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
     else
-      launch_done(k_p2p_adj<R, false>, dim3(grid), dim3(P2P_THREADS), 0, s, done, b);
+      launch_done(k_p2p_adj<R, false>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
   } else {
     if (imag)
-      launch_done(k_p2p<R, true>, dim3(grid), dim3(P2P_THREADS), 0, s, done, b);
+      launch_done(k_p2p<R, true>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
     else
-      launch_done(k_p2p<R, false>, dim3(grid), dim3(P2P_THREADS), 0, s, done, b);
+      launch_done(k_p2p<R, false>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
   }
   BEM_LAUNCH_CHECK();
   return 0;
@@ -1520,7 +1556,7 @@ static int launch_leaf_jobs(const LeafJobDev<R>* jobs, const int* nleaf, int nj,
     if (done) BEM_HIP_TRY(hipEventRecord(done, s));
     return 0;
   }
-  launch_done(k_leaf_accumulate<R>, dim3(tot), dim3(256), 0, s, done, b, mode);
+  launch_done(k_leaf_accumulate<R>, dim3(tot), dim3(256), 0, s, nullptr, done, b, mode);
   BEM_LAUNCH_CHECK();
   return 0;
 }
@@ -1635,9 +1671,9 @@ static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, ExecBuf<R>& 
 
 // Join before the finish: the completion events of the near field and (on
 // the third stream) of the leaf-level M2L, both signalled by their launches.
-static int join_side_streams(Problem& P, hipStream_t s, bool leaf_side) {
+static int join_side_streams(Problem& P, hipStream_t s, hipEvent_t leaf_done) {
   BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
-  if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
+  if (leaf_done) BEM_HIP_TRY(hipStreamWaitEvent(s, leaf_done, 0));
   return 0;
 }
 
@@ -1657,8 +1693,9 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   // follows it directly
   const bool fork_at_gather = p2p_first && !P.direct;
   PROF_BEGIN(e0);
-  launch_done(k_gather_in<R>, dim3(nb), dim3(256), 0, s, fork_at_gather ? P.ev_fork : nullptr, p,
-              q, P.perm, n, X.ps, X.qs, X.p64s, X.q64s, chain_zero_list(P, D, X, false, true));
+  launch_done(k_gather_in<R>, dim3(nb), dim3(256), 0, s, nullptr,
+              fork_at_gather ? P.ev_fork : nullptr, p, q, P.perm, n, X.ps, X.qs, X.p64s, X.q64s,
+              chain_zero_list(P, D, X, false, true));
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   // the near field runs on the side stream, concurrently with the far field
@@ -1704,10 +1741,11 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   PROF_END(e2, ST_P2M);
   if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   // (its per-destination sums are formed by the leaf finish)
+  hipEvent_t m2l_start, m2l_done;
+  leaf_m2l_events<R>(P, false, leaf_side, &m2l_start, &m2l_done);
   if ((r = launch_grouped<R, 0>(D.m2l[L], false, X.M[L], X.Lc[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
-                                P.m2l_cap[sizeof(R) == 4], false,
-                                leaf_side ? P.ev_join2 : nullptr)))
+                                P.m2l_cap[sizeof(R) == 4], false, m2l_done, m2l_start)))
     return r;
   if ((sched == SCHED_LEAF_FIRST || sched == SCHED_LEAF_THEN_P2P) && (r = launch_p2p()))
     return r;
@@ -1719,7 +1757,7 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   PROF_BEGIN(e5);
   if ((r = downward_pass<R>(P, D, X, false, s))) return r;
   PROF_END(e5, ST_L2L);
-  if ((r = join_side_streams(P, s, leaf_side))) return r;
+  if ((r = join_side_streams(P, s, leaf_side ? m2l_done : nullptr))) return r;
   PROF_BEGIN(e6);
   {
     const GroupedOp<R>& op = D.m2l[L];
@@ -1760,8 +1798,9 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
   const bool fork_at_gather = p2p_first && !P.direct;
   PROF_BEGIN(e0);
-  launch_done(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, fork_at_gather ? P.ev_fork : nullptr, y,
-              P.perm, n, X.ps, X.p64s, chain_zero_list(P, D, X, true, true));
+  launch_done(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, nullptr,
+              fork_at_gather ? P.ev_fork : nullptr, y, P.perm, n, X.ps, X.p64s,
+              chain_zero_list(P, D, X, true, true));
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
   auto launch_p2p = [&]() -> int {
@@ -1805,10 +1844,11 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   }
   PROF_END(e2, ST_P2M);
   if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
+  hipEvent_t m2l_start, m2l_done;
+  leaf_m2l_events<R>(P, true, leaf_side, &m2l_start, &m2l_done);
   if ((r = launch_grouped<R, 0>(D.m2l[L], true, X.Lc[L], X.M[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
-                                P.m2l_cap[sizeof(R) == 4], false,
-                                leaf_side ? P.ev_join2 : nullptr)))
+                                P.m2l_cap[sizeof(R) == 4], false, m2l_done, m2l_start)))
     return r;
   if ((sched == SCHED_LEAF_FIRST || sched == SCHED_LEAF_THEN_P2P) && (r = launch_p2p()))
     return r;
@@ -1820,7 +1860,7 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   PROF_BEGIN(e3);
   if ((r = downward_pass<R>(P, D, X, true, s))) return r;
   PROF_END(e3, ST_M2M);
-  if ((r = join_side_streams(P, s, leaf_side))) return r;
+  if ((r = join_side_streams(P, s, leaf_side ? m2l_done : nullptr))) return r;
   PROF_BEGIN(e6);
   {
     const GroupedOp<R>& op = D.m2l[L];

@@ -930,7 +930,6 @@ int build_operators(Problem& P, hipStream_t s) {
   }
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
   BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side2, hipStreamNonBlocking));
-  BEM_HIP_TRY(hipStreamCreateWithFlags(&P.bstream, hipStreamNonBlocking));
   // fork/join events order work between this device's streams only: a
   // device-scope release suffices (no system-scope cache write-back)
   const unsigned evf = hipEventDisableTiming | hipEventReleaseToDevice;

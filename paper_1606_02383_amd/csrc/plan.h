@@ -173,11 +173,13 @@ struct Problem {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // third stream: the leaf-level M2L (the largest) overlaps the coarser levels
   hipStream_t side2 = nullptr;
-  // stream of this problem inside batched solves (problems run concurrently)
-  hipStream_t bstream = nullptr;
   hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
-  // stage profiling with HIP events (off unless enabled)
+  // stage profiling with HIP events (off unless enabled): prof_on times every
+  // stage with event pairs recorded on the streams; prof_leaf times only the
+  // leaf-level M2L launches, with events attached to the launches themselves
+  // (nothing recorded between kernels), for timing inside a timed region
   bool prof_on = false;
+  bool prof_leaf = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_slot;   // slot of each recorded (start, end) pair
   int ev_used = 0;
@@ -192,6 +194,7 @@ constexpr int PROF_SLOTS = 64;
 constexpr int prof_slot(int stage, bool f32, bool adj) { return stage + 16 * f32 + 32 * adj; }
 int prof_begin(Problem& P, hipStream_t s);                 // returns event index or -1
 int prof_end(Problem& P, int idx, int slot, hipStream_t s);
+int prof_pair(Problem& P, int slot);  // a (start, end) pair for a launch's own events
 
 // Stream schedules of one product (the near field P2P always runs on the
 // side stream, concurrently with the far field):
