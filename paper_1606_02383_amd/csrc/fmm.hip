@@ -4,18 +4,22 @@
 //
 // (the paper's boundary integral equation, Sec. 2.3, combined with its
 // normal derivative).  Per product, in float32 or float64:
-//   gather   caller order -> Morton order, split by precision
-//   P2P      3-point-rule direct sum over neighbouring leaves (U lists), j != i
+//   gather   caller order -> Morton order, split by precision (also clears
+//            the expansions accumulated further down)
+//   P2P      3-point-rule direct sum over neighbouring leaves (U lists),
+//            j != i, plus the near-field corrections (accurate - 3-point rule)
 //   P2M      leaf multipoles from per-element matrices (monopole q, dipole p)
 //   M2M      child -> parent, grouped by octant
 //   M2L      interaction lists, grouped by translation vector
 //   L2L      parent -> child
-//   finish   L2P + near-field corrections (accurate - 3-point rule) + the
+//   finish   per leaf: the leaf-level M2L sums, L2P, the P2P sums and the
 //            float64 diagonal (I/2, alpha/2 I and self integrals), scatter
-// The grouped translations are gather-GEMM-scatter kernels: every pair of
-// one group shares one dense matrix, the output columns are accumulated with
-// atomics.  The adjoint applies the conjugate transpose of every stage in
-// reverse order with the same lists and matrices.
+// The grouped translations are gather-GEMM-scatter kernels on the matrix
+// cores: every pair of one group shares one dense matrix.  M2L writes one
+// result per pair, summed per destination box in a fixed order afterwards
+// (deterministic); the other translations add into their destinations.  The
+// adjoint applies the conjugate transpose of every stage in reverse order
+// with the same lists and matrices.
 //
 // Pair kernel (rv = x - y, u = 1/r, G = exp(ikr)/(4 pi r)):
 //   coefficient of p_j: -(G_y + alpha G_xy)
@@ -1891,12 +1895,12 @@ static int launch_grouped_any(const std::vector<GemmJob<R>>& jobs, bool adj, hip
   return KIND == 0 ? launch_reduce_jobs<R>(jobs, adj, s) : 0;
 }
 
-// The batched product: the per-element stages (gather, finish) run per
-// item; every other stage is one launch (or one per tile width and
-// MAX_JOBS items) over all items, in the order of the single product
-// (near field and leaf-level M2L on the side streams when given).  Level
-// chains of problems with different depths are merged step by step from
-// the leaves.
+// The batched product: every stage is one launch (or one per tile width and
+// MAX_JOBS items) over all items, in the order of the single product (near
+// field and leaf-level M2L on the side streams when given); the gathers and
+// finishes take MAX_JOBS items per launch.  Level chains of problems with
+// different depths are merged step by step from the leaves.  The leaf-level
+// M2L is reduced by its own pass here (the finish is per element).
 template <typename R>
 int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const BatchStreams& bs) {
   int r = 0;
