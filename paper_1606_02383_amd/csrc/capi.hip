@@ -27,10 +27,10 @@ static void destroy_problem(Problem* P) {
   P->ev_pool.clear();
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
-  if (P->side) (void)hipStreamDestroy(P->side);
+  if (P->own_streams && P->side) (void)hipStreamDestroy(P->side);
   if (P->ev_fork2) (void)hipEventDestroy(P->ev_fork2);
   if (P->ev_join2) (void)hipEventDestroy(P->ev_join2);
-  if (P->side2) (void)hipStreamDestroy(P->side2);
+  if (P->own_streams && P->side2) (void)hipStreamDestroy(P->side2);
   P->arena.release();
   delete P;
 }
@@ -41,7 +41,20 @@ using namespace bemfmm;
 
 struct bem_plan {
   std::vector<Problem*> probs;
+  // the side streams of every product of the plan (near field, leaf-level
+  // M2L) and of its batched solves: created before anything else of the
+  // plan, so that the runtime gives them hardware queues of their own rather
+  // than one it already uses for the caller's stream (work on streams that
+  // share a queue runs one launch after another)
+  hipStream_t side = nullptr, side2 = nullptr;
 };
+
+static void destroy_plan(bem_plan* plan) {
+  for (Problem* P : plan->probs) destroy_problem(P);
+  if (plan->side) (void)hipStreamDestroy(plan->side);
+  if (plan->side2) (void)hipStreamDestroy(plan->side2);
+  delete plan;
+}
 
 static int fail(int code, const std::string& msg) {
   set_error(msg);
@@ -223,8 +236,15 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
   }
   hipStream_t s = (hipStream_t)stream;
   bem_plan* plan = new bem_plan();
+  if (hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&plan->side2, hipStreamNonBlocking) != hipSuccess) {
+    destroy_plan(plan);
+    return fail(BEM_E_HIP, "stream creation failed");
+  }
   auto build_one = [&](const bem_problem& q, int leaf_level, Problem** outp) -> int {
     Problem* P = new Problem();
+    P->side = plan->side;
+    P->side2 = plan->side2;
     P->n = q.n_tri;
     P->k = q.k;
     P->alpha = mk(q.alpha_re, q.alpha_im);
@@ -250,8 +270,7 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
     if (!r && q.leaf_level < 0 && !P->direct) r = autotune_leaf_level(q, build_one, &P, s);
     if (!r && !P->direct) r = tune_schedule(*P, s);
     if (r) {
-      for (Problem* pp : plan->probs) destroy_problem(pp);
-      delete plan;
+      destroy_plan(plan);
       return r;
     }
     plan->probs.push_back(P);
@@ -262,8 +281,7 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
 
 int bem_plan_destroy(bem_plan* plan) {
   if (!plan) return BEM_OK;
-  for (Problem* P : plan->probs) destroy_problem(P);
-  delete plan;
+  destroy_plan(plan);
   return BEM_OK;
 }
 

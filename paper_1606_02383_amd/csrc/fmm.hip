@@ -545,6 +545,7 @@ struct LeafBatch {
 template <typename R>
 __global__ void __launch_bounds__(256) k_leaf_accumulate(const LeafBatch<R> batch, int mode) {
   __shared__ cplx<R> part[4][64];
+  __builtin_amdgcn_s_setprio(2);  // critical path: ahead of the near-field waves
   const int qj = job_of(batch.leaf0, batch.n, (int)blockIdx.x);
   const LeafJobDev<R> J = select_job(batch.job, qj);
   const int b = (int)blockIdx.x - select_job(batch.leaf0, qj);
@@ -685,6 +686,9 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW, TileShape<CT>::NW == 4
   // compute units for work on other streams).  Virtual block vb =
   // blockIdx + i * gridDim keeps the XCD of blockIdx as the grid is a
   // multiple of 8 (or the whole tile count).
+  // issue priority over the near-field waves sharing the compute unit (the
+  // translations are on the product's critical path; the near field is not)
+  __builtin_amdgcn_s_setprio(2);
   const int nt = batch.ntiles;
   for (int vb = blockIdx.x; vb < nt; vb += gridDim.x) {
   __syncthreads();  // the previous tile no longer reads the shared arrays
@@ -898,6 +902,7 @@ __device__ __forceinline__ cplx<R> slice_sum(const int* __restrict__ pairs,
 template <typename R>
 __global__ void __launch_bounds__(256)
     k_pair_reduce(const RedBatch<R> batch, int accumulate) {
+  __builtin_amdgcn_s_setprio(2);  // critical path: ahead of the near-field waves
   __shared__ cplx<R> part[4][64];
   int q = 0;
 #pragma unroll
@@ -1095,6 +1100,7 @@ __global__ void __launch_bounds__(256)
                   const c64* __restrict__ dp, const c64* __restrict__ dq,
                   const c64* __restrict__ p64, const c64* __restrict__ q64,
                   c64* __restrict__ y) {
+  __builtin_amdgcn_s_setprio(2);  // critical path: ahead of the near-field waves
   cplx<R>* Lf = reinterpret_cast<cplx<R>*>(leaf_lds);
   const int b = blockIdx.x;
   leaf_expansion<R>(b, ncoef, red_ptr, red_pairs, cbuf, Lc, Lf);
@@ -1120,6 +1126,7 @@ __global__ void __launch_bounds__(256)
                       const cplx<R>* __restrict__ us, const cplx<R>* __restrict__ ws,
                       const c64* __restrict__ dp, const c64* __restrict__ dq,
                       const c64* __restrict__ y64, c64* __restrict__ u, c64* __restrict__ w) {
+  __builtin_amdgcn_s_setprio(2);  // critical path: ahead of the near-field waves
   cplx<R>* Mf = reinterpret_cast<cplx<R>*>(leaf_lds);
   const int b = blockIdx.x;
   leaf_expansion<R>(b, ncoef, red_ptr, red_pairs, cbuf, Mc, Mf);

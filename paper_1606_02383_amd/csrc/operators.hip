@@ -928,8 +928,11 @@ int build_operators(Problem& P, hipStream_t s) {
     if (!r) r = alloc_exec<float>(P, P.f32, P.f32.X, P.arena);
     if (r) return r;
   }
-  BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
-  BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side2, hipStreamNonBlocking));
+  if (!P.side || !P.side2) {
+    P.own_streams = true;
+    BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+    BEM_HIP_TRY(hipStreamCreateWithFlags(&P.side2, hipStreamNonBlocking));
+  }
   // fork/join events order work between this device's streams only: a
   // device-scope release suffices (no system-scope cache write-back)
   const unsigned evf = hipEventDisableTiming | hipEventReleaseToDevice;

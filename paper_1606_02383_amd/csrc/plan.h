@@ -171,6 +171,9 @@ struct Problem {
   // concurrently with the far-field chain; fork/join events
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // side streams given by the plan (shared by its problems) or created and
+  // owned by this problem
+  bool own_streams = false;
   // third stream: the leaf-level M2L (the largest) overlaps the coarser levels
   hipStream_t side2 = nullptr;
   hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
@@ -210,10 +213,6 @@ int prof_pair(Problem& P, int slot);  // a (start, end) pair for a launch's own 
 enum {
   SCHED_CONCURRENT = 0, SCHED_LEAF_SERIAL = 1, SCHED_LEAF_FIRST = 2, SCHED_P2P_AFTER_UP = 3,
   SCHED_LEAF_THEN_P2P = 4, SCHED_COUNT
-};
-
-struct Plan {
-  std::vector<Problem*> probs;
 };
 
 // ---- host entry points implemented in the .hip translation units ----

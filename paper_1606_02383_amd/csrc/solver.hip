@@ -1026,20 +1026,19 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
     }
   } sys_guard{sys};
   // every stage of the tick's products is launched once for all systems (on
-  // the caller's stream, near field and leaf-level M2L on two side streams)
+  // the caller's stream, near field and leaf-level M2L on the plan's two side
+  // streams, which the products of its problems use too)
   BatchStreams bs;
   bs.main = caller;
+  bs.side = probs[0]->side;
+  bs.side2 = probs[0]->side2;
   struct StreamGuard {
     BatchStreams& b;
     ~StreamGuard() {
       for (auto& e : b.ev)
         if (e) (void)hipEventDestroy(e);
-      if (b.side) (void)hipStreamDestroy(b.side);
-      if (b.side2) (void)hipStreamDestroy(b.side2);
     }
   } stream_guard{bs};
-  BEM_HIP_TRY(hipStreamCreateWithFlags(&bs.side, hipStreamNonBlocking));
-  BEM_HIP_TRY(hipStreamCreateWithFlags(&bs.side2, hipStreamNonBlocking));
   for (auto& e : bs.ev)
     BEM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventReleaseToDevice));
   hipStream_t s = caller;
