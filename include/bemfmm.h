@@ -185,10 +185,13 @@ int bem_gmres_solve(bem_plan* plan, int prob, const void* sigma, int adjoint, co
  * complex128, distinct x).  probs, sigma, adjoint, b, x and infos are HOST
  * arrays (of device pointers).  All systems advance in lockstep, one float64
  * residual or one Arnoldi step per system per tick, with one host
- * synchronisation per tick; systems of different problems run concurrently
- * on per-problem streams, systems of one problem share its stream.  Same
- * options and exit test as bem_gmres_solve (mode 1: GMRES(m) on the float32
- * operator inside each refinement step, restarted from the float64 residual).
+ * synchronisation per tick; each stage of a tick's products and each phase
+ * of its orthogonalisation is one launch over all systems (near field and
+ * leaf-level M2L on the plan's side streams).  The systems' Krylov and
+ * product buffers are kept by the plan for later calls (freed with it).
+ * Same options and exit test as bem_gmres_solve (mode 1: GMRES(m) on the
+ * float32 operator inside each refinement step, restarted from the float64
+ * residual).
  * Returns BEM_OK when every system converged, else the first failing status;
  * infos[i] (may be NULL) reports each system.  Ordered after prior work on
  * `stream`; synchronises before returning. */

@@ -165,8 +165,10 @@ struct Problem {
   c64* diag_q = nullptr;     // S_ii + alpha/2
   PrecisionData<double> f64;
   PrecisionData<float> f32;
-  // solver workspace (Krylov basis etc.), owned, see solver.hip
+  // solver workspace (Krylov basis etc.) and the batched solver's cached
+  // buffers, owned, see solver.hip
   void* solver_ws = nullptr;
+  void* batch_cache = nullptr;
   // second stream (default priority) for the direct near field, which runs
   // concurrently with the far-field chain; fork/join events
   hipStream_t side = nullptr;

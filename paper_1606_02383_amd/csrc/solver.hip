@@ -946,6 +946,8 @@ int objective_grad(Problem& P, const c64* beta, const double* dir, const double*
   return 0;
 }
 
+static void release_batch_cache(Problem& P);
+
 void release_workspace(Problem& P) {
   if (P.solver_ws) {
     Workspace* W = (Workspace*)P.solver_ws;
@@ -953,6 +955,7 @@ void release_workspace(Problem& P) {
     delete W;
     P.solver_ws = nullptr;
   }
+  release_batch_cache(P);
 }
 
 // ---------------------------------------------------------------------------
@@ -993,16 +996,52 @@ static int orth_batch(const OrthSysDev* tab, const std::vector<int>& sys_idx,
   return 0;
 }
 
+// Per-problem cache of the batched solver's buffers, kept across calls and
+// freed with the plan (allocations and frees inside a call would cost more
+// than a tick): system k of a problem in a batch uses slot k; slots k >= 1
+// also hold product buffers of their own.  The first problem of a batch
+// keeps the device table of the orthogonalisation operands.
+struct BatchSlot {
+  Workspace W;
+  DevArena exec_arena;
+  ExecBuf<float> x32;
+  ExecBuf<double> x64;
+  bool has_exec = false;
+};
+struct BatchCache {
+  std::vector<BatchSlot*> slots;
+  DevArena tab_arena;
+  OrthSysDev* tab = nullptr;
+  int tab_cap = 0;
+};
+
+static BatchCache& batch_cache_for(Problem& P) {
+  if (!P.batch_cache) P.batch_cache = new BatchCache();
+  return *(BatchCache*)P.batch_cache;
+}
+
+static void release_batch_cache(Problem& P) {
+  if (!P.batch_cache) return;
+  BatchCache* C = (BatchCache*)P.batch_cache;
+  for (BatchSlot* sl : C->slots) {
+    sl->W.release();
+    sl->exec_arena.release();
+    delete sl;
+  }
+  C->tab_arena.release();
+  delete C;
+  P.batch_cache = nullptr;
+}
+
 struct BatchSys {
   Problem* P = nullptr;
   int adjoint = 0;
   const c64* sigma = nullptr;
   const c64* b = nullptr;
   c64* x = nullptr;
-  Workspace W;
-  // product buffers: the problem's own for its first system, else these
-  ExecBuf<float> own32;
-  ExecBuf<double> own64;
+  Workspace* W = nullptr;  // from the problem's batch cache
+  // product buffers: the problem's own for its first system, else the
+  // cache slot's
   ExecBuf<float>* X32 = nullptr;
   ExecBuf<double>* X64 = nullptr;
   int state = 0;  // 0 outer residual, 1 Arnoldi, 2 done
@@ -1019,12 +1058,6 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
                       double inner_tol, int use_x0, bem_gmres_info* infos, hipStream_t caller) {
   const int ns = (int)probs.size();
   std::vector<BatchSys> sys(ns);
-  struct SysGuard {  // every exit path frees the per-system workspaces
-    std::vector<BatchSys>& v;
-    ~SysGuard() {
-      for (auto& S : v) S.W.release();
-    }
-  } sys_guard{sys};
   // every stage of the tick's products is launched once for all systems (on
   // the caller's stream, near field and leaf-level M2L on the plan's two side
   // streams, which the products of its problems use too)
@@ -1042,7 +1075,7 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
   for (auto& e : bs.ev)
     BEM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventReleaseToDevice));
   hipStream_t s = caller;
-  std::vector<Problem*> seen;
+  std::vector<std::pair<Problem*, int>> used;  // systems per problem so far
   for (int i = 0; i < ns; ++i) {
     BatchSys& S = sys[i];
     S.P = probs[i];
@@ -1050,17 +1083,27 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
     S.sigma = sigma[i];
     S.b = b[i];
     S.x = x[i];
-    int r = S.W.ensure(S.P->n, m);
+    int k = 0;
+    for (auto& u : used)
+      if (u.first == S.P) k = ++u.second;
+    if (k == 0) used.push_back({S.P, 0});
+    BatchCache& C = batch_cache_for(*S.P);
+    while ((int)C.slots.size() <= k) C.slots.push_back(new BatchSlot());
+    BatchSlot& sl = *C.slots[k];
+    int r = sl.W.ensure(S.P->n, m);
     if (r) return r;
-    if (std::find(seen.begin(), seen.end(), S.P) == seen.end()) {
-      seen.push_back(S.P);
+    S.W = &sl.W;
+    if (k == 0) {
       S.X32 = &S.P->f32.X;
       S.X64 = &S.P->f64.X;
     } else {  // a further system of the same problem: buffers of its own
-      if ((r = alloc_exec<float>(*S.P, S.P->f32, S.own32, S.W.arena))) return r;
-      if ((r = alloc_exec<double>(*S.P, S.P->f64, S.own64, S.W.arena))) return r;
-      S.X32 = &S.own32;
-      S.X64 = &S.own64;
+      if (!sl.has_exec) {
+        if ((r = alloc_exec<float>(*S.P, S.P->f32, sl.x32, sl.exec_arena))) return r;
+        if ((r = alloc_exec<double>(*S.P, S.P->f64, sl.x64, sl.exec_arena))) return r;
+        sl.has_exec = true;
+      }
+      S.X32 = &sl.x32;
+      S.X64 = &sl.x64;
     }
     S.H.assign((size_t)(m + 1) * m, 0.0);
     S.cs.assign(m, 0.0);
@@ -1068,19 +1111,24 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
     S.g.assign(m + 1, 0.0);
     S.first = !use_x0;
   }
-  // device table of the per-system orthogonalisation operands
-  DevArena tab_arena;
-  struct ArenaGuard {
-    DevArena& a;
-    ~ArenaGuard() { a.release(); }
-  } tab_guard{tab_arena};
+  // device table of the per-system orthogonalisation operands (written for
+  // every call: the slots of the systems depend on the batch)
   OrthSysDev* tab = nullptr;
   {
-    int r = tab_arena.alloc((void**)&tab, sizeof(OrthSysDev) * ns);
-    if (r) return r;
+    BatchCache& C0 = batch_cache_for(*probs[0]);
+    if (C0.tab_cap < ns) {
+      C0.tab_arena.release();
+      C0.tab = nullptr;
+      C0.tab_cap = 0;
+      const int cap = std::max(ns, 64);
+      int r = C0.tab_arena.alloc((void**)&C0.tab, sizeof(OrthSysDev) * cap);
+      if (r) return r;
+      C0.tab_cap = cap;
+    }
+    tab = C0.tab;
     std::vector<OrthSysDev> h(ns);
     for (int i = 0; i < ns; ++i) {
-      Workspace& W = sys[i].W;
+      Workspace& W = *sys[i].W;
       h[i] = OrthSysDev{W.V, W.w, W.n, W.partial, W.partial2, W.h, W.h2, W.hcol};
     }
     BEM_HIP_TRY(hipMemcpyAsync(tab, h.data(), sizeof(OrthSysDev) * ns, hipMemcpyHostToDevice, s));
@@ -1090,9 +1138,9 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
   std::vector<int64_t> orth_n;
   // norms of the right-hand sides
   for (auto& S : sys) {
-    int r = multidot(S.W, S.b, S.P->n, S.P->n, 1, S.b, S.W.h2, s);
+    int r = multidot(*S.W, S.b, S.P->n, S.P->n, 1, S.b, S.W->h2, s);
     if (r) return r;
-    BEM_HIP_TRY(hipMemcpyAsync(S.W.hscal, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, s));
+    BEM_HIP_TRY(hipMemcpyAsync(S.W->hscal, S.W->h2, sizeof(c64), hipMemcpyDeviceToHost, s));
     if (S.first) {
       hipLaunchKernelGGL(k_set_zero, dim3(ceil_div(S.P->n, 256)), dim3(256), 0, s, S.x, S.P->n);
       BEM_LAUNCH_CHECK();
@@ -1100,7 +1148,7 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
   }
   BEM_HIP_TRY(hipStreamSynchronize(s));
   for (auto& S : sys) {
-    S.bn = sqrt(S.W.hscal[0].re);
+    S.bn = sqrt(S.W->hscal[0].re);
     if (!std::isfinite(S.bn)) {
       S.status = -6;
       S.state = 2;
@@ -1124,16 +1172,16 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
       const int64_t n = S.P->n;
       const int nb = ceil_div(n, 256);
       const bool f32 = S.state == 1 && mode == 1;
-      const c64* vin = S.state == 0 ? S.x : S.W.V + (int64_t)S.j * n;
-      c64* vout = S.state == 0 ? S.W.t1 : S.W.w;
+      const c64* vin = S.state == 0 ? S.x : S.W->V + (int64_t)S.j * n;
+      c64* vout = S.state == 0 ? S.W->t1 : S.W->w;
       const c64* q = nullptr;
       c64* out2 = nullptr;
       if (!S.adjoint && S.sigma) {  // q = sigma v
-        hipLaunchKernelGGL(k_diag_mul, dim3(nb), dim3(256), 0, s, S.sigma, vin, n, 0, S.W.t3);
+        hipLaunchKernelGGL(k_diag_mul, dim3(nb), dim3(256), 0, s, S.sigma, vin, n, 0, S.W->t3);
         BEM_LAUNCH_CHECK();
-        q = S.W.t3;
+        q = S.W->t3;
       }
-      if (S.adjoint && S.sigma) out2 = S.W.t3;
+      if (S.adjoint && S.sigma) out2 = S.W->t3;
       wants[i] = 1;
       is32[i] = f32;
       if (f32)
@@ -1159,9 +1207,9 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
       const int nb = ceil_div(n, 256);
       int r = 0;
       if (wants[i]) {
-        c64* vout = S.state == 0 ? S.W.t1 : S.W.w;
+        c64* vout = S.state == 0 ? S.W->t1 : S.W->w;
         if (S.adjoint && S.sigma) {
-          hipLaunchKernelGGL(k_add_conj_diag, dim3(nb), dim3(256), 0, s, vout, S.sigma, S.W.t3,
+          hipLaunchKernelGGL(k_add_conj_diag, dim3(nb), dim3(256), 0, s, vout, S.sigma, S.W->t3,
                              n, vout);
           BEM_LAUNCH_CHECK();
         }
@@ -1172,13 +1220,13 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
       }
       if (S.state == 0) {
         if (S.first) {
-          hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, S.b, n, S.W.r);
+          hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, S.b, n, S.W->r);
         } else {
-          hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, s, S.b, S.W.t1, n, S.W.r);
+          hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, s, S.b, S.W->t1, n, S.W->r);
         }
         BEM_LAUNCH_CHECK();
-        if ((r = multidot(S.W, S.W.r, n, n, 1, S.W.r, S.W.h2, s))) return r;
-        BEM_HIP_TRY(hipMemcpyAsync(S.W.hscal, S.W.h2, sizeof(c64), hipMemcpyDeviceToHost, s));
+        if ((r = multidot(*S.W, S.W->r, n, n, 1, S.W->r, S.W->h2, s))) return r;
+        BEM_HIP_TRY(hipMemcpyAsync(S.W->hscal, S.W->h2, sizeof(c64), hipMemcpyDeviceToHost, s));
       } else {
         orth_sys.push_back(i);
         orth_nk.push_back(S.j + 1);
@@ -1197,7 +1245,7 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
       const int nb = ceil_div(n, 256);
       if (S.state == 0) {
         S.first = false;
-        S.rn = sqrt(S.W.hscal[0].re);
+        S.rn = sqrt(S.W->hscal[0].re);
         S.hist.push_back(S.rn / S.bn);
         if (!std::isfinite(S.rn)) {
           S.status = -6;
@@ -1218,9 +1266,9 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
                                         : tol * S.bn / S.rn;
         S.atol = itol * S.rn;
         S.beta = S.rn;
-        hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, S.W.r, n, S.W.V);
+        hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, S.W->r, n, S.W->V);
         BEM_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, s, S.W.V, n, 1.0 / S.beta);
+        hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, s, S.W->V, n, 1.0 / S.beta);
         BEM_LAUNCH_CHECK();
         std::fill(S.g.begin(), S.g.end(), 0.0);
         S.g[0] = S.beta;
@@ -1230,8 +1278,8 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
         const int j = S.j;
         std::vector<std::complex<double>> col(j + 2);
         for (int i = 0; i <= j; ++i)
-          col[i] = std::complex<double>(S.W.hcol[i].re, S.W.hcol[i].im);
-        double hn = sqrt(S.W.hcol[j + 1].re);
+          col[i] = std::complex<double>(S.W->hcol[i].re, S.W->hcol[i].im);
+        double hn = sqrt(S.W->hcol[j + 1].re);
         col[j + 1] = hn;
         ++S.iters;
         if (!std::isfinite(hn)) {
@@ -1271,11 +1319,11 @@ int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjo
             }
             yv[i] = acc / S.H[i * m + i];
           }
-          c64* yh = S.W.hcol + (S.W.m + 2);
+          c64* yh = S.W->hcol + (S.W->m + 2);
           for (int i = 0; i < jend; ++i) yh[i] = mk(yv[i].real(), yv[i].imag());
-          BEM_HIP_TRY(hipMemcpyAsync(S.W.y, yh, sizeof(c64) * jend,
+          BEM_HIP_TRY(hipMemcpyAsync(S.W->y, yh, sizeof(c64) * jend,
                                      hipMemcpyHostToDevice, s));
-          hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, S.W.V, n, n, jend, S.W.y, S.x);
+          hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, S.W->V, n, n, jend, S.W->y, S.x);
           BEM_LAUNCH_CHECK();
           ++S.outer;
           S.state = 0;
