@@ -960,7 +960,19 @@ __device__ __forceinline__ void finish_elem(
     if (ncoef > 0) {
       const cplx<R>* Bi = l2p + i * ncoef;
       const cplx<R>* Lb = elem_leaf ? Lc + (int64_t)elem_leaf[i] * ncoef : Lc;
-      for (int c = l; c < ncoef; c += FIN_LANES) cfma(acc, Bi[c], Lb[c]);
+      // four coefficients per lane per step, loads issued together (terms
+      // past ncoef are zero, so the sum and its order are unchanged)
+      for (int c0 = l; c0 < ncoef; c0 += 4 * FIN_LANES) {
+        cplx<R> bv[4], lv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u * FIN_LANES;
+          bv[u] = c < ncoef ? Bi[c] : mk<R>(0, 0);
+          lv[u] = c < ncoef ? Lb[c] : mk<R>(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cfma(acc, bv[u], lv[u]);
+      }
     }
     if (near_ptr)
       for (int t = near_ptr[i] + l; t < near_ptr[i + 1]; t += FIN_LANES) {
@@ -1013,11 +1025,24 @@ __device__ __forceinline__ void finish_adj_elem(
     if (ncoef > 0) {
       const cplx<R>* Aj = p2m + j * ncoef * 2;
       const cplx<R>* Mb = elem_leaf ? Mc + (int64_t)elem_leaf[j] * ncoef : Mc;
-      for (int c = l; c < ncoef; c += FIN_LANES) {
-        cplx<R> ap, aq;
-        load_pair(Aj + 2 * c, ap, aq);
-        cfmac(au, ap, Mb[c]);
-        cfmac(aw, aq, Mb[c]);
+      // four coefficients per lane per step, loads issued together
+      for (int c0 = l; c0 < ncoef; c0 += 4 * FIN_LANES) {
+        cplx<R> ap[4], aq[4], mv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u * FIN_LANES;
+          if (c < ncoef) {
+            load_pair(Aj + 2 * c, ap[u], aq[u]);
+            mv[u] = Mb[c];
+          } else {
+            ap[u] = aq[u] = mv[u] = mk<R>(0, 0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          cfmac(au, ap[u], mv[u]);
+          cfmac(aw, aq[u], mv[u]);
+        }
       }
     }
     if (tptr)
