@@ -587,10 +587,10 @@ __global__ void __launch_bounds__(256) k_leaf_accumulate(const LeafBatch<R> batc
 // for 128, else 4), operands staged through LDS in 16-wide k chunks, double
 // buffered: the global loads of chunk c + 1 are in flight while chunk c runs
 // on the matrix cores.  Complex products:
-//   float32: three real products per block (P1 = Ar Br, P2 = Ai Bi,
-//            P3 = (Ar + Ai)(Br + Bi); C = (P1 - P2, P3 - P1 - P2)), with the
-//            sums (Ar + Ai), (Br + Bi) formed once when staging;
-//   float64: four real products (C_re = Ar Br - Ai Bi, C_im = Ar Bi + Ai Br).
+//   three real products per block (P1 = Ar Br, P2 = Ai Bi,
+//   P3 = (Ar + Ai)(Br + Bi); C = (P1 - P2, P3 - P1 - P2)); float32 forms the
+//   sums (Ar + Ai), (Br + Bi) once when staging (a third LDS plane),
+//   float64 from the operands loaded from LDS.
 // The output tile is staged in LDS and written as whole coefficient rows per
 // pair (contiguous), either to the per-pair buffer, or added into the
 // destination (plain read-modify-write where every destination of the launch
