@@ -50,14 +50,20 @@ __host__ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) {
 // acc += a * b
 template <typename T>
 __host__ __device__ __forceinline__ void cfma(cplx<T>& acc, cplx<T> a, cplx<T> b) {
-  acc.re += a.re * b.re - a.im * b.im;
-  acc.im += a.re * b.im + a.im * b.re;
+  // two fused multiply-adds per component (acc += x*y - z*w would take a
+  // product, a fused multiply-add and an add)
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
 }
 // acc += conj(a) * b
 template <typename T>
 __host__ __device__ __forceinline__ void cfmac(cplx<T>& acc, cplx<T> a, cplx<T> b) {
-  acc.re += a.re * b.re + a.im * b.im;
-  acc.im += a.re * b.im - a.im * b.re;
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
 }
 
 typedef cplx<double> c64;  // complex128

@@ -91,9 +91,10 @@ __device__ __forceinline__ void bm_elem(R xx, R xy, R xz, R nxx, R nxy, R nxz, c
                                         cplx<R>& sp, cplx<R>& sq) {
   const R nn = nxx * nyx + nxy * nyy + nxz * nyz;
   const R rny = xx * nyx + xy * nyy + xz * nyz - d;
-  const R c1r = IMAG ? rny : rny + alr * nn, c1i = ali * nn;  // rny + alpha nn
+  const R c1r = rny + alr * nn, c1i = ali * nn;  // rny + alpha nn
   const R k2 = k * k, m3k = R(-3) * k;
-  R spr = 0, spi = 0, sqr = 0, sqi = 0;
+  const R ann = ali * nn, ali3 = R(3) * ali, alik2 = ali * k2;  // IMAG only
+  R spr, spi, sqr, sqi;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const R rx = xx - yq[3 * q], ry = xy - yq[3 * q + 1], rz = xz - yq[3 * q + 2];
@@ -104,30 +105,47 @@ __device__ __forceinline__ void bm_elem(R xx, R xy, R xz, R nxx, R nxy, R nxz, c
     phase<R>(r, k, k_turns, &sn, &cs);
     const R Gr = cs * u, Gi = sn * u;
     const R u2 = u * u;
-    const R a1r = -u2, a1i = k * u;
     const R rnx = rx * nxx + ry * nxy + rz * nxz;
-    // a2 rnx rny u^2 = (t, v) with a2 = (3 u^2 - k^2, -3 k u)
-    const R sc = rnx * rny * u2;
-    const R t = (R(3) * u2 - k2) * sc, v = m3k * u * sc;
-    // f = a1 (rny + alpha nn) + alpha (t, v);  g = 1 + alpha a1 rnx
-    R fr = a1r * c1r - a1i * c1i, fi = a1r * c1i + a1i * c1r;
-    R gr, gi;
-    if (IMAG) {
-      fr -= ali * v;
-      fi += ali * t;
-      const R ar = ali * rnx;
-      gr = R(1) - a1i * ar;
-      gi = a1r * ar;
+    R fr, fi, gr, gi;
+    if constexpr (IMAG) {
+      // alpha = i ali; with w = u^2, s = rnx rny w (terms of the general
+      // branch below, multiplied out):
+      //   f = (ali k u (3 s - nn) - w rny,  ali (3 w - k^2) s + k u rny - ali nn w)
+      //   g = (1 - ali k u rnx,  -ali w rnx)
+      const R ku = k * u, aku = ali * ku;
+      const R wr = u2 * rny, sc = rnx * wr;
+      fr = fma(aku, fma(R(3), sc, -nn), -wr);
+      fi = fma(fma(ali3, u2, -alik2), sc, fma(ku, rny, -u2 * ann));
+      gr = fma(-aku, rnx, R(1));
+      gi = -(ali * u2) * rnx;
     } else {
-      fr += alr * t - ali * v;
-      fi += alr * v + ali * t;
+      const R a1r = -u2, a1i = k * u;
+      // a2 rnx rny u^2 = (t, v) with a2 = (3 u^2 - k^2, -3 k u)
+      const R sc = rnx * rny * u2;
+      const R t = (R(3) * u2 - k2) * sc, v = m3k * u * sc;
+      // f = a1 (rny + alpha nn) + alpha (t, v);  g = 1 + alpha a1 rnx
+      fr = a1r * c1r - a1i * c1i + alr * t - ali * v;
+      fi = a1r * c1i + a1i * c1r + alr * v + ali * t;
       gr = R(1) + (alr * a1r - ali * a1i) * rnx;
       gi = (alr * a1i + ali * a1r) * rnx;
     }
-    spr += Gr * fr - Gi * fi;
-    spi += Gr * fi + Gi * fr;
-    sqr += Gr * gr - Gi * gi;
-    sqi += Gr * gi + Gi * gr;
+    // G f and G g, the first point's as the start of the sums (no additions
+    // of zero), then fused multiply-adds
+    if (q == 0) {
+      spr = Gr * fr;
+      spi = Gr * fi;
+      sqr = Gr * gr;
+      sqi = Gr * gi;
+    } else {
+      spr = fma(Gr, fr, spr);
+      spi = fma(Gr, fi, spi);
+      sqr = fma(Gr, gr, sqr);
+      sqi = fma(Gr, gi, sqi);
+    }
+    spr = fma(-Gi, fi, spr);
+    spi = fma(Gi, fr, spi);
+    sqr = fma(-Gi, gi, sqr);
+    sqi = fma(Gi, gr, sqi);
   }
   sp = mk<R>(spr, spi);
   sq = mk<R>(sqr, sqi);
