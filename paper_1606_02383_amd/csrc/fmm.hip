@@ -1316,14 +1316,12 @@ int prof_pair(Problem& P, int slot) {
   return idx;
 }
 
-// the leaf-level M2L's launch events: (start, done) = a timing pair when the
-// leaf M2L alone is profiled, else (none, the join event when it runs on the
-// third stream)
+// the leaf-level M2L's launch events: a timing pair when the leaf M2L alone is
+// profiled, else none
 template <typename R>
-static void leaf_m2l_events(Problem& P, bool adj, bool leaf_side, hipEvent_t* start,
-                            hipEvent_t* done) {
+static void leaf_m2l_events(Problem& P, bool adj, hipEvent_t* start, hipEvent_t* done) {
   *start = nullptr;
-  *done = leaf_side ? P.ev_join2 : nullptr;
+  *done = nullptr;
   if (!P.prof_leaf) return;
   const int idx = prof_pair(P, prof_slot(ST_M2L_LEAF, sizeof(R) == 4, adj));
   if (idx < 0) return;
@@ -1723,11 +1721,18 @@ static ZeroList<R> chain_zero_list(Problem& P, PrecisionData<R>& D, ExecBuf<R>& 
 }
 
 
-// Join before the finish: the completion events of the near field and (on
-// the third stream) of the leaf-level M2L, both signalled by their launches.
-static int join_side_streams(Problem& P, hipStream_t s, hipEvent_t leaf_done) {
-  BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
-  if (leaf_done) BEM_HIP_TRY(hipStreamWaitEvent(s, leaf_done, 0));
+// Join before the finish.  With the leaf-level M2L on the third stream (the
+// later of the two side paths to finish), that stream first waits for the
+// near field's completion event, so the caller's stream waits on one event
+// (each wait there costs it several microseconds).
+static int join_side_streams(Problem& P, hipStream_t s, bool leaf_side) {
+  if (leaf_side) {
+    BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_join, 0));
+    BEM_HIP_TRY(hipEventRecord(P.ev_join2, P.side2));
+    BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join2, 0));
+  } else {
+    BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
+  }
   return 0;
 }
 
@@ -1796,7 +1801,7 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   // (its per-destination sums are formed by the leaf finish)
   hipEvent_t m2l_start, m2l_done;
-  leaf_m2l_events<R>(P, false, leaf_side, &m2l_start, &m2l_done);
+  leaf_m2l_events<R>(P, false, &m2l_start, &m2l_done);
   if ((r = launch_grouped<R, 0>(D.m2l[L], false, X.M[L], X.Lc[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
                                 P.m2l_cap[sizeof(R) == 4], false, m2l_done, m2l_start)))
@@ -1811,7 +1816,7 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   PROF_BEGIN(e5);
   if ((r = downward_pass<R>(P, D, X, false, s))) return r;
   PROF_END(e5, ST_L2L);
-  if ((r = join_side_streams(P, s, leaf_side ? m2l_done : nullptr))) return r;
+  if ((r = join_side_streams(P, s, leaf_side))) return r;
   PROF_BEGIN(e6);
   {
     const GroupedOp<R>& op = D.m2l[L];
@@ -1899,7 +1904,7 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   PROF_END(e2, ST_P2M);
   if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   hipEvent_t m2l_start, m2l_done;
-  leaf_m2l_events<R>(P, true, leaf_side, &m2l_start, &m2l_done);
+  leaf_m2l_events<R>(P, true, &m2l_start, &m2l_done);
   if ((r = launch_grouped<R, 0>(D.m2l[L], true, X.Lc[L], X.M[L], sl, X.cbufL, 0,
                                 P.prof_on ? &P : nullptr, ST_M2L_LEAF,
                                 P.m2l_cap[sizeof(R) == 4], false, m2l_done, m2l_start)))
@@ -1914,7 +1919,7 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   PROF_BEGIN(e3);
   if ((r = downward_pass<R>(P, D, X, true, s))) return r;
   PROF_END(e3, ST_M2M);
-  if ((r = join_side_streams(P, s, leaf_side ? m2l_done : nullptr))) return r;
+  if ((r = join_side_streams(P, s, leaf_side))) return r;
   PROF_BEGIN(e6);
   {
     const GroupedOp<R>& op = D.m2l[L];
