@@ -173,6 +173,30 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+# float32 near field (alpha = i/k): per source element (three rule points)
+# the compiled inner loop of k_p2p<float, true> issues 122 vector ALU
+# instructions and 9 transcendentals (sin, cos, rsqrt; quarter rate, 4 issue
+# cycles each); a wave64 instruction occupies a 16-lane SIMD for 4 cycles, so
+# the chip issues 256 CUs x 2.4 GHz wave instructions per second (non-packed).
+P2P_VALU_PER_PAIR = 122
+P2P_TRANS_PER_PAIR = 9
+VALU_WAVE_SLOTS = 256 * 2.4e9
+
+
+def p2p_valu(st, prof):
+    """Issue-slot rate of the float32 near field (stage time from the stage
+    profile; the kernel shares the GPU with the far field there)."""
+    ms, calls = prof.get(("p2p", "f32", "fwd"), (0.0, 0))
+    if not calls:
+        return None
+    t = ms / calls / 1e3
+    slots = st["n_p2p_pairs"] / 64.0 * (P2P_VALU_PER_PAIR + 4 * P2P_TRANS_PER_PAIR)
+    return {"bound": "alu", "element_pairs": st["n_p2p_pairs"],
+            "vector_instr_per_pair": P2P_VALU_PER_PAIR + P2P_TRANS_PER_PAIR,
+            "avg_ms": round(t * 1e3, 5), "achieved_wave_slots_per_s": slots / t,
+            "peak_wave_slots_per_s": VALU_WAVE_SLOTS, "frac": round(slots / t / VALU_WAVE_SLOTS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,7 +325,8 @@ def main():
                 "coarse_levels_m2l": {"flops_per_launch": flops_coarse,
                                       "avg_launch_ms": round(coarse_launch_ms, 5),
                                       "tflops": round(flops_coarse / max(coarse_launch_ms, 1e-9)
-                                                      / 1e9, 3)}}
+                                                      / 1e9, 3)},
+                "p2p_valu": p2p_valu(st, prof)}
 
     cpu = None
     if not args.no_cpu_baseline:
