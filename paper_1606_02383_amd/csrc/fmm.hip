@@ -677,8 +677,12 @@ struct GemmBatch {
 
 // KIND: 0 M2L (per-pair output), 1 M2M, 2 L2L, 3 leaf -> ancestor, 4
 // ancestor -> leaf (the others add into dst)
+// Two workgroups per CU: at most 128 registers for the 8-wave (128-pair)
+// tiles, 256 for the 4-wave ones, so one tile's epilogue (the per-pair
+// output write) overlaps the other's matrix products.
 template <typename R, int CT, bool ADJ, int KIND>
-__global__ void __launch_bounds__(64 * TileShape<CT>::NW, TileShape<CT>::NW == 4 ? 2 : 1)
+__global__ void __launch_bounds__(64 * TileShape<CT>::NW)
+    __attribute__((amdgpu_waves_per_eu(TileShape<CT>::NW == 8 ? 4 : 2)))
     k_grouped_gemm(const GemmBatch<R> batch) {
   typedef typename MfmaOp<R>::v4 v4;
   typedef TileShape<CT> S;
