@@ -598,6 +598,72 @@ __global__ void __launch_bounds__(256) k_leaf_accumulate(const LeafBatch<R> batc
   }
 }
 
+// dynamic LDS of the leaf kernels (gather + leaf accumulation, leaf finish)
+extern __shared__ double leaf_lds[];
+constexpr size_t FUSED_LDS_MAX = 32768;  // bytes of leaf values in the fused gather
+
+// The gather folded into the leaf accumulation (P2M, or L2P^H for the
+// adjoint): block b gathers the elements of leaf b from the caller's order
+// into the sorted float64 and working-precision copies (used by P2P and the
+// finish) and into LDS, then forms the leaf expansion from them as
+// k_leaf_accumulate does; the grid also clears the listed expansions.
+// Dynamic LDS: (ADJ ? 1 : 2) * max_leaf values.
+template <typename R, bool ADJ>
+__global__ void __launch_bounds__(256)
+    k_gather_leaf(const c64* __restrict__ p, const c64* __restrict__ q,
+                  const int* __restrict__ perm, const int* __restrict__ bstart, int ncoef,
+                  const cplx<R>* __restrict__ mat, cplx<R>* __restrict__ ps,
+                  cplx<R>* __restrict__ qs, c64* __restrict__ p64, c64* __restrict__ q64,
+                  cplx<R>* __restrict__ out, const ZeroList<R> zl) {
+  __shared__ cplx<R> part[4][64];
+  __builtin_amdgcn_s_setprio(2);  // critical path: ahead of the near-field waves
+  cplx<R>* sa = reinterpret_cast<cplx<R>*>(leaf_lds);
+  const int b = blockIdx.x;
+  const int e0 = bstart[b], ne = bstart[b + 1] - e0;
+  cplx<R>* sb = sa + ne;
+  zero_list(zl, grid_tid(), grid_threads());
+  for (int t = threadIdx.x; t < ne; t += blockDim.x) {
+    const int e = e0 + t, o = perm[e];
+    const c64 a = p ? p[o] : mk(0.0, 0.0);
+    const cplx<R> ar = mk<R>((R)a.re, (R)a.im);
+    ps[e] = ar;
+    p64[e] = a;
+    sa[t] = ar;
+    if (!ADJ) {
+      const c64 c = q ? q[o] : mk(0.0, 0.0);
+      const cplx<R> cr = mk<R>((R)c.re, (R)c.im);
+      qs[e] = cr;
+      q64[e] = c;
+      sb[t] = cr;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncoef; c0 += 64) {
+    const int c = c0 + lane;
+    cplx<R> acc = mk<R>(0, 0);
+    if (c < ncoef) {
+      for (int t = sl; t < ne; t += 4) {
+        const int64_t e = e0 + t;
+        if (!ADJ) {
+          cplx<R> mp, mq;
+          load_pair(mat + (e * ncoef + c) * 2, mp, mq);
+          cfma(acc, mp, sa[t]);
+          cfma(acc, mq, sb[t]);
+        } else {
+          cfmac(acc, mat[e * ncoef + c], sa[t]);
+        }
+      }
+    }
+    part[sl][lane] = acc;
+    __syncthreads();
+    if (sl == 0 && c < ncoef)
+      out[(int64_t)b * ncoef + c] =
+          cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // grouped gather-GEMM-scatter on the matrix cores:
 //   dst[pair_dst] (+)= op_g src[pair_src]      (ADJ: op_g conjugate-transposed)
@@ -1111,8 +1177,6 @@ __global__ void __launch_bounds__(256)
 // so the values equal those of the separate reduction); then every element
 // of the leaf as in k_finish / k_finish_adj.
 // ---------------------------------------------------------------------------
-extern __shared__ double leaf_lds[];
-
 template <typename R>
 __device__ __forceinline__ void leaf_expansion(int b, int ncoef, const int* __restrict__ ptr,
                                                const int* __restrict__ pairs,
@@ -1752,22 +1816,34 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
   const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
-  // fork of the near field: signalled by the gather itself when the P2P
-  // follows it directly
+  // gather and P2M in one launch when a leaf's values fit in LDS and the
+  // near field does not start right after the gather (it would start later:
+  // measured slower); its completion (event ev_fork2) forks the leaf M2L
+  const size_t lds_fused = 2 * (size_t)P.max_leaf * sizeof(cplx<R>);
+  const bool fused = !P.direct && !p2p_first && lds_fused <= FUSED_LDS_MAX;
+  // else the gather's completion forks the near field when it follows directly
   const bool fork_at_gather = p2p_first && !P.direct;
+  int r = 0;
   PROF_BEGIN(e0);
-  launch_done(k_gather_in<R>, dim3(nb), dim3(256), 0, s, nullptr,
-              fork_at_gather ? P.ev_fork : nullptr, p, q, P.perm, n, X.ps, X.qs, X.p64s, X.q64s,
-              chain_zero_list(P, D, X, false, true));
+  if (fused) {
+    launch_done(k_gather_leaf<R, false>, dim3(nleaf), dim3(256), lds_fused, s, nullptr,
+                P.ev_fork2, p, q, P.perm, P.box_start[L], D.ncoef[L], D.p2m, X.ps, X.qs, X.p64s,
+                X.q64s, X.M[L], chain_zero_list(P, D, X, false, true));
+  } else {
+    launch_done(k_gather_in<R>, dim3(nb), dim3(256), 0, s, nullptr,
+                fork_at_gather ? P.ev_fork : nullptr, p, q, P.perm, n, X.ps, X.qs, X.p64s,
+                X.q64s, chain_zero_list(P, D, X, false, true));
+  }
   BEM_LAUNCH_CHECK();
-  PROF_END(e0, ST_GATHER);
+  PROF_END(e0, fused ? ST_P2M : ST_GATHER);
   // the near field runs on the side stream, concurrently with the far field
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
     if (!P.direct) {
-      // behind the leaf M2L: forked by the P2M's completion event
-      hipEvent_t fork = sched == SCHED_LEAF_THEN_P2P ? P.ev_fork2 : P.ev_fork;
-      if (!fork_at_gather && sched != SCHED_LEAF_THEN_P2P)
+      hipEvent_t fork = P.ev_fork;
+      if (sched == SCHED_LEAF_THEN_P2P)
+        fork = P.ev_fork2;  // completion of the P2M (or gather + P2M)
+      else if (!fork_at_gather)
         BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
       BEM_HIP_TRY(hipStreamWaitEvent(sn, fork, 0));
     }
@@ -1780,7 +1856,6 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
     if (pr) return pr;
     return 0;
   };
-  int r = 0;
   if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
@@ -1795,13 +1870,13 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP ||
                          sched == SCHED_LEAF_THEN_P2P;
   hipStream_t sl = leaf_side ? P.side2 : s;
-  PROF_BEGIN(e2);
-  {
+  if (!fused) {
+    PROF_BEGIN(e2);
     const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], D.p2m, X.ps, X.qs, X.M[L]};
     if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, 0, s, leaf_side ? P.ev_fork2 : nullptr)))
       return r;
+    PROF_END(e2, ST_P2M);
   }
-  PROF_END(e2, ST_P2M);
   if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   // (its per-destination sums are formed by the leaf finish)
   hipEvent_t m2l_start, m2l_done;
@@ -1859,19 +1934,31 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
   const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
+  // gather and L2P^H in one launch under the forward product's conditions
+  const size_t lds_fused = (size_t)P.max_leaf * sizeof(cplx<R>);
+  const bool fused = !P.direct && !p2p_first && lds_fused <= FUSED_LDS_MAX;
   const bool fork_at_gather = p2p_first && !P.direct;
+  int r = 0;
   PROF_BEGIN(e0);
-  launch_done(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, nullptr,
-              fork_at_gather ? P.ev_fork : nullptr, y, P.perm, n, X.ps, X.p64s,
-              chain_zero_list(P, D, X, true, true));
+  if (fused) {
+    launch_done(k_gather_leaf<R, true>, dim3(nleaf), dim3(256), lds_fused, s, nullptr,
+                P.ev_fork2, y, (const c64*)nullptr, P.perm, P.box_start[L], D.ncoef[L], D.l2p,
+                X.ps, (cplx<R>*)nullptr, X.p64s, (c64*)nullptr, X.Lc[L],
+                chain_zero_list(P, D, X, true, true));
+  } else {
+    launch_done(k_gather_adj<R>, dim3(nb), dim3(256), 0, s, nullptr,
+                fork_at_gather ? P.ev_fork : nullptr, y, P.perm, n, X.ps, X.p64s,
+                chain_zero_list(P, D, X, true, true));
+  }
   BEM_LAUNCH_CHECK();
-  PROF_END(e0, ST_GATHER);
+  PROF_END(e0, fused ? ST_P2M : ST_GATHER);
   auto launch_p2p = [&]() -> int {
     hipStream_t sn = P.direct ? s : P.side;
     if (!P.direct) {
-      // behind the leaf M2L: forked by the P2M's completion event
-      hipEvent_t fork = sched == SCHED_LEAF_THEN_P2P ? P.ev_fork2 : P.ev_fork;
-      if (!fork_at_gather && sched != SCHED_LEAF_THEN_P2P)
+      hipEvent_t fork = P.ev_fork;
+      if (sched == SCHED_LEAF_THEN_P2P)
+        fork = P.ev_fork2;  // completion of the L2P^H (or gather + L2P^H)
+      else if (!fork_at_gather)
         BEM_HIP_TRY(hipEventRecord(P.ev_fork, s));
       BEM_HIP_TRY(hipStreamWaitEvent(sn, fork, 0));
     }
@@ -1884,7 +1971,6 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
     if (pr) return pr;
     return 0;
   };
-  int r = 0;
   if (p2p_first && (r = launch_p2p())) return r;
   if (P.direct) {
     hipLaunchKernelGGL(k_finish_adj<R>, dim3(ceil_div(n * FIN_LANES, 256)), dim3(256), 0, s, n, P.perm,
@@ -1899,13 +1985,13 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP ||
                          sched == SCHED_LEAF_THEN_P2P;
   hipStream_t sl = leaf_side ? P.side2 : s;
-  PROF_BEGIN(e2);
-  {
+  if (!fused) {
+    PROF_BEGIN(e2);
     const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], D.l2p, X.ps, nullptr, X.Lc[L]};
     if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, 1, s, leaf_side ? P.ev_fork2 : nullptr)))
       return r;
+    PROF_END(e2, ST_P2M);
   }
-  PROF_END(e2, ST_P2M);
   if (leaf_side) BEM_HIP_TRY(hipStreamWaitEvent(P.side2, P.ev_fork2, 0));
   hipEvent_t m2l_start, m2l_done;
   leaf_m2l_events<R>(P, true, &m2l_start, &m2l_done);

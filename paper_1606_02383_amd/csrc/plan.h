@@ -132,6 +132,7 @@ struct Problem {
   double lo[3]{}, R0 = 0, scale = 0, ell_max = 0;
   // tree
   int L = 0;
+  int max_leaf = 0;  // elements in the fullest leaf
   float tuned_ms = 0.f;  // autotuner: float32 product time of the kept leaf level
   // stream schedule of the products per precision (0 float64, 1 float32),
   // chosen by timing at plan creation

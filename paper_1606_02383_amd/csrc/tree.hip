@@ -651,6 +651,8 @@ int build_geometry_and_tree(Problem& P, const double* vert, int64_t n_vert, cons
   }
   if (L > L_near) L = L_near;
   P.L = L;
+  r = max_occupancy(P, L, scratch, s, &P.max_leaf);
+  if (r) return r;
   P.direct = !(P.h[L] > P.eta * P.ell_max);
 
   // boxes of every level 0..L and parents
