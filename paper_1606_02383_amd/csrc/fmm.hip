@@ -833,14 +833,10 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
       }
       const int r = r0 + rr, c = k0 + kk;
       cplx<R> v = mk<R>(0, 0);
-      if (r < out_rows && c < in_cols) {
-        if (ADJ) {
-          cplx<R> m = M[(int64_t)c * mat_cols + r];
-          v = mk<R>(m.re, -m.im);
-        } else {
-          v = M[(int64_t)r * mat_cols + c];
-        }
-      }
+      // (ADJ: the stored entry, conjugated when staged in LDS, so that no
+      // use of the loaded value waits for the load inside this prefetch)
+      if (r < out_rows && c < in_cols)
+        v = ADJ ? M[(int64_t)c * mat_cols + r] : M[(int64_t)r * mat_cols + c];
       ra[q] = v;
     }
 #pragma unroll
@@ -858,9 +854,10 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
     for (int q = 0; q < PA; ++q) {
       const int e = tid + NT * q;
       const int kk = ADJ ? e / G_RT : e % G_KC, rr = ADJ ? e % G_RT : e / G_KC;
+      const R im = ADJ ? -ra[q].im : ra[q].im;  // ADJ: conjugate
       A0[rr * G_LD + kk] = ra[q].re;
-      A0[G_RT * G_LD + rr * G_LD + kk] = ra[q].im;
-      if (STAGE3) A0[2 * G_RT * G_LD + rr * G_LD + kk] = ra[q].re + ra[q].im;
+      A0[G_RT * G_LD + rr * G_LD + kk] = im;
+      if (STAGE3) A0[2 * G_RT * G_LD + rr * G_LD + kk] = ra[q].re + im;
     }
 #pragma unroll
     for (int q = 0; q < PB; ++q) {
