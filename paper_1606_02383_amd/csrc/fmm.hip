@@ -1468,6 +1468,10 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
   RedBatch<R> rb{};
   b.n = rb.n = nj;
   int nt = 0, nbox = 0, ct = 0;
+  // adjoint M2L: the stored conjugate transposes through the forward
+  // operand path (the transposed load path is slower)
+  bool via_fwd = adj && KIND == 0;
+  for (int q = 0; q < nj; ++q) via_fwd = via_fwd && jobs[q].op->mats_h;
   for (int q = 0; q < nj; ++q) {
     const GroupedOp<R>& op = *jobs[q].op;
     if (KIND == 0 && !jobs[q].cbuf) {
@@ -1481,8 +1485,8 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
     }
     ct = jct;
     GemmJobDev<R>& J = b.job[q];
-    J.mat_rows = op.rows;
-    J.mat_cols = op.cols;
+    J.mat_rows = via_fwd ? op.cols : op.rows;
+    J.mat_cols = via_fwd ? op.rows : op.cols;
     J.tile_group = adj ? op.tile_group_adj : op.tile_group;
     J.tile_pair0 = adj ? op.tile_pair0_adj : op.tile_pair0;
     J.tile_npairs = adj ? op.tile_npairs_adj : op.tile_npairs;
@@ -1490,7 +1494,7 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
     J.group_slot = op.group_slot;
     J.pair_dst = adj ? op.pair_dst_adj : op.pair_dst;
     J.pair_src = adj ? op.pair_src_adj : op.pair_src;
-    J.mats = op.mats;
+    J.mats = via_fwd ? op.mats_h : op.mats;
     J.src = jobs[q].src;
     J.dst = jobs[q].dst;
     J.cbuf = jobs[q].cbuf;
@@ -1513,8 +1517,9 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
   if (nt > 0) {
     int evg = prof ? prof_begin(*prof, s) : -1;
     const int grid = (grid_cap > 0 && grid_cap < nt) ? (grid_cap & ~7) : nt;
-    int r = adj ? launch_gemm_ct<R, true, KIND>(b, ct, grid > 0 ? grid : nt, s, done, start)
-                : launch_gemm_ct<R, false, KIND>(b, ct, grid > 0 ? grid : nt, s, done, start);
+    int r = (adj && !via_fwd)
+                 ? launch_gemm_ct<R, true, KIND>(b, ct, grid > 0 ? grid : nt, s, done, start)
+                 : launch_gemm_ct<R, false, KIND>(b, ct, grid > 0 ? grid : nt, s, done, start);
     if (r) return r;
     if (prof) {
       int pr = prof_end(*prof, evg, prof_slot(st_gemm, sizeof(R) == 4, adj), s);

@@ -383,6 +383,18 @@ static std::vector<double> coef_scale(int p, double kh, int power) {
   return out;
 }
 
+// out[g][c][r] = conj(in[g][r][c]) for n matrices of rows x cols
+template <typename R>
+__global__ void k_conj_transpose(const cplx<R>* __restrict__ in, int n, int rows, int cols,
+                                 cplx<R>* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * rows * cols) return;
+  const int64_t per = (int64_t)rows * cols, g = t / per;
+  const int r = (int)((t - g * per) / cols), c = (int)(t - g * per - (int64_t)r * cols);
+  const cplx<R> v = in[t];
+  out[g * per + (int64_t)c * rows + r] = mk<R>(v.re, -v.im);
+}
+
 template <typename R>
 static int make_translations(Problem& P, int ngroups, const std::vector<double>& tvec, int sing,
                              int pin, int pout, const std::vector<double>& rs,
@@ -696,6 +708,11 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
       std::vector<double> rs = coef_scale(p, k * P.h[l], +1), cs = coef_scale(p, k * P.h[l], +1);
       r = make_translations<R>(P, ns, tv, 1, p, p, rs, cs, &op.mats, scratch, s);
       if (r) return r;
+      const int64_t tot = (int64_t)ns * op.rows * op.cols;
+      ARENA_ALLOC(P.arena, op.mats_h, tot);
+      hipLaunchKernelGGL(k_conj_transpose<R>, dim3(ceil_div(tot, 256)), dim3(256), 0, s,
+                         op.mats, ns, op.rows, op.cols, op.mats_h);
+      BEM_LAUNCH_CHECK();
     }
     r = finish_grouped<R>(op, d0, s0, c0, np, N_OFFSETS, slot, P.arena, scratch, s);
     if (r) return r;

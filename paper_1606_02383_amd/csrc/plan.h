@@ -45,6 +45,9 @@ struct GroupedOp {
   int* tile_row0 = nullptr;
   int* group_slot = nullptr;       // device: group id -> matrix slot
   cplx<R>* mats = nullptr;         // device: n_slots x rows x cols
+  // M2L only: the conjugate transposes (n_slots x cols x rows), so that the
+  // adjoint product runs the forward kernel's operand path
+  cplx<R>* mats_h = nullptr;
   int n_slots = 0;
   // adjoint: dst/src swapped, op conjugate-transposed (rows <-> cols)
   int n_tiles_adj = 0;
