@@ -237,6 +237,20 @@ int bem_tree_export(bem_plan* plan, int prob, void* keys, void* perm, void* stre
 int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, void* end,
                       void* stream);
 
+/* Interaction lists of the octree (the FMM's partition of the element pairs,
+ * Sec. 3): at tree level `level` (2 .. leaf level) the level's non-empty box
+ * keys (uint64, level keys, ascending; *n_boxes of them) and its
+ * multipole-to-local (V list) pairs as (destination, source) indices into
+ * those keys (int32, *n_pairs each; grouped by translation vector); at the
+ * leaf level also the near-field (U) lists, CSR over the leaves (u_ptr:
+ * *n_boxes + 1 int32, u_idx: *n_u int32 leaf indices).  Device buffers
+ * (any may be NULL: sizes only); the sizes go to the host integers (any may
+ * be NULL).  Level outside 2 .. leaf level: BEM_E_INVALID; a plan without a
+ * far field (direct sum) has no V pairs.  Synchronises the stream. */
+int bem_lists_export(bem_plan* plan, int prob, int level, void* box_keys, void* v_dst,
+                     void* v_src, void* u_ptr, void* u_idx, int64_t* n_boxes,
+                     int64_t* n_pairs, int64_t* n_u, void* stream);
+
 /* Overrides the choices made by timing at plan creation for problem `prob`
  * and precision prec (BEM_C128 / BEM_C64), see bem_plan_stats: stream
  * schedule (0..4), near-field and leaf-level M2L grids (0: one workgroup per

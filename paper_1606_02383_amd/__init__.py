@@ -32,7 +32,7 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
            "bem_plane_wave_rhs", "bem_eval_field",
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
-           "bem_leaves_export", "bem_plan_set_tuning", "bem_profile_start",
+           "bem_leaves_export", "bem_lists_export", "bem_plan_set_tuning", "bem_profile_start",
            "bem_profile_leaf_m2l_start", "bem_profile_stop", "bem_last_error"]
 
 STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH):
                                        vp, ctypes.POINTER(_Info), ctypes.POINTER(_Info), vp]
     lib.bem_tree_export.argtypes = [vp, i32, vp, vp, vp]
     lib.bem_leaves_export.argtypes = [vp, i32, vp, vp, vp, vp]
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.bem_lists_export.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, i64p, i64p, i64p, vp]
     lib.bem_plan_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32, i32]
     lib.bem_profile_start.argtypes = [vp, i32]
     lib.bem_profile_leaf_m2l_start.argtypes = [vp, i32]
@@ -394,6 +396,27 @@ class Plan:
         e = torch.empty(nl, dtype=torch.int32, device=self.device)
         _check(_LIB.bem_leaves_export(self._h, prob, _ptr(keys), _ptr(s), _ptr(e), _stream()))
         return keys, s, e
+
+    def lists_export(self, level, prob=0):
+        """Box keys, V-list (destination, source) index pairs and, at the leaf
+        level, the U lists (CSR) of tree level ``level``."""
+        import torch
+        nb, npr, nu = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_LIB.bem_lists_export(self._h, prob, int(level), None, None, None, None, None,
+                                     ctypes.byref(nb), ctypes.byref(npr), ctypes.byref(nu),
+                                     _stream()))
+        dev = self.device
+        keys = torch.empty(nb.value, dtype=torch.int64, device=dev)
+        vd = torch.empty(max(npr.value, 1), dtype=torch.int32, device=dev)
+        vs = torch.empty(max(npr.value, 1), dtype=torch.int32, device=dev)
+        up = torch.empty(nb.value + 1, dtype=torch.int32, device=dev)
+        ui = torch.empty(max(nu.value, 1), dtype=torch.int32, device=dev)
+        _check(_LIB.bem_lists_export(self._h, prob, int(level), _ptr(keys), _ptr(vd), _ptr(vs),
+                                     _ptr(up), _ptr(ui), None, None, None, _stream()))
+        out = dict(keys=keys, v_dst=vd[:npr.value], v_src=vs[:npr.value])
+        if nu.value:
+            out.update(u_ptr=up, u_idx=ui[:nu.value])
+        return out
 
 
 def _objective_function():

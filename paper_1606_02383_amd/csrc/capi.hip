@@ -467,6 +467,37 @@ int bem_leaves_export(bem_plan* plan, int prob, void* box_keys, void* start, voi
   return BEM_OK;
 }
 
+int bem_lists_export(bem_plan* plan, int prob, int level, void* box_keys, void* v_dst,
+                     void* v_src, void* u_ptr, void* u_idx, int64_t* n_boxes,
+                     int64_t* n_pairs, int64_t* n_u, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  if (level < 2 || level > P->L) return fail(BEM_E_INVALID, "level outside 2 .. leaf level");
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = P->nbox[level];
+  const GroupedOp<double>& op = P->f64.m2l[level];
+  const int np = P->direct ? 0 : op.n_pairs;
+  const bool leaf = level == P->L;
+  if (n_boxes) *n_boxes = nb;
+  if (n_pairs) *n_pairs = np;
+  if (n_u) *n_u = leaf ? P->n_u : 0;
+  if (box_keys)
+    BEM_HIP_TRY(hipMemcpyAsync(box_keys, P->box_keys[level], sizeof(uint64_t) * nb,
+                               hipMemcpyDeviceToDevice, s));
+  if (np > 0 && v_dst)
+    BEM_HIP_TRY(hipMemcpyAsync(v_dst, op.pair_dst, sizeof(int) * np, hipMemcpyDeviceToDevice, s));
+  if (np > 0 && v_src)
+    BEM_HIP_TRY(hipMemcpyAsync(v_src, op.pair_src, sizeof(int) * np, hipMemcpyDeviceToDevice, s));
+  if (leaf && u_ptr)
+    BEM_HIP_TRY(hipMemcpyAsync(u_ptr, P->u_ptr, sizeof(int) * (nb + 1), hipMemcpyDeviceToDevice,
+                               s));
+  if (leaf && u_idx && P->n_u > 0)
+    BEM_HIP_TRY(hipMemcpyAsync(u_idx, P->u_idx, sizeof(int) * P->n_u, hipMemcpyDeviceToDevice,
+                               s));
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  return BEM_OK;
+}
+
 int bem_plan_set_tuning(bem_plan* plan, int prob, int prec, int schedule, int p2p_grid,
                         int m2l_grid, int direct_depth) {
   Problem* P = get_prob(plan, prob);

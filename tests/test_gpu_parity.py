@@ -82,6 +82,45 @@ def test_tree_bit_exact_small(mesh):
     assert ls.cpu().numpy().tolist() == t.leaf_start
 
 
+def _check_lists(plan, t):
+    """Box keys, V-list pairs (every level) and U lists (leaf level) of the
+    GPU tree equal the oracle's, element for element (as ordered pairs)."""
+    L = t.L
+    assert plan.stats()["leaf_level"] == L
+    for lev in range(2, L + 1):
+        d = plan.lists_export(lev)
+        keys = [int(x) for x in d["keys"].cpu().numpy()]
+        assert keys == t.boxes[lev], lev
+        vd, vs = d["v_dst"].cpu().numpy(), d["v_src"].cpu().numpy()
+        got = sorted((keys[i], keys[j]) for i, j in zip(vd, vs))
+        want = sorted((b, c) for b in t.boxes[lev] for c in t.vlist(lev, b))
+        assert got == want, lev
+    d = plan.lists_export(L)
+    keys = [int(x) for x in d["keys"].cpu().numpy()]
+    up, ui = d["u_ptr"].cpu().numpy(), d["u_idx"].cpu().numpy()
+    assert len(up) == len(keys) + 1
+    for b, key in enumerate(keys):
+        got = sorted(keys[j] for j in ui[up[b]:up[b + 1]])
+        assert got == t.ulist(key), key
+
+
+def test_interaction_lists_bit_exact_sphere1280(sphere1280, plan1280):
+    V, T, g, k, _, _ = sphere1280
+    _log("case: interaction lists sphere1280")
+    _check_lists(plan1280, otree.Tree(g.cen, leaf_cap=32, ell_max=float(g.ell.max())))
+
+
+@pytest.mark.parametrize("mesh", ["cube32", "ico5"])
+def test_interaction_lists_bit_exact(mesh):
+    bem = _lib()
+    V, T = cube_surface(32) if mesh == "cube32" else icosphere(5)
+    cap = 32 if mesh == "cube32" else 64
+    _log(f"case: interaction lists {mesh}")
+    plan = bem.Plan(bem.Problem(V, T, 2.0, leaf_cap=cap))
+    gg = obem.Geometry(V, T)
+    _check_lists(plan, otree.Tree(gg.cen, leaf_cap=cap, ell_max=float(gg.ell.max())))
+
+
 def test_matvec_f64_sphere1280(sphere1280, plan1280):
     import torch
     _, T, g, k, Mp, Mq = sphere1280
