@@ -251,6 +251,15 @@ int bem_lists_export(bem_plan* plan, int prob, int level, void* box_keys, void* 
                      void* v_src, void* u_ptr, void* u_idx, int64_t* n_boxes,
                      int64_t* n_pairs, int64_t* n_u, void* stream);
 
+/* Near-field pairs of problem `prob` (the pairs whose rule-point integrals
+ * are replaced by accurate ones, Sec. 2.3 discretisation): CSR by target in
+ * sorted element order (bem_tree_export's perm maps a sorted index to the
+ * caller's), ptr: n + 1 int32, col: *n_near int32 source indices (sorted
+ * order).  Device buffers (either may be NULL: size only); *n_near on the
+ * host (may be NULL).  Synchronises the stream. */
+int bem_near_export(bem_plan* plan, int prob, void* ptr, void* col, int64_t* n_near,
+                    void* stream);
+
 /* Overrides the choices made by timing at plan creation for problem `prob`
  * and precision prec (BEM_C128 / BEM_C64), see bem_plan_stats: stream
  * schedule (0..4), near-field and leaf-level M2L grids (0: one workgroup per

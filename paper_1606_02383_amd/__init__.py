@@ -32,7 +32,8 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
            "bem_plane_wave_rhs", "bem_eval_field",
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
-           "bem_leaves_export", "bem_lists_export", "bem_plan_set_tuning", "bem_profile_start",
+           "bem_leaves_export", "bem_lists_export", "bem_near_export", "bem_plan_set_tuning",
+           "bem_profile_start",
            "bem_profile_leaf_m2l_start", "bem_profile_stop", "bem_last_error"]
 
 STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
@@ -111,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     lib.bem_leaves_export.argtypes = [vp, i32, vp, vp, vp, vp]
     i64p = ctypes.POINTER(ctypes.c_int64)
     lib.bem_lists_export.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, i64p, i64p, i64p, vp]
+    lib.bem_near_export.argtypes = [vp, i32, vp, vp, i64p, vp]
     lib.bem_plan_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32, i32]
     lib.bem_profile_start.argtypes = [vp, i32]
     lib.bem_profile_leaf_m2l_start.argtypes = [vp, i32]
@@ -417,6 +419,16 @@ class Plan:
         if nu.value:
             out.update(u_ptr=up, u_idx=ui[:nu.value])
         return out
+
+    def near_export(self, prob=0):
+        """Near-field pairs as CSR by target (sorted element order)."""
+        import torch
+        nn = ctypes.c_int64()
+        _check(_LIB.bem_near_export(self._h, prob, None, None, ctypes.byref(nn), _stream()))
+        ptr = torch.empty(self.n[prob] + 1, dtype=torch.int32, device=self.device)
+        col = torch.empty(max(nn.value, 1), dtype=torch.int32, device=self.device)
+        _check(_LIB.bem_near_export(self._h, prob, _ptr(ptr), _ptr(col), None, _stream()))
+        return ptr, col[:nn.value]
 
 
 def _objective_function():

@@ -498,6 +498,22 @@ int bem_lists_export(bem_plan* plan, int prob, int level, void* box_keys, void* 
   return BEM_OK;
 }
 
+int bem_near_export(bem_plan* plan, int prob, void* ptr, void* col, int64_t* n_near,
+                    void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  hipStream_t s = (hipStream_t)stream;
+  if (n_near) *n_near = P->n_near;
+  if (ptr)
+    BEM_HIP_TRY(hipMemcpyAsync(ptr, P->near_ptr, sizeof(int) * (P->n + 1),
+                               hipMemcpyDeviceToDevice, s));
+  if (col && P->n_near > 0)
+    BEM_HIP_TRY(hipMemcpyAsync(col, P->near_col, sizeof(int) * P->n_near,
+                               hipMemcpyDeviceToDevice, s));
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  return BEM_OK;
+}
+
 int bem_plan_set_tuning(bem_plan* plan, int prob, int prec, int schedule, int p2p_grid,
                         int m2l_grid, int direct_depth) {
   Problem* P = get_prob(plan, prob);

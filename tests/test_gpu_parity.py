@@ -121,6 +121,30 @@ def test_interaction_lists_bit_exact(mesh):
     _check_lists(plan, otree.Tree(gg.cen, leaf_cap=cap, ell_max=float(gg.ell.max())))
 
 
+def test_near_pairs_match_oracle_sphere1280(sphere1280, plan1280):
+    """The near-field pairs (accurate integrals) are the oracle's: same
+    pairs, except ones whose squared distance ties the squared radius to
+    rounding (both sides decide in float64, in their own operation order)."""
+    V, T, g, k, _, _ = sphere1280
+    _log("case: near-field pairs sphere1280")
+    _, perm = plan1280.tree_export()
+    perm = perm.cpu().numpy()
+    ptr, col = plan1280.near_export()
+    ptr, col = ptr.cpu().numpy(), col.cpu().numpy()
+    got = {(int(perm[i]), int(perm[j])) for i in range(len(perm)) for j in col[ptr[i]:ptr[i + 1]]}
+    assert len(got) == len(col)  # no repeated pair
+    n = len(T)
+    m = obem.near_mask(g, np.arange(n), np.arange(n))
+    want = set(zip(*np.nonzero(m)))
+    want = {(int(a), int(b)) for a, b in want}
+    for i, j in got ^ want:
+        d2 = float(np.sum((g.cen[i] - g.cen[j]) ** 2))
+        lim = (2.0 * g.ell[j]) ** 2
+        assert abs(d2 - lim) <= 1e-12 * lim, (i, j, d2, lim)
+    assert len(got ^ want) <= 2
+    _log(f"  {len(got)} near pairs, {len(got ^ want)} on the radius")
+
+
 def test_matvec_f64_sphere1280(sphere1280, plan1280):
     import torch
     _, T, g, k, Mp, Mq = sphere1280
