@@ -67,6 +67,14 @@ def test_bad_calls_are_rejected():
         plan.matvec(p, prec=7)
     with pytest.raises(RuntimeError, match="INVALID"):
         plan.solve(p, opts=bem.GmresOptions(tol=0.0))
+    L = plan.stats()["leaf_level"]
+    for bad in (1, L + 1):
+        with pytest.raises(RuntimeError, match="INVALID"):
+            plan.lists_export(bad)
+    n = ctypes.c_int64()
+    assert lib.bem_near_export(plan._h, 5, None, None, ctypes.byref(n), None) == -1
+    assert lib.bem_lists_export(plan._h, 0, 2, None, None, None, None, None, None, None, None,
+                                None) == (0 if L >= 2 else -1)
 
 
 def test_solver_status_paths():
