@@ -541,6 +541,7 @@ __device__ __forceinline__ void load_pair(const cplx<double>* p, cplx<double>& a
 // Per-leaf accumulation over the leaf's elements e:
 //   mode 0 (P2M):     out[b][c] = sum_e mat[e][c][0] a_e + mat[e][c][1] bvec_e
 //   mode 1 (L2P^H):   out[b][c] = sum_e conj(mat[e][c]) a_e
+//   mode 2 (P2M, q = 0, mat = the p columns alone): out[b][c] = sum_e mat[e][c] a_e
 // One 256-thread block per leaf: lane l of slice q handles coefficients
 // l, l + 64, ... over the elements e0 + q, e0 + q + 4, ...; the four slices
 // are added in a fixed order.
@@ -584,6 +585,8 @@ __global__ void __launch_bounds__(256) k_leaf_accumulate(const LeafBatch<R> batc
           load_pair(mat + ((int64_t)e * ncoef + c) * 2, mp, mq);
           cfma(acc, mp, a[e]);
           cfma(acc, mq, bvec[e]);
+        } else if (mode == 2) {
+          cfma(acc, mat[(int64_t)e * ncoef + c], a[e]);
         } else {
           cfmac(acc, mat[(int64_t)e * ncoef + c], a[e]);
         }
@@ -645,11 +648,13 @@ __global__ void __launch_bounds__(256)
     if (c < ncoef) {
       for (int t = sl; t < ne; t += 4) {
         const int64_t e = e0 + t;
-        if (!ADJ) {
+        if (!ADJ && q) {
           cplx<R> mp, mq;
           load_pair(mat + (e * ncoef + c) * 2, mp, mq);
           cfma(acc, mp, sa[t]);
           cfma(acc, mq, sb[t]);
+        } else if (!ADJ) {  // q = 0: mat holds the p columns alone
+          cfma(acc, mat[e * ncoef + c], sa[t]);
         } else {
           cfmac(acc, mat[e * ncoef + c], sa[t]);
         }
@@ -1652,7 +1657,8 @@ static int launch_p2p_jobs(const P2PJobDev<R>* jobs, const int* nleaf, int nj, b
   return 0;
 }
 
-// one leaf-accumulation launch (mode 0 P2M, 1 L2P^H) over up to MAX_JOBS problems
+// one leaf-accumulation launch (mode 0 P2M, 2 P2M with q = 0, 1 L2P^H) over up to
+// MAX_JOBS problems
 template <typename R>
 static int launch_leaf_jobs(const LeafJobDev<R>* jobs, const int* nleaf, int nj, int mode,
                             hipStream_t s, hipEvent_t done = nullptr) {
@@ -1829,7 +1835,8 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   PROF_BEGIN(e0);
   if (fused) {
     launch_done(k_gather_leaf<R, false>, dim3(nleaf), dim3(256), lds_fused, s, nullptr,
-                P.ev_fork2, p, q, P.perm, P.box_start[L], D.ncoef[L], D.p2m, X.ps, X.qs, X.p64s,
+                P.ev_fork2, p, q, P.perm, P.box_start[L], D.ncoef[L], q ? D.p2m : D.p2m_p, X.ps,
+                X.qs, X.p64s,
                 X.q64s, X.M[L], chain_zero_list(P, D, X, false, true));
   } else {
     launch_done(k_gather_in<R>, dim3(nb), dim3(256), 0, s, nullptr,
@@ -1874,8 +1881,9 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   hipStream_t sl = leaf_side ? P.side2 : s;
   if (!fused) {
     PROF_BEGIN(e2);
-    const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], D.p2m, X.ps, X.qs, X.M[L]};
-    if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, 0, s, leaf_side ? P.ev_fork2 : nullptr)))
+    // with q = 0 the q columns meet zeros: the p columns alone are read
+    const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], q ? D.p2m : D.p2m_p, X.ps, X.qs, X.M[L]};
+    if ((r = launch_leaf_jobs<R>(&lj, &nleaf, 1, q ? 0 : 2, s, leaf_side ? P.ev_fork2 : nullptr)))
       return r;
     PROF_END(e2, ST_P2M);
   }

@@ -395,6 +395,14 @@ __global__ void k_conj_transpose(const cplx<R>* __restrict__ in, int n, int rows
   out[g * per + (int64_t)c * rows + r] = mk<R>(v.re, -v.im);
 }
 
+// out[t] = in[2 t] (the p columns of the interleaved P2M matrices)
+template <typename R>
+__global__ void k_p_columns(const cplx<R>* __restrict__ in, int64_t cnt,
+                            cplx<R>* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < cnt) out[t] = in[2 * t];
+}
+
 template <typename R>
 static int make_translations(Problem& P, int ngroups, const std::vector<double>& tvec, int sing,
                              int pin, int pout, const std::vector<double>& rs,
@@ -890,6 +898,10 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
                          dgc, dfinv, Rbuf, tmpb, D.p2m, D.l2p);
       BEM_LAUNCH_CHECK();
     }
+    ARENA_ALLOC(P.arena, D.p2m_p, (int64_t)P.n * Pc);
+    hipLaunchKernelGGL(k_p_columns<R>, dim3(ceil_div((int64_t)P.n * Pc, 256)), dim3(256), 0, s,
+                       D.p2m, (int64_t)P.n * Pc, D.p2m_p);
+    BEM_LAUNCH_CHECK();
     BEM_HIP_TRY(hipStreamSynchronize(s));
   }
   return 0;

@@ -99,6 +99,7 @@ struct PrecisionData {
   std::array<int64_t, MAX_LEVEL + 1> cbuf_off{};  // offset of each level's pairs in cbuf
   int64_t cbuf_count = 0, cbufL_count = 0;        // sizes of the per-pair buffers
   cplx<R>* p2m = nullptr;   // n x ncoef_L x 2 (columns: p, q), sorted order
+  cplx<R>* p2m_p = nullptr; // n x ncoef_L: the p columns alone (products with q = 0)
   cplx<R>* l2p = nullptr;   // n x ncoef_L
   // near-field corrections (accurate - 3-point rule), CSR by target and
   // CSC by source (both sorted order)
