@@ -228,12 +228,13 @@ def run_grad(args):
     print(json.dumps(out), flush=True)
 
 
-# float32 near field (alpha = i/k): per source element (three rule points)
-# the compiled inner loop of k_p2p<float, true> issues 122 vector ALU
-# instructions and 9 transcendentals (sin, cos, rsqrt; quarter rate, 4 issue
-# cycles each); a wave64 instruction occupies a 16-lane SIMD for 4 cycles, so
-# the chip issues 256 CUs x 2.4 GHz wave instructions per second (non-packed).
-P2P_VALU_PER_PAIR = 122
+# float32 near field (alpha = i/k, q = 0 as in the rigid solves timed here):
+# per source element (three rule points) the compiled inner loop of
+# k_p2p<float, true, true> issues 97 vector ALU instructions and 9
+# transcendentals (sin, cos, rsqrt; quarter rate, 4 issue cycles each); a
+# wave64 instruction occupies a 16-lane SIMD for 4 cycles, so the chip issues
+# 256 CUs x 2.4 GHz wave instructions per second (non-packed).
+P2P_VALU_PER_PAIR = 97
 P2P_TRANS_PER_PAIR = 9
 VALU_WAVE_SLOTS = 256 * 2.4e9
 

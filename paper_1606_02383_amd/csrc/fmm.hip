@@ -257,6 +257,7 @@ struct P2PJobDev {
   cplx<R>* ys2;
   R k, alr, ali;
   int all_src;
+  int q_zero;  // forward with q = 0 (rigid): the q terms are left out
   // near-field corrections (accurate minus rule integrals): CSR by target
   // element (forward) or by source element (adjoint)
   const int* nptr;
@@ -272,7 +273,9 @@ struct P2PBatch {
   P2PJobDev<R> job[MAX_JOBS];
 };
 
-template <typename R, bool IMAG>
+// QZ: q = 0 for every job of the launch; the q coefficients, densities and
+// corrections are left out (they would meet zeros)
+template <typename R, bool IMAG, bool QZ>
 __global__ void __launch_bounds__(P2P_THREADS) k_p2p(const P2PBatch<R> batch) {
   __shared__ R s_q[9][P2P_CHUNK];
   __shared__ R s_n[4][P2P_CHUNK];  // normal and plane offset y . n
@@ -350,11 +353,14 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p(const P2PBatch<R> batch) {
         s_n[3][v] = s_q[0][v] * nx + s_q[1][v] * ny + s_q[2][v] * nz;
         // densities times the per-point weight (rule weight x area / (4 pi))
         const R wj = geo[GEO_AREA * n + j] * R(1.0 / 3.0) * R(INV_4PI_D);
-        cplx<R> pv = ps[j], qv = qs[j];
+        const cplx<R> pv = ps[j];
         s_pq[0][v] = wj * pv.re;
         s_pq[1][v] = wj * pv.im;
-        s_pq[2][v] = wj * qv.re;
-        s_pq[3][v] = wj * qv.im;
+        if (!QZ) {
+          const cplx<R> qv = qs[j];
+          s_pq[2][v] = wj * qv.re;
+          s_pq[3][v] = wj * qv.im;
+        }
         s_id[v] = j;
       }
       __syncthreads();
@@ -368,7 +374,7 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p(const P2PBatch<R> batch) {
           bm_elem<R, IMAG>(xx, xy, xz, nxx, nxy, nxz, yq, s_n[0][v], s_n[1][v], s_n[2][v],
                            s_n[3][v], k, k_turns, alr, ali, sp, sq);
           cfma(acc, sp, mk<R>(s_pq[0][v], s_pq[1][v]));
-          cfma(acc, sq, mk<R>(s_pq[2][v], s_pq[3][v]));
+          if (!QZ) cfma(acc, sq, mk<R>(s_pq[2][v], s_pq[3][v]));
         }
       }
     }
@@ -377,7 +383,7 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p(const P2PBatch<R> batch) {
       for (int t = nptr[i] + sl; t < nptr[i + 1]; t += nsl) {
         const int j = J.nidx[t];
         cfma(acc, J.ncp[t], ps[j]);
-        cfma(acc, J.ncq[t], qs[j]);
+        if (!QZ) cfma(acc, J.ncq[t], qs[j]);
       }
     }
     __syncthreads();
@@ -1648,10 +1654,16 @@ static int launch_p2p_jobs(const P2PJobDev<R>* jobs, const int* nleaf, int nj, b
     else
       launch_done(k_p2p_adj<R, false>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
   } else {
-    if (imag)
-      launch_done(k_p2p<R, true>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
+    bool qz = true;
+    for (int q = 0; q < nj; ++q) qz = qz && jobs[q].q_zero;
+    if (imag && qz)
+      launch_done(k_p2p<R, true, true>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
+    else if (imag)
+      launch_done(k_p2p<R, true, false>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
+    else if (qz)
+      launch_done(k_p2p<R, false, true>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
     else
-      launch_done(k_p2p<R, false>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
+      launch_done(k_p2p<R, false, false>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
   }
   BEM_LAUNCH_CHECK();
   return 0;
@@ -1857,7 +1869,8 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
       BEM_HIP_TRY(hipStreamWaitEvent(sn, fork, 0));
     }
     int e1 = prof_begin(P, sn);
-    const P2PJobDev<R> job = p2p_job(P, D, X, false);
+    P2PJobDev<R> job = p2p_job(P, D, X, false);
+    job.q_zero = q ? 0 : 1;
     int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, false, P.alpha.re == 0.0, cap, sn,
                                 P.direct ? nullptr : P.ev_join);
     if (rr) return rr;
