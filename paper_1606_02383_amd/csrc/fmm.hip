@@ -257,7 +257,7 @@ struct P2PJobDev {
   cplx<R>* ys2;
   R k, alr, ali;
   int all_src;
-  int q_zero;  // forward with q = 0 (rigid): the q terms are left out
+  int q_zero;  // q = 0 (forward) or w not wanted (adjoint): the q terms are left out
   // near-field corrections (accurate minus rule integrals): CSR by target
   // element (forward) or by source element (adjoint)
   const int* nptr;
@@ -400,7 +400,9 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p(const P2PBatch<R> batch) {
 
 // Adjoint P2P: one block per leaf of output elements j; iterates over the
 // target elements i of the U list:  u_j += conj(cp_ij) y_i,  w_j += conj(cq_ij) y_i.
-template <typename R, bool IMAG>
+// WZ: w not wanted by any job of the launch (rigid adjoint): the q
+// coefficients and the w sums and corrections are left out
+template <typename R, bool IMAG, bool WZ>
 __global__ void __launch_bounds__(P2P_THREADS) k_p2p_adj(const P2PBatch<R> batch) {
   __shared__ R s_x[6][P2P_CHUNK];
   __shared__ R s_y[2][P2P_CHUNK];
@@ -488,7 +490,7 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p_adj(const P2PBatch<R> batch
                            nyx, nyy, nyz, dj, k, k_turns, alr, ali, sp, sq);
           cplx<R> yv = mk<R>(s_y[0][v], s_y[1][v]);
           cfmac(au, sp, yv);
-          cfmac(aw, sq, yv);
+          if (!WZ) cfmac(aw, sq, yv);
         }
       }
     }
@@ -499,7 +501,7 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p_adj(const P2PBatch<R> batch
       for (int t = nptr[j] + sl; t < nptr[j + 1]; t += nsl) {
         const cplx<R> yv = ysrt[J.nidx[t]];
         cfmac(cu, J.ncp[t], yv);
-        cfmac(cw, J.ncq[t], yv);
+        if (!WZ) cfmac(cw, J.ncq[t], yv);
       }
     }
     __syncthreads();
@@ -519,7 +521,7 @@ __global__ void __launch_bounds__(P2P_THREADS) k_p2p_adj(const P2PBatch<R> batch
       // per-point weight of element j (rule weight x area / (4 pi))
       const R wj = geo[GEO_AREA * n + t0 + tg + tid] * R(1.0 / 3.0) * R(INV_4PI_D);
       us[t0 + tg + tid] = cadd(cscale(su, wj), scu);
-      ws[t0 + tg + tid] = cadd(cscale(sw, wj), scw);
+      if (!WZ) ws[t0 + tg + tid] = cadd(cscale(sw, wj), scw);
     }
   }
   }
@@ -1107,7 +1109,8 @@ __global__ void __launch_bounds__(256)
 // elem_leaf is null), transposed near corrections when tptr is non-null (the
 // products pass null: their P2P kernels apply them), the adjoint P2P sums and
 // the conjugated diagonal.  Every lane of a group calls it.
-template <typename R>
+// WZ: w not wanted; p2m then holds the p columns alone (n x ncoef)
+template <typename R, bool WZ = false>
 __device__ __forceinline__ void finish_adj_elem(
     int64_t j, int l, int64_t n, const int* __restrict__ perm, const int* __restrict__ elem_leaf,
     int ncoef, const cplx<R>* __restrict__ p2m, const cplx<R>* __restrict__ Mc,
@@ -1119,7 +1122,7 @@ __device__ __forceinline__ void finish_adj_elem(
   cplx<R> au = mk<R>(0, 0), aw = mk<R>(0, 0);
   if (j < n) {
     if (ncoef > 0) {
-      const cplx<R>* Aj = p2m + j * ncoef * 2;
+      const cplx<R>* Aj = p2m + j * ncoef * (WZ ? 1 : 2);
       const cplx<R>* Mb = elem_leaf ? Mc + (int64_t)elem_leaf[j] * ncoef : Mc;
       // four coefficients per lane per step, loads issued together
       for (int c0 = l; c0 < ncoef; c0 += 4 * FIN_LANES) {
@@ -1128,7 +1131,10 @@ __device__ __forceinline__ void finish_adj_elem(
         for (int u = 0; u < 4; ++u) {
           const int c = c0 + u * FIN_LANES;
           if (c < ncoef) {
-            load_pair(Aj + 2 * c, ap[u], aq[u]);
+            if (WZ)
+              ap[u] = Aj[c];
+            else
+              load_pair(Aj + 2 * c, ap[u], aq[u]);
             mv[u] = Mb[c];
           } else {
             ap[u] = aq[u] = mv[u] = mk<R>(0, 0);
@@ -1137,7 +1143,7 @@ __device__ __forceinline__ void finish_adj_elem(
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           cfmac(au, ap[u], mv[u]);
-          cfmac(aw, aq[u], mv[u]);
+          if (!WZ) cfmac(aw, aq[u], mv[u]);
         }
       }
     }
@@ -1145,21 +1151,27 @@ __device__ __forceinline__ void finish_adj_elem(
       for (int t = tptr[j] + l; t < tptr[j + 1]; t += FIN_LANES) {
         cplx<R> yv = ysrt[trow[t]];
         cfmac(au, tcp[t], yv);
-        cfmac(aw, tcq[t], yv);
+        if (!WZ) cfmac(aw, tcq[t], yv);
       }
   }
   au.re = group_sum16(au.re);
   au.im = group_sum16(au.im);
-  aw.re = group_sum16(aw.re);
-  aw.im = group_sum16(aw.im);
+  if (!WZ) {
+    aw.re = group_sum16(aw.re);
+    aw.im = group_sum16(aw.im);
+  }
   if (j < n && l == 0) {
-    cplx<R> su = cadd(au, us[j]), sw = cadd(aw, ws[j]);
-    c64 ou = mk((double)su.re, (double)su.im), ow = mk((double)sw.re, (double)sw.im);
+    cplx<R> su = cadd(au, us[j]);
+    c64 ou = mk((double)su.re, (double)su.im);
     cfmac(ou, dp[j], y64[j]);
-    cfmac(ow, dq[j], y64[j]);
     int o = perm[j];
     if (u) u[o] = ou;
-    if (w) w[o] = ow;
+    if (!WZ && w) {
+      cplx<R> sw = cadd(aw, ws[j]);
+      c64 ow = mk((double)sw.re, (double)sw.im);
+      cfmac(ow, dq[j], y64[j]);
+      w[o] = ow;
+    }
   }
 }
 
@@ -1233,8 +1245,8 @@ __global__ void __launch_bounds__(256)
 }
 
 // adjoint: u, w for the elements of leaf b (P2M^H against the leaf's
-// adjoint multipoles)
-template <typename R>
+// adjoint multipoles; WZ: u alone, p2m = the p columns)
+template <typename R, bool WZ>
 __global__ void __launch_bounds__(256)
     k_leaf_finish_adj(const int* __restrict__ bstart, int ncoef, const int* __restrict__ red_ptr,
                       const int* __restrict__ red_pairs, const cplx<R>* __restrict__ cbuf,
@@ -1253,8 +1265,8 @@ __global__ void __launch_bounds__(256)
   const int g = threadIdx.x / FIN_LANES, l = threadIdx.x % FIN_LANES;
   for (int e = 0; e < ne; e += 256 / FIN_LANES) {
     const int64_t j = e + g < ne ? e0 + e + g : n;
-    finish_adj_elem<R>(j, l, n, perm, nullptr, ncoef, p2m, Mf, tptr, trow, tcp, tcq, ysrt, us, ws,
-                       dp, dq, y64, u, w);
+    finish_adj_elem<R, WZ>(j, l, n, perm, nullptr, ncoef, p2m, Mf, tptr, trow, tcp, tcq, ysrt,
+                           us, ws, dp, dq, y64, u, w);
   }
 }
 
@@ -1649,10 +1661,19 @@ static int launch_p2p_jobs(const P2PJobDev<R>* jobs, const int* nleaf, int nj, b
   }
   const int grid = (grid_cap > 0 && grid_cap < tot) ? grid_cap : tot;
   if (adj) {
-    if (imag)
-      launch_done(k_p2p_adj<R, true>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
+    bool wz = true;
+    for (int q = 0; q < nj; ++q) wz = wz && jobs[q].q_zero;
+    if (imag && wz)
+      launch_done(k_p2p_adj<R, true, true>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
+    else if (imag)
+      launch_done(k_p2p_adj<R, true, false>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done,
+                  b);
+    else if (wz)
+      launch_done(k_p2p_adj<R, false, true>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done,
+                  b);
     else
-      launch_done(k_p2p_adj<R, false>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done, b);
+      launch_done(k_p2p_adj<R, false, false>, dim3(grid), dim3(P2P_THREADS), 0, s, nullptr, done,
+                  b);
   } else {
     bool qz = true;
     for (int q = 0; q < nj; ++q) qz = qz && jobs[q].q_zero;
@@ -1986,7 +2007,8 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
       BEM_HIP_TRY(hipStreamWaitEvent(sn, fork, 0));
     }
     int e1 = prof_begin(P, sn);
-    const P2PJobDev<R> job = p2p_job(P, D, X, true);
+    P2PJobDev<R> job = p2p_job(P, D, X, true);
+    job.q_zero = w ? 0 : 1;
     int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, true, P.alpha.re == 0.0, cap, sn,
                                 P.direct ? nullptr : P.ev_join);
     if (rr) return rr;
@@ -2036,10 +2058,19 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   PROF_BEGIN(e6);
   {
     const GroupedOp<R>& op = D.m2l[L];
-    hipLaunchKernelGGL(k_leaf_finish_adj<R>, dim3(nleaf), dim3(256), sizeof(cplx<R>) * D.ncoef[L],
-                       s, P.box_start[L], D.ncoef[L], op.red_ptr_adj, op.red_pairs_adj, X.cbufL,
-                       X.M[L], n, P.perm, D.p2m, nullptr, nullptr, nullptr,
-                       nullptr, X.ps, X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, u, w);
+    // w not wanted (rigid adjoint): the p columns of P2M^H alone
+    if (w)
+      hipLaunchKernelGGL((k_leaf_finish_adj<R, false>), dim3(nleaf), dim3(256),
+                         sizeof(cplx<R>) * D.ncoef[L], s, P.box_start[L], D.ncoef[L],
+                         op.red_ptr_adj, op.red_pairs_adj, X.cbufL, X.M[L], n, P.perm, D.p2m,
+                         nullptr, nullptr, nullptr, nullptr, X.ps, X.ys, X.ys2, P.diag_p,
+                         P.diag_q, X.p64s, u, w);
+    else
+      hipLaunchKernelGGL((k_leaf_finish_adj<R, true>), dim3(nleaf), dim3(256),
+                         sizeof(cplx<R>) * D.ncoef[L], s, P.box_start[L], D.ncoef[L],
+                         op.red_ptr_adj, op.red_pairs_adj, X.cbufL, X.M[L], n, P.perm, D.p2m_p,
+                         nullptr, nullptr, nullptr, nullptr, X.ps, X.ys, X.ys2, P.diag_p,
+                         P.diag_q, X.p64s, u, w);
     BEM_LAUNCH_CHECK();
   }
   PROF_END(e6, ST_FINISH);
