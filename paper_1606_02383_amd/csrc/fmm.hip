@@ -1349,7 +1349,8 @@ struct FinBatch {
   FinJobDev<R> job[MAX_JOBS];
 };
 
-template <typename R, bool ADJ>
+// WZ (adjoint): no job wants w; ex holds the p columns of P2M alone
+template <typename R, bool ADJ, bool WZ = false>
 __global__ void __launch_bounds__(256) k_finish_batch(const FinBatch<R> batch) {
   const int qj = job_of(batch.blk0, batch.n, (int)blockIdx.x);
   const FinJobDev<R> J = select_job(batch.job, qj);
@@ -1357,8 +1358,9 @@ __global__ void __launch_bounds__(256) k_finish_batch(const FinBatch<R> batch) {
                     threadIdx.x;
   const int l = threadIdx.x % FIN_LANES;
   if (ADJ)
-    finish_adj_elem<R>(t / FIN_LANES, l, J.n, J.perm, J.elem_leaf, J.ncoef, J.ex, J.Mx, J.nptr,
-                       J.nidx, J.ncp, J.ncq, J.a, J.b, J.c, J.dp, J.dq, J.p64, J.out, J.out2);
+    finish_adj_elem<R, WZ>(t / FIN_LANES, l, J.n, J.perm, J.elem_leaf, J.ncoef, J.ex, J.Mx,
+                           J.nptr, J.nidx, J.ncp, J.ncq, J.a, J.b, J.c, J.dp, J.dq, J.p64, J.out,
+                           J.out2);
   else
     finish_elem<R>(t / FIN_LANES, l, J.n, J.perm, J.elem_leaf, J.ncoef, J.ex, J.Mx, J.nptr,
                    J.nidx, J.ncp, J.ncq, J.a, J.b, J.c, J.dp, J.dq, J.p64, J.q64, J.out);
@@ -2159,7 +2161,9 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
     std::vector<int> nl;
     for (const BatchItem<R>& it : items)
       if ((it.P->alpha.re == 0.0) == (imag == 1)) {
-        jobs.push_back(p2p_job(*it.P, *it.D, *it.X, adj));
+        P2PJobDev<R> job = p2p_job(*it.P, *it.D, *it.X, adj);
+        job.q_zero = adj ? (it.out2 ? 0 : 1) : (it.q ? 0 : 1);
+        jobs.push_back(job);
         nl.push_back(it.P->nbox[it.P->L]);
       }
     for (size_t a = 0; a < jobs.size(); a += MAX_JOBS) {
@@ -2172,7 +2176,9 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
   std::vector<const BatchItem<R>*> far;
   for (const BatchItem<R>& it : items)
     if (!it.P->direct) far.push_back(&it);
-  {
+  // (forward items with q = 0 read the p columns alone: mode 2, launched
+  // apart from those with q)
+  for (int pass = 0; pass < (adj ? 1 : 2); ++pass) {
     std::vector<LeafJobDev<R>> jobs;
     std::vector<int> nl;
     for (const BatchItem<R>* it : far) {
@@ -2182,13 +2188,18 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
       const int L = P.L;
       if (adj)
         jobs.push_back(LeafJobDev<R>{P.box_start[L], D.ncoef[L], D.l2p, X.ps, nullptr, X.Lc[L]});
-      else
+      else if (pass == 0 && it->q)
         jobs.push_back(LeafJobDev<R>{P.box_start[L], D.ncoef[L], D.p2m, X.ps, X.qs, X.M[L]});
+      else if (pass == 1 && !it->q)
+        jobs.push_back(LeafJobDev<R>{P.box_start[L], D.ncoef[L], D.p2m_p, X.ps, nullptr, X.M[L]});
+      else
+        continue;
       nl.push_back(P.nbox[L]);
     }
+    const int mode = adj ? 1 : (pass == 0 ? 0 : 2);
     for (size_t a = 0; a < jobs.size(); a += MAX_JOBS) {
       const int nj = (int)std::min<size_t>(MAX_JOBS, jobs.size() - a);
-      if ((r = launch_leaf_jobs<R>(&jobs[a], &nl[a], nj, adj ? 1 : 0, s))) return r;
+      if ((r = launch_leaf_jobs<R>(&jobs[a], &nl[a], nj, mode, s))) return r;
     }
   }
   // level chains only: merged across problems step by step they need few
@@ -2295,9 +2306,13 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
   if (sides) BEM_HIP_TRY(hipStreamWaitEvent(s, bs.ev[1], 0));
   {
     FinBatch<R> fb{};
+    bool fb_wz = false;  // the adjoint jobs of fb want no w (P2M^H p columns alone)
     auto flush = [&]() -> int {
       if (fb.n == 0) return 0;
-      if (adj)
+      if (adj && fb_wz)
+        hipLaunchKernelGGL((k_finish_batch<R, true, true>), dim3(fb.blk0[fb.n]), dim3(256), 0, s,
+                           fb);
+      else if (adj)
         hipLaunchKernelGGL((k_finish_batch<R, true>), dim3(fb.blk0[fb.n]), dim3(256), 0, s, fb);
       else
         hipLaunchKernelGGL((k_finish_batch<R, false>), dim3(fb.blk0[fb.n]), dim3(256), 0, s, fb);
@@ -2311,8 +2326,11 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
       ExecBuf<R>& X = *it.X;
       const int L = P.L;
       const int ncoef = P.direct ? 0 : D.ncoef[L];
+      const bool wz = adj && !it.out2 && !P.direct;
+      if (fb.n > 0 && wz != fb_wz && (r = flush())) return r;
+      fb_wz = wz;
       if (adj)
-        fb.job[fb.n] = FinJobDev<R>{P.n, P.perm, P.elem_leaf, ncoef, D.p2m, X.M[L],
+        fb.job[fb.n] = FinJobDev<R>{P.n, P.perm, P.elem_leaf, ncoef, wz ? D.p2m_p : D.p2m, X.M[L],
                                     nullptr, nullptr, nullptr, nullptr, X.ps,
                                     X.ys, X.ys2, P.diag_p, P.diag_q, X.p64s, nullptr, it.out,
                                     it.out2};
