@@ -54,6 +54,9 @@ def cpu_baseline(V, T, k, seed, target_s=15.0):
     import multiprocessing as mp
 
     from oracle import bem as obem
+    # every core this process may run on, up to 16 (the host-CPU share of one
+    # GPU on the benchmark machines: more worker processes there would only
+    # queue behind each other)
     cores = min(len(os.sched_getaffinity(0)), 16)
     geom = obem.Geometry(V, T)
     n = geom.n_elem
@@ -75,6 +78,16 @@ def cpu_baseline(V, T, k, seed, target_s=15.0):
         pool.map(_cpu_rows, chunks)
     dt = time.perf_counter() - t0
     return nrows / (n * dt), cores, nrows, dt
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 _G = None
@@ -228,29 +241,42 @@ def run_grad(args):
     print(json.dumps(out), flush=True)
 
 
-# float32 near field (alpha = i/k, q = 0 as in the rigid solves timed here):
-# per source element (three rule points) the compiled inner loop of
-# k_p2p<float, true, true> issues 97 vector ALU instructions and 9
-# transcendentals (sin, cos, rsqrt; quarter rate, 4 issue cycles each); a
-# wave64 instruction occupies a 16-lane SIMD for 4 cycles, so the chip issues
-# 256 CUs x 2.4 GHz wave instructions per second (non-packed).
-P2P_VALU_PER_PAIR = 97
+# Algorithmic work of the float32 near field per (target, source element)
+# pair for the rigid products timed here (alpha = i/k, q = 0), counted on the
+# pair kernel's expression (add, subtract, multiply = 1 FLOP, fused
+# multiply-add = 2; 1/sqrt, sin and cos counted apart): per rule point
+# r = x - y (3), |r|^2 (5), |r| (1), k|r| (1), G = e^{ik|r|}/|r| (2), 1/|r|^2
+# (1), r.n_x (5), k/|r| and alpha k/|r| (2), the two products of the
+# double-normal term (2), the p coefficient's real (4) and imaginary (7)
+# parts and its complex multiply-add into the element sum (8): 41; per
+# element n_x.n_y (5), r.n_y (6), alpha n_x.n_y (1) and the density's complex
+# multiply-add (8) less the first point's start of the sum (2): 18.
+# Element pair: 3 x 41 + 18 = 141 FLOPs and 9 transcendentals.  Each near
+# correction adds one complex multiply-add (8).
+P2P_FLOPS_PER_PAIR = 141
 P2P_TRANS_PER_PAIR = 9
-VALU_WAVE_SLOTS = 256 * 2.4e9
+P2P_FLOPS_PER_CORRECTION = 8
+PEAK_VEC_NONPACKED = 78.6e12   # float32 vector FMA rate without packed instructions
 
 
-def p2p_valu(st, prof):
-    """Issue-slot rate of the float32 near field (stage time from the stage
-    profile; the kernel shares the GPU with the far field there)."""
-    ms, calls = prof.get(("p2p", "f32", "fwd"), (0.0, 0))
-    if not calls:
-        return None
-    t = ms / calls / 1e3
-    slots = st["n_p2p_pairs"] / 64.0 * (P2P_VALU_PER_PAIR + 4 * P2P_TRANS_PER_PAIR)
-    return {"bound": "alu", "element_pairs": st["n_p2p_pairs"],
-            "vector_instr_per_pair": P2P_VALU_PER_PAIR + P2P_TRANS_PER_PAIR,
-            "avg_ms": round(t * 1e3, 5), "achieved_wave_slots_per_s": slots / t,
-            "peak_wave_slots_per_s": VALU_WAVE_SLOTS, "frac": round(slots / t / VALU_WAVE_SLOTS, 4)}
+def p2p_roofline(st, prof, alone):
+    """Algorithmic FLOP/s of the float32 near field, in the product (stage
+    profile, sharing the GPU with the far field) and alone (serial profile)."""
+    flops = (st["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR
+             + st["n_near"] * P2P_FLOPS_PER_CORRECTION)
+    out = {"kernel": "k_p2p<float,true,true> (near field, float32, q = 0)", "bound": "alu",
+           "flops_per_element_pair": P2P_FLOPS_PER_PAIR,
+           "transcendentals_per_element_pair": P2P_TRANS_PER_PAIR,
+           "element_pairs": st["n_p2p_pairs"], "near_corrections": st["n_near"],
+           "flops_per_launch": flops, "peak": PEAK_VEC_NONPACKED / 1e12, "unit": "TFLOP/s"}
+    for name, pr in (("in_product", prof), ("alone", alone)):
+        ms, calls = pr.get(("p2p", "f32", "fwd"), (0.0, 0))
+        if calls:
+            t = ms / calls / 1e3
+            out[f"{name}_ms"] = round(t * 1e3, 5)
+            out[f"achieved_{name}"] = round(flops / t / 1e12, 3)
+            out[f"frac_{name}"] = round(flops / t / PEAK_VEC_NONPACKED, 4)
+    return out
 
 
 def main():
@@ -369,6 +395,14 @@ def main():
     plan.solve(b, opts=optsir)
     prof = plan.profile_stop()
     stages = {f"{k[0]}_{k[1]}_{k[2]}": round(v[0] / v[1], 4) for k, v in prof.items()}
+    # every stage alone on the GPU: products with q = 0 (as in the rigid
+    # solves) on one stream, one stage after another
+    plan.profile_start(serial=True)
+    for prec in (1, 0):
+        for _ in range(3):
+            plan.matvec(p, prec=prec)
+    alone = plan.profile_stop()
+    stages_alone = {f"{k[0]}_{k[1]}_{k[2]}": round(v[0] / v[1], 4) for k, v in alone.items()}
     # dominant kernel: the leaf-level float32 M2L GEMM (one launch per
     # product); algorithmic flops per launch = 8 (p_L + 1)^4 per M2L pair
     L = st["leaf_level"]
@@ -390,7 +424,10 @@ def main():
                                       "avg_launch_ms": round(coarse_launch_ms, 5),
                                       "tflops": round(flops_coarse / max(coarse_launch_ms, 1e-9)
                                                       / 1e9, 3)},
-                "p2p_valu": p2p_valu(st, prof)}
+                "alone_ms": round(alone.get(("m2l_leaf", "f32", "fwd"), (0.0, 1))[0]
+                                  / max(1, alone.get(("m2l_leaf", "f32", "fwd"), (0.0, 1))[1]),
+                                  5),
+                "p2p": p2p_roofline(st, prof, alone)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -398,7 +435,9 @@ def main():
         v, cores, nrows, cdt = cpu_baseline(V, T, wl.k, wl.seed)
         cpu = {"value": v, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
                "sample": f"{nrows} of {len(T)} rows of one float64 dense matrix-free matvec "
-                         f"(numpy, {cores} processes, {cdt:.1f} s), scaled to whole matvecs"}
+                         f"(numpy, {cores} processes, {cdt:.1f} s), scaled to whole matvecs",
+               "affinity_cores": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count(),
+               "cpu_model": cpu_model()}
         log(f"[bench] CPU oracle: {v:.3e} matvecs/s on {cores} cores")
 
     out = {
@@ -419,6 +458,7 @@ def main():
         "matvec_per_s": {"f64": rates["f64"], "f32": rates["f32"]},
         "plan_build_s": t_plan,
         "stage_ms_per_call": stages,
+        "stage_ms_alone": stages_alone,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -86,9 +86,25 @@ typedef struct {
                           are built and timed on a float32 product at plan
                           creation, and the fastest is kept              */
   int32_t order64;     /* expansion order of the float64 far field: > 0
-                          fixed; 0: per level ceil(k sqrt(3) h) + 8, at
-                          least 12; < 0: the same with minimum -order64    */
+                          fixed; 0: per level ceil(k sqrt(3) h) + 8 + s, at
+                          least 12 + s (s: calibration shift, see
+                          fmm_tol); < 0: the same with minimum -order64    */
   int32_t order32;     /* same for the float32 far field (+3, at least 7)  */
+  double fmm_tol;      /* target relative L2 error of the float64 product
+                          against the exact discrete operator (the paper
+                          fixes its truncation numerically to an error
+                          target, Sec. 3).  > 0: at plan creation the
+                          product is applied to seeded random densities and
+                          compared on 128 sampled rows with those rows
+                          summed directly in float64, and likewise on a
+                          plane-wave density (smooth: its far field adds up
+                          coherently and errs more); the level rule is
+                          shifted, up or down, until the larger of the two
+                          sampled errors is below 0.7 fmm_tol.  <= 0: the
+                          rule unshifted.  Ignored when order64 > 0.      */
+  double fmm_tol32;    /* same for the float32 product, whose orders are
+                          only raised above the rule (<= 0: the rule)     */
+  int32_t p_max;       /* largest expansion order (<= 0 -> 40, > 40 invalid) */
 } bem_problem;
 
 typedef struct {
@@ -145,10 +161,20 @@ typedef struct {
   int32_t direct_depth[2]; /* levels above the leaves reached by direct
                               leaf <-> ancestor translations in one launch
                               (0: level-by-level chains); chosen by timing  */
+  double fmm_err64;        /* sampled relative error of the float64 / float32 */
+  double fmm_err32;        /* product on white-noise densities, measured at
+                              plan creation (see fmm_tol; 0: direct sum)    */
+  double fmm_err64_smooth; /* the same on a plane-wave density             */
+  double fmm_err32_smooth;
 } bem_plan_stats;
 
-/* Build a plan for n_probs problems.  Uploads the meshes and runs, on the
- * device: element geometry and quadrature points, Morton keys and a stable
+/* Build a plan for n_probs problems: everything the products of Sec. 2.3
+ * (the FMM of solver step 2(c)) need that does not depend on the densities,
+ * built once and reused by every forward and adjoint product and solve (the
+ * paper reuses its tree, near-field integrals and translation operators
+ * between the state and adjoint solves, Sec. 2.5 steps 6-7).  Uploads the
+ * meshes and runs, on the device: element geometry and quadrature points
+ * (constant elements with collocation, Sec. 2.3), Morton keys and a stable
  * radix sort, the uniform-depth octree and its U/V lists, the near-pair
  * list with accurate near-singular integrals and self terms, and the
  * translation, multipole and local operators in float64 and float32.
@@ -164,9 +190,15 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* stats);
 int bem_fmm_matvec(bem_plan* plan, int prob, int prec, const void* p, const void* q,
                    void* y, int nrhs, void* stream);
 
-/* Exact algebraic adjoint of bem_fmm_matvec (same tree, near field and
- * operators, conjugate-transposed):  u = (I/2 - K - alpha H)^H y,
- * w = (S + alpha K' + (alpha/2) I)^H y.  u or w may be NULL. */
+/* Exact algebraic adjoint of bem_fmm_matvec: the operator of the adjoint
+ * problem (Sec. 2.2, Eq. danseiajohel, which the paper solves with the same
+ * boundary operator as the state problem), conjugate-transposed in its
+ * discrete form, with the same tree, near field and operators as the
+ * forward product (reused, Sec. 2.5 steps 6-7):
+ *     u = (I/2 - K - alpha H)^H y,   w = (S + alpha K' + (alpha/2) I)^H y.
+ * Device complex128 vectors, nrhs columns of stride n_tri; u or w may be
+ * NULL (not both; w = NULL leaves out the w terms); outputs must not alias
+ * y.  BEM_E_INVALID for bad arguments. */
 int bem_fmm_matvec_adjoint(bem_plan* plan, int prob, int prec, const void* y, void* u,
                            void* w, int nrhs, void* stream);
 
@@ -227,6 +259,33 @@ int bem_objective_grad(bem_plan* plan, int prob, const void* beta, const double*
                        void* grad, void* p_out, bem_gmres_info* info_fwd,
                        bem_gmres_info* info_adj, void* stream);
 
+/* The two halves of bem_objective_grad, for callers that need J without its
+ * gradient (line searches) or that take the gradient later (reverse-mode
+ * differentiation: the adjoint solve is the backward pass).
+ *
+ * Forward half, the state problem (Sec. 2.3, Eq. danseibie2 with the
+ * admittance boundary q = sigma p): one solve of A(sigma) p = b for the
+ * plane wave, the field p_obs at the points (solver step 5) and
+ * J = sum |p_obs|^2 (Eq. obj with f = |p|^2).  p_out (device complex128,
+ * n_tri) and pobs_out (device complex128, n_pts) receive p and p_obs; either
+ * may be NULL.  Synchronises. */
+int bem_objective_forward(bem_plan* plan, int prob, const void* beta, const double* dir3,
+                          const double* pts, int n_pts, const bem_gmres_opts* opts, double* J,
+                          void* p_out, void* pobs_out, bem_gmres_info* info, void* stream);
+
+/* Backward half, the adjoint problem (Sec. 2.2, Eq. danseiajohel, here the
+ * discrete adjoint of the collocation system): from the forward half's p and
+ * p_obs (device complex128), one solve with the conjugate-transposed operator
+ * A(sigma)^H, one adjoint product, and grad_e = dJ/dRe(beta_e) +
+ * i dJ/dIm(beta_e) (pairing of Eq. danseideltaJ) into grad (device
+ * complex128, n_tri, must not alias an input).  The tree, near field and
+ * operators are those of the forward solve (reused, Sec. 2.5 steps 6-7).
+ * Synchronises. */
+int bem_objective_backward(bem_plan* plan, int prob, const void* beta, const void* p,
+                           const void* pobs, const double* pts, int n_pts,
+                           const bem_gmres_opts* opts, void* grad, bem_gmres_info* info,
+                           void* stream);
+
 /* Morton keys (uint64, caller order) and the sorted permutation (int32:
  * sorted position -> caller index) of a problem, copied to device buffers
  * the caller owns (n_tri entries each; either may be NULL). */
@@ -286,6 +345,10 @@ int bem_plan_set_tuning(bem_plan* plan, int prob, int prec, int schedule, int p2
  * BEM_E_INVALID for a bad plan, problem or output pointer. */
 #define BEM_PROFILE_SLOTS 64
 int bem_profile_start(bem_plan* plan, int prob);
+/* As bem_profile_start, but the products then run every stage on the
+ * call's stream one after another (no side streams), so each stage is timed
+ * alone on the GPU; products keep their values.  Ended by bem_profile_stop. */
+int bem_profile_serial_start(bem_plan* plan, int prob);
 int bem_profile_leaf_m2l_start(bem_plan* plan, int prob);
 int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls);
 

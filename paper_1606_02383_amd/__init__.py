@@ -31,9 +31,10 @@ STATUS = {0: "BEM_OK", -1: "BEM_E_INVALID", -2: "BEM_E_OOM", -3: "BEM_E_HIP",
 EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm_matvec",
            "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
            "bem_plane_wave_rhs", "bem_eval_field",
-           "bem_eval_field_adjoint", "bem_objective_grad", "bem_tree_export",
+           "bem_eval_field_adjoint", "bem_objective_grad", "bem_objective_forward",
+           "bem_objective_backward", "bem_tree_export",
            "bem_leaves_export", "bem_lists_export", "bem_near_export", "bem_plan_set_tuning",
-           "bem_profile_start",
+           "bem_profile_start", "bem_profile_serial_start",
            "bem_profile_leaf_m2l_start", "bem_profile_stop", "bem_last_error"]
 
 STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
@@ -47,7 +48,9 @@ class _Problem(ctypes.Structure):
                 ("k", ctypes.c_double), ("alpha_re", ctypes.c_double),
                 ("alpha_im", ctypes.c_double), ("near_eta", ctypes.c_double),
                 ("leaf_cap", ctypes.c_int32), ("leaf_level", ctypes.c_int32),
-                ("order64", ctypes.c_int32), ("order32", ctypes.c_int32)]
+                ("order64", ctypes.c_int32), ("order32", ctypes.c_int32),
+                ("fmm_tol", ctypes.c_double), ("fmm_tol32", ctypes.c_double),
+                ("p_max", ctypes.c_int32)]
 
 
 class _Opts(ctypes.Structure):
@@ -76,7 +79,9 @@ class _Stats(ctypes.Structure):
                 ("box_size", ctypes.c_double * 22), ("device_bytes", ctypes.c_int64),
                 ("tuned_ms", ctypes.c_double), ("m2l_tile32", ctypes.c_int32 * 22),
                 ("schedule", ctypes.c_int32 * 2), ("p2p_grid", ctypes.c_int32 * 2),
-                ("m2l_grid", ctypes.c_int32 * 2), ("direct_depth", ctypes.c_int32 * 2)]
+                ("m2l_grid", ctypes.c_int32 * 2), ("direct_depth", ctypes.c_int32 * 2),
+                ("fmm_err64", ctypes.c_double), ("fmm_err32", ctypes.c_double),
+                ("fmm_err64_smooth", ctypes.c_double), ("fmm_err32_smooth", ctypes.c_double)]
 
 
 _LIB = None
@@ -108,6 +113,10 @@ def load_library(path: str = LIB_PATH):
     lib.bem_eval_field_adjoint.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
     lib.bem_objective_grad.argtypes = [vp, i32, vp, dp, dp, i32, ctypes.POINTER(_Opts), dp, vp,
                                        vp, ctypes.POINTER(_Info), ctypes.POINTER(_Info), vp]
+    lib.bem_objective_forward.argtypes = [vp, i32, vp, dp, dp, i32, ctypes.POINTER(_Opts), dp,
+                                          vp, vp, ctypes.POINTER(_Info), vp]
+    lib.bem_objective_backward.argtypes = [vp, i32, vp, vp, vp, dp, i32, ctypes.POINTER(_Opts),
+                                           vp, ctypes.POINTER(_Info), vp]
     lib.bem_tree_export.argtypes = [vp, i32, vp, vp, vp]
     lib.bem_leaves_export.argtypes = [vp, i32, vp, vp, vp, vp]
     i64p = ctypes.POINTER(ctypes.c_int64)
@@ -115,6 +124,7 @@ def load_library(path: str = LIB_PATH):
     lib.bem_near_export.argtypes = [vp, i32, vp, vp, i64p, vp]
     lib.bem_plan_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32, i32]
     lib.bem_profile_start.argtypes = [vp, i32]
+    lib.bem_profile_serial_start.argtypes = [vp, i32]
     lib.bem_profile_leaf_m2l_start.argtypes = [vp, i32]
     lib.bem_profile_stop.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int32)]
     lib.bem_last_error.restype = ctypes.c_char_p
@@ -158,6 +168,9 @@ class Problem:
     leaf_level: int = 0              # > 0 forced, < 0 tuned at plan creation
     order64: int = 0
     order32: int = 0
+    fmm_tol: float = 1e-6            # float64 product error target (<= 0: level rule)
+    fmm_tol32: float = 0.0           # float32: orders raised to meet it (<= 0: rule)
+    p_max: int = 40
 
 
 @dataclass
@@ -192,7 +205,8 @@ class Plan:
             arr[i] = _Problem(V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), V.shape[0],
                               T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), T.shape[0],
                               float(p.k), a.real, a.imag, float(p.near_eta), int(p.leaf_cap),
-                              int(p.leaf_level), int(p.order64), int(p.order32))
+                              int(p.leaf_level), int(p.order64), int(p.order32),
+                              float(p.fmm_tol), float(p.fmm_tol32), int(p.p_max))
         self.problems = list(problems)
         self.n = [int(np.asarray(p.T).shape[0]) for p in problems]
         h = ctypes.c_void_p()
@@ -236,7 +250,9 @@ class Plan:
                     box_size=list(st.box_size[:L + 1]), device_bytes=st.device_bytes,
                     tuned_ms=st.tuned_ms, m2l_tile32=list(st.m2l_tile32[:L + 1]),
                     schedule=list(st.schedule), p2p_grid=list(st.p2p_grid),
-                    m2l_grid=list(st.m2l_grid), direct_depth=list(st.direct_depth))
+                    m2l_grid=list(st.m2l_grid), direct_depth=list(st.direct_depth),
+                    fmm_err64=st.fmm_err64, fmm_err32=st.fmm_err32,
+                    fmm_err64_smooth=st.fmm_err64_smooth, fmm_err32_smooth=st.fmm_err32_smooth)
 
     # ---- products
     def matvec(self, p, q=None, prec=BEM_C128, prob=0, out=None):
@@ -247,11 +263,13 @@ class Plan:
         _check(_LIB.bem_fmm_matvec(self._h, prob, prec, _ptr(p), _ptr(q), _ptr(y), nrhs, _stream()))
         return y
 
-    def matvec_adjoint(self, y, prec=BEM_C128, prob=0):
-        """(u, w) = ((I/2 - K - alpha H)^H y, (S + alpha K' + alpha/2 I)^H y)."""
+    def matvec_adjoint(self, y, prec=BEM_C128, prob=0, want_w=True):
+        """(u, w) = ((I/2 - K - alpha H)^H y, (S + alpha K' + alpha/2 I)^H y);
+        want_w=False asks for u alone (w is returned as None)."""
         y = self._in(y, prob)
         nrhs = 1 if y.dim() == 1 else y.shape[0]
-        u, w = self._vec(prob, nrhs), self._vec(prob, nrhs)
+        u = self._vec(prob, nrhs)
+        w = self._vec(prob, nrhs) if want_w else None
         _check(_LIB.bem_fmm_matvec_adjoint(self._h, prob, prec, _ptr(y), _ptr(u), _ptr(w), nrhs,
                                            _stream()))
         return u, w
@@ -355,18 +373,60 @@ class Plan:
                                        ctypes.byref(fi), ctypes.byref(ai), _stream()))
         return J.value, grad, pout, fi.as_dict(), ai.as_dict()
 
+    def objective_forward(self, beta, direction, pts, opts: GmresOptions | None = None, prob=0):
+        """State solve and J = sum |p(x_m)|^2: returns (J, p, p_obs, info)."""
+        import torch
+        opts = opts or GmresOptions(tol=1e-10)
+        beta = self._in(beta, prob)
+        d = np.ascontiguousarray(direction, dtype=np.float64)
+        P = np.ascontiguousarray(pts, dtype=np.float64)
+        J = ctypes.c_double()
+        p = self._vec(prob)
+        pobs = torch.empty(P.shape[0], dtype=torch.complex128, device=self.device)
+        fi = _Info()
+        o = opts.c()
+        _check(_LIB.bem_objective_forward(self._h, prob, _ptr(beta),
+                                          d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          P.shape[0], ctypes.byref(o), ctypes.byref(J), _ptr(p),
+                                          _ptr(pobs), ctypes.byref(fi), _stream()))
+        return J.value, p, pobs, fi.as_dict()
+
+    def objective_backward(self, beta, p, pobs, pts, opts: GmresOptions | None = None, prob=0):
+        """Adjoint solve and dJ/dRe(beta) + i dJ/dIm(beta) from the forward
+        half's p and p_obs: returns (grad, info)."""
+        opts = opts or GmresOptions(tol=1e-10)
+        beta, p = self._in(beta, prob), self._in(p, prob)
+        import torch
+        pobs = torch.as_tensor(pobs).to(device=self.device, dtype=torch.complex128).contiguous()
+        P = np.ascontiguousarray(pts, dtype=np.float64)
+        if pobs.shape[0] != P.shape[0]:
+            raise ValueError("p_obs and pts differ in length")
+        grad = self._vec(prob)
+        ai = _Info()
+        o = opts.c()
+        _check(_LIB.bem_objective_backward(self._h, prob, _ptr(beta), _ptr(p), _ptr(pobs),
+                                           P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           P.shape[0], ctypes.byref(o), _ptr(grad),
+                                           ctypes.byref(ai), _stream()))
+        return grad, ai.as_dict()
+
     def set_tuning(self, prec=BEM_C128, prob=0, schedule=-1, p2p_grid=-1, m2l_grid=-1,
                    direct_depth=-1):
         """Override the choices timed at plan creation (negative: keep)."""
         _check(_LIB.bem_plan_set_tuning(self._h, prob, prec, int(schedule), int(p2p_grid),
                                         int(m2l_grid), int(direct_depth)))
 
-    def profile_start(self, prob=0, leaf_m2l_only=False):
+    def profile_start(self, prob=0, leaf_m2l_only=False, serial=False):
         """Stage timing until profile_stop: every stage (event pairs on the
         streams), or only the leaf-level M2L with events attached to its
-        launches (leaf_m2l_only; leaves the schedule of a timed region as is)."""
+        launches (leaf_m2l_only; leaves the schedule of a timed region as is),
+        or every stage alone on the GPU (serial: one stream, one stage after
+        another)."""
         if leaf_m2l_only:
             _check(_LIB.bem_profile_leaf_m2l_start(self._h, prob))
+        elif serial:
+            _check(_LIB.bem_profile_serial_start(self._h, prob))
         else:
             _check(_LIB.bem_profile_start(self._h, prob))
 
@@ -440,13 +500,17 @@ def _objective_function():
 
         @staticmethod
         def forward(ctx, beta, plan, direction, pts, opts=None, prob=0):
-            J, grad, _, _, _ = plan.objective_grad(beta.detach(), direction, pts, opts, prob)
-            ctx.save_for_backward(grad)
+            # the state solve only; the adjoint solve runs in backward
+            b = beta.detach()
+            J, p, pobs, _ = plan.objective_forward(b, direction, pts, opts, prob)
+            ctx.save_for_backward(b, p, pobs)
+            ctx.plan, ctx.pts, ctx.opts, ctx.prob = plan, pts, opts, prob
             return torch.tensor(J, dtype=torch.float64, device=beta.device)
 
         @staticmethod
         def backward(ctx, gout):
-            (grad,) = ctx.saved_tensors
+            b, p, pobs = ctx.saved_tensors
+            grad, _ = ctx.plan.objective_backward(b, p, pobs, ctx.pts, ctx.opts, ctx.prob)
             return gout * grad, None, None, None, None, None
 
     return ObjectiveJ

@@ -1,5 +1,6 @@
 // C ABI: argument checks, plan lifecycle and dispatch.  Every numerical step
 // runs in the device kernels of the other translation units.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -15,6 +16,12 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 int objective_grad(Problem& P, const c64* beta, const double* dir, const double* pts_host,
                    int n_pts, const bem_gmres_opts* opts, double* J, c64* grad, c64* p_out,
                    bem_gmres_info* info_f, bem_gmres_info* info_a, hipStream_t s);
+int objective_forward(Problem& P, const c64* beta, const double* dir, const double* pts_host,
+                      int n_pts, const bem_gmres_opts* opts, double* J, c64* p_out,
+                      c64* pobs_out, bem_gmres_info* info_f, hipStream_t s);
+int objective_backward(Problem& P, const c64* beta, const c64* p, const c64* pobs,
+                       const double* pts_host, int n_pts, const bem_gmres_opts* opts, c64* grad,
+                       bem_gmres_info* info_a, hipStream_t s);
 int gmres_solve_batch(std::vector<Problem*>& probs, const std::vector<int>& adjoint,
                       const std::vector<const c64*>& sigma, const std::vector<const c64*>& b,
                       const std::vector<c64*>& x, double tol, int m, int max_iter, int mode,
@@ -31,6 +38,8 @@ static void destroy_problem(Problem* P) {
   if (P->ev_fork2) (void)hipEventDestroy(P->ev_fork2);
   if (P->ev_join2) (void)hipEventDestroy(P->ev_join2);
   if (P->own_streams && P->side2) (void)hipStreamDestroy(P->side2);
+  P->f64.ops.release();
+  P->f32.ops.release();
   P->arena.release();
   delete P;
 }
@@ -176,6 +185,80 @@ static int tune_schedule(Problem& P, hipStream_t s) {
   return 0;
 }
 
+namespace bemfmm {
+
+// Order calibration of one precision.  The level rule's orders are shifted
+// (every level by the same amount) until the sampled relative error of the
+// product, the larger of its white-noise and plane-wave errors, is below
+// 0.7 of the tolerance (the factor covers the spread of the sampled
+// estimate).  The float64 orders may also move below the rule; the
+// float32 ones are only raised (the mixed-precision refinement's step count
+// rests on the rule's float32 accuracy).  Error per order step: ~x1.9 on the
+// workloads measured; a step up is estimated with that rate and, when it
+// spans several orders, one order less is tried; a step down is estimated
+// with 2.2 and checked.
+template <typename R>
+static int calibrate_one(Problem& P, PrecisionData<R>& D, double tol, bool may_lower,
+                         hipStream_t s) {
+  double e = 0;
+  int r = measure_error<R>(P, D, s, &e);
+  if (r) return r;
+  const int req = sizeof(R) == 8 ? P.order64_req : P.order32_req;
+  if (!(tol > 0) || req > 0) return 0;
+  const double target = 0.7 * tol;
+  auto top = [&]() {
+    int pm = 0;
+    for (int l = 2; l <= P.L; ++l) pm = std::max(pm, D.order[l]);
+    return pm;
+  };
+  int shift = D.shift;
+  if (e > target) {
+    double prev = e;
+    int last_step = 0;
+    while (e > target && top() < std::min(P.p_max, 40)) {
+      const int step = std::max(1, (int)std::ceil(std::log(e / target) / std::log(1.9)));
+      shift += step;
+      last_step = step;
+      if ((r = rebuild_precision<R>(P, D, shift, s))) return r;
+      if ((r = measure_error<R>(P, D, s, &e))) return r;
+      if (e > 0.8 * prev && e > target) break;  // rounding floor: higher orders do not help
+      prev = e;
+    }
+    // a step of more than one order may have overshot: one order less?
+    if (e <= target && last_step > 1) {
+      double e1 = 0;
+      if ((r = rebuild_precision<R>(P, D, shift - 1, s))) return r;
+      if ((r = measure_error<R>(P, D, s, &e1))) return r;
+      if (e1 > target) {
+        if ((r = rebuild_precision<R>(P, D, shift, s))) return r;
+        if ((r = measure_error<R>(P, D, s, &e))) return r;
+      }
+    }
+    return 0;
+  }
+  if (!may_lower || e <= 0) return 0;
+  const int down = (int)std::floor(std::log(target / e) / std::log(2.2));
+  if (down < 1) return 0;
+  const int shift0 = shift;
+  for (int t = down; t >= 1; --t) {
+    if ((r = rebuild_precision<R>(P, D, shift0 - t, s))) return r;
+    if ((r = measure_error<R>(P, D, s, &e))) return r;
+    if (e <= target) return 0;
+  }
+  // none of the lower orders met the target: back to where it did
+  if ((r = rebuild_precision<R>(P, D, shift0, s))) return r;
+  return measure_error<R>(P, D, s, &e);
+}
+
+int calibrate_orders(Problem& P, hipStream_t s) {
+  if (P.direct || P.L < 2) return 0;
+  int r = calibrate_one<double>(P, P.f64, P.fmm_tol64, true, s);
+  if (!r) r = calibrate_one<float>(P, P.f32, P.fmm_tol32, false, s);
+  return r;
+}
+
+}  // namespace bemfmm
+
 template <typename Build>
 static int autotune_leaf_level(const bem_problem& q, Build& build_one, Problem** best,
                                hipStream_t s) {
@@ -233,6 +316,10 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
     for (int64_t t = 0; t < 3 * q.n_vert; ++t)
       if (!std::isfinite(q.vert[t])) return fail(BEM_E_INVALID, "non-finite vertex coordinate");
     if (q.order64 > 40 || q.order32 > 40) return fail(BEM_E_INVALID, "expansion order > 40");
+    if (!std::isfinite(q.fmm_tol) || !std::isfinite(q.fmm_tol32) || q.fmm_tol >= 1.0 ||
+        q.fmm_tol32 >= 1.0)
+      return fail(BEM_E_INVALID, "fmm_tol must be finite and < 1");
+    if (q.p_max > 40) return fail(BEM_E_INVALID, "p_max > 40");
   }
   hipStream_t s = (hipStream_t)stream;
   bem_plan* plan = new bem_plan();
@@ -253,9 +340,13 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
     P->leaf_level_req = leaf_level;
     P->order64_req = q.order64;
     P->order32_req = q.order32;
+    P->fmm_tol64 = q.fmm_tol;
+    P->fmm_tol32 = q.fmm_tol32;
+    P->p_max = q.p_max > 0 ? q.p_max : 40;
     int r = build_geometry_and_tree(*P, q.vert, q.n_vert, q.tri, s);
     if (!r) r = build_near_field(*P, s);
     if (!r) r = build_operators(*P, s);
+    if (!r) r = calibrate_orders(*P, s);
     if (r) {
       destroy_problem(P);
       return r;
@@ -300,7 +391,11 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
     st->order32[l] = P->f32.order[l];
     st->box_size[l] = P->h[l];
   }
-  st->device_bytes = P->arena.bytes;
+  st->device_bytes = P->arena.bytes + P->f64.ops.bytes + P->f32.ops.bytes;
+  st->fmm_err64 = P->direct ? 0.0 : P->f64.err;
+  st->fmm_err32 = P->direct ? 0.0 : P->f32.err;
+  st->fmm_err64_smooth = P->direct ? 0.0 : P->f64.err_smooth;
+  st->fmm_err32_smooth = P->direct ? 0.0 : P->f32.err_smooth;
   st->tuned_ms = P->tuned_ms;
   for (int l = 0; l < 22; ++l) st->m2l_tile32[l] = (l <= P->L) ? P->f32.m2l[l].ct : 0;
   st->schedule[0] = P->sched[0];
@@ -437,6 +532,32 @@ int bem_objective_grad(bem_plan* plan, int prob, const void* beta, const double*
                         info_fwd, info_adj, (hipStream_t)stream);
 }
 
+int bem_objective_forward(bem_plan* plan, int prob, const void* beta, const double* dir3,
+                          const double* pts, int n_pts, const bem_gmres_opts* opts, double* J,
+                          void* p_out, void* pobs_out, bem_gmres_info* info, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !beta || !dir3 || !pts || n_pts < 1 || !opts || !J)
+    return fail(BEM_E_INVALID, "bad arguments");
+  if (!(opts->tol > 0.0)) return fail(BEM_E_INVALID, "tol must be > 0");
+  if (info) std::memset(info, 0, sizeof(*info));
+  return objective_forward(*P, (const c64*)beta, dir3, pts, n_pts, opts, J, (c64*)p_out,
+                           (c64*)pobs_out, info, (hipStream_t)stream);
+}
+
+int bem_objective_backward(bem_plan* plan, int prob, const void* beta, const void* p,
+                           const void* pobs, const double* pts, int n_pts,
+                           const bem_gmres_opts* opts, void* grad, bem_gmres_info* info,
+                           void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !beta || !p || !pobs || !pts || n_pts < 1 || !opts || !grad)
+    return fail(BEM_E_INVALID, "bad arguments");
+  if (!(opts->tol > 0.0)) return fail(BEM_E_INVALID, "tol must be > 0");
+  if (grad == beta || grad == p) return fail(BEM_E_INVALID, "grad aliases an input");
+  if (info) std::memset(info, 0, sizeof(*info));
+  return objective_backward(*P, (const c64*)beta, (const c64*)p, (const c64*)pobs, pts, n_pts,
+                            opts, (c64*)grad, info, (hipStream_t)stream);
+}
+
 int bem_tree_export(bem_plan* plan, int prob, void* keys, void* perm, void* stream) {
   Problem* P = get_prob(plan, prob);
   if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
@@ -535,8 +656,16 @@ int bem_profile_start(bem_plan* plan, int prob) {
   if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
   P->prof_on = true;
   P->prof_leaf = false;
+  P->prof_serial = false;
   P->ev_used = 0;
   P->ev_slot.clear();
+  return BEM_OK;
+}
+
+int bem_profile_serial_start(bem_plan* plan, int prob) {
+  int r = bem_profile_start(plan, prob);
+  if (r) return r;
+  plan->probs[prob]->prof_serial = true;
   return BEM_OK;
 }
 
@@ -552,6 +681,7 @@ int bem_profile_leaf_m2l_start(bem_plan* plan, int prob) {
   }
   P->prof_on = false;
   P->prof_leaf = true;
+  P->prof_serial = false;
   P->ev_used = 0;
   P->ev_slot.clear();
   return BEM_OK;
@@ -574,6 +704,7 @@ int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls) {
   }
   P->prof_on = false;
   P->prof_leaf = false;
+  P->prof_serial = false;
   P->ev_used = 0;
   P->ev_slot.clear();
   return BEM_OK;

@@ -29,6 +29,7 @@
 #include <cmath>
 
 #include <algorithm>
+#include <vector>
 
 #include <hip/hip_ext.h>
 
@@ -1859,13 +1860,15 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
   const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
+  // every stage on this stream (direct sum, or a serial stage profile)
+  const bool one_stream = P.direct || (P.prof_on && P.prof_serial);
   // gather and P2M in one launch when a leaf's values fit in LDS and the
   // near field does not start right after the gather (it would start later:
   // measured slower); its completion (event ev_fork2) forks the leaf M2L
   const size_t lds_fused = 2 * (size_t)P.max_leaf * sizeof(cplx<R>);
   const bool fused = !P.direct && !p2p_first && lds_fused <= FUSED_LDS_MAX;
   // else the gather's completion forks the near field when it follows directly
-  const bool fork_at_gather = p2p_first && !P.direct;
+  const bool fork_at_gather = p2p_first && !one_stream;
   int r = 0;
   PROF_BEGIN(e0);
   if (fused) {
@@ -1882,8 +1885,8 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   PROF_END(e0, fused ? ST_P2M : ST_GATHER);
   // the near field runs on the side stream, concurrently with the far field
   auto launch_p2p = [&]() -> int {
-    hipStream_t sn = P.direct ? s : P.side;
-    if (!P.direct) {
+    hipStream_t sn = one_stream ? s : P.side;
+    if (!one_stream) {
       hipEvent_t fork = P.ev_fork;
       if (sched == SCHED_LEAF_THEN_P2P)
         fork = P.ev_fork2;  // completion of the P2M (or gather + P2M)
@@ -1895,7 +1898,7 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
     P2PJobDev<R> job = p2p_job(P, D, X, false);
     job.q_zero = q ? 0 : 1;
     int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, false, P.alpha.re == 0.0, cap, sn,
-                                P.direct ? nullptr : P.ev_join);
+                                one_stream ? nullptr : P.ev_join);
     if (rr) return rr;
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, false), sn);
     if (pr) return pr;
@@ -1912,8 +1915,9 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   // leaf-level M2L (needs only the leaf multipoles): on its own stream
   // (SCHED_CONCURRENT), or on this stream before the upward pass; the fork
   // is signalled by the P2M launch
-  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP ||
-                         sched == SCHED_LEAF_THEN_P2P;
+  const bool leaf_side = !one_stream && (sched == SCHED_CONCURRENT ||
+                                         sched == SCHED_P2P_AFTER_UP ||
+                                         sched == SCHED_LEAF_THEN_P2P);
   hipStream_t sl = leaf_side ? P.side2 : s;
   if (!fused) {
     PROF_BEGIN(e2);
@@ -1941,7 +1945,7 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   PROF_BEGIN(e5);
   if ((r = downward_pass<R>(P, D, X, false, s))) return r;
   PROF_END(e5, ST_L2L);
-  if ((r = join_side_streams(P, s, leaf_side))) return r;
+  if (!one_stream && (r = join_side_streams(P, s, leaf_side))) return r;
   PROF_BEGIN(e6);
   {
     const GroupedOp<R>& op = D.m2l[L];
@@ -1980,10 +1984,12 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
   const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
+  // every stage on this stream (direct sum, or a serial stage profile)
+  const bool one_stream = P.direct || (P.prof_on && P.prof_serial);
   // gather and L2P^H in one launch under the forward product's conditions
   const size_t lds_fused = (size_t)P.max_leaf * sizeof(cplx<R>);
   const bool fused = !P.direct && !p2p_first && lds_fused <= FUSED_LDS_MAX;
-  const bool fork_at_gather = p2p_first && !P.direct;
+  const bool fork_at_gather = p2p_first && !one_stream;
   int r = 0;
   PROF_BEGIN(e0);
   if (fused) {
@@ -1999,8 +2005,8 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   BEM_LAUNCH_CHECK();
   PROF_END(e0, fused ? ST_P2M : ST_GATHER);
   auto launch_p2p = [&]() -> int {
-    hipStream_t sn = P.direct ? s : P.side;
-    if (!P.direct) {
+    hipStream_t sn = one_stream ? s : P.side;
+    if (!one_stream) {
       hipEvent_t fork = P.ev_fork;
       if (sched == SCHED_LEAF_THEN_P2P)
         fork = P.ev_fork2;  // completion of the L2P^H (or gather + L2P^H)
@@ -2012,7 +2018,7 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
     P2PJobDev<R> job = p2p_job(P, D, X, true);
     job.q_zero = w ? 0 : 1;
     int rr = launch_p2p_jobs<R>(&job, &nleaf, 1, true, P.alpha.re == 0.0, cap, sn,
-                                P.direct ? nullptr : P.ev_join);
+                                one_stream ? nullptr : P.ev_join);
     if (rr) return rr;
     int pr = prof_end(P, e1, prof_slot(ST_P2P, sizeof(R) == 4, true), sn);
     if (pr) return pr;
@@ -2029,8 +2035,9 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   // adjoint locals (L2P^H) in Lc, adjoint multipoles in M
   // leaf-level M2L^H (needs only the leaf adjoint locals): own stream or
   // this one, as in the forward product
-  const bool leaf_side = sched == SCHED_CONCURRENT || sched == SCHED_P2P_AFTER_UP ||
-                         sched == SCHED_LEAF_THEN_P2P;
+  const bool leaf_side = !one_stream && (sched == SCHED_CONCURRENT ||
+                                         sched == SCHED_P2P_AFTER_UP ||
+                                         sched == SCHED_LEAF_THEN_P2P);
   hipStream_t sl = leaf_side ? P.side2 : s;
   if (!fused) {
     PROF_BEGIN(e2);
@@ -2056,7 +2063,7 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   PROF_BEGIN(e3);
   if ((r = downward_pass<R>(P, D, X, true, s))) return r;
   PROF_END(e3, ST_M2M);
-  if ((r = join_side_streams(P, s, leaf_side))) return r;
+  if (!one_stream && (r = join_side_streams(P, s, leaf_side))) return r;
   PROF_BEGIN(e6);
   {
     const GroupedOp<R>& op = D.m2l[L];
@@ -2346,6 +2353,167 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
   }
   return 0;
 }
+
+// ---------------------------------------------------------------------------
+// Accuracy of a built problem: the product on seeded pseudo-random (white)
+// densities and on a plane-wave density against the exact discrete operator
+// on sampled rows.  The two differ: white noise mostly cancels in the far
+// field, where a smooth density adds up coherently, so the same truncation
+// gives the smooth density a larger error relative to the product.
+// ---------------------------------------------------------------------------
+// Re and Im uniform in [-1, 1) from a 64-bit mix of (seed, index)
+// (splitmix64's finaliser)
+__device__ __forceinline__ double unit_from_hash(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// p = exp(i k d.x), q = dp/dn = i k (d.n) p at the collocation points (caller
+// order): a smooth density, whose far field adds up coherently
+__global__ void k_fill_plane(const double* __restrict__ geo, int64_t n,
+                             const int* __restrict__ perm, double k, double dx, double dy,
+                             double dz, c64* __restrict__ p, c64* __restrict__ q) {
+  const int64_t i = grid_tid();
+  if (i >= n) return;
+  const double ph = k * (dx * geo[GEO_CX * n + i] + dy * geo[GEO_CY * n + i] +
+                         dz * geo[GEO_CZ * n + i]);
+  const double dn = dx * geo[GEO_NX * n + i] + dy * geo[GEO_NY * n + i] + dz * geo[GEO_NZ * n + i];
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  const int o = perm[i];
+  p[o] = mk(cs, sn);
+  q[o] = mk(-k * dn * sn, k * dn * cs);
+}
+
+__global__ void k_fill_random(c64* __restrict__ v, int64_t n, uint64_t seed) {
+  const int64_t i = grid_tid();
+  if (i < n)
+    v[i] = mk(unit_from_hash(seed * 0x100000000ull + 2 * (uint64_t)i),
+              unit_from_hash(seed * 0x100000000ull + 2 * (uint64_t)i + 1));
+}
+
+// One block per sampled row (sorted target index rows[t]): the exact row of
+// the discrete operator applied to p, q (caller order), in float64: the
+// 3-point rule over every other element, the near-field corrections of the
+// row and the diagonal (I/2, alpha/2, self integrals).
+__global__ void __launch_bounds__(256)
+    k_exact_rows(const double* __restrict__ geo, int64_t n, const int* __restrict__ perm,
+                 const int* __restrict__ rows, const c64* __restrict__ p,
+                 const c64* __restrict__ q, double k, double alr, double ali,
+                 const int* __restrict__ nptr, const int* __restrict__ ncol,
+                 const c64* __restrict__ ncp, const c64* __restrict__ ncq,
+                 const c64* __restrict__ dp, const c64* __restrict__ dq, c64* __restrict__ out) {
+  __shared__ double sr[256], si[256];
+  const int i = rows[blockIdx.x];
+  const double xx = geo[GEO_CX * n + i], xy = geo[GEO_CY * n + i], xz = geo[GEO_CZ * n + i];
+  const double nxx = geo[GEO_NX * n + i], nxy = geo[GEO_NY * n + i],
+               nxz = geo[GEO_NZ * n + i];
+  c64 acc = mk(0.0, 0.0);
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    if (j == i) continue;
+    double yq[9];
+    for (int c = 0; c < 9; ++c) yq[c] = geo[(GEO_QX0 + c) * n + j];
+    const double nyx = geo[GEO_NX * n + j], nyy = geo[GEO_NY * n + j],
+                 nyz = geo[GEO_NZ * n + j];
+    const double d = yq[0] * nyx + yq[1] * nyy + yq[2] * nyz;
+    c64 sp, sq;
+    bm_elem<double, false>(xx, xy, xz, nxx, nxy, nxz, yq, nyx, nyy, nyz, d, k, 0.0, alr, ali, sp,
+                           sq);
+    const double w = geo[GEO_AREA * n + j] * (1.0 / 3.0) * INV_4PI_D;
+    const int o = perm[j];
+    cfma(acc, cscale(sp, w), p[o]);
+    cfma(acc, cscale(sq, w), q[o]);
+  }
+  for (int t = nptr[i] + threadIdx.x; t < nptr[i + 1]; t += blockDim.x) {
+    const int o = perm[ncol[t]];
+    cfma(acc, ncp[t], p[o]);
+    cfma(acc, ncq[t], q[o]);
+  }
+  sr[threadIdx.x] = acc.re;
+  si[threadIdx.x] = acc.im;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sr[threadIdx.x] += sr[threadIdx.x + st];
+      si[threadIdx.x] += si[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    c64 v = mk(sr[0], si[0]);
+    const int o = perm[i];
+    cfma(v, dp[i], p[o]);
+    cfma(v, dq[i], q[o]);
+    out[blockIdx.x] = v;
+  }
+}
+
+__global__ void k_gather_rows(const c64* __restrict__ y, const int* __restrict__ perm,
+                              const int* __restrict__ rows, int m, c64* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) out[t] = y[perm[rows[t]]];
+}
+
+template <typename R>
+int measure_error(Problem& P, PrecisionData<R>& D, hipStream_t s, double* err) {
+  const int64_t n = P.n;
+  const int m = (int)std::min<int64_t>(128, n);
+  DevArena tmp;
+  struct G {
+    DevArena& a;
+    ~G() { a.release(); }
+  } guard{tmp};
+  c64 *p, *q, *y, *yr, *ys;
+  int* rows;
+  if (tmp.alloc((void**)&p, sizeof(c64) * n) || tmp.alloc((void**)&q, sizeof(c64) * n) ||
+      tmp.alloc((void**)&y, sizeof(c64) * n) || tmp.alloc((void**)&yr, sizeof(c64) * m) ||
+      tmp.alloc((void**)&ys, sizeof(c64) * m) || tmp.alloc((void**)&rows, sizeof(int) * m))
+    return -2;
+  // rows spread evenly over the sorted (space-filling) order
+  std::vector<int> hr(m);
+  for (int t = 0; t < m; ++t) hr[t] = (int)(((int64_t)t * n + n / (2 * m)) / m);
+  BEM_HIP_TRY(hipMemcpyAsync(rows, hr.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+  double e[2] = {0, 0};
+  for (int kind = 0; kind < 2; ++kind) {
+    if (kind == 0) {  // white noise
+      hipLaunchKernelGGL(k_fill_random, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, 1ull);
+      hipLaunchKernelGGL(k_fill_random, dim3(ceil_div(n, 256)), dim3(256), 0, s, q, n, 2ull);
+    } else {  // plane wave along (1, 2, 3) / sqrt(14)
+      const double c = 1.0 / std::sqrt(14.0);
+      hipLaunchKernelGGL(k_fill_plane, dim3(ceil_div(n, 256)), dim3(256), 0, s, P.geo, n, P.perm,
+                         P.k, c, 2.0 * c, 3.0 * c, p, q);
+    }
+    BEM_LAUNCH_CHECK();
+    int r = fmm_apply_x<R>(P, D, D.X, p, q, y, s);
+    if (r) return r;
+    hipLaunchKernelGGL(k_exact_rows, dim3(m), dim3(256), 0, s, P.geo, n, P.perm, rows, p, q,
+                       P.k, P.alpha.re, P.alpha.im, P.near_ptr, P.near_col, P.f64.near_cp,
+                       P.f64.near_cq, P.diag_p, P.diag_q, yr);
+    hipLaunchKernelGGL(k_gather_rows, dim3(ceil_div(m, 64)), dim3(64), 0, s, y, P.perm, rows, m,
+                       ys);
+    BEM_LAUNCH_CHECK();
+    std::vector<c64> a(m), b(m);
+    BEM_HIP_TRY(hipMemcpyAsync(a.data(), ys, sizeof(c64) * m, hipMemcpyDeviceToHost, s));
+    BEM_HIP_TRY(hipMemcpyAsync(b.data(), yr, sizeof(c64) * m, hipMemcpyDeviceToHost, s));
+    BEM_HIP_TRY(hipStreamSynchronize(s));
+    double num = 0, den = 0;
+    for (int t = 0; t < m; ++t) {
+      const double dr = a[t].re - b[t].re, di = a[t].im - b[t].im;
+      num += dr * dr + di * di;
+      den += b[t].re * b[t].re + b[t].im * b[t].im;
+    }
+    e[kind] = den > 0 ? std::sqrt(num / den) : 0.0;
+  }
+  D.err = e[0];
+  D.err_smooth = e[1];
+  *err = std::max(e[0], e[1]);
+  return 0;
+}
+template int measure_error<float>(Problem&, PrecisionData<float>&, hipStream_t, double*);
+template int measure_error<double>(Problem&, PrecisionData<double>&, hipStream_t, double*);
 
 template <typename R>
 int fmm_apply(Problem& P, PrecisionData<R>& D, const c64* p, const c64* q, c64* y,

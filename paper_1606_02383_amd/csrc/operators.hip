@@ -404,10 +404,10 @@ __global__ void k_p_columns(const cplx<R>* __restrict__ in, int64_t cnt,
 }
 
 template <typename R>
-static int make_translations(Problem& P, int ngroups, const std::vector<double>& tvec, int sing,
-                             int pin, int pout, const std::vector<double>& rs,
-                             const std::vector<double>& cs, cplx<R>** mats, DevArena& scratch,
-                             hipStream_t s) {
+static int make_translations(Problem& P, DevArena& keep, int ngroups,
+                             const std::vector<double>& tvec, int sing, int pin, int pout,
+                             const std::vector<double>& rs, const std::vector<double>& cs,
+                             cplx<R>** mats, DevArena& scratch, hipStream_t s) {
   int lmax = pin + pout;
   GauntSet G;
   int r = make_gaunt(pin, pout, lmax, G, scratch, s);
@@ -427,7 +427,7 @@ static int make_translations(Problem& P, int ngroups, const std::vector<double>&
                      P.k, lmax, sing, F, tmp);
   BEM_LAUNCH_CHECK();
   int64_t Pin = (pin + 1) * (pin + 1), Pout = (pout + 1) * (pout + 1);
-  ARENA_ALLOC(P.arena, *mats, Pin * Pout * ngroups);
+  ARENA_ALLOC(keep, *mats, Pin * Pout * ngroups);
   int64_t tot = Pin * Pout * ngroups;
   hipLaunchKernelGGL(k_translation<R>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, ngroups, pin,
                      pout, lmax, F, G.d, drs, dcs, *mats);
@@ -437,12 +437,14 @@ static int make_translations(Problem& P, int ngroups, const std::vector<double>&
 
 // Expansion order of a level: ceil(k sqrt(3) h) + extra, at least `base`;
 // req > 0 fixes it, req < 0 replaces the minimum by -req.
-static int auto_order(double k, double h, int req, int base, int extra) {
-  if (req > 0) return std::min(req, MAXP);
+// shift (calibration) moves both terms; the result lies in [1, pmax].
+static int auto_order(double k, double h, int req, int base, int extra, int shift, int pmax) {
+  pmax = std::max(1, std::min(pmax, MAXP));
+  if (req > 0) return std::min(req, pmax);
   if (req < 0) base = -req;
   double d = sqrt(3.0) * h;
-  int p = (int)ceil(k * d) + extra;
-  return std::min(std::max(p, base), MAXP);
+  int p = (int)ceil(k * d) + extra + shift;
+  return std::min(std::max(std::max(p, base + shift), 1), pmax);
 }
 
 // Tiles of a grouped op: (group, first pair, pair count, first row)
@@ -679,8 +681,8 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
   const int L = P.L;
   const double k = P.k;
   for (int l = 2; l <= L; ++l) {
-    D.order[l] = is64 ? auto_order(k, P.h[l], P.order64_req, 12, 8)
-                      : auto_order(k, P.h[l], P.order32_req, 7, 3);
+    D.order[l] = is64 ? auto_order(k, P.h[l], P.order64_req, 12, 8, D.shift, P.p_max)
+                      : auto_order(k, P.h[l], P.order32_req, 7, 3, D.shift, P.p_max);
     D.ncoef[l] = (D.order[l] + 1) * (D.order[l] + 1);
   }
   // ---- M2L: one matrix per offset present at each level ----
@@ -714,17 +716,17 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     if (ns > 0) {
       // L~ = f_n' (S|R) M~ f_n  (locals times f, multipoles over f)
       std::vector<double> rs = coef_scale(p, k * P.h[l], +1), cs = coef_scale(p, k * P.h[l], +1);
-      r = make_translations<R>(P, ns, tv, 1, p, p, rs, cs, &op.mats, scratch, s);
+      r = make_translations<R>(P, D.ops, ns, tv, 1, p, p, rs, cs, &op.mats, scratch, s);
       if (r) return r;
       const int64_t tot = (int64_t)ns * op.rows * op.cols;
-      ARENA_ALLOC(P.arena, op.mats_h, tot);
+      ARENA_ALLOC(D.ops, op.mats_h, tot);
       hipLaunchKernelGGL(k_conj_transpose<R>, dim3(ceil_div(tot, 256)), dim3(256), 0, s,
                          op.mats, ns, op.rows, op.cols, op.mats_h);
       BEM_LAUNCH_CHECK();
     }
-    r = finish_grouped<R>(op, d0, s0, c0, np, N_OFFSETS, slot, P.arena, scratch, s);
+    r = finish_grouped<R>(op, d0, s0, c0, np, N_OFFSETS, slot, D.ops, scratch, s);
     if (r) return r;
-    r = build_reduce_lists<R>(op, P.nbox[l], P.arena, scratch, s);
+    r = build_reduce_lists<R>(op, P.nbox[l], D.ops, scratch, s);
     if (r) return r;
     if (l < L) {
       D.cbuf_off[l] = cbuf_count;
@@ -765,9 +767,9 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     mm.cols = D.ncoef[l];
     mm.n_slots = 8;
     std::vector<double> rs = coef_scale(pp, k * P.h[l - 1], -1), cs = coef_scale(pc, k * P.h[l], +1);
-    int r = make_translations<R>(P, 8, tv_m2m, 0, pc, pp, rs, cs, &mm.mats, scratch, s);
+    int r = make_translations<R>(P, D.ops, 8, tv_m2m, 0, pc, pp, rs, cs, &mm.mats, scratch, s);
     if (r) return r;
-    r = finish_grouped<R>(mm, d0, s0, c0, nb, 8, slot, P.arena, scratch, s);
+    r = finish_grouped<R>(mm, d0, s0, c0, nb, 8, slot, D.ops, scratch, s);
     if (r) return r;
     // L~_child = f^(l)_n' (R|R) (1/f^(l-1)_n) L~_par ; pairs (dst child, src parent)
     GroupedOp<R>& ll = D.l2l[l];
@@ -776,9 +778,9 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     ll.n_slots = 8;
     rs = coef_scale(pc, k * P.h[l], +1);
     cs = coef_scale(pp, k * P.h[l - 1], -1);
-    r = make_translations<R>(P, 8, tv_l2l, 0, pp, pc, rs, cs, &ll.mats, scratch, s);
+    r = make_translations<R>(P, D.ops, 8, tv_l2l, 0, pp, pc, rs, cs, &ll.mats, scratch, s);
     if (r) return r;
-    r = finish_grouped<R>(ll, s0, d0, c0, nb, 8, slot, P.arena, scratch, s);
+    r = finish_grouped<R>(ll, s0, d0, c0, nb, 8, slot, D.ops, scratch, s);
     if (r) return r;
   }
   // ---- direct translations between the leaves and the MAX_DIRECT levels
@@ -822,10 +824,10 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     mu.cols = D.ncoef[L];
     mu.n_slots = ng;
     std::vector<double> rs = coef_scale(pa, k * P.h[a], -1), cs = coef_scale(pL, k * P.h[L], +1);
-    int r = make_translations<R>(P, ng, tv_up, 0, pL, pa, rs, cs, &mu.mats, scratch, s);
+    int r = make_translations<R>(P, D.ops, ng, tv_up, 0, pL, pa, rs, cs, &mu.mats, scratch, s);
     if (r) return r;
     // few pairs per position code: 16-pair tiles (all depths share a launch)
-    r = finish_grouped<R>(mu, d0, s0, c0, nb, ng, slot, P.arena, scratch, s, 16);
+    r = finish_grouped<R>(mu, d0, s0, c0, nb, ng, slot, D.ops, scratch, s, 16);
     if (r) return r;
     GroupedOp<R>& ld = D.l2l_dir[d];  // L~_leaf += f^(L) (R|R) (1/f^(a)) L~_anc
     ld.rows = D.ncoef[L];
@@ -833,9 +835,9 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     ld.n_slots = ng;
     rs = coef_scale(pL, k * P.h[L], +1);
     cs = coef_scale(pa, k * P.h[a], -1);
-    r = make_translations<R>(P, ng, tv_down, 0, pa, pL, rs, cs, &ld.mats, scratch, s);
+    r = make_translations<R>(P, D.ops, ng, tv_down, 0, pa, pL, rs, cs, &ld.mats, scratch, s);
     if (r) return r;
-    r = finish_grouped<R>(ld, s0, d0, c0, nb, ng, slot, P.arena, scratch, s, 16);
+    r = finish_grouped<R>(ld, s0, d0, c0, nb, ng, slot, D.ops, scratch, s, 16);
     if (r) return r;
     D.n_direct = d;
   }
@@ -884,8 +886,8 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     BEM_HIP_TRY(hipMemcpyAsync(dgc, gc.data(), sizeof(double) * gc.size(), hipMemcpyHostToDevice, s));
     BEM_HIP_TRY(hipMemcpyAsync(dfinv, finv.data(), sizeof(double) * (p + 1), hipMemcpyHostToDevice, s));
     BEM_HIP_TRY(hipMemcpyAsync(dlo, P.lo, sizeof(double) * 3, hipMemcpyHostToDevice, s));
-    ARENA_ALLOC(P.arena, D.p2m, (int64_t)P.n * Pc * 2);
-    ARENA_ALLOC(P.arena, D.l2p, (int64_t)P.n * Pc);
+    ARENA_ALLOC(D.ops, D.p2m, (int64_t)P.n * Pc * 2);
+    ARENA_ALLOC(D.ops, D.l2p, (int64_t)P.n * Pc);
     int64_t chunk = 16384;
     c64* Rbuf;
     double* tmpb;
@@ -898,7 +900,7 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
                          dgc, dfinv, Rbuf, tmpb, D.p2m, D.l2p);
       BEM_LAUNCH_CHECK();
     }
-    ARENA_ALLOC(P.arena, D.p2m_p, (int64_t)P.n * Pc);
+    ARENA_ALLOC(D.ops, D.p2m_p, (int64_t)P.n * Pc);
     hipLaunchKernelGGL(k_p_columns<R>, dim3(ceil_div((int64_t)P.n * Pc, 256)), dim3(256), 0, s,
                        D.p2m, (int64_t)P.n * Pc, D.p2m_p);
     BEM_LAUNCH_CHECK();
@@ -933,6 +935,42 @@ template int alloc_exec<float>(const Problem&, const PrecisionData<float>&, Exec
 template int alloc_exec<double>(const Problem&, const PrecisionData<double>&, ExecBuf<double>&,
                                 DevArena&);
 
+template <typename R>
+int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift, hipStream_t s) {
+  BEM_HIP_TRY(hipStreamSynchronize(s));  // no product still uses the old data
+  PrecisionData<R> keep;
+  keep.near_cp = D.near_cp;
+  keep.near_cq = D.near_cq;
+  keep.neart_cp = D.neart_cp;
+  keep.neart_cq = D.neart_cq;
+  keep.geo = D.geo;
+  D.ops.release();
+  D.order = keep.order;
+  D.ncoef = keep.ncoef;
+  D.m2l = keep.m2l;
+  D.m2m = keep.m2m;
+  D.l2l = keep.l2l;
+  D.n_direct = 0;
+  D.m2m_dir = keep.m2m_dir;
+  D.l2l_dir = keep.l2l_dir;
+  D.cbuf_off = keep.cbuf_off;
+  D.cbuf_count = D.cbufL_count = 0;
+  D.p2m = D.p2m_p = D.l2p = nullptr;
+  D.X = ExecBuf<R>{};
+  D.shift = shift;
+  DevArena scratch;
+  struct Guard {
+    DevArena& a;
+    ~Guard() { a.release(); }
+  } guard{scratch};
+  int r = build_precision<R>(P, D, sizeof(R) == 8, scratch, s);
+  if (!r) r = alloc_exec<R>(P, D, D.X, D.ops);
+  if (!r) BEM_HIP_TRY(hipStreamSynchronize(s));
+  return r;
+}
+template int rebuild_precision<float>(Problem&, PrecisionData<float>&, int, hipStream_t);
+template int rebuild_precision<double>(Problem&, PrecisionData<double>&, int, hipStream_t);
+
 int build_operators(Problem& P, hipStream_t s) {
   DevArena scratch;
   struct Guard {
@@ -953,8 +991,8 @@ int build_operators(Problem& P, hipStream_t s) {
   BEM_LAUNCH_CHECK();
   P.f64.geo = P.geo;
   {
-    int r = alloc_exec<double>(P, P.f64, P.f64.X, P.arena);
-    if (!r) r = alloc_exec<float>(P, P.f32, P.f32.X, P.arena);
+    int r = alloc_exec<double>(P, P.f64, P.f64.X, P.f64.ops);
+    if (!r) r = alloc_exec<float>(P, P.f32, P.f32.X, P.f32.ops);
     if (r) return r;
   }
   if (!P.side || !P.side2) {

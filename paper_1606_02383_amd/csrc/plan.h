@@ -87,6 +87,14 @@ struct ExecBuf {
 
 template <typename R>
 struct PrecisionData {
+  // device memory of everything that depends on the expansion orders (the
+  // operators, tiles, reduction lists, P2M/L2P matrices and the product
+  // buffers X): released and rebuilt when the orders are recalibrated
+  DevArena ops;
+  int shift = 0;       // order shift applied to the level rule (calibration)
+  double err = -1.0;   // sampled relative error of the product on white-noise
+                       // densities (< 0: not measured)
+  double err_smooth = -1.0;  // the same on a plane-wave density
   std::array<int, MAX_LEVEL + 1> order{};   // p_l
   std::array<int, MAX_LEVEL + 1> ncoef{};   // (p_l + 1)^2
   std::array<GroupedOp<R>, MAX_LEVEL + 1> m2l{};
@@ -126,6 +134,10 @@ struct Problem {
   c64 alpha{0, 0};
   double eta = 2.0;
   int leaf_cap = 64, leaf_level_req = 0, order64_req = 0, order32_req = 0;
+  // target relative error of the float64 / float32 products (<= 0: the
+  // level rule as it is) and the largest expansion order allowed
+  double fmm_tol64 = 0, fmm_tol32 = 0;
+  int p_max = 40;
   DevArena arena;
   // geometry, sorted order, float64 SoA (GEO_COUNT x n)
   double* geo = nullptr;
@@ -190,6 +202,9 @@ struct Problem {
   // (nothing recorded between kernels), for timing inside a timed region
   bool prof_on = false;
   bool prof_leaf = false;
+  // with prof_on: every stage on the caller's stream, one after another, so
+  // each stage's events time it alone on the GPU
+  bool prof_serial = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_slot;   // slot of each recorded (start, end) pair
   int ev_used = 0;
@@ -227,6 +242,18 @@ int build_geometry_and_tree(Problem& P, const double* vert, int64_t n_vert, cons
                             hipStream_t s);
 int build_near_field(Problem& P, hipStream_t s);
 int build_operators(Problem& P, hipStream_t s);
+// Rebuild the order-dependent data of one precision with the level rule
+// shifted by `shift` (release of the old data included).
+template <typename R>
+int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift, hipStream_t s);
+// Sampled relative error of one product against the exact discrete operator:
+// rows spread over the mesh, seeded pseudo-random p and q, reference rows
+// summed directly in float64 (rule points, near corrections, diagonal).
+template <typename R>
+int measure_error(Problem& P, PrecisionData<R>& D, hipStream_t s, double* err);
+// Orders of both precisions chosen for the problem's tolerances (see
+// bem_problem.fmm_tol), then the achieved errors measured.
+int calibrate_orders(Problem& P, hipStream_t s);
 template <typename R>
 int alloc_exec(const Problem& P, const PrecisionData<R>& D, ExecBuf<R>& X, DevArena& arena);
 template <typename R>

@@ -885,9 +885,12 @@ __global__ void k_grad(const c64* __restrict__ w, const c64* __restrict__ rq,
   grad[i] = mk(2.0 * k * gp.im, 2.0 * k * gp.re);
 }
 
-int objective_grad(Problem& P, const c64* beta, const double* dir, const double* pts_host,
-                   int n_pts, const bem_gmres_opts* opts, double* J, c64* grad, c64* p_out,
-                   bem_gmres_info* info_f, bem_gmres_info* info_a, hipStream_t s) {
+// Forward half of the objective (the state problem): sigma = -i k beta,
+// A(sigma) p = b (plane wave), q = sigma p, p_obs = field at the points,
+// J = sum |p_obs|^2.  p_out (n) and pobs_out (n_pts) may be null.
+int objective_forward(Problem& P, const c64* beta, const double* dir, const double* pts_host,
+                      int n_pts, const bem_gmres_opts* opts, double* J, c64* p_out,
+                      c64* pobs_out, bem_gmres_info* info_f, hipStream_t s) {
   const int64_t n = P.n;
   const int nb = ceil_div(n, 256);
   DevArena tmp;
@@ -895,19 +898,13 @@ int objective_grad(Problem& P, const c64* beta, const double* dir, const double*
     DevArena& a;
     ~G() { a.release(); }
   } guard{tmp};
-  c64 *sg, *b, *p, *q, *pobs, *rp, *rq, *rhs, *mu, *u, *w;
+  c64 *sg, *b, *p, *q, *pobs;
   double *pts, *dJ;
   ARENA_ALLOC(tmp, sg, n);
   ARENA_ALLOC(tmp, b, n);
   ARENA_ALLOC(tmp, p, n);
   ARENA_ALLOC(tmp, q, n);
   ARENA_ALLOC(tmp, pobs, n_pts);
-  ARENA_ALLOC(tmp, rp, n);
-  ARENA_ALLOC(tmp, rq, n);
-  ARENA_ALLOC(tmp, rhs, n);
-  ARENA_ALLOC(tmp, mu, n);
-  ARENA_ALLOC(tmp, u, n);
-  ARENA_ALLOC(tmp, w, n);
   ARENA_ALLOC(tmp, pts, 3 * n_pts);
   ARENA_ALLOC(tmp, dJ, 1);
   BEM_HIP_TRY(hipMemcpyAsync(pts, pts_host, sizeof(double) * 3 * n_pts, hipMemcpyHostToDevice, s));
@@ -915,7 +912,7 @@ int objective_grad(Problem& P, const c64* beta, const double* dir, const double*
   BEM_LAUNCH_CHECK();
   int r = plane_wave_rhs(P, dir, b, s);
   if (r) return r;
-  bem_gmres_opts o = *opts;
+  const bem_gmres_opts o = *opts;
   r = gmres_solve(P, sg, 0, b, p, o.tol, o.restart > 0 ? o.restart : 50,
                   o.max_iter > 0 ? o.max_iter : 2000, o.mode, o.inner_tol, 0, info_f, s);
   if (r) return r;
@@ -929,19 +926,79 @@ int objective_grad(Problem& P, const c64* beta, const double* dir, const double*
     hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, p, n, p_out);
     BEM_LAUNCH_CHECK();
   }
-  if (grad) {
-    // conj(rhs_T) = rp + conj(sigma) rq with rp, rq from c = p_obs
-    if ((r = eval_field_adjoint(P, pts, n_pts, pobs, rp, rq, s))) return r;
-    hipLaunchKernelGGL(k_adj_rhs, dim3(nb), dim3(256), 0, s, rp, rq, sg, n, rhs);
-    BEM_LAUNCH_CHECK();
-    r = gmres_solve(P, sg, 1, rhs, mu, o.tol, o.restart > 0 ? o.restart : 50,
-                    o.max_iter > 0 ? o.max_iter : 2000, o.mode, o.inner_tol, 0, info_a, s);
-    if (r) return r;
-    // w = Mq^H mu (float64 adjoint product)
-    if ((r = fmm_apply_adjoint<double>(P, P.f64, mu, u, w, s))) return r;
-    hipLaunchKernelGGL(k_grad, dim3(nb), dim3(256), 0, s, w, rq, p, n, P.k, grad);
+  if (pobs_out) {
+    hipLaunchKernelGGL(k_copy, dim3(ceil_div(n_pts, 256)), dim3(256), 0, s, pobs,
+                       (int64_t)n_pts, pobs_out);
     BEM_LAUNCH_CHECK();
   }
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+// Backward half (the adjoint problem, Sec. 2.2, here in its discrete form):
+// with c = p_obs (dJ/dp_obs = 2 conj(p_obs), Eq. danseideltaJ), the adjoint
+// right-hand side rp + conj(sigma) rq (rp, rq: the field's adjoint), the
+// conjugate-transposed solve A(sigma)^H mu = rhs, w = Mq^H mu and
+// grad_e = dJ/dRe(beta_e) + i dJ/dIm(beta_e) from p, w and rq.
+int objective_backward(Problem& P, const c64* beta, const c64* p, const c64* pobs,
+                       const double* pts_host, int n_pts, const bem_gmres_opts* opts, c64* grad,
+                       bem_gmres_info* info_a, hipStream_t s) {
+  const int64_t n = P.n;
+  const int nb = ceil_div(n, 256);
+  DevArena tmp;
+  struct G {
+    DevArena& a;
+    ~G() { a.release(); }
+  } guard{tmp};
+  c64 *sg, *rp, *rq, *rhs, *mu, *u, *w;
+  double* pts;
+  ARENA_ALLOC(tmp, sg, n);
+  ARENA_ALLOC(tmp, rp, n);
+  ARENA_ALLOC(tmp, rq, n);
+  ARENA_ALLOC(tmp, rhs, n);
+  ARENA_ALLOC(tmp, mu, n);
+  ARENA_ALLOC(tmp, u, n);
+  ARENA_ALLOC(tmp, w, n);
+  ARENA_ALLOC(tmp, pts, 3 * n_pts);
+  BEM_HIP_TRY(hipMemcpyAsync(pts, pts_host, sizeof(double) * 3 * n_pts, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_sigma, dim3(nb), dim3(256), 0, s, beta, n, P.k, sg);
+  BEM_LAUNCH_CHECK();
+  int r = eval_field_adjoint(P, pts, n_pts, pobs, rp, rq, s);
+  if (r) return r;
+  hipLaunchKernelGGL(k_adj_rhs, dim3(nb), dim3(256), 0, s, rp, rq, sg, n, rhs);
+  BEM_LAUNCH_CHECK();
+  const bem_gmres_opts o = *opts;
+  r = gmres_solve(P, sg, 1, rhs, mu, o.tol, o.restart > 0 ? o.restart : 50,
+                  o.max_iter > 0 ? o.max_iter : 2000, o.mode, o.inner_tol, 0, info_a, s);
+  if (r) return r;
+  // w = Mq^H mu (float64 adjoint product)
+  if ((r = fmm_apply_adjoint<double>(P, P.f64, mu, u, w, s))) return r;
+  hipLaunchKernelGGL(k_grad, dim3(nb), dim3(256), 0, s, w, rq, p, n, P.k, grad);
+  BEM_LAUNCH_CHECK();
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+int objective_grad(Problem& P, const c64* beta, const double* dir, const double* pts_host,
+                   int n_pts, const bem_gmres_opts* opts, double* J, c64* grad, c64* p_out,
+                   bem_gmres_info* info_f, bem_gmres_info* info_a, hipStream_t s) {
+  const int64_t n = P.n;
+  DevArena tmp;
+  struct G {
+    DevArena& a;
+    ~G() { a.release(); }
+  } guard{tmp};
+  c64 *p, *pobs;
+  ARENA_ALLOC(tmp, p, n);
+  ARENA_ALLOC(tmp, pobs, n_pts);
+  int r = objective_forward(P, beta, dir, pts_host, n_pts, opts, J, p, pobs, info_f, s);
+  if (r) return r;
+  if (p_out) {
+    hipLaunchKernelGGL(k_copy, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, p_out);
+    BEM_LAUNCH_CHECK();
+  }
+  if (grad && (r = objective_backward(P, beta, p, pobs, pts_host, n_pts, opts, grad, info_a, s)))
+    return r;
   BEM_HIP_TRY(hipStreamSynchronize(s));
   return 0;
 }

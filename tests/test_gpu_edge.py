@@ -196,9 +196,16 @@ def test_deep_tree_hybrid_passes():
     rows = np.sort(rng.choice(len(T), 16, replace=False))
     ref = obem.matvec(g, k, 1j / k, p, q, rows=rows, block=16)
     yv = complex_normal(rng, len(T))
+    _log(f"  orders f64 {st['order64'][2:]} f32 {st['order32'][2:]}")
+    done = set()
     for depth in (0, 1, 2, 3):
         for prec, tol in ((0, 1e-6), (1, 1e-4)):
-            plan.set_tuning(prec=prec, direct_depth=depth)
+            try:
+                plan.set_tuning(prec=prec, direct_depth=depth)
+            except RuntimeError:
+                # depths whose operators would pass the memory cap are not built
+                continue
+            done.add((depth, prec))
             y = plan.matvec(torch.from_numpy(p), torch.from_numpy(q), prec=prec).cpu().numpy()
             e = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
             u, w = plan.matvec_adjoint(torch.from_numpy(yv), prec=prec)
@@ -209,3 +216,4 @@ def test_deep_tree_hybrid_passes():
             _log(f"  depth {depth} prec {prec}: rows {e:.2e}, dot test {dot:.1e}")
             assert e < tol
             assert dot < (1e-12 if prec == 0 else 1e-5)
+    assert {(1, 0), (2, 0), (1, 1), (2, 1), (3, 1)} <= done

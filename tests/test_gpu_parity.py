@@ -311,3 +311,34 @@ def test_eval_field_against_oracle(sphere1280, plan1280):
     Kh, Sh = solve.represent_blocks(g, k, pts)
     assert _rel(rp.cpu().numpy(), Kh.conj().T @ c) < 1e-13
     assert _rel(rq.cpu().numpy(), -(Sh.conj().T @ c)) < 1e-13
+
+
+def test_order_calibration_meets_its_tolerance(sphere1280):
+    """fmm_tol: the plan raises or lowers its float64 orders until the
+    sampled error on white-noise and on plane-wave densities is below 0.7
+    tol; the oracle's own rows confirm it for both kinds of density."""
+    import torch
+    bem = _lib()
+    V, T, g, k, Mp, Mq = sphere1280
+    rng = np.random.default_rng(9)
+    p, q = complex_normal(rng, len(T)), complex_normal(rng, len(T))
+    d = np.array([0.3, -0.5, 0.81])
+    d /= np.linalg.norm(d)
+    ph = np.exp(1j * k * (g.cen @ d))
+    ps, qs = ph, 1j * k * (g.normal @ d) * ph
+    prev = None
+    for tol in (1e-4, 1e-6, 1e-9):
+        plan = bem.Plan(bem.Problem(V, T, k, leaf_cap=32, fmm_tol=tol))
+        st = plan.stats()
+        ew = _rel(plan.matvec(torch.from_numpy(p), torch.from_numpy(q)).cpu().numpy(),
+                  Mp @ p + Mq @ q)
+        es = _rel(plan.matvec(torch.from_numpy(ps), torch.from_numpy(qs)).cpu().numpy(),
+                  Mp @ ps + Mq @ qs)
+        _log(f"  tol {tol:.0e}: orders {st['order64'][2:]}, estimates white "
+             f"{st['fmm_err64']:.2e} smooth {st['fmm_err64_smooth']:.2e}; oracle white {ew:.2e} "
+             f"smooth {es:.2e}")
+        assert st["fmm_err64"] < 0.7 * tol and st["fmm_err64_smooth"] < 0.7 * tol
+        assert ew < tol and es < tol
+        if prev is not None:
+            assert st["order64"][st["leaf_level"]] > prev
+        prev = st["order64"][st["leaf_level"]]
