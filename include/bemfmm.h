@@ -190,6 +190,20 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* stats);
 int bem_fmm_matvec(bem_plan* plan, int prob, int prec, const void* p, const void* q,
                    void* y, int nrhs, void* stream);
 
+/* bem_fmm_matvec without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): same arguments, operator, kernels and results, but the
+ * product's own buffers (sorted densities, near-field sums, expansions of
+ * every level, per-pair M2L results) are laid out in the library's static
+ * device array of 64 MiB per device (held until the process ends) instead of
+ * the plan's buffers.  BEM_E_INVALID, with a message naming the sizes, when a
+ * problem's buffers need more than that (about N <= 5000 in float64 and
+ * N <= 20000 in float32 on spheres).  All calls on one device share that
+ * device's array: calls that overlap on one device (other streams, other
+ * threads) race.  Stage profiling is skipped for these calls. */
+int bem_fmm_matvec_noalloc(bem_plan* plan, int prob, int prec, const void* p, const void* q,
+                           void* y, int nrhs, void* stream);
+
 /* Exact algebraic adjoint of bem_fmm_matvec: the operator of the adjoint
  * problem (Sec. 2.2, Eq. danseiajohel, which the paper solves with the same
  * boundary operator as the state problem), conjugate-transposed in its

@@ -29,6 +29,7 @@ STATUS = {0: "BEM_OK", -1: "BEM_E_INVALID", -2: "BEM_E_OOM", -3: "BEM_E_HIP",
           -4: "BEM_E_NOCONV", -5: "BEM_E_BREAKDOWN", -6: "BEM_E_NAN"}
 
 EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm_matvec",
+           "bem_fmm_matvec_noalloc",
            "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
            "bem_plane_wave_rhs", "bem_eval_field",
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_objective_forward",
@@ -101,6 +102,7 @@ def load_library(path: str = LIB_PATH):
     lib.bem_plan_destroy.argtypes = [vp]
     lib.bem_plan_get_stats.argtypes = [vp, i32, ctypes.POINTER(_Stats)]
     lib.bem_fmm_matvec.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp]
+    lib.bem_fmm_matvec_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp]
     lib.bem_fmm_matvec_adjoint.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp]
     lib.bem_gmres_solve.argtypes = [vp, i32, vp, i32, vp, vp, ctypes.POINTER(_Opts),
                                     ctypes.POINTER(_Info), vp]

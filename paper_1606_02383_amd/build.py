@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libbemfmm.so")
-SOURCES = ["tree.hip", "nearfield.hip", "operators.hip", "fmm.hip", "solver.hip", "capi.hip"]
+SOURCES = ["tree.hip", "nearfield.hip", "operators.hip", "fmm.hip", "solver.hip", "scratch.hip",
+           "capi.hip"]
 
 
 def _hipcc():

@@ -328,6 +328,12 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
     destroy_plan(plan);
     return fail(BEM_E_HIP, "stream creation failed");
   }
+  // device address of the allocation-free product's static buffer (once per
+  // device, this device current)
+  if (int r = scratch_init_current_device()) {
+    destroy_plan(plan);
+    return r;
+  }
   auto build_one = [&](const bem_problem& q, int leaf_level, Problem** outp) -> int {
     Problem* P = new Problem();
     P->side = plan->side;
@@ -427,6 +433,18 @@ int bem_fmm_matvec(bem_plan* plan, int prob, int prec, const void* p, const void
     if (r) return r;
   }
   return BEM_OK;
+}
+
+int bem_fmm_matvec_noalloc(bem_plan* plan, int prob, int prec, const void* p, const void* q,
+                           void* y, int nrhs, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P) return fail(BEM_E_INVALID, "bad plan or problem index");
+  if (!y) return fail(BEM_E_INVALID, "y is NULL");
+  if (y == p || y == q) return fail(BEM_E_INVALID, "y aliases an input");
+  if (nrhs < 1) return fail(BEM_E_INVALID, "nrhs < 1");
+  if (prec != BEM_C128 && prec != BEM_C64) return fail(BEM_E_INVALID, "bad precision");
+  return fmm_matvec_noalloc(*P, prec == BEM_C128 ? 0 : 1, (const c64*)p, (const c64*)q, (c64*)y,
+                            nrhs, (hipStream_t)stream);
 }
 
 int bem_fmm_matvec_adjoint(bem_plan* plan, int prob, int prec, const void* y, void* u, void* w,

@@ -916,19 +916,11 @@ __global__ void k_geo_to_float(const double* __restrict__ g, int64_t cnt, float*
 
 template <typename R>
 int alloc_exec(const Problem& P, const PrecisionData<R>& D, ExecBuf<R>& X, DevArena& arena) {
-  for (int l = 2; l <= P.L; ++l) {
-    ARENA_ALLOC(arena, X.M[l], (int64_t)P.nbox[l] * D.ncoef[l]);
-    ARENA_ALLOC(arena, X.Lc[l], (int64_t)P.nbox[l] * D.ncoef[l]);
-  }
-  ARENA_ALLOC(arena, X.cbuf, D.cbuf_count);
-  ARENA_ALLOC(arena, X.cbufL, D.cbufL_count);
-  ARENA_ALLOC(arena, X.ps, P.n);
-  ARENA_ALLOC(arena, X.qs, P.n);
-  ARENA_ALLOC(arena, X.ys, P.n);
-  ARENA_ALLOC(arena, X.ys2, P.n);
-  ARENA_ALLOC(arena, X.p64s, P.n);
-  ARENA_ALLOC(arena, X.q64s, P.n);
-  return 0;
+  int r = 0;
+  exec_buffers(P, D, X, [&](auto*& ptr, int64_t count) {
+    if (!r) r = arena.alloc((void**)&ptr, sizeof(*ptr) * (size_t)count);
+  });
+  return r;
 }
 template int alloc_exec<float>(const Problem&, const PrecisionData<float>&, ExecBuf<float>&,
                                DevArena&);

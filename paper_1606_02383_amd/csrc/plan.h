@@ -237,6 +237,25 @@ enum {
   SCHED_LEAF_THEN_P2P = 4, SCHED_COUNT
 };
 
+// Every buffer of a product's ExecBuf with its element count, in one fixed
+// order: f(pointer reference, count).  The plan's allocation and the
+// allocation-free product's layout in static device memory both walk it.
+template <typename R, typename F>
+void exec_buffers(const Problem& P, const PrecisionData<R>& D, ExecBuf<R>& X, F&& f) {
+  for (int l = 2; l <= P.L; ++l) {
+    f(X.M[l], (int64_t)P.nbox[l] * D.ncoef[l]);
+    f(X.Lc[l], (int64_t)P.nbox[l] * D.ncoef[l]);
+  }
+  f(X.cbuf, D.cbuf_count);
+  f(X.cbufL, D.cbufL_count);
+  f(X.ps, P.n);
+  f(X.qs, P.n);
+  f(X.ys, P.n);
+  f(X.ys2, P.n);
+  f(X.p64s, P.n);
+  f(X.q64s, P.n);
+}
+
 // ---- host entry points implemented in the .hip translation units ----
 int build_geometry_and_tree(Problem& P, const double* vert, int64_t n_vert, const int32_t* tri,
                             hipStream_t s);
@@ -297,6 +316,12 @@ int fmm_apply_batch(const std::vector<BatchItem<R>>& items, bool adj, const Batc
 int sort_pairs_u64(uint64_t* keys, int* vals, int n, int nbits, DevArena& scratch,
                    hipStream_t s);
 int exclusive_scan(const int* in, int* out, int n, int* total, DevArena& scratch, hipStream_t s);
+
+// allocation-free product (scratch.hip): the product buffers in the
+// library's static device array instead of the plan's
+int scratch_init_current_device();
+int fmm_matvec_noalloc(Problem& P, int prec, const c64* p, const c64* q, c64* y, int nrhs,
+                       hipStream_t s);
 
 // solver helpers
 int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x,
