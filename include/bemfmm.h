@@ -153,7 +153,9 @@ typedef struct {
                               field started after it, 3 as 0 with the near
                               field started after the upward pass, 4 as 0
                               with the near field started after the leaf
-                              multipoles, behind the leaf-level M2L         */
+                              multipoles, behind the leaf-level M2L, 5
+                              every stage on the caller's stream, one after
+                              another                                       */
   int32_t p2p_grid[2];     /* near-field workgroups (float64 / float32): 0 one
                               per leaf, else a grid-stride launch of that
                               many (chosen with the schedule)               */
@@ -335,7 +337,7 @@ int bem_near_export(bem_plan* plan, int prob, void* ptr, void* col, int64_t* n_n
 
 /* Overrides the choices made by timing at plan creation for problem `prob`
  * and precision prec (BEM_C128 / BEM_C64), see bem_plan_stats: stream
- * schedule (0..4), near-field and leaf-level M2L grids (0: one workgroup per
+ * schedule (0..5), near-field and leaf-level M2L grids (0: one workgroup per
  * leaf / tile, else a grid-stride launch of that many) and direct
  * translation depth (0 .. the depth built).  A negative value keeps the
  * current choice.  Products agree up to rounding whatever the choice.

@@ -188,15 +188,17 @@ static int tune_schedule(Problem& P, hipStream_t s) {
 namespace bemfmm {
 
 // Order calibration of one precision.  The level rule's orders are shifted
-// (every level by the same amount) until the sampled relative error of the
-// product, the larger of its white-noise and plane-wave errors, is below
-// 0.7 of the tolerance (the factor covers the spread of the sampled
-// estimate).  The float64 orders may also move below the rule; the
-// float32 ones are only raised (the mixed-precision refinement's step count
-// rests on the rule's float32 accuracy).  Error per order step: ~x1.9 on the
-// workloads measured; a step up is estimated with that rate and, when it
-// spans several orders, one order less is tried; a step down is estimated
-// with 2.2 and checked.
+// until the sampled relative error of the product, the larger of its
+// white-noise and plane-wave errors, is below 0.7 of the tolerance (the
+// factor covers the spread of the sampled estimate): all levels by the same
+// amount first (error per order step: ~x1.9 on the workloads measured, so a
+// step up is estimated with that rate and a step down with 2.2, then
+// checked), then the leaf level alone and the coarser levels alone are
+// lowered one order at a time while the target still holds (the leaf level
+// holds most of the pairs, so its order sets most of the cost).  The float64
+// orders may move below the rule; the float32 ones are only raised (the
+// mixed-precision refinement's step count rests on the rule's float32
+// accuracy).
 template <typename R>
 static int calibrate_one(Problem& P, PrecisionData<R>& D, double tol, bool may_lower,
                          hipStream_t s) {
@@ -211,43 +213,62 @@ static int calibrate_one(Problem& P, PrecisionData<R>& D, double tol, bool may_l
     for (int l = 2; l <= P.L; ++l) pm = std::max(pm, D.order[l]);
     return pm;
   };
-  int shift = D.shift;
+  auto lowest = [&]() {
+    int pm = 1 << 20;
+    for (int l = 2; l <= P.L; ++l) pm = std::min(pm, D.order[l]);
+    return pm;
+  };
+  int sc = D.shift_c, sl = D.shift;
+  auto build = [&](int c, int l, double* ee) -> int {
+    int rr = rebuild_precision<R>(P, D, c, l, s);
+    if (!rr) rr = measure_error<R>(P, D, s, ee);
+    return rr;
+  };
   if (e > target) {
     double prev = e;
-    int last_step = 0;
     while (e > target && top() < std::min(P.p_max, 40)) {
       const int step = std::max(1, (int)std::ceil(std::log(e / target) / std::log(1.9)));
-      shift += step;
-      last_step = step;
-      if ((r = rebuild_precision<R>(P, D, shift, s))) return r;
-      if ((r = measure_error<R>(P, D, s, &e))) return r;
+      sc += step;
+      sl += step;
+      if ((r = build(sc, sl, &e))) return r;
       if (e > 0.8 * prev && e > target) break;  // rounding floor: higher orders do not help
       prev = e;
     }
-    // a step of more than one order may have overshot: one order less?
-    if (e <= target && last_step > 1) {
-      double e1 = 0;
-      if ((r = rebuild_precision<R>(P, D, shift - 1, s))) return r;
-      if ((r = measure_error<R>(P, D, s, &e1))) return r;
-      if (e1 > target) {
-        if ((r = rebuild_precision<R>(P, D, shift, s))) return r;
-        if ((r = measure_error<R>(P, D, s, &e))) return r;
+    if (e > target) return 0;  // the best the orders allow
+  } else if (may_lower && e > 0) {
+    const int down = (int)std::floor(std::log(target / e) / std::log(2.2));
+    if (down >= 1) {
+      double e2 = 0;
+      if ((r = build(sc - down, sl - down, &e2))) return r;
+      if (e2 <= target) {
+        sc -= down;
+        sl -= down;
+        e = e2;
       }
     }
-    return 0;
   }
-  if (!may_lower || e <= 0) return 0;
-  const int down = (int)std::floor(std::log(target / e) / std::log(2.2));
-  if (down < 1) return 0;
-  const int shift0 = shift;
-  for (int t = down; t >= 1; --t) {
-    if ((r = rebuild_precision<R>(P, D, shift0 - t, s))) return r;
-    if ((r = measure_error<R>(P, D, s, &e))) return r;
-    if (e <= target) return 0;
+  // one order less on the leaf level alone, then on the coarser levels
+  // alone, while the target holds
+  bool built_is_best = D.shift_c == sc && D.shift == sl;
+  for (int which = 0; which < 2; ++which) {
+    if (which == 1 && P.L <= 2) break;  // no levels above the leaves
+    for (;;) {
+      const int nc = sc - (which == 1 ? 1 : 0), nl = sl - (which == 0 ? 1 : 0);
+      if (!may_lower && (nc < 0 || nl < 0)) break;
+      if (lowest() <= 1) break;
+      const auto before = D.order;
+      double e2 = 0;
+      if ((r = build(nc, nl, &e2))) return r;
+      built_is_best = e2 <= target;
+      if (D.order == before) break;  // no order moved (all at their bound)
+      if (!built_is_best) break;
+      sc = nc;
+      sl = nl;
+      e = e2;
+    }
   }
-  // none of the lower orders met the target: back to where it did
-  if ((r = rebuild_precision<R>(P, D, shift0, s))) return r;
-  return measure_error<R>(P, D, s, &e);
+  if (!built_is_best && (r = build(sc, sl, &e))) return r;
+  return 0;
 }
 
 int calibrate_orders(Problem& P, hipStream_t s) {

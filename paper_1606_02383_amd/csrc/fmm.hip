@@ -1859,9 +1859,11 @@ int fmm_apply_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c64* p, co
   const int nleaf = P.nbox[L];
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
-  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
-  // every stage on this stream (direct sum, or a serial stage profile)
-  const bool one_stream = P.direct || (P.prof_on && P.prof_serial);
+  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL ||
+                         sched == SCHED_SERIAL || P.direct;
+  // every stage on this stream (direct sum, serial schedule or serial stage
+  // profile)
+  const bool one_stream = P.direct || sched == SCHED_SERIAL || (P.prof_on && P.prof_serial);
   // gather and P2M in one launch when a leaf's values fit in LDS and the
   // near field does not start right after the gather (it would start later:
   // measured slower); its completion (event ev_fork2) forks the leaf M2L
@@ -1983,9 +1985,11 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
   const int nleaf = P.nbox[L];
   const int sched = P.direct ? 0 : P.sched[sizeof(R) == 4];
   const int cap = P.direct ? 0 : P.p2p_cap[sizeof(R) == 4];
-  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL || P.direct;
-  // every stage on this stream (direct sum, or a serial stage profile)
-  const bool one_stream = P.direct || (P.prof_on && P.prof_serial);
+  const bool p2p_first = sched == SCHED_CONCURRENT || sched == SCHED_LEAF_SERIAL ||
+                         sched == SCHED_SERIAL || P.direct;
+  // every stage on this stream (direct sum, serial schedule or serial stage
+  // profile)
+  const bool one_stream = P.direct || sched == SCHED_SERIAL || (P.prof_on && P.prof_serial);
   // gather and L2P^H in one launch under the forward product's conditions
   const size_t lds_fused = (size_t)P.max_leaf * sizeof(cplx<R>);
   const bool fused = !P.direct && !p2p_first && lds_fused <= FUSED_LDS_MAX;

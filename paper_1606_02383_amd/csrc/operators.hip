@@ -681,8 +681,9 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
   const int L = P.L;
   const double k = P.k;
   for (int l = 2; l <= L; ++l) {
-    D.order[l] = is64 ? auto_order(k, P.h[l], P.order64_req, 12, 8, D.shift, P.p_max)
-                      : auto_order(k, P.h[l], P.order32_req, 7, 3, D.shift, P.p_max);
+    const int sh = l == L ? D.shift : D.shift_c;
+    D.order[l] = is64 ? auto_order(k, P.h[l], P.order64_req, 12, 8, sh, P.p_max)
+                      : auto_order(k, P.h[l], P.order32_req, 7, 3, sh, P.p_max);
     D.ncoef[l] = (D.order[l] + 1) * (D.order[l] + 1);
   }
   // ---- M2L: one matrix per offset present at each level ----
@@ -928,7 +929,7 @@ template int alloc_exec<double>(const Problem&, const PrecisionData<double>&, Ex
                                 DevArena&);
 
 template <typename R>
-int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift, hipStream_t s) {
+int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift_c, int shift_l, hipStream_t s) {
   BEM_HIP_TRY(hipStreamSynchronize(s));  // no product still uses the old data
   PrecisionData<R> keep;
   keep.near_cp = D.near_cp;
@@ -949,7 +950,8 @@ int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift, hipStream_t s)
   D.cbuf_count = D.cbufL_count = 0;
   D.p2m = D.p2m_p = D.l2p = nullptr;
   D.X = ExecBuf<R>{};
-  D.shift = shift;
+  D.shift = shift_l;
+  D.shift_c = shift_c;
   DevArena scratch;
   struct Guard {
     DevArena& a;
@@ -960,8 +962,8 @@ int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift, hipStream_t s)
   if (!r) BEM_HIP_TRY(hipStreamSynchronize(s));
   return r;
 }
-template int rebuild_precision<float>(Problem&, PrecisionData<float>&, int, hipStream_t);
-template int rebuild_precision<double>(Problem&, PrecisionData<double>&, int, hipStream_t);
+template int rebuild_precision<float>(Problem&, PrecisionData<float>&, int, int, hipStream_t);
+template int rebuild_precision<double>(Problem&, PrecisionData<double>&, int, int, hipStream_t);
 
 int build_operators(Problem& P, hipStream_t s) {
   DevArena scratch;

@@ -91,7 +91,8 @@ struct PrecisionData {
   // operators, tiles, reduction lists, P2M/L2P matrices and the product
   // buffers X): released and rebuilt when the orders are recalibrated
   DevArena ops;
-  int shift = 0;       // order shift applied to the level rule (calibration)
+  int shift = 0;       // order shifts applied to the level rule (calibration):
+  int shift_c = 0;     //   the leaf level's and the coarser levels'
   double err = -1.0;   // sampled relative error of the product on white-noise
                        // densities (< 0: not measured)
   double err_smooth = -1.0;  // the same on a plane-wave density
@@ -229,12 +230,15 @@ int prof_pair(Problem& P, int slot);  // a (start, end) pair for a launch's own 
 //   SCHED_P2P_AFTER_UP as SCHED_CONCURRENT, with P2P started after the
 //                     upward pass (whose small launches then do not wait
 //                     for compute units behind it)
+//   SCHED_SERIAL      every stage on the caller's stream, one after another
+//                     (no stage shares the GPU: fastest when one large
+//                     launch dominates, e.g. the float64 leaf-level M2L)
 //   SCHED_LEAF_THEN_P2P as SCHED_CONCURRENT, with P2P forked after the P2M,
 //                     behind the leaf-level M2L (whose workgroups then take
 //                     their place on the compute units first)
 enum {
   SCHED_CONCURRENT = 0, SCHED_LEAF_SERIAL = 1, SCHED_LEAF_FIRST = 2, SCHED_P2P_AFTER_UP = 3,
-  SCHED_LEAF_THEN_P2P = 4, SCHED_COUNT
+  SCHED_LEAF_THEN_P2P = 4, SCHED_SERIAL = 5, SCHED_COUNT
 };
 
 // Every buffer of a product's ExecBuf with its element count, in one fixed
@@ -262,9 +266,10 @@ int build_geometry_and_tree(Problem& P, const double* vert, int64_t n_vert, cons
 int build_near_field(Problem& P, hipStream_t s);
 int build_operators(Problem& P, hipStream_t s);
 // Rebuild the order-dependent data of one precision with the level rule
-// shifted by `shift` (release of the old data included).
+// shifted by shift_c on the levels above the leaves and shift_l on the leaf
+// level (release of the old data included).
 template <typename R>
-int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift, hipStream_t s);
+int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift_c, int shift_l, hipStream_t s);
 // Sampled relative error of one product against the exact discrete operator:
 // rows spread over the mesh, seeded pseudo-random p and q, reference rows
 // summed directly in float64 (rule points, near corrections, diagonal).

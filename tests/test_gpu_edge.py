@@ -130,7 +130,7 @@ def test_multiple_rhs_columns():
 
 
 def test_every_tuning_choice_gives_the_same_products():
-    """Stream schedules (all five), capped grids and direct leaf <-> ancestor
+    """Stream schedules (all six), capped grids and direct leaf <-> ancestor
     translations run the same arithmetic in another order or another
     factorisation: forward and adjoint products agree to rounding and to the
     expansion truncation."""
@@ -141,12 +141,12 @@ def test_every_tuning_choice_gives_the_same_products():
     st = plan.stats()
     _log(f"case: tuning choices (tuned schedule {st['schedule']} grids {st['p2p_grid']} "
          f"{st['m2l_grid']} direct {st['direct_depth']}, leaf level {st['leaf_level']})")
-    assert all(0 <= c < 5 for c in st["schedule"])
+    assert all(0 <= c < 6 for c in st["schedule"])
     rng = np.random.default_rng(17)
     p = torch.from_numpy(complex_normal(rng, len(T)))
     q = torch.from_numpy(complex_normal(rng, len(T)))
     ref = {}
-    choices = [dict(schedule=c, p2p_grid=0, m2l_grid=0, direct_depth=0) for c in range(5)]
+    choices = [dict(schedule=c, p2p_grid=0, m2l_grid=0, direct_depth=0) for c in range(6)]
     choices += [dict(schedule=0, p2p_grid=512, m2l_grid=256, direct_depth=0),
                 dict(schedule=3, p2p_grid=0, m2l_grid=0, direct_depth=3),
                 dict(schedule=1, p2p_grid=1024, m2l_grid=0, direct_depth=2),
@@ -172,7 +172,7 @@ def test_every_tuning_choice_gives_the_same_products():
             _log(f"  {ch2} prec {prec}: {max(errs):.1e} (tol {tol:.0e})")
             assert max(errs) < tol
     with pytest.raises(RuntimeError, match="INVALID"):
-        plan.set_tuning(schedule=5)
+        plan.set_tuning(schedule=6)
     with pytest.raises(RuntimeError, match="INVALID"):
         plan.set_tuning(direct_depth=9)
 

@@ -97,14 +97,14 @@ def test_rigid_paths_under_every_schedule():
     n = len(T)
     plan = bem.Plan(bem.Problem(V, T, 1.0, leaf_cap=16))
     st = plan.stats()
-    _log(f"case: rigid paths, leaf level {st['leaf_level']}, schedules 0..4")
+    _log(f"case: rigid paths, leaf level {st['leaf_level']}, schedules 0..5")
     assert st["n_m2l"][st["leaf_level"]] > 0
     rng = np.random.default_rng(37)
     p, yv = complex_normal(rng, n), complex_normal(rng, n)
     P, Y = torch.from_numpy(p), torch.from_numpy(yv)
     ref_y, ref_u = Mp @ p, Mp.conj().T @ yv
     for prec, tol in ((bem.BEM_C128, 1e-6), (bem.BEM_C64, 1e-4)):
-        for sched in range(5):
+        for sched in range(6):
             for depth in (0, 1):
                 try:
                     plan.set_tuning(prec, schedule=sched, direct_depth=depth)
