@@ -252,6 +252,14 @@ int bem_gmres_solve_batch(bem_plan* plan, int n_sys, const int32_t* probs,
  * b_i = p_inc(x_i) + alpha dp_inc/dn(x_i) (device complex128 out). */
 int bem_plane_wave_rhs(bem_plan* plan, int prob, const double* dir3, void* b, void* stream);
 
+/* Right-hand side of point sources of intensity A_m at y_m (the source term
+ * of the paper's forward problem, Eq. hel, whose incident field is
+ * p_inc = sum_m A_m G(x - y_m)):  b_i = p_inc(x_i) + alpha dp_inc/dn(x_i).
+ * src: device float64 n_src x 3 (off the boundary); amp: device complex128
+ * n_src; b: device complex128 n_tri out (caller order).  n_src >= 1. */
+int bem_point_source_rhs(bem_plan* plan, int prob, const double* src, const void* amp, int n_src,
+                         void* b, void* stream);
+
 /* Field at exterior points by the integral representation (solver step 5,
  * Sec. 2.3): out_m = inc_m + sum_j [int_j dG/dn_y p_j - int_j G q_j] with the
  * 3-point rule, inc_m = exp(i k d.x_m) if dir3 != NULL else 0.  pts: device

@@ -384,3 +384,17 @@ def plane_wave_rhs(geom: Geometry, k: float, alpha: complex, d):
     d = np.asarray(d, dtype=np.float64)
     ph = np.exp(1j * k * (geom.cen @ d))
     return ph + alpha * (1j * k * (geom.normal @ d)) * ph
+
+
+def point_source_rhs(geom: Geometry, k: float, alpha: complex, src, amp):
+    """Right-hand side of point sources of intensity A_m at y_m (the paper's
+    forward problem, Eq. hel: Helmholtz equation with sum_m A_m delta(x - y_m),
+    whose incident field is p_inc(x) = sum_m A_m G(x - y_m)):
+    b_i = p_inc(x_i) + alpha dp_inc/dn(x_i), dp_inc/dn = sum_m A_m dG/dn_x."""
+    src = np.asarray(src, dtype=np.float64).reshape(-1, 3)
+    amp = np.asarray(amp, dtype=np.complex128).reshape(-1)
+    x = geom.cen[:, None, :]
+    nx = geom.normal[:, None, :]
+    y = src[None, :, :]
+    G, _, Gx, _ = kernels(x, nx, y, np.zeros_like(y), k)
+    return (G * amp[None, :]).sum(1) + alpha * (Gx * amp[None, :]).sum(1)

@@ -106,6 +106,14 @@ def represent(geom: bem.Geometry, k: float, pts, p, q, d):
     return pinc + Kh @ p - Sh @ q
 
 
+def point_source_field(k: float, pts, src, amp):
+    """Incident field of point sources, sum_m A_m G(x - y_m) (Eq. hel)."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    src = np.asarray(src, dtype=np.float64).reshape(-1, 3)
+    r = np.linalg.norm(pts[:, None, :] - src[None, :, :], axis=2)
+    return (np.exp(1j * k * r) / (4.0 * np.pi * r) * np.asarray(amp)[None, :]).sum(1)
+
+
 def objective_and_gradient(geom: bem.Geometry, k: float, alpha: complex, beta, d, pts,
                            Mp=None, Mq=None):
     """Dense discrete J(beta) and dJ/dRe(beta) + i dJ/dIm(beta).

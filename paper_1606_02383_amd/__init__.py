@@ -31,7 +31,7 @@ STATUS = {0: "BEM_OK", -1: "BEM_E_INVALID", -2: "BEM_E_OOM", -3: "BEM_E_HIP",
 EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm_matvec",
            "bem_fmm_matvec_noalloc",
            "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
-           "bem_plane_wave_rhs", "bem_eval_field",
+           "bem_plane_wave_rhs", "bem_point_source_rhs", "bem_eval_field",
            "bem_eval_field_adjoint", "bem_objective_grad", "bem_objective_forward",
            "bem_objective_backward", "bem_tree_export",
            "bem_leaves_export", "bem_lists_export", "bem_near_export", "bem_plan_set_tuning",
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH):
                                           ctypes.POINTER(vp), ctypes.POINTER(vp),
                                           ctypes.POINTER(_Opts), ctypes.POINTER(_Info), vp]
     lib.bem_plane_wave_rhs.argtypes = [vp, i32, dp, vp, vp]
+    lib.bem_point_source_rhs.argtypes = [vp, i32, vp, vp, i32, vp, vp]
     lib.bem_eval_field.argtypes = [vp, i32, vp, vp, vp, i32, dp, vp, vp]
     lib.bem_eval_field_adjoint.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
     lib.bem_objective_grad.argtypes = [vp, i32, vp, dp, dp, i32, ctypes.POINTER(_Opts), dp, vp,
@@ -329,6 +330,19 @@ class Plan:
         b = self._vec(prob)
         _check(_LIB.bem_plane_wave_rhs(self._h, prob, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                        _ptr(b), _stream()))
+        return b
+
+    def point_source_rhs(self, src, amp, prob=0):
+        """b = p_inc + alpha dp_inc/dn for point sources (src (m, 3), amp (m,))."""
+        import torch
+        src = torch.as_tensor(np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3))
+        src = src.to(self.device)
+        amp = torch.as_tensor(np.asarray(amp, dtype=np.complex128).reshape(-1)).to(self.device)
+        if amp.shape[0] != src.shape[0]:
+            raise ValueError("src and amp differ in length")
+        b = self._vec(prob)
+        _check(_LIB.bem_point_source_rhs(self._h, prob, _ptr(src), _ptr(amp), src.shape[0],
+                                         _ptr(b), _stream()))
         return b
 
     def eval_field(self, p, q, pts, direction=None, prob=0):

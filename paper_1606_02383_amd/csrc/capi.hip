@@ -541,6 +541,13 @@ int bem_plane_wave_rhs(bem_plan* plan, int prob, const double* dir3, void* b, vo
   return plane_wave_rhs(*P, dir3, (c64*)b, (hipStream_t)stream);
 }
 
+int bem_point_source_rhs(bem_plan* plan, int prob, const double* src, const void* amp, int n_src,
+                         void* b, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !src || !amp || !b || n_src < 1) return fail(BEM_E_INVALID, "bad arguments");
+  return point_source_rhs(*P, src, (const c64*)amp, n_src, (c64*)b, (hipStream_t)stream);
+}
+
 int bem_eval_field(bem_plan* plan, int prob, const void* p, const void* q, const double* pts,
                    int n_pts, const double* dir3, void* out, void* stream) {
   Problem* P = get_prob(plan, prob);

@@ -333,6 +333,8 @@ int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x,
                 double tol, int restart, int max_iter, int mode, double inner_tol, int use_x0,
                 void* info, hipStream_t s);
 int plane_wave_rhs(Problem& P, const double* d, c64* b, hipStream_t s);
+int point_source_rhs(Problem& P, const double* src, const c64* amp, int n_src, c64* b,
+                     hipStream_t s);
 int eval_field(Problem& P, const c64* p, const c64* q, const double* pts, int n_pts,
                const double* d, c64* out, hipStream_t s);
 int eval_field_adjoint(Problem& P, const double* pts, int n_pts, const c64* c, c64* rp,

@@ -738,6 +738,42 @@ int plane_wave_rhs(Problem& P, const double* d, c64* b, hipStream_t s) {
 
 constexpr double INV4PI = 0.07957747154594767;
 
+// b_i = sum_m A_m [G(x_i - y_m) + alpha dG/dn_x(x_i - y_m)] at the collocation
+// points (sorted order in, caller order out): the incident field of point
+// sources of intensity A_m (the forward problem's source term, Eq. hel) and
+// alpha times its normal derivative
+__global__ void k_point_sources(const double* __restrict__ g, int64_t n,
+                                const int* __restrict__ perm, double k, double alr, double ali,
+                                const double* __restrict__ src, const c64* __restrict__ amp,
+                                int nsrc, c64* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x0 = g[GEO_CX * n + i], x1 = g[GEO_CY * n + i], x2 = g[GEO_CZ * n + i];
+  const double n0 = g[GEO_NX * n + i], n1 = g[GEO_NY * n + i], n2 = g[GEO_NZ * n + i];
+  c64 acc = mk(0.0, 0.0), accn = mk(0.0, 0.0);
+  for (int m = 0; m < nsrc; ++m) {
+    const double rx = x0 - src[3 * m], ry = x1 - src[3 * m + 1], rz = x2 - src[3 * m + 2];
+    const double r = sqrt(rx * rx + ry * ry + rz * rz), u = 1.0 / r;
+    double sn, cs;
+    sincos(k * r, &sn, &cs);
+    const c64 G = mk(cs * u * INV4PI, sn * u * INV4PI);
+    // dG/dn_x = G (ik - 1/r) (r.n_x) / r
+    const c64 Gx = cscale(cmul(G, mk(-u, k)), (rx * n0 + ry * n1 + rz * n2) * u);
+    cfma(acc, G, amp[m]);
+    cfma(accn, Gx, amp[m]);
+  }
+  cfma(acc, mk(alr, ali), accn);
+  b[perm[i]] = acc;
+}
+
+int point_source_rhs(Problem& P, const double* src, const c64* amp, int n_src, c64* b,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_point_sources, dim3(ceil_div(P.n, 256)), dim3(256), 0, s, P.geo, P.n,
+                     P.perm, P.k, P.alpha.re, P.alpha.im, src, amp, n_src, b);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
 // one block per point: out_m = inc + sum_j sum_q w [G_y p_j - G q_j]
 __global__ void k_eval_field(const double* __restrict__ g, int64_t n, const int* __restrict__ perm,
                              const c64* __restrict__ p, const c64* __restrict__ q,
