@@ -56,3 +56,10 @@ def incident_series(k: float, r, cos_t):
     for n in range(_nmax(k * float(np.max(r)))):
         out += (1j ** n) * (2 * n + 1) * eval_legendre(n, cos_t) * spherical_jn(n, k * r)
     return out
+
+
+def total_field_xyz(k: float, a: float, pts, d):
+    """total_field at Cartesian points for incidence direction d."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    r = np.linalg.norm(pts, axis=1)
+    return total_field(k, a, r, (pts @ np.asarray(d)) / r)

@@ -11,6 +11,9 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 * ``represent`` - the integral representation at exterior points (solver
   step 5, Sec. 2.3):  p(x) = p_inc(x) + sum_j [Khat_j(x) p_j - Shat_j(x) q_j],
   with the 3-point rule (points well separated from the boundary).
+* ``represent_grad`` / ``point_source_grad`` - gradients of the scattered
+  and incident fields at exterior points; ``topological_derivative`` - the
+  paper's T_Omega (Eq. danseitpoderi) from the state and adjoint fields;
 * ``objective_and_gradient`` - J = sum_m |p(x_m)|^2 (Eq. obj with
   f = |p|^2) for an admittance boundary q = sigma p, sigma = -i k beta, and
   its gradient in beta by the discrete adjoint; the pairing
@@ -104,6 +107,63 @@ def represent(geom: bem.Geometry, k: float, pts, p, q, d):
     Kh, Sh = represent_blocks(geom, k, pts)
     pinc = np.exp(1j * k * (np.asarray(pts) @ np.asarray(d)))
     return pinc + Kh @ p - Sh @ q
+
+
+def represent_grad_blocks(geom: bem.Geometry, k: float, pts):
+    """Gradients in x of the representation's kernels (3-point rule):
+    GK (M, N, 3) = grad_x int_j dG/dn_y(x - y), GS (M, N, 3) = grad_x int_j G.
+    With rv = x - y, r = |rv|, G' = G (ik - 1/r), G'' = G ((ik - 1/r)^2 + 1/r^2):
+    grad G = G' rv / r;  grad dG/dn_y = -(G'' - G'/r)(rv.n_y) rv / r^2 - G' n_y / r."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    rv = pts[:, None, None, :] - geom.qpts[None]            # (M, N, 3, 3)
+    r2 = np.einsum("...i,...i->...", rv, rv)
+    r = np.sqrt(r2)
+    ik = 1j * k
+    G = np.exp(ik * r) / (4.0 * np.pi * r)
+    g1 = G * (ik - 1.0 / r)
+    g2 = G * ((ik - 1.0 / r) ** 2 + 1.0 / r2)
+    ny = geom.normal[None, :, None, :]
+    rny = np.einsum("...i,...i->...", rv, ny)
+    w = geom.qw[None, :, :, None]
+    gS = (g1 / r)[..., None] * rv
+    gK = (-(g2 - g1 / r) * rny / r2)[..., None] * rv - (g1 / r)[..., None] * ny
+    return (gK * w).sum(2), (gS * w).sum(2)
+
+
+def represent_grad(geom: bem.Geometry, k: float, pts, p, q):
+    """grad_x of sum_j [Khat_j(x) p_j - Shat_j(x) q_j] (scattered part), (M, 3)."""
+    GK, GS = represent_grad_blocks(geom, k, pts)
+    out = np.einsum("mnc,n->mc", GK, p)
+    if q is not None:
+        out -= np.einsum("mnc,n->mc", GS, q)
+    return out
+
+
+def point_source_grad(k: float, pts, src, amp):
+    """grad of sum_m A_m G(x - y_m), (M, 3)."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    src = np.asarray(src, dtype=np.float64).reshape(-1, 3)
+    rv = pts[:, None, :] - src[None, :, :]
+    r = np.linalg.norm(rv, axis=2)
+    G = np.exp(1j * k * r) / (4.0 * np.pi * r)
+    g1 = G * (1j * k - 1.0 / r)
+    return ((g1 / r * np.asarray(amp)[None, :])[..., None] * rv).sum(1)
+
+
+def topological_derivative(p, gp, pt, gpt, rho_f, rho_s, lam_f, lam_s, omega):
+    """T_Omega at points (Eq. danseitpoderi): appearance of a small elastic
+    sphere (density rho_s, bulk modulus lam_s) in the fluid (rho_f, lam_f)
+    at frequency omega, from the state field p, grad p and the adjoint field
+    pt, grad pt there:
+      Re[3 (rho_s - rho_f) / (2 rho_s + rho_f) grad p . grad pt
+         - (lam_s - lam_f) / (lam_s lam_f) rho_f omega^2 p pt].
+    lam_s = inf, rho_s = inf is the sound-hard (rigid) limit."""
+    if np.isinf(rho_s):
+        cg = 1.5
+    else:
+        cg = 3.0 * (rho_s - rho_f) / (2.0 * rho_s + rho_f)
+    cv = (1.0 / lam_f if np.isinf(lam_s) else (lam_s - lam_f) / (lam_s * lam_f)) * rho_f * omega ** 2
+    return np.real(cg * np.einsum("mc,mc->m", gp, gpt) - cv * p * pt)
 
 
 def point_source_field(k: float, pts, src, amp):
