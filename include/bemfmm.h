@@ -267,6 +267,42 @@ int bem_point_source_rhs(bem_plan* plan, int prob, const double* src, const void
 int bem_eval_field(bem_plan* plan, int prob, const void* p, const void* q, const double* pts,
                    int n_pts, const double* dir3, void* out, void* stream);
 
+/* Total field and its gradient at exterior points (solver step 5, the
+ * integral representation; 3-point rule, so points should lie more than an
+ * element size off the boundary):
+ *   out_m  = inc(x_m) + sum_j [int_j dG/dn_y p_j - int_j G q_j],
+ *   grad_m = grad of the same (3 complex per point, x y z),
+ * inc = exp(i k d.x) if dir3 != NULL, plus sum_s A_s G(x - y_s) for point
+ * sources (src: device float64 n_src x 3, amp: device complex128 n_src; src
+ * NULL for none).  p, q (q may be NULL): device complex128 boundary data;
+ * pts: device float64 n_pts x 3; out: device complex128 n_pts; grad (may be
+ * NULL): device complex128 3 n_pts.  Summed directly over the elements
+ * (cost n_pts x n_tri). */
+int bem_eval_field_grad(bem_plan* plan, int prob, const void* p, const void* q,
+                        const double* pts, int n_pts, const double* dir3, const double* src,
+                        const void* amp, int n_src, void* out, void* grad, void* stream);
+
+/* Fluid and solid constants of the topological derivative: densities
+ * rho_f, rho_s, bulk moduli lam_f, lam_s, angular frequency omega (time
+ * factor exp(-i omega t)).  rho_s = lam_s = +INFINITY is the sound-hard
+ * (rigid) limit. */
+typedef struct {
+  double rho_f, lam_f, rho_s, lam_s, omega;
+} bem_material;
+
+/* Topological derivative for the appearance of a small elastic sphere in
+ * the fluid (Sec. 2.2, Eq. danseitpoderi) at n_pts points, from the state
+ * field p, grad p and the adjoint field pt, grad pt there (as from
+ * bem_eval_field_grad; the adjoint field is the one radiated by point
+ * sources of intensity df/dp at the observation points, Eq. danseiajohel):
+ *   T = Re[3 (rho_s - rho_f) / (2 rho_s + rho_f) grad p . grad pt
+ *          - (lam_s - lam_f) / (lam_s lam_f) rho_f omega^2 p pt].
+ * Device arrays: p, pt complex128 n_pts; grad_p, grad_pt complex128 3 n_pts;
+ * T float64 n_pts out. */
+int bem_topological_derivative(int n_pts, const void* p, const void* grad_p, const void* pt,
+                               const void* grad_pt, const bem_material* mat, double* T,
+                               void* stream);
+
 /* Adjoint of bem_eval_field's boundary part: rp_j = sum_m conj(int_j dG/dn_y
  * (x_m)) c_m, rq_j = -sum_m conj(int_j G(x_m)) c_m.  rq may be NULL. */
 int bem_eval_field_adjoint(bem_plan* plan, int prob, const double* pts, int n_pts,

@@ -32,7 +32,8 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_fmm_matvec_noalloc",
            "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
            "bem_plane_wave_rhs", "bem_point_source_rhs", "bem_eval_field",
-           "bem_eval_field_adjoint", "bem_objective_grad", "bem_objective_forward",
+           "bem_eval_field_adjoint", "bem_eval_field_grad", "bem_topological_derivative",
+           "bem_objective_grad", "bem_objective_forward",
            "bem_objective_backward", "bem_tree_export",
            "bem_leaves_export", "bem_lists_export", "bem_near_export", "bem_plan_set_tuning",
            "bem_profile_start", "bem_profile_serial_start",
@@ -70,6 +71,12 @@ class _Info(ctypes.Structure):
         return dict(iterations=self.iterations, matvec64=self.matvec64, matvec32=self.matvec32,
                     restarts=self.restarts, resid=self.resid, converged=bool(self.converged),
                     hist=list(self.hist[:self.n_hist]))
+
+
+class _Material(ctypes.Structure):
+    _fields_ = [("rho_f", ctypes.c_double), ("lam_f", ctypes.c_double),
+                ("rho_s", ctypes.c_double), ("lam_s", ctypes.c_double),
+                ("omega", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -114,6 +121,9 @@ def load_library(path: str = LIB_PATH):
     lib.bem_point_source_rhs.argtypes = [vp, i32, vp, vp, i32, vp, vp]
     lib.bem_eval_field.argtypes = [vp, i32, vp, vp, vp, i32, dp, vp, vp]
     lib.bem_eval_field_adjoint.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
+    lib.bem_eval_field_grad.argtypes = [vp, i32, vp, vp, vp, i32, dp, vp, vp, i32, vp, vp, vp]
+    lib.bem_topological_derivative.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(_Material),
+                                               vp, vp]
     lib.bem_objective_grad.argtypes = [vp, i32, vp, dp, dp, i32, ctypes.POINTER(_Opts), dp, vp,
                                        vp, ctypes.POINTER(_Info), ctypes.POINTER(_Info), vp]
     lib.bem_objective_forward.argtypes = [vp, i32, vp, dp, dp, i32, ctypes.POINTER(_Opts), dp,
@@ -360,6 +370,33 @@ class Plan:
                                    pts.shape[0], dptr, _ptr(out), _stream()))
         return out
 
+    def eval_field_grad(self, p, q, pts, direction=None, src=None, amp=None, prob=0):
+        """Total field (n_pts,) and its gradient (n_pts, 3) at exterior points:
+        incident plane wave (direction) and/or point sources (src, amp) plus
+        the representation of the boundary data p, q."""
+        import torch
+        p, q = self._in(p, prob), self._in(q, prob)
+        pts = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3))
+        pts = pts.to(self.device)
+        n = pts.shape[0]
+        out = torch.empty(n, dtype=torch.complex128, device=self.device)
+        grad = torch.empty((n, 3), dtype=torch.complex128, device=self.device)
+        dptr = None
+        if direction is not None:
+            d = np.ascontiguousarray(direction, dtype=np.float64)
+            self._keep.append(d)
+            dptr = d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s_t = a_t = None
+        if src is not None:
+            s_t = torch.as_tensor(np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3))
+            s_t = s_t.to(self.device)
+            a_t = torch.as_tensor(amp).to(device=self.device, dtype=torch.complex128)
+            a_t = a_t.reshape(-1).contiguous()
+        _check(_LIB.bem_eval_field_grad(self._h, prob, _ptr(p), _ptr(q), _ptr(pts), n, dptr,
+                                        _ptr(s_t), _ptr(a_t), 0 if s_t is None else s_t.shape[0],
+                                        _ptr(out), _ptr(grad), _stream()))
+        return out, grad
+
     def eval_field_adjoint(self, pts, c, prob=0):
         import torch
         pts = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64)).to(self.device)
@@ -505,6 +542,22 @@ class Plan:
         col = torch.empty(max(nn.value, 1), dtype=torch.int32, device=self.device)
         _check(_LIB.bem_near_export(self._h, prob, _ptr(ptr), _ptr(col), None, _stream()))
         return ptr, col[:nn.value]
+
+
+def topological_derivative(p, grad_p, pt, grad_pt, rho_f=1.0, lam_f=1.0, rho_s=float("inf"),
+                           lam_s=float("inf"), omega=1.0):
+    """T_Omega at points (Eq. danseitpoderi) from the state and adjoint fields
+    and their gradients (device tensors); infinite rho_s, lam_s: sound-hard."""
+    import torch
+    load_library()
+    p, pt = p.contiguous(), pt.contiguous()
+    grad_p, grad_pt = grad_p.contiguous(), grad_pt.contiguous()
+    n = p.shape[0]
+    T = torch.empty(n, dtype=torch.float64, device=p.device)
+    m = _Material(rho_f, lam_f, rho_s, lam_s, omega)
+    _check(_LIB.bem_topological_derivative(n, _ptr(p), _ptr(grad_p), _ptr(pt), _ptr(grad_pt),
+                                           ctypes.byref(m), _ptr(T), _stream()))
+    return T
 
 
 def _objective_function():

@@ -556,6 +556,34 @@ int bem_eval_field(bem_plan* plan, int prob, const void* p, const void* q, const
                     (hipStream_t)stream);
 }
 
+int bem_eval_field_grad(bem_plan* plan, int prob, const void* p, const void* q,
+                        const double* pts, int n_pts, const double* dir3, const double* src,
+                        const void* amp, int n_src, void* out, void* grad, void* stream) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !p || !pts || !out || n_pts < 0) return fail(BEM_E_INVALID, "bad arguments");
+  if (src && (!amp || n_src < 1)) return fail(BEM_E_INVALID, "point sources without amplitudes");
+  return eval_field_grad(*P, (const c64*)p, (const c64*)q, pts, n_pts, dir3, src,
+                         (const c64*)amp, n_src, (c64*)out, (c64*)grad, (hipStream_t)stream);
+}
+
+int bem_topological_derivative(int n_pts, const void* p, const void* grad_p, const void* pt,
+                               const void* grad_pt, const bem_material* mat, double* T,
+                               void* stream) {
+  if (!p || !grad_p || !pt || !grad_pt || !mat || !T || n_pts < 0)
+    return fail(BEM_E_INVALID, "bad arguments");
+  const bem_material& m = *mat;
+  if (!(m.rho_f > 0) || !(m.lam_f > 0) || !(m.rho_s > 0) || !(m.lam_s > 0) || !(m.omega > 0) ||
+      !std::isfinite(m.rho_f) || !std::isfinite(m.lam_f) || !std::isfinite(m.omega))
+    return fail(BEM_E_INVALID, "material constants must be > 0 (solid ones may be +inf)");
+  // 3 (rho_s - rho_f) / (2 rho_s + rho_f) and (Lambda_s - Lambda_f) rho_f omega^2 /
+  // (Lambda_s Lambda_f); infinite solid constants give the sound-hard limits
+  const double cg = std::isinf(m.rho_s) ? 1.5 : 3.0 * (m.rho_s - m.rho_f) / (2.0 * m.rho_s + m.rho_f);
+  const double cv = (std::isinf(m.lam_s) ? 1.0 / m.lam_f : (m.lam_s - m.lam_f) / (m.lam_s * m.lam_f)) *
+                    m.rho_f * m.omega * m.omega;
+  return topological_derivative(n_pts, (const c64*)p, (const c64*)grad_p, (const c64*)pt,
+                                (const c64*)grad_pt, cg, cv, T, (hipStream_t)stream);
+}
+
 int bem_eval_field_adjoint(bem_plan* plan, int prob, const double* pts, int n_pts, const void* c,
                            void* rp, void* rq, void* stream) {
   Problem* P = get_prob(plan, prob);

@@ -337,6 +337,11 @@ int point_source_rhs(Problem& P, const double* src, const c64* amp, int n_src, c
                      hipStream_t s);
 int eval_field(Problem& P, const c64* p, const c64* q, const double* pts, int n_pts,
                const double* d, c64* out, hipStream_t s);
+int eval_field_grad(Problem& P, const c64* p, const c64* q, const double* pts, int n_pts,
+                    const double* d, const double* src, const c64* amp, int n_src, c64* out,
+                    c64* grad, hipStream_t s);
+int topological_derivative(int n, const c64* p, const c64* gp, const c64* pt, const c64* gpt,
+                           double cg, double cv, double* T, hipStream_t s);
 int eval_field_adjoint(Problem& P, const double* pts, int n_pts, const c64* c, c64* rp,
                        c64* rq, hipStream_t s);
 void release_workspace(Problem& P);

@@ -825,6 +825,153 @@ __global__ void k_eval_field(const double* __restrict__ g, int64_t n, const int*
   }
 }
 
+// Total field and its gradient at points (solver step 5: the integral
+// representation, 3-point rule, off the boundary), one thread per point,
+// 256 points per block, source elements staged through LDS in chunks:
+//   p(x) = inc(x) + sum_j [int_j dG/dn_y(x - y) p_j - int_j G(x - y) q_j]
+// with rv = x - y, u = 1/|rv|, G' = G (ik - u), G'' = G ((ik - u)^2 + u^2):
+//   grad G = G' u rv,  grad dG/dn_y = -(G'' - G' u)(rv.n_y) u^2 rv - G' u n_y.
+// The incident part: a unit plane wave exp(i k d.x) (has_pw) plus point
+// sources sum_m A_m G(x - y_m) (n_src of them).
+constexpr int FG_CHUNK = 128;
+__global__ void __launch_bounds__(256)
+    k_field_grad(const double* __restrict__ g, int64_t n, const int* __restrict__ perm,
+                 const c64* __restrict__ p, const c64* __restrict__ q,
+                 const double* __restrict__ pts, int npts, double k, int has_pw, double dx,
+                 double dy, double dz, const double* __restrict__ src,
+                 const c64* __restrict__ amp, int nsrc, c64* __restrict__ out,
+                 c64* __restrict__ grad) {
+  __shared__ double s_y[9][FG_CHUNK];
+  __shared__ double s_n[3][FG_CHUNK];
+  __shared__ c64 s_p[FG_CHUNK], s_q[FG_CHUNK];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = t < npts;
+  const double x0 = active ? pts[3 * t] : 0.0, x1 = active ? pts[3 * t + 1] : 0.0,
+               x2 = active ? pts[3 * t + 2] : 0.0;
+  c64 f = mk(0.0, 0.0), f0 = mk(0.0, 0.0), f1 = mk(0.0, 0.0), f2 = mk(0.0, 0.0);
+  for (int64_t c0 = 0; c0 < n; c0 += FG_CHUNK) {
+    const int cnt = (int)std::min<int64_t>(FG_CHUNK, n - c0);
+    __syncthreads();
+    for (int v = threadIdx.x; v < cnt; v += blockDim.x) {
+      const int64_t j = c0 + v;
+      for (int c = 0; c < 9; ++c) s_y[c][v] = g[(GEO_QX0 + c) * n + j];
+      s_n[0][v] = g[GEO_NX * n + j];
+      s_n[1][v] = g[GEO_NY * n + j];
+      s_n[2][v] = g[GEO_NZ * n + j];
+      // per-point weight (rule weight x area / (4 pi)) folded into the densities
+      const double w = g[GEO_AREA * n + j] / 3.0 * INV4PI;
+      const int o = perm[j];
+      s_p[v] = cscale(p[o], w);
+      s_q[v] = q ? cscale(q[o], w) : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (!active) continue;
+    for (int v = 0; v < cnt; ++v) {
+      const double ny0 = s_n[0][v], ny1 = s_n[1][v], ny2 = s_n[2][v];
+      const c64 pv = s_p[v], qv = s_q[v];
+      for (int qq = 0; qq < 3; ++qq) {
+        const double r0 = x0 - s_y[3 * qq][v], r1 = x1 - s_y[3 * qq + 1][v],
+                     r2 = x2 - s_y[3 * qq + 2][v];
+        const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+        const double r = sqrt(rr), u = 1.0 / r;
+        double sn, cs;
+        sincos(k * r, &sn, &cs);
+        const c64 G = mk(cs * u, sn * u);              // without 1/(4 pi): in the weights
+        const c64 a = mk(-u, k);                        // ik - u
+        const c64 g1 = cmul(G, a);                      // G'
+        const c64 g2 = cmul(G, cadd(cmul(a, a), mk(u * u, 0.0)));  // G''
+        const double rny = r0 * ny0 + r1 * ny1 + r2 * ny2;
+        const c64 Gy = cscale(g1, -rny * u);            // dG/dn_y
+        // field: Gy p - G q
+        cfma(f, Gy, pv);
+        cfma(f, cscale(G, -1.0), qv);
+        // gradient: coefficient of rv and of n_y
+        const c64 crv_p = cscale(csub(g2, cscale(g1, u)), -rny * u * u);
+        const c64 cny_p = cscale(g1, -u);
+        const c64 crv_q = cscale(g1, -u);               // -(grad G) = -G' u rv
+        c64 cr = cmul(crv_p, pv), cn = cmul(cny_p, pv);
+        cfma(cr, crv_q, qv);
+        f0 = cadd(f0, cadd(cscale(cr, r0), cscale(cn, ny0)));
+        f1 = cadd(f1, cadd(cscale(cr, r1), cscale(cn, ny1)));
+        f2 = cadd(f2, cadd(cscale(cr, r2), cscale(cn, ny2)));
+      }
+    }
+  }
+  if (!active) return;
+  if (has_pw) {
+    double sn, cs;
+    sincos(k * (dx * x0 + dy * x1 + dz * x2), &sn, &cs);
+    const c64 e = mk(cs, sn), ike = mk(-k * sn, k * cs);
+    f = cadd(f, e);
+    f0 = cadd(f0, cscale(ike, dx));
+    f1 = cadd(f1, cscale(ike, dy));
+    f2 = cadd(f2, cscale(ike, dz));
+  }
+  for (int m = 0; m < nsrc; ++m) {
+    const double r0 = x0 - src[3 * m], r1 = x1 - src[3 * m + 1], r2 = x2 - src[3 * m + 2];
+    const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2), u = 1.0 / r;
+    double sn, cs;
+    sincos(k * r, &sn, &cs);
+    const c64 G = cmul(mk(cs * u * INV4PI, sn * u * INV4PI), amp[m]);
+    const c64 g1u = cscale(cmul(G, mk(-u, k)), u);  // A G' / r
+    f = cadd(f, G);
+    f0 = cadd(f0, cscale(g1u, r0));
+    f1 = cadd(f1, cscale(g1u, r1));
+    f2 = cadd(f2, cscale(g1u, r2));
+  }
+  out[t] = f;
+  if (grad) {
+    grad[3 * t] = f0;
+    grad[3 * t + 1] = f1;
+    grad[3 * t + 2] = f2;
+  }
+}
+
+int eval_field_grad(Problem& P, const c64* p, const c64* q, const double* pts, int n_pts,
+                    const double* d, const double* src, const c64* amp, int n_src, c64* out,
+                    c64* grad, hipStream_t s) {
+  if (n_pts <= 0) return 0;
+  double dx = 0, dy = 0, dz = 0;
+  if (d) {
+    const double nrm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(nrm > 0)) {
+      set_error("zero incidence direction");
+      return -1;
+    }
+    dx = d[0] / nrm;
+    dy = d[1] / nrm;
+    dz = d[2] / nrm;
+  }
+  hipLaunchKernelGGL(k_field_grad, dim3(ceil_div(n_pts, 256)), dim3(256), 0, s, P.geo, P.n,
+                     P.perm, p, q, pts, n_pts, P.k, d ? 1 : 0, dx, dy, dz, src, amp,
+                     src ? n_src : 0, out, grad);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+// Topological derivative (Eq. danseitpoderi), pointwise:
+//   T = Re[cg grad p . grad pt - cv p pt]
+__global__ void k_topological(int n, const c64* __restrict__ p, const c64* __restrict__ gp,
+                              const c64* __restrict__ pt, const c64* __restrict__ gpt, double cg,
+                              double cv, double* __restrict__ T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  c64 dot = cmul(gp[3 * t], gpt[3 * t]);
+  cfma(dot, gp[3 * t + 1], gpt[3 * t + 1]);
+  cfma(dot, gp[3 * t + 2], gpt[3 * t + 2]);
+  const c64 pp = cmul(p[t], pt[t]);
+  T[t] = cg * dot.re - cv * pp.re;
+}
+
+int topological_derivative(int n, const c64* p, const c64* gp, const c64* pt, const c64* gpt,
+                           double cg, double cv, double* T, hipStream_t s) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(k_topological, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, p, gp, pt, gpt,
+                     cg, cv, T);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
 // rp_j = sum_m conj(Khat_mj) c_m,  rq_j = -sum_m conj(Shat_mj) c_m
 __global__ void k_eval_field_adj(const double* __restrict__ g, int64_t n,
                                  const int* __restrict__ perm, const double* __restrict__ pts,
