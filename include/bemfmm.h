@@ -282,6 +282,46 @@ int bem_eval_field_grad(bem_plan* plan, int prob, const void* p, const void* q,
                         const double* pts, int n_pts, const double* dir3, const double* src,
                         const void* amp, int n_src, void* out, void* grad, void* stream);
 
+/* A fixed set of evaluation points (the design-domain lattice on which the
+ * topology loop of Sec. 3 evaluates the state and adjoint fields, step 8)
+ * sorted into an octree on the grid of problem `prob`'s tree, with the
+ * translations from the problem's boxes into the point boxes, for one
+ * precision (BEM_C128 or BEM_C64).  Created once per point set and problem,
+ * reused by every evaluation; it refers to the plan, so destroy it first.
+ * pts: host float64 n_pts x 3 (row-major, copied).  Every point must lie
+ * within two widths of the tree's root cube from that cube (per axis);
+ * BEM_E_INVALID otherwise (and for non-finite coordinates or prec 2).  A
+ * problem without a far field (leaves not wider than the near radius) keeps
+ * the points for the direct sum. */
+typedef struct bem_field_points bem_field_points;
+int bem_field_points_create(bem_plan* plan, int prob, int prec, const double* pts,
+                            int64_t n_pts, void* stream, bem_field_points** out);
+int bem_field_points_destroy(bem_field_points* fp);
+
+typedef struct {
+  int64_t n_pts;
+  int32_t levels;                    /* deepest level (the problem's leaf level) */
+  int32_t n_box[22];     /* point boxes per level */
+  int64_t n_m2l[22];     /* translations into point boxes per level */
+  int32_t order[22];     /* expansion orders (the problem's) */
+  int64_t n_leaf;                    /* point boxes evaluated (leaves) */
+  int64_t n_near_pairs;              /* point x element pairs summed directly */
+  int64_t device_bytes;
+} bem_field_points_stats;
+int bem_field_points_get_stats(const bem_field_points* fp, bem_field_points_stats* st);
+
+/* bem_eval_field_grad on the point set of `fp` (outputs in the order the
+ * points were given), with the boundary sums split by the FMM: translations
+ * of the problem's multipoles into the point boxes, local expansions
+ * evaluated with their gradient at the points, and the 3-point rule summed
+ * directly over the touching leaves.  It differs from the direct sum by the
+ * expansions' truncation (the products' tolerance).  Arguments as
+ * bem_eval_field_grad; stream-ordered, the set's buffers are reused by the
+ * next call (overlapping calls on one set race). */
+int bem_eval_field_grad_fmm(bem_field_points* fp, const void* p, const void* q,
+                            const double* dir3, const double* src, const void* amp, int n_src,
+                            void* out, void* grad, void* stream);
+
 /* Fluid and solid constants of the topological derivative: densities
  * rho_f, rho_s, bulk moduli lam_f, lam_s, angular frequency omega (time
  * factor exp(-i omega t)).  rho_s = lam_s = +INFINITY is the sound-hard

@@ -33,6 +33,8 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_fmm_matvec_adjoint", "bem_gmres_solve", "bem_gmres_solve_batch",
            "bem_plane_wave_rhs", "bem_point_source_rhs", "bem_eval_field",
            "bem_eval_field_adjoint", "bem_eval_field_grad", "bem_topological_derivative",
+           "bem_field_points_create", "bem_field_points_destroy", "bem_field_points_get_stats",
+           "bem_eval_field_grad_fmm",
            "bem_objective_grad", "bem_objective_forward",
            "bem_objective_backward", "bem_tree_export",
            "bem_leaves_export", "bem_lists_export", "bem_near_export", "bem_plan_set_tuning",
@@ -92,6 +94,13 @@ class _Stats(ctypes.Structure):
                 ("fmm_err64_smooth", ctypes.c_double), ("fmm_err32_smooth", ctypes.c_double)]
 
 
+class _PointStats(ctypes.Structure):
+    _fields_ = [("n_pts", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("n_box", ctypes.c_int32 * 22), ("n_m2l", ctypes.c_int64 * 22),
+                ("order", ctypes.c_int32 * 22), ("n_leaf", ctypes.c_int64),
+                ("n_near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
 _LIB = None
 
 
@@ -124,6 +133,10 @@ def load_library(path: str = LIB_PATH):
     lib.bem_eval_field_grad.argtypes = [vp, i32, vp, vp, vp, i32, dp, vp, vp, i32, vp, vp, vp]
     lib.bem_topological_derivative.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(_Material),
                                                vp, vp]
+    lib.bem_field_points_create.argtypes = [vp, i32, i32, dp, i64, vp, ctypes.POINTER(vp)]
+    lib.bem_field_points_destroy.argtypes = [vp]
+    lib.bem_field_points_get_stats.argtypes = [vp, ctypes.POINTER(_PointStats)]
+    lib.bem_eval_field_grad_fmm.argtypes = [vp, vp, vp, dp, vp, vp, i32, vp, vp, vp]
     lib.bem_objective_grad.argtypes = [vp, i32, vp, dp, dp, i32, ctypes.POINTER(_Opts), dp, vp,
                                        vp, ctypes.POINTER(_Info), ctypes.POINTER(_Info), vp]
     lib.bem_objective_forward.argtypes = [vp, i32, vp, dp, dp, i32, ctypes.POINTER(_Opts), dp,
@@ -542,6 +555,67 @@ class Plan:
         col = torch.empty(max(nn.value, 1), dtype=torch.int32, device=self.device)
         _check(_LIB.bem_near_export(self._h, prob, _ptr(ptr), _ptr(col), None, _stream()))
         return ptr, col[:nn.value]
+
+
+class FieldPoints:
+    """A fixed set of evaluation points (e.g. the design-domain lattice) sorted
+    into an octree on the grid of one problem of a plan, for FMM evaluation of
+    the total field and its gradient (bem_eval_field_grad_fmm)."""
+
+    def __init__(self, plan, pts, prec=BEM_C128, prob=0):
+        self._plan = plan  # keeps the plan alive while the points exist
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        self.n = pts.shape[0]
+        self.prob = prob
+        h = ctypes.c_void_p()
+        _check(_LIB.bem_field_points_create(plan._h, prob, int(prec),
+                                            pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            self.n, _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _LIB.bem_field_points_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self):
+        st = _PointStats()
+        _check(_LIB.bem_field_points_get_stats(self._h, ctypes.byref(st)))
+        L = st.levels
+        return dict(n_pts=st.n_pts, levels=L, n_box=list(st.n_box)[:L + 1],
+                    n_m2l=list(st.n_m2l)[:L + 1], order=list(st.order)[:L + 1],
+                    n_leaf=st.n_leaf, n_near_pairs=st.n_near_pairs,
+                    device_bytes=st.device_bytes)
+
+    def eval_field_grad(self, p, q=None, direction=None, src=None, amp=None):
+        """Total field (n,) and gradient (n, 3) at the points, as
+        Plan.eval_field_grad, with the boundary sums by the FMM."""
+        import torch
+        plan = self._plan
+        p, q = plan._in(p, self.prob), plan._in(q, self.prob)
+        out = torch.empty(self.n, dtype=torch.complex128, device=plan.device)
+        grad = torch.empty((self.n, 3), dtype=torch.complex128, device=plan.device)
+        dptr = None
+        if direction is not None:
+            d = np.ascontiguousarray(direction, dtype=np.float64)
+            plan._keep.append(d)
+            dptr = d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s_t = a_t = None
+        if src is not None:
+            s_t = torch.as_tensor(np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3))
+            s_t = s_t.to(plan.device)
+            a_t = torch.as_tensor(amp).to(device=plan.device, dtype=torch.complex128)
+            a_t = a_t.reshape(-1).contiguous()
+        _check(_LIB.bem_eval_field_grad_fmm(self._h, _ptr(p), _ptr(q), dptr, _ptr(s_t),
+                                            _ptr(a_t), 0 if s_t is None else s_t.shape[0],
+                                            _ptr(out), _ptr(grad), _stream()))
+        return out, grad
 
 
 def topological_derivative(p, grad_p, pt, grad_pt, rho_f=1.0, lam_f=1.0, rho_s=float("inf"),

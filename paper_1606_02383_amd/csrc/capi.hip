@@ -566,6 +566,56 @@ int bem_eval_field_grad(bem_plan* plan, int prob, const void* p, const void* q,
                          (const c64*)amp, n_src, (c64*)out, (c64*)grad, (hipStream_t)stream);
 }
 
+struct bem_field_points {
+  FieldPoints* F;
+};
+
+int bem_field_points_create(bem_plan* plan, int prob, int prec, const double* pts,
+                            int64_t n_pts, void* stream, bem_field_points** out) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !out || n_pts < 0 || (n_pts > 0 && !pts)) return fail(BEM_E_INVALID, "bad arguments");
+  *out = nullptr;
+  FieldPoints* F = nullptr;
+  int r = field_points_create(*P, prec, pts, n_pts, &F, (hipStream_t)stream);
+  if (r) return r;
+  *out = new bem_field_points{F};
+  return BEM_OK;
+}
+
+int bem_field_points_destroy(bem_field_points* fp) {
+  if (!fp) return BEM_OK;
+  field_points_destroy(fp->F);
+  delete fp;
+  return BEM_OK;
+}
+
+int bem_field_points_get_stats(const bem_field_points* fp, bem_field_points_stats* st) {
+  if (!fp || !st) return fail(BEM_E_INVALID, "bad arguments");
+  const FieldPoints& F = *fp->F;
+  const Problem& P = *F.P;
+  std::memset(st, 0, sizeof(*st));
+  st->n_pts = F.n;
+  st->levels = F.L;
+  for (int l = 0; l <= MAX_LEVEL; ++l) {
+    st->n_box[l] = F.nbox[l];
+    st->n_m2l[l] = F.n_m2l[l];
+    st->order[l] = F.prec == 0 ? P.f64.order[l] : P.f32.order[l];
+  }
+  st->n_leaf = F.n_leaf;
+  st->n_near_pairs = F.n_near_pairs;
+  st->device_bytes = F.arena.bytes;
+  return BEM_OK;
+}
+
+int bem_eval_field_grad_fmm(bem_field_points* fp, const void* p, const void* q,
+                            const double* dir3, const double* src, const void* amp, int n_src,
+                            void* out, void* grad, void* stream) {
+  if (!fp || !p || (!out && fp->F->n > 0)) return fail(BEM_E_INVALID, "bad arguments");
+  if (src && (!amp || n_src < 1)) return fail(BEM_E_INVALID, "point sources without amplitudes");
+  return eval_field_grad_fmm(*fp->F, (const c64*)p, (const c64*)q, dir3, src, (const c64*)amp,
+                             n_src, (c64*)out, (c64*)grad, (hipStream_t)stream);
+}
+
 int bem_topological_derivative(int n_pts, const void* p, const void* grad_p, const void* pt,
                                const void* grad_pt, const bem_material* mat, double* T,
                                void* stream) {

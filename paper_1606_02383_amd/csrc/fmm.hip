@@ -33,46 +33,12 @@
 
 #include <hip/hip_ext.h>
 
-#include "phase64.h"
+#include "kernel_math.h"
 #include "plan.h"
 
 namespace bemfmm {
 
 constexpr double INV_4PI_D = 0.07957747154594767;
-
-// e^{i k r}: float32 uses the hardware sine/cosine, which take the phase in
-// turns (k r / 2 pi; here a few radians at most, absolute error ~1e-6, far
-// below the float32 operator's tolerance); float64 the reduced Taylor
-// evaluation of phase64.h (error < 2e-16, branch-free).
-template <typename R>
-__device__ __forceinline__ void phase(R r, R k, R k_turns, R* s, R* c);
-template <>
-__device__ __forceinline__ void phase<float>(float r, float, float k_turns, float* s, float* c) {
-  const float t = r * k_turns;
-  *s = __builtin_amdgcn_sinf(t);
-  *c = __builtin_amdgcn_cosf(t);
-}
-template <>
-__device__ __forceinline__ void phase<double>(double r, double k, double, double* s, double* c) {
-  sincos_reduced(k * r, s, c);
-}
-// 1/sqrt(x) for x well inside the normal range (squared distances between
-// distinct rule points and collocation points)
-template <typename R>
-__device__ __forceinline__ R rsqrt_r(R x);
-template <>
-__device__ __forceinline__ float rsqrt_r<float>(float x) {
-  return __builtin_amdgcn_rsqf(x);
-}
-// float64: hardware estimate refined by two Newton steps
-// y <- y + (y/2)(1 - x y^2) (each doubles the correct bits)
-template <>
-__device__ __forceinline__ double rsqrt_r<double>(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-  return y;
-}
 
 // Burton-Miller coefficients (sp, sq) of a target point x (normal n_x)
 // against one source element, summed over the element's three rule points
@@ -2529,6 +2495,44 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
                       hipStream_t s) {
   return fmm_apply_adjoint_x<R>(P, D, D.X, y, u, w, s);
 }
+
+// Far field at evaluation points off the boundary: the problem's multipoles
+// for (p, q) (gather, P2M, upward pass, as in a product), then the locals of
+// the point boxes level by level: L2L from the parent point box onto the
+// cleared locals (one pair per child), then the M2L from the source boxes,
+// added atomically (a point box receives several of them in one launch).
+template <typename R>
+int point_far_field(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>& O,
+                    const c64* p, const c64* q, hipStream_t s) {
+  const int L = P.L;
+  ExecBuf<R>& X = O.X;
+  ZeroList<R> z = chain_zero_list(P, D, X, false, false);
+  for (int l = 2; l <= L; ++l) {
+    if (z.n >= MAX_ZERO) {
+      set_error("too many levels for the point-box clear");
+      return -1;
+    }
+    z.ptr[z.n] = O.Lc[l];
+    z.cnt[z.n] = (int64_t)F.nbox[l] * D.ncoef[l];
+    ++z.n;
+  }
+  hipLaunchKernelGGL(k_gather_in<R>, dim3(ceil_div(P.n, 256)), dim3(256), 0, s, p, q, P.perm,
+                     P.n, X.ps, X.qs, X.p64s, X.q64s, z);
+  BEM_LAUNCH_CHECK();
+  const int nleaf = P.nbox[L];
+  const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], q ? D.p2m : D.p2m_p, X.ps, X.qs, X.M[L]};
+  int r = launch_leaf_jobs<R>(&lj, &nleaf, 1, q ? 0 : 2, s);
+  if (!r) r = upward_pass(P, D, X, false, s);
+  for (int l = 2; l <= L && !r; ++l) {
+    if (l >= 3) r = launch_grouped<R, 2>(O.l2l[l], false, O.Lc[l - 1], O.Lc[l], s);
+    if (!r) r = launch_grouped<R, 1>(O.m2l[l], false, X.M[l], O.Lc[l], s);
+  }
+  return r;
+}
+template int point_far_field<float>(Problem&, PrecisionData<float>&, FieldPoints&,
+                                    PointOps<float>&, const c64*, const c64*, hipStream_t);
+template int point_far_field<double>(Problem&, PrecisionData<double>&, FieldPoints&,
+                                     PointOps<double>&, const c64*, const c64*, hipStream_t);
 
 template int fmm_apply_x<float>(Problem&, PrecisionData<float>&, ExecBuf<float>&, const c64*,
                                 const c64*, c64*, hipStream_t);

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "plan.h"
+#include "wavefun.h"
 
 namespace bemfmm {
 
@@ -66,41 +67,6 @@ __device__ void theta_table(int nmax, double x, double* out, int stride) {
         t1 = t2;
       }
     }
-  }
-}
-
-// spherical Bessel j_n(x), n = 0..nmax, by downward (Miller) recurrence of
-// the scaled values jt_n = j_n (2n+1)!! / x^n, normalised by j_0 = sin x / x;
-// returns j_n in out.
-__device__ void sph_jn(int nmax, double x, double* out) {
-  if (x == 0.0) {
-    out[0] = 1.0;
-    for (int n = 1; n <= nmax; ++n) out[n] = 0.0;
-    return;
-  }
-  int top = nmax + 24 + (int)(1.5 * x);
-  double x2 = x * x;
-  double jp1 = 1.0 - x2 / (2.0 * (2 * top + 5)), jn = 1.0 - x2 / (2.0 * (2 * top + 3));
-  // jt_{n-1} = jt_n - jt_{n+1} x^2 / ((2n+1)(2n+3))
-  for (int n = top; n >= 1; --n) {
-    double jm1 = jn - jp1 * x2 / ((2.0 * n + 1.0) * (2.0 * n + 3.0));
-    jp1 = jn;
-    jn = jm1;
-    if (n - 1 <= nmax) out[n - 1] = jm1;
-  }
-  // normalise on j_0 or j_1, whichever is larger (they never vanish together)
-  double j0 = (fabs(x) < 1e-4) ? 1.0 - x2 / 6.0 + x2 * x2 / 120.0 : sin(x) / x;
-  double scale;
-  if (nmax >= 1 && fabs(x) > 1.0) {
-    double j1 = (sin(x) / x - cos(x)) / x;
-    scale = (fabs(j0) >= fabs(j1)) ? j0 / out[0] : j1 / (out[1] * x / 3.0);
-  } else {
-    scale = j0 / out[0];
-  }
-  double f = 1.0;  // x^n / (2n+1)!!
-  for (int n = 0; n <= nmax; ++n) {
-    if (n > 0) f *= x / (2.0 * n + 1.0);
-    out[n] *= scale * f;
   }
 }
 
@@ -557,8 +523,9 @@ static int finish_grouped(GroupedOp<R>& op, int* d0, int* s0, int* c0, int np, i
     hipLaunchKernelGGL(k_sort_keys, dim3(ceil_div(np, 256)), dim3(256), 0, s, c0, d0, np, dbits,
                        keys, idx);
     BEM_LAUNCH_CHECK();
-    int nbits = dbits + 10;
-    int r = sort_pairs_u64(keys, idx, np, nbits, scratch, s);
+    int cbits = 1;
+    while ((1 << cbits) < ngroups) ++cbits;
+    int r = sort_pairs_u64(keys, idx, np, dbits + cbits, scratch, s);
     if (r) return r;
   }
   int* code_sorted;
@@ -672,6 +639,40 @@ static int build_reduce_lists(GroupedOp<R>& op, int nbox, DevArena& arena, DevAr
                    scratch, s);
   if (r) return r;
   op.n_red = op.n_red_adj = nbox;
+  return 0;
+}
+
+// Directional derivative coefficients of the regular wave functions up to
+// order p (the l = 1 terms of the translation formula, output order p + 1),
+// as interleaved complex pairs: see cmu() for their use.
+int derivative_table(Problem& P, int p, std::vector<double>& gc, DevArena& scratch,
+                     hipStream_t s) {
+  const int P1 = (p + 2) * (p + 2), Pc = (p + 1) * (p + 1);
+  GauntSet G1;
+  int r = make_gaunt(p, p + 1, 1, G1, scratch, s);
+  if (r) return r;
+  const int J = std::min(p, p + 1) + 1;
+  std::vector<double> hg((size_t)Pc * P1 * J);
+  BEM_HIP_TRY(hipMemcpyAsync(hg.data(), G1.d, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, s));
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  gc.assign((size_t)Pc * 2 * 3 * 2, 0.0);
+  for (int nn = 0; nn <= p; ++nn)
+    for (int m = -nn; m <= nn; ++m)
+      for (int sg = 0; sg < 2; ++sg) {
+        int n2 = sg ? nn + 1 : nn - 1;
+        if (n2 < 0) continue;
+        for (int mu = -1; mu <= 1; ++mu) {
+          int m2 = m - mu;
+          if (abs(m2) > n2) continue;
+          // l = 1 = |nn - n2| + 2j -> j = 0
+          double gv = hg[((size_t)cidx(nn, m) * P1 + cidx(n2, m2)) * J + 0];
+          std::complex<double> ie = std::pow(std::complex<double>(0, 1), (n2 + 1 - nn) & 3);
+          std::complex<double> cf = ie * (FOUR_PI * gv * P.k / 3.0);
+          size_t o = ((size_t)(cidx(nn, m) * 2 + sg) * 3 + (mu + 1)) * 2;
+          gc[o] = cf.real();
+          gc[o + 1] = cf.imag();
+        }
+      }
   return 0;
 }
 
@@ -848,32 +849,9 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     int p = D.order[L];
     int P1 = (p + 2) * (p + 2);
     int Pc = (p + 1) * (p + 1);
-    // derivative coefficients from the l = 1 Gaunt terms (output order p+1)
-    GauntSet G1;
-    int r = make_gaunt(p, p + 1, 1, G1, scratch, s);
+    std::vector<double> gc;
+    int r = derivative_table(P, p, gc, scratch, s);
     if (r) return r;
-    int J = std::min(p, p + 1) + 1;
-    std::vector<double> hg((size_t)Pc * P1 * J);
-    BEM_HIP_TRY(hipMemcpyAsync(hg.data(), G1.d, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, s));
-    BEM_HIP_TRY(hipStreamSynchronize(s));
-    std::vector<double> gc((size_t)Pc * 2 * 3 * 2, 0.0);
-    for (int nn = 0; nn <= p; ++nn)
-      for (int m = -nn; m <= nn; ++m)
-        for (int sg = 0; sg < 2; ++sg) {
-          int n2 = sg ? nn + 1 : nn - 1;
-          if (n2 < 0) continue;
-          for (int mu = -1; mu <= 1; ++mu) {
-            int m2 = m - mu;
-            if (abs(m2) > n2) continue;
-            // l = 1 = |nn - n2| + 2j -> j = 0
-            double gv = hg[((size_t)cidx(nn, m) * P1 + cidx(n2, m2)) * J + 0];
-            std::complex<double> ie = std::pow(std::complex<double>(0, 1), (n2 + 1 - nn) & 3);
-            std::complex<double> cf = ie * (FOUR_PI * gv * k / 3.0);
-            size_t o = ((size_t)(cidx(nn, m) * 2 + sg) * 3 + (mu + 1)) * 2;
-            gc[o] = cf.real();
-            gc[o + 1] = cf.imag();
-          }
-        }
     double *dgc, *dfinv, *dlo;
     ARENA_ALLOC(scratch, dgc, gc.size());
     ARENA_ALLOC(scratch, dfinv, p + 1);
@@ -1004,5 +982,107 @@ int build_operators(Problem& P, hipStream_t s) {
   BEM_HIP_TRY(hipStreamSynchronize(s));
   return 0;
 }
+
+// ---------------------------------------------------------------------------
+// translations into the boxes of evaluation points (off the boundary)
+// ---------------------------------------------------------------------------
+// The point boxes share the problem's grid, so the translations have the
+// problem's form and orders: M2L from the source boxes of level l (offset
+// codes over the PT_W^3 table, translation vector = point box centre minus
+// source box centre) and L2L from a point box to its children (octant
+// codes, as for the problem's tree).  Pairs come from the host lists.
+template <typename R>
+int build_point_ops(Problem& P, PrecisionData<R>& D, const PointLists& lists, FieldPoints& F,
+                    PointOps<R>& O, hipStream_t s) {
+  DevArena scratch;
+  struct Guard {
+    DevArena& a;
+    ~Guard() { a.release(); }
+  } guard{scratch};
+  const int L = P.L;
+  const double k = P.k;
+  auto upload = [&](const std::vector<int>& h, int** d) -> int {
+    ARENA_ALLOC(scratch, *d, std::max<size_t>(1, h.size()));
+    if (!h.empty())
+      BEM_HIP_TRY(hipMemcpyAsync(*d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
+    return 0;
+  };
+  for (int l = 2; l <= L; ++l) {
+    const int p = D.order[l];
+    // ---- M2L: one matrix per offset present ----
+    {
+      const std::vector<int>& hc = lists.m2l_code[l];
+      const int np = (int)hc.size();
+      std::vector<int> slot(PT_CODES, -1);
+      std::vector<double> tv;
+      int ns = 0;
+      for (int c : hc)
+        if (slot[c] < 0) slot[c] = 0;
+      for (int c = 0; c < PT_CODES; ++c)
+        if (slot[c] == 0) {
+          slot[c] = ns++;
+          const int dx = c / (PT_W * PT_W) - PT_OFF, dy = (c / PT_W) % PT_W - PT_OFF,
+                    dz = c % PT_W - PT_OFF;
+          tv.push_back(dx * P.h[l]);
+          tv.push_back(dy * P.h[l]);
+          tv.push_back(dz * P.h[l]);
+        }
+      GroupedOp<R>& op = O.m2l[l];
+      op.rows = op.cols = D.ncoef[l];
+      op.n_slots = ns;
+      if (ns > 0) {
+        // L~ = f_n' (S|R) M~ f_n, as for the problem's own boxes
+        std::vector<double> rs = coef_scale(p, k * P.h[l], +1), cs = rs;
+        int r = make_translations<R>(P, F.arena, ns, tv, 1, p, p, rs, cs, &op.mats, scratch, s);
+        if (r) return r;
+      }
+      int *d0, *s0, *c0;
+      int r = upload(lists.m2l_dst[l], &d0);
+      if (!r) r = upload(lists.m2l_src[l], &s0);
+      if (!r) r = upload(hc, &c0);
+      if (!r) r = finish_grouped<R>(op, d0, s0, c0, np, PT_CODES, slot, F.arena, scratch, s);
+      if (r) return r;
+      F.n_m2l[l] = np;
+    }
+    // ---- L2L from the parent point boxes (level l - 1) ----
+    if (l >= 3) {
+      const int pp = D.order[l - 1];
+      std::vector<int> slot(8);
+      std::vector<double> tv;
+      for (int o = 0; o < 8; ++o) {
+        slot[o] = o;
+        tv.push_back((((o >> 2) & 1) ? 0.5 : -0.5) * P.h[l]);  // child - parent centre
+        tv.push_back((((o >> 1) & 1) ? 0.5 : -0.5) * P.h[l]);
+        tv.push_back(((o & 1) ? 0.5 : -0.5) * P.h[l]);
+      }
+      GroupedOp<R>& ll = O.l2l[l];
+      ll.rows = D.ncoef[l];
+      ll.cols = D.ncoef[l - 1];
+      ll.n_slots = 8;
+      std::vector<double> rs = coef_scale(p, k * P.h[l], +1), cs = coef_scale(pp, k * P.h[l - 1], -1);
+      int r = make_translations<R>(P, F.arena, 8, tv, 0, pp, p, rs, cs, &ll.mats, scratch, s);
+      int *d0, *s0, *c0;
+      if (!r) r = upload(lists.l2l_dst[l], &d0);
+      if (!r) r = upload(lists.l2l_src[l], &s0);
+      if (!r) r = upload(lists.l2l_code[l], &c0);
+      if (!r)
+        r = finish_grouped<R>(ll, d0, s0, c0, (int)lists.l2l_code[l].size(), 8, slot, F.arena,
+                              scratch, s);
+      if (r) return r;
+    }
+    ARENA_ALLOC(F.arena, O.Lc[l], std::max<int64_t>(1, (int64_t)F.nbox[l] * D.ncoef[l]));
+    ARENA_ALLOC(F.arena, O.X.M[l], std::max<int64_t>(1, (int64_t)P.nbox[l] * D.ncoef[l]));
+  }
+  ARENA_ALLOC(F.arena, O.X.ps, P.n);
+  ARENA_ALLOC(F.arena, O.X.qs, P.n);
+  ARENA_ALLOC(F.arena, O.X.p64s, P.n);
+  ARENA_ALLOC(F.arena, O.X.q64s, P.n);
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+template int build_point_ops<float>(Problem&, PrecisionData<float>&, const PointLists&,
+                                    FieldPoints&, PointOps<float>&, hipStream_t);
+template int build_point_ops<double>(Problem&, PrecisionData<double>&, const PointLists&,
+                                     FieldPoints&, PointOps<double>&, hipStream_t);
 
 }  // namespace bemfmm

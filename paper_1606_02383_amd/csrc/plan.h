@@ -340,6 +340,88 @@ int eval_field(Problem& P, const c64* p, const c64* q, const double* pts, int n_
 int eval_field_grad(Problem& P, const c64* p, const c64* q, const double* pts, int n_pts,
                     const double* d, const double* src, const c64* amp, int n_src, c64* out,
                     c64* grad, hipStream_t s);
+// ---- evaluation points off the boundary (field_points.hip) ----
+// Point boxes live on the grid of the problem's tree (same origin and box
+// sides per level) and may reach PT_EXT level-2 boxes beyond its root cube
+// on every side; translations into them from level-2 boxes then span up to
+// PT_OFF boxes per axis (codes over a PT_W^3 table), from finer levels at
+// most 3.
+constexpr int PT_EXT = 8;
+constexpr int PT_OFF = 3 + PT_EXT;
+constexpr int PT_W = 2 * PT_OFF + 1;
+constexpr int PT_CODES = PT_W * PT_W * PT_W;
+
+// Translations of one precision into the point boxes, their locals and the
+// buffers of the source tree's upward pass (multipoles and sorted densities).
+template <typename R>
+struct PointOps {
+  std::array<GroupedOp<R>, MAX_LEVEL + 1> m2l{};  // source boxes -> point boxes, level l
+  std::array<GroupedOp<R>, MAX_LEVEL + 1> l2l{};  // point boxes level l - 1 -> l (index l)
+  std::array<cplx<R>*, MAX_LEVEL + 1> Lc{};       // locals of the point boxes
+  ExecBuf<R> X;                                    // M[l], ps, qs, p64s, q64s only
+};
+
+// Host-side lists of the point octree (inputs of the operator build).
+struct PointLists {
+  std::array<std::vector<int>, MAX_LEVEL + 1> m2l_dst, m2l_src, m2l_code;
+  std::array<std::vector<int>, MAX_LEVEL + 1> l2l_dst, l2l_src, l2l_code;
+};
+
+struct FieldPoints {
+  Problem* P = nullptr;
+  int prec = 0;          // 0 float64, 1 float32
+  int64_t n = 0;
+  DevArena arena;
+  double* xyz = nullptr;  // sorted points, SoA (3 x n)
+  int* perm = nullptr;    // sorted position -> caller index
+  int L = 0;              // deepest point level (the problem's leaf level)
+  std::array<int, MAX_LEVEL + 1> nbox{};
+  std::array<int64_t, MAX_LEVEL + 1> n_m2l{};
+  // leaves (boxes without children) in point order, cut into chunks of at
+  // most 64 points; chunk_* describe the far-field (L2P) chunks, near_* the
+  // chunks of leaves on the deepest level with their source-leaf lists
+  int n_leaf = 0, n_chunk = 0, n_near_chunk = 0;
+  int* leaf_level = nullptr;
+  int* leaf_box = nullptr;     // index among the point boxes of its level
+  double* leaf_c = nullptr;    // centres, 3 per leaf
+  int* chunk_leaf = nullptr;
+  int* chunk_pt = nullptr;     // first point; count in chunk_cnt
+  int* chunk_cnt = nullptr;
+  int* near_pt = nullptr;      // first point, count, first / end entry of near_src
+  int* near_cnt = nullptr;
+  int* near_s0 = nullptr;
+  int* near_s1 = nullptr;
+  int* near_src = nullptr;     // source leaves (indices among the problem's leaves)
+  int64_t n_near_pairs = 0;    // point x element pairs summed directly
+  int max_order = 0;
+  double* finv = nullptr;      // 1 / f_n per level: finv[l * (MAXP_PT + 1) + n]
+  double* gcoef = nullptr;     // derivative coefficients up to max_order
+  c64* acc = nullptr;          // far + near sums (field, d/dx, d/dy, d/dz) per sorted point
+  const void* const* lev_lc = nullptr;  // device: locals of the point boxes per level
+  int* lev_order = nullptr;             // device: expansion order per level
+  PointOps<float> f32;
+  PointOps<double> f64;
+};
+constexpr int MAXP_PT = 40;    // largest expansion order (the library's)
+
+int field_points_create(Problem& P, int prec, const double* pts, int64_t n, FieldPoints** out,
+                        hipStream_t s);
+void field_points_destroy(FieldPoints* F);
+int eval_field_grad_fmm(FieldPoints& F, const c64* p, const c64* q, const double* d,
+                        const double* src, const c64* amp, int n_src, c64* out, c64* grad,
+                        hipStream_t s);
+// operators.hip: translations into the point boxes and the derivative table
+template <typename R>
+int build_point_ops(Problem& P, PrecisionData<R>& D, const PointLists& lists, FieldPoints& F,
+                    PointOps<R>& O, hipStream_t s);
+int derivative_table(Problem& P, int p, std::vector<double>& gc, DevArena& scratch,
+                     hipStream_t s);
+// fmm.hip: multipoles of the problem's tree for (p, q), then the locals of
+// the point boxes
+template <typename R>
+int point_far_field(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>& O,
+                    const c64* p, const c64* q, hipStream_t s);
+
 int topological_derivative(int n, const c64* p, const c64* gp, const c64* pt, const c64* gpt,
                            double cg, double cv, double* T, hipStream_t s);
 int eval_field_adjoint(Problem& P, const double* pts, int n_pts, const c64* c, c64* rp,
