@@ -26,6 +26,11 @@ the 49152-element cube surface at k = 6: J = sum |p(x_m)|^2 over 8 points on
 the radius-3 sphere and dJ/dbeta for a per-element admittance beta, i.e. a
 state solve, the field at the points, an adjoint solve and the gradient,
 both solves in mixed precision to a float64 residual of 1e-6.
+
+``--workload topo_sphere81920_k8`` times the topological derivative T_Omega
+on the design-domain lattice (101^3 points on [-1.25, 1.25]^3, those outside
+the sphere): state and adjoint fields and gradients at the points by the
+FMM, then T_Omega; its line reports lattice points/s.
 """
 import argparse
 import json
@@ -241,6 +246,165 @@ def run_grad(args):
     print(json.dumps(out), flush=True)
 
 
+def _cpu_points(chunk):
+    """Oracle state and adjoint fields, gradients and T_Omega at a few points."""
+    from oracle import solve
+    geom, k, p, pt, d, obs, amp = _G
+    Kh, Sh = solve.represent_blocks(geom, k, chunk)
+    inc = np.exp(1j * k * (chunk @ d))
+    fs = Kh @ p + inc
+    gs = solve.represent_grad(geom, k, chunk, p, None) + (1j * k * inc)[:, None] * d[None, :]
+    fa = Kh @ pt + solve.point_source_field(k, chunk, obs, amp)
+    ga = solve.represent_grad(geom, k, chunk, pt, None) + solve.point_source_grad(k, chunk, obs, amp)
+    return solve.topological_derivative(fs, gs, fa, ga, 1.0, np.inf, 1.0, np.inf, k)
+
+
+def cpu_baseline_points(V, T, k, p, pt, d, obs, amp, lat, seed, target_s=15.0):
+    """The oracle's T_Omega (both fields and gradients by dense sums) on
+    sampled lattice points, process-parallel; returns (points/s, cores,
+    points, seconds)."""
+    import multiprocessing as mp
+
+    from oracle import bem as obem
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    global _G
+    _G = (obem.Geometry(V, T), k, p, pt, d, obs, amp)
+    rng = np.random.default_rng(seed)
+    pick = lat[rng.permutation(len(lat))]
+    t0 = time.perf_counter()
+    _cpu_points(pick[:4])
+    per_pt = (time.perf_counter() - t0) / 4
+    npts = int(max(cores * 4, min(len(lat), target_s * cores / max(per_pt, 1e-6))))
+    chunks = np.array_split(pick[:npts], max(1, npts // 4))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_cpu_points, chunks)
+    dt = time.perf_counter() - t0
+    return npts / dt, cores, npts, dt
+
+
+def run_topo(args):
+    """Topological derivative on the design-domain lattice (the topology
+    loop's step 8): state and adjoint fields with their gradients at the
+    lattice points by the FMM, then T_Omega.  The state solve (plane wave)
+    and the adjoint solve (point sources of intensity 2 conj(p) at the 8
+    observation points) run before the timed region."""
+    import torch
+
+    import paper_1606_02383_amd as bem
+    from workloads import WORKLOADS, unit_directions
+
+    wl = WORKLOADS["sphere81920_k8"]
+    V, T = wl.mesh_arrays()
+    rng = np.random.default_rng(wl.seed)
+    d = unit_directions(rng, 1)[0]
+    obs = 3.0 * unit_directions(rng, 8)
+    t = np.linspace(-1.25, 1.25, 101)
+    X = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    lat = X[np.linalg.norm(X, axis=1) > 1.02]
+    plan = bem.Plan(bem.Problem(V, T, wl.k, leaf_cap=64))
+    opts = bem.GmresOptions(tol=1e-6, restart=50, mode=1, inner_tol=args.inner_tol)
+    p, info = plan.solve(plan.plane_wave_rhs(d), opts=opts)
+    pobs = plan.eval_field(p, None, obs, direction=d).cpu().numpy()
+    amp = 2.0 * np.conj(pobs)
+    pt, info_t = plan.solve(plan.point_source_rhs(obs, amp), opts=opts)
+    log(f"[bench] topo: {len(lat)} lattice points; state / adjoint residuals "
+        f"{info['resid']:.2e} / {info_t['resid']:.2e}")
+    res = {}
+    for prec, name in ((bem.BEM_C128, "f64"), (bem.BEM_C64, "f32")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fp = bem.FieldPoints(plan, lat, prec=prec)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+
+        def step():
+            fs, gs = fp.eval_field_grad(p, None, direction=d)
+            fa, ga = fp.eval_field_grad(pt, None, src=obs, amp=amp)
+            return bem.topological_derivative(fs, gs, fa, ga, omega=wl.k)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Tg = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        plan.profile_start()
+        step()
+        prof = plan.profile_stop()
+        res[name] = dict(ms=dt * 1e3, build_s=t_build, stats=fp.stats(), T=Tg.cpu().numpy(),
+                         prof=prof)
+        log(f"[bench] topo {name}: {dt * 1e3:.2f} ms per T_Omega evaluation "
+            f"({len(lat) / dt:.3e} points/s), point set built in {t_build:.2f} s")
+        fp.close()
+    # the direct sums on a sample of the lattice, for speed and agreement
+    pick = np.sort(rng.choice(len(lat), 20000, replace=False))
+    sub = lat[pick]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    plan.eval_field_grad(p, None, sub[:256], direction=d)
+    ev[0].record()
+    fs, gs = plan.eval_field_grad(p, None, sub, direction=d)
+    fa, ga = plan.eval_field_grad(pt, None, sub, src=obs, amp=amp)
+    Td = bem.topological_derivative(fs, gs, fa, ga, omega=wl.k)
+    ev[1].record()
+    torch.cuda.synchronize()
+    direct_ms = ev[0].elapsed_time(ev[1]) * len(lat) / len(sub)
+    Td = Td.cpu().numpy()
+    err = {n: float(np.linalg.norm(res[n]["T"][pick] - Td) / np.linalg.norm(Td)) for n in res}
+    log(f"[bench] topo direct sums: {direct_ms:.1f} ms for the lattice (from 20000 points); "
+        f"T_Omega rel. difference FMM vs direct: f64 {err['f64']:.2e}, f32 {err['f32']:.2e}")
+    # roofline: the leaf-level M2L into the point boxes (float64), timed by
+    # HIP events on the stream in the profiled step (two evaluations)
+    r64 = res["f64"]
+    st = r64["stats"]
+    L = st["levels"]
+    ms_leaf, calls_leaf = r64["prof"].get(("m2l_leaf", "f64", "fwd"), (0.0, 0))
+    flops = 8.0 * st["n_m2l"][L] * (st["order"][L] + 1) ** 4
+    per_ms = ms_leaf / max(1, calls_leaf)
+    ach = flops / (per_ms / 1e3) if per_ms > 0 else 0.0
+    stages = {f"{k_[0]}_{k_[1]}": round(v[0] / v[1], 4) for k_, v in r64["prof"].items()}
+    roofline = {"kernel": "k_grouped_gemm<double,*,false,1> (leaf-level M2L into the point "
+                          "boxes, float64)", "bound": "mfma", "achieved": round(ach / 1e12, 3),
+                "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64, 4),
+                "traffic": None, "flops_per_launch": flops, "avg_launch_ms": round(per_ms, 5),
+                "launches": calls_leaf}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (sampled lattice points)...")
+        v, cores, npts, cdt = cpu_baseline_points(V, T, wl.k, p.cpu().numpy(), pt.cpu().numpy(),
+                                                  d, obs, amp, lat, wl.seed)
+        cpu = {"value": v, "unit": "points/s", "cores": cores, "kind": "oracle",
+               "sample": f"T_Omega at {npts} of {len(lat)} lattice points (both fields and "
+                         f"gradients by dense numpy sums over all elements, {cores} processes, "
+                         f"{cdt:.1f} s)",
+               "affinity_cores": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()}
+        log(f"[bench] CPU oracle: {v:.3e} points/s on {cores} cores")
+    out = {
+        "metric": "T_Omega lattice points/sec (state and adjoint field + gradient by FMM at "
+                  "the 101^3 design-domain lattice points outside the sphere N=81920, k=8)",
+        "value": len(lat) / (r64["ms"] / 1e3), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "topo_sphere81920_k8", "n_tri": len(T), "k": wl.k,
+                   "lattice": "101^3 on [-1.25, 1.25]^3, points with |x| > 1.02",
+                   "n_points": len(lat), "material": "sound-hard limit",
+                   "objective": "sum |p|^2 over 8 points on the radius-3 sphere"},
+        "f32": {"ms_per_step": res["f32"]["ms"], "points_per_s": len(lat) / (res["f32"]["ms"] / 1e3),
+                "T_rel_diff_vs_direct": err["f32"]},
+        "T_rel_diff_vs_direct": err["f64"],
+        "direct_sum_ms": direct_ms,
+        "point_set_build_s": {"f64": r64["build_s"], "f32": res["f32"]["build_s"]},
+        "point_tree": {"n_box": st["n_box"][2:], "n_m2l": st["n_m2l"][2:],
+                       "order": st["order"][2:], "n_leaf": st["n_leaf"],
+                       "n_near_pairs": st["n_near_pairs"]},
+        "stage_ms_per_call": stages,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 # Algorithmic work of the float32 near field per (target, source element)
 # pair for the rigid products timed here (alpha = i/k, q = 0), counted on the
 # pair kernel's expression (add, subtract, multiply = 1 FLOP, fused
@@ -301,6 +465,9 @@ def main():
         return
     if args.workload == "grad_cube49152_k6":
         run_grad(args)
+        return
+    if args.workload == "topo_sphere81920_k8":
+        run_topo(args)
         return
     import torch
 

@@ -42,7 +42,7 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_profile_leaf_m2l_start", "bem_profile_stop", "bem_last_error"]
 
 STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
-          "m2l_leaf_reduce"]
+          "m2l_leaf_reduce", "pt_l2p", "pt_p2p"]
 PROFILE_SLOTS = 64
 
 

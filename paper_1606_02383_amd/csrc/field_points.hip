@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -111,78 +112,82 @@ int pt_code(int dx, int dy, int dz) {
 // gradient is sum R_{n'}^{m'} B_a(n', m') with
 //   B_x = c (A_-1 - A_+1),  B_y = -i c (A_+1 + A_-1),  B_z = c0 A_0,
 //   c = sqrt(3/(8 pi)), c0 = sqrt(3/(4 pi)).
-// Each workgroup (one chunk of a leaf's points) first forms the four
-// coefficient arrays (value: Lt; B_x, B_y, B_z) in LDS, then every lane
-// generates the wave functions of its point in m-major order by the
-// normalised Legendre recurrences (Condon-Shortley phase), j_n in LDS per
-// lane, and reads the coefficients with wave-uniform (broadcast) LDS loads.
+// Each workgroup (one chunk of a leaf's points; one launch per level, so
+// that LDS is sized by that level's order) first forms the four coefficient
+// arrays (value: Lt; B_x, B_y, B_z) and the Legendre recurrence
+// coefficients in LDS, then every lane generates the wave functions of its
+// point in m-major order by the normalised Legendre recurrences
+// (Condon-Shortley phase), j_n in LDS per lane, and reads the coefficients
+// with wave-uniform (broadcast) LDS loads.  Arithmetic type T: float64 for
+// the float64 evaluation, float32 for the float32 one.
 __host__ __device__ inline int cidx_pt(int n, int m) { return n * n + n + m; }
 
-// LDS of the L2P kernel for expansion order p: j_n per lane, the
-// reciprocals 1/((2n+1)(2n+3)) of the Bessel recurrence, the Legendre
-// recurrence coefficients per (n, m >= 0), the four coefficient arrays
-constexpr int JN_TOP = 256;  // Bessel recurrence start orders tabulated
-__host__ __device__ inline size_t l2p_lds_bytes(int p) {
-  return sizeof(double) * ((MAXP_PT + 2) * PT_CHUNK + JN_TOP + 2 * (p + 2) * (p + 2)) +
-         sizeof(c64) * 4 * (p + 2) * (p + 2);
+// LDS of the L2P kernel for expansion order p and jn_top tabulated Bessel
+// recurrence reciprocals: j_n per lane, the reciprocals, the Legendre
+// recurrence coefficients a, b per (n, m >= 0), the four coefficient arrays
+template <typename T>
+__host__ __device__ inline size_t l2p_lds_bytes(int p, int jn_top) {
+  return sizeof(T) * ((size_t)(p + 2) * PT_CHUNK + jn_top + 2 * (p + 2) * (p + 2)) +
+         sizeof(cplx<T>) * 4 * (p + 2) * (p + 2);
 }
 
-// j_n(x), n = 0..nmax, into out[n * stride]: sph_jn with the recurrence's
-// divisions replaced by the tabulated reciprocals (start orders < JN_TOP)
-__device__ inline void jn_tab(int nmax, double x, double* out, int stride,
-                              const double* __restrict__ inv) {
-  int top = nmax + 24 + (int)(1.5 * x);
-  if (x == 0.0 || top >= JN_TOP - 1) {
-    sph_jn(nmax, x, out, stride);
+// j_n(x), n = 0..nmax, into out[n * stride] by the downward (Miller)
+// recurrence of sph_jn, with 1/((2n+1)(2n+3)) from the table inv for
+// n < ninv
+template <typename T>
+__device__ inline void jn_tab(int nmax, T x, T* out, int stride, const T* __restrict__ inv,
+                              int ninv) {
+  if (x == T(0)) {
+    out[0] = T(1);
+    for (int nn = 1; nn <= nmax; ++nn) out[nn * stride] = T(0);
     return;
   }
-  const double x2 = x * x;
-  double jp1 = 1.0 - x2 / (2.0 * (2 * top + 5)), jn = 1.0 - x2 / (2.0 * (2 * top + 3));
+  const int top = nmax + 24 + (int)(T(1.5) * x);
+  const T x2 = x * x;
+  T jp1 = T(1) - x2 / (T(2) * (2 * top + 5)), jn = T(1) - x2 / (T(2) * (2 * top + 3));
   for (int nn = top; nn >= 1; --nn) {
-    const double jm1 = jn - jp1 * x2 * inv[nn];
+    const T rc = nn < ninv ? inv[nn] : T(1) / ((T(2) * nn + T(1)) * (T(2) * nn + T(3)));
+    const T jm1 = jn - jp1 * x2 * rc;
     jp1 = jn;
     jn = jm1;
     if (nn - 1 <= nmax) out[(nn - 1) * stride] = jm1;
   }
-  double sn, cs;
-  sincos(x, &sn, &cs);
-  const double j0 = (fabs(x) < 1e-4) ? 1.0 - x2 / 6.0 + x2 * x2 / 120.0 : sn / x;
-  double scale;
-  if (nmax >= 1 && fabs(x) > 1.0) {
-    const double j1 = (sn / x - cs) / x;
-    scale = (fabs(j0) >= fabs(j1)) ? j0 / out[0] : j1 / (out[stride] * x / 3.0);
+  const T sn = sin(x), cs = cos(x);
+  const T j0 = (fabs(x) < T(1e-4)) ? T(1) - x2 / T(6) + x2 * x2 / T(120) : sn / x;
+  T scale;
+  if (nmax >= 1 && fabs(x) > T(1)) {
+    const T j1 = (sn / x - cs) / x;
+    scale = (fabs(j0) >= fabs(j1)) ? j0 / out[0] : j1 / (out[stride] * x / T(3));
   } else {
     scale = j0 / out[0];
   }
-  double fct = 1.0;  // x^n / (2n+1)!!
+  T fct = T(1);  // x^n / (2n+1)!!
   for (int nn = 0; nn <= nmax; ++nn) {
-    if (nn > 0) fct *= x / (2.0 * nn + 1.0);
+    if (nn > 0) fct *= x / (T(2) * nn + T(1));
     out[nn * stride] *= scale * fct;
   }
 }
 
-template <typename R>
+template <typename R, typename T>
 __global__ void __launch_bounds__(PT_CHUNK)
-    k_points_l2p(const cplx<R>* const* __restrict__ lev_lc, const int* __restrict__ lev_order,
+    k_points_l2p(const cplx<R>* __restrict__ Lc, int p, int jn_top, int chunk0,
                  const int* __restrict__ chunk_leaf, const int* __restrict__ chunk_pt,
-                 const int* __restrict__ chunk_cnt, const int* __restrict__ leaf_level,
-                 const int* __restrict__ leaf_box, const double* __restrict__ leaf_c,
-                 const double* __restrict__ xyz, int64_t n, double k,
-                 const double* __restrict__ finv, const double* __restrict__ gc,
+                 const int* __restrict__ chunk_cnt, const int* __restrict__ leaf_box,
+                 const double* __restrict__ leaf_c, const double* __restrict__ xyz, int64_t n,
+                 double k, const double* __restrict__ fi, const double* __restrict__ gc,
                  c64* __restrict__ acc) {
   extern __shared__ double pt_lds[];
-  const int chunk = blockIdx.x, t = threadIdx.x;
+  const int chunk = chunk0 + blockIdx.x, t = threadIdx.x;
   const int leaf = chunk_leaf[chunk];
-  const int l = leaf_level[leaf], p = lev_order[l];
   const int ncoef = (p + 1) * (p + 1), P2 = (p + 2) * (p + 2);
-  double* s_j = pt_lds;
-  double* s_inv = s_j + (MAXP_PT + 2) * PT_CHUNK;
-  double* s_a = s_inv + JN_TOP;
-  double* s_b = s_a + P2;
-  c64* sB = (c64*)(s_b + P2);
-  for (int c = t; c < JN_TOP; c += PT_CHUNK) s_inv[c] = 1.0 / ((2.0 * c + 1.0) * (2.0 * c + 3.0));
-  const cplx<R>* __restrict__ Lb = lev_lc[l] + (int64_t)leaf_box[leaf] * ncoef;
-  const double* __restrict__ fi = finv + l * (MAXP_PT + 1);
+  const cplx<R>* __restrict__ Lb = Lc + (int64_t)leaf_box[leaf] * ncoef;
+  T* s_j = (T*)pt_lds;
+  T* s_inv = s_j + (p + 2) * PT_CHUNK;
+  T* s_a = s_inv + jn_top;
+  T* s_b = s_a + P2;
+  cplx<T>* sB = (cplx<T>*)(s_b + P2);
+  for (int c = t; c < jn_top; c += PT_CHUNK)
+    s_inv[c] = (T)(1.0 / ((2.0 * c + 1.0) * (2.0 * c + 3.0)));
   constexpr double C1 = 0.3454941494713355, C0 = 0.4886025119029199;
   auto Lt = [&](int nn, int m) -> c64 {
     const cplx<R> v = Lb[cidx_pt(nn, m)];
@@ -204,56 +209,60 @@ __global__ void __launch_bounds__(PT_CHUNK)
       }
     }
     const c64 s2 = cadd(A[2], A[0]);
-    sB[c] = n2 <= p ? Lt(n2, m2) : mk(0.0, 0.0);
-    sB[P2 + c] = cscale(csub(A[0], A[2]), C1);      // c (A_-1 - A_+1)
-    sB[2 * P2 + c] = mk(C1 * s2.im, -C1 * s2.re);   // -i c (A_+1 + A_-1)
-    sB[3 * P2 + c] = cscale(A[1], C0);
+    const c64 v0 = n2 <= p ? Lt(n2, m2) : mk(0.0, 0.0);
+    const c64 v1 = cscale(csub(A[0], A[2]), C1);      // c (A_-1 - A_+1)
+    const c64 v2 = mk(C1 * s2.im, -C1 * s2.re);       // -i c (A_+1 + A_-1)
+    const c64 v3 = cscale(A[1], C0);
+    sB[c] = mk<T>((T)v0.re, (T)v0.im);
+    sB[P2 + c] = mk<T>((T)v1.re, (T)v1.im);
+    sB[2 * P2 + c] = mk<T>((T)v2.re, (T)v2.im);
+    sB[3 * P2 + c] = mk<T>((T)v3.re, (T)v3.im);
     // Legendre recurrence coefficients of (n2, m2 >= 0), n2 >= m2 + 2
     if (m2 >= 0 && n2 >= m2 + 2) {
-      s_a[c] = sqrt((4.0 * n2 * n2 - 1.0) / ((double)n2 * n2 - (double)m2 * m2));
-      s_b[c] = sqrt(((n2 - 1.0) * (n2 - 1.0) - (double)m2 * m2) /
-                    (4.0 * (n2 - 1.0) * (n2 - 1.0) - 1.0));
+      s_a[c] = (T)sqrt((4.0 * n2 * n2 - 1.0) / ((double)n2 * n2 - (double)m2 * m2));
+      s_b[c] = (T)sqrt(((n2 - 1.0) * (n2 - 1.0) - (double)m2 * m2) /
+                       (4.0 * (n2 - 1.0) * (n2 - 1.0) - 1.0));
     }
   }
   __syncthreads();
   const bool active = t < chunk_cnt[chunk];
   const int64_t i = chunk_pt[chunk] + t;
-  double vx = 1.0, vy = 0.0, vz = 0.0;
+  T vx = T(1), vy = T(0), vz = T(0);
   if (active) {
-    vx = xyz[i] - leaf_c[3 * leaf];
-    vy = xyz[n + i] - leaf_c[3 * leaf + 1];
-    vz = xyz[2 * n + i] - leaf_c[3 * leaf + 2];
+    vx = (T)(xyz[i] - leaf_c[3 * leaf]);
+    vy = (T)(xyz[n + i] - leaf_c[3 * leaf + 1]);
+    vz = (T)(xyz[2 * n + i] - leaf_c[3 * leaf + 2]);
   }
-  const double r = sqrt(vx * vx + vy * vy + vz * vz);
-  const double ct = r > 0.0 ? vz / r : 1.0;
-  const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
-  const double rxy = sqrt(vx * vx + vy * vy);
-  const double cp = rxy > 0.0 ? vx / rxy : 1.0, sp = rxy > 0.0 ? vy / rxy : 0.0;
-  jn_tab(p + 1, k * r, s_j + t, PT_CHUNK, s_inv);
-  c64 f = mk(0.0, 0.0), gx = mk(0.0, 0.0), gy = mk(0.0, 0.0), gz = mk(0.0, 0.0);
-  auto add = [&](int c, c64 Rv) {
+  const T r = sqrt(vx * vx + vy * vy + vz * vz);
+  const T ct = r > T(0) ? vz / r : T(1);
+  const T st = sqrt(fmax(T(0), T(1) - ct * ct));
+  const T rxy = sqrt(vx * vx + vy * vy);
+  const T cp = rxy > T(0) ? vx / rxy : T(1), sp = rxy > T(0) ? vy / rxy : T(0);
+  jn_tab<T>(p + 1, (T)k * r, s_j + t, PT_CHUNK, s_inv, jn_top);
+  cplx<T> f = mk<T>(0, 0), gx = mk<T>(0, 0), gy = mk<T>(0, 0), gz = mk<T>(0, 0);
+  auto add = [&](int c, cplx<T> Rv) {
     cfma(f, sB[c], Rv);
     cfma(gx, sB[P2 + c], Rv);
     cfma(gy, sB[2 * P2 + c], Rv);
     cfma(gz, sB[3 * P2 + c], Rv);
   };
-  double tmm = 0.28209479177387814;  // 1/sqrt(4 pi)
-  double er = 1.0, ei = 0.0;         // exp(i m phi)
+  T tmm = T(0.28209479177387814);  // 1/sqrt(4 pi)
+  T er = T(1), ei = T(0);          // exp(i m phi)
   for (int m = 0; m <= p + 1; ++m) {
     if (m > 0) {
-      const double tr = er * cp - ei * sp;
+      const T tr = er * cp - ei * sp;
       ei = er * sp + ei * cp;
       er = tr;
-      tmm = -sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * tmm;
+      tmm = -sqrt((T(2) * m + T(1)) / (T(2) * m)) * st * tmm;
     }
-    const double sgn = (m & 1) ? -1.0 : 1.0;
-    double t0 = 0.0, t1 = tmm;
+    const T sgn = (m & 1) ? T(-1) : T(1);
+    T t0 = T(0), t1 = tmm;
     for (int nn = m; nn <= p + 1; ++nn) {
-      double th;
+      T th;
       if (nn == m) {
         th = tmm;
       } else if (nn == m + 1) {
-        th = sqrt(2.0 * m + 3.0) * ct * tmm;
+        th = sqrt(T(2) * m + T(3)) * ct * tmm;
         t0 = tmm;
         t1 = th;
       } else {
@@ -262,17 +271,17 @@ __global__ void __launch_bounds__(PT_CHUNK)
         t0 = t1;
         t1 = th;
       }
-      const double jt = s_j[nn * PT_CHUNK + t] * th;
-      add(cidx_pt(nn, m), mk(jt * er, jt * ei));
+      const T jt = s_j[nn * PT_CHUNK + t] * th;
+      add(cidx_pt(nn, m), mk<T>(jt * er, jt * ei));
       // R_n^-m = (-1)^m conj(R_n^m) (j_n real)
-      if (m > 0) add(cidx_pt(nn, -m), mk(sgn * jt * er, -sgn * jt * ei));
+      if (m > 0) add(cidx_pt(nn, -m), mk<T>(sgn * jt * er, -sgn * jt * ei));
     }
   }
   if (active) {
-    acc[4 * i] = f;
-    acc[4 * i + 1] = gx;
-    acc[4 * i + 2] = gy;
-    acc[4 * i + 3] = gz;
+    acc[4 * i] = mk((double)f.re, (double)f.im);
+    acc[4 * i + 1] = mk((double)gx.re, (double)gx.im);
+    acc[4 * i + 2] = mk((double)gy.re, (double)gy.im);
+    acc[4 * i + 3] = mk((double)gz.re, (double)gz.im);
   }
 }
 
@@ -434,27 +443,6 @@ PointOps<double>& pops<double>(FieldPoints& F) {
   return F.f64;
 }
 
-// device tables of one precision: per-level local pointers and orders
-template <typename R>
-int level_tables(FieldPoints& F, PrecisionData<R>& D, const cplx<R>* const** lc, int** ord,
-                 DevArena& arena, hipStream_t s) {
-  std::vector<const cplx<R>*> hl(MAX_LEVEL + 1, nullptr);
-  std::vector<int> ho(MAX_LEVEL + 1, 0);
-  for (int l = 2; l <= F.L; ++l) {
-    hl[l] = pops<R>(F).Lc[l];
-    ho[l] = D.order[l];
-  }
-  const cplx<R>** dl;
-  int* dord;
-  ARENA_ALLOC(arena, dl, MAX_LEVEL + 1);
-  ARENA_ALLOC(arena, dord, MAX_LEVEL + 1);
-  BEM_HIP_TRY(hipMemcpyAsync(dl, hl.data(), sizeof(void*) * hl.size(), hipMemcpyHostToDevice, s));
-  BEM_HIP_TRY(hipMemcpyAsync(dord, ho.data(), sizeof(int) * ho.size(), hipMemcpyHostToDevice, s));
-  *lc = dl;
-  *ord = dord;
-  return 0;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -489,12 +477,6 @@ static int build_points_precision(Problem& P, const PointLists& lists, FieldPoin
   ARENA_ALLOC(F.arena, F.gcoef, gc.size());
   BEM_HIP_TRY(hipMemcpyAsync(F.gcoef, gc.data(), sizeof(double) * gc.size(),
                              hipMemcpyHostToDevice, s));
-  const cplx<R>* const* lc = nullptr;
-  int* ord = nullptr;
-  r = level_tables<R>(F, D, &lc, &ord, F.arena, s);
-  if (r) return r;
-  F.lev_lc = (const void* const*)lc;
-  F.lev_order = ord;
   BEM_HIP_TRY(hipStreamSynchronize(s));
   return 0;
 }
@@ -650,6 +632,7 @@ static int build_point_tree(Problem& P, const double* pts, FieldPoints& F, Point
     return BEM_E_INVALID;
   }
   std::vector<int> lv, lb, cl, cpt, ccnt, npt, ncnt, ns0, ns1, nsrc;
+  std::vector<std::vector<std::array<int, 3>>> lchunks(L + 1);  // (leaf, first point, count)
   std::vector<double> lc;
   int64_t near_pairs = 0;
   for (size_t q = 0; q < leaves.size(); ++q) {
@@ -658,11 +641,8 @@ static int build_point_tree(Problem& P, const double* pts, FieldPoints& F, Point
     lv.push_back(lf.level);
     lb.push_back(lf.box);
     for (int a = 0; a < 3; ++a) lc.push_back(P.lo[a] + (B.c[a] + 0.5) * P.h[lf.level]);
-    for (int a = lf.pt0; a < lf.pt1; a += PT_CHUNK) {
-      cl.push_back((int)q);
-      cpt.push_back(a);
-      ccnt.push_back(std::min(PT_CHUNK, lf.pt1 - a));
-    }
+    for (int a = lf.pt0; a < lf.pt1; a += PT_CHUNK)
+      lchunks[lf.level].push_back({(int)q, a, std::min(PT_CHUNK, lf.pt1 - a)});
     if (lf.level != L) continue;
     const int s0 = (int)nsrc.size();
     int64_t nel = 0;
@@ -681,6 +661,17 @@ static int build_point_tree(Problem& P, const double* pts, FieldPoints& F, Point
       ns1.push_back((int)nsrc.size());
     }
   }
+  // far-field chunks grouped by level (one launch per level)
+  F.chunk_off.fill(0);
+  for (int l = 2; l <= L; ++l) {
+    F.chunk_off[l] = (int)cl.size();
+    for (const auto& c : lchunks[l]) {
+      cl.push_back(c[0]);
+      cpt.push_back(c[1]);
+      ccnt.push_back(c[2]);
+    }
+  }
+  F.chunk_off[L + 1] = (int)cl.size();
   F.n_leaf = (int)leaves.size();
   F.n_chunk = (int)cl.size();
   F.n_near_chunk = (int)npt.size();
@@ -765,23 +756,35 @@ static int eval_points(FieldPoints& F, const c64* p, const c64* q, c64* acc, hip
   PointOps<R>& O = pops<R>(F);
   int r = point_far_field<R>(P, D, F, O, p, q, s);
   if (r) return r;
-  if (F.n_chunk > 0) {
-    const size_t lds = l2p_lds_bytes(F.max_order);
+  // local expansions at the points, one launch per level (chunks grouped by
+  // level, LDS sized by the level's order)
+  typedef typename std::conditional<sizeof(R) == 4, float, double>::type T;
+  const int ev = prof_begin(P, s);
+  for (int l = 2; l <= F.L; ++l) {
+    const int nc = F.chunk_off[l + 1] - F.chunk_off[l];
+    if (nc <= 0) continue;
+    const int p = D.order[l];
+    // the recurrence starts at p + 25 + 1.5 k r, r <= sqrt(3)/2 h_l
+    const int jn_top = std::min(p + 28 + (int)(1.5 * P.k * 0.87 * P.h[l]), 512);
+    const size_t lds = l2p_lds_bytes<T>(p, jn_top);
     if (lds > 65536)
-      BEM_HIP_TRY(hipFuncSetAttribute((const void*)k_points_l2p<R>,
+      BEM_HIP_TRY(hipFuncSetAttribute((const void*)k_points_l2p<R, T>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_points_l2p<R>, dim3(F.n_chunk), dim3(PT_CHUNK), lds, s,
-                       (const cplx<R>* const*)F.lev_lc, F.lev_order, F.chunk_leaf, F.chunk_pt,
-                       F.chunk_cnt, F.leaf_level, F.leaf_box, F.leaf_c, F.xyz, F.n, P.k, F.finv,
+    hipLaunchKernelGGL((k_points_l2p<R, T>), dim3(nc), dim3(PT_CHUNK), lds, s, O.Lc[l], p,
+                       jn_top, F.chunk_off[l], F.chunk_leaf, F.chunk_pt, F.chunk_cnt,
+                       F.leaf_box, F.leaf_c, F.xyz, F.n, P.k, F.finv + l * (MAXP_PT + 1),
                        F.gcoef, acc);
     BEM_LAUNCH_CHECK();
   }
+  if ((r = prof_end(P, ev, prof_slot(ST_PT_L2P, sizeof(R) == 4, false), s))) return r;
   if (F.n_near_chunk > 0) {
     const R k = (R)P.k, k_turns = (R)(P.k / (2.0 * M_PI));
+    const int ev = prof_begin(P, s);
     hipLaunchKernelGGL(k_points_p2p<R>, dim3(F.n_near_chunk), dim3(PT_CHUNK), 0, s, F.near_pt,
                        F.near_cnt, F.near_s0, F.near_s1, F.near_src, P.box_start[P.L], D.geo,
                        P.n, O.X.ps, O.X.qs, F.xyz, F.n, k, k_turns, acc);
     BEM_LAUNCH_CHECK();
+    if ((r = prof_end(P, ev, prof_slot(ST_PT_P2P, sizeof(R) == 4, false), s))) return r;
   }
   return 0;
 }

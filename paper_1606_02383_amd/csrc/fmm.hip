@@ -2516,16 +2516,28 @@ int point_far_field(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>
     z.cnt[z.n] = (int64_t)F.nbox[l] * D.ncoef[l];
     ++z.n;
   }
+  constexpr int ADJ_FLAG = 0;
+  Problem* prof = P.prof_on ? &P : nullptr;
+  PROF_BEGIN(e0);
   hipLaunchKernelGGL(k_gather_in<R>, dim3(ceil_div(P.n, 256)), dim3(256), 0, s, p, q, P.perm,
                      P.n, X.ps, X.qs, X.p64s, X.q64s, z);
   BEM_LAUNCH_CHECK();
+  PROF_END(e0, ST_GATHER);
   const int nleaf = P.nbox[L];
   const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], q ? D.p2m : D.p2m_p, X.ps, X.qs, X.M[L]};
+  PROF_BEGIN(e1);
   int r = launch_leaf_jobs<R>(&lj, &nleaf, 1, q ? 0 : 2, s);
-  if (!r) r = upward_pass(P, D, X, false, s);
+  if (r) return r;
+  PROF_END(e1, ST_P2M);
+  PROF_BEGIN(e2);
+  if ((r = upward_pass(P, D, X, false, s))) return r;
+  PROF_END(e2, ST_M2M);
   for (int l = 2; l <= L && !r; ++l) {
-    if (l >= 3) r = launch_grouped<R, 2>(O.l2l[l], false, O.Lc[l - 1], O.Lc[l], s);
-    if (!r) r = launch_grouped<R, 1>(O.m2l[l], false, X.M[l], O.Lc[l], s);
+    if (l >= 3) r = launch_grouped<R, 2>(O.l2l[l], false, O.Lc[l - 1], O.Lc[l], s, nullptr, 0,
+                                         prof, ST_L2L);
+    if (!r)
+      r = launch_grouped<R, 1>(O.m2l[l], false, X.M[l], O.Lc[l], s, nullptr, 0, prof,
+                               l == L ? ST_M2L_LEAF : ST_M2L);
   }
   return r;
 }

@@ -214,7 +214,11 @@ struct Problem {
 // profiling slots: stage + 16 * precision (0: float64, 1: float32) + 32 * adjoint
 enum {
   ST_GATHER = 0, ST_P2P, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_FINISH, ST_M2L_RED,
-  ST_M2L_LEAF, ST_M2L_LEAF_RED, ST_COUNT
+  ST_M2L_LEAF, ST_M2L_LEAF_RED,
+  // evaluation at points off the boundary: local expansions at the points,
+  // direct sums over touching leaves (its translations use ST_M2L,
+  // ST_M2L_LEAF and ST_L2L, its gather ST_GATHER, P2M ST_P2M)
+  ST_PT_L2P, ST_PT_P2P, ST_COUNT
 };
 constexpr int PROF_SLOTS = 64;
 constexpr int prof_slot(int stage, bool f32, bool adj) { return stage + 16 * f32 + 32 * adj; }
@@ -397,8 +401,7 @@ struct FieldPoints {
   double* finv = nullptr;      // 1 / f_n per level: finv[l * (MAXP_PT + 1) + n]
   double* gcoef = nullptr;     // derivative coefficients up to max_order
   c64* acc = nullptr;          // far + near sums (field, d/dx, d/dy, d/dz) per sorted point
-  const void* const* lev_lc = nullptr;  // device: locals of the point boxes per level
-  int* lev_order = nullptr;             // device: expansion order per level
+  std::array<int, MAX_LEVEL + 2> chunk_off{};  // first far-field chunk of each level
   PointOps<float> f32;
   PointOps<double> f64;
 };
