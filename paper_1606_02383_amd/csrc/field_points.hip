@@ -373,25 +373,34 @@ __global__ void __launch_bounds__(PT_CHUNK)
   g2r = wave_sum(g2r, S);
   g2i = wave_sum(g2i, S);
   if (active && sl == 0) {
-    acc[4 * i] = cadd(acc[4 * i], mk((double)fr, (double)fi));
-    acc[4 * i + 1] = cadd(acc[4 * i + 1], mk((double)g0r, (double)g0i));
-    acc[4 * i + 2] = cadd(acc[4 * i + 2], mk((double)g1r, (double)g1i));
-    acc[4 * i + 3] = cadd(acc[4 * i + 3], mk((double)g2r, (double)g2i));
+    acc[4 * i] = mk((double)fr, (double)fi);
+    acc[4 * i + 1] = mk((double)g0r, (double)g0i);
+    acc[4 * i + 2] = mk((double)g1r, (double)g1i);
+    acc[4 * i + 3] = mk((double)g2r, (double)g2i);
   }
 }
 
 // total field = incident part - phi (the representation's boundary sums are
-// -phi: phi = S q - K p), written in the caller's point order
+// -phi: phi = S q - K p, far part in acc, direct part in acc_near where
+// near_flag is set), written in the caller's point order
 __global__ void k_points_finish(const double* __restrict__ xyz, const int* __restrict__ perm,
-                                int64_t n, const c64* __restrict__ acc, double k, int has_pw,
+                                int64_t n, const c64* __restrict__ acc,
+                                const c64* __restrict__ acc_near,
+                                const uint8_t* __restrict__ near_flag, double k, int has_pw,
                                 double dx, double dy, double dz, const double* __restrict__ src,
                                 const c64* __restrict__ amp, int nsrc, c64* __restrict__ out,
                                 c64* __restrict__ grad) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double x0 = xyz[i], x1 = xyz[n + i], x2 = xyz[2 * n + i];
-  c64 f = cscale(acc[4 * i], -1.0), f0 = cscale(acc[4 * i + 1], -1.0),
-      f1 = cscale(acc[4 * i + 2], -1.0), f2 = cscale(acc[4 * i + 3], -1.0);
+  c64 a0 = acc[4 * i], a1 = acc[4 * i + 1], a2 = acc[4 * i + 2], a3 = acc[4 * i + 3];
+  if (near_flag[i]) {
+    a0 = cadd(a0, acc_near[4 * i]);
+    a1 = cadd(a1, acc_near[4 * i + 1]);
+    a2 = cadd(a2, acc_near[4 * i + 2]);
+    a3 = cadd(a3, acc_near[4 * i + 3]);
+  }
+  c64 f = cscale(a0, -1.0), f0 = cscale(a1, -1.0), f1 = cscale(a2, -1.0), f2 = cscale(a3, -1.0);
   if (has_pw) {
     double sn, cs;
     sincos(k * (dx * x0 + dy * x1 + dz * x2), &sn, &cs);
@@ -697,6 +706,12 @@ static int build_point_tree(Problem& P, const double* pts, FieldPoints& F, Point
     BEM_HIP_TRY(hipMemcpyAsync(F.xyz, xyz.data(), sizeof(double) * xyz.size(),
                                hipMemcpyHostToDevice, s));
   ARENA_ALLOC(F.arena, F.acc, std::max<int64_t>(1, 4 * n));
+  ARENA_ALLOC(F.arena, F.acc_near, std::max<int64_t>(1, 4 * n));
+  std::vector<uint8_t> flag(std::max<int64_t>(1, n), 0);
+  for (size_t c = 0; c < npt.size(); ++c)
+    for (int a = 0; a < ncnt[c]; ++a) flag[npt[c] + a] = 1;
+  ARENA_ALLOC(F.arena, F.near_flag, flag.size());
+  BEM_HIP_TRY(hipMemcpyAsync(F.near_flag, flag.data(), flag.size(), hipMemcpyHostToDevice, s));
   BEM_HIP_TRY(hipStreamSynchronize(s));
   return 0;
 }
@@ -754,8 +769,23 @@ static int eval_points(FieldPoints& F, const c64* p, const c64* q, c64* acc, hip
   Problem& P = *F.P;
   PrecisionData<R>& D = pdata<R>(P);
   PointOps<R>& O = pops<R>(F);
-  int r = point_far_field<R>(P, D, F, O, p, q, s);
+  // the direct sums need only the gathered densities: on the problem's side
+  // stream, concurrently with the far field (joined before the finish)
+  const bool near = F.n_near_chunk > 0;
+  int r = point_far_field<R>(P, D, F, O, p, q, s, near ? P.ev_fork : nullptr);
   if (r) return r;
+  if (near) {
+    BEM_HIP_TRY(hipStreamWaitEvent(P.side, P.ev_fork, 0));
+    const R k = (R)P.k, k_turns = (R)(P.k / (2.0 * M_PI));
+    const int ev = prof_begin(P, P.side);
+    hipLaunchKernelGGL(k_points_p2p<R>, dim3(F.n_near_chunk), dim3(PT_CHUNK), 0, P.side,
+                       F.near_pt, F.near_cnt, F.near_s0, F.near_s1, F.near_src,
+                       P.box_start[P.L], D.geo, P.n, O.X.ps, O.X.qs, F.xyz, F.n, k, k_turns,
+                       F.acc_near);
+    BEM_LAUNCH_CHECK();
+    if ((r = prof_end(P, ev, prof_slot(ST_PT_P2P, sizeof(R) == 4, false), P.side))) return r;
+    BEM_HIP_TRY(hipEventRecord(P.ev_join, P.side));
+  }
   // local expansions at the points, one launch per level (chunks grouped by
   // level, LDS sized by the level's order)
   typedef typename std::conditional<sizeof(R) == 4, float, double>::type T;
@@ -777,15 +807,7 @@ static int eval_points(FieldPoints& F, const c64* p, const c64* q, c64* acc, hip
     BEM_LAUNCH_CHECK();
   }
   if ((r = prof_end(P, ev, prof_slot(ST_PT_L2P, sizeof(R) == 4, false), s))) return r;
-  if (F.n_near_chunk > 0) {
-    const R k = (R)P.k, k_turns = (R)(P.k / (2.0 * M_PI));
-    const int ev = prof_begin(P, s);
-    hipLaunchKernelGGL(k_points_p2p<R>, dim3(F.n_near_chunk), dim3(PT_CHUNK), 0, s, F.near_pt,
-                       F.near_cnt, F.near_s0, F.near_s1, F.near_src, P.box_start[P.L], D.geo,
-                       P.n, O.X.ps, O.X.qs, F.xyz, F.n, k, k_turns, acc);
-    BEM_LAUNCH_CHECK();
-    if ((r = prof_end(P, ev, prof_slot(ST_PT_P2P, sizeof(R) == 4, false), s))) return r;
-  }
+  if (near) BEM_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
   return 0;
 }
 
@@ -811,8 +833,8 @@ int eval_field_grad_fmm(FieldPoints& F, const c64* p, const c64* q, const double
                       : eval_points<float>(F, p, q, F.acc, s);
   if (r) return r;
   hipLaunchKernelGGL(k_points_finish, dim3(ceil_div(F.n, 256)), dim3(256), 0, s, F.xyz, F.perm,
-                     F.n, F.acc, P.k, d ? 1 : 0, dx, dy, dz, src, amp, src ? n_src : 0, out,
-                     grad);
+                     F.n, F.acc, F.acc_near, F.near_flag, P.k, d ? 1 : 0, dx, dy, dz, src, amp,
+                     src ? n_src : 0, out, grad);
   BEM_LAUNCH_CHECK();
   return 0;
 }

@@ -2503,7 +2503,7 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
 // added atomically (a point box receives several of them in one launch).
 template <typename R>
 int point_far_field(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>& O,
-                    const c64* p, const c64* q, hipStream_t s) {
+                    const c64* p, const c64* q, hipStream_t s, hipEvent_t fork) {
   const int L = P.L;
   ExecBuf<R>& X = O.X;
   ZeroList<R> z = chain_zero_list(P, D, X, false, false);
@@ -2523,6 +2523,7 @@ int point_far_field(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>
                      P.n, X.ps, X.qs, X.p64s, X.q64s, z);
   BEM_LAUNCH_CHECK();
   PROF_END(e0, ST_GATHER);
+  if (fork) BEM_HIP_TRY(hipEventRecord(fork, s));
   const int nleaf = P.nbox[L];
   const LeafJobDev<R> lj{P.box_start[L], D.ncoef[L], q ? D.p2m : D.p2m_p, X.ps, X.qs, X.M[L]};
   PROF_BEGIN(e1);
@@ -2542,9 +2543,11 @@ int point_far_field(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>
   return r;
 }
 template int point_far_field<float>(Problem&, PrecisionData<float>&, FieldPoints&,
-                                    PointOps<float>&, const c64*, const c64*, hipStream_t);
+                                    PointOps<float>&, const c64*, const c64*, hipStream_t,
+                                    hipEvent_t);
 template int point_far_field<double>(Problem&, PrecisionData<double>&, FieldPoints&,
-                                     PointOps<double>&, const c64*, const c64*, hipStream_t);
+                                     PointOps<double>&, const c64*, const c64*, hipStream_t,
+                                     hipEvent_t);
 
 template int fmm_apply_x<float>(Problem&, PrecisionData<float>&, ExecBuf<float>&, const c64*,
                                 const c64*, c64*, hipStream_t);

@@ -400,7 +400,9 @@ struct FieldPoints {
   int max_order = 0;
   double* finv = nullptr;      // 1 / f_n per level: finv[l * (MAXP_PT + 1) + n]
   double* gcoef = nullptr;     // derivative coefficients up to max_order
-  c64* acc = nullptr;          // far + near sums (field, d/dx, d/dy, d/dz) per sorted point
+  c64* acc = nullptr;          // far-field sums (field, d/dx, d/dy, d/dz) per sorted point
+  c64* acc_near = nullptr;     // direct sums, the same layout (points of near chunks only)
+  uint8_t* near_flag = nullptr;  // per sorted point: 1 if it has direct sums
   std::array<int, MAX_LEVEL + 2> chunk_off{};  // first far-field chunk of each level
   PointOps<float> f32;
   PointOps<double> f64;
@@ -421,9 +423,10 @@ int derivative_table(Problem& P, int p, std::vector<double>& gc, DevArena& scrat
                      hipStream_t s);
 // fmm.hip: multipoles of the problem's tree for (p, q), then the locals of
 // the point boxes
+// `fork` (may be null) is recorded on s once the densities are gathered
 template <typename R>
 int point_far_field(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>& O,
-                    const c64* p, const c64* q, hipStream_t s);
+                    const c64* p, const c64* q, hipStream_t s, hipEvent_t fork);
 
 int topological_derivative(int n, const c64* p, const c64* gp, const c64* pt, const c64* gpt,
                            double cg, double cv, double* T, hipStream_t s);
