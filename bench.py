@@ -392,7 +392,9 @@ def run_topo(args):
                    "n_points": len(lat), "material": "sound-hard limit",
                    "objective": "sum |p|^2 over 8 points on the radius-3 sphere"},
         "f32": {"ms_per_step": res["f32"]["ms"], "points_per_s": len(lat) / (res["f32"]["ms"] / 1e3),
-                "T_rel_diff_vs_direct": err["f32"]},
+                "T_rel_diff_vs_direct": err["f32"],
+                "stage_ms_per_call": {f"{k_[0]}_{k_[1]}": round(v[0] / v[1], 4)
+                                      for k_, v in res["f32"]["prof"].items()}},
         "T_rel_diff_vs_direct": err["f64"],
         "direct_sum_ms": direct_ms,
         "point_set_build_s": {"f64": r64["build_s"], "f32": res["f32"]["build_s"]},
@@ -623,6 +625,9 @@ def main():
         "ir_solve": {"matvec32": info["matvec32"], "matvec64": info["matvec64"],
                      "resid": info["resid"], "rel_diff_vs_f64_solution": sol_err},
         "matvec_per_s": {"f64": rates["f64"], "f32": rates["f32"]},
+        "sampled_error": {"f64_white_noise": st["fmm_err64"], "f64_plane_wave": st["fmm_err64_smooth"],
+                          "f32_white_noise": st["fmm_err32"], "f32_plane_wave": st["fmm_err32_smooth"],
+                          "rows": 128, "reference": "rows summed directly in float64"},
         "plan_build_s": t_plan,
         "stage_ms_per_call": stages,
         "stage_ms_alone": stages_alone,
