@@ -12,7 +12,8 @@ topology loop's step 8, Sec. 3, with the boundary sums split by the FMM).
 * T_Omega from the FMM fields against T_Omega from the direct fields.
 * Edge cases: no points, points out of range, non-finite points, bad
   precision, a problem without far field (direct sum kept), a point set
-  with one point, points on box faces of the tree's grid.
+  with one point, points on box faces of the tree's grid, the second
+  problem of a two-problem plan.
 """
 import numpy as np
 import pytest
@@ -241,6 +242,17 @@ def test_fmm_points_edge_cases():
         bem.FieldPoints(plan, np.array([[np.nan, 0.0, 0.0]]))
     with pytest.raises(bem.BemError):
         bem.FieldPoints(plan, np.array([[2.0, 0.0, 0.0]]), prec=2)
+    # the second problem of a two-problem plan (its own tree, k and orders)
+    V4, T4 = icosphere(4)
+    plan2 = bem.Plan([bem.Problem(V, T, k, leaf_cap=16), bem.Problem(V4, T4, 3.0)])
+    p4 = complex_normal(rng, len(T4))
+    pts = _lattice(7, 1.8, 1.2)
+    fp = bem.FieldPoints(plan2, pts, prob=1)
+    f, gr = fp.eval_field_grad(torch.from_numpy(p4))
+    fr, grr = _oracle_field(obem.Geometry(V4, T4), 3.0, pts, p4, None)
+    tf, tg = TOL[("noise", 0)]
+    assert _rel(f.cpu().numpy(), fr) < tf and _rel(gr.cpu().numpy(), grr) < tg
+    fp.close()
     # a problem without far field: the points are summed directly
     V1, T1 = icosphere(1)
     plan1 = bem.Plan(bem.Problem(V1, T1, 1.0))
