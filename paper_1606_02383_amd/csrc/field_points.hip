@@ -640,14 +640,13 @@ static int build_point_tree(Problem& P, const double* pts, FieldPoints& F, Point
     set_error("internal: point leaves do not cover the points");
     return BEM_E_INVALID;
   }
-  std::vector<int> lv, lb, cl, cpt, ccnt, npt, ncnt, ns0, ns1, nsrc;
+  std::vector<int> lb, cl, cpt, ccnt, npt, ncnt, ns0, ns1, nsrc;
   std::vector<std::vector<std::array<int, 3>>> lchunks(L + 1);  // (leaf, first point, count)
   std::vector<double> lc;
   int64_t near_pairs = 0;
   for (size_t q = 0; q < leaves.size(); ++q) {
     const Leaf& lf = leaves[q];
     const PBox& B = T[lf.level][lf.box];
-    lv.push_back(lf.level);
     lb.push_back(lf.box);
     for (int a = 0; a < 3; ++a) lc.push_back(P.lo[a] + (B.c[a] + 0.5) * P.h[lf.level]);
     for (int a = lf.pt0; a < lf.pt1; a += PT_CHUNK)
@@ -692,7 +691,7 @@ static int build_point_tree(Problem& P, const double* pts, FieldPoints& F, Point
     return 0;
   };
   int r = 0;
-  if ((r = up_i(lv, &F.leaf_level)) || (r = up_i(lb, &F.leaf_box)) || (r = up_i(cl, &F.chunk_leaf)) ||
+  if ((r = up_i(lb, &F.leaf_box)) || (r = up_i(cl, &F.chunk_leaf)) ||
       (r = up_i(cpt, &F.chunk_pt)) || (r = up_i(ccnt, &F.chunk_cnt)) || (r = up_i(npt, &F.near_pt)) ||
       (r = up_i(ncnt, &F.near_cnt)) || (r = up_i(ns0, &F.near_s0)) || (r = up_i(ns1, &F.near_s1)) ||
       (r = up_i(nsrc, &F.near_src)) || (r = up_i(order, &F.perm)))

@@ -385,7 +385,6 @@ struct FieldPoints {
   // most 64 points; chunk_* describe the far-field (L2P) chunks, near_* the
   // chunks of leaves on the deepest level with their source-leaf lists
   int n_leaf = 0, n_chunk = 0, n_near_chunk = 0;
-  int* leaf_level = nullptr;
   int* leaf_box = nullptr;     // index among the point boxes of its level
   double* leaf_c = nullptr;    // centres, 3 per leaf
   int* chunk_leaf = nullptr;
