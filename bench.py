@@ -246,6 +246,14 @@ def run_grad(args):
     print(json.dumps(out), flush=True)
 
 
+def m2l_flops(n, nfar, p, cut):
+    """Algorithmic FLOPs of n M2L pairs at order p: 8 (p+1)^4 per pair (complex
+    multiply-add = 8), the nfar pairs across three boxes reading only the
+    (p - cut + 1)^2 input coefficients of degree <= p - cut."""
+    pf = max(0, p - cut) if cut > 0 else p
+    return 8.0 * ((n - nfar) * (p + 1) ** 4 + nfar * (p + 1) ** 2 * (pf + 1) ** 2)
+
+
 def _cpu_points(chunk):
     """Oracle state and adjoint fields, gradients and T_Omega at a few points."""
     from oracle import solve
@@ -360,7 +368,7 @@ def run_topo(args):
     st = r64["stats"]
     L = st["levels"]
     ms_leaf, calls_leaf = r64["prof"].get(("m2l_leaf", "f64", "fwd"), (0.0, 0))
-    flops = 8.0 * st["n_m2l"][L] * (st["order"][L] + 1) ** 4
+    flops = m2l_flops(st["n_m2l"][L], st["n_m2l_far"][L], st["order"][L], st["far_cut"])
     per_ms = ms_leaf / max(1, calls_leaf)
     ach = flops / (per_ms / 1e3) if per_ms > 0 else 0.0
     stages = {f"{k_[0]}_{k_[1]}": round(v[0] / v[1], 4) for k_, v in r64["prof"].items()}
@@ -491,7 +499,7 @@ def main():
         f"orders f64 {st['order64'][2:]} f32 {st['order32'][2:]}, m2l pairs {st['n_m2l'][2:]}, "
         f"P2P pairs {st['n_p2p_pairs']}, schedule f64/f32 {st['schedule']}, "
         f"P2P grid {st['p2p_grid']}, leaf M2L grid {st['m2l_grid']}, "
-        f"direct depth {st['direct_depth']}")
+        f"direct depth {st['direct_depth']}, far cut {st['far_cut']}")
     b = plan.plane_wave_rhs(d)
     if args.counters:
         for prec in (1, 0):
@@ -573,14 +581,17 @@ def main():
     alone = plan.profile_stop()
     stages_alone = {f"{k[0]}_{k[1]}_{k[2]}": round(v[0] / v[1], 4) for k, v in alone.items()}
     # dominant kernel: the leaf-level float32 M2L GEMM (one launch per
-    # product); algorithmic flops per launch = 8 (p_L + 1)^4 per M2L pair
+    # product); algorithmic flops per launch = 8 (p_L + 1)^4 per M2L pair,
+    # 8 (p_L + 1)^2 (p_L - far_cut + 1)^2 for the pairs across three boxes
     L = st["leaf_level"]
     leaf_ms, leaf_calls = leaf_prof.get(("m2l_leaf", "f32", "fwd"), (0.0, 0))
-    flops_leaf = 8.0 * st["n_m2l"][L] * (st["order32"][L] + 1) ** 4
+    fc32 = st["far_cut"][1]
+    flops_leaf = m2l_flops(st["n_m2l"][L], st["n_m2l_far"][L], st["order32"][L], fc32)
     per_launch_ms = leaf_ms / max(1, leaf_calls)
     achieved = flops_leaf / (per_launch_ms / 1e3) if per_launch_ms > 0 else 0.0
     coarse_ms, coarse_calls = prof.get(("m2l", "f32", "fwd"), (0.0, 0))
-    flops_coarse = sum(8.0 * st["n_m2l"][l] * (st["order32"][l] + 1) ** 4 for l in range(2, L))
+    flops_coarse = sum(m2l_flops(st["n_m2l"][l], st["n_m2l_far"][l], st["order32"][l], fc32)
+                       for l in range(2, L))
     coarse_launch_ms = coarse_ms / max(1, coarse_calls)
     roofline = {"kernel": f"k_grouped_gemm<float,{st['m2l_tile32'][L]},false,0> "
                           f"(leaf-level M2L, float32)", "bound": "mfma",
@@ -619,7 +630,8 @@ def main():
                    "rhs": "plane wave, seeded direction", "tol": wl.tol,
                    "solver": "GMRES(50), float32 inner / float64 refinement",
                    "inner_tol": args.inner_tol, "leaf_level": L, "schedule": st["schedule"],
-                   "order32": st["order32"][2:], "order64": st["order64"][2:]},
+                   "order32": st["order32"][2:], "order64": st["order64"][2:],
+                   "far_cut": st["far_cut"]},
         "f64_gmres": {"matvecs": info64["matvec64"], "ms": t64_solve * 1e3,
                       "matvecs_per_s": info64["matvec64"] / t64_solve},
         "ir_solve": {"matvec32": info["matvec32"], "matvec64": info["matvec64"],

@@ -168,6 +168,12 @@ typedef struct {
                               plan creation (see fmm_tol; 0: direct sum)    */
   double fmm_err64_smooth; /* the same on a plane-wave density             */
   double fmm_err32_smooth;
+  int32_t far_cut[2];      /* orders dropped from the multipole side of the M2L
+                              translations across three boxes, float64 / float32
+                              (chosen by the calibration: they converge much
+                              faster than those across two)                    */
+  int64_t n_m2l_far[22];   /* of the multipole-to-local pairs per level, those
+                              across three boxes (Chebyshev distance 3)        */
 } bem_plan_stats;
 
 /* Build a plan for n_probs problems: everything the products of Sec. 2.3
@@ -307,6 +313,10 @@ typedef struct {
   int64_t n_leaf;                    /* point boxes evaluated (leaves) */
   int64_t n_near_pairs;              /* point x element pairs summed directly */
   int64_t device_bytes;
+  int64_t n_m2l_far[22];             /* of the translations, those across three
+                                        boxes or more                         */
+  int32_t far_cut;                   /* input orders cut from those (0: the
+                                        point-box translations use full orders) */
 } bem_field_points_stats;
 int bem_field_points_get_stats(const bem_field_points* fp, bem_field_points_stats* st);
 

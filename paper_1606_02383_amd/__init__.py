@@ -91,14 +91,16 @@ class _Stats(ctypes.Structure):
                 ("schedule", ctypes.c_int32 * 2), ("p2p_grid", ctypes.c_int32 * 2),
                 ("m2l_grid", ctypes.c_int32 * 2), ("direct_depth", ctypes.c_int32 * 2),
                 ("fmm_err64", ctypes.c_double), ("fmm_err32", ctypes.c_double),
-                ("fmm_err64_smooth", ctypes.c_double), ("fmm_err32_smooth", ctypes.c_double)]
+                ("fmm_err64_smooth", ctypes.c_double), ("fmm_err32_smooth", ctypes.c_double),
+                ("far_cut", ctypes.c_int32 * 2), ("n_m2l_far", ctypes.c_int64 * 22)]
 
 
 class _PointStats(ctypes.Structure):
     _fields_ = [("n_pts", ctypes.c_int64), ("levels", ctypes.c_int32),
                 ("n_box", ctypes.c_int32 * 22), ("n_m2l", ctypes.c_int64 * 22),
                 ("order", ctypes.c_int32 * 22), ("n_leaf", ctypes.c_int64),
-                ("n_near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("n_near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("n_m2l_far", ctypes.c_int64 * 22), ("far_cut", ctypes.c_int32)]
 
 
 _LIB = None
@@ -278,7 +280,8 @@ class Plan:
                     schedule=list(st.schedule), p2p_grid=list(st.p2p_grid),
                     m2l_grid=list(st.m2l_grid), direct_depth=list(st.direct_depth),
                     fmm_err64=st.fmm_err64, fmm_err32=st.fmm_err32,
-                    fmm_err64_smooth=st.fmm_err64_smooth, fmm_err32_smooth=st.fmm_err32_smooth)
+                    fmm_err64_smooth=st.fmm_err64_smooth, fmm_err32_smooth=st.fmm_err32_smooth,
+                    far_cut=list(st.far_cut), n_m2l_far=list(st.n_m2l_far)[:L + 1])
 
     # ---- products
     def matvec(self, p, q=None, prec=BEM_C128, prob=0, out=None):
@@ -591,7 +594,8 @@ class FieldPoints:
         return dict(n_pts=st.n_pts, levels=L, n_box=list(st.n_box)[:L + 1],
                     n_m2l=list(st.n_m2l)[:L + 1], order=list(st.order)[:L + 1],
                     n_leaf=st.n_leaf, n_near_pairs=st.n_near_pairs,
-                    device_bytes=st.device_bytes)
+                    device_bytes=st.device_bytes, n_m2l_far=list(st.n_m2l_far)[:L + 1],
+                    far_cut=st.far_cut)
 
     def eval_field_grad(self, p, q=None, direction=None, src=None, amp=None):
         """Total field (n,) and gradient (n, 3) at the points, as

@@ -268,13 +268,55 @@ static int calibrate_one(Problem& P, PrecisionData<R>& D, double tol, bool may_l
     }
   }
   if (!built_is_best && (r = build(sc, sl, &e))) return r;
+  // translations across three boxes converge much faster than those across
+  // two: drop input orders from them while the target holds
+  if (may_lower) {
+    int fc = D.far_cut;
+    for (;;) {
+      double e2 = 0;
+      D.far_cut = fc + 1;
+      if ((r = build(sc, sl, &e2))) return r;
+      if (e2 > target || fc + 1 >= lowest()) {
+        D.far_cut = fc;
+        if ((r = build(sc, sl, &e))) return r;
+        break;
+      }
+      fc = D.far_cut;
+      e = e2;
+    }
+  }
   return 0;
+}
+
+// Without a float32 target the float32 orders stay at the level rule; the
+// input cut of the translations across three boxes is still taken as far as
+// it leaves both sampled errors within 25% of the uncut ones.
+template <typename R>
+static int cut_far_relative(Problem& P, PrecisionData<R>& D, hipStream_t s) {
+  const double w0 = D.err, s0 = D.err_smooth;
+  if (!(w0 > 0) || !(s0 > 0)) return 0;
+  int lowest = 1 << 20;
+  for (int l = 2; l <= P.L; ++l) lowest = std::min(lowest, D.order[l]);
+  int fc = D.far_cut, r = 0;
+  for (;;) {
+    double e = 0;
+    D.far_cut = fc + 1;
+    if ((r = rebuild_precision<R>(P, D, D.shift_c, D.shift, s))) return r;
+    if ((r = measure_error<R>(P, D, s, &e))) return r;
+    if (D.err > 1.25 * w0 || D.err_smooth > 1.25 * s0 || fc + 1 >= lowest) {
+      D.far_cut = fc;
+      if ((r = rebuild_precision<R>(P, D, D.shift_c, D.shift, s))) return r;
+      return measure_error<R>(P, D, s, &e);
+    }
+    fc = D.far_cut;
+  }
 }
 
 int calibrate_orders(Problem& P, hipStream_t s) {
   if (P.direct || P.L < 2) return 0;
   int r = calibrate_one<double>(P, P.f64, P.fmm_tol64, true, s);
   if (!r) r = calibrate_one<float>(P, P.f32, P.fmm_tol32, false, s);
+  if (!r && !(P.fmm_tol32 > 0) && P.order32_req <= 0) r = cut_far_relative<float>(P, P.f32, s);
   return r;
 }
 
@@ -414,6 +456,7 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
   st->n_p2p_pairs = P->n_p2p_pairs;
   for (int l = 0; l <= MAX_LEVEL; ++l) {
     st->n_m2l[l] = P->n_m2l[l];
+    st->n_m2l_far[l] = P->n_m2l_far[l];
     st->order64[l] = P->f64.order[l];
     st->order32[l] = P->f32.order[l];
     st->box_size[l] = P->h[l];
@@ -423,6 +466,8 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
   st->fmm_err32 = P->direct ? 0.0 : P->f32.err;
   st->fmm_err64_smooth = P->direct ? 0.0 : P->f64.err_smooth;
   st->fmm_err32_smooth = P->direct ? 0.0 : P->f32.err_smooth;
+  st->far_cut[0] = P->f64.far_cut;
+  st->far_cut[1] = P->f32.far_cut;
   st->tuned_ms = P->tuned_ms;
   for (int l = 0; l < 22; ++l) st->m2l_tile32[l] = (l <= P->L) ? P->f32.m2l[l].ct : 0;
   st->schedule[0] = P->sched[0];
@@ -599,11 +644,13 @@ int bem_field_points_get_stats(const bem_field_points* fp, bem_field_points_stat
   for (int l = 0; l <= MAX_LEVEL; ++l) {
     st->n_box[l] = F.nbox[l];
     st->n_m2l[l] = F.n_m2l[l];
+    st->n_m2l_far[l] = F.n_m2l_far[l];
     st->order[l] = F.prec == 0 ? P.f64.order[l] : P.f32.order[l];
   }
   st->n_leaf = F.n_leaf;
   st->n_near_pairs = F.n_near_pairs;
   st->device_bytes = F.arena.bytes;
+  st->far_cut = 0;  // point-box translations use full orders
   return BEM_OK;
 }
 

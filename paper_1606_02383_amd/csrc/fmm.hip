@@ -705,6 +705,7 @@ struct GemmJobDev {
   const int* tile_npairs;
   const int* tile_row0;
   const int* group_slot;
+  const int* group_kc;  // input coefficients read per group (null: all)
   const int* pair_dst;
   const int* pair_src;
   const cplx<R>* mats;
@@ -777,6 +778,9 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
   const int grp = J.tile_group[tile], p0 = J.tile_pair0[tile], np = J.tile_npairs[tile];
   const int r0 = J.tile_row0[tile];
   const int slot = J.group_slot[grp];
+  // translations across three boxes read fewer input coefficients (their
+  // stored operator is zero beyond them)
+  const int kc = J.group_kc ? min(mat_cols, J.group_kc[grp]) : mat_cols;
   const int out_rows = ADJ ? mat_cols : mat_rows;  // rows of the effective op
   const int in_cols = ADJ ? mat_rows : mat_cols;
   const cplx<R>* M = J.mats + (int64_t)slot * mat_rows * mat_cols;
@@ -850,7 +854,7 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
       }
     }
   };
-  const int nchunk = (in_cols + G_KC - 1) / G_KC;
+  const int nchunk = ((ADJ ? in_cols : kc) + G_KC - 1) / G_KC;
   load(0);
   store(0);
   __syncthreads();
@@ -1484,6 +1488,7 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
     J.tile_npairs = adj ? op.tile_npairs_adj : op.tile_npairs;
     J.tile_row0 = adj ? op.tile_row0_adj : op.tile_row0;
     J.group_slot = op.group_slot;
+    J.group_kc = adj ? nullptr : op.group_kc;
     J.pair_dst = adj ? op.pair_dst_adj : op.pair_dst;
     J.pair_src = adj ? op.pair_src_adj : op.pair_src;
     J.mats = via_fwd ? op.mats_h : op.mats;

@@ -44,6 +44,10 @@ struct GroupedOp {
   int* tile_npairs = nullptr;
   int* tile_row0 = nullptr;
   int* group_slot = nullptr;       // device: group id -> matrix slot
+  // device, group id -> input coefficients the forward product reads (null:
+  // all); the stored operator is zero beyond them, so the adjoint (which
+  // reads every row of the stored conjugate transpose) stays its transpose
+  int* group_kc = nullptr;
   cplx<R>* mats = nullptr;         // device: n_slots x rows x cols
   // M2L only: the conjugate transposes (n_slots x cols x rows), so that the
   // adjoint product runs the forward kernel's operand path
@@ -93,6 +97,10 @@ struct PrecisionData {
   DevArena ops;
   int shift = 0;       // order shifts applied to the level rule (calibration):
   int shift_c = 0;     //   the leaf level's and the coarser levels'
+  // orders dropped from the multipole side of M2L translations across three
+  // boxes (Chebyshev distance 3, which converge much faster than those across
+  // two): their operators read (p_l - far_cut + 1)^2 input coefficients
+  int far_cut = 0;
   double err = -1.0;   // sampled relative error of the product on white-noise
                        // densities (< 0: not measured)
   double err_smooth = -1.0;  // the same on a plane-wave density
@@ -169,6 +177,7 @@ struct Problem {
   std::array<int*, MAX_LEVEL + 1> box_parent{};
   std::array<double, MAX_LEVEL + 1> h{};          // box side per level
   std::array<int64_t, MAX_LEVEL + 1> n_m2l{};
+  std::array<int64_t, MAX_LEVEL + 1> n_m2l_far{};  // of them across three boxes
   int* elem_leaf = nullptr;                        // sorted element -> leaf
   int* u_ptr = nullptr;                            // leaf U lists (CSR)
   int* u_idx = nullptr;
@@ -381,6 +390,7 @@ struct FieldPoints {
   int L = 0;              // deepest point level (the problem's leaf level)
   std::array<int, MAX_LEVEL + 1> nbox{};
   std::array<int64_t, MAX_LEVEL + 1> n_m2l{};
+  std::array<int64_t, MAX_LEVEL + 1> n_m2l_far{};  // of them across three boxes or more
   // leaves (boxes without children) in point order, cut into chunks of at
   // most 64 points; chunk_* describe the far-field (L2P) chunks, near_* the
   // chunks of leaves on the deepest level with their source-leaf lists
