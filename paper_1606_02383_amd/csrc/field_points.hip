@@ -294,11 +294,16 @@ __global__ void __launch_bounds__(PT_CHUNK)
 //   grad G = G' u rv,  grad dG/dn_y = -(G'' - G' u)(rv.n_y) u^2 rv - G' u n_y.
 // One wave per chunk of a leaf's points: lane = point * S + slice, the S
 // slices of a point split the elements and are summed by lane shuffles.
+// The elements of the touching leaves are staged through LDS in batches of
+// 64 (one per lane, coalesced loads; rule points, normal, the densities
+// with their weight folded in), then read back as broadcasts.
 template <typename R>
 __device__ __forceinline__ R wave_sum(R v, int S) {
   for (int o = S >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+
+constexpr int PT_MAX_NEAR = 27;  // touching leaves of a point leaf
 
 template <typename R>
 __global__ void __launch_bounds__(PT_CHUNK)
@@ -308,8 +313,23 @@ __global__ void __launch_bounds__(PT_CHUNK)
                  const R* __restrict__ geo, int64_t ne, const cplx<R>* __restrict__ ps,
                  const cplx<R>* __restrict__ qs, const double* __restrict__ xyz, int64_t n,
                  R k, R k_turns, c64* __restrict__ acc) {
+  __shared__ int s_pref[PT_MAX_NEAR + 1], s_first[PT_MAX_NEAR];
+  __shared__ R s_y[9][PT_CHUNK], s_n[3][PT_CHUNK], s_d[4][PT_CHUNK];
   const int c = blockIdx.x, lane = threadIdx.x;
   const int cnt = near_cnt[c];
+  const int j0 = near_s0[c], nl = near_s1[c] - j0;
+  // prefix counts of the touching leaves' element ranges
+  if (lane < nl) {
+    const int sleaf = near_src[j0 + lane];
+    s_first[lane] = bstart[sleaf];
+    s_pref[lane + 1] = bstart[sleaf + 1] - bstart[sleaf];
+  }
+  if (lane == 0) s_pref[0] = 0;
+  __syncthreads();
+  if (lane == 0)
+    for (int j = 1; j <= nl; ++j) s_pref[j] += s_pref[j - 1];
+  __syncthreads();
+  const int total = s_pref[nl];
   int S = 1;
   while (S * 2 * cnt <= PT_CHUNK) S *= 2;
   const int ip = lane / S, sl = lane % S;
@@ -317,40 +337,53 @@ __global__ void __launch_bounds__(PT_CHUNK)
   const int64_t i = near_pt[c] + (active ? ip : 0);
   const R x0 = (R)xyz[i], x1 = (R)xyz[n + i], x2 = (R)xyz[2 * n + i];
   R fr = 0, fi = 0, g0r = 0, g0i = 0, g1r = 0, g1i = 0, g2r = 0, g2i = 0;
-  if (active) {
-    for (int j = near_s0[c]; j < near_s1[c]; ++j) {
-      const int sleaf = near_src[j];
-      const int e1 = bstart[sleaf + 1];
-      for (int e = bstart[sleaf] + sl; e < e1; e += S) {
-        const R w = geo[GEO_AREA * ne + e] * R(INV4PI_PT / 3.0);
-        const cplx<R> pv = ps[e], qv = qs[e];
-        const R pr = pv.re * w, pi = pv.im * w, qr = qv.re * w, qi = qv.im * w;
-        const R ny0 = geo[GEO_NX * ne + e], ny1 = geo[GEO_NY * ne + e],
-                ny2 = geo[GEO_NZ * ne + e];
+  for (int b0 = 0; b0 < total; b0 += PT_CHUNK) {
+    const int v = b0 + lane;
+    if (v < total) {
+      int j = 0;
+      while (j + 1 < nl && s_pref[j + 1] <= v) ++j;
+      const int64_t e = s_first[j] + (v - s_pref[j]);
+      for (int q = 0; q < 9; ++q) s_y[q][lane] = geo[(GEO_QX0 + q) * ne + e];
+      s_n[0][lane] = geo[GEO_NX * ne + e];
+      s_n[1][lane] = geo[GEO_NY * ne + e];
+      s_n[2][lane] = geo[GEO_NZ * ne + e];
+      const R w = geo[GEO_AREA * ne + e] * R(INV4PI_PT / 3.0);
+      const cplx<R> pv = ps[e], qv = qs[e];
+      s_d[0][lane] = pv.re * w;
+      s_d[1][lane] = pv.im * w;
+      s_d[2][lane] = qv.re * w;
+      s_d[3][lane] = qv.im * w;
+    }
+    __syncthreads();
+    const int nb = min(PT_CHUNK, total - b0);
+    if (active) {
+      for (int u = sl; u < nb; u += S) {
+        const R pr = s_d[0][u], pi = s_d[1][u], qr = s_d[2][u], qi = s_d[3][u];
+        const R ny0 = s_n[0][u], ny1 = s_n[1][u], ny2 = s_n[2][u];
 #pragma unroll
         for (int qq = 0; qq < 3; ++qq) {
-          const R r0 = x0 - geo[(GEO_QX0 + 3 * qq) * ne + e];
-          const R r1 = x1 - geo[(GEO_QX0 + 3 * qq + 1) * ne + e];
-          const R r2 = x2 - geo[(GEO_QX0 + 3 * qq + 2) * ne + e];
+          const R r0 = x0 - s_y[3 * qq][u];
+          const R r1 = x1 - s_y[3 * qq + 1][u];
+          const R r2 = x2 - s_y[3 * qq + 2][u];
           const R rr = r0 * r0 + r1 * r1 + r2 * r2;
-          const R u = rsqrt_r<R>(rr);
+          const R uu = rsqrt_r<R>(rr);
           R sn, cs;
-          phase<R>(rr * u, k, k_turns, &sn, &cs);
-          const R Gr = cs * u, Gi = sn * u;
+          phase<R>(rr * uu, k, k_turns, &sn, &cs);
+          const R Gr = cs * uu, Gi = sn * uu;
           // G' = G (ik - u), G'' = G ((ik - u)^2 + u^2) = G (2 u^2 - k^2 - 2 i k u)
-          const R G1r = -Gr * u - Gi * k, G1i = Gr * k - Gi * u;
-          const R ar = R(2) * u * u - k * k, ai = R(-2) * k * u;
+          const R G1r = -Gr * uu - Gi * k, G1i = Gr * k - Gi * uu;
+          const R ar = R(2) * uu * uu - k * k, ai = R(-2) * k * uu;
           const R G2r = Gr * ar - Gi * ai, G2i = Gr * ai + Gi * ar;
           const R rny = r0 * ny0 + r1 * ny1 + r2 * ny2;
           // dG/dn_y = -G' u rny
-          const R Gyr = -G1r * u * rny, Gyi = -G1i * u * rny;
+          const R Gyr = -G1r * uu * rny, Gyi = -G1i * uu * rny;
           // phi: G q - G_y p
           fr += Gr * qr - Gi * qi - (Gyr * pr - Gyi * pi);
           fi += Gr * qi + Gi * qr - (Gyr * pi + Gyi * pr);
           // grad: coefficient of rv: G' u q + (G'' - G' u) rny u^2 p; of n_y: G' u p
-          const R h = rny * u * u;
-          const R dr = (G2r - G1r * u) * h, di = (G2i - G1i * u) * h;
-          const R a1r = G1r * u, a1i = G1i * u;  // G' u
+          const R h = rny * uu * uu;
+          const R dr = (G2r - G1r * uu) * h, di = (G2i - G1i * uu) * h;
+          const R a1r = G1r * uu, a1i = G1i * uu;  // G' u
           const R crv_r = a1r * qr - a1i * qi + dr * pr - di * pi;
           const R crv_i = a1r * qi + a1i * qr + dr * pi + di * pr;
           const R cn_r = a1r * pr - a1i * pi, cn_i = a1r * pi + a1i * pr;
@@ -363,6 +396,7 @@ __global__ void __launch_bounds__(PT_CHUNK)
         }
       }
     }
+    __syncthreads();
   }
   fr = wave_sum(fr, S);
   fi = wave_sum(fi, S);
