@@ -2504,8 +2504,10 @@ int fmm_apply_adjoint(Problem& P, PrecisionData<R>& D, const c64* y, c64* u, c64
 // Far field at evaluation points off the boundary: the problem's multipoles
 // for (p, q) (gather, P2M, upward pass, as in a product), then the locals of
 // the point boxes level by level: L2L from the parent point box onto the
-// cleared locals (one pair per child), then the M2L from the source boxes,
-// added atomically (a point box receives several of them in one launch).
+// cleared locals (one pair per child), then the M2L from the source boxes
+// (a point box receives several of them in one launch): float32 writes
+// per-pair outputs and sums them per box in a fixed order, float64 adds
+// atomically.
 template <typename R>
 int point_far_field(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>& O,
                     const c64* p, const c64* q, hipStream_t s, hipEvent_t fork) {
@@ -2541,7 +2543,10 @@ int point_far_field(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>
   for (int l = 2; l <= L && !r; ++l) {
     if (l >= 3) r = launch_grouped<R, 2>(O.l2l[l], false, O.Lc[l - 1], O.Lc[l], s, nullptr, 0,
                                          prof, ST_L2L);
-    if (!r)
+    if (!r && O.cbuf)  // per-pair outputs, then the fixed-order sums
+      r = launch_grouped<R, 0>(O.m2l[l], false, X.M[l], O.Lc[l], s, O.cbuf + O.cbuf_off[l], 1,
+                               prof, l == L ? ST_M2L_LEAF : ST_M2L);
+    else if (!r)
       r = launch_grouped<R, 1>(O.m2l[l], false, X.M[l], O.Lc[l], s, nullptr, 0, prof,
                                l == L ? ST_M2L_LEAF : ST_M2L);
   }

@@ -1063,6 +1063,7 @@ int build_point_ops(Problem& P, PrecisionData<R>& D, const PointLists& lists, Fi
       BEM_HIP_TRY(hipMemcpyAsync(*d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
     return 0;
   };
+  int64_t cbuf_count = 0;
   for (int l = 2; l <= L; ++l) {
     const int p = D.order[l];
     // ---- M2L: one matrix per offset present ----
@@ -1109,6 +1110,12 @@ int build_point_ops(Problem& P, PrecisionData<R>& D, const PointLists& lists, Fi
       if (!r) r = finish_grouped<R>(op, d0, s0, c0, np, PT_CODES, slot, F.arena, scratch, s);
       if (r) return r;
       F.n_m2l[l] = np;
+      if (sizeof(R) == 4) {
+        r = build_reduce_lists<R>(op, F.nbox[l], F.arena, scratch, s);
+        if (r) return r;
+        O.cbuf_off[l] = cbuf_count;
+        cbuf_count += (int64_t)np * D.ncoef[l];
+      }
     }
     // ---- L2L from the parent point boxes (level l - 1) ----
     if (l >= 3) {
@@ -1139,6 +1146,7 @@ int build_point_ops(Problem& P, PrecisionData<R>& D, const PointLists& lists, Fi
     ARENA_ALLOC(F.arena, O.Lc[l], std::max<int64_t>(1, (int64_t)F.nbox[l] * D.ncoef[l]));
     ARENA_ALLOC(F.arena, O.X.M[l], std::max<int64_t>(1, (int64_t)P.nbox[l] * D.ncoef[l]));
   }
+  if (sizeof(R) == 4) ARENA_ALLOC(F.arena, O.cbuf, std::max<int64_t>(1, cbuf_count));
   ARENA_ALLOC(F.arena, O.X.ps, P.n);
   ARENA_ALLOC(F.arena, O.X.qs, P.n);
   ARENA_ALLOC(F.arena, O.X.p64s, P.n);

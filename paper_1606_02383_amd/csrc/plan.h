@@ -372,6 +372,12 @@ struct PointOps {
   std::array<GroupedOp<R>, MAX_LEVEL + 1> l2l{};  // point boxes level l - 1 -> l (index l)
   std::array<cplx<R>*, MAX_LEVEL + 1> Lc{};       // locals of the point boxes
   ExecBuf<R> X;                                    // M[l], ps, qs, p64s, q64s only
+  // float32: per-pair M2L outputs of every level (offset cbuf_off[l]),
+  // summed per point box in a fixed order (float64 adds atomically: its
+  // per-pair buffer would take gigabytes and its products are bound by the
+  // matrix cores)
+  cplx<R>* cbuf = nullptr;
+  std::array<int64_t, MAX_LEVEL + 1> cbuf_off{};
 };
 
 // Host-side lists of the point octree (inputs of the operator build).
