@@ -263,3 +263,50 @@ def test_fmm_points_edge_cases():
     fr, grr = _oracle_field(obem.Geometry(V1, T1), 1.0, pts, p1, None)
     assert _rel(f.cpu().numpy(), fr) < 1e-12 and _rel(gr.cpu().numpy(), grr) < 1e-12
     fp.close()
+
+
+def test_design_lattice_at_full_size_against_oracle():
+    """The benchmark's configuration: the 81920-element sphere at k = 8, the
+    101^3 design-domain lattice (points outside |x| > 1.02), state and
+    adjoint densities from the GPU solves; fields, gradients and T_Omega by
+    the FMM on the whole lattice, compared on 40 sampled points with the
+    oracle's dense sums over all elements for the same densities."""
+    import torch
+    bem = _lib()
+    from workloads import WORKLOADS
+    wl = WORKLOADS["sphere81920_k8"]
+    V, T = wl.mesh_arrays()
+    rng = np.random.default_rng(wl.seed)
+    d = unit_directions(rng, 1)[0]
+    obs = 3.0 * unit_directions(rng, 8)
+    t = np.linspace(-1.25, 1.25, 101)
+    X = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    lat = X[np.linalg.norm(X, axis=1) > 1.02]
+    plan = bem.Plan(bem.Problem(V, T, wl.k, leaf_cap=64))
+    opts = bem.GmresOptions(tol=1e-6, mode=1)
+    p, info = plan.solve(plan.plane_wave_rhs(d), opts=opts)
+    pobs = plan.eval_field(p, None, obs, direction=d).cpu().numpy()
+    amp = 2.0 * np.conj(pobs)
+    pt, info_t = plan.solve(plan.point_source_rhs(obs, amp), opts=opts)
+    assert info["converged"] and info_t["converged"]
+    pick = np.sort(np.random.default_rng(77).choice(len(lat), 40, replace=False))
+    x = lat[pick]
+    g = obem.Geometry(V, T)
+    pn, ptn = p.cpu().numpy(), pt.cpu().numpy()
+    fsr, gsr = _oracle_field(g, wl.k, x, pn, None, d=d, chunk=10)
+    far_, gar = _oracle_field(g, wl.k, x, ptn, None, src=obs, amp=amp, chunk=10)
+    Tr = solve.topological_derivative(fsr, gsr, far_, gar, 1.0, np.inf, 1.0, np.inf, wl.k)
+    # bars: three times the measured errors (float64 4e-8 / 3e-6 / 1.1e-6,
+    # float32 2e-5 / 2.6e-4 / 1.6e-4 for field / gradient / T_Omega)
+    for prec, tf, tg, tt in ((bem.BEM_C128, 1.5e-7, 1e-5, 4e-6), (bem.BEM_C64, 6e-5, 8e-4, 5e-4)):
+        fp = bem.FieldPoints(plan, lat, prec=prec)
+        fs, gs = fp.eval_field_grad(p, None, direction=d)
+        fa, ga = fp.eval_field_grad(pt, None, src=obs, amp=amp)
+        Tg = bem.topological_derivative(fs, gs, fa, ga, omega=wl.k).cpu().numpy()[pick]
+        e = [_rel(fs.cpu().numpy()[pick], fsr), _rel(gs.cpu().numpy()[pick], gsr),
+             _rel(fa.cpu().numpy()[pick], far_), _rel(ga.cpu().numpy()[pick], gar), _rel(Tg, Tr)]
+        _log(f"case: {len(lat)} lattice points, sphere81920 k = 8, prec {prec}: state field / "
+             f"gradient, adjoint field / gradient, T_Omega on 40 sampled points vs oracle "
+             f"{['%.2e' % v for v in e]}")
+        assert max(e[0], e[2]) < tf and max(e[1], e[3]) < tg and e[4] < tt
+        fp.close()
