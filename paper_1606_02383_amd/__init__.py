@@ -18,8 +18,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["Plan", "Problem", "GmresOptions", "ObjectiveJ", "load_library", "LIB_PATH",
-           "BEM_C128", "BEM_C64"]
+__all__ = ["Plan", "Problem", "GmresOptions", "ObjectiveJ", "FieldPoints",
+           "topological_derivative", "BemError", "load_library", "LIB_PATH", "BEM_C128",
+           "BEM_C64"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libbemfmm.so")
 BEM_C128 = 0
