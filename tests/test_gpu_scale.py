@@ -2,7 +2,9 @@
 
 * 20480-element sphere, k = 4 and 81920-element sphere, k = 8: the FMM
   product (float64 and float32) against the oracle's exact rows on seeded
-  random densities; the adjoint against the oracle's exact columns;
+  random densities; the adjoint against the oracle's exact columns; the
+  same on the 49152-element cube (k = 6), whose edges and corners put many
+  elements in the near field of elements on other faces;
 * solves: the float64 GMRES(50) and the mixed-precision solve reach the true
   relative residual 1e-6, and the oracle's own rows confirm the residual;
 * 49152-element cube, k = 6: J = sum |p(x_obs)|^2 with an admittance
@@ -49,7 +51,8 @@ def _setup(name):
     return _CACHE[name]
 
 
-@pytest.mark.parametrize("name,nrows", [("sphere20480_k4", 96), ("sphere81920_k8", 48)])
+@pytest.mark.parametrize("name,nrows", [("sphere20480_k4", 96), ("sphere81920_k8", 48),
+                                        ("cube49152_k6", 48)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_matvec_sampled_rows(name, nrows, prec):
     import torch
@@ -95,7 +98,8 @@ def test_matvec_plane_wave_density_rows(name, nrows):
     assert e32 < 4 * st["fmm_err32_smooth"] and st["fmm_err32_smooth"] < 4 * e32
 
 
-@pytest.mark.parametrize("name,ncols", [("sphere20480_k4", 48), ("sphere81920_k8", 24)])
+@pytest.mark.parametrize("name,ncols", [("sphere20480_k4", 48), ("sphere81920_k8", 24),
+                                        ("cube49152_k6", 24)])
 def test_adjoint_sampled_columns(name, ncols):
     import torch
     wl, V, T, g, plan = _setup(name)
