@@ -105,6 +105,16 @@ typedef struct {
   double fmm_tol32;    /* same for the float32 product, whose orders are
                           only raised above the rule (<= 0: the rule)     */
   int32_t p_max;       /* largest expansion order (<= 0 -> 40, > 40 invalid) */
+  int32_t m2l_rot;     /* multipole-to-local variant per level (the paper's
+                          low-frequency FMM fixes none, Sec. 2.3): 0 dense
+                          or rotation-based (point-and-shoot: rotate the
+                          multipole onto the translation axis, translate
+                          along it, rotate back; ~3.3 (p+1)^3 instead of
+                          (p+1)^4 operations per pair, ahead as the orders
+                          grow with k times the box size), whichever the
+                          plan times faster on the level; 1 dense only;
+                          2 rotation-based on every level of order <= 23;
+                          else BEM_E_INVALID.  Products agree to rounding. */
 } bem_problem;
 
 typedef struct {
@@ -174,6 +184,8 @@ typedef struct {
                               faster than those across two)                    */
   int64_t n_m2l_far[22];   /* of the multipole-to-local pairs per level, those
                               across three boxes (Chebyshev distance 3)        */
+  int32_t m2l_rot64[22];   /* 1 where the level's float64 / float32 M2L is */
+  int32_t m2l_rot32[22];   /* rotation-based (see bem_problem.m2l_rot)     */
 } bem_plan_stats;
 
 /* Build a plan for n_probs problems: everything the products of Sec. 2.3

@@ -55,7 +55,7 @@ class _Problem(ctypes.Structure):
                 ("leaf_cap", ctypes.c_int32), ("leaf_level", ctypes.c_int32),
                 ("order64", ctypes.c_int32), ("order32", ctypes.c_int32),
                 ("fmm_tol", ctypes.c_double), ("fmm_tol32", ctypes.c_double),
-                ("p_max", ctypes.c_int32)]
+                ("p_max", ctypes.c_int32), ("m2l_rot", ctypes.c_int32)]
 
 
 class _Opts(ctypes.Structure):
@@ -93,7 +93,8 @@ class _Stats(ctypes.Structure):
                 ("m2l_grid", ctypes.c_int32 * 2), ("direct_depth", ctypes.c_int32 * 2),
                 ("fmm_err64", ctypes.c_double), ("fmm_err32", ctypes.c_double),
                 ("fmm_err64_smooth", ctypes.c_double), ("fmm_err32_smooth", ctypes.c_double),
-                ("far_cut", ctypes.c_int32 * 2), ("n_m2l_far", ctypes.c_int64 * 22)]
+                ("far_cut", ctypes.c_int32 * 2), ("n_m2l_far", ctypes.c_int64 * 22),
+                ("m2l_rot64", ctypes.c_int32 * 22), ("m2l_rot32", ctypes.c_int32 * 22)]
 
 
 class _PointStats(ctypes.Structure):
@@ -200,6 +201,7 @@ class Problem:
     fmm_tol: float = 1e-6            # float64 product error target (<= 0: level rule)
     fmm_tol32: float = 0.0           # float32: orders raised to meet it (<= 0: rule)
     p_max: int = 40
+    m2l_rot: int = 0                 # M2L per level: 0 timed, 1 dense, 2 rotation-based
 
 
 @dataclass
@@ -235,7 +237,8 @@ class Plan:
                               T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), T.shape[0],
                               float(p.k), a.real, a.imag, float(p.near_eta), int(p.leaf_cap),
                               int(p.leaf_level), int(p.order64), int(p.order32),
-                              float(p.fmm_tol), float(p.fmm_tol32), int(p.p_max))
+                              float(p.fmm_tol), float(p.fmm_tol32), int(p.p_max),
+                              int(p.m2l_rot))
         self.problems = list(problems)
         self.n = [int(np.asarray(p.T).shape[0]) for p in problems]
         h = ctypes.c_void_p()
@@ -282,7 +285,8 @@ class Plan:
                     m2l_grid=list(st.m2l_grid), direct_depth=list(st.direct_depth),
                     fmm_err64=st.fmm_err64, fmm_err32=st.fmm_err32,
                     fmm_err64_smooth=st.fmm_err64_smooth, fmm_err32_smooth=st.fmm_err32_smooth,
-                    far_cut=list(st.far_cut), n_m2l_far=list(st.n_m2l_far)[:L + 1])
+                    far_cut=list(st.far_cut), n_m2l_far=list(st.n_m2l_far)[:L + 1],
+                    m2l_rot64=list(st.m2l_rot64)[:L + 1], m2l_rot32=list(st.m2l_rot32)[:L + 1])
 
     # ---- products
     def matvec(self, p, q=None, prec=BEM_C128, prob=0, out=None):

@@ -126,6 +126,27 @@ static int time_product(Problem& P, bool f32, hipStream_t s, float* ms) {
 // per tile, or 1 or 2 per compute unit).
 // A candidate replaces the current choice only when more than 2% faster
 // (timings of a few products vary by about that much).
+template <typename R>
+static int tune_rotations(Problem& P, PrecisionData<R>& D, int prec, hipStream_t s, float gain,
+                          float* best_ms) {
+  int r = build_rotations<R>(P, D, s);
+  if (r) return r;
+  for (int l = P.L; l >= 2; --l) {
+    GroupedOp<R>& op = D.m2l[l];
+    if (!op.rot_ready) continue;
+    op.rot_on = true;
+    if (P.m2l_rot_req == 2) continue;  // requested wherever the order allows
+    float ms = 0.f;
+    if ((r = time_product(P, prec == 1, s, &ms))) return r;
+    if (ms < gain * *best_ms)
+      *best_ms = ms;
+    else
+      op.rot_on = false;
+  }
+  if (P.m2l_rot_req == 2) return time_product(P, prec == 1, s, best_ms);
+  return 0;
+}
+
 static int tune_schedule(Problem& P, hipStream_t s) {
   int dev = 0, ncu = 0;
   BEM_HIP_TRY(hipGetDevice(&dev));
@@ -159,6 +180,12 @@ static int tune_schedule(Problem& P, hipStream_t s) {
         best_ms = ms;
       else
         P.ndir[prec] = 0;
+    }
+    // multipole-to-local by rotation, level by level from the leaves up
+    if (P.m2l_rot_req != 1) {
+      int r = prec == 1 ? tune_rotations<float>(P, P.f32, prec, s, gain, &best_ms)
+                        : tune_rotations<double>(P, P.f64, prec, s, gain, &best_ms);
+      if (r) return r;
     }
     // near-field grid x leaf-level M2L grid (one or two workgroups per CU)
     int best_p = 0, best_m = 0;
@@ -383,6 +410,7 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
         q.fmm_tol32 >= 1.0)
       return fail(BEM_E_INVALID, "fmm_tol must be finite and < 1");
     if (q.p_max > 40) return fail(BEM_E_INVALID, "p_max > 40");
+    if (q.m2l_rot < 0 || q.m2l_rot > 2) return fail(BEM_E_INVALID, "m2l_rot must be 0, 1 or 2");
   }
   hipStream_t s = (hipStream_t)stream;
   bem_plan* plan = new bem_plan();
@@ -412,6 +440,7 @@ int bem_plan_create(const bem_problem* probs, int n_probs, void* stream, bem_pla
     P->fmm_tol64 = q.fmm_tol;
     P->fmm_tol32 = q.fmm_tol32;
     P->p_max = q.p_max > 0 ? q.p_max : 40;
+    P->m2l_rot_req = q.m2l_rot;
     int r = build_geometry_and_tree(*P, q.vert, q.n_vert, q.tri, s);
     if (!r) r = build_near_field(*P, s);
     if (!r) r = build_operators(*P, s);
@@ -468,6 +497,10 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
   st->fmm_err32_smooth = P->direct ? 0.0 : P->f32.err_smooth;
   st->far_cut[0] = P->f64.far_cut;
   st->far_cut[1] = P->f32.far_cut;
+  for (int l = 2; l <= P->L && !P->direct; ++l) {
+    st->m2l_rot64[l] = P->f64.m2l[l].rot_on ? 1 : 0;
+    st->m2l_rot32[l] = P->f32.m2l[l].rot_on ? 1 : 0;
+  }
   st->tuned_ms = P->tuned_ms;
   for (int l = 0; l < 22; ++l) st->m2l_tile32[l] = (l <= P->L) ? P->f32.m2l[l].ct : 0;
   st->schedule[0] = P->sched[0];

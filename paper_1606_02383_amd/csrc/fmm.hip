@@ -926,6 +926,306 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Multipole-to-local by rotation (point-and-shoot).  With the translation
+// t = |t| Q e_z, Q = R_z(phi) R_y(theta), the operator factors as
+//     T(t) = Phi d T_z d^T Phi^H,
+// Phi = diag(e^{-i m phi}), d the real rotation blocks of R_y(theta) (one of
+// order 2n + 1 per degree n) and T_z = T(|t| e_z), which couples equal orders
+// m only (one block over the degrees |m| .. p per m): about 3.3 (p+1)^3
+// multiply-adds per pair instead of (p+1)^4.  A tile of up to ROT_CT pairs of
+// one offset group keeps its expansions in LDS ([coefficient][pair], real and
+// imaginary planes) and applies the five factors in place on the matrix
+// cores: the real blocks of d act on both planes, the complex blocks of T_z
+// as four real products.  Each wave owns whole blocks (degrees paired large
+// with small, orders dealt in a zigzag), so within a step no wave reads what
+// another writes; the blocks' operands sit in registers before the block is
+// overwritten.  Output: per pair, as the dense kernel's KIND 0.
+// The input cut of translations across three boxes (degrees <= pf read):
+// forward, the degrees above pf are loaded as zero and skipped; adjoint
+// (T^H = Phi d T_z^H d^T Phi^H, cut rows), the coaxial step zeroes the
+// output degrees above pf and the last rotation skips them.
+// ---------------------------------------------------------------------------
+constexpr int ROT_NW = 8;  // waves per tile
+
+template <typename R>
+struct RotJobDev {
+  int p;
+  const int* tile_group;
+  const int* tile_pair0;
+  const int* tile_npairs;
+  const int* group_kc;  // input coefficients of the forward operator (null: all)
+  const int* group_theta;
+  const int* group_dist;
+  const int* pair_src;
+  const R* phase;
+  const R* dtab;
+  const cplx<R>* coax;  // adjoint: the conjugate-transposed blocks
+  const cplx<R>* src;
+  cplx<R>* cbuf;
+};
+template <typename R>
+struct RotBatch {
+  int n;
+  int ntiles;
+  int tile0[MAX_JOBS + 1];
+  RotJobDev<R> job[MAX_JOBS];
+};
+
+__device__ __forceinline__ int isqrt_small(int c) {
+  int n = (int)sqrtf((float)c);
+  while (n * n > c) --n;
+  while ((n + 1) * (n + 1) <= c) ++n;
+  return n;
+}
+
+// Degrees 0 .. nmax of both planes, rows n^2 .. n^2 + 2n, replaced in place
+// by d_n^T (TR) or d_n times them; degree pairs (nmax - j, j) go to wave
+// j % ROT_NW.  KS: k steps of the largest block (2 ROT_MAXP + 1 <= 4 KS).
+template <typename R, int KS, bool TR>
+__device__ __forceinline__ void rot_degrees(R* __restrict__ X, int PL,
+                                            const R* __restrict__ dt, int nmax, int wave,
+                                            int li, int lk) {
+  typedef typename MfmaOp<R>::v4 v4;
+  const int npair = nmax / 2 + 1;
+  for (int j = wave; j < npair; j += ROT_NW) {
+    for (int h = 0; h < 2; ++h) {
+      const int n = h ? j : nmax - j;
+      if (h && n == nmax - j) break;  // the middle degree once
+      const int s = 2 * n + 1, rb = n * n, nks = (s + 3) >> 2;
+      const R* __restrict__ A = dt + rot_doff(n);
+      R b0[KS], b1[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + lk;
+        const bool ok = ks < nks && k < s;
+        b0[ks] = ok ? X[(rb + k) * ROT_LD + li] : R(0);
+        b1[ks] = ok ? X[PL + (rb + k) * ROT_LD + li] : R(0);
+      }
+      for (int r0 = 0; r0 < s; r0 += 16) {
+        const int row = r0 + li;
+        R a[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int k = 4 * ks + lk;
+          a[ks] = (ks < nks && k < s && row < s) ? (TR ? A[k * s + row] : A[row * s + k]) : R(0);
+        }
+        v4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+          if (ks < nks) {
+            c0 = MfmaOp<R>::mma(a[ks], b0[ks], c0);
+            c1 = MfmaOp<R>::mma(a[ks], b1[ks], c1);
+          }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + MfmaOp<R>::row(lk, e);
+          if (r < s) {
+            X[(rb + r) * ROT_LD + li] = c0[e];
+            X[PL + (rb + r) * ROT_LD + li] = c1[e];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Orders m = -p .. p: rows cidx(n, m), n = |m| .. p, replaced in place by the
+// coaxial block of order m times them (complex: four real products).
+// Forward: the input degrees above pf are zero and not read; adjoint: the
+// output degrees above pf are zero.  KZ: k steps of the largest block
+// (ROT_MAXP + 1 <= 4 KZ).
+template <typename R, int KZ, bool ADJ>
+__device__ __forceinline__ void rot_orders(R* __restrict__ X, int PL,
+                                           const cplx<R>* __restrict__ cz, int p, int pf,
+                                           int wave, int li, int lk) {
+  typedef typename MfmaOp<R>::v4 v4;
+  for (int rnd = 0;; ++rnd) {
+    // zigzag over the waves: order index i = 0, 1, 2, ... is m = 0, 1, -1, 2, ...
+    const int i = rnd * ROT_NW + ((rnd & 1) ? ROT_NW - 1 - wave : wave);
+    if (i > 2 * p) break;
+    const int m = (i & 1) ? (i + 1) / 2 : -(i / 2);
+    const int am = m < 0 ? -m : m, s = p + 1 - am;
+    const int kin = ADJ ? s : min(s, pf + 1 - am);   // input degrees read
+    const int kout = ADJ ? min(s, pf + 1 - am) : s;  // output degrees kept
+    const int nks = kin > 0 ? (kin + 3) >> 2 : 0;
+    const cplx<R>* __restrict__ T = cz + rot_coff(p, m);
+    R yr[KZ], yi[KZ];
+#pragma unroll
+    for (int ks = 0; ks < KZ; ++ks) {
+      const int k = 4 * ks + lk, n = am + k;
+      const bool ok = ks < nks && k < kin;
+      const int row = n * n + n + m;
+      yr[ks] = ok ? X[row * ROT_LD + li] : R(0);
+      yi[ks] = ok ? X[PL + row * ROT_LD + li] : R(0);
+    }
+    for (int r0 = 0; r0 < s; r0 += 16) {
+      const int row = r0 + li;
+      R ar[KZ], ai[KZ];
+#pragma unroll
+      for (int ks = 0; ks < KZ; ++ks) {
+        const int k = 4 * ks + lk;
+        cplx<R> v = mk<R>(0, 0);
+        if (ks < nks && k < kin && row < s) v = T[row * s + k];
+        ar[ks] = v.re;
+        ai[ks] = v.im;
+      }
+      v4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < KZ; ++ks)
+        if (ks < nks) {
+          cr = MfmaOp<R>::mma(ar[ks], yr[ks], cr);
+          cr = MfmaOp<R>::mma(-ai[ks], yi[ks], cr);
+          ci = MfmaOp<R>::mma(ar[ks], yi[ks], ci);
+          ci = MfmaOp<R>::mma(ai[ks], yr[ks], ci);
+        }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + MfmaOp<R>::row(lk, e);
+        if (r < s) {
+          const int n = am + r, idx = n * n + n + m;
+          const bool keep = r < kout;
+          X[idx * ROT_LD + li] = keep ? cr[e] : R(0);
+          X[PL + idx * ROT_LD + li] = keep ? ci[e] : R(0);
+        }
+      }
+    }
+  }
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads and stores
+// in flight (a tile's prefetched inputs, the previous tile's outputs) are not
+// waited for, as a full barrier's release fence would.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// NC: LDS rows per plane (>= (p+1)^2 of every job of the launch).  TAB: the
+// group's rotation and coaxial tables are staged in LDS as well (orders
+// <= 15; float64 then fills the LDS), else read from global memory.
+// Persistent: workgroup b takes a contiguous run of tiles (the tiles of an
+// XCD's range split evenly over the workgroups on that XCD), so consecutive
+// tiles mostly share their group and its tables; the inputs of the next
+// tile are loaded into registers while the current one is computed.
+template <typename R, int NC, bool ADJ, bool TAB>
+__global__ void __launch_bounds__(64 * ROT_NW) k_rot_m2l(const RotBatch<R> batch) {
+  constexpr int NT = 64 * ROT_NW;
+  constexpr int PL = NC * ROT_LD;
+  constexpr int PM = NC <= 256 ? 15 : ROT_MAXP;  // largest order of the class
+  constexpr int KS = (2 * PM + 4) / 4;            // k steps of a degree block
+  constexpr int KZ = (PM + 4) / 4;                // k steps of an order block
+  constexpr int DSZ = TAB ? rot_dsz(PM) : 1;
+  constexpr int CSZ = TAB ? rot_csz(PM) : 1;
+  constexpr int PRE = (ROT_CT * NC + NT - 1) / NT;  // input values per thread
+  __shared__ __attribute__((aligned(16))) R X[2 * PL];
+  __shared__ __attribute__((aligned(16))) R s_dt[DSZ];
+  __shared__ __attribute__((aligned(16))) cplx<R> s_cz[CSZ];
+  __shared__ R s_ph[2][2 * ROT_MAXP + 1];
+  __builtin_amdgcn_s_setprio(2);  // critical path: ahead of the near-field waves
+  const int nt = batch.ntiles, G = gridDim.x, wb = blockIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  // this workgroup's tiles [t0, t1): XCD x = wb % 8 owns a contiguous range
+  const int x = wb & 7, jx = wb >> 3, gx = (G - x + 7) >> 3;
+  const int cnt = (nt >> 3) + (x < (nt & 7) ? 1 : 0);
+  const int start = x * (nt >> 3) + min(x, nt & 7);
+  const int t0 = start + (int)((int64_t)jx * cnt / gx);
+  const int t1 = start + (int)((int64_t)(jx + 1) * cnt / gx);
+  auto job_of = [&](int gt) {
+    int q = 0;
+#pragma unroll
+    for (int i = 1; i < MAX_JOBS; ++i)
+      if (i < batch.n && gt >= batch.tile0[i]) q = i;
+    return q;
+  };
+  // inputs of tile gt (forward: the kc coefficients the cut keeps, rest zero)
+  cplx<R> pre[PRE];
+  auto fetch = [&](int gt) {
+    const int q = job_of(gt);
+    const RotJobDev<R> J = select_job(batch.job, q);
+    const int tile = gt - select_job(batch.tile0, q);
+    const int nc = (J.p + 1) * (J.p + 1);
+    const int grp = J.tile_group[tile], p0 = J.tile_pair0[tile], np = J.tile_npairs[tile];
+    const int kin = (!ADJ && J.group_kc) ? min(nc, J.group_kc[grp]) : nc;
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) {
+      const int e = tid + NT * i, cc = e / nc, c = e - cc * nc;
+      pre[i] = mk<R>(0, 0);
+      if (cc < np && c < kin) pre[i] = J.src[(int64_t)J.pair_src[p0 + cc] * nc + c];
+    }
+  };
+  // tables in LDS: the next tile's inputs are prefetched (registers allow);
+  // else each tile loads its own
+  if (TAB && t0 < t1) fetch(t0);
+  int cur_q = -1, cur_th = -1, cur_di = -1, cur_grp = -1;
+  for (int gt = t0; gt < t1; ++gt) {
+    const int q = job_of(gt);
+    const RotJobDev<R> J = select_job(batch.job, q);
+    const int tile = gt - select_job(batch.tile0, q);
+    const int p = J.p, nc = (p + 1) * (p + 1);
+    const int grp = J.tile_group[tile], p0 = J.tile_pair0[tile], np = J.tile_npairs[tile];
+    const int kc = J.group_kc ? min(nc, J.group_kc[grp]) : nc;
+    int pf = 0;
+    while ((pf + 2) * (pf + 2) <= kc) ++pf;
+    const int th = J.group_theta[grp], di = J.group_dist[grp];
+    lds_barrier();  // the previous tile no longer reads the shared arrays
+    const bool new_tab = TAB && (q != cur_q || th != cur_th || di != cur_di);
+    const bool new_ph = q != cur_q || grp != cur_grp;
+    if (new_tab) {
+      const R* __restrict__ gd = J.dtab + (int64_t)th * rot_dsz(p);
+      const cplx<R>* __restrict__ gc = J.coax + (int64_t)di * rot_csz(p);
+      const int nd = rot_dsz(p), ncz = rot_csz(p);
+#pragma unroll 4
+      for (int t = tid; t < nd; t += NT) s_dt[t] = gd[t];
+#pragma unroll 4
+      for (int t = tid; t < ncz; t += NT) s_cz[t] = gc[t];
+    }
+    if (new_ph && tid < 2 * p + 1) {  // e^{i m phi}, m = -p .. p
+      const int m = tid - p, am = m < 0 ? -m : m;
+      const R* ph = J.phase + ((int64_t)grp * (p + 1) + am) * 2;
+      s_ph[0][tid] = ph[0];
+      s_ph[1][tid] = m < 0 ? -ph[1] : ph[1];
+    }
+    cur_q = q;
+    cur_th = th;
+    cur_di = di;
+    cur_grp = grp;
+    if (!TAB) fetch(gt);
+    if (new_tab || new_ph) lds_barrier();
+    // Phi^H: coefficient (n, m) times e^{i m phi}
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) {
+      const int e = tid + NT * i, cc = e / nc, c = e - cc * nc;
+      if (cc < ROT_CT) {
+        const int n = isqrt_small(c), m = c - n * n - n;
+        const R er = s_ph[0][m + p], ei = s_ph[1][m + p];
+        X[c * ROT_LD + cc] = pre[i].re * er - pre[i].im * ei;
+        X[PL + c * ROT_LD + cc] = pre[i].re * ei + pre[i].im * er;
+      }
+    }
+    if (TAB && gt + 1 < t1) fetch(gt + 1);  // in flight during the steps below
+    lds_barrier();
+    const R* dt = TAB ? (const R*)s_dt : J.dtab + (int64_t)th * rot_dsz(p);
+    const cplx<R>* cz = TAB ? (const cplx<R>*)s_cz : J.coax + (int64_t)di * rot_csz(p);
+    rot_degrees<R, KS, true>(X, PL, dt, ADJ ? p : pf, wave, li, lk);  // d^T
+    lds_barrier();
+    rot_orders<R, KZ, ADJ>(X, PL, cz, p, pf, wave, li, lk);  // T_z (or T_z^H)
+    lds_barrier();
+    rot_degrees<R, KS, false>(X, PL, dt, ADJ ? pf : p, wave, li, lk);  // d
+    lds_barrier();
+    // Phi: coefficient (n, m) times e^{-i m phi}, written per pair
+    for (int t = tid; t < np * nc; t += NT) {
+      const int cc = t / nc, c = t - cc * nc;
+      const int n = isqrt_small(c), m = c - n * n - n;
+      const R er = s_ph[0][m + p], ei = s_ph[1][m + p];
+      const R xr = X[c * ROT_LD + cc], xi = X[PL + c * ROT_LD + cc];
+      J.cbuf[(int64_t)(p0 + cc) * nc + c] = mk<R>(xr * er + xi * ei, xi * er - xr * ei);
+    }
+  }
+}
+
 // dst[b][c] (+)= sum over the pairs t of box b of cbuf[t][c]  (pairs listed
 // per box in a fixed order: deterministic, no atomics)
 // 256 threads per box: 4 slices of 64 coefficients, each slice sums every
@@ -1419,6 +1719,46 @@ static void launch_gemm(const GemmBatch<R>& b, int nt, hipStream_t s, hipEvent_t
               start, done, b);
 }
 
+// compute units of the current device (cached per device)
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev] &&
+      hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus[dev] = 256;
+  return cus[dev];
+}
+
+// grid: workgroups (0: four per compute unit); at least min(tiles, 8) so that
+// every XCD's range of tiles has a workgroup
+template <typename R, bool ADJ>
+static int launch_rot(const RotBatch<R>& b, int maxnc, int grid, hipStream_t s, hipEvent_t done,
+                      hipEvent_t start) {
+  constexpr int NC_HI = (ROT_MAXP + 1) * (ROT_MAXP + 1);
+  const int nt = b.ntiles;
+  int g = grid > 0 ? grid : 4 * device_cus();
+  g = std::min(nt, std::max(g, 8));
+  if (maxnc <= 256)
+    launch_done(k_rot_m2l<R, 256, ADJ, true>, dim3(g), dim3(64 * ROT_NW), 0, s, start, done, b);
+  else if (maxnc <= NC_HI)
+    launch_done(k_rot_m2l<R, NC_HI, ADJ, false>, dim3(g), dim3(64 * ROT_NW), 0, s, start, done,
+                b);
+  else {
+    set_error("expansion order too high for the rotation-based translations");
+    return -1;
+  }
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+// launch-grouping key of an M2L product: its pair-tile width, or 1 for the
+// rotation-based kernel
+template <typename R>
+static int tile_key(const GroupedOp<R>& op, bool adj) {
+  return op.rot_on ? 1 : (adj ? op.ct_adj : op.ct);
+}
+
 template <typename R, bool ADJ, int KIND>
 static int launch_gemm_ct(const GemmBatch<R>& b, int ct, int nt, hipStream_t s,
                           hipEvent_t done = nullptr, hipEvent_t start = nullptr) {
@@ -1462,8 +1802,11 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
   }
   GemmBatch<R> b{};
   RedBatch<R> rb{};
-  b.n = rb.n = nj;
-  int nt = 0, nbox = 0, ct = 0;
+  RotBatch<R> tb{};
+  b.n = rb.n = tb.n = nj;
+  int nt = 0, nbox = 0, ct = 0, maxnc = 0;
+  // rotation-based M2L (every job of the launch or none)
+  const bool rot = KIND == 0 && jobs[0].op->rot_on;
   // adjoint M2L: the stored conjugate transposes through the forward
   // operand path (the transposed load path is slower)
   bool via_fwd = adj && KIND == 0;
@@ -1475,11 +1818,35 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
       return -1;
     }
     const int jct = adj ? op.ct_adj : op.ct;
-    if (q > 0 && jct != ct) {
+    if (q > 0 && jct != ct && !rot) {
       set_error("grouped products of one launch differ in tile width");
       return -1;
     }
     ct = jct;
+    if (op.rot_on != rot || (rot && (!op.rot_ready || op.rot_p > ROT_MAXP ||
+                                     (op.rot_p + 1) * (op.rot_p + 1) != op.rows))) {
+      set_error("rotation-based and dense translations in one launch, or rotation tables missing");
+      return -1;
+    }
+    if (rot) {
+      RotJobDev<R>& T = tb.job[q];
+      T.p = op.rot_p;
+      T.tile_group = op.rot_tile_group;
+      T.tile_pair0 = op.rot_tile_pair0;
+      T.tile_npairs = op.rot_tile_npairs;
+      T.group_kc = op.group_kc;
+      T.group_theta = op.rot_theta;
+      T.group_dist = op.rot_dist;
+      T.pair_src = adj ? op.pair_src_adj : op.pair_src;
+      T.phase = op.rot_phase;
+      T.dtab = op.rot_dtab;
+      T.coax = adj ? op.rot_coax_h : op.rot_coax;
+      T.src = jobs[q].src;
+      T.cbuf = jobs[q].cbuf;
+      tb.tile0[q] = nt;
+      nt += op.rot_n_tiles;
+      maxnc = std::max(maxnc, op.rows);
+    }
     GemmJobDev<R>& J = b.job[q];
     J.mat_rows = via_fwd ? op.cols : op.rows;
     J.mat_cols = via_fwd ? op.rows : op.cols;
@@ -1495,8 +1862,10 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
     J.src = jobs[q].src;
     J.dst = jobs[q].dst;
     J.cbuf = jobs[q].cbuf;
-    b.tile0[q] = nt;
-    nt += adj ? op.n_tiles_adj : op.n_tiles;
+    if (!rot) {
+      b.tile0[q] = nt;
+      nt += adj ? op.n_tiles_adj : op.n_tiles;
+    }
     RedJobDev<R>& RJ = rb.job[q];
     RJ.ncoef = adj ? op.cols : op.rows;
     RJ.ptr = adj ? op.red_ptr_adj : op.red_ptr;
@@ -1506,17 +1875,19 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
     rb.box0[q] = nbox;
     nbox += adj ? op.n_red_adj : op.n_red;
   }
-  b.tile0[nj] = nt;
-  b.ntiles = nt;
+  b.tile0[nj] = tb.tile0[nj] = nt;
+  b.ntiles = tb.ntiles = nt;
   rb.box0[nj] = nbox;
   if (nt == 0 && start) BEM_HIP_TRY(hipEventRecord(start, s));
   if (nt == 0 && done) BEM_HIP_TRY(hipEventRecord(done, s));
   if (nt > 0) {
     int evg = prof ? prof_begin(*prof, s) : -1;
     const int grid = (grid_cap > 0 && grid_cap < nt) ? (grid_cap & ~7) : nt;
-    int r = (adj && !via_fwd)
-                 ? launch_gemm_ct<R, true, KIND>(b, ct, grid > 0 ? grid : nt, s, done, start)
-                 : launch_gemm_ct<R, false, KIND>(b, ct, grid > 0 ? grid : nt, s, done, start);
+    const int g = grid > 0 ? grid : nt;
+    int r = rot ? (adj ? launch_rot<R, true>(tb, maxnc, grid, s, done, start)
+                       : launch_rot<R, false>(tb, maxnc, grid, s, done, start))
+            : (adj && !via_fwd) ? launch_gemm_ct<R, true, KIND>(b, ct, g, s, done, start)
+                                : launch_gemm_ct<R, false, KIND>(b, ct, g, s, done, start);
     if (r) return r;
     if (prof) {
       int pr = prof_end(*prof, evg, prof_slot(st_gemm, sizeof(R) == 4, adj), s);
@@ -1708,8 +2079,8 @@ static int launch_coarse_m2l(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, boo
   while (l < L) {
     GemmJob<R> jobs[MAX_JOBS];
     int nj = 0;
-    const int ct = adj ? D.m2l[l].ct_adj : D.m2l[l].ct;
-    for (; l < L && nj < MAX_JOBS && (adj ? D.m2l[l].ct_adj : D.m2l[l].ct) == ct; ++l, ++nj) {
+    const int key = tile_key(D.m2l[l], adj);
+    for (; l < L && nj < MAX_JOBS && tile_key(D.m2l[l], adj) == key; ++l, ++nj) {
       jobs[nj].op = &D.m2l[l];
       jobs[nj].src = adj ? X.Lc[l] : X.M[l];
       jobs[nj].dst = adj ? X.M[l] : X.Lc[l];
@@ -2064,10 +2435,11 @@ int fmm_apply_adjoint_x(Problem& P, PrecisionData<R>& D, ExecBuf<R>& X, const c6
 // grouped launches of any number of jobs: by pair-tile width, MAX_JOBS at a time
 template <typename R, int KIND>
 static int launch_grouped_any(const std::vector<GemmJob<R>>& jobs, bool adj, hipStream_t s) {
-  for (int ct : {16, 32, 64, 128}) {
+  for (int key : {1, 16, 32, 64, 128}) {
     std::vector<GemmJob<R>> g;
     for (const GemmJob<R>& j : jobs)
-      if ((adj ? j.op->ct_adj : j.op->ct) == ct) g.push_back(j);
+      if ((KIND == 0 ? tile_key(*j.op, adj) : (adj ? j.op->ct_adj : j.op->ct)) == key)
+        g.push_back(j);
     for (size_t a = 0; a < g.size(); a += MAX_JOBS) {
       const int nj = (int)std::min<size_t>(MAX_JOBS, g.size() - a);
       int r = launch_grouped_jobs<R, KIND>(&g[a], nj, adj, s, 0, nullptr, ST_M2L, 0, false);

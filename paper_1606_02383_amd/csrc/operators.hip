@@ -598,6 +598,7 @@ static int finish_grouped(GroupedOp<R>& op, int* d0, int* s0, int* c0, int np, i
   BEM_HIP_TRY(hipStreamSynchronize(s));
   std::vector<int> gstart(ngroups + 1, 0);
   for (int g = 0; g < ngroups; ++g) gstart[g + 1] = gstart[g] + hcnt[g];
+  op.gstart_h = gstart;
   std::vector<int> tg, tp0, tnp, tr0, ta, tap0, tanp, tar0;
   op.ct = force_ct ? force_ct : pick_pair_tile(gstart, op.rows, sizeof(R) == 4);
   op.ct_adj = force_ct ? force_ct : pick_pair_tile(gstart, op.cols, sizeof(R) == 4);
@@ -998,6 +999,234 @@ int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift_c, int shift_l,
 }
 template int rebuild_precision<float>(Problem&, PrecisionData<float>&, int, int, hipStream_t);
 template int rebuild_precision<double>(Problem&, PrecisionData<double>&, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// tables of the rotation-based M2L
+// ---------------------------------------------------------------------------
+// A translation t = |t| Q e_z with Q = R_z(phi) R_y(theta) factors as
+//     T(t) = D(Q) T(|t| e_z) D(Q)^H,   D(Q) = Phi d,
+// where D(Q)[m][m'] = int conj(Y_n^m(x)) Y_n^m'(Q^T x) dOmega (block-diagonal
+// in the degree n: rotating a field rotates its expansions in either kind of
+// wave functions alike), Phi = diag(e^{-i m phi}) and d = D(R_y(theta)),
+// real with the Condon-Shortley phase; T(|t| e_z) couples equal orders m
+// only (Y_l^mu(e_z) = 0 for mu != 0).  The level scaling depends on n alone
+// and commutes with D.
+
+// Theta_n^m(x) for one degree and order (the recurrence of theta_table
+// along n at fixed m)
+__device__ double theta_one(int n, int m, double x) {
+  const double s = sqrt(fmax(0.0, 1.0 - x * x));
+  double tmm = 0.28209479177387814;
+  for (int i = 1; i <= m; ++i) tmm = -sqrt((2.0 * i + 1.0) / (2.0 * i)) * s * tmm;
+  if (n == m) return tmm;
+  double t0 = tmm, t1 = sqrt(2.0 * m + 3.0) * x * tmm;
+  for (int nn = m + 2; nn <= n; ++nn) {
+    const double a = sqrt((4.0 * nn * nn - 1.0) / ((double)nn * nn - (double)m * m));
+    const double b =
+        sqrt(((nn - 1.0) * (nn - 1.0) - (double)m * m) / (4.0 * (nn - 1.0) * (nn - 1.0) - 1.0));
+    const double t2 = a * (x * t1 - b * t0);
+    t0 = t1;
+    t1 = t2;
+  }
+  return t1;
+}
+
+// d_n(theta)[m][m'] by a product rule exact for the integrand (degree <= 2n
+// on the sphere): nu >= n + 1 Gauss-Legendre nodes in the cosine of the
+// polar angle times nph > 2n equispaced azimuths.  One workgroup per
+// (rotation class c, degree n); cs[2c], cs[2c+1] = cos, sin theta_c;
+// dtab[c * rot_dsz(p) + rot_doff(n) + (m + n)(2n + 1) + (m' + n)].
+constexpr int ROT_QCH = 64;  // quadrature points per LDS chunk
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_rot_small_d(int p, const double* __restrict__ cs, int nu, int nph,
+                  const double* __restrict__ gx, const double* __restrict__ gw,
+                  R* __restrict__ dtab) {
+  constexpr int EPT = ((2 * ROT_MAXP + 1) * (2 * ROT_MAXP + 1) + 255) / 256;
+  __shared__ double ta[ROT_QCH][ROT_MAXP + 1], tb[ROT_QCH][ROT_MAXP + 1];
+  __shared__ double fa[ROT_QCH], fb[ROT_QCH], wq[ROT_QCH];
+  const int c = blockIdx.x, n = blockIdx.y, s = 2 * n + 1, ne = s * s;
+  const double ct = cs[2 * c], st = cs[2 * c + 1];
+  const double two_pi = 6.283185307179586;
+  double acc[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) acc[i] = 0.0;
+  const int nq = nu * nph;
+  for (int q0 = 0; q0 < nq; q0 += ROT_QCH) {
+    const int nqc = min(ROT_QCH, nq - q0);
+    // Theta_n^|m| at the nodes x and at R_y(theta)^T x, with the azimuths
+    for (int it = threadIdx.x; it < 2 * nqc * (n + 1); it += blockDim.x) {
+      const int qq = it % nqc, rest = it / nqc, mm = rest % (n + 1), rot = rest / (n + 1);
+      const int q = q0 + qq, iu = q / nph, ip = q % nph;
+      const double u = gx[iu], az = two_pi * ip / nph;
+      double x = u, a = az;
+      if (rot) {
+        const double sn = sqrt(fmax(0.0, 1.0 - u * u));
+        const double vx = sn * cos(az), vy = sn * sin(az);
+        x = fmin(1.0, fmax(-1.0, st * vx + ct * u));
+        a = atan2(vy, ct * vx - st * u);
+      }
+      (rot ? tb : ta)[qq][mm] = theta_one(n, mm, x);
+      if (mm == 0) {
+        (rot ? fb : fa)[qq] = a;
+        if (!rot) wq[qq] = gw[iu] * two_pi / nph;
+      }
+    }
+    __syncthreads();
+    // Re[conj(Y_n^m(x)) Y_n^m'(x')], Y_n^m = sigma_m Theta_n^|m| e^{i m phi}
+    // with sigma_m = (-1)^m for m < 0
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < ne) {
+        const int m = e / s - n, m2 = e % s - n;
+        const int am = abs(m), am2 = abs(m2);
+        double sum = 0.0;
+        for (int qq = 0; qq < nqc; ++qq)
+          sum += wq[qq] * ta[qq][am] * tb[qq][am2] * cos(m2 * fb[qq] - m * fa[qq]);
+        const bool neg = ((m < 0) && (am & 1)) != ((m2 < 0) && (am2 & 1));
+        acc[i] += neg ? -sum : sum;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e < ne) dtab[(int64_t)c * rot_dsz(p) + rot_doff(n) + e] = (R)acc[i];
+  }
+}
+
+// Coaxial blocks from the dense translations along e_z (one per distance
+// class, rows = outputs): coax[c][coff(m) + i s + j] = T_c[(|m|+i, m)][(|m|+j, m)]
+// with s = p + 1 - |m|, and coax_h the block-wise conjugate transposes.
+template <typename R>
+__global__ void k_rot_coax(int p, int ndist, const cplx<R>* __restrict__ dense,
+                           cplx<R>* __restrict__ coax, cplx<R>* __restrict__ coax_h) {
+  const int csz = rot_csz(p), nc = (p + 1) * (p + 1);
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ndist * csz) return;
+  const int c = (int)(t / csz), e = (int)(t % csz);
+  int m = -p;
+  while (m < p && rot_coff(p, m + 1) <= e) ++m;
+  const int am = m < 0 ? -m : m, s = p + 1 - am, o = e - rot_coff(p, m);
+  const int i = o / s, j = o % s;
+  const cplx<R>* T = dense + (int64_t)c * nc * nc;
+  const int ri = cidx(am + i, m), rj = cidx(am + j, m);
+  coax[t] = T[(int64_t)ri * nc + rj];
+  const cplx<R> v = T[(int64_t)rj * nc + ri];
+  coax_h[t] = mk<R>(v.re, -v.im);
+}
+
+template <typename R>
+int build_rotations(Problem& P, PrecisionData<R>& D, hipStream_t s) {
+  DevArena scratch;
+  struct Guard {
+    DevArena& a;
+    ~Guard() { a.release(); }
+  } guard{scratch};
+  for (int l = 2; l <= P.L; ++l) {
+    GroupedOp<R>& op = D.m2l[l];
+    const int p = D.order[l];
+    if (op.rot_ready || op.n_pairs == 0 || p > ROT_MAXP ||
+        (int)op.gstart_h.size() != N_OFFSETS + 1)
+      continue;
+    // classes: polar angle by (dz, dx^2 + dy^2), distance by |d|^2 (offsets
+    // in box sides; the translation vector is the offset times h_l)
+    std::vector<std::array<int, 3>> tkeys, dkeys;
+    std::vector<int> g_theta(N_OFFSETS, 0), g_dist(N_OFFSETS, 0);
+    std::vector<double> cs_theta, tv_dist;
+    std::vector<R> phase((size_t)N_OFFSETS * (p + 1) * 2, R(0));
+    std::vector<int> tg, tp0, tnp;
+    for (int c = 0; c < N_OFFSETS; ++c) {
+      const int a = op.gstart_h[c], b = op.gstart_h[c + 1];
+      if (b <= a) continue;
+      const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
+      const int rxy2 = dx * dx + dy * dy, r2 = rxy2 + dz * dz;
+      const double r = std::sqrt((double)r2);
+      const std::array<int, 3> tk{dz, rxy2, 0}, dk{r2, 0, 0};
+      int ti = 0, di = 0;
+      while (ti < (int)tkeys.size() && tkeys[ti] != tk) ++ti;
+      if (ti == (int)tkeys.size()) {
+        tkeys.push_back(tk);
+        cs_theta.push_back(dz / r);
+        cs_theta.push_back(std::sqrt((double)rxy2) / r);
+      }
+      while (di < (int)dkeys.size() && dkeys[di] != dk) ++di;
+      if (di == (int)dkeys.size()) {
+        dkeys.push_back(dk);
+        tv_dist.push_back(0.0);
+        tv_dist.push_back(0.0);
+        tv_dist.push_back(r * P.h[l]);
+      }
+      g_theta[c] = ti;
+      g_dist[c] = di;
+      const double phi = rxy2 > 0 ? std::atan2((double)dy, (double)dx) : 0.0;
+      for (int m = 0; m <= p; ++m) {
+        phase[((size_t)c * (p + 1) + m) * 2] = (R)std::cos(m * phi);
+        phase[((size_t)c * (p + 1) + m) * 2 + 1] = (R)std::sin(m * phi);
+      }
+      for (int p0 = a; p0 < b; p0 += ROT_CT) {
+        tg.push_back(c);
+        tp0.push_back(p0);
+        tnp.push_back(std::min(ROT_CT, b - p0));
+      }
+    }
+    const int nth = (int)tkeys.size(), ndist = (int)dkeys.size(), nt = (int)tg.size();
+    ARENA_ALLOC(D.ops, op.rot_tile_group, nt);
+    ARENA_ALLOC(D.ops, op.rot_tile_pair0, nt);
+    ARENA_ALLOC(D.ops, op.rot_tile_npairs, nt);
+    ARENA_ALLOC(D.ops, op.rot_theta, N_OFFSETS);
+    ARENA_ALLOC(D.ops, op.rot_dist, N_OFFSETS);
+    ARENA_ALLOC(D.ops, op.rot_phase, phase.size());
+    ARENA_ALLOC(D.ops, op.rot_dtab, (int64_t)nth * rot_dsz(p));
+    ARENA_ALLOC(D.ops, op.rot_coax, (int64_t)ndist * rot_csz(p));
+    ARENA_ALLOC(D.ops, op.rot_coax_h, (int64_t)ndist * rot_csz(p));
+    auto up = [&](void* d, const void* h, size_t bytes) -> int {
+      if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+      return 0;
+    };
+    int r = 0;
+    if ((r = up(op.rot_tile_group, tg.data(), sizeof(int) * nt)) ||
+        (r = up(op.rot_tile_pair0, tp0.data(), sizeof(int) * nt)) ||
+        (r = up(op.rot_tile_npairs, tnp.data(), sizeof(int) * nt)) ||
+        (r = up(op.rot_theta, g_theta.data(), sizeof(int) * N_OFFSETS)) ||
+        (r = up(op.rot_dist, g_dist.data(), sizeof(int) * N_OFFSETS)) ||
+        (r = up(op.rot_phase, phase.data(), sizeof(R) * phase.size())))
+      return r;
+    // rotation blocks by quadrature
+    std::vector<double> gx, gw;
+    gauss_legendre(p + 1, gx, gw);
+    double *dgx, *dgw, *dcs;
+    ARENA_ALLOC(scratch, dgx, p + 1);
+    ARENA_ALLOC(scratch, dgw, p + 1);
+    ARENA_ALLOC(scratch, dcs, cs_theta.size());
+    if ((r = up(dgx, gx.data(), sizeof(double) * (p + 1))) ||
+        (r = up(dgw, gw.data(), sizeof(double) * (p + 1))) ||
+        (r = up(dcs, cs_theta.data(), sizeof(double) * cs_theta.size())))
+      return r;
+    hipLaunchKernelGGL(k_rot_small_d<R>, dim3(nth, p + 1), dim3(256), 0, s, p, dcs, p + 1,
+                       2 * p + 2, dgx, dgw, op.rot_dtab);
+    BEM_LAUNCH_CHECK();
+    // coaxial blocks: the dense translations along e_z, same level scaling
+    std::vector<double> rs = coef_scale(p, P.k * P.h[l], +1), cs = coef_scale(p, P.k * P.h[l], +1);
+    cplx<R>* dense = nullptr;
+    r = make_translations<R>(P, scratch, ndist, tv_dist, 1, p, p, rs, cs, &dense, scratch, s);
+    if (r) return r;
+    const int64_t tot = (int64_t)ndist * rot_csz(p);
+    hipLaunchKernelGGL(k_rot_coax<R>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, p, ndist, dense,
+                       op.rot_coax, op.rot_coax_h);
+    BEM_LAUNCH_CHECK();
+    BEM_HIP_TRY(hipStreamSynchronize(s));
+    scratch.release();
+    op.rot_n_tiles = nt;
+    op.rot_p = p;
+    op.rot_ready = true;
+  }
+  return 0;
+}
+template int build_rotations<float>(Problem&, PrecisionData<float>&, hipStream_t);
+template int build_rotations<double>(Problem&, PrecisionData<double>&, hipStream_t);
 
 int build_operators(Problem& P, hipStream_t s) {
   DevArena scratch;

@@ -20,6 +20,22 @@ constexpr int SELF_RULE = 64;    // self terms: Gauss points per edge angle
 constexpr int MAX_DIRECT = 3;    // levels above the leaves reached by direct translations
 constexpr int64_t DIRECT_BYTES = int64_t(1) << 30;  // operator memory cap per direct depth
 
+// Multipole-to-local by rotation (point-and-shoot): pairs per tile, LDS row
+// stride of a tile's expansions, largest order (its LDS holds 2 (p+1)^2 rows)
+constexpr int ROT_CT = 16;
+constexpr int ROT_LD = ROT_CT + 1;
+constexpr int ROT_MAXP = 23;
+// Table layouts: real rotation blocks of degrees 0..p one after another
+// ((2n+1)^2 each, block n at rot_doff(n)); coaxial blocks of orders
+// m = -p..p one after another ((p+1-|m|)^2 each, block m at rot_coff(p, m))
+__host__ __device__ constexpr int rot_doff(int n) { return n * (4 * n * n - 1) / 3; }
+__host__ __device__ constexpr int rot_dsz(int p) { return rot_doff(p + 1); }
+__host__ __device__ constexpr int rot_s2(int x) { return x * (x + 1) * (2 * x + 1) / 6; }
+__host__ __device__ constexpr int rot_csz(int p) { return (p + 1) * (p + 1) + 2 * rot_s2(p); }
+__host__ __device__ constexpr int rot_coff(int p, int m) {
+  return m <= 0 ? rot_s2(p + m) : 2 * rot_s2(p) + (p + 1) * (p + 1) - rot_s2(p + 1 - m);
+}
+
 // Device allocation registry: every buffer a problem owns.
 struct DevArena {
   std::vector<void*> ptrs;
@@ -68,6 +84,25 @@ struct GroupedOp {
   int* red_pairs = nullptr;
   int* red_ptr_adj = nullptr;
   int* red_pairs_adj = nullptr;
+  // host: the pairs of group c are gstart_h[c] .. gstart_h[c + 1] - 1
+  std::vector<int> gstart_h;
+  // M2L by rotation (built on demand for orders <= ROT_MAXP; used when
+  // rot_on): tiles of up to ROT_CT pairs of one group (forward and adjoint
+  // alike, the adjoint pair lists keep the group order), per group the
+  // rotation class (polar angle), distance class and e^{i m phi} for
+  // m = 0..p (re, im); per rotation class the real blocks d_n; per distance
+  // class the coaxial blocks and their conjugate transposes
+  bool rot_on = false, rot_ready = false;
+  int rot_p = 0, rot_n_tiles = 0;
+  int* rot_tile_group = nullptr;
+  int* rot_tile_pair0 = nullptr;
+  int* rot_tile_npairs = nullptr;
+  int* rot_theta = nullptr;
+  int* rot_dist = nullptr;
+  R* rot_phase = nullptr;
+  R* rot_dtab = nullptr;
+  cplx<R>* rot_coax = nullptr;
+  cplx<R>* rot_coax_h = nullptr;
 };
 
 // Buffers that one product writes, for one precision: sorted densities and
@@ -167,6 +202,9 @@ struct Problem {
   std::array<int, 2> p2p_cap{{0, 0}};
   // workgroups of the leaf-level M2L launch (0: one per tile, else that many)
   std::array<int, 2> m2l_cap{{0, 0}};
+  // M2L variant: 0 dense or rotation per level by timing, 1 dense only,
+  // 2 rotation wherever the order allows
+  int m2l_rot_req = 0;
   // depth of the direct leaf <-> ancestor translations used (<= n_direct of
   // the precision; 0: level-by-level chains only)
   std::array<int, 2> ndir{{0, 0}};
@@ -283,6 +321,11 @@ int build_operators(Problem& P, hipStream_t s);
 // level (release of the old data included).
 template <typename R>
 int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift_c, int shift_l, hipStream_t s);
+// Tables and tiles of the rotation-based M2L for every level of one
+// precision whose order allows it (kept until the next rebuild; no level is
+// switched on).
+template <typename R>
+int build_rotations(Problem& P, PrecisionData<R>& D, hipStream_t s);
 // Sampled relative error of one product against the exact discrete operator:
 // rows spread over the mesh, seeded pseudo-random p and q, reference rows
 // summed directly in float64 (rule points, near corrections, diagonal).
