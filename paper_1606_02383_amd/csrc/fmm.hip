@@ -938,9 +938,14 @@ __global__ void __launch_bounds__(64 * TileShape<CT>::NW)
 // imaginary planes) and applies the five factors in place on the matrix
 // cores: the real blocks of d act on both planes, the complex blocks of T_z
 // as four real products.  Each wave owns whole blocks (degrees paired large
-// with small, orders dealt in a zigzag), so within a step no wave reads what
-// another writes; the blocks' operands sit in registers before the block is
-// overwritten.  Output: per pair, as the dense kernel's KIND 0.
+// with small, orders dealt in a zigzag), so within a step no wave writes what
+// another reads for its own block; a block's operands sit in registers
+// before it is overwritten.  The blocks are read from global memory in the
+// matrix-core layout (zero-padded 64-value chunks in lane order), so a
+// block product is its k steps' loads followed by its matrix instructions,
+// specialised on the step count.  Rows read past a block's end hold finite
+// values (other blocks', or the zeroed rows past the last one) and meet
+// zero table entries.  Output: per pair, as the dense kernel's KIND 0.
 // The input cut of translations across three boxes (degrees <= pf read):
 // forward, the degrees above pf are loaded as zero and skipped; adjoint
 // (T^H = Phi d T_z^H d^T Phi^H, cut rows), the coaxial step zeroes the
@@ -959,7 +964,7 @@ struct RotJobDev {
   const int* group_dist;
   const int* pair_src;
   const R* phase;
-  const R* dtab;
+  const R* dtab;        // per rotation class: d blocks, then d^T blocks
   const cplx<R>* coax;  // adjoint: the conjugate-transposed blocks
   const cplx<R>* src;
   cplx<R>* cbuf;
@@ -972,6 +977,21 @@ struct RotBatch {
   RotJobDev<R> job[MAX_JOBS];
 };
 
+// Block offsets of the matrix-core tables (rot_dpoff, rot_cpoff), tabulated
+// at compile time: c_rot.d[n], c_rot.c[p][m + p]
+struct RotOffsets {
+  int d[ROT_MAXP + 2];
+  int c[ROT_MAXP + 1][2 * ROT_MAXP + 2];
+};
+constexpr RotOffsets make_rot_offsets() {
+  RotOffsets o{};
+  for (int n = 0; n <= ROT_MAXP + 1; ++n) o.d[n] = rot_dpoff(n);
+  for (int p = 0; p <= ROT_MAXP; ++p)
+    for (int m = -p; m <= p + 1; ++m) o.c[p][m + p] = rot_cpoff(p, m);
+  return o;
+}
+__constant__ RotOffsets c_rot = make_rot_offsets();
+
 __device__ __forceinline__ int isqrt_small(int c) {
   int n = (int)sqrtf((float)c);
   while (n * n > c) --n;
@@ -979,249 +999,241 @@ __device__ __forceinline__ int isqrt_small(int c) {
   return n;
 }
 
-// Degrees 0 .. nmax of both planes, rows n^2 .. n^2 + 2n, replaced in place
-// by d_n^T (TR) or d_n times them; degree pairs (nmax - j, j) go to wave
-// j % ROT_NW.  KS: k steps of the largest block (2 ROT_MAXP + 1 <= 4 KS).
-template <typename R, int KS, bool TR>
-__device__ __forceinline__ void rot_degrees(R* __restrict__ X, int PL,
-                                            const R* __restrict__ dt, int nmax, int wave,
-                                            int li, int lk) {
+// One degree block (rows rb .. rb + s - 1 of both planes) times the table
+// block A (matrix-core layout, NK k steps per 16-row tile; a block of NK
+// steps, s in 4 NK - 3 .. 4 NK, has (NK + 3) / 4 tiles, whose table entries
+// are all loaded at once).
+template <typename R, int NK>
+__device__ __forceinline__ void rot_deg_block(R* __restrict__ X, int PL,
+                                              const R* __restrict__ A, int rb, int s, int li,
+                                              int lk, int lane) {
   typedef typename MfmaOp<R>::v4 v4;
-  const int npair = nmax / 2 + 1;
-  for (int j = wave; j < npair; j += ROT_NW) {
-    for (int h = 0; h < 2; ++h) {
-      const int n = h ? j : nmax - j;
-      if (h && n == nmax - j) break;  // the middle degree once
-      const int s = 2 * n + 1, rb = n * n, nks = (s + 3) >> 2;
-      const R* __restrict__ A = dt + rot_doff(n);
-      R b0[KS], b1[KS];
+  constexpr int NMT = (NK + 3) / 4;
+  R a[NMT][NK];
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int k = 4 * ks + lk;
-        const bool ok = ks < nks && k < s;
-        b0[ks] = ok ? X[(rb + k) * ROT_LD + li] : R(0);
-        b1[ks] = ok ? X[PL + (rb + k) * ROT_LD + li] : R(0);
-      }
-      for (int r0 = 0; r0 < s; r0 += 16) {
-        const int row = r0 + li;
-        R a[KS];
+  for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const int k = 4 * ks + lk;
-          a[ks] = (ks < nks && k < s && row < s) ? (TR ? A[k * s + row] : A[row * s + k]) : R(0);
-        }
-        v4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+    for (int ks = 0; ks < NK; ++ks) a[mt][ks] = A[(mt * NK + ks) * 64 + lane];
+  R b0[NK], b1[NK];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-          if (ks < nks) {
-            c0 = MfmaOp<R>::mma(a[ks], b0[ks], c0);
-            c1 = MfmaOp<R>::mma(a[ks], b1[ks], c1);
-          }
+  for (int ks = 0; ks < NK; ++ks) {
+    const int row = rb + 4 * ks + lk;
+    b0[ks] = X[row * ROT_LD + li];
+    b1[ks] = X[PL + row * ROT_LD + li];
+  }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = r0 + MfmaOp<R>::row(lk, e);
-          if (r < s) {
-            X[(rb + r) * ROT_LD + li] = c0[e];
-            X[PL + (rb + r) * ROT_LD + li] = c1[e];
-          }
-        }
+  for (int mt = 0; mt < NMT; ++mt) {
+    v4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks) {
+      c0 = MfmaOp<R>::mma(a[mt][ks], b0[ks], c0);
+      c1 = MfmaOp<R>::mma(a[mt][ks], b1[ks], c1);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = 16 * mt + MfmaOp<R>::row(lk, e);
+      if (r < s) {
+        X[(rb + r) * ROT_LD + li] = c0[e];
+        X[PL + (rb + r) * ROT_LD + li] = c1[e];
       }
     }
   }
 }
 
-// Orders m = -p .. p: rows cidx(n, m), n = |m| .. p, replaced in place by the
-// coaxial block of order m times them (complex: four real products).
-// Forward: the input degrees above pf are zero and not read; adjoint: the
-// output degrees above pf are zero.  KZ: k steps of the largest block
-// (ROT_MAXP + 1 <= 4 KZ).
+// Degrees 0 .. nmax in place, times d_n (table tb = d or d^T blocks); degree
+// pairs (nmax - j, j) go to wave j % ROT_NW.  KS: k steps of the largest block.
+template <typename R, int KS>
+__device__ __forceinline__ void rot_degrees(R* __restrict__ X, int PL,
+                                            const R* __restrict__ tb, int nmax, int wave,
+                                            int li, int lk, int lane) {
+  const int npair = nmax / 2 + 1;
+  for (int j = wave; j < npair; j += ROT_NW) {
+    for (int h = 0; h < 2; ++h) {
+      const int n = h ? j : nmax - j;
+      if (h && n == nmax - j) break;  // the middle degree once
+      const int s = 2 * n + 1, rb = n * n;
+      const R* __restrict__ A = tb + c_rot.d[n];
+      switch (rot_nks(s)) {
+#define ROT_DEG_CASE(K)                                            \
+  case K:                                                          \
+    if constexpr (K <= KS) rot_deg_block<R, K>(X, PL, A, rb, s, li, lk, lane); \
+    break;
+        ROT_DEG_CASE(1) ROT_DEG_CASE(2) ROT_DEG_CASE(3) ROT_DEG_CASE(4)
+        ROT_DEG_CASE(5) ROT_DEG_CASE(6) ROT_DEG_CASE(7) ROT_DEG_CASE(8)
+        ROT_DEG_CASE(9) ROT_DEG_CASE(10) ROT_DEG_CASE(11) ROT_DEG_CASE(12)
+#undef ROT_DEG_CASE
+        default: break;
+      }
+    }
+  }
+}
+
+// One order block: rows cidx(n, m), n = am .. p, times the coaxial block T
+// (matrix-core layout, nks k steps per tile, of which the first NK are read:
+// the forward cut reads fewer).  Input rows past p are clamped to p (finite;
+// they meet zero table entries); output degrees past kout - 1 + am are zero.
+template <typename R, int NK>
+__device__ __forceinline__ void rot_ord_block(R* __restrict__ X, int PL,
+                                              const cplx<R>* __restrict__ T, int p, int m,
+                                              int am, int s, int nks, int kout, int li, int lk,
+                                              int lane) {
+  typedef typename MfmaOp<R>::v4 v4;
+  R yr[NK], yi[NK];
+#pragma unroll
+  for (int ks = 0; ks < NK; ++ks) {
+    const int n = min(am + 4 * ks + lk, p), row = n * n + n + m;
+    yr[ks] = X[row * ROT_LD + li];
+    yi[ks] = X[PL + row * ROT_LD + li];
+  }
+  const int nmt = rot_nmt(s);
+  for (int mt = 0; mt < nmt; ++mt) {
+    cplx<R> a[NK];
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks) a[ks] = T[(mt * nks + ks) * 64 + lane];
+    v4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks) {
+      cr = MfmaOp<R>::mma(a[ks].re, yr[ks], cr);
+      cr = MfmaOp<R>::mma(-a[ks].im, yi[ks], cr);
+      ci = MfmaOp<R>::mma(a[ks].re, yi[ks], ci);
+      ci = MfmaOp<R>::mma(a[ks].im, yr[ks], ci);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = 16 * mt + MfmaOp<R>::row(lk, e);
+      if (r < s) {
+        const int n = am + r, idx = n * n + n + m;
+        const bool keep = r < kout;
+        X[idx * ROT_LD + li] = keep ? cr[e] : R(0);
+        X[PL + idx * ROT_LD + li] = keep ? ci[e] : R(0);
+      }
+    }
+  }
+}
+
+// Orders m = -p .. p in place, dealt in a zigzag over the waves (order index
+// i = 0, 1, 2, ... is m = 0, 1, -1, 2, ...).  Forward: the input degrees
+// above pf are zero and not read; adjoint: the output degrees above pf are
+// zero.  KZ: k steps of the largest block.
 template <typename R, int KZ, bool ADJ>
 __device__ __forceinline__ void rot_orders(R* __restrict__ X, int PL,
                                            const cplx<R>* __restrict__ cz, int p, int pf,
-                                           int wave, int li, int lk) {
-  typedef typename MfmaOp<R>::v4 v4;
+                                           int wave, int li, int lk, int lane) {
   for (int rnd = 0;; ++rnd) {
-    // zigzag over the waves: order index i = 0, 1, 2, ... is m = 0, 1, -1, 2, ...
     const int i = rnd * ROT_NW + ((rnd & 1) ? ROT_NW - 1 - wave : wave);
     if (i > 2 * p) break;
     const int m = (i & 1) ? (i + 1) / 2 : -(i / 2);
     const int am = m < 0 ? -m : m, s = p + 1 - am;
     const int kin = ADJ ? s : min(s, pf + 1 - am);   // input degrees read
     const int kout = ADJ ? min(s, pf + 1 - am) : s;  // output degrees kept
-    const int nks = kin > 0 ? (kin + 3) >> 2 : 0;
-    const cplx<R>* __restrict__ T = cz + rot_coff(p, m);
-    R yr[KZ], yi[KZ];
-#pragma unroll
-    for (int ks = 0; ks < KZ; ++ks) {
-      const int k = 4 * ks + lk, n = am + k;
-      const bool ok = ks < nks && k < kin;
-      const int row = n * n + n + m;
-      yr[ks] = ok ? X[row * ROT_LD + li] : R(0);
-      yi[ks] = ok ? X[PL + row * ROT_LD + li] : R(0);
-    }
-    for (int r0 = 0; r0 < s; r0 += 16) {
-      const int row = r0 + li;
-      R ar[KZ], ai[KZ];
-#pragma unroll
-      for (int ks = 0; ks < KZ; ++ks) {
-        const int k = 4 * ks + lk;
-        cplx<R> v = mk<R>(0, 0);
-        if (ks < nks && k < kin && row < s) v = T[row * s + k];
-        ar[ks] = v.re;
-        ai[ks] = v.im;
-      }
-      v4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-#pragma unroll
-      for (int ks = 0; ks < KZ; ++ks)
-        if (ks < nks) {
-          cr = MfmaOp<R>::mma(ar[ks], yr[ks], cr);
-          cr = MfmaOp<R>::mma(-ai[ks], yi[ks], cr);
-          ci = MfmaOp<R>::mma(ar[ks], yi[ks], ci);
-          ci = MfmaOp<R>::mma(ai[ks], yr[ks], ci);
-        }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = r0 + MfmaOp<R>::row(lk, e);
-        if (r < s) {
-          const int n = am + r, idx = n * n + n + m;
-          const bool keep = r < kout;
-          X[idx * ROT_LD + li] = keep ? cr[e] : R(0);
-          X[PL + idx * ROT_LD + li] = keep ? ci[e] : R(0);
+    const cplx<R>* __restrict__ T = cz + c_rot.c[p][m + p];
+    const int nks = rot_nks(s);
+    switch (kin > 0 ? rot_nks(kin) : 0) {
+#define ROT_ORD_CASE(K)                                                          \
+  case K:                                                                        \
+    if constexpr (K <= KZ) rot_ord_block<R, K>(X, PL, T, p, m, am, s, nks, kout, li, lk, lane); \
+    break;
+      ROT_ORD_CASE(1) ROT_ORD_CASE(2) ROT_ORD_CASE(3)
+      ROT_ORD_CASE(4) ROT_ORD_CASE(5) ROT_ORD_CASE(6)
+#undef ROT_ORD_CASE
+      default: {  // no input degree: the block's outputs are zero
+        for (int r = lane; r < s * ROT_CT; r += 64) {
+          const int n = am + r / ROT_CT, cc = r % ROT_CT, idx = n * n + n + m;
+          X[idx * ROT_LD + cc] = R(0);
+          X[PL + idx * ROT_LD + cc] = R(0);
         }
       }
     }
   }
 }
 
-// Workgroup barrier that orders LDS accesses only: global loads and stores
-// in flight (a tile's prefetched inputs, the previous tile's outputs) are not
-// waited for, as a full barrier's release fence would.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// NC: LDS rows per plane (>= (p+1)^2 of every job of the launch).  TAB: the
-// group's rotation and coaxial tables are staged in LDS as well (orders
-// <= 15; float64 then fills the LDS), else read from global memory.
-// Persistent: workgroup b takes a contiguous run of tiles (the tiles of an
-// XCD's range split evenly over the workgroups on that XCD), so consecutive
-// tiles mostly share their group and its tables; the inputs of the next
-// tile are loaded into registers while the current one is computed.
-template <typename R, int NC, bool ADJ, bool TAB>
-__global__ void __launch_bounds__(64 * ROT_NW) k_rot_m2l(const RotBatch<R> batch) {
+// NC: LDS rows per plane (>= (p+1)^2 of every job of the launch; 4 rows more
+// hold zeros for reads past the last block).
+template <typename R, int NC, bool ADJ>
+__global__ void __launch_bounds__(64 * ROT_NW)
+    __attribute__((amdgpu_waves_per_eu(NC <= 256 ? 4 : 2))) k_rot_m2l(const RotBatch<R> batch) {
   constexpr int NT = 64 * ROT_NW;
-  constexpr int PL = NC * ROT_LD;
+  constexpr int NR = NC + 4;
+  constexpr int PL = NR * ROT_LD;
   constexpr int PM = NC <= 256 ? 15 : ROT_MAXP;  // largest order of the class
-  constexpr int KS = (2 * PM + 4) / 4;            // k steps of a degree block
-  constexpr int KZ = (PM + 4) / 4;                // k steps of an order block
-  constexpr int DSZ = TAB ? rot_dsz(PM) : 1;
-  constexpr int CSZ = TAB ? rot_csz(PM) : 1;
-  constexpr int PRE = (ROT_CT * NC + NT - 1) / NT;  // input values per thread
+  constexpr int KS = rot_nks(2 * PM + 1);
+  constexpr int KZ = rot_nks(PM + 1);
+  constexpr int CSTR = NC <= 256 ? 256 : 512;  // coefficients per pass
+  constexpr int CCS = NT / CSTR;               // pairs per pass
   __shared__ __attribute__((aligned(16))) R X[2 * PL];
-  __shared__ __attribute__((aligned(16))) R s_dt[DSZ];
-  __shared__ __attribute__((aligned(16))) cplx<R> s_cz[CSZ];
   __shared__ R s_ph[2][2 * ROT_MAXP + 1];
+  __shared__ int s_src[ROT_CT];
   __builtin_amdgcn_s_setprio(2);  // critical path: ahead of the near-field waves
-  const int nt = batch.ntiles, G = gridDim.x, wb = blockIdx.x;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  // this workgroup's tiles [t0, t1): XCD x = wb % 8 owns a contiguous range
-  const int x = wb & 7, jx = wb >> 3, gx = (G - x + 7) >> 3;
-  const int cnt = (nt >> 3) + (x < (nt & 7) ? 1 : 0);
-  const int start = x * (nt >> 3) + min(x, nt & 7);
-  const int t0 = start + (int)((int64_t)jx * cnt / gx);
-  const int t1 = start + (int)((int64_t)(jx + 1) * cnt / gx);
-  auto job_of = [&](int gt) {
+  for (int t = tid; t < 2 * PL; t += NT) X[t] = R(0);
+  const int nt = batch.ntiles;
+  for (int vb = blockIdx.x; vb < nt; vb += gridDim.x) {
+    __syncthreads();  // the previous tile no longer reads the shared arrays
+    // XCD-aware order, as for the dense kernel
+    const int xcd = vb & 7, slot_in_xcd = vb >> 3;
+    const int gtile = xcd * (nt >> 3) + min(xcd, nt & 7) + slot_in_xcd;
     int q = 0;
 #pragma unroll
     for (int i = 1; i < MAX_JOBS; ++i)
-      if (i < batch.n && gt >= batch.tile0[i]) q = i;
-    return q;
-  };
-  // inputs of tile gt (forward: the kc coefficients the cut keeps, rest zero)
-  cplx<R> pre[PRE];
-  auto fetch = [&](int gt) {
-    const int q = job_of(gt);
+      if (i < batch.n && gtile >= batch.tile0[i]) q = i;
     const RotJobDev<R> J = select_job(batch.job, q);
-    const int tile = gt - select_job(batch.tile0, q);
-    const int nc = (J.p + 1) * (J.p + 1);
-    const int grp = J.tile_group[tile], p0 = J.tile_pair0[tile], np = J.tile_npairs[tile];
-    const int kin = (!ADJ && J.group_kc) ? min(nc, J.group_kc[grp]) : nc;
-#pragma unroll
-    for (int i = 0; i < PRE; ++i) {
-      const int e = tid + NT * i, cc = e / nc, c = e - cc * nc;
-      pre[i] = mk<R>(0, 0);
-      if (cc < np && c < kin) pre[i] = J.src[(int64_t)J.pair_src[p0 + cc] * nc + c];
-    }
-  };
-  // tables in LDS: the next tile's inputs are prefetched (registers allow);
-  // else each tile loads its own
-  if (TAB && t0 < t1) fetch(t0);
-  int cur_q = -1, cur_th = -1, cur_di = -1, cur_grp = -1;
-  for (int gt = t0; gt < t1; ++gt) {
-    const int q = job_of(gt);
-    const RotJobDev<R> J = select_job(batch.job, q);
-    const int tile = gt - select_job(batch.tile0, q);
+    const int tile = gtile - select_job(batch.tile0, q);
     const int p = J.p, nc = (p + 1) * (p + 1);
     const int grp = J.tile_group[tile], p0 = J.tile_pair0[tile], np = J.tile_npairs[tile];
     const int kc = J.group_kc ? min(nc, J.group_kc[grp]) : nc;
     int pf = 0;
     while ((pf + 2) * (pf + 2) <= kc) ++pf;
     const int th = J.group_theta[grp], di = J.group_dist[grp];
-    lds_barrier();  // the previous tile no longer reads the shared arrays
-    const bool new_tab = TAB && (q != cur_q || th != cur_th || di != cur_di);
-    const bool new_ph = q != cur_q || grp != cur_grp;
-    if (new_tab) {
-      const R* __restrict__ gd = J.dtab + (int64_t)th * rot_dsz(p);
-      const cplx<R>* __restrict__ gc = J.coax + (int64_t)di * rot_csz(p);
-      const int nd = rot_dsz(p), ncz = rot_csz(p);
-#pragma unroll 4
-      for (int t = tid; t < nd; t += NT) s_dt[t] = gd[t];
-#pragma unroll 4
-      for (int t = tid; t < ncz; t += NT) s_cz[t] = gc[t];
-    }
-    if (new_ph && tid < 2 * p + 1) {  // e^{i m phi}, m = -p .. p
+    if (tid < ROT_CT) s_src[tid] = tid < np ? J.pair_src[p0 + tid] : -1;
+    if (tid < 2 * p + 1) {  // e^{i m phi}, m = -p .. p
       const int m = tid - p, am = m < 0 ? -m : m;
       const R* ph = J.phase + ((int64_t)grp * (p + 1) + am) * 2;
       s_ph[0][tid] = ph[0];
       s_ph[1][tid] = m < 0 ? -ph[1] : ph[1];
     }
-    cur_q = q;
-    cur_th = th;
-    cur_di = di;
-    cur_grp = grp;
-    if (!TAB) fetch(gt);
-    if (new_tab || new_ph) lds_barrier();
-    // Phi^H: coefficient (n, m) times e^{i m phi}
-#pragma unroll
-    for (int i = 0; i < PRE; ++i) {
-      const int e = tid + NT * i, cc = e / nc, c = e - cc * nc;
-      if (cc < ROT_CT) {
-        const int n = isqrt_small(c), m = c - n * n - n;
-        const R er = s_ph[0][m + p], ei = s_ph[1][m + p];
-        X[c * ROT_LD + cc] = pre[i].re * er - pre[i].im * ei;
-        X[PL + c * ROT_LD + cc] = pre[i].re * ei + pre[i].im * er;
-      }
-    }
-    if (TAB && gt + 1 < t1) fetch(gt + 1);  // in flight during the steps below
-    lds_barrier();
-    const R* dt = TAB ? (const R*)s_dt : J.dtab + (int64_t)th * rot_dsz(p);
-    const cplx<R>* cz = TAB ? (const cplx<R>*)s_cz : J.coax + (int64_t)di * rot_csz(p);
-    rot_degrees<R, KS, true>(X, PL, dt, ADJ ? p : pf, wave, li, lk);  // d^T
-    lds_barrier();
-    rot_orders<R, KZ, ADJ>(X, PL, cz, p, pf, wave, li, lk);  // T_z (or T_z^H)
-    lds_barrier();
-    rot_degrees<R, KS, false>(X, PL, dt, ADJ ? pf : p, wave, li, lk);  // d
-    lds_barrier();
-    // Phi: coefficient (n, m) times e^{-i m phi}, written per pair
-    for (int t = tid; t < np * nc; t += NT) {
-      const int cc = t / nc, c = t - cc * nc;
+    __syncthreads();
+    // Phi^H: coefficient (n, m) times e^{i m phi} (forward: the kc
+    // coefficients the cut keeps, the rest zero)
+    const int kin = ADJ ? nc : kc;
+    for (int c = tid % CSTR; c < nc; c += CSTR) {
       const int n = isqrt_small(c), m = c - n * n - n;
       const R er = s_ph[0][m + p], ei = s_ph[1][m + p];
-      const R xr = X[c * ROT_LD + cc], xi = X[PL + c * ROT_LD + cc];
-      J.cbuf[(int64_t)(p0 + cc) * nc + c] = mk<R>(xr * er + xi * ei, xi * er - xr * ei);
+      cplx<R> v[ROT_CT / CCS];
+#pragma unroll
+      for (int i = 0; i < ROT_CT / CCS; ++i) {
+        const int cc = tid / CSTR + CCS * i;
+        v[i] = (cc < np && c < kin) ? J.src[(int64_t)s_src[cc] * nc + c] : mk<R>(0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < ROT_CT / CCS; ++i) {
+        const int cc = tid / CSTR + CCS * i;
+        X[c * ROT_LD + cc] = v[i].re * er - v[i].im * ei;
+        X[PL + c * ROT_LD + cc] = v[i].re * ei + v[i].im * er;
+      }
+    }
+    __syncthreads();
+    const int dpsz = c_rot.d[p + 1], cpsz = c_rot.c[p][2 * p + 1];
+    const R* __restrict__ dt = J.dtab + (int64_t)th * 2 * dpsz;
+    const cplx<R>* __restrict__ cz = J.coax + (int64_t)di * cpsz;
+    rot_degrees<R, KS>(X, PL, dt + dpsz, ADJ ? p : pf, wave, li, lk, lane);  // d^T
+    __syncthreads();
+    rot_orders<R, KZ, ADJ>(X, PL, cz, p, pf, wave, li, lk, lane);  // T_z (or T_z^H)
+    __syncthreads();
+    rot_degrees<R, KS>(X, PL, dt, ADJ ? pf : p, wave, li, lk, lane);  // d
+    __syncthreads();
+    // Phi: coefficient (n, m) times e^{-i m phi}, written per pair
+    for (int c = tid % CSTR; c < nc; c += CSTR) {
+      const int n = isqrt_small(c), m = c - n * n - n;
+      const R er = s_ph[0][m + p], ei = s_ph[1][m + p];
+#pragma unroll
+      for (int i = 0; i < ROT_CT / CCS; ++i) {
+        const int cc = tid / CSTR + CCS * i;
+        if (cc < np) {
+          const R xr = X[c * ROT_LD + cc], xi = X[PL + c * ROT_LD + cc];
+          J.cbuf[(int64_t)(p0 + cc) * nc + c] = mk<R>(xr * er + xi * ei, xi * er - xr * ei);
+        }
+      }
     }
   }
 }
@@ -1719,31 +1731,17 @@ static void launch_gemm(const GemmBatch<R>& b, int nt, hipStream_t s, hipEvent_t
               start, done, b);
 }
 
-// compute units of the current device (cached per device)
-static int device_cus() {
-  static int cus[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!cus[dev] &&
-      hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    cus[dev] = 256;
-  return cus[dev];
-}
-
-// grid: workgroups (0: four per compute unit); at least min(tiles, 8) so that
-// every XCD's range of tiles has a workgroup
+// grid: workgroups (0: one per tile), a multiple of 8 or all tiles
 template <typename R, bool ADJ>
 static int launch_rot(const RotBatch<R>& b, int maxnc, int grid, hipStream_t s, hipEvent_t done,
                       hipEvent_t start) {
   constexpr int NC_HI = (ROT_MAXP + 1) * (ROT_MAXP + 1);
   const int nt = b.ntiles;
-  int g = grid > 0 ? grid : 4 * device_cus();
-  g = std::min(nt, std::max(g, 8));
+  const int g = (grid > 0 && grid < nt) ? std::max(8, grid & ~7) : nt;
   if (maxnc <= 256)
-    launch_done(k_rot_m2l<R, 256, ADJ, true>, dim3(g), dim3(64 * ROT_NW), 0, s, start, done, b);
+    launch_done(k_rot_m2l<R, 256, ADJ>, dim3(g), dim3(64 * ROT_NW), 0, s, start, done, b);
   else if (maxnc <= NC_HI)
-    launch_done(k_rot_m2l<R, NC_HI, ADJ, false>, dim3(g), dim3(64 * ROT_NW), 0, s, start, done,
-                b);
+    launch_done(k_rot_m2l<R, NC_HI, ADJ>, dim3(g), dim3(64 * ROT_NW), 0, s, start, done, b);
   else {
     set_error("expansion order too high for the rotation-based translations");
     return -1;

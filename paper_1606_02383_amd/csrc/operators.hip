@@ -1118,6 +1118,46 @@ __global__ void k_rot_coax(int p, int ndist, const cplx<R>* __restrict__ dense,
   coax_h[t] = mk<R>(v.re, -v.im);
 }
 
+// Matrix-core layout of the degree blocks: out[c][o][rot_dpoff(n) + chunk]
+// with o = 0 for d_n, 1 for d_n^T (from dtab, rot_dsz(p) per class).
+template <typename R>
+__global__ void k_rot_pad_d(int p, int nth, const R* __restrict__ dtab, R* __restrict__ out) {
+  const int dp = rot_dpsz(p);
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nth * 2 * dp) return;
+  const int c = (int)(t / (2 * dp)), o = (int)(t / dp % 2), e = (int)(t % dp);
+  int n = 0;
+  while (n < p && rot_dpoff(n + 1) <= e) ++n;
+  const int s = 2 * n + 1, nks = rot_nks(s), l = e - rot_dpoff(n);
+  const int chunk = l >> 6, lane = l & 63, mt = chunk / nks, ks = chunk % nks;
+  const int row = 16 * mt + (lane & 15), col = 4 * ks + (lane >> 4);
+  R v = 0;
+  if (row < s && col < s) {
+    const R* A = dtab + (int64_t)c * rot_dsz(p) + rot_doff(n);
+    v = o ? A[col * s + row] : A[row * s + col];
+  }
+  out[t] = v;
+}
+
+// Matrix-core layout of the coaxial blocks: out[c][rot_cpoff(p, m) + chunk]
+// (from coax, rot_csz(p) per class)
+template <typename R>
+__global__ void k_rot_pad_c(int p, int ndist, const cplx<R>* __restrict__ coax,
+                            cplx<R>* __restrict__ out) {
+  const int cp = rot_cpsz(p);
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ndist * cp) return;
+  const int c = (int)(t / cp), e = (int)(t % cp);
+  int m = -p;
+  while (m < p && rot_cpoff(p, m + 1) <= e) ++m;
+  const int s = p + 1 - (m < 0 ? -m : m), nks = rot_nks(s), l = e - rot_cpoff(p, m);
+  const int chunk = l >> 6, lane = l & 63, mt = chunk / nks, ks = chunk % nks;
+  const int row = 16 * mt + (lane & 15), col = 4 * ks + (lane >> 4);
+  cplx<R> v = mk<R>(0, 0);
+  if (row < s && col < s) v = coax[(int64_t)c * rot_csz(p) + rot_coff(p, m) + row * s + col];
+  out[t] = v;
+}
+
 template <typename R>
 int build_rotations(Problem& P, PrecisionData<R>& D, hipStream_t s) {
   DevArena scratch;
@@ -1179,9 +1219,14 @@ int build_rotations(Problem& P, PrecisionData<R>& D, hipStream_t s) {
     ARENA_ALLOC(D.ops, op.rot_theta, N_OFFSETS);
     ARENA_ALLOC(D.ops, op.rot_dist, N_OFFSETS);
     ARENA_ALLOC(D.ops, op.rot_phase, phase.size());
-    ARENA_ALLOC(D.ops, op.rot_dtab, (int64_t)nth * rot_dsz(p));
-    ARENA_ALLOC(D.ops, op.rot_coax, (int64_t)ndist * rot_csz(p));
-    ARENA_ALLOC(D.ops, op.rot_coax_h, (int64_t)ndist * rot_csz(p));
+    ARENA_ALLOC(D.ops, op.rot_dtab, (int64_t)nth * 2 * rot_dpsz(p));
+    ARENA_ALLOC(D.ops, op.rot_coax, (int64_t)ndist * rot_cpsz(p));
+    ARENA_ALLOC(D.ops, op.rot_coax_h, (int64_t)ndist * rot_cpsz(p));
+    R* dtab;
+    cplx<R>*coax, *coax_h;
+    ARENA_ALLOC(scratch, dtab, (int64_t)nth * rot_dsz(p));
+    ARENA_ALLOC(scratch, coax, (int64_t)ndist * rot_csz(p));
+    ARENA_ALLOC(scratch, coax_h, (int64_t)ndist * rot_csz(p));
     auto up = [&](void* d, const void* h, size_t bytes) -> int {
       if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
       return 0;
@@ -1206,7 +1251,11 @@ int build_rotations(Problem& P, PrecisionData<R>& D, hipStream_t s) {
         (r = up(dcs, cs_theta.data(), sizeof(double) * cs_theta.size())))
       return r;
     hipLaunchKernelGGL(k_rot_small_d<R>, dim3(nth, p + 1), dim3(256), 0, s, p, dcs, p + 1,
-                       2 * p + 2, dgx, dgw, op.rot_dtab);
+                       2 * p + 2, dgx, dgw, dtab);
+    BEM_LAUNCH_CHECK();
+    const int64_t totd = (int64_t)nth * 2 * rot_dpsz(p);
+    hipLaunchKernelGGL(k_rot_pad_d<R>, dim3(ceil_div(totd, 256)), dim3(256), 0, s, p, nth, dtab,
+                       op.rot_dtab);
     BEM_LAUNCH_CHECK();
     // coaxial blocks: the dense translations along e_z, same level scaling
     std::vector<double> rs = coef_scale(p, P.k * P.h[l], +1), cs = coef_scale(p, P.k * P.h[l], +1);
@@ -1215,7 +1264,14 @@ int build_rotations(Problem& P, PrecisionData<R>& D, hipStream_t s) {
     if (r) return r;
     const int64_t tot = (int64_t)ndist * rot_csz(p);
     hipLaunchKernelGGL(k_rot_coax<R>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, p, ndist, dense,
-                       op.rot_coax, op.rot_coax_h);
+                       coax, coax_h);
+    BEM_LAUNCH_CHECK();
+    const int64_t totc = (int64_t)ndist * rot_cpsz(p);
+    hipLaunchKernelGGL(k_rot_pad_c<R>, dim3(ceil_div(totc, 256)), dim3(256), 0, s, p, ndist, coax,
+                       op.rot_coax);
+    BEM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rot_pad_c<R>, dim3(ceil_div(totc, 256)), dim3(256), 0, s, p, ndist,
+                       coax_h, op.rot_coax_h);
     BEM_LAUNCH_CHECK();
     BEM_HIP_TRY(hipStreamSynchronize(s));
     scratch.release();

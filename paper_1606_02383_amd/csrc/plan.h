@@ -35,6 +35,29 @@ __host__ __device__ constexpr int rot_csz(int p) { return (p + 1) * (p + 1) + 2 
 __host__ __device__ constexpr int rot_coff(int p, int m) {
   return m <= 0 ? rot_s2(p + m) : 2 * rot_s2(p) + (p + 1) * (p + 1) - rot_s2(p + 1 - m);
 }
+// Matrix-core layout of the same blocks, as the rotation kernel reads them:
+// a block of s rows and columns in 16-row tiles (rot_nmt) and 4-column
+// k steps (rot_nks), each (tile, step) a chunk of 64 values in lane order
+// (lane = row + 16 column-in-step), zero outside the block; block n of the
+// degree tables at rot_dpoff(n), block m of the coaxial tables at
+// rot_cpoff(p, m).
+__host__ __device__ constexpr int rot_nmt(int s) { return (s + 15) >> 4; }
+__host__ __device__ constexpr int rot_nks(int s) { return (s + 3) >> 2; }
+__host__ __device__ constexpr int rot_dpoff(int n) {
+  int o = 0;
+  for (int j = 0; j < n; ++j) o += rot_nmt(2 * j + 1) * rot_nks(2 * j + 1) * 64;
+  return o;
+}
+__host__ __device__ constexpr int rot_dpsz(int p) { return rot_dpoff(p + 1); }
+__host__ __device__ constexpr int rot_cpoff(int p, int m) {
+  int o = 0;
+  for (int mm = -p; mm < m; ++mm) {
+    const int s = p + 1 - (mm < 0 ? -mm : mm);
+    o += rot_nmt(s) * rot_nks(s) * 64;
+  }
+  return o;
+}
+__host__ __device__ constexpr int rot_cpsz(int p) { return rot_cpoff(p, p + 1); }
 
 // Device allocation registry: every buffer a problem owns.
 struct DevArena {
@@ -90,8 +113,9 @@ struct GroupedOp {
   // rot_on): tiles of up to ROT_CT pairs of one group (forward and adjoint
   // alike, the adjoint pair lists keep the group order), per group the
   // rotation class (polar angle), distance class and e^{i m phi} for
-  // m = 0..p (re, im); per rotation class the real blocks d_n; per distance
-  // class the coaxial blocks and their conjugate transposes
+  // m = 0..p (re, im); per rotation class the real blocks d_n and d_n^T
+  // (matrix-core layout, rot_dpsz(p) values each); per distance class the
+  // coaxial blocks and their conjugate transposes (rot_cpsz(p) each)
   bool rot_on = false, rot_ready = false;
   int rot_p = 0, rot_n_tiles = 0;
   int* rot_tile_group = nullptr;
