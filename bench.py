@@ -254,6 +254,26 @@ def m2l_flops(n, nfar, p, cut):
     return 8.0 * ((n - nfar) * (p + 1) ** 4 + nfar * (p + 1) ** 2 * (pf + 1) ** 2)
 
 
+def rot_m2l_flops(n, nfar, p, cut):
+    """Algorithmic FLOPs of n rotation-based M2L pairs at order p: per pair the
+    two real rotations (4 (2l+1)^2 per degree l: a real block on a complex
+    vector), the coaxial step (8 per complex multiply-add, s^2 per order m,
+    s = p + 1 - |m|) and the two phase multiplications (6 per coefficient);
+    the nfar pairs across three boxes rotate and translate only the degrees
+    <= p - cut of their input."""
+    pf = max(0, p - cut) if cut > 0 else p
+
+    def rot(q):
+        return sum(4 * (2 * l + 1) ** 2 for l in range(q + 1))
+
+    coax = sum(8 * (p + 1 - abs(m)) ** 2 for m in range(-p, p + 1))
+    coax_cut = sum(8 * (p + 1 - abs(m)) * max(0, pf + 1 - abs(m)) for m in range(-p, p + 1))
+    nc, kc = (p + 1) ** 2, (pf + 1) ** 2
+    full = 2 * rot(p) + coax + 12 * nc
+    far = rot(pf) + rot(p) + coax_cut + 6 * kc + 6 * nc
+    return float((n - nfar) * full + nfar * far)
+
+
 def _cpu_points(chunk):
     """Oracle state and adjoint fields, gradients and T_Omega at a few points."""
     from oracle import solve
@@ -609,6 +629,28 @@ def main():
                                   5),
                 "p2p": p2p_roofline(st, prof, alone)}
 
+    # float64 leaf-level M2L (the refinement's float64 products; rotation-based
+    # where the plan's tuner found it faster): algorithmic FLOPs of the
+    # algorithm run, and those of the same translations by dense operators
+    rot64 = st["m2l_rot64"]
+    fc64 = st["far_cut"][0]
+    dense64 = m2l_flops(st["n_m2l"][L], st["n_m2l_far"][L], st["order64"][L], fc64)
+    flops64 = (rot_m2l_flops(st["n_m2l"][L], st["n_m2l_far"][L], st["order64"][L], fc64)
+               if rot64[L] else dense64)
+    f64_ms, f64_calls = prof.get(("m2l_leaf", "f64", "fwd"), (0.0, 0))
+    f64_alone_ms, f64_alone_calls = alone.get(("m2l_leaf", "f64", "fwd"), (0.0, 0))
+    f64_launch = f64_ms / max(1, f64_calls)
+    f64_alone = f64_alone_ms / max(1, f64_alone_calls)
+    m2l64 = {"kernel": ("k_rot_m2l<double,256,false> (rotation-based)" if rot64[L]
+                        else "k_grouped_gemm<double,...,false,0> (dense)"),
+             "rotation_based_levels": [l for l in range(2, L + 1) if rot64[l]],
+             "order": st["order64"][L], "far_cut": fc64,
+             "flops_per_launch": flops64, "dense_equivalent_flops": dense64,
+             "avg_launch_ms": round(f64_launch, 5), "alone_ms": round(f64_alone, 5),
+             "tflops_alone": round(flops64 / max(f64_alone, 1e-9) / 1e9, 3),
+             "frac_alone": round(flops64 / max(f64_alone, 1e-9) / 1e9 / (PEAK_FP64 / 1e12), 4),
+             "peak_tflops": PEAK_FP64 / 1e12}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (sampled rows)...")
@@ -631,7 +673,8 @@ def main():
                    "solver": "GMRES(50), float32 inner / float64 refinement",
                    "inner_tol": args.inner_tol, "leaf_level": L, "schedule": st["schedule"],
                    "order32": st["order32"][2:], "order64": st["order64"][2:],
-                   "far_cut": st["far_cut"]},
+                   "far_cut": st["far_cut"], "m2l_rotation_levels_f64": st["m2l_rot64"][2:],
+                   "m2l_rotation_levels_f32": st["m2l_rot32"][2:]},
         "f64_gmres": {"matvecs": info64["matvec64"], "ms": t64_solve * 1e3,
                       "matvecs_per_s": info64["matvec64"] / t64_solve},
         "ir_solve": {"matvec32": info["matvec32"], "matvec64": info["matvec64"],
@@ -644,6 +687,7 @@ def main():
         "stage_ms_per_call": stages,
         "stage_ms_alone": stages_alone,
         "roofline": roofline,
+        "m2l_f64_leaf": m2l64,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

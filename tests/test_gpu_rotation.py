@@ -15,7 +15,9 @@ along it, rotate back; bem_problem.m2l_rot).
   rotation-based kernel (launches merging levels and problems) against the
   same systems solved one by one on a dense plan.
 * The tuner (m2l_rot = 0) reports per level what it kept; its product
-  matches the dense plan's.
+  matches the dense plan's, on the 20480-element sphere at k = 4 and on the
+  81920-element sphere at k = 16 (higher orders; there also against the
+  oracle's rows and columns).
 """
 import numpy as np
 import pytest
@@ -178,3 +180,46 @@ def test_bad_rotation_request_is_rejected():
     V, T = icosphere(2)
     with pytest.raises(bem.BemError):
         bem.Plan(bem.Problem(V, T, 2.0, m2l_rot=3))
+
+
+def test_larger_kd_sphere81920_k16():
+    """The 81920-element sphere at k = 16 (twice the benchmark's k h): the
+    orders rise, the tuner keeps the rotation-based translations where they
+    are faster; the product matches the oracle's rows and the dense-only
+    plan's product, the adjoint the oracle's columns."""
+    import torch
+    bem = _lib()
+    wl = WORKLOADS["sphere81920_k16"]
+    V, T = wl.mesh_arrays()
+    _log("case: sphere81920_k16 tuned plan against the oracle and a dense-only plan")
+    tuned = bem.Plan(bem.Problem(V, T, wl.k, leaf_cap=64))
+    st = tuned.stats()
+    _log(f"  orders f64 {st['order64'][2:]} f32 {st['order32'][2:]}, far cut {st['far_cut']}, "
+         f"rotation-based f64 {st['m2l_rot64'][2:]} f32 {st['m2l_rot32'][2:]}")
+    g = obem.Geometry(V, T)
+    rng = np.random.default_rng(wl.seed)
+    p, q = complex_normal(rng, len(T)), complex_normal(rng, len(T))
+    rows = np.sort(rng.choice(len(T), 32, replace=False))
+    ref = obem.matvec(g, wl.k, wl.alpha, p, q, rows=rows, block=16)
+    ys = {}
+    for prec, bar in ((0, 1e-6), (1, 1e-4)):
+        y = tuned.matvec(torch.from_numpy(p), torch.from_numpy(q), prec=prec).cpu().numpy()
+        ys[prec] = y
+        e = _rel(y[rows], ref)
+        _log(f"  prec {prec}: sampled rel-L2 err {e:.3e}")
+        assert e < bar
+    yv = complex_normal(rng, len(T))
+    cols = np.sort(rng.choice(len(T), 16, replace=False))
+    u, w = tuned.matvec_adjoint(torch.from_numpy(yv))
+    uref, wref = obem.matvec_adjoint(g, wl.k, wl.alpha, yv, cols=cols, block=8)
+    eu, ew = _rel(u.cpu().numpy()[cols], uref), _rel(w.cpu().numpy()[cols], wref)
+    _log(f"  adjoint columns: u {eu:.3e} w {ew:.3e}")
+    assert eu < 1e-6 and ew < 1e-6
+    tuned.close()
+    dense = bem.Plan(bem.Problem(V, T, wl.k, leaf_cap=64, m2l_rot=1))
+    for prec, bar in ((0, 1e-13), (1, 1e-6)):
+        y = dense.matvec(torch.from_numpy(p), torch.from_numpy(q), prec=prec).cpu().numpy()
+        e = _rel(ys[prec], y)
+        _log(f"  prec {prec}: tuned vs dense-only plan {e:.2e}")
+        assert e < bar
+    dense.close()

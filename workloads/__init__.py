@@ -187,6 +187,9 @@ WORKLOADS = {
     "sphere20480_k4": Workload("sphere20480_k4", "ico5", 4.0, 2),
     "sphere81920_k8": Workload("sphere81920_k8", "ico6", 8.0, 3),
     "cube49152_k6": Workload("cube49152_k6", "cube64", 6.0, 4),
+    # twice the wavenumber on the same mesh (~21 elements per wavelength):
+    # higher expansion orders, where the rotation-based translations pay
+    "sphere81920_k16": Workload("sphere81920_k16", "ico6", 16.0, 6),
 }
 
 
