@@ -1,8 +1,10 @@
 """The allocation-free product (bem_fmm_matvec_noalloc) against
 bem_fmm_matvec through the C ABI: two calls in a row on one device, the
 second on a smaller problem (the static buffer keeps the first call's
-contents), float64 and float32, with and without q; a problem whose buffers
-exceed the static buffer is rejected before any launch."""
+contents), float64 and float32, with and without q, with the plan's tuned
+translations and with rotation-based multipole-to-local translations on
+every level; a problem whose buffers exceed the static buffer is rejected
+before any launch."""
 import ctypes
 
 import numpy as np
@@ -32,11 +34,13 @@ def _call(bem, fn, plan, prob, prec, p, q, y):
     return getattr(bem._LIB, fn)(plan._h, prob, prec, bem._ptr(p), bem._ptr(q), bem._ptr(y), 1, s)
 
 
-def test_noalloc_product_matches_the_allocating_one():
+@pytest.mark.parametrize("rot", [0, 2])
+def test_noalloc_product_matches_the_allocating_one(rot):
     import torch
     bem = _lib()
     meshes = [(icosphere(3), 1.0), (icosphere(2), 2.0)]
-    plan = bem.Plan([bem.Problem(V, T, k, leaf_cap=16) for (V, T), k in meshes])
+    plan = bem.Plan([bem.Problem(V, T, k, leaf_cap=16, m2l_rot=rot) for (V, T), k in meshes])
+    _log(f"case: m2l_rot={rot}, rotation-based levels f64 {plan.stats(0)['m2l_rot64'][2:]}")
     rng = np.random.default_rng(71)
     for prec, tol in ((bem.BEM_C128, 1e-12), (bem.BEM_C64, 1e-6)):
         for prob in (0, 1):          # the second call on the smaller problem
