@@ -120,6 +120,9 @@ static int time_product(Problem& P, bool f32, hipStream_t s, float* ms) {
 // Stream schedule per precision: each candidate is timed on the problem's
 // own products and the fastest kept (the products' results do not depend on
 // the schedule).
+// Then, per level, dense or rotation-based M2L (rotation tables built here),
+// and the pair-tile width of the leaf-level M2L where it stays dense (its
+// width from the tile-count rule and the other widths).
 // Then, for the kept schedule, the grids of the two large launches that run
 // beside the far-field chain: the near field (one workgroup per leaf, or a
 // grid-stride launch of 2 or 4 per compute unit) and the leaf-level M2L (one
@@ -145,6 +148,27 @@ static int tune_rotations(Problem& P, PrecisionData<R>& D, int prec, hipStream_t
   }
   if (P.m2l_rot_req == 2) return time_product(P, prec == 1, s, best_ms);
   return 0;
+}
+
+template <typename R>
+static int tune_leaf_tile(Problem& P, PrecisionData<R>& D, int prec, hipStream_t s, float gain,
+                          float* best_ms) {
+  GroupedOp<R>& op = D.m2l[P.L];
+  if (op.rot_on || op.n_pairs == 0) return 0;
+  const int first = op.ct;
+  int best = first;
+  for (int ct : {128, 64, 32, 16}) {
+    if (ct == first || (ct == 128 && sizeof(R) == 8)) continue;
+    int r = retile_forward<R>(op, ct, D.ops, s);
+    float ms = 0.f;
+    if (!r) r = time_product(P, prec == 1, s, &ms);
+    if (r) return r;
+    if (ms < gain * *best_ms) {
+      *best_ms = ms;
+      best = ct;
+    }
+  }
+  return retile_forward<R>(op, best, D.ops, s);
 }
 
 static int tune_schedule(Problem& P, hipStream_t s) {
@@ -185,6 +209,12 @@ static int tune_schedule(Problem& P, hipStream_t s) {
     if (P.m2l_rot_req != 1) {
       int r = prec == 1 ? tune_rotations<float>(P, P.f32, prec, s, gain, &best_ms)
                         : tune_rotations<double>(P, P.f64, prec, s, gain, &best_ms);
+      if (r) return r;
+    }
+    // pair-tile width of the leaf-level M2L where it runs the dense kernel
+    {
+      int r = prec == 1 ? tune_leaf_tile<float>(P, P.f32, prec, s, gain, &best_ms)
+                        : tune_leaf_tile<double>(P, P.f64, prec, s, gain, &best_ms);
       if (r) return r;
     }
     // near-field grid x leaf-level M2L grid (one or two workgroups per CU)

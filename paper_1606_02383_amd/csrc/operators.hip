@@ -632,6 +632,38 @@ static int finish_grouped(GroupedOp<R>& op, int* d0, int* s0, int* c0, int np, i
   return 0;
 }
 
+// Forward tiles of a grouped op rebuilt for pair-tile width ct (16, 32, 64,
+// or 128 in float32) from its group ranges; the pairs, operators and
+// reduction lists are unchanged.
+template <typename R>
+int retile_forward(GroupedOp<R>& op, int ct, DevArena& arena, hipStream_t s) {
+  if (op.gstart_h.empty() || op.ct == ct) return 0;
+  std::vector<int> tg, tp0, tnp, tr0;
+  make_tiles(op.gstart_h, op.rows, ct, GEMM_RT, tg, tp0, tnp, tr0);
+  const int nt = (int)tg.size();
+  int *g, *p0, *np, *r0;
+  ARENA_ALLOC(arena, g, nt);
+  ARENA_ALLOC(arena, p0, nt);
+  ARENA_ALLOC(arena, np, nt);
+  ARENA_ALLOC(arena, r0, nt);
+  if (nt > 0) {
+    BEM_HIP_TRY(hipMemcpyAsync(g, tg.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+    BEM_HIP_TRY(hipMemcpyAsync(p0, tp0.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+    BEM_HIP_TRY(hipMemcpyAsync(np, tnp.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+    BEM_HIP_TRY(hipMemcpyAsync(r0, tr0.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  }
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  op.tile_group = g;
+  op.tile_pair0 = p0;
+  op.tile_npairs = np;
+  op.tile_row0 = r0;
+  op.n_tiles = nt;
+  op.ct = ct;
+  return 0;
+}
+template int retile_forward<float>(GroupedOp<float>&, int, DevArena&, hipStream_t);
+template int retile_forward<double>(GroupedOp<double>&, int, DevArena&, hipStream_t);
+
 __global__ void k_count_boxes(const int* __restrict__ box, int np, int* __restrict__ cnt) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < np) atomicAdd(&cnt[box[t]], 1);

@@ -350,6 +350,10 @@ int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift_c, int shift_l,
 // switched on).
 template <typename R>
 int build_rotations(Problem& P, PrecisionData<R>& D, hipStream_t s);
+// Forward tiles of a grouped op rebuilt for another pair-tile width (the
+// tuner's choice for the leaf-level M2L).
+template <typename R>
+int retile_forward(GroupedOp<R>& op, int ct, DevArena& arena, hipStream_t s);
 // Sampled relative error of one product against the exact discrete operator:
 // rows spread over the mesh, seeded pseudo-random p and q, reference rows
 // summed directly in float64 (rule points, near corrections, diagonal).
