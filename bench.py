@@ -388,15 +388,23 @@ def run_topo(args):
     st = r64["stats"]
     L = st["levels"]
     ms_leaf, calls_leaf = r64["prof"].get(("m2l_leaf", "f64", "fwd"), (0.0, 0))
-    flops = m2l_flops(st["n_m2l"][L], st["n_m2l_far"][L], st["order"][L], st["far_cut"])
+    # algorithmic FLOPs of the algorithm the leaf level runs (rotation-based
+    # where the problem's float64 leaf M2L is, else dense operators)
+    rot_leaf = bool(st["m2l_rot"][L])
+    dense = m2l_flops(st["n_m2l"][L], st["n_m2l_far"][L], st["order"][L], st["far_cut"])
+    flops = (rot_m2l_flops(st["n_m2l"][L], st["n_m2l_far"][L], st["order"][L], st["far_cut"])
+             if rot_leaf else dense)
     per_ms = ms_leaf / max(1, calls_leaf)
     ach = flops / (per_ms / 1e3) if per_ms > 0 else 0.0
     stages = {f"{k_[0]}_{k_[1]}": round(v[0] / v[1], 4) for k_, v in r64["prof"].items()}
-    roofline = {"kernel": "k_grouped_gemm<double,*,false,1> (leaf-level M2L into the point "
-                          "boxes, float64)", "bound": "mfma", "achieved": round(ach / 1e12, 3),
+    kern = ("k_rot_m2l<double,256,false> (rotation-based, results added atomically)" if rot_leaf
+            else "k_grouped_gemm<double,*,false,1>")
+    roofline = {"kernel": f"{kern} (leaf-level M2L into the point boxes, float64)",
+                "bound": "mfma", "achieved": round(ach / 1e12, 3),
                 "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64, 4),
-                "traffic": None, "flops_per_launch": flops, "avg_launch_ms": round(per_ms, 5),
-                "launches": calls_leaf}
+                "traffic": None, "flops_per_launch": flops, "dense_equivalent_flops": dense,
+                "avg_launch_ms": round(per_ms, 5), "launches": calls_leaf,
+                "rotation_based_levels": [l for l in range(2, L + 1) if st["m2l_rot"][l]]}
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (sampled lattice points)...")

@@ -329,6 +329,10 @@ typedef struct {
                                         boxes or more                         */
   int32_t far_cut;                   /* input orders cut from those (0: the
                                         point-box translations use full orders) */
+  int32_t m2l_rot[22];               /* 1 where the level's translations into
+                                        point boxes are rotation-based (the
+                                        problem's own M2L of the precision is,
+                                        or bem_problem.m2l_rot = 2)            */
 } bem_field_points_stats;
 int bem_field_points_get_stats(const bem_field_points* fp, bem_field_points_stats* st);
 

@@ -102,7 +102,8 @@ class _PointStats(ctypes.Structure):
                 ("n_box", ctypes.c_int32 * 22), ("n_m2l", ctypes.c_int64 * 22),
                 ("order", ctypes.c_int32 * 22), ("n_leaf", ctypes.c_int64),
                 ("n_near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("n_m2l_far", ctypes.c_int64 * 22), ("far_cut", ctypes.c_int32)]
+                ("n_m2l_far", ctypes.c_int64 * 22), ("far_cut", ctypes.c_int32),
+                ("m2l_rot", ctypes.c_int32 * 22)]
 
 
 _LIB = None
@@ -600,7 +601,7 @@ class FieldPoints:
                     n_m2l=list(st.n_m2l)[:L + 1], order=list(st.order)[:L + 1],
                     n_leaf=st.n_leaf, n_near_pairs=st.n_near_pairs,
                     device_bytes=st.device_bytes, n_m2l_far=list(st.n_m2l_far)[:L + 1],
-                    far_cut=st.far_cut)
+                    far_cut=st.far_cut, m2l_rot=list(st.m2l_rot)[:L + 1])
 
     def eval_field_grad(self, p, q=None, direction=None, src=None, amp=None):
         """Total field (n,) and gradient (n, 3) at the points, as

@@ -714,6 +714,8 @@ int bem_field_points_get_stats(const bem_field_points* fp, bem_field_points_stat
   st->n_near_pairs = F.n_near_pairs;
   st->device_bytes = F.arena.bytes;
   st->far_cut = 0;  // point-box translations use full orders
+  for (int l = 0; l <= F.L && l <= MAX_LEVEL; ++l)
+    st->m2l_rot[l] = (F.prec == 0 ? F.f64.m2l[l].rot_on : F.f32.m2l[l].rot_on) ? 1 : 0;
   return BEM_OK;
 }
 

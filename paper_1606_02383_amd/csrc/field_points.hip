@@ -496,6 +496,7 @@ static int build_points_precision(Problem& P, const PointLists& lists, FieldPoin
                                   hipStream_t s) {
   PrecisionData<R>& D = pdata<R>(P);
   int r = build_point_ops<R>(P, D, lists, F, pops<R>(F), s);
+  if (!r) r = build_point_rotations<R>(P, D, F, pops<R>(F), s);
   if (r) return r;
   int pmax = 0;
   for (int l = 2; l <= F.L; ++l) pmax = std::max(pmax, D.order[l]);

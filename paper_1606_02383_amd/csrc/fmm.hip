@@ -967,7 +967,10 @@ struct RotJobDev {
   const R* dtab;        // per rotation class: d blocks, then d^T blocks
   const cplx<R>* coax;  // adjoint: the conjugate-transposed blocks
   const cplx<R>* src;
-  cplx<R>* cbuf;
+  cplx<R>* cbuf;        // per-pair output (atomic = 0)
+  cplx<R>* dst;         // atomic = 1: results added atomically into dst[pair_dst]
+  const int* pair_dst;
+  int atomic;
 };
 template <typename R>
 struct RotBatch {
@@ -1162,7 +1165,7 @@ __global__ void __launch_bounds__(64 * ROT_NW)
   constexpr int CCS = NT / CSTR;               // pairs per pass
   __shared__ __attribute__((aligned(16))) R X[2 * PL];
   __shared__ R s_ph[2][2 * ROT_MAXP + 1];
-  __shared__ int s_src[ROT_CT];
+  __shared__ int s_src[ROT_CT], s_dst[ROT_CT];
   __builtin_amdgcn_s_setprio(2);  // critical path: ahead of the near-field waves
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -1185,7 +1188,10 @@ __global__ void __launch_bounds__(64 * ROT_NW)
     int pf = 0;
     while ((pf + 2) * (pf + 2) <= kc) ++pf;
     const int th = J.group_theta[grp], di = J.group_dist[grp];
-    if (tid < ROT_CT) s_src[tid] = tid < np ? J.pair_src[p0 + tid] : -1;
+    if (tid < ROT_CT) {
+      s_src[tid] = tid < np ? J.pair_src[p0 + tid] : -1;
+      s_dst[tid] = (J.atomic && tid < np) ? J.pair_dst[p0 + tid] : -1;
+    }
     if (tid < 2 * p + 1) {  // e^{i m phi}, m = -p .. p
       const int m = tid - p, am = m < 0 ? -m : m;
       const R* ph = J.phase + ((int64_t)grp * (p + 1) + am) * 2;
@@ -1222,7 +1228,8 @@ __global__ void __launch_bounds__(64 * ROT_NW)
     __syncthreads();
     rot_degrees<R, KS>(X, PL, dt, ADJ ? pf : p, wave, li, lk, lane);  // d
     __syncthreads();
-    // Phi: coefficient (n, m) times e^{-i m phi}, written per pair
+    // Phi: coefficient (n, m) times e^{-i m phi}, written per pair (or added
+    // atomically into the destination's expansion)
     for (int c = tid % CSTR; c < nc; c += CSTR) {
       const int n = isqrt_small(c), m = c - n * n - n;
       const R er = s_ph[0][m + p], ei = s_ph[1][m + p];
@@ -1231,7 +1238,11 @@ __global__ void __launch_bounds__(64 * ROT_NW)
         const int cc = tid / CSTR + CCS * i;
         if (cc < np) {
           const R xr = X[c * ROT_LD + cc], xi = X[PL + c * ROT_LD + cc];
-          J.cbuf[(int64_t)(p0 + cc) * nc + c] = mk<R>(xr * er + xi * ei, xi * er - xr * ei);
+          const cplx<R> v = mk<R>(xr * er + xi * ei, xi * er - xr * ei);
+          if (J.atomic)
+            atomic_cadd(&J.dst[(int64_t)s_dst[cc] * nc + c], v);
+          else
+            J.cbuf[(int64_t)(p0 + cc) * nc + c] = v;
         }
       }
     }
@@ -1803,8 +1814,14 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
   RotBatch<R> tb{};
   b.n = rb.n = tb.n = nj;
   int nt = 0, nbox = 0, ct = 0, maxnc = 0;
-  // rotation-based M2L (every job of the launch or none)
-  const bool rot = KIND == 0 && jobs[0].op->rot_on;
+  // rotation-based M2L (every job of the launch or none): per-pair outputs
+  // (KIND 0) or added atomically (KIND 1, the float64 translations into
+  // point boxes; forward only)
+  const bool rot = (KIND == 0 || KIND == 1) && jobs[0].op->rot_on;
+  if (rot && KIND == 1 && adj) {
+    set_error("atomic rotation-based translations are forward only");
+    return -1;
+  }
   // adjoint M2L: the stored conjugate transposes through the forward
   // operand path (the transposed load path is slower)
   bool via_fwd = adj && KIND == 0;
@@ -1841,6 +1858,9 @@ static int launch_grouped_jobs(const GemmJob<R>* jobs, int nj, bool adj, hipStre
       T.coax = adj ? op.rot_coax_h : op.rot_coax;
       T.src = jobs[q].src;
       T.cbuf = jobs[q].cbuf;
+      T.dst = jobs[q].dst;
+      T.pair_dst = op.pair_dst;
+      T.atomic = KIND == 1 ? 1 : 0;
       tb.tile0[q] = nt;
       nt += op.rot_n_tiles;
       maxnc = std::max(maxnc, op.rows);

@@ -1190,126 +1190,133 @@ __global__ void k_rot_pad_c(int p, int ndist, const cplx<R>* __restrict__ coax,
   out[t] = v;
 }
 
+// Rotation tables and tiles of one M2L op at order p on a level of box side
+// h, whose offset codes index a width^3 table (offset + width / 2 per axis).
 template <typename R>
-int build_rotations(Problem& P, PrecisionData<R>& D, hipStream_t s) {
+static int rot_tables(Problem& P, GroupedOp<R>& op, int p, double h, int width, DevArena& keep,
+                      hipStream_t s) {
+  const int ncodes = width * width * width, off = width / 2;
+  if (op.rot_ready || op.n_pairs == 0 || p > ROT_MAXP || (int)op.gstart_h.size() != ncodes + 1)
+    return 0;
   DevArena scratch;
   struct Guard {
     DevArena& a;
     ~Guard() { a.release(); }
   } guard{scratch};
-  for (int l = 2; l <= P.L; ++l) {
-    GroupedOp<R>& op = D.m2l[l];
-    const int p = D.order[l];
-    if (op.rot_ready || op.n_pairs == 0 || p > ROT_MAXP ||
-        (int)op.gstart_h.size() != N_OFFSETS + 1)
-      continue;
-    // classes: polar angle by (dz, dx^2 + dy^2), distance by |d|^2 (offsets
-    // in box sides; the translation vector is the offset times h_l)
-    std::vector<std::array<int, 3>> tkeys, dkeys;
-    std::vector<int> g_theta(N_OFFSETS, 0), g_dist(N_OFFSETS, 0);
-    std::vector<double> cs_theta, tv_dist;
-    std::vector<R> phase((size_t)N_OFFSETS * (p + 1) * 2, R(0));
-    std::vector<int> tg, tp0, tnp;
-    for (int c = 0; c < N_OFFSETS; ++c) {
-      const int a = op.gstart_h[c], b = op.gstart_h[c + 1];
-      if (b <= a) continue;
-      const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
-      const int rxy2 = dx * dx + dy * dy, r2 = rxy2 + dz * dz;
-      const double r = std::sqrt((double)r2);
-      const std::array<int, 3> tk{dz, rxy2, 0}, dk{r2, 0, 0};
-      int ti = 0, di = 0;
-      while (ti < (int)tkeys.size() && tkeys[ti] != tk) ++ti;
-      if (ti == (int)tkeys.size()) {
-        tkeys.push_back(tk);
-        cs_theta.push_back(dz / r);
-        cs_theta.push_back(std::sqrt((double)rxy2) / r);
-      }
-      while (di < (int)dkeys.size() && dkeys[di] != dk) ++di;
-      if (di == (int)dkeys.size()) {
-        dkeys.push_back(dk);
-        tv_dist.push_back(0.0);
-        tv_dist.push_back(0.0);
-        tv_dist.push_back(r * P.h[l]);
-      }
-      g_theta[c] = ti;
-      g_dist[c] = di;
-      const double phi = rxy2 > 0 ? std::atan2((double)dy, (double)dx) : 0.0;
-      for (int m = 0; m <= p; ++m) {
-        phase[((size_t)c * (p + 1) + m) * 2] = (R)std::cos(m * phi);
-        phase[((size_t)c * (p + 1) + m) * 2 + 1] = (R)std::sin(m * phi);
-      }
-      for (int p0 = a; p0 < b; p0 += ROT_CT) {
-        tg.push_back(c);
-        tp0.push_back(p0);
-        tnp.push_back(std::min(ROT_CT, b - p0));
-      }
+  // classes: polar angle by (dz, dx^2 + dy^2), distance by |d|^2 (offsets
+  // in box sides; the translation vector is the offset times h)
+  std::vector<std::array<int, 3>> tkeys, dkeys;
+  std::vector<int> g_theta(ncodes, 0), g_dist(ncodes, 0);
+  std::vector<double> cs_theta, tv_dist;
+  std::vector<R> phase((size_t)ncodes * (p + 1) * 2, R(0));
+  std::vector<int> tg, tp0, tnp;
+  for (int c = 0; c < ncodes; ++c) {
+    const int a = op.gstart_h[c], b = op.gstart_h[c + 1];
+    if (b <= a) continue;
+    const int dx = c / (width * width) - off, dy = (c / width) % width - off, dz = c % width - off;
+    const int rxy2 = dx * dx + dy * dy, r2 = rxy2 + dz * dz;
+    const double r = std::sqrt((double)r2);
+    const std::array<int, 3> tk{dz, rxy2, 0}, dk{r2, 0, 0};
+    int ti = 0, di = 0;
+    while (ti < (int)tkeys.size() && tkeys[ti] != tk) ++ti;
+    if (ti == (int)tkeys.size()) {
+      tkeys.push_back(tk);
+      cs_theta.push_back(dz / r);
+      cs_theta.push_back(std::sqrt((double)rxy2) / r);
     }
-    const int nth = (int)tkeys.size(), ndist = (int)dkeys.size(), nt = (int)tg.size();
-    ARENA_ALLOC(D.ops, op.rot_tile_group, nt);
-    ARENA_ALLOC(D.ops, op.rot_tile_pair0, nt);
-    ARENA_ALLOC(D.ops, op.rot_tile_npairs, nt);
-    ARENA_ALLOC(D.ops, op.rot_theta, N_OFFSETS);
-    ARENA_ALLOC(D.ops, op.rot_dist, N_OFFSETS);
-    ARENA_ALLOC(D.ops, op.rot_phase, phase.size());
-    ARENA_ALLOC(D.ops, op.rot_dtab, (int64_t)nth * 2 * rot_dpsz(p));
-    ARENA_ALLOC(D.ops, op.rot_coax, (int64_t)ndist * rot_cpsz(p));
-    ARENA_ALLOC(D.ops, op.rot_coax_h, (int64_t)ndist * rot_cpsz(p));
-    R* dtab;
-    cplx<R>*coax, *coax_h;
-    ARENA_ALLOC(scratch, dtab, (int64_t)nth * rot_dsz(p));
-    ARENA_ALLOC(scratch, coax, (int64_t)ndist * rot_csz(p));
-    ARENA_ALLOC(scratch, coax_h, (int64_t)ndist * rot_csz(p));
-    auto up = [&](void* d, const void* h, size_t bytes) -> int {
-      if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
-      return 0;
-    };
-    int r = 0;
-    if ((r = up(op.rot_tile_group, tg.data(), sizeof(int) * nt)) ||
-        (r = up(op.rot_tile_pair0, tp0.data(), sizeof(int) * nt)) ||
-        (r = up(op.rot_tile_npairs, tnp.data(), sizeof(int) * nt)) ||
-        (r = up(op.rot_theta, g_theta.data(), sizeof(int) * N_OFFSETS)) ||
-        (r = up(op.rot_dist, g_dist.data(), sizeof(int) * N_OFFSETS)) ||
-        (r = up(op.rot_phase, phase.data(), sizeof(R) * phase.size())))
-      return r;
-    // rotation blocks by quadrature
-    std::vector<double> gx, gw;
-    gauss_legendre(p + 1, gx, gw);
-    double *dgx, *dgw, *dcs;
-    ARENA_ALLOC(scratch, dgx, p + 1);
-    ARENA_ALLOC(scratch, dgw, p + 1);
-    ARENA_ALLOC(scratch, dcs, cs_theta.size());
-    if ((r = up(dgx, gx.data(), sizeof(double) * (p + 1))) ||
-        (r = up(dgw, gw.data(), sizeof(double) * (p + 1))) ||
-        (r = up(dcs, cs_theta.data(), sizeof(double) * cs_theta.size())))
-      return r;
-    hipLaunchKernelGGL(k_rot_small_d<R>, dim3(nth, p + 1), dim3(256), 0, s, p, dcs, p + 1,
-                       2 * p + 2, dgx, dgw, dtab);
-    BEM_LAUNCH_CHECK();
-    const int64_t totd = (int64_t)nth * 2 * rot_dpsz(p);
-    hipLaunchKernelGGL(k_rot_pad_d<R>, dim3(ceil_div(totd, 256)), dim3(256), 0, s, p, nth, dtab,
-                       op.rot_dtab);
-    BEM_LAUNCH_CHECK();
-    // coaxial blocks: the dense translations along e_z, same level scaling
-    std::vector<double> rs = coef_scale(p, P.k * P.h[l], +1), cs = coef_scale(p, P.k * P.h[l], +1);
-    cplx<R>* dense = nullptr;
-    r = make_translations<R>(P, scratch, ndist, tv_dist, 1, p, p, rs, cs, &dense, scratch, s);
+    while (di < (int)dkeys.size() && dkeys[di] != dk) ++di;
+    if (di == (int)dkeys.size()) {
+      dkeys.push_back(dk);
+      tv_dist.push_back(0.0);
+      tv_dist.push_back(0.0);
+      tv_dist.push_back(r * h);
+    }
+    g_theta[c] = ti;
+    g_dist[c] = di;
+    const double phi = rxy2 > 0 ? std::atan2((double)dy, (double)dx) : 0.0;
+    for (int m = 0; m <= p; ++m) {
+      phase[((size_t)c * (p + 1) + m) * 2] = (R)std::cos(m * phi);
+      phase[((size_t)c * (p + 1) + m) * 2 + 1] = (R)std::sin(m * phi);
+    }
+    for (int p0 = a; p0 < b; p0 += ROT_CT) {
+      tg.push_back(c);
+      tp0.push_back(p0);
+      tnp.push_back(std::min(ROT_CT, b - p0));
+    }
+  }
+  const int nth = (int)tkeys.size(), ndist = (int)dkeys.size(), nt = (int)tg.size();
+  ARENA_ALLOC(keep, op.rot_tile_group, nt);
+  ARENA_ALLOC(keep, op.rot_tile_pair0, nt);
+  ARENA_ALLOC(keep, op.rot_tile_npairs, nt);
+  ARENA_ALLOC(keep, op.rot_theta, ncodes);
+  ARENA_ALLOC(keep, op.rot_dist, ncodes);
+  ARENA_ALLOC(keep, op.rot_phase, phase.size());
+  ARENA_ALLOC(keep, op.rot_dtab, (int64_t)nth * 2 * rot_dpsz(p));
+  ARENA_ALLOC(keep, op.rot_coax, (int64_t)ndist * rot_cpsz(p));
+  ARENA_ALLOC(keep, op.rot_coax_h, (int64_t)ndist * rot_cpsz(p));
+  R* dtab;
+  cplx<R>*coax, *coax_h;
+  ARENA_ALLOC(scratch, dtab, (int64_t)nth * rot_dsz(p));
+  ARENA_ALLOC(scratch, coax, (int64_t)ndist * rot_csz(p));
+  ARENA_ALLOC(scratch, coax_h, (int64_t)ndist * rot_csz(p));
+  auto up = [&](void* d, const void* hp, size_t bytes) -> int {
+    if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d, hp, bytes, hipMemcpyHostToDevice, s));
+    return 0;
+  };
+  int r = 0;
+  if ((r = up(op.rot_tile_group, tg.data(), sizeof(int) * nt)) ||
+      (r = up(op.rot_tile_pair0, tp0.data(), sizeof(int) * nt)) ||
+      (r = up(op.rot_tile_npairs, tnp.data(), sizeof(int) * nt)) ||
+      (r = up(op.rot_theta, g_theta.data(), sizeof(int) * ncodes)) ||
+      (r = up(op.rot_dist, g_dist.data(), sizeof(int) * ncodes)) ||
+      (r = up(op.rot_phase, phase.data(), sizeof(R) * phase.size())))
+    return r;
+  // rotation blocks by quadrature
+  std::vector<double> gx, gw;
+  gauss_legendre(p + 1, gx, gw);
+  double *dgx, *dgw, *dcs;
+  ARENA_ALLOC(scratch, dgx, p + 1);
+  ARENA_ALLOC(scratch, dgw, p + 1);
+  ARENA_ALLOC(scratch, dcs, cs_theta.size());
+  if ((r = up(dgx, gx.data(), sizeof(double) * (p + 1))) ||
+      (r = up(dgw, gw.data(), sizeof(double) * (p + 1))) ||
+      (r = up(dcs, cs_theta.data(), sizeof(double) * cs_theta.size())))
+    return r;
+  hipLaunchKernelGGL(k_rot_small_d<R>, dim3(nth, p + 1), dim3(256), 0, s, p, dcs, p + 1,
+                     2 * p + 2, dgx, dgw, dtab);
+  BEM_LAUNCH_CHECK();
+  const int64_t totd = (int64_t)nth * 2 * rot_dpsz(p);
+  hipLaunchKernelGGL(k_rot_pad_d<R>, dim3(ceil_div(totd, 256)), dim3(256), 0, s, p, nth, dtab,
+                     op.rot_dtab);
+  BEM_LAUNCH_CHECK();
+  // coaxial blocks: the dense translations along e_z, same level scaling
+  std::vector<double> rs = coef_scale(p, P.k * h, +1), cs = coef_scale(p, P.k * h, +1);
+  cplx<R>* dense = nullptr;
+  r = make_translations<R>(P, scratch, ndist, tv_dist, 1, p, p, rs, cs, &dense, scratch, s);
+  if (r) return r;
+  const int64_t tot = (int64_t)ndist * rot_csz(p);
+  hipLaunchKernelGGL(k_rot_coax<R>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, p, ndist, dense,
+                     coax, coax_h);
+  BEM_LAUNCH_CHECK();
+  const int64_t totc = (int64_t)ndist * rot_cpsz(p);
+  hipLaunchKernelGGL(k_rot_pad_c<R>, dim3(ceil_div(totc, 256)), dim3(256), 0, s, p, ndist, coax,
+                     op.rot_coax);
+  BEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_rot_pad_c<R>, dim3(ceil_div(totc, 256)), dim3(256), 0, s, p, ndist,
+                     coax_h, op.rot_coax_h);
+  BEM_LAUNCH_CHECK();
+  BEM_HIP_TRY(hipStreamSynchronize(s));
+  op.rot_n_tiles = nt;
+  op.rot_p = p;
+  op.rot_ready = true;
+  return 0;
+}
+
+template <typename R>
+int build_rotations(Problem& P, PrecisionData<R>& D, hipStream_t s) {
+  for (int l = 2; l <= P.L; ++l) {
+    int r = rot_tables<R>(P, D.m2l[l], D.order[l], P.h[l], 7, D.ops, s);
     if (r) return r;
-    const int64_t tot = (int64_t)ndist * rot_csz(p);
-    hipLaunchKernelGGL(k_rot_coax<R>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, p, ndist, dense,
-                       coax, coax_h);
-    BEM_LAUNCH_CHECK();
-    const int64_t totc = (int64_t)ndist * rot_cpsz(p);
-    hipLaunchKernelGGL(k_rot_pad_c<R>, dim3(ceil_div(totc, 256)), dim3(256), 0, s, p, ndist, coax,
-                       op.rot_coax);
-    BEM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rot_pad_c<R>, dim3(ceil_div(totc, 256)), dim3(256), 0, s, p, ndist,
-                       coax_h, op.rot_coax_h);
-    BEM_LAUNCH_CHECK();
-    BEM_HIP_TRY(hipStreamSynchronize(s));
-    scratch.release();
-    op.rot_n_tiles = nt;
-    op.rot_p = p;
-    op.rot_ready = true;
   }
   return 0;
 }
@@ -1473,6 +1480,26 @@ int build_point_ops(Problem& P, PrecisionData<R>& D, const PointLists& lists, Fi
 }
 template int build_point_ops<float>(Problem&, PrecisionData<float>&, const PointLists&,
                                     FieldPoints&, PointOps<float>&, hipStream_t);
+
+// Rotation-based M2L into the point boxes on the levels where the problem's
+// own M2L of the precision is rotation-based (or everywhere the order allows,
+// as the plan was asked), over the PT_W^3 offset table.
+template <typename R>
+int build_point_rotations(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>& O,
+                          hipStream_t s) {
+  if (P.m2l_rot_req == 1) return 0;
+  for (int l = 2; l <= P.L; ++l) {
+    if (P.m2l_rot_req != 2 && !D.m2l[l].rot_on) continue;
+    int r = rot_tables<R>(P, O.m2l[l], D.order[l], P.h[l], PT_W, F.arena, s);
+    if (r) return r;
+    O.m2l[l].rot_on = O.m2l[l].rot_ready;
+  }
+  return 0;
+}
+template int build_point_rotations<float>(Problem&, PrecisionData<float>&, FieldPoints&,
+                                          PointOps<float>&, hipStream_t);
+template int build_point_rotations<double>(Problem&, PrecisionData<double>&, FieldPoints&,
+                                           PointOps<double>&, hipStream_t);
 template int build_point_ops<double>(Problem&, PrecisionData<double>&, const PointLists&,
                                      FieldPoints&, PointOps<double>&, hipStream_t);
 

@@ -505,6 +505,11 @@ int eval_field_grad_fmm(FieldPoints& F, const c64* p, const c64* q, const double
 template <typename R>
 int build_point_ops(Problem& P, PrecisionData<R>& D, const PointLists& lists, FieldPoints& F,
                     PointOps<R>& O, hipStream_t s);
+// Rotation tables of the point-box M2L (see build_rotations), on the levels
+// where the problem's M2L of the precision is rotation-based.
+template <typename R>
+int build_point_rotations(Problem& P, PrecisionData<R>& D, FieldPoints& F, PointOps<R>& O,
+                          hipStream_t s);
 int derivative_table(Problem& P, int p, std::vector<double>& gc, DevArena& scratch,
                      hipStream_t s);
 // fmm.hip: multipoles of the problem's tree for (p, q), then the locals of

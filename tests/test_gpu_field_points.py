@@ -10,6 +10,7 @@ topology loop's step 8, Sec. 3, with the boundary sums split by the FMM).
 * Against the direct GPU sum (itself pinned to the oracle) on the
   20480-element sphere and a 31^3 lattice, both precisions.
 * T_Omega from the FMM fields against T_Omega from the direct fields.
+* Rotation-based translations into the point boxes against dense ones.
 * Edge cases: no points, points out of range, non-finite points, bad
   precision, a problem without far field (direct sum kept), a point set
   with one point, points on box faces of the tree's grid, the second
@@ -158,6 +159,38 @@ def test_fmm_points_against_direct_sum():
              f"{['%.2e' % v for v in e]}")
         assert max(e[0], e[2]) < tf and max(e[1], e[3]) < tg
         fp.close()
+
+
+def test_fmm_points_rotation_matches_dense():
+    """Translations into the point boxes rotation-based (plan asked for them
+    on every level: float64 results added atomically, float32 per pair) or
+    dense: the same fields and gradients to rounding."""
+    import torch
+    bem = _lib()
+    V, T = icosphere(4)
+    k = 6.0
+    plans = {rot: bem.Plan(bem.Problem(V, T, k, m2l_rot=rot)) for rot in (1, 2)}
+    rng = np.random.default_rng(75)
+    p, q = complex_normal(rng, len(T)), complex_normal(rng, len(T))
+    P, Q = torch.from_numpy(p), torch.from_numpy(q)
+    pts = _lattice(21, 1.5, 1.03)
+    d = np.array([0.0, 0.6, 0.8])
+    for prec, bar in ((bem.BEM_C128, 1e-12), (bem.BEM_C64, 1e-5)):
+        out = {}
+        for rot, plan in plans.items():
+            fp = bem.FieldPoints(plan, pts, prec=prec)
+            st = fp.stats()
+            want = [1 if (rot == 2 and o <= 23) else 0 for o in st["order"][2:]]
+            assert st["m2l_rot"][2:] == want, (st["m2l_rot"], st["order"])
+            f, gr = fp.eval_field_grad(P, Q, direction=d)
+            out[rot] = (f.cpu().numpy(), gr.cpu().numpy(), st["m2l_rot"][2:])
+            fp.close()
+        ef, eg = _rel(out[2][0], out[1][0]), _rel(out[2][1], out[1][1])
+        _log(f"case: sphere5120 k = 6, {len(pts)} points, prec {prec}: rotation-based levels "
+             f"{out[2][2]}: field {ef:.2e}, gradient {eg:.2e} against dense")
+        assert ef < bar and eg < bar
+    for plan in plans.values():
+        plan.close()
 
 
 def test_topological_derivative_from_fmm_fields():
