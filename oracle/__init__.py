@@ -19,7 +19,10 @@ It computes, plainly and slowly, in complex128:
                integers (the bit-exact reference);
 * ``solve``  - restarted GMRES (modified Gram-Schmidt), dense LU solves, the
                field representation at exterior points, the objective
-               J = sum |p(x_obs)|^2 and its discrete-adjoint gradient.
+               J = sum |p(x_obs)|^2 and its discrete-adjoint gradient;
+* ``fem``    - linear-tetrahedron stiffness and mass of the elastic body, the
+               boundary coupling and the Schur form of the BEM-FEM system
+               (Eqs. fem_2, renritupu, kousokuu, GMRES).
 
 Paper anchors (Isakari, Kondo, Takahashi, Matsumoto, "A level-set-based
 topology optimisation for acoustic-elastic coupled problems with a fast

@@ -98,6 +98,38 @@ def icosphere(level: int, radius: float = 1.0):
     return V, T.astype(np.int32)
 
 
+def ball_mesh(level: int, n_shell: int = 3):
+    """Tetrahedral mesh of the unit ball whose boundary faces are the
+    triangles of ``icosphere(level)``: concentric scaled copies of the surface
+    vertices at radii s / n_shell (s = n_shell .. 1), the prism between two
+    shells over each surface triangle split into three tetrahedra (with the
+    triangle's vertices sorted a < b < c, inner shell 0 and outer shell 1:
+    (a0 b0 c0 c1), (a0 b0 b1 c1), (a0 a1 b1 c1), so every quadrilateral face
+    is cut along the same diagonal from both sides), the innermost layer
+    joined to the centre.  Returns (nodes, tets, V, T): the first len(V)
+    nodes are the surface vertices V, T the surface triangles (the
+    icosphere's, outward normals)."""
+    V, T = icosphere(level)
+    nv = len(V)
+    shells = [V * (s / n_shell) for s in range(n_shell, 0, -1)]   # shell index 0 = surface
+    nodes = np.vstack(shells + [np.zeros((1, 3))])
+    centre = n_shell * nv
+
+    def idx(shell, v):  # shell 0 = surface (radius 1), n_shell - 1 = innermost
+        return shell * nv + v
+
+    tets = []
+    for tri in T:
+        a, b, c = sorted(int(v) for v in tri)
+        for sh in range(n_shell - 1):       # outer shell sh, inner shell sh + 1
+            a1, b1, c1 = idx(sh, a), idx(sh, b), idx(sh, c)
+            a0, b0, c0 = idx(sh + 1, a), idx(sh + 1, b), idx(sh + 1, c)
+            tets += [(a0, b0, c0, c1), (a0, b0, b1, c1), (a0, a1, b1, c1)]
+        inner = n_shell - 1
+        tets.append((centre, idx(inner, a), idx(inner, b), idx(inner, c)))
+    return nodes, np.array(tets, dtype=np.int32), V, T
+
+
 def cube_surface(n: int = 64, half: float = 1.0):
     """Surface of the cube ``[-half, half]^3``; each face is an ``n x n`` grid
     of squares, each split along its (i,j)->(i+1,j+1) diagonal.
