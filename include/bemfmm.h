@@ -478,6 +478,43 @@ int bem_profile_serial_start(bem_plan* plan, int prob);
 int bem_profile_leaf_m2l_start(bem_plan* plan, int prob);
 int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls);
 
+/* BEM-FEM coupled operator of an elastic scatterer (Sec. 2.3: the weak form
+ * of the body, Eq. fem_2, with linear tetrahedra; the coupled system,
+ * Eq. renritupu; its Schur form, Eqs. kousokuu and GMRES).  The body is a
+ * tetrahedral mesh (nodes: host, n_nodes x 3; tets: host, n_tets x 4 node
+ * indices) whose boundary faces are the problem's triangles: tri (host,
+ * n_tri x 3, the problem's element order) gives their node indices, normals
+ * (v1 - v0) x (v2 - v0) pointing into the fluid.  Isotropic material lambda,
+ * mu (mu > 0, 3 lambda + 2 mu > 0), density rho_s; fluid density rho_f;
+ * angular frequency omega (> 0; the problem's k = omega / c_f).  At creation
+ * the device assembles K - omega^2 M densely (3 n_nodes <= BEM_FEM_MAX_DOF
+ * unknowns), solves it against the boundary load N by Gauss-Jordan
+ * elimination with partial pivoting (in place of the paper's multi-frontal
+ * factorisation) and keeps C = -rho_f omega^2 Tc (K - omega^2 M)^-1 N
+ * (n_tri x n_tri, float64, row-major, the problem's element order): q = C p
+ * is dp/dn on the fluid side for the boundary pressure p (momentum balance
+ * dp/dn = rho_f omega^2 u.n at the collocation points).  BEM_E_INVALID for a
+ * bad plan, problem, mesh, material or size; BEM_E_NAN when K - omega^2 M is
+ * singular (omega^2 an eigenvalue of the free body). */
+#define BEM_FEM_MAX_DOF 12288
+typedef struct bem_coupling bem_coupling;
+int bem_coupling_create(bem_plan* plan, int prob, const double* nodes, int64_t n_nodes,
+                        const int32_t* tets, int64_t n_tets, const int32_t* tri, double lambda,
+                        double mu, double rho_s, double rho_f, double omega, void* stream,
+                        bem_coupling** out);
+int bem_coupling_destroy(bem_coupling* c);
+/* C copied into C_out (device, n_tri x n_tri float64). */
+int bem_coupling_get_matrix(const bem_coupling* c, void* C_out, void* stream);
+/* y = (I/2 - K - alpha H) p + (S + alpha K' + alpha/2 I) C p: the coupled
+ * operator (alpha = 0: the paper's Eq. GMRES), float64 (BEM_C128) or the
+ * float32 far field (BEM_C64) as bem_fmm_matvec; p, y device complex128. */
+int bem_coupled_matvec(bem_coupling* c, int prec, const void* p, void* y, void* stream);
+/* GMRES on the coupled operator (adjoint != 0: on its conjugate transpose,
+ * the adjoint problem of Sec. 2.2 solved the same way), options and status
+ * as bem_gmres_solve. */
+int bem_coupled_solve(bem_coupling* c, int adjoint, const void* b, void* x,
+                      const bem_gmres_opts* opts, bem_gmres_info* info, void* stream);
+
 const char* bem_last_error(void);
 
 #ifdef __cplusplus

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["Plan", "Problem", "GmresOptions", "ObjectiveJ", "FieldPoints",
+__all__ = ["Plan", "Problem", "GmresOptions", "ObjectiveJ", "FieldPoints", "Coupling",
            "topological_derivative", "BemError", "load_library", "LIB_PATH", "BEM_C128",
            "BEM_C64"]
 
@@ -40,7 +40,9 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_objective_backward", "bem_tree_export",
            "bem_leaves_export", "bem_lists_export", "bem_near_export", "bem_plan_set_tuning",
            "bem_profile_start", "bem_profile_serial_start",
-           "bem_profile_leaf_m2l_start", "bem_profile_stop", "bem_last_error"]
+           "bem_profile_leaf_m2l_start", "bem_profile_stop", "bem_coupling_create",
+           "bem_coupling_destroy", "bem_coupling_get_matrix", "bem_coupled_matvec",
+           "bem_coupled_solve", "bem_last_error"]
 
 STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
           "m2l_leaf_reduce", "pt_l2p", "pt_p2p"]
@@ -158,6 +160,15 @@ def load_library(path: str = LIB_PATH):
     lib.bem_profile_serial_start.argtypes = [vp, i32]
     lib.bem_profile_leaf_m2l_start.argtypes = [vp, i32]
     lib.bem_profile_stop.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int32)]
+    ip = ctypes.POINTER(ctypes.c_int32)
+    dd = ctypes.c_double
+    lib.bem_coupling_create.argtypes = [vp, i32, dp, i64, ip, i64, ip, dd, dd, dd, dd, dd, vp,
+                                        ctypes.POINTER(vp)]
+    lib.bem_coupling_destroy.argtypes = [vp]
+    lib.bem_coupling_get_matrix.argtypes = [vp, vp, vp]
+    lib.bem_coupled_matvec.argtypes = [vp, i32, vp, vp, vp]
+    lib.bem_coupled_solve.argtypes = [vp, i32, vp, vp, ctypes.POINTER(_Opts),
+                                      ctypes.POINTER(_Info), vp]
     lib.bem_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "bem_last_error":
@@ -564,6 +575,75 @@ class Plan:
         col = torch.empty(max(nn.value, 1), dtype=torch.int32, device=self.device)
         _check(_LIB.bem_near_export(self._h, prob, _ptr(ptr), _ptr(col), None, _stream()))
         return ptr, col[:nn.value]
+
+
+class Coupling:
+    """The BEM-FEM coupled operator of an elastic body (Sec. 2.3, Eqs.
+    renritupu, kousokuu, GMRES) on one problem of a plan: a tetrahedral mesh
+    (nodes n x 3, tets m x 4) whose boundary faces are the problem's
+    triangles (tri, its element order, as node indices), isotropic material
+    (lam, mu, rho_s), fluid density rho_f and angular frequency omega.  The
+    device builds C = -rho_f omega^2 Tc (K - omega^2 M)^-1 N once; products
+    and solves apply Mp + Mq C."""
+
+    def __init__(self, plan, nodes, tets, tri, lam, mu, rho_s, rho_f, omega, prob=0):
+        self._plan = plan  # keeps the plan alive while the coupling exists
+        self.prob = prob
+        self.n = plan.n[prob]
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64).reshape(-1, 3)
+        tets = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
+        tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+        if tri.shape[0] != self.n:
+            raise ValueError("tri must hold the problem's triangles")
+        ip = ctypes.POINTER(ctypes.c_int32)
+        h = ctypes.c_void_p()
+        _check(_LIB.bem_coupling_create(plan._h, prob,
+                                        nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        nodes.shape[0], tets.ctypes.data_as(ip), tets.shape[0],
+                                        tri.ctypes.data_as(ip), float(lam), float(mu),
+                                        float(rho_s), float(rho_f), float(omega), _stream(),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _LIB.bem_coupling_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matrix(self):
+        """C (n x n float64, device)."""
+        import torch
+        C = torch.empty((self.n, self.n), dtype=torch.float64, device=self._plan.device)
+        _check(_LIB.bem_coupling_get_matrix(self._h, _ptr(C), _stream()))
+        return C
+
+    def matvec(self, p, prec=BEM_C128):
+        """y = Mp p + Mq C p."""
+        p = self._plan._in(p, self.prob)
+        y = self._plan._vec(self.prob)
+        _check(_LIB.bem_coupled_matvec(self._h, int(prec), _ptr(p), _ptr(y), _stream()))
+        return y
+
+    def solve(self, b, adjoint=False, opts: GmresOptions | None = None):
+        """GMRES on Mp + Mq C (or its conjugate transpose)."""
+        opts = opts or GmresOptions()
+        b = self._plan._in(b, self.prob)
+        x = self._plan._vec(self.prob)
+        info = _Info()
+        o = opts.c()
+        code = _LIB.bem_coupled_solve(self._h, int(adjoint), _ptr(b), _ptr(x), ctypes.byref(o),
+                                      ctypes.byref(info), _stream())
+        d = info.as_dict()
+        if code not in (0, -4):
+            _check(code)
+        d["status"] = STATUS.get(code, code)
+        return x, d
 
 
 class FieldPoints:

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libbemfmm.so")
 SOURCES = ["tree.hip", "nearfield.hip", "operators.hip", "fmm.hip", "solver.hip", "scratch.hip",
-           "field_points.hip",
+           "field_points.hip", "fem.hip",
            "capi.hip"]
 
 

@@ -678,6 +678,99 @@ struct bem_field_points {
   FieldPoints* F;
 };
 
+struct bem_coupling {
+  Problem* P = nullptr;
+  DevArena arena;
+  double* C = nullptr;  // n x n, row-major
+  c64* q = nullptr;     // work vector of the coupled product
+};
+
+int bem_coupling_create(bem_plan* plan, int prob, const double* nodes, int64_t n_nodes,
+                        const int32_t* tets, int64_t n_tets, const int32_t* tri, double lambda,
+                        double mu, double rho_s, double rho_f, double omega, void* stream,
+                        bem_coupling** out) {
+  Problem* P = get_prob(plan, prob);
+  if (!P || !out) return fail(BEM_E_INVALID, "bad plan, problem index or output pointer");
+  *out = nullptr;
+  if (!nodes || !tets || !tri || n_nodes < 4 || n_tets < 1)
+    return fail(BEM_E_INVALID, "empty or missing solid mesh");
+  if (3 * n_nodes > BEM_FEM_MAX_DOF)
+    return fail(BEM_E_INVALID, "solid mesh too large for the dense factorisation (3 n_nodes > " +
+                                   std::to_string(BEM_FEM_MAX_DOF) + ")");
+  if (!(mu > 0) || !(3 * lambda + 2 * mu > 0) || !(rho_s > 0) || !(rho_f > 0) || !(omega > 0) ||
+      !std::isfinite(lambda) || !std::isfinite(mu) || !std::isfinite(rho_s) ||
+      !std::isfinite(rho_f) || !std::isfinite(omega))
+    return fail(BEM_E_INVALID, "bad material or frequency");
+  for (int64_t i = 0; i < 3 * n_nodes; ++i)
+    if (!std::isfinite(nodes[i])) return fail(BEM_E_INVALID, "non-finite node coordinate");
+  for (int64_t i = 0; i < 4 * n_tets; ++i)
+    if (tets[i] < 0 || tets[i] >= n_nodes) return fail(BEM_E_INVALID, "tetrahedron node out of range");
+  for (int64_t i = 0; i < 3 * P->n; ++i)
+    if (tri[i] < 0 || tri[i] >= n_nodes) return fail(BEM_E_INVALID, "triangle node out of range");
+  hipStream_t s = (hipStream_t)stream;
+  bem_coupling* c = new bem_coupling();
+  c->P = P;
+  int r = coupling_build(*P, nodes, n_nodes, tets, n_tets, tri, lambda, mu, rho_s, rho_f, omega,
+                         c->arena, &c->C, s);
+  if (!r) r = c->arena.alloc((void**)&c->q, sizeof(c64) * P->n);
+  if (!r) {
+    std::vector<double> h((size_t)P->n * P->n);
+    if (hipMemcpy(h.data(), c->C, sizeof(double) * h.size(), hipMemcpyDeviceToHost) != hipSuccess)
+      r = fail(BEM_E_HIP, "copy of the coupling matrix");
+    for (size_t i = 0; !r && i < h.size(); ++i)
+      if (!std::isfinite(h[i]))
+        r = fail(BEM_E_NAN, "K - omega^2 M is singular (omega^2 an eigenvalue of the free body)");
+  }
+  if (r) {
+    c->arena.release();
+    delete c;
+    return r;
+  }
+  *out = c;
+  return BEM_OK;
+}
+
+int bem_coupling_destroy(bem_coupling* c) {
+  if (!c) return BEM_OK;
+  c->arena.release();
+  delete c;
+  return BEM_OK;
+}
+
+int bem_coupling_get_matrix(const bem_coupling* c, void* C_out, void* stream) {
+  if (!c || !C_out) return fail(BEM_E_INVALID, "bad coupling or output pointer");
+  BEM_HIP_TRY(hipMemcpyAsync(C_out, c->C, sizeof(double) * c->P->n * c->P->n,
+                             hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return BEM_OK;
+}
+
+int bem_coupled_matvec(bem_coupling* c, int prec, const void* p, void* y, void* stream) {
+  if (!c || !p || !y) return fail(BEM_E_INVALID, "bad coupling, p or y");
+  if (y == p) return fail(BEM_E_INVALID, "y aliases p");
+  if (prec != BEM_C128 && prec != BEM_C64) return fail(BEM_E_INVALID, "bad precision");
+  Problem& P = *c->P;
+  hipStream_t s = (hipStream_t)stream;
+  int r = coupling_q(c->C, P.n, (const c64*)p, c->q, s);
+  if (r) return r;
+  return (prec == BEM_C128) ? fmm_apply<double>(P, P.f64, (const c64*)p, c->q, (c64*)y, s)
+                            : fmm_apply<float>(P, P.f32, (const c64*)p, c->q, (c64*)y, s);
+}
+
+int bem_coupled_solve(bem_coupling* c, int adjoint, const void* b, void* x,
+                      const bem_gmres_opts* opts, bem_gmres_info* info, void* stream) {
+  if (!c || !b || !x || !opts) return fail(BEM_E_INVALID, "NULL coupling, b, x or opts");
+  if (b == x) return fail(BEM_E_INVALID, "x aliases b");
+  if (!(opts->tol > 0.0)) return fail(BEM_E_INVALID, "tol must be > 0");
+  if (opts->mode != 0 && opts->mode != 1) return fail(BEM_E_INVALID, "bad mode");
+  const int m = opts->restart > 0 ? opts->restart : 50;
+  if (m > 500) return fail(BEM_E_INVALID, "restart > 500");
+  const int mi = opts->max_iter > 0 ? opts->max_iter : 2000;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return gmres_solve(*c->P, nullptr, adjoint, (const c64*)b, (c64*)x, opts->tol, m, mi,
+                     opts->mode, opts->inner_tol, opts->use_x0, info, (hipStream_t)stream,
+                     c->C);
+}
+
 int bem_field_points_create(bem_plan* plan, int prob, int prec, const double* pts,
                             int64_t n_pts, void* stream, bem_field_points** out) {
   Problem* P = get_prob(plan, prob);
