@@ -505,6 +505,12 @@ int bem_coupling_create(bem_plan* plan, int prob, const double* nodes, int64_t n
 int bem_coupling_destroy(bem_coupling* c);
 /* C copied into C_out (device, n_tri x n_tri float64). */
 int bem_coupling_get_matrix(const bem_coupling* c, void* C_out, void* stream);
+/* out = C v (transpose != 0: C^T v), v and out device complex128 of n_tri:
+ * the body's response alone (dp/dn for the boundary pressure v, Eq.
+ * kousokuu), e.g. to recover the normal derivative after a coupled solve.
+ * BEM_E_INVALID for a null pointer or out == v. */
+int bem_coupling_apply(const bem_coupling* c, int transpose, const void* v, void* out,
+                       void* stream);
 /* y = (I/2 - K - alpha H) p + (S + alpha K' + alpha/2 I) C p: the coupled
  * operator (alpha = 0: the paper's Eq. GMRES), float64 (BEM_C128) or the
  * float32 far field (BEM_C64) as bem_fmm_matvec; p, y device complex128. */

@@ -41,7 +41,8 @@ EXPORTS = ["bem_plan_create", "bem_plan_destroy", "bem_plan_get_stats", "bem_fmm
            "bem_leaves_export", "bem_lists_export", "bem_near_export", "bem_plan_set_tuning",
            "bem_profile_start", "bem_profile_serial_start",
            "bem_profile_leaf_m2l_start", "bem_profile_stop", "bem_coupling_create",
-           "bem_coupling_destroy", "bem_coupling_get_matrix", "bem_coupled_matvec",
+           "bem_coupling_destroy", "bem_coupling_get_matrix", "bem_coupling_apply",
+           "bem_coupled_matvec",
            "bem_coupled_solve", "bem_last_error"]
 
 STAGES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "finish", "m2l_reduce", "m2l_leaf",
@@ -166,6 +167,7 @@ def load_library(path: str = LIB_PATH):
                                         ctypes.POINTER(vp)]
     lib.bem_coupling_destroy.argtypes = [vp]
     lib.bem_coupling_get_matrix.argtypes = [vp, vp, vp]
+    lib.bem_coupling_apply.argtypes = [vp, i32, vp, vp, vp]
     lib.bem_coupled_matvec.argtypes = [vp, i32, vp, vp, vp]
     lib.bem_coupled_solve.argtypes = [vp, i32, vp, vp, ctypes.POINTER(_Opts),
                                       ctypes.POINTER(_Info), vp]
@@ -622,6 +624,14 @@ class Coupling:
         C = torch.empty((self.n, self.n), dtype=torch.float64, device=self._plan.device)
         _check(_LIB.bem_coupling_get_matrix(self._h, _ptr(C), _stream()))
         return C
+
+    def apply(self, v, transpose=False):
+        """C v (or C^T v): the body's response dp/dn to the boundary pressure v."""
+        v = self._plan._in(v, self.prob)
+        out = self._plan._vec(self.prob)
+        _check(_LIB.bem_coupling_apply(self._h, int(bool(transpose)), _ptr(v), _ptr(out),
+                                       _stream()))
+        return out
 
     def matvec(self, p, prec=BEM_C128):
         """y = Mp p + Mq C p."""

@@ -681,8 +681,9 @@ struct bem_field_points {
 struct bem_coupling {
   Problem* P = nullptr;
   DevArena arena;
-  double* C = nullptr;  // n x n, row-major
-  c64* q = nullptr;     // work vector of the coupled product
+  double* C = nullptr;   // n x n, row-major
+  double* Ct = nullptr;  // its transpose (the adjoint's rows)
+  c64* q = nullptr;      // work vector of the coupled product
 };
 
 int bem_coupling_create(bem_plan* plan, int prob, const double* nodes, int64_t n_nodes,
@@ -711,7 +712,7 @@ int bem_coupling_create(bem_plan* plan, int prob, const double* nodes, int64_t n
   bem_coupling* c = new bem_coupling();
   c->P = P;
   int r = coupling_build(*P, nodes, n_nodes, tets, n_tets, tri, lambda, mu, rho_s, rho_f, omega,
-                         c->arena, &c->C, s);
+                         c->arena, &c->C, &c->Ct, s);
   if (!r) r = c->arena.alloc((void**)&c->q, sizeof(c64) * P->n);
   if (!r) {
     std::vector<double> h((size_t)P->n * P->n);
@@ -744,13 +745,21 @@ int bem_coupling_get_matrix(const bem_coupling* c, void* C_out, void* stream) {
   return BEM_OK;
 }
 
+int bem_coupling_apply(const bem_coupling* c, int transpose, const void* v, void* out,
+                       void* stream) {
+  if (!c || !v || !out) return fail(BEM_E_INVALID, "bad coupling, v or out");
+  if (v == out) return fail(BEM_E_INVALID, "out aliases v");
+  return coupling_apply(transpose ? c->Ct : c->C, c->P->n, (const c64*)v, (c64*)out, false,
+                        (hipStream_t)stream);
+}
+
 int bem_coupled_matvec(bem_coupling* c, int prec, const void* p, void* y, void* stream) {
   if (!c || !p || !y) return fail(BEM_E_INVALID, "bad coupling, p or y");
   if (y == p) return fail(BEM_E_INVALID, "y aliases p");
   if (prec != BEM_C128 && prec != BEM_C64) return fail(BEM_E_INVALID, "bad precision");
   Problem& P = *c->P;
   hipStream_t s = (hipStream_t)stream;
-  int r = coupling_q(c->C, P.n, (const c64*)p, c->q, s);
+  int r = coupling_apply(c->C, P.n, (const c64*)p, c->q, false, s);
   if (r) return r;
   return (prec == BEM_C128) ? fmm_apply<double>(P, P.f64, (const c64*)p, c->q, (c64*)y, s)
                             : fmm_apply<float>(P, P.f32, (const c64*)p, c->q, (c64*)y, s);
@@ -768,7 +777,7 @@ int bem_coupled_solve(bem_coupling* c, int adjoint, const void* b, void* x,
   if (info) std::memset(info, 0, sizeof(*info));
   return gmres_solve(*c->P, nullptr, adjoint, (const c64*)b, (c64*)x, opts->tol, m, mi,
                      opts->mode, opts->inner_tol, opts->use_x0, info, (hipStream_t)stream,
-                     c->C);
+                     c->C, c->Ct);
 }
 
 int bem_field_points_create(bem_plan* plan, int prob, int prec, const double* pts,

@@ -12,12 +12,13 @@
 //
 // The paper factorises K - omega^2 M once with a multi-frontal sparse solver;
 // here the plan-time step assembles it densely on the device and solves
-// (K - omega^2 M) X = N by Gauss-Jordan elimination with partial pivoting
-// on the augmented matrix [A | N] (one launch per step for the pivot, the
-// row swap and scaling, and the elimination), then forms C once (n_tri^2
-// doubles); each product then costs one dense real-by-complex matrix-vector
-// product besides the FMM.  Dense storage limits the body to BEM_FEM_MAX_DOF
+// (K - omega^2 M) X = N by a blocked LU with partial pivoting of the
+// augmented matrix [A | N] (trailing updates on the matrix cores) and
+// blocked back substitution, then forms C once (n_tri^2
+// doubles, and its transpose for the adjoint); each product then costs one
+// dense real-by-complex matrix-vector product besides the FMM.  Dense storage limits the body to BEM_FEM_MAX_DOF
 // unknowns.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -112,17 +113,31 @@ __global__ void k_fem_load(const double* __restrict__ x, const int* __restrict__
   }
 }
 
-// Gauss-Jordan step k on the n x (n + m) augmented matrix (row stride ld):
-// pivot: the largest |A[i][k]|, i >= k (one workgroup), its row and value
-__global__ void __launch_bounds__(1024) k_gj_pivot(const double* __restrict__ A, int64_t n,
-                                                   int64_t ld, int64_t k, int* __restrict__ piv,
-                                                   double* __restrict__ pval) {
+// ---------------------------------------------------------------------------
+// Blocked LU with partial pivoting of the augmented matrix W = [A | N]
+// (n x ncol, row stride ld; panels of LU_B columns), then blocked back
+// substitution with U: the right block of W ends as X = A^-1 N.  Per panel:
+// column by column a pivot search (k_lu_pivot) and the row swap, the
+// multipliers and the rank-1 update inside the panel (k_lu_update); then the
+// panel's swaps (k_lu_laswp) and the unit-lower solve L11^-1 (k_lu_trsm_lower)
+// on the trailing columns, and the trailing update W22 -= L21 U12 on the
+// matrix cores (k_lu_gemm).  The multipliers of earlier panels are not swapped:
+// the right block is eliminated in place, so L is never read again.
+// ---------------------------------------------------------------------------
+constexpr int LU_B = 64;
+
+// pivot of column kk (rows kk..n-1), then the panel segments of the pivot
+// row and of row kk into pbuf[0..kb) and pbuf[64..64+kb)
+__global__ void __launch_bounds__(1024) k_lu_pivot(const double* __restrict__ W, int64_t n,
+                                                   int64_t ld, int64_t k0, int kb, int64_t kk,
+                                                   int* __restrict__ piv,
+                                                   double* __restrict__ pbuf) {
   __shared__ double sv[1024];
   __shared__ int si[1024];
   double best = -1.0;
-  int bi = (int)k;
-  for (int64_t i = k + threadIdx.x; i < n; i += blockDim.x) {
-    const double a = fabs(A[i * ld + k]);
+  int bi = (int)kk;
+  for (int64_t i = kk + threadIdx.x; i < n; i += blockDim.x) {
+    const double a = fabs(W[i * ld + kk]);
     if (a > best) {
       best = a;
       bi = (int)i;
@@ -142,36 +157,203 @@ __global__ void __launch_bounds__(1024) k_gj_pivot(const double* __restrict__ A,
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    *piv = si[0];
-    *pval = A[(int64_t)si[0] * ld + k];
+  const int64_t r = si[0];
+  if (threadIdx.x == 0) piv[kk] = (int)r;
+  if ((int)threadIdx.x < kb)
+    pbuf[threadIdx.x] = W[r * ld + k0 + threadIdx.x];
+  else if (threadIdx.x >= 64 && (int)threadIdx.x < 64 + kb)
+    pbuf[threadIdx.x] = W[kk * ld + k0 + threadIdx.x - 64];
+}
+
+// step kk inside the panel, one wave per row i >= kk, lane c = panel column:
+// row kk takes the pivot row; row piv takes row kk's old values; every row
+// below keeps its multiplier l = W[i][kk] / pivot in column kk and updates
+// the panel columns right of kk (each row reads only itself and pbuf)
+__global__ void __launch_bounds__(256) k_lu_update(double* __restrict__ W, int64_t n, int64_t ld,
+                                                   int64_t k0, int kb, int64_t kk,
+                                                   const int* __restrict__ piv,
+                                                   const double* __restrict__ pbuf) {
+  const int64_t i = kk + blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int c = threadIdx.x & 63;
+  if (i >= n || c >= kb) return;
+  const int64_t r = piv[kk];
+  const int ck = (int)(kk - k0);
+  double* row = W + i * ld + k0;
+  if (i == kk) {
+    row[c] = pbuf[c];
+    return;
+  }
+  const double src_c = (i == r) ? pbuf[64 + c] : row[c];
+  const double src_k = (i == r) ? pbuf[64 + ck] : row[ck];
+  const double l = src_k / pbuf[ck];
+  if (c == ck)
+    row[c] = l;
+  else if (c > ck)
+    row[c] = src_c - l * pbuf[c];
+  else if (i == r)
+    row[c] = src_c;
+}
+
+// trailing columns j in [c0, ncol), one thread each: the panel's row swaps
+__global__ void __launch_bounds__(256) k_lu_laswp(double* __restrict__ W, int64_t ld, int64_t k0,
+                                                  int kb, int64_t c0, int64_t ncol,
+                                                  const int* __restrict__ piv) {
+  const int64_t j = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= ncol) return;
+  for (int t = 0; t < kb; ++t) {
+    const int64_t kk = k0 + t, r = piv[kk];
+    if (r != kk) {
+      const double a = W[kk * ld + j];
+      W[kk * ld + j] = W[r * ld + j];
+      W[r * ld + j] = a;
+    }
   }
 }
 
-// swap rows k and piv over the columns j > k, scale row k by 1 / pivot
-__global__ void k_gj_swap(double* __restrict__ A, int64_t ld, int64_t k, int64_t ncol,
-                          const int* __restrict__ piv, const double* __restrict__ pval) {
-  const int64_t j = k + 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= ncol) return;
-  const int64_t r = *piv;
-  const double a = A[k * ld + j], b = A[r * ld + j];
-  if (r != k) A[r * ld + j] = a;
-  A[k * ld + j] = b / *pval;
+// trailing columns j in [c0, ncol), one lane each (one wave per block): x =
+// L11^-1 x over the panel's rows, L11 unit lower and the 64 columns' values
+// staged in LDS (lane-major, conflict-free)
+__global__ void __launch_bounds__(64) k_lu_trsm_lower(double* __restrict__ W, int64_t ld,
+                                                      int64_t k0, int kb, int64_t c0,
+                                                      int64_t ncol) {
+  __shared__ double L[LU_B][LU_B + 1];
+  __shared__ double X[LU_B][64];
+  for (int e = threadIdx.x; e < LU_B * LU_B; e += 64) {
+    const int r = e / LU_B, t = e % LU_B;
+    L[r][t] = (r < kb && t < r) ? W[(k0 + r) * ld + k0 + t] : 0.0;
+  }
+  const int lane = threadIdx.x;
+  const int64_t j = c0 + blockIdx.x * (int64_t)64 + lane;
+  const bool on = j < ncol;
+  for (int t = 0; t < kb; ++t) X[t][lane] = on ? W[(k0 + t) * ld + j] : 0.0;
+  __syncthreads();
+  for (int r = 1; r < kb; ++r) {
+    double s = X[r][lane];
+    for (int t = 0; t < r; ++t) s -= L[r][t] * X[t][lane];
+    X[r][lane] = s;
+  }
+  if (on)
+    for (int t = 0; t < kb; ++t) W[(k0 + t) * ld + j] = X[t][lane];
 }
 
-// A[i][j] -= A[i][k] A[k][j] for i != k, j > k, with the multipliers of the
-// swapped rows (column k is not swapped: row piv takes row k's entry; the
-// column is never read after this step)
-__global__ void k_gj_eliminate(double* __restrict__ A, int64_t n, int64_t ld, int64_t k,
-                               int64_t ncol, const int* __restrict__ piv,
-                               const double* __restrict__ pval) {
-  const int64_t j = k + 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t i = blockIdx.y;
-  if (j >= ncol || i == k) return;
-  const int64_t r = *piv;
-  // multiplier of row i after the swap (column k itself is not updated)
-  const double f = (i == r) ? A[k * ld + k] : A[i * ld + k];
-  A[i * ld + j] -= f * A[k * ld + j];
+// right block columns j in [c0, ncol), one thread each: x = U11^-1 x over
+// the panel's rows (U11 upper with its diagonal, staged in LDS)
+__global__ void __launch_bounds__(256) k_lu_trsm_upper(double* __restrict__ W, int64_t ld,
+                                                       int64_t k0, int kb, int64_t c0,
+                                                       int64_t ncol) {
+  __shared__ double U[LU_B][LU_B + 1];
+  for (int e = threadIdx.x; e < LU_B * LU_B; e += blockDim.x) {
+    const int r = e / LU_B, t = e % LU_B;
+    U[r][t] = (r < kb && t < kb && t >= r) ? W[(k0 + r) * ld + k0 + t] : (r == t ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int64_t j = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= ncol) return;
+  double x[LU_B];
+#pragma unroll
+  for (int t = 0; t < LU_B; ++t) x[t] = (t < kb) ? W[(k0 + t) * ld + j] : 0.0;
+#pragma unroll
+  for (int r = LU_B - 1; r >= 0; --r) {
+    double s = x[r];
+#pragma unroll
+    for (int t = r + 1; t < LU_B; ++t) s -= U[r][t] * x[t];
+    x[r] = s / U[r][r];
+  }
+#pragma unroll
+  for (int t = 0; t < LU_B; ++t)
+    if (t < kb) W[(k0 + t) * ld + j] = x[t];
+}
+
+// W[i][j] -= sum_{t < kb} W[i][k0 + t] W[k0 + t][j] for i in [r0, r1),
+// j in [c0, c1): 64 x 64 output tiles, four waves of 2 x 2 float64 MFMA
+// 16x16x4 blocks; both operands staged whole (kb <= 64) in LDS, zero-padded.
+// The operand columns / rows lie outside the output range in both uses (the
+// trailing update and the back substitution).
+typedef double lu_v4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_lu_gemm(double* __restrict__ W, int64_t ld, int64_t r0,
+                                                 int64_t r1, int64_t c0, int64_t c1, int64_t k0,
+                                                 int kb) {
+  __shared__ double As[64][65];  // [row][t]
+  __shared__ double Bs[64][65];  // [t][column]
+  const int64_t ib = r0 + blockIdx.y * (int64_t)64, jb = c0 + blockIdx.x * (int64_t)64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int rr = e >> 6, t = e & 63;
+    const int64_t i = ib + rr, j = jb + t;
+    As[rr][t] = (i < r1 && t < kb) ? W[i * ld + k0 + t] : 0.0;
+    Bs[rr][t] = (rr < kb && j < c1) ? W[(k0 + rr) * ld + j] : 0.0;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = w >> 1, wc = w & 1, lm = lane & 15, lk = lane >> 4;
+  lu_v4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = lu_v4{0.0, 0.0, 0.0, 0.0};
+  // MFMA 16x16x4 float64 (wave64): A[m][k] from lane m + 16 k, B[k][n] from
+  // lane n + 16 k; D[m][n] in lane n + 16 j, element e, m = 4 e + j
+  for (int t0 = 0; t0 < kb; t0 += 4) {
+    double a[2], b[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) a[x] = As[wr * 32 + x * 16 + lm][t0 + lk];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) b[y] = Bs[t0 + lk][wc * 32 + y * 16 + lm];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = ib + wr * 32 + x * 16 + 4 * e + lk;
+        const int64_t j = jb + wc * 32 + y * 16 + lm;
+        if (i < r1 && j < c1) W[i * ld + j] -= acc[x][y][e];
+      }
+}
+
+static int lu_gemm(double* W, int64_t ld, int64_t r0, int64_t r1, int64_t c0, int64_t c1,
+                   int64_t k0, int kb, hipStream_t s) {
+  if (r1 <= r0 || c1 <= c0) return 0;
+  hipLaunchKernelGGL(k_lu_gemm, dim3(ceil_div(c1 - c0, 64), ceil_div(r1 - r0, 64)), dim3(256), 0,
+                     s, W, ld, r0, r1, c0, c1, k0, kb);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+// X = A^-1 N in the right block of W (n x ncol)
+static int lu_solve_augmented(double* W, int64_t n, int64_t ncol, int* piv, double* pbuf,
+                              hipStream_t s) {
+  const int64_t ld = ncol;
+  int r;
+  for (int64_t k0 = 0; k0 < n; k0 += LU_B) {
+    const int kb = (int)std::min<int64_t>(LU_B, n - k0);
+    for (int64_t kk = k0; kk < k0 + kb; ++kk) {
+      hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(1024), 0, s, W, n, ld, k0, kb, kk, piv, pbuf);
+      hipLaunchKernelGGL(k_lu_update, dim3(ceil_div(n - kk, 4)), dim3(256), 0, s, W, n, ld, k0,
+                         kb, kk, piv, pbuf);
+    }
+    BEM_LAUNCH_CHECK();
+    const int64_t c0 = k0 + kb;
+    hipLaunchKernelGGL(k_lu_laswp, dim3(ceil_div(ncol - c0, 256)), dim3(256), 0, s, W, ld, k0,
+                       kb, c0, ncol, piv);
+    hipLaunchKernelGGL(k_lu_trsm_lower, dim3(ceil_div(ncol - c0, 64)), dim3(64), 0, s, W, ld,
+                       k0, kb, c0, ncol);
+    BEM_LAUNCH_CHECK();
+    if ((r = lu_gemm(W, ld, c0, n, c0, ncol, k0, kb, s))) return r;
+  }
+  for (int64_t k0 = ((n - 1) / LU_B) * LU_B; k0 >= 0; k0 -= LU_B) {
+    const int kb = (int)std::min<int64_t>(LU_B, n - k0);
+    hipLaunchKernelGGL(k_lu_trsm_upper, dim3(ceil_div(ncol - n, 256)), dim3(256), 0, s, W, ld,
+                       k0, kb, n, ncol);
+    BEM_LAUNCH_CHECK();
+    if ((r = lu_gemm(W, ld, 0, k0, n, ncol, k0, kb, s))) return r;
+  }
+  return 0;
 }
 
 // C[j][c] = -rho_f omega^2 sum_{a in tri j} sum_i n_{j,i} / 3 X[3a + i][c],
@@ -190,43 +372,62 @@ __global__ void k_fem_schur(const double* __restrict__ A, int64_t ld, int64_t nd
   C[(int64_t)j * ntri + c] = coef * s / 3.0;
 }
 
-// q = C v (real n x n, complex v): one wave per row
-__global__ void __launch_bounds__(256) k_real_matvec(const double* __restrict__ C, int64_t n,
+// B = A^T (n x n), through 32 x 32 tiles in LDS so that both the reads and
+// the writes are coalesced
+__global__ void __launch_bounds__(256) k_transpose(const double* __restrict__ A, int64_t n,
+                                                   double* __restrict__ B) {
+  __shared__ double t[32][33];
+  const int64_t bx = (int64_t)blockIdx.x * 32, by = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = by + j, c = bx + tx;
+    if (r < n && c < n) t[j][tx] = A[r * n + c];
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = bx + j, c = by + tx;
+    if (r < n && c < n) B[r * n + c] = t[tx][j];
+  }
+}
+
+// out = M v (ADD: out += M v) for a real row-major n x n M and complex v: one
+// wave per row, 16-byte loads of the row when n is even (every row then
+// starts 16-byte aligned)
+template <bool ADD>
+__global__ void __launch_bounds__(256) k_real_matvec(const double* __restrict__ M, int64_t n,
                                                      const c64* __restrict__ v,
-                                                     c64* __restrict__ q) {
+                                                     c64* __restrict__ out) {
   const int64_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
+  const double* r = M + row * n;
   double sr = 0.0, si = 0.0;
-  for (int64_t c = lane; c < n; c += 64) {
-    const double a = C[row * n + c];
-    sr += a * v[c].re;
-    si += a * v[c].im;
+  if ((n & 1) == 0) {
+    const double2* r2 = reinterpret_cast<const double2*>(r);
+    for (int64_t c = lane; c < n / 2; c += 64) {
+      const double2 a = r2[c];
+      const c64 v0 = v[2 * c], v1 = v[2 * c + 1];
+      sr += a.x * v0.re + a.y * v1.re;
+      si += a.x * v0.im + a.y * v1.im;
+    }
+  } else {
+    for (int64_t c = lane; c < n; c += 64) {
+      const double a = r[c];
+      sr += a * v[c].re;
+      si += a * v[c].im;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     sr += __shfl_xor(sr, off, 64);
     si += __shfl_xor(si, off, 64);
   }
-  if (lane == 0) q[row] = mk(sr, si);
-}
-
-// out += C^T w (real n x n, complex w): one thread per column
-__global__ void k_real_matvec_t_add(const double* __restrict__ C, int64_t n,
-                                    const c64* __restrict__ w, c64* __restrict__ out) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  double sr = 0.0, si = 0.0;
-  for (int64_t j = 0; j < n; ++j) {
-    const double a = C[j * n + c];
-    sr += a * w[j].re;
-    si += a * w[j].im;
-  }
-  out[c] = cadd(out[c], mk(sr, si));
+  if (lane == 0) out[row] = ADD ? cadd(out[row], mk(sr, si)) : mk(sr, si);
 }
 
 int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int* tets_h,
                    int64_t n_tets, const int* tri_h, double lam, double mu, double rho_s,
-                   double rho_f, double omega, DevArena& keep, double** C_out, hipStream_t s) {
+                   double rho_f, double omega, DevArena& keep, double** C_out, double** Ct_out,
+                   hipStream_t s) {
   DevArena scratch;
   struct Guard {
     DevArena& a;
@@ -242,9 +443,10 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
   ARENA_ALLOC(scratch, tri, 3 * (int64_t)ntri);
   ARENA_ALLOC(scratch, A, ndof * ld);
   ARENA_ALLOC(scratch, nt, 3 * (int64_t)ntri);
-  ARENA_ALLOC(scratch, piv, 1);
-  ARENA_ALLOC(scratch, pval, 1);
+  ARENA_ALLOC(scratch, piv, ndof);
+  ARENA_ALLOC(scratch, pval, 128);
   ARENA_ALLOC(keep, *C_out, (int64_t)ntri * ntri);
+  ARENA_ALLOC(keep, *Ct_out, (int64_t)ntri * ntri);
   BEM_HIP_TRY(hipMemcpyAsync(x, nodes_h, sizeof(double) * 3 * n_nodes, hipMemcpyHostToDevice, s));
   BEM_HIP_TRY(hipMemcpyAsync(tets, tets_h, sizeof(int) * 4 * n_tets, hipMemcpyHostToDevice, s));
   BEM_HIP_TRY(hipMemcpyAsync(tri, tri_h, sizeof(int) * 3 * ntri, hipMemcpyHostToDevice, s));
@@ -255,32 +457,23 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
   hipLaunchKernelGGL(k_fem_load, dim3(ceil_div(ntri, 128)), dim3(128), 0, s, x, tri, ntri, ndof,
                      ld, A, nt);
   BEM_LAUNCH_CHECK();
-  for (int64_t k = 0; k < ndof; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, A, ndof, ld, k, piv, pval);
-    const int64_t nj = ncol - k - 1;
-    if (nj > 0) {
-      hipLaunchKernelGGL(k_gj_swap, dim3(ceil_div(nj, 256)), dim3(256), 0, s, A, ld, k, ncol,
-                         piv, pval);
-      hipLaunchKernelGGL(k_gj_eliminate, dim3(ceil_div(nj, 256), ndof), dim3(256), 0, s, A,
-                         ndof, ld, k, ncol, piv, pval);
-    }
-  }
-  BEM_LAUNCH_CHECK();
+  int r = lu_solve_augmented(A, ndof, ncol, piv, pval, s);
+  if (r) return r;
   hipLaunchKernelGGL(k_fem_schur, dim3(ceil_div(ntri, 128), ntri), dim3(128), 0, s, A, ld, ndof,
                      tri, nt, ntri, -rho_f * omega * omega, *C_out);
+  BEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_transpose, dim3(ceil_div(ntri, 32), ceil_div(ntri, 32)), dim3(32, 8), 0, s,
+                     *C_out, (int64_t)ntri, *Ct_out);
   BEM_LAUNCH_CHECK();
   BEM_HIP_TRY(hipStreamSynchronize(s));
   return 0;
 }
 
-int coupling_q(const double* C, int64_t n, const c64* v, c64* q, hipStream_t s) {
-  hipLaunchKernelGGL(k_real_matvec, dim3(ceil_div(n, 4)), dim3(256), 0, s, C, n, v, q);
-  BEM_LAUNCH_CHECK();
-  return 0;
-}
-
-int coupling_qt_add(const double* C, int64_t n, const c64* w, c64* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_real_matvec_t_add, dim3(ceil_div(n, 256)), dim3(256), 0, s, C, n, w, out);
+int coupling_apply(const double* M, int64_t n, const c64* v, c64* out, bool add, hipStream_t s) {
+  if (add)
+    hipLaunchKernelGGL(k_real_matvec<true>, dim3(ceil_div(n, 4)), dim3(256), 0, s, M, n, v, out);
+  else
+    hipLaunchKernelGGL(k_real_matvec<false>, dim3(ceil_div(n, 4)), dim3(256), 0, s, M, n, v, out);
   BEM_LAUNCH_CHECK();
   return 0;
 }

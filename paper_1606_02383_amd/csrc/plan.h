@@ -413,18 +413,20 @@ int fmm_matvec_noalloc(Problem& P, int prec, const c64* p, const c64* q, c64* y,
                        hipStream_t s);
 
 // solver helpers
-// coup (device, n x n real, row-major; null: none): the coupled operator of
-// an elastic body, q = coup x (adjoint: + coup^T w); excludes sigma
+// coup, coup_t (device, n x n real, row-major; null: none): the coupled
+// operator of an elastic body, q = coup x (adjoint: + coup_t w, coup_t the
+// transpose of coup); excludes sigma
 int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x,
                 double tol, int restart, int max_iter, int mode, double inner_tol, int use_x0,
-                void* info, hipStream_t s, const double* coup = nullptr);
-// BEM-FEM coupling (fem.hip): C = -rho_f omega^2 Tc (K - omega^2 M)^(-1) N
-// built on the device into keep; q = C v; out += C^T w
+                void* info, hipStream_t s, const double* coup = nullptr,
+                const double* coup_t = nullptr);
+// BEM-FEM coupling (fem.hip): C = -rho_f omega^2 Tc (K - omega^2 M)^(-1) N and
+// its transpose built on the device into keep; out = M v (add: out += M v)
 int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int* tets_h,
                    int64_t n_tets, const int* tri_h, double lam, double mu, double rho_s,
-                   double rho_f, double omega, DevArena& keep, double** C_out, hipStream_t s);
-int coupling_q(const double* C, int64_t n, const c64* v, c64* q, hipStream_t s);
-int coupling_qt_add(const double* C, int64_t n, const c64* w, c64* out, hipStream_t s);
+                   double rho_f, double omega, DevArena& keep, double** C_out, double** Ct_out,
+                   hipStream_t s);
+int coupling_apply(const double* M, int64_t n, const c64* v, c64* out, bool add, hipStream_t s);
 int plane_wave_rhs(Problem& P, const double* d, c64* b, hipStream_t s);
 int point_source_rhs(Problem& P, const double* src, const c64* amp, int n_src, c64* b,
                      hipStream_t s);

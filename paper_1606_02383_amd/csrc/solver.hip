@@ -586,7 +586,7 @@ static int gmres_core(Workspace& W, const ApplyFn& apply, const c64* b, c64* x, 
 
 int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x, double tol,
                 int restart, int max_iter, int mode, double inner_tol, int use_x0, void* info_v,
-                hipStream_t s, const double* coup) {
+                hipStream_t s, const double* coup, const double* coup_t) {
   bem_gmres_info* info = (bem_gmres_info*)info_v;
   const int64_t n = P.n;
   const int nb = ceil_div(n, 256);
@@ -605,7 +605,7 @@ int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x,
           BEM_LAUNCH_CHECK();
           q = W.t3;
         } else if (coup) {  // the elastic body's response q = C p
-          if ((rr = coupling_q(coup, n, v, W.t3, s))) return rr;
+          if ((rr = coupling_apply(coup, n, v, W.t3, false, s))) return rr;
           q = W.t3;
         }
         rr = f32 ? fmm_apply<float>(P, P.f32, v, q, out, s) : fmm_apply<double>(P, P.f64, v, q, out, s);
@@ -619,7 +619,7 @@ int gmres_solve(Problem& P, const c64* sigma, int adjoint, const c64* b, c64* x,
           hipLaunchKernelGGL(k_add_conj_diag, dim3(nb), dim3(256), 0, s, out, sigma, W.t3, n, out);
           BEM_LAUNCH_CHECK();
         } else if (coup) {  // (Mp + Mq C)^H = Mp^H + C^T Mq^H (C real)
-          if ((rr = coupling_qt_add(coup, n, W.t3, out, s))) return rr;
+          if ((rr = coupling_apply(coup_t, n, W.t3, out, true, s))) return rr;
         }
       }
       if (f32)

@@ -16,6 +16,10 @@ with the dense BEM blocks of oracle/bem.py):
   and mixed precision) against LU solves of the oracle's dense system;
 * rigid limit: an ever stiffer and heavier body gives the sound-hard
   solution;
+* the elastic-sphere benchmark (tungsten in water, 9633 unknowns, 151
+  panels of the blocked factorisation): sampled columns of C against
+  sparse solves of the oracle's K - omega^2 M and N, and the symmetry of
+  C diag(1 / area) over the whole matrix;
 * bad meshes, materials and sizes are rejected on the host.
 """
 import numpy as np
@@ -23,7 +27,7 @@ import pytest
 
 from oracle import bem as obem
 from oracle import fem
-from workloads import ball_mesh, complex_normal, unit_directions
+from workloads import ELASTIC_SPHERE, ball_mesh, complex_normal, unit_directions
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +80,13 @@ def test_coupling_matrix_against_oracle(ball):
     e = float(np.max(np.abs(Cg - C)) / np.max(np.abs(C)))
     _log(f"  coupling matrix: max rel diff {e:.2e}")
     assert e < 1e-10
+    # the body's response alone, and its transpose (the adjoint's), against
+    # products with the device's own matrix
+    import torch
+    v = complex_normal(np.random.default_rng(8), len(T))
+    for tr, M in ((False, Cg), (True, Cg.T)):
+        out = cp.apply(torch.from_numpy(v), transpose=tr).cpu().numpy()
+        assert _rel(out, M @ v) < 1e-14
     cp.close()
     plan.close()
 
@@ -186,6 +197,33 @@ def test_rigid_limit_gives_the_sound_hard_solution(ball):
     # C scales exactly as 1 / scale: the difference falls about 100-fold per step
     assert errs[1] < errs[0] / 30 and errs[2] < errs[1] / 30 and errs[2] < 1e-4
     plan.close()
+
+
+def test_coupling_matrix_elastic_sphere_benchmark():
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spla
+    bem = _lib()
+    E = ELASTIC_SPHERE
+    nodes, tets, V, T = E.mesh()
+    _log(f"case: elastic sphere, {len(nodes)} nodes ({3 * len(nodes)} unknowns), "
+         f"{len(T)} boundary triangles")
+    plan = bem.Plan(bem.Problem(V, T, E.omega))
+    cp = bem.Coupling(plan, nodes, tets, T, E.lam, E.mu, E.rho_s, E.rho_f, E.omega)
+    Cg = cp.matrix().cpu().numpy()
+    cp.close()
+    plan.close()
+    K, M = fem.elasticity_matrices(nodes, tets, E.lam, E.mu, E.rho_s)
+    A = sps.csc_matrix(K - E.omega ** 2 * M)
+    del K, M
+    Tc, N, area, _ = fem.surface_coupling(nodes, T)
+    cols = np.sort(np.random.default_rng(12).choice(len(T), 6, replace=False))
+    X = spla.spsolve(A, N[:, cols])
+    ref = -E.rho_f * E.omega ** 2 * (Tc @ X)
+    e = float(np.max(np.abs(Cg[:, cols] - ref)) / np.max(np.abs(ref)))
+    S = Cg / area[None, :]
+    es = float(np.max(np.abs(S - S.T)) / np.max(np.abs(S)))
+    _log(f"  sampled columns: max rel diff {e:.2e}; asymmetry of C / area {es:.2e}")
+    assert e < 1e-8 and es < 1e-8
 
 
 def test_bad_coupling_inputs_are_rejected(ball):

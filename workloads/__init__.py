@@ -245,3 +245,43 @@ def batch32(seed: int = 5):
 
 def workload(name: str) -> Workload:
     return WORKLOADS[name]
+
+
+# --------------------------------------------------------------------------
+# the elastic-sphere benchmark of the BEM-FEM coupling (Sec. 3.1): a tungsten
+# sphere of radius 0.25 in water, plane wave along x_3 at omega = 1; material
+# constants normalised by water's density and bulk modulus (so c_f = 1 and
+# k = omega).  The paper meshes the surface with 2456 triangles and the body
+# with 3007 nodes; the stand-in is the ball mesh over the 1280-triangle
+# icosphere with 5 shells (3211 nodes, 9633 unknowns).
+# --------------------------------------------------------------------------
+@dataclass
+class ElasticSphere:
+    radius: float = 0.25
+    level: int = 3
+    n_shell: int = 5
+    rho_s: float = 64.85
+    young: float = 174.57
+    poisson: float = 0.3
+    rho_f: float = 1.0
+    omega: float = 1.0
+    direction: tuple = (0.0, 0.0, 1.0)
+
+    @property
+    def lam(self) -> float:
+        """Lame's first parameter E nu / ((1 + nu)(1 - 2 nu))."""
+        nu = self.poisson
+        return self.young * nu / ((1 + nu) * (1 - 2 * nu))
+
+    @property
+    def mu(self) -> float:
+        """Shear modulus E / (2 (1 + nu))."""
+        return self.young / (2 * (1 + self.poisson))
+
+    def mesh(self):
+        """(nodes, tets, V, T) scaled to the sphere's radius."""
+        nodes, tets, V, T = ball_mesh(self.level, self.n_shell)
+        return nodes * self.radius, tets, V * self.radius, T
+
+
+ELASTIC_SPHERE = ElasticSphere()
