@@ -19,6 +19,7 @@
 // dense real-by-complex matrix-vector product besides the FMM.  Dense storage limits the body to BEM_FEM_MAX_DOF
 // unknowns.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -126,37 +127,57 @@ __global__ void k_fem_load(const double* __restrict__ x, const int* __restrict__
 // ---------------------------------------------------------------------------
 constexpr int LU_B = 64;
 
+constexpr int LU_UR = 16;  // rows (waves) per block of the in-panel update
+
+// (|value|, row) candidates: the larger value wins, the lower row on ties
+__device__ __forceinline__ void lu_better(double& bv, int& bi, double v, int i) {
+  if (v > bv || (v == bv && i < bi)) {
+    bv = v;
+    bi = i;
+  }
+}
+
 // pivot of column kk (rows kk..n-1), then the panel segments of the pivot
-// row and of row kk into pbuf[0..kb) and pbuf[64..64+kb)
+// row and of row kk into pbuf[0..kb) and pbuf[64..64+kb).  The first column
+// of a panel is searched in W; the others from the per-block candidates
+// (pmax, pidx; npart of them) that the previous in-panel update left.
 __global__ void __launch_bounds__(1024) k_lu_pivot(const double* __restrict__ W, int64_t n,
                                                    int64_t ld, int64_t k0, int kb, int64_t kk,
+                                                   const double* __restrict__ pmax,
+                                                   const int* __restrict__ pidx, int npart,
                                                    int* __restrict__ piv,
                                                    double* __restrict__ pbuf) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
+  __shared__ double sv[16];
+  __shared__ int si[16];
   double best = -1.0;
   int bi = (int)kk;
-  for (int64_t i = kk + threadIdx.x; i < n; i += blockDim.x) {
-    const double a = fabs(W[i * ld + kk]);
-    if (a > best) {
-      best = a;
-      bi = (int)i;
-    }
+  if (kk == k0) {
+    for (int64_t i = kk + threadIdx.x; i < n; i += blockDim.x)
+      lu_better(best, bi, fabs(W[i * ld + kk]), (int)i);
+  } else {
+    for (int t = threadIdx.x; t < npart; t += blockDim.x) lu_better(best, bi, pmax[t], pidx[t]);
   }
-  sv[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    lu_better(best, bi, ov, oi);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sv[threadIdx.x >> 6] = best;
+    si[threadIdx.x >> 6] = bi;
+  }
   __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) {
-      const double o = sv[threadIdx.x + h];
-      const int oi = si[threadIdx.x + h];
-      if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && oi < si[threadIdx.x])) {
-        sv[threadIdx.x] = o;
-        si[threadIdx.x] = oi;
-      }
+  if (threadIdx.x < 64) {
+    best = (threadIdx.x < blockDim.x / 64) ? sv[threadIdx.x] : -1.0;
+    bi = (threadIdx.x < blockDim.x / 64) ? si[threadIdx.x] : (int)kk;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      lu_better(best, bi, ov, oi);
     }
-    __syncthreads();
+    if (threadIdx.x == 0) si[0] = bi;
   }
+  __syncthreads();
   const int64_t r = si[0];
   if (threadIdx.x == 0) piv[kk] = (int)r;
   if ((int)threadIdx.x < kb)
@@ -168,30 +189,55 @@ __global__ void __launch_bounds__(1024) k_lu_pivot(const double* __restrict__ W,
 // step kk inside the panel, one wave per row i >= kk, lane c = panel column:
 // row kk takes the pivot row; row piv takes row kk's old values; every row
 // below keeps its multiplier l = W[i][kk] / pivot in column kk and updates
-// the panel columns right of kk (each row reads only itself and pbuf)
-__global__ void __launch_bounds__(256) k_lu_update(double* __restrict__ W, int64_t n, int64_t ld,
-                                                   int64_t k0, int kb, int64_t kk,
-                                                   const int* __restrict__ piv,
-                                                   const double* __restrict__ pbuf) {
-  const int64_t i = kk + blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int c = threadIdx.x & 63;
-  if (i >= n || c >= kb) return;
-  const int64_t r = piv[kk];
+// the panel columns right of kk (each row reads only itself and pbuf).
+// While column kk + 1 is in the panel, each block also leaves its best
+// pivot candidate for that column (rows > kk) in pmax / pidx.
+__global__ void __launch_bounds__(64 * LU_UR) k_lu_update(double* __restrict__ W, int64_t n,
+                                                          int64_t ld, int64_t k0, int kb,
+                                                          int64_t kk, const int* __restrict__ piv,
+                                                          const double* __restrict__ pbuf,
+                                                          double* __restrict__ pmax,
+                                                          int* __restrict__ pidx) {
+  __shared__ double bv[LU_UR];
+  __shared__ int bix[LU_UR];
+  const int w = threadIdx.x >> 6, c = threadIdx.x & 63;
+  const int64_t i = kk + blockIdx.x * (int64_t)LU_UR + w;
   const int ck = (int)(kk - k0);
-  double* row = W + i * ld + k0;
-  if (i == kk) {
-    row[c] = pbuf[c];
-    return;
+  double cand = -1.0;
+  if (i < n && c < kb) {
+    const int64_t r = piv[kk];
+    double* row = W + i * ld + k0;
+    if (i == kk) {
+      row[c] = pbuf[c];
+    } else {
+      const double src_c = (i == r) ? pbuf[64 + c] : row[c];
+      const double src_k = (i == r) ? pbuf[64 + ck] : row[ck];
+      const double l = src_k / pbuf[ck];
+      if (c == ck) {
+        row[c] = l;
+      } else if (c > ck) {
+        const double v = src_c - l * pbuf[c];
+        row[c] = v;
+        cand = fabs(v);
+      } else if (i == r) {
+        row[c] = src_c;
+      }
+    }
   }
-  const double src_c = (i == r) ? pbuf[64 + c] : row[c];
-  const double src_k = (i == r) ? pbuf[64 + ck] : row[ck];
-  const double l = src_k / pbuf[ck];
-  if (c == ck)
-    row[c] = l;
-  else if (c > ck)
-    row[c] = src_c - l * pbuf[c];
-  else if (i == r)
-    row[c] = src_c;
+  if (ck + 1 < kb) {
+    if (c == ck + 1) {
+      bv[w] = cand;
+      bix[w] = (i < n && i > kk) ? (int)i : INT_MAX;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double b = -1.0;
+      int bi = INT_MAX;
+      for (int t = 0; t < LU_UR; ++t) lu_better(b, bi, bv[t], bix[t]);
+      pmax[blockIdx.x] = b;
+      pidx[blockIdx.x] = bi;
+    }
+  }
 }
 
 // trailing columns j in [c0, ncol), one thread each: the panel's row swaps
@@ -276,6 +322,21 @@ __global__ void __launch_bounds__(256) k_lu_gemm(double* __restrict__ W, int64_t
   __shared__ double As[64][65];  // [row][t]
   __shared__ double Bs[64][65];  // [t][column]
   const int64_t ib = r0 + blockIdx.y * (int64_t)64, jb = c0 + blockIdx.x * (int64_t)64;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = w >> 1, wc = w & 1, lm = lane & 15, lk = lane >> 4;
+  // this lane's 16 outputs, loaded first so that their latency overlaps the
+  // staging of the operands
+  double cv[2][2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = ib + wr * 32 + x * 16 + 4 * e + lk;
+        const int64_t j = jb + wc * 32 + y * 16 + lm;
+        cv[x][y][e] = (i < r1 && j < c1) ? W[i * ld + j] : 0.0;
+      }
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int rr = e >> 6, t = e & 63;
     const int64_t i = ib + rr, j = jb + t;
@@ -283,8 +344,6 @@ __global__ void __launch_bounds__(256) k_lu_gemm(double* __restrict__ W, int64_t
     Bs[rr][t] = (rr < kb && j < c1) ? W[(k0 + rr) * ld + j] : 0.0;
   }
   __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wr = w >> 1, wc = w & 1, lm = lane & 15, lk = lane >> 4;
   lu_v4 acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -312,7 +371,7 @@ __global__ void __launch_bounds__(256) k_lu_gemm(double* __restrict__ W, int64_t
       for (int e = 0; e < 4; ++e) {
         const int64_t i = ib + wr * 32 + x * 16 + 4 * e + lk;
         const int64_t j = jb + wc * 32 + y * 16 + lm;
-        if (i < r1 && j < c1) W[i * ld + j] -= acc[x][y][e];
+        if (i < r1 && j < c1) W[i * ld + j] = cv[x][y][e] - acc[x][y][e];
       }
 }
 
@@ -327,15 +386,18 @@ static int lu_gemm(double* W, int64_t ld, int64_t r0, int64_t r1, int64_t c0, in
 
 // X = A^-1 N in the right block of W (n x ncol)
 static int lu_solve_augmented(double* W, int64_t n, int64_t ncol, int* piv, double* pbuf,
-                              hipStream_t s) {
+                              double* pmax, int* pidx, hipStream_t s) {
   const int64_t ld = ncol;
   int r;
   for (int64_t k0 = 0; k0 < n; k0 += LU_B) {
     const int kb = (int)std::min<int64_t>(LU_B, n - k0);
+    int npart = 0;
     for (int64_t kk = k0; kk < k0 + kb; ++kk) {
-      hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(1024), 0, s, W, n, ld, k0, kb, kk, piv, pbuf);
-      hipLaunchKernelGGL(k_lu_update, dim3(ceil_div(n - kk, 4)), dim3(256), 0, s, W, n, ld, k0,
-                         kb, kk, piv, pbuf);
+      hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(1024), 0, s, W, n, ld, k0, kb, kk, pmax, pidx,
+                         npart, piv, pbuf);
+      npart = (int)ceil_div(n - kk, LU_UR);
+      hipLaunchKernelGGL(k_lu_update, dim3(npart), dim3(64 * LU_UR), 0, s, W, n, ld, k0, kb, kk,
+                         piv, pbuf, pmax, pidx);
     }
     BEM_LAUNCH_CHECK();
     const int64_t c0 = k0 + kb;
@@ -436,8 +498,8 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
   const int64_t ndof = 3 * n_nodes;
   const int ntri = (int)P.n;
   const int64_t ncol = ndof + ntri, ld = ncol;
-  double *x, *A, *nt, *pval;
-  int *tets, *tri, *piv;
+  double *x, *A, *nt, *pval, *pmax;
+  int *tets, *tri, *piv, *pidx;
   ARENA_ALLOC(scratch, x, 3 * n_nodes);
   ARENA_ALLOC(scratch, tets, 4 * n_tets);
   ARENA_ALLOC(scratch, tri, 3 * (int64_t)ntri);
@@ -445,6 +507,8 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
   ARENA_ALLOC(scratch, nt, 3 * (int64_t)ntri);
   ARENA_ALLOC(scratch, piv, ndof);
   ARENA_ALLOC(scratch, pval, 128);
+  ARENA_ALLOC(scratch, pmax, ceil_div(ndof, LU_UR));
+  ARENA_ALLOC(scratch, pidx, ceil_div(ndof, LU_UR));
   ARENA_ALLOC(keep, *C_out, (int64_t)ntri * ntri);
   ARENA_ALLOC(keep, *Ct_out, (int64_t)ntri * ntri);
   BEM_HIP_TRY(hipMemcpyAsync(x, nodes_h, sizeof(double) * 3 * n_nodes, hipMemcpyHostToDevice, s));
@@ -457,7 +521,7 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
   hipLaunchKernelGGL(k_fem_load, dim3(ceil_div(ntri, 128)), dim3(128), 0, s, x, tri, ntri, ndof,
                      ld, A, nt);
   BEM_LAUNCH_CHECK();
-  int r = lu_solve_augmented(A, ndof, ncol, piv, pval, s);
+  int r = lu_solve_augmented(A, ndof, ncol, piv, pval, pmax, pidx, s);
   if (r) return r;
   hipLaunchKernelGGL(k_fem_schur, dim3(ceil_div(ntri, 128), ntri), dim3(128), 0, s, A, ld, ndof,
                      tri, nt, ntri, -rho_f * omega * omega, *C_out);
