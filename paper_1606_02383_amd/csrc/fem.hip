@@ -118,8 +118,8 @@ __global__ void k_fem_load(const double* __restrict__ x, const int* __restrict__
 // Blocked LU with partial pivoting of the augmented matrix W = [A | N]
 // (n x ncol, row stride ld; panels of LU_B columns), then blocked back
 // substitution with U: the right block of W ends as X = A^-1 N.  Per panel:
-// column by column a pivot search (k_lu_pivot) and the row swap, the
-// multipliers and the rank-1 update inside the panel (k_lu_update); then the
+// column by column one launch (k_lu_step) for the pivot, the row swap, the
+// multipliers and the rank-1 update inside the panel; then the
 // panel's swaps (k_lu_laswp) and the unit-lower solve L11^-1 (k_lu_trsm_lower)
 // on the trailing columns, and the trailing update W22 -= L21 U12 on the
 // matrix cores (k_lu_gemm).  The multipliers of earlier panels are not swapped:
@@ -127,7 +127,7 @@ __global__ void k_fem_load(const double* __restrict__ x, const int* __restrict__
 // ---------------------------------------------------------------------------
 constexpr int LU_B = 64;
 
-constexpr int LU_UR = 16;  // rows (waves) per block of the in-panel update
+constexpr int LU_UR = 4;  // rows (waves) per block of the in-panel update
 
 // (|value|, row) candidates: the larger value wins, the lower row on ties
 __device__ __forceinline__ void lu_better(double& bv, int& bi, double v, int i) {
@@ -137,107 +137,123 @@ __device__ __forceinline__ void lu_better(double& bv, int& bi, double v, int i) 
   }
 }
 
-// pivot of column kk (rows kk..n-1), then the panel segments of the pivot
-// row and of row kk into pbuf[0..kb) and pbuf[64..64+kb).  The first column
-// of a panel is searched in W; the others from the per-block candidates
-// (pmax, pidx; npart of them) that the previous in-panel update left.
-__global__ void __launch_bounds__(1024) k_lu_pivot(const double* __restrict__ W, int64_t n,
-                                                   int64_t ld, int64_t k0, int kb, int64_t kk,
-                                                   const double* __restrict__ pmax,
-                                                   const int* __restrict__ pidx, int npart,
-                                                   int* __restrict__ piv,
-                                                   double* __restrict__ pbuf) {
-  __shared__ double sv[16];
-  __shared__ int si[16];
-  double best = -1.0;
-  int bi = (int)kk;
-  if (kk == k0) {
-    for (int64_t i = kk + threadIdx.x; i < n; i += blockDim.x)
-      lu_better(best, bi, fabs(W[i * ld + kk]), (int)i);
-  } else {
-    for (int t = threadIdx.x; t < npart; t += blockDim.x) lu_better(best, bi, pmax[t], pidx[t]);
-  }
+// block-wide best of one candidate per thread (blockDim = 64 * LU_UR); every
+// thread returns the winner's row
+__device__ __forceinline__ int lu_block_best(double bv, int bi, double* sv, int* si) {
   for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(best, off, 64);
+    const double ov = __shfl_xor(bv, off, 64);
     const int oi = __shfl_xor(bi, off, 64);
-    lu_better(best, bi, ov, oi);
+    lu_better(bv, bi, ov, oi);
   }
   if ((threadIdx.x & 63) == 0) {
-    sv[threadIdx.x >> 6] = best;
+    sv[threadIdx.x >> 6] = bv;
     si[threadIdx.x >> 6] = bi;
   }
   __syncthreads();
-  if (threadIdx.x < 64) {
-    best = (threadIdx.x < blockDim.x / 64) ? sv[threadIdx.x] : -1.0;
-    bi = (threadIdx.x < blockDim.x / 64) ? si[threadIdx.x] : (int)kk;
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      lu_better(best, bi, ov, oi);
-    }
-    if (threadIdx.x == 0) si[0] = bi;
+  if (threadIdx.x == 0) {
+    for (int t = 1; t < LU_UR; ++t) lu_better(sv[0], si[0], sv[t], si[t]);
   }
   __syncthreads();
-  const int64_t r = si[0];
-  if (threadIdx.x == 0) piv[kk] = (int)r;
-  if ((int)threadIdx.x < kb)
-    pbuf[threadIdx.x] = W[r * ld + k0 + threadIdx.x];
-  else if (threadIdx.x >= 64 && (int)threadIdx.x < 64 + kb)
-    pbuf[threadIdx.x] = W[kk * ld + k0 + threadIdx.x - 64];
+  return si[0];
 }
 
-// step kk inside the panel, one wave per row i >= kk, lane c = panel column:
-// row kk takes the pivot row; row piv takes row kk's old values; every row
-// below keeps its multiplier l = W[i][kk] / pivot in column kk and updates
-// the panel columns right of kk (each row reads only itself and pbuf).
-// While column kk + 1 is in the panel, each block also leaves its best
-// pivot candidate for that column (rows > kk) in pmax / pidx.
-__global__ void __launch_bounds__(64 * LU_UR) k_lu_update(double* __restrict__ W, int64_t n,
-                                                          int64_t ld, int64_t k0, int kb,
-                                                          int64_t kk, const int* __restrict__ piv,
-                                                          const double* __restrict__ pbuf,
-                                                          double* __restrict__ pmax,
-                                                          int* __restrict__ pidx) {
-  __shared__ double bv[LU_UR];
-  __shared__ int bix[LU_UR];
+// The panel (rows k0..n-1, its kb columns) is factorised in two row-major
+// n x 64 buffers: step s = kk - k0 reads B[s % 2] and writes B[(s + 1) % 2],
+// so the pivot row and row kk that every block reads are never written in
+// the same launch.  Row k0 + s is final after step s (in B[(s + 1) % 2]);
+// the other rows after the last step (in B[kb % 2]).
+//
+// panel load: W -> B0, and each block's best candidate for the pivot of
+// column k0 (one wave per row)
+__global__ void __launch_bounds__(64 * LU_UR) k_lu_panel_load(const double* __restrict__ W,
+                                                              int64_t n, int64_t ld, int64_t k0,
+                                                              int kb, double* __restrict__ B0,
+                                                              double* __restrict__ pmax,
+                                                              int* __restrict__ pidx) {
+  __shared__ double sv[LU_UR];
+  __shared__ int si[LU_UR];
   const int w = threadIdx.x >> 6, c = threadIdx.x & 63;
-  const int64_t i = kk + blockIdx.x * (int64_t)LU_UR + w;
-  const int ck = (int)(kk - k0);
-  double cand = -1.0;
+  const int64_t i = k0 + blockIdx.x * (int64_t)LU_UR + w;
+  double v = 0.0;
   if (i < n && c < kb) {
-    const int64_t r = piv[kk];
-    double* row = W + i * ld + k0;
+    v = W[i * ld + k0 + c];
+    B0[(i - k0) * 64 + c] = v;
+  }
+  const bool cand = (i < n && c == 0);
+  const int best = lu_block_best(cand ? fabs(v) : -1.0, cand ? (int)i : INT_MAX, sv, si);
+  if (threadIdx.x == 0) {
+    pmax[blockIdx.x] = sv[0];
+    pidx[blockIdx.x] = best;
+  }
+}
+
+// step kk of the panel: every block reduces the previous step's candidates
+// (npart of them) to the pivot row r, then its waves stride over the rows
+// i >= kk (one wave per row at a time, lane c = panel column) and write each
+// row's new state: row kk takes the pivot row, row r takes row kk's old
+// values, every row below keeps its multiplier l = W[i][kk] / pivot in
+// column kk and updates the columns right of kk; while column kk + 1 is in
+// the panel each block leaves its best candidate (rows > kk) for it.  At
+// most LU_STEP_BLOCKS blocks, so that one round of them fills the chip.
+constexpr int LU_STEP_BLOCKS = 1024;
+__global__ void __launch_bounds__(64 * LU_UR) k_lu_step(
+    int64_t n, int64_t k0, int kb, int64_t kk, const double* __restrict__ Pin,
+    double* __restrict__ Pout, const double* __restrict__ pin_max,
+    const int* __restrict__ pin_idx, int npart, double* __restrict__ pout_max,
+    int* __restrict__ pout_idx, int* __restrict__ piv) {
+  __shared__ double sv[LU_UR];
+  __shared__ int si[LU_UR];
+  __shared__ double prow[64], rowk[64];
+  const int w = threadIdx.x >> 6, c = threadIdx.x & 63;
+  const int ck = (int)(kk - k0);
+  const double k_c = (threadIdx.x < 64 && c < kb) ? Pin[(kk - k0) * 64 + c] : 0.0;
+  double bv = -1.0;
+  int bi = (int)kk;
+  for (int t = threadIdx.x; t < npart; t += blockDim.x) lu_better(bv, bi, pin_max[t], pin_idx[t]);
+  if (threadIdx.x < 64) rowk[c] = k_c;
+  const int64_t r = lu_block_best(bv, bi, sv, si);
+  if (threadIdx.x < 64) prow[c] = c < kb ? Pin[(r - k0) * 64 + c] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) piv[kk] = (int)r;
+  __syncthreads();
+  double cv = -1.0;
+  int ci = INT_MAX;
+  const int64_t stride = (int64_t)gridDim.x * LU_UR;
+  for (int64_t i = kk + blockIdx.x * (int64_t)LU_UR + w; i < n; i += stride) {
+    if (c >= kb) continue;
+    double out;
     if (i == kk) {
-      row[c] = pbuf[c];
+      out = prow[c];
     } else {
-      const double src_c = (i == r) ? pbuf[64 + c] : row[c];
-      const double src_k = (i == r) ? pbuf[64 + ck] : row[ck];
-      const double l = src_k / pbuf[ck];
-      if (c == ck) {
-        row[c] = l;
-      } else if (c > ck) {
-        const double v = src_c - l * pbuf[c];
-        row[c] = v;
-        cand = fabs(v);
-      } else if (i == r) {
-        row[c] = src_c;
-      }
+      const double src_c = (i == r) ? rowk[c] : Pin[(i - k0) * 64 + c];
+      const double src_k = (i == r) ? rowk[ck] : Pin[(i - k0) * 64 + ck];
+      const double l = src_k / prow[ck];
+      out = (c == ck) ? l : (c > ck ? src_c - l * prow[c] : src_c);
+      lu_better(cv, ci, fabs(out), (int)i);
     }
+    Pout[(i - k0) * 64 + c] = out;
   }
   if (ck + 1 < kb) {
-    if (c == ck + 1) {
-      bv[w] = cand;
-      bix[w] = (i < n && i > kk) ? (int)i : INT_MAX;
-    }
-    __syncthreads();
+    // the candidates sit in lane ck + 1 of each wave
+    const bool cand = (c == ck + 1);
+    const int best = lu_block_best(cand ? cv : -1.0, cand ? ci : INT_MAX, sv, si);
     if (threadIdx.x == 0) {
-      double b = -1.0;
-      int bi = INT_MAX;
-      for (int t = 0; t < LU_UR; ++t) lu_better(b, bi, bv[t], bix[t]);
-      pmax[blockIdx.x] = b;
-      pidx[blockIdx.x] = bi;
+      pout_max[blockIdx.x] = sv[0];
+      pout_idx[blockIdx.x] = best;
     }
   }
+}
+
+// panel store: the final rows back into W (one wave per row)
+__global__ void __launch_bounds__(256) k_lu_panel_store(double* __restrict__ W, int64_t n,
+                                                        int64_t ld, int64_t k0, int kb,
+                                                        const double* __restrict__ B0,
+                                                        const double* __restrict__ B1) {
+  const int64_t i = k0 + blockIdx.x * (int64_t)4 + (threadIdx.x >> 6);
+  const int c = threadIdx.x & 63;
+  if (i >= n || c >= kb) return;
+  const int64_t li = i - k0;
+  const int b = li < kb ? (int)((li + 1) & 1) : (kb & 1);
+  W[i * ld + k0 + c] = (b ? B1 : B0)[li * 64 + c];
 }
 
 // trailing columns j in [c0, ncol), one thread each: the panel's row swaps
@@ -312,15 +328,17 @@ __global__ void __launch_bounds__(256) k_lu_trsm_upper(double* __restrict__ W, i
 
 // W[i][j] -= sum_{t < kb} W[i][k0 + t] W[k0 + t][j] for i in [r0, r1),
 // j in [c0, c1): 64 x 64 output tiles, four waves of 2 x 2 float64 MFMA
-// 16x16x4 blocks; both operands staged whole (kb <= 64) in LDS, zero-padded.
+// 16x16x4 blocks; the operands staged in LDS in chunks of 32 of the inner
+// dimension, zero-padded (34 KB of LDS: four workgroups per CU).
 // The operand columns / rows lie outside the output range in both uses (the
 // trailing update and the back substitution).
 typedef double lu_v4 __attribute__((ext_vector_type(4)));
+constexpr int LU_KC = 32;  // inner-dimension chunk staged in LDS
 __global__ void __launch_bounds__(256) k_lu_gemm(double* __restrict__ W, int64_t ld, int64_t r0,
                                                  int64_t r1, int64_t c0, int64_t c1, int64_t k0,
                                                  int kb) {
-  __shared__ double As[64][65];  // [row][t]
-  __shared__ double Bs[64][65];  // [t][column]
+  __shared__ double As[64][LU_KC + 1];  // [row][t]
+  __shared__ double Bs[LU_KC][64 + 1];  // [t][column]
   const int64_t ib = r0 + blockIdx.y * (int64_t)64, jb = c0 + blockIdx.x * (int64_t)64;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1, lm = lane & 15, lk = lane >> 4;
@@ -337,31 +355,37 @@ __global__ void __launch_bounds__(256) k_lu_gemm(double* __restrict__ W, int64_t
         const int64_t j = jb + wc * 32 + y * 16 + lm;
         cv[x][y][e] = (i < r1 && j < c1) ? W[i * ld + j] : 0.0;
       }
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int rr = e >> 6, t = e & 63;
-    const int64_t i = ib + rr, j = jb + t;
-    As[rr][t] = (i < r1 && t < kb) ? W[i * ld + k0 + t] : 0.0;
-    Bs[rr][t] = (rr < kb && j < c1) ? W[(k0 + rr) * ld + j] : 0.0;
-  }
-  __syncthreads();
   lu_v4 acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = lu_v4{0.0, 0.0, 0.0, 0.0};
-  // MFMA 16x16x4 float64 (wave64): A[m][k] from lane m + 16 k, B[k][n] from
-  // lane n + 16 k; D[m][n] in lane n + 16 j, element e, m = 4 e + j
-  for (int t0 = 0; t0 < kb; t0 += 4) {
-    double a[2], b[2];
+  for (int tc = 0; tc < kb; tc += LU_KC) {
+    if (tc > 0) __syncthreads();
+    for (int e = threadIdx.x; e < 64 * LU_KC; e += 256) {
+      const int rr = e / LU_KC, t = e % LU_KC;  // A: row rr, inner t
+      const int64_t i = ib + rr;
+      As[rr][t] = (i < r1 && tc + t < kb) ? W[i * ld + k0 + tc + t] : 0.0;
+      const int tb = e / 64, cb = e % 64;      // B: inner tb, column cb
+      const int64_t j = jb + cb;
+      Bs[tb][cb] = (tc + tb < kb && j < c1) ? W[(k0 + tc + tb) * ld + j] : 0.0;
+    }
+    __syncthreads();
+    // MFMA 16x16x4 float64 (wave64): A[m][k] from lane m + 16 k, B[k][n] from
+    // lane n + 16 k; D[m][n] in lane n + 16 j, element e, m = 4 e + j
+    const int tn = min(LU_KC, kb - tc);
+    for (int t0 = 0; t0 < tn; t0 += 4) {
+      double a[2], b[2];
 #pragma unroll
-    for (int x = 0; x < 2; ++x) a[x] = As[wr * 32 + x * 16 + lm][t0 + lk];
+      for (int x = 0; x < 2; ++x) a[x] = As[wr * 32 + x * 16 + lm][t0 + lk];
 #pragma unroll
-    for (int y = 0; y < 2; ++y) b[y] = Bs[t0 + lk][wc * 32 + y * 16 + lm];
+      for (int y = 0; y < 2; ++y) b[y] = Bs[t0 + lk][wc * 32 + y * 16 + lm];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
-        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -385,20 +409,27 @@ static int lu_gemm(double* W, int64_t ld, int64_t r0, int64_t r1, int64_t c0, in
 }
 
 // X = A^-1 N in the right block of W (n x ncol)
-static int lu_solve_augmented(double* W, int64_t n, int64_t ncol, int* piv, double* pbuf,
-                              double* pmax, int* pidx, hipStream_t s) {
+// B: two n x 64 panel buffers; pmax / pidx: two candidate arrays of
+// ceil(n / LU_UR) entries each
+static int lu_solve_augmented(double* W, int64_t n, int64_t ncol, int* piv, double* const B[2],
+                              double* const pmax[2], int* const pidx[2], hipStream_t s) {
   const int64_t ld = ncol;
   int r;
   for (int64_t k0 = 0; k0 < n; k0 += LU_B) {
     const int kb = (int)std::min<int64_t>(LU_B, n - k0);
-    int npart = 0;
-    for (int64_t kk = k0; kk < k0 + kb; ++kk) {
-      hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(1024), 0, s, W, n, ld, k0, kb, kk, pmax, pidx,
-                         npart, piv, pbuf);
-      npart = (int)ceil_div(n - kk, LU_UR);
-      hipLaunchKernelGGL(k_lu_update, dim3(npart), dim3(64 * LU_UR), 0, s, W, n, ld, k0, kb, kk,
-                         piv, pbuf, pmax, pidx);
+    int npart = ceil_div(n - k0, LU_UR);
+    hipLaunchKernelGGL(k_lu_panel_load, dim3(npart), dim3(64 * LU_UR), 0, s, W, n, ld, k0, kb,
+                       B[0], pmax[0], pidx[0]);
+    for (int st = 0; st < kb; ++st) {
+      const int64_t kk = k0 + st;
+      const int nb = std::min(ceil_div(n - kk, LU_UR), LU_STEP_BLOCKS);
+      hipLaunchKernelGGL(k_lu_step, dim3(nb), dim3(64 * LU_UR), 0, s, n, k0, kb, kk,
+                         B[st & 1], B[(st + 1) & 1], pmax[st & 1], pidx[st & 1], npart,
+                         pmax[(st + 1) & 1], pidx[(st + 1) & 1], piv);
+      npart = nb;
     }
+    hipLaunchKernelGGL(k_lu_panel_store, dim3(ceil_div(n - k0, 4)), dim3(256), 0, s, W, n, ld, k0,
+                       kb, B[0], B[1]);
     BEM_LAUNCH_CHECK();
     const int64_t c0 = k0 + kb;
     hipLaunchKernelGGL(k_lu_laswp, dim3(ceil_div(ncol - c0, 256)), dim3(256), 0, s, W, ld, k0,
@@ -498,7 +529,7 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
   const int64_t ndof = 3 * n_nodes;
   const int ntri = (int)P.n;
   const int64_t ncol = ndof + ntri, ld = ncol;
-  double *x, *A, *nt, *pval, *pmax;
+  double *x, *A, *nt, *pbuf, *pmax;
   int *tets, *tri, *piv, *pidx;
   ARENA_ALLOC(scratch, x, 3 * n_nodes);
   ARENA_ALLOC(scratch, tets, 4 * n_tets);
@@ -506,9 +537,9 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
   ARENA_ALLOC(scratch, A, ndof * ld);
   ARENA_ALLOC(scratch, nt, 3 * (int64_t)ntri);
   ARENA_ALLOC(scratch, piv, ndof);
-  ARENA_ALLOC(scratch, pval, 128);
-  ARENA_ALLOC(scratch, pmax, ceil_div(ndof, LU_UR));
-  ARENA_ALLOC(scratch, pidx, ceil_div(ndof, LU_UR));
+  ARENA_ALLOC(scratch, pbuf, 2 * ndof * 64);
+  ARENA_ALLOC(scratch, pmax, 2 * (int64_t)ceil_div(ndof, LU_UR));
+  ARENA_ALLOC(scratch, pidx, 2 * (int64_t)ceil_div(ndof, LU_UR));
   ARENA_ALLOC(keep, *C_out, (int64_t)ntri * ntri);
   ARENA_ALLOC(keep, *Ct_out, (int64_t)ntri * ntri);
   BEM_HIP_TRY(hipMemcpyAsync(x, nodes_h, sizeof(double) * 3 * n_nodes, hipMemcpyHostToDevice, s));
@@ -521,7 +552,10 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
   hipLaunchKernelGGL(k_fem_load, dim3(ceil_div(ntri, 128)), dim3(128), 0, s, x, tri, ntri, ndof,
                      ld, A, nt);
   BEM_LAUNCH_CHECK();
-  int r = lu_solve_augmented(A, ndof, ncol, piv, pval, pmax, pidx, s);
+  double* const Bp[2] = {pbuf, pbuf + ndof * 64};
+  double* const pm[2] = {pmax, pmax + ceil_div(ndof, LU_UR)};
+  int* const pi[2] = {pidx, pidx + ceil_div(ndof, LU_UR)};
+  int r = lu_solve_augmented(A, ndof, ncol, piv, Bp, pm, pi, s);
   if (r) return r;
   hipLaunchKernelGGL(k_fem_schur, dim3(ceil_div(ntri, 128), ntri), dim3(128), 0, s, A, ld, ndof,
                      tri, nt, ntri, -rho_f * omega * omega, *C_out);
