@@ -17,7 +17,8 @@ with the dense BEM blocks of oracle/bem.py):
 * rigid limit: an ever stiffer and heavier body gives the sound-hard
   solution;
 * the elastic-sphere benchmark (tungsten in water, 9633 unknowns, 151
-  panels of the blocked factorisation): sampled columns of C against
+  panels of the blocked factorisation) and a finer body near the size
+  limit (11559 unknowns): sampled columns of C against
   sparse solves of the oracle's K - omega^2 M and N, and the symmetry of
   C diag(1 / area) over the whole matrix;
 * bad meshes, materials and sizes are rejected on the host.
@@ -199,11 +200,16 @@ def test_rigid_limit_gives_the_sound_hard_solution(ball):
     plan.close()
 
 
-def test_coupling_matrix_elastic_sphere_benchmark():
+@pytest.mark.parametrize("n_shell", [5, 6])
+def test_coupling_matrix_elastic_sphere_benchmark(n_shell):
+    """5 shells: the benchmark's body; 6 shells: 11559 unknowns, near the
+    size limit (ragged last panels of 33 and 39 columns)."""
+    import dataclasses
+
     import scipy.sparse as sps
     import scipy.sparse.linalg as spla
     bem = _lib()
-    E = ELASTIC_SPHERE
+    E = dataclasses.replace(ELASTIC_SPHERE, n_shell=n_shell)
     nodes, tets, V, T = E.mesh()
     _log(f"case: elastic sphere, {len(nodes)} nodes ({3 * len(nodes)} unknowns), "
          f"{len(T)} boundary triangles")
