@@ -266,13 +266,15 @@ def run_elastic(args):
     nodes, tets, V, T = E.mesh()
     n = len(T)
     d = np.array(E.direction)
+    # the paper's numerical examples: FMM truncation and GMRES tolerance 1e-5
+    fmm_tol = 1e-5
     opts = bem.GmresOptions(tol=1e-5, restart=50, mode=0)
     log(f"[bench] elastic sphere: {len(nodes)} nodes ({3 * len(nodes)} unknowns), "
         f"{len(tets)} tetrahedra, {n} boundary triangles, omega = {E.omega}")
 
     def step():
         t0 = time.perf_counter()
-        plan = bem.Plan(bem.Problem(V, T, E.omega))
+        plan = bem.Plan(bem.Problem(V, T, E.omega, fmm_tol=fmm_tol))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         cp = bem.Coupling(plan, nodes, tets, T, E.lam, E.mu, E.rho_s, E.rho_f, E.omega)
@@ -302,19 +304,28 @@ def run_elastic(args):
     log(f"[bench] elastic sphere: {dt * 1e3:.1f} ms per solve: plan {plan_s * 1e3:.1f}, "
         f"coupling (assembly, LU, C) {coup_s * 1e3:.1f}, GMRES {solve_s * 1e3:.2f} ms "
         f"({info['iterations']} iterations, residual {info['resid']:.2e})")
-    # the dense coupling product alone (one kernel per call): HIP events on
-    # the library's stream, 8 n^2 bytes of C per launch
+    # the dense coupling product alone (one kernel per call, 8 n^2 bytes of C
+    # per launch): 200 launches captured in a HIP graph and replayed between
+    # two HIP events on the stream, so that the launches run back to back
+    # (calls from Python one by one would time the host's launch rate)
     p = torch.ones(n, dtype=torch.complex128, device="cuda")
     for _ in range(10):
         cp.apply(p)
-    reps = 500
+    torch.cuda.synchronize()
+    reps = 200
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(reps):
+            cp.apply(p)
+    graph.replay()
+    torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record()
-    for _ in range(reps):
-        cp.apply(p)
+    graph.replay()
     ev[1].record()
     torch.cuda.synchronize()
     apply_s = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+    del graph
     cbytes = 8.0 * n * n + 2 * 16.0 * n
     log(f"[bench] coupling product C p: {apply_s * 1e6:.2f} us per launch, "
         f"{cbytes / apply_s / 1e9:.0f} GB/s")
@@ -343,7 +354,7 @@ def run_elastic(args):
         "config": {"workload": "elastic_sphere", "radius": E.radius,
                    "fe_nodes": len(nodes), "fe_unknowns": 3 * len(nodes), "tetrahedra": len(tets),
                    "n_tri": n, "omega": E.omega, "rho_s": E.rho_s, "young": E.young,
-                   "poisson": E.poisson, "tol": 1e-5},
+                   "poisson": E.poisson, "tol": 1e-5, "fmm_tol": fmm_tol},
         "parts_ms": {"plan": plan_s * 1e3, "coupling": coup_s * 1e3, "gmres": solve_s * 1e3},
         "gmres_iterations": info["iterations"],
         "coupling_product": {"us": apply_s * 1e6, "bytes": cbytes,

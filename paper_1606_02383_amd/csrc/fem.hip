@@ -484,27 +484,28 @@ __global__ void __launch_bounds__(256) k_transpose(const double* __restrict__ A,
 }
 
 // out = M v (ADD: out += M v) for a real row-major n x n M and complex v: one
-// wave per row, 16-byte loads of the row when n is even (every row then
-// starts 16-byte aligned)
+// workgroup of four waves per row (enough loads in flight to stream the
+// matrix), 16-byte loads of the row when n is even (every row then starts
+// 16-byte aligned)
 template <bool ADD>
 __global__ void __launch_bounds__(256) k_real_matvec(const double* __restrict__ M, int64_t n,
                                                      const c64* __restrict__ v,
                                                      c64* __restrict__ out) {
-  const int64_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
+  __shared__ double red[2][4];
+  const int64_t row = blockIdx.x;
+  const int t = threadIdx.x;
   const double* r = M + row * n;
   double sr = 0.0, si = 0.0;
   if ((n & 1) == 0) {
     const double2* r2 = reinterpret_cast<const double2*>(r);
-    for (int64_t c = lane; c < n / 2; c += 64) {
+    for (int64_t c = t; c < n / 2; c += 256) {
       const double2 a = r2[c];
       const c64 v0 = v[2 * c], v1 = v[2 * c + 1];
       sr += a.x * v0.re + a.y * v1.re;
       si += a.x * v0.im + a.y * v1.im;
     }
   } else {
-    for (int64_t c = lane; c < n; c += 64) {
+    for (int64_t c = t; c < n; c += 256) {
       const double a = r[c];
       sr += a * v[c].re;
       si += a * v[c].im;
@@ -514,7 +515,16 @@ __global__ void __launch_bounds__(256) k_real_matvec(const double* __restrict__ 
     sr += __shfl_xor(sr, off, 64);
     si += __shfl_xor(si, off, 64);
   }
-  if (lane == 0) out[row] = ADD ? cadd(out[row], mk(sr, si)) : mk(sr, si);
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = sr;
+    red[1][t >> 6] = si;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const c64 y = mk(red[0][0] + red[0][1] + red[0][2] + red[0][3],
+                     red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    out[row] = ADD ? cadd(out[row], y) : y;
+  }
 }
 
 int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int* tets_h,
@@ -568,10 +578,11 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
 }
 
 int coupling_apply(const double* M, int64_t n, const c64* v, c64* out, bool add, hipStream_t s) {
+  if (n <= 0) return 0;
   if (add)
-    hipLaunchKernelGGL(k_real_matvec<true>, dim3(ceil_div(n, 4)), dim3(256), 0, s, M, n, v, out);
+    hipLaunchKernelGGL(k_real_matvec<true>, dim3(n), dim3(256), 0, s, M, n, v, out);
   else
-    hipLaunchKernelGGL(k_real_matvec<false>, dim3(ceil_div(n, 4)), dim3(256), 0, s, M, n, v, out);
+    hipLaunchKernelGGL(k_real_matvec<false>, dim3(n), dim3(256), 0, s, M, n, v, out);
   BEM_LAUNCH_CHECK();
   return 0;
 }
