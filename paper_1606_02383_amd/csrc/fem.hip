@@ -119,11 +119,12 @@ __global__ void k_fem_load(const double* __restrict__ x, const int* __restrict__
 // (n x ncol, row stride ld; panels of LU_B columns), then blocked back
 // substitution with U: the right block of W ends as X = A^-1 N.  Per panel:
 // column by column one launch (k_lu_step) for the pivot, the row swap, the
-// multipliers and the rank-1 update inside the panel; then the
-// panel's swaps (k_lu_laswp) and the unit-lower solve L11^-1 (k_lu_trsm_lower)
-// on the trailing columns, and the trailing update W22 -= L21 U12 on the
-// matrix cores (k_lu_gemm).  The multipliers of earlier panels are not swapped:
-// the right block is eliminated in place, so L is never read again.
+// multipliers and the rank-1 update inside the panel; then the panel's swaps
+// (k_lu_laswp) and the unit-lower solve L11^-1 (k_lu_trsm) on the
+// columns right of it, and the update W22 -= L21 U12 on the matrix cores
+// (k_lu_gemm), the trailing one once per two panels.  The multipliers of
+// earlier blocks are not swapped: the right block is eliminated in place, so
+// they are never read again.
 // ---------------------------------------------------------------------------
 constexpr int LU_B = 64;
 
@@ -272,66 +273,54 @@ __global__ void __launch_bounds__(256) k_lu_laswp(double* __restrict__ W, int64_
   }
 }
 
-// trailing columns j in [c0, ncol), one lane each (one wave per block): x =
-// L11^-1 x over the panel's rows, L11 unit lower and the 64 columns' values
-// staged in LDS (lane-major, conflict-free)
-__global__ void __launch_bounds__(64) k_lu_trsm_lower(double* __restrict__ W, int64_t ld,
-                                                      int64_t k0, int kb, int64_t c0,
-                                                      int64_t ncol) {
-  __shared__ double L[LU_B][LU_B + 1];
-  __shared__ double X[LU_B][64];
-  for (int e = threadIdx.x; e < LU_B * LU_B; e += 64) {
-    const int r = e / LU_B, t = e % LU_B;
-    L[r][t] = (r < kb && t < r) ? W[(k0 + r) * ld + k0 + t] : 0.0;
-  }
-  const int lane = threadIdx.x;
-  const int64_t j = c0 + blockIdx.x * (int64_t)64 + lane;
-  const bool on = j < ncol;
-  for (int t = 0; t < kb; ++t) X[t][lane] = on ? W[(k0 + t) * ld + j] : 0.0;
-  __syncthreads();
-  for (int r = 1; r < kb; ++r) {
-    double s = X[r][lane];
-    for (int t = 0; t < r; ++t) s -= L[r][t] * X[t][lane];
-    X[r][lane] = s;
-  }
-  if (on)
-    for (int t = 0; t < kb; ++t) W[(k0 + t) * ld + j] = X[t][lane];
-}
-
-// right block columns j in [c0, ncol), one thread each: x = U11^-1 x over
-// the panel's rows (U11 upper with its diagonal, staged in LDS)
-__global__ void __launch_bounds__(256) k_lu_trsm_upper(double* __restrict__ W, int64_t ld,
-                                                       int64_t k0, int kb, int64_t c0,
-                                                       int64_t ncol) {
+// columns j in [c0, ncol), one thread each, over the panel's rows k0..k0+kb-1:
+// UPPER, x = U11^-1 x (U11 with its diagonal); else x = L11^-1 x (L11 unit
+// lower).  The lower solve is the upper one on reversed rows and columns
+// (index q = LU_B - 1 - r), so both run the same register-resident
+// back substitution; the triangle is staged in LDS.
+template <bool UPPER>
+__global__ void __launch_bounds__(256) k_lu_trsm(double* __restrict__ W, int64_t ld, int64_t k0,
+                                                 int kb, int64_t c0, int64_t ncol) {
   __shared__ double U[LU_B][LU_B + 1];
   for (int e = threadIdx.x; e < LU_B * LU_B; e += blockDim.x) {
-    const int r = e / LU_B, t = e % LU_B;
-    U[r][t] = (r < kb && t < kb && t >= r) ? W[(k0 + r) * ld + k0 + t] : (r == t ? 1.0 : 0.0);
+    const int q = e / LU_B, u = e % LU_B;  // U[q][u], u >= q
+    double v = (q == u) ? 1.0 : 0.0;
+    if (u > q || (UPPER && u == q)) {
+      const int r = UPPER ? q : LU_B - 1 - q, t = UPPER ? u : LU_B - 1 - u;
+      if (r < kb && t < kb) v = W[(k0 + r) * ld + k0 + t];
+    }
+    U[q][u] = v;
   }
   __syncthreads();
   const int64_t j = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= ncol) return;
   double x[LU_B];
 #pragma unroll
-  for (int t = 0; t < LU_B; ++t) x[t] = (t < kb) ? W[(k0 + t) * ld + j] : 0.0;
-#pragma unroll
-  for (int r = LU_B - 1; r >= 0; --r) {
-    double s = x[r];
-#pragma unroll
-    for (int t = r + 1; t < LU_B; ++t) s -= U[r][t] * x[t];
-    x[r] = s / U[r][r];
+  for (int q = 0; q < LU_B; ++q) {
+    const int r = UPPER ? q : LU_B - 1 - q;
+    x[q] = (r < kb) ? W[(k0 + r) * ld + j] : 0.0;
   }
 #pragma unroll
-  for (int t = 0; t < LU_B; ++t)
-    if (t < kb) W[(k0 + t) * ld + j] = x[t];
+  for (int q = LU_B - 1; q >= 0; --q) {
+    double s = x[q];
+#pragma unroll
+    for (int u = q + 1; u < LU_B; ++u) s -= U[q][u] * x[u];
+    x[q] = s / U[q][q];
+  }
+#pragma unroll
+  for (int q = 0; q < LU_B; ++q) {
+    const int r = UPPER ? q : LU_B - 1 - q;
+    if (r < kb) W[(k0 + r) * ld + j] = x[q];
+  }
 }
 
 // W[i][j] -= sum_{t < kb} W[i][k0 + t] W[k0 + t][j] for i in [r0, r1),
 // j in [c0, c1): 64 x 64 output tiles, four waves of 2 x 2 float64 MFMA
 // 16x16x4 blocks; the operands staged in LDS in chunks of 32 of the inner
 // dimension, zero-padded (34 KB of LDS: four workgroups per CU).
-// The operand columns / rows lie outside the output range in both uses (the
-// trailing update and the back substitution).
+// The operand columns / rows lie outside the output range in every use (the
+// updates inside a block of panels, the trailing update, the back
+// substitution).
 typedef double lu_v4 __attribute__((ext_vector_type(4)));
 constexpr int LU_KC = 32;  // inner-dimension chunk staged in LDS
 __global__ void __launch_bounds__(256) k_lu_gemm(double* __restrict__ W, int64_t ld, int64_t r0,
@@ -411,37 +400,77 @@ static int lu_gemm(double* W, int64_t ld, int64_t r0, int64_t r1, int64_t c0, in
 // X = A^-1 N in the right block of W (n x ncol)
 // B: two n x 64 panel buffers; pmax / pidx: two candidate arrays of
 // ceil(n / LU_UR) entries each
+static int lu_swaps(double* W, int64_t ld, int64_t k0, int kb, int64_t c0, int64_t c1,
+                    const int* piv, hipStream_t s) {
+  if (c1 <= c0) return 0;
+  hipLaunchKernelGGL(k_lu_laswp, dim3(ceil_div(c1 - c0, 256)), dim3(256), 0, s, W, ld, k0, kb, c0,
+                     c1, piv);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+static int lu_trsm_lower(double* W, int64_t ld, int64_t k0, int kb, int64_t c0, int64_t c1,
+                         hipStream_t s) {
+  if (c1 <= c0) return 0;
+  hipLaunchKernelGGL(k_lu_trsm<false>, dim3(ceil_div(c1 - c0, 256)), dim3(256), 0, s, W, ld, k0, kb,
+                     c0, c1);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+// 64-column panel k0..k0+kb-1 over rows k0..n-1 (pivots into piv)
+static int lu_panel(double* W, int64_t n, int64_t ld, int64_t k0, int kb, int* piv,
+                    double* const B[2], double* const pmax[2], int* const pidx[2], hipStream_t s) {
+  int npart = ceil_div(n - k0, LU_UR);
+  hipLaunchKernelGGL(k_lu_panel_load, dim3(npart), dim3(64 * LU_UR), 0, s, W, n, ld, k0, kb, B[0],
+                     pmax[0], pidx[0]);
+  for (int st = 0; st < kb; ++st) {
+    const int64_t kk = k0 + st;
+    const int nb = std::min(ceil_div(n - kk, LU_UR), LU_STEP_BLOCKS);
+    hipLaunchKernelGGL(k_lu_step, dim3(nb), dim3(64 * LU_UR), 0, s, n, k0, kb, kk, B[st & 1],
+                       B[(st + 1) & 1], pmax[st & 1], pidx[st & 1], npart, pmax[(st + 1) & 1],
+                       pidx[(st + 1) & 1], piv);
+    npart = nb;
+  }
+  hipLaunchKernelGGL(k_lu_panel_store, dim3(ceil_div(n - k0, 4)), dim3(256), 0, s, W, n, ld, k0,
+                     kb, B[0], B[1]);
+  BEM_LAUNCH_CHECK();
+  return 0;
+}
+
+// Blocks of LU_OB = 2 panels share one trailing update with an inner
+// dimension of 128, so the trailing matrix is read and written once per 128
+// columns.  Inside a block each panel first updates the block's own columns
+// right of it; its row swaps also reach the multipliers of the block's
+// earlier panel, which the trailing update reads.
+constexpr int LU_OB = 2 * LU_B;
 static int lu_solve_augmented(double* W, int64_t n, int64_t ncol, int* piv, double* const B[2],
                               double* const pmax[2], int* const pidx[2], hipStream_t s) {
   const int64_t ld = ncol;
   int r;
-  for (int64_t k0 = 0; k0 < n; k0 += LU_B) {
-    const int kb = (int)std::min<int64_t>(LU_B, n - k0);
-    int npart = ceil_div(n - k0, LU_UR);
-    hipLaunchKernelGGL(k_lu_panel_load, dim3(npart), dim3(64 * LU_UR), 0, s, W, n, ld, k0, kb,
-                       B[0], pmax[0], pidx[0]);
-    for (int st = 0; st < kb; ++st) {
-      const int64_t kk = k0 + st;
-      const int nb = std::min(ceil_div(n - kk, LU_UR), LU_STEP_BLOCKS);
-      hipLaunchKernelGGL(k_lu_step, dim3(nb), dim3(64 * LU_UR), 0, s, n, k0, kb, kk,
-                         B[st & 1], B[(st + 1) & 1], pmax[st & 1], pidx[st & 1], npart,
-                         pmax[(st + 1) & 1], pidx[(st + 1) & 1], piv);
-      npart = nb;
+  for (int64_t K0 = 0; K0 < n; K0 += LU_OB) {
+    const int KB = (int)std::min<int64_t>(LU_OB, n - K0);
+    const int64_t K1 = K0 + KB;
+    for (int64_t k0 = K0; k0 < K1; k0 += LU_B) {
+      const int kb = (int)std::min<int64_t>(LU_B, K1 - k0);
+      if ((r = lu_panel(W, n, ld, k0, kb, piv, B, pmax, pidx, s))) return r;
+      if ((r = lu_swaps(W, ld, k0, kb, K0, k0, piv, s))) return r;
+      if ((r = lu_swaps(W, ld, k0, kb, k0 + kb, K1, piv, s))) return r;
+      if ((r = lu_trsm_lower(W, ld, k0, kb, k0 + kb, K1, s))) return r;
+      if ((r = lu_gemm(W, ld, k0 + kb, n, k0 + kb, K1, k0, kb, s))) return r;
     }
-    hipLaunchKernelGGL(k_lu_panel_store, dim3(ceil_div(n - k0, 4)), dim3(256), 0, s, W, n, ld, k0,
-                       kb, B[0], B[1]);
-    BEM_LAUNCH_CHECK();
-    const int64_t c0 = k0 + kb;
-    hipLaunchKernelGGL(k_lu_laswp, dim3(ceil_div(ncol - c0, 256)), dim3(256), 0, s, W, ld, k0,
-                       kb, c0, ncol, piv);
-    hipLaunchKernelGGL(k_lu_trsm_lower, dim3(ceil_div(ncol - c0, 64)), dim3(64), 0, s, W, ld,
-                       k0, kb, c0, ncol);
-    BEM_LAUNCH_CHECK();
-    if ((r = lu_gemm(W, ld, c0, n, c0, ncol, k0, kb, s))) return r;
+    // the block's swaps and L11^-1 on the trailing columns, then W22 -= L21 U12
+    if ((r = lu_swaps(W, ld, K0, KB, K1, ncol, piv, s))) return r;
+    for (int64_t k0 = K0; k0 < K1; k0 += LU_B) {
+      const int kb = (int)std::min<int64_t>(LU_B, K1 - k0);
+      if ((r = lu_trsm_lower(W, ld, k0, kb, K1, ncol, s))) return r;
+      if ((r = lu_gemm(W, ld, k0 + kb, K1, K1, ncol, k0, kb, s))) return r;
+    }
+    if ((r = lu_gemm(W, ld, K1, n, K1, ncol, K0, KB, s))) return r;
   }
   for (int64_t k0 = ((n - 1) / LU_B) * LU_B; k0 >= 0; k0 -= LU_B) {
     const int kb = (int)std::min<int64_t>(LU_B, n - k0);
-    hipLaunchKernelGGL(k_lu_trsm_upper, dim3(ceil_div(ncol - n, 256)), dim3(256), 0, s, W, ld,
+    hipLaunchKernelGGL(k_lu_trsm<true>, dim3(ceil_div(ncol - n, 256)), dim3(256), 0, s, W, ld,
                        k0, kb, n, ncol);
     BEM_LAUNCH_CHECK();
     if ((r = lu_gemm(W, ld, 0, k0, n, ncol, k0, kb, s))) return r;
