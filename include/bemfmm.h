@@ -488,14 +488,21 @@ int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls);
  * mu (mu > 0, 3 lambda + 2 mu > 0), density rho_s; fluid density rho_f;
  * angular frequency omega (> 0; the problem's k = omega / c_f).  At creation
  * the device assembles K - omega^2 M densely (3 n_nodes <= BEM_FEM_MAX_DOF
- * unknowns), solves it against the boundary load N by Gauss-Jordan
- * elimination with partial pivoting (in place of the paper's multi-frontal
- * factorisation) and keeps C = -rho_f omega^2 Tc (K - omega^2 M)^-1 N
+ * unknowns), solves it against the boundary load N by a blocked LU with
+ * partial pivoting (in place of the paper's multi-frontal factorisation)
+ * and keeps C = -rho_f omega^2 Tc (K - omega^2 M)^-1 N
  * (n_tri x n_tri, float64, row-major, the problem's element order): q = C p
  * is dp/dn on the fluid side for the boundary pressure p (momentum balance
- * dp/dn = rho_f omega^2 u.n at the collocation points).  BEM_E_INVALID for a
- * bad plan, problem, mesh, material or size; BEM_E_NAN when K - omega^2 M is
- * singular (omega^2 an eigenvalue of the free body). */
+ * dp/dn = rho_f omega^2 u.n at the collocation points), and its transpose
+ * for the adjoint (2 n_tri^2 doubles of device memory while the coupling
+ * lives; the factorisation's workspace, 8 (3 n_nodes) (3 n_nodes + n_tri)
+ * bytes, only during creation).  The coupling keeps a pointer to its plan's
+ * problem: destroy it before the plan.  Products and solves on one coupling
+ * share a work vector, so calls on different streams must not overlap.
+ * BEM_E_INVALID for a bad plan, problem, mesh, material or size; BEM_E_NAN
+ * when K - omega^2 M is singular to working precision (omega^2 an eigenvalue
+ * of the free body: C comes out non-finite; near such a frequency C is
+ * large but finite and is kept). */
 #define BEM_FEM_MAX_DOF 12288
 typedef struct bem_coupling bem_coupling;
 int bem_coupling_create(bem_plan* plan, int prob, const double* nodes, int64_t n_nodes,

@@ -3,7 +3,7 @@ Eqs. fem_2, renritupu, kousokuu, GMRES) against the oracle (oracle/fem.py
 with the dense BEM blocks of oracle/bem.py):
 
 * the coupling matrix C = -rho_f omega^2 Tc (K - omega^2 M)^-1 N built on
-  the device (dense assembly, Gauss-Jordan with partial pivoting) against
+  the device (dense assembly, blocked LU with partial pivoting) against
   the oracle's dense solve, on a tetrahedral ball whose boundary is the
   320-element sphere;
 * the coupled product Mp + Mq C in float64 and float32, with the
