@@ -232,6 +232,39 @@ def test_coupling_matrix_elastic_sphere_benchmark(n_shell):
     assert e < 1e-8 and es < 1e-8
 
 
+def test_coupling_on_the_second_problem_of_a_plan(ball):
+    """The body couples to problem 1 of a two-problem plan (problem 0 a
+    different mesh and wavenumber); its product matches the oracle's, and a
+    product on problem 0 is untouched by the coupling."""
+    import torch
+    bem = _lib()
+    nodes, tets, V, T = ball[:4]
+    g, C = ball[4], ball[5]
+    from workloads import icosphere
+    V0, T0 = icosphere(2)
+    plan = bem.Plan([bem.Problem(V0, T0, 3.0), bem.Problem(V, T, K_WAVE)])
+    cp = bem.Coupling(plan, nodes, tets, T, MAT["lam"], MAT["mu"], MAT["rho_s"], MAT["rho_f"],
+                      K_WAVE, prob=1)
+    Cg = cp.matrix().cpu().numpy()
+    assert float(np.max(np.abs(Cg - C)) / np.max(np.abs(C))) < 1e-10
+    Mp, Mq = obem.bm_blocks(g, K_WAVE, 1j / K_WAVE)
+    p = complex_normal(np.random.default_rng(13), len(T))
+    y = cp.matvec(torch.from_numpy(p)).cpu().numpy()
+    e = _rel(y, fem.coupled_operator(Mp, Mq, C) @ p)
+    g0 = obem.Geometry(V0, T0)
+    p0 = complex_normal(np.random.default_rng(14), len(T0))
+    y0 = plan.matvec(torch.from_numpy(p0), prob=0).cpu().numpy()
+    e0 = _rel(y0, obem.matvec(g0, 3.0, 1j / 3.0, p0))
+    _log(f"case: coupling on problem 1 of 2: rel err {e:.2e}; problem 0 product {e0:.2e}")
+    assert e < 1e-6 and e0 < 1e-6
+    pt = torch.from_numpy(p).cuda()
+    with pytest.raises(bem.BemError):
+        bem._check(bem._LIB.bem_coupling_apply(cp._h, 0, bem._ptr(pt), bem._ptr(pt),
+                                               bem._stream()))
+    cp.close()
+    plan.close()
+
+
 def test_bad_coupling_inputs_are_rejected(ball):
     bem = _lib()
     nodes, tets, V, T, g, C = ball
