@@ -556,6 +556,15 @@ __global__ void __launch_bounds__(256) k_real_matvec(const double* __restrict__ 
   }
 }
 
+// flag = 1 if any of the n values is not finite
+__global__ void k_any_nonfinite(const double* __restrict__ a, int64_t n, int* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(a[i]);
+  if (bad) *flag = 1;
+}
+
 int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int* tets_h,
                    int64_t n_tets, const int* tri_h, double lam, double mu, double rho_s,
                    double rho_f, double omega, DevArena& keep, double** C_out, double** Ct_out,
@@ -602,7 +611,20 @@ int coupling_build(Problem& P, const double* nodes_h, int64_t n_nodes, const int
   hipLaunchKernelGGL(k_transpose, dim3(ceil_div(ntri, 32), ceil_div(ntri, 32)), dim3(32, 8), 0, s,
                      *C_out, (int64_t)ntri, *Ct_out);
   BEM_LAUNCH_CHECK();
+  // a singular K - omega^2 M leaves C non-finite
+  int* flag;
+  ARENA_ALLOC(scratch, flag, 1);
+  BEM_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_any_nonfinite, dim3(1024), dim3(256), 0, s, *C_out, (int64_t)ntri * ntri,
+                     flag);
+  BEM_LAUNCH_CHECK();
+  int hflag = 0;
+  BEM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   BEM_HIP_TRY(hipStreamSynchronize(s));
+  if (hflag) {
+    set_error("K - omega^2 M is singular (omega^2 an eigenvalue of the free body)");
+    return BEM_E_NAN;
+  }
   return 0;
 }
 
