@@ -304,6 +304,17 @@ def run_elastic(args):
     log(f"[bench] elastic sphere: {dt * 1e3:.1f} ms per solve: plan {plan_s * 1e3:.1f}, "
         f"coupling (assembly, LU, C) {coup_s * 1e3:.1f}, GMRES {solve_s * 1e3:.2f} ms "
         f"({info['iterations']} iterations, residual {info['resid']:.2e})")
+    # the adjoint problem on the same plan and coupling (no new factorisation,
+    # Sec. 2.5): GMRES on the conjugate-transposed coupled operator
+    b_adj = plan.plane_wave_rhs(d)
+    cp.solve(b_adj, adjoint=True, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, ainfo = cp.solve(b_adj, adjoint=True, opts=opts)
+    torch.cuda.synchronize()
+    adj_s = time.perf_counter() - t0
+    log(f"[bench] adjoint solve on the same coupling: {adj_s * 1e3:.2f} ms "
+        f"({ainfo['iterations']} iterations)")
     # the dense coupling product alone (one kernel per call, 8 n^2 bytes of C
     # per launch): 200 launches captured in a HIP graph and replayed between
     # two HIP events on the stream, so that the launches run back to back
@@ -357,6 +368,7 @@ def run_elastic(args):
                    "poisson": E.poisson, "tol": 1e-5, "fmm_tol": fmm_tol},
         "parts_ms": {"plan": plan_s * 1e3, "coupling": coup_s * 1e3, "gmres": solve_s * 1e3},
         "gmres_iterations": info["iterations"],
+        "adjoint_gmres": {"ms": adj_s * 1e3, "iterations": ainfo["iterations"]},
         "coupling_product": {"us": apply_s * 1e6, "bytes": cbytes,
                              "GBps": cbytes / apply_s / 1e9},
         "matvec_us": {"coupled_f64": tm[0] * 1e6, "plain_f64": tm[1] * 1e6},
