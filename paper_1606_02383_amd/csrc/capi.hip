@@ -40,6 +40,8 @@ static void destroy_problem(Problem* P) {
   if (P->own_streams && P->side2) (void)hipStreamDestroy(P->side2);
   P->f64.ops.release();
   P->f32.ops.release();
+  P->f64.leafops.release();
+  P->f32.leafops.release();
   P->arena.release();
   delete P;
 }
@@ -520,7 +522,8 @@ int bem_plan_get_stats(const bem_plan* plan, int prob, bem_plan_stats* st) {
     st->order32[l] = P->f32.order[l];
     st->box_size[l] = P->h[l];
   }
-  st->device_bytes = P->arena.bytes + P->f64.ops.bytes + P->f32.ops.bytes;
+  st->device_bytes = P->arena.bytes + P->f64.ops.bytes + P->f32.ops.bytes +
+                     P->f64.leafops.bytes + P->f32.leafops.bytes;
   st->fmm_err64 = P->direct ? 0.0 : P->f64.err;
   st->fmm_err32 = P->direct ? 0.0 : P->f32.err;
   st->fmm_err64_smooth = P->direct ? 0.0 : P->f64.err_smooth;

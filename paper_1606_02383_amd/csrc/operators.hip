@@ -933,9 +933,12 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     D.n_direct = d;
   }
   D.cbuf_count = cbuf_count;
-  // ---- P2M and L2P per element ----
-  {
+  // ---- P2M and L2P per element (kept while the leaf order stays) ----
+  if (D.leaf_order != D.order[L] || !D.p2m) {
     int p = D.order[L];
+    D.leafops.release();
+    D.p2m = D.p2m_p = D.l2p = nullptr;
+    D.leaf_order = -1;
     int P1 = (p + 2) * (p + 2);
     int Pc = (p + 1) * (p + 1);
     std::vector<double> gc;
@@ -954,8 +957,8 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     BEM_HIP_TRY(hipMemcpyAsync(dgc, gc.data(), sizeof(double) * gc.size(), hipMemcpyHostToDevice, s));
     BEM_HIP_TRY(hipMemcpyAsync(dfinv, finv.data(), sizeof(double) * (p + 1), hipMemcpyHostToDevice, s));
     BEM_HIP_TRY(hipMemcpyAsync(dlo, P.lo, sizeof(double) * 3, hipMemcpyHostToDevice, s));
-    ARENA_ALLOC(D.ops, D.p2m, (int64_t)P.n * Pc * 2);
-    ARENA_ALLOC(D.ops, D.l2p, (int64_t)P.n * Pc);
+    ARENA_ALLOC(D.leafops, D.p2m, (int64_t)P.n * Pc * 2);
+    ARENA_ALLOC(D.leafops, D.l2p, (int64_t)P.n * Pc);
     int64_t chunk = 16384;
     c64* Rbuf;
     double* tmpb;
@@ -968,11 +971,12 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
                          dgc, dfinv, Rbuf, tmpb, D.p2m, D.l2p);
       BEM_LAUNCH_CHECK();
     }
-    ARENA_ALLOC(D.ops, D.p2m_p, (int64_t)P.n * Pc);
+    ARENA_ALLOC(D.leafops, D.p2m_p, (int64_t)P.n * Pc);
     hipLaunchKernelGGL(k_p_columns<R>, dim3(ceil_div((int64_t)P.n * Pc, 256)), dim3(256), 0, s,
                        D.p2m, (int64_t)P.n * Pc, D.p2m_p);
     BEM_LAUNCH_CHECK();
     BEM_HIP_TRY(hipStreamSynchronize(s));
+    D.leaf_order = p;
   }
   return 0;
 }
@@ -1015,7 +1019,6 @@ int rebuild_precision(Problem& P, PrecisionData<R>& D, int shift_c, int shift_l,
   D.l2l_dir = keep.l2l_dir;
   D.cbuf_off = keep.cbuf_off;
   D.cbuf_count = D.cbufL_count = 0;
-  D.p2m = D.p2m_p = D.l2p = nullptr;
   D.X = ExecBuf<R>{};
   D.shift = shift_l;
   D.shift_c = shift_c;

@@ -151,9 +151,13 @@ struct ExecBuf {
 template <typename R>
 struct PrecisionData {
   // device memory of everything that depends on the expansion orders (the
-  // operators, tiles, reduction lists, P2M/L2P matrices and the product
-  // buffers X): released and rebuilt when the orders are recalibrated
+  // operators, tiles, reduction lists and the product buffers X): released
+  // and rebuilt when the orders or the far cut are recalibrated
   DevArena ops;
+  // the P2M/L2P matrices, which depend on the leaf order alone: kept across
+  // rebuilds while that order stays (leaf_order: the order they hold)
+  DevArena leafops;
+  int leaf_order = -1;
   int shift = 0;       // order shifts applied to the level rule (calibration):
   int shift_c = 0;     //   the leaf level's and the coarser levels'
   // orders dropped from the multipole side of M2L translations across three
