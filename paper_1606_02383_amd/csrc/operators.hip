@@ -771,9 +771,25 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
   // ---- M2L: one matrix per offset present at each level ----
   int64_t cbuf_count = 0;
   for (int l = 2; l <= L; ++l) {
-    int *d0, *s0, *c0, np = 0;
-    int r = build_vlist(P, l, &d0, &s0, &c0, &np, scratch, s);
-    if (r) return r;
+    if (P.vl_n[l] < 0) {  // the tree's V-list of this level, once per problem
+      int *vd, *vs, *vc, nv = 0;
+      int r = build_vlist(P, l, &vd, &vs, &vc, &nv, scratch, s);
+      if (r) return r;
+      ARENA_ALLOC(P.arena, P.vl_dst[l], std::max(nv, 1));
+      ARENA_ALLOC(P.arena, P.vl_src[l], std::max(nv, 1));
+      ARENA_ALLOC(P.arena, P.vl_code[l], std::max(nv, 1));
+      if (nv > 0) {
+        BEM_HIP_TRY(hipMemcpyAsync(P.vl_dst[l], vd, sizeof(int) * nv, hipMemcpyDeviceToDevice, s));
+        BEM_HIP_TRY(hipMemcpyAsync(P.vl_src[l], vs, sizeof(int) * nv, hipMemcpyDeviceToDevice, s));
+        BEM_HIP_TRY(hipMemcpyAsync(P.vl_code[l], vc, sizeof(int) * nv, hipMemcpyDeviceToDevice, s));
+      }
+      P.vl_n[l] = nv;
+    }
+    int* d0 = P.vl_dst[l];
+    int* s0 = P.vl_src[l];
+    int* c0 = P.vl_code[l];
+    const int np = P.vl_n[l];
+    int r = 0;
     P.n_m2l[l] = np;
     int p = D.order[l];
     // present offsets

@@ -148,6 +148,13 @@ struct ExecBuf {
   c64* q64s = nullptr;
 };
 
+template <typename T, size_t N>
+constexpr std::array<T, N> filled_array(T v) {
+  std::array<T, N> a{};
+  for (size_t i = 0; i < N; ++i) a[i] = v;
+  return a;
+}
+
 template <typename R>
 struct PrecisionData {
   // device memory of everything that depends on the expansion orders (the
@@ -244,6 +251,10 @@ struct Problem {
   std::array<double, MAX_LEVEL + 1> h{};          // box side per level
   std::array<int64_t, MAX_LEVEL + 1> n_m2l{};
   std::array<int64_t, MAX_LEVEL + 1> n_m2l_far{};  // of them across three boxes
+  // V-list pairs per level (destination box, source box, offset code), built
+  // once from the tree on first use (vl_n < 0: not yet)
+  std::array<int*, MAX_LEVEL + 1> vl_dst{}, vl_src{}, vl_code{};
+  std::array<int, MAX_LEVEL + 1> vl_n = filled_array<int, MAX_LEVEL + 1>(-1);
   int* elem_leaf = nullptr;                        // sorted element -> leaf
   int* u_ptr = nullptr;                            // leaf U lists (CSR)
   int* u_idx = nullptr;
