@@ -195,8 +195,9 @@ __global__ void __launch_bounds__(64 * LU_UR) k_lu_panel_load(const double* __re
 // values, every row below keeps its multiplier l = W[i][kk] / pivot in
 // column kk and updates the columns right of kk; while column kk + 1 is in
 // the panel each block leaves its best candidate (rows > kk) for it.  At
-// most LU_STEP_BLOCKS blocks, so that one round of them fills the chip.
-constexpr int LU_STEP_BLOCKS = 1024;
+// most LU_STEP_BLOCKS blocks (two per CU: fewer candidates for every block
+// to reduce; 256 and 1024 measured slower).
+constexpr int LU_STEP_BLOCKS = 512;
 __global__ void __launch_bounds__(64 * LU_UR) k_lu_step(
     int64_t n, int64_t k0, int kb, int64_t kk, const double* __restrict__ Pin,
     double* __restrict__ Pout, const double* __restrict__ pin_max,
