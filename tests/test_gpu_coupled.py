@@ -20,7 +20,9 @@ with the dense BEM blocks of oracle/bem.py):
   panels of the blocked factorisation) and a finer body near the size
   limit (11559 unknowns): sampled columns of C against
   sparse solves of the oracle's K - omega^2 M and N, and the symmetry of
-  C diag(1 / area) over the whole matrix;
+  C diag(1 / area) over the whole matrix; the benchmark's solve as the
+  bench times it (alpha = 0, tolerances 1e-5) against LU of the oracle's
+  dense system, in the paper's 3 iterations;
 * bad meshes, materials and sizes are rejected on the host.
 """
 import numpy as np
@@ -230,6 +232,38 @@ def test_coupling_matrix_elastic_sphere_benchmark(n_shell):
     es = float(np.max(np.abs(S - S.T)) / np.max(np.abs(S)))
     _log(f"  sampled columns: max rel diff {e:.2e}; asymmetry of C / area {es:.2e}")
     assert e < 1e-8 and es < 1e-8
+
+
+def test_elastic_sphere_solve_as_benchmarked():
+    """The elastic-sphere benchmark in the configuration the bench times
+    (alpha = 0, the paper's Eq. GMRES; FMM and GMRES tolerances 1e-5):
+    forward and adjoint solutions against LU of the oracle's dense coupled
+    system (its dense coupling matrix), and the iteration
+    count the paper reports for this sphere (3, Table 4)."""
+    bem = _lib()
+    E = ELASTIC_SPHERE
+    nodes, tets, V, T = E.mesh()
+    plan = bem.Plan(bem.Problem(V, T, E.omega, alpha=0.0, fmm_tol=1e-5))
+    cp = bem.Coupling(plan, nodes, tets, T, E.lam, E.mu, E.rho_s, E.rho_f, E.omega)
+    b = plan.plane_wave_rhs(np.array(E.direction))
+    opts = bem.GmresOptions(tol=1e-5, restart=50)
+    x, info = cp.solve(b, opts=opts)
+    xa, infa = cp.solve(b, adjoint=True, opts=opts)
+    C = fem.coupling_matrix(nodes, tets, T, E.lam, E.mu, E.rho_s, E.rho_f, E.omega)
+    g = obem.Geometry(V, T)
+    Mp, Mq = obem.bm_blocks(g, E.omega, 0.0)
+    Ad = fem.coupled_operator(Mp, Mq, C)
+    bd = obem.plane_wave_rhs(g, E.omega, 0.0, np.array(E.direction))
+    assert _rel(b.cpu().numpy(), bd) < 1e-12
+    e = _rel(x.cpu().numpy(), np.linalg.solve(Ad, bd))
+    ea = _rel(xa.cpu().numpy(), np.linalg.solve(Ad.conj().T, bd))
+    _log(f"case: elastic sphere as benchmarked: {info['iterations']} iterations, err {e:.2e}; "
+         f"adjoint {infa['iterations']} iterations, err {ea:.2e}")
+    assert info["converged"] and infa["converged"]
+    assert info["iterations"] <= 4
+    assert e < 1e-4 and ea < 1e-4
+    cp.close()
+    plan.close()
 
 
 def test_coupling_on_the_second_problem_of_a_plan(ball):
