@@ -22,7 +22,10 @@ It computes, plainly and slowly, in complex128:
                J = sum |p(x_obs)|^2 and its discrete-adjoint gradient;
 * ``fem``    - linear-tetrahedron stiffness and mass of the elastic body, the
                boundary coupling and the Schur form of the BEM-FEM system
-               (Eqs. fem_2, renritupu, kousokuu, GMRES).
+               (Eqs. fem_2, renritupu, kousokuu, GMRES);
+* ``elastic_sphere`` - plane-wave scattering by an elastic sphere in a
+               fluid, the partial-wave series from the governing equations
+               (the analytic check of Sec. 3.1).
 
 Paper anchors (Isakari, Kondo, Takahashi, Matsumoto, "A level-set-based
 topology optimisation for acoustic-elastic coupled problems with a fast
