@@ -503,7 +503,7 @@ int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls);
  * when K - omega^2 M is singular to working precision (omega^2 an eigenvalue
  * of the free body: C comes out non-finite; near such a frequency C is
  * large but finite and is kept). */
-#define BEM_FEM_MAX_DOF 12288
+#define BEM_FEM_MAX_DOF 24576
 typedef struct bem_coupling bem_coupling;
 int bem_coupling_create(bem_plan* plan, int prob, const double* nodes, int64_t n_nodes,
                         const int32_t* tets, int64_t n_tets, const int32_t* tri, double lambda,

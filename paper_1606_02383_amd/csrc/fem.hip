@@ -14,10 +14,10 @@
 // here the plan-time step assembles it densely on the device and solves
 // (K - omega^2 M) X = N by a blocked LU with partial pivoting of the
 // augmented matrix [A | N] (trailing updates on the matrix cores) and
-// blocked back substitution, then forms C once (n_tri^2
-// doubles, and its transpose for the adjoint); each product then costs one
-// dense real-by-complex matrix-vector product besides the FMM.  Dense storage limits the body to BEM_FEM_MAX_DOF
-// unknowns.
+// blocked back substitution, then forms C once (n_tri^2 doubles, and its
+// transpose for the adjoint); each product then costs one dense
+// real-by-complex matrix-vector product besides the FMM.  Dense storage
+// limits the body to BEM_FEM_MAX_DOF unknowns.
 #include <algorithm>
 #include <climits>
 #include <cmath>

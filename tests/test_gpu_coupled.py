@@ -17,8 +17,8 @@ with the dense BEM blocks of oracle/bem.py):
 * rigid limit: an ever stiffer and heavier body gives the sound-hard
   solution;
 * the elastic-sphere benchmark (tungsten in water, 9633 unknowns, 151
-  panels of the blocked factorisation) and a finer body near the size
-  limit (11559 unknowns): sampled columns of C against
+  panels of the blocked factorisation) and finer bodies up to near the
+  size limit (11559 and 23061 unknowns): sampled columns of C against
   sparse solves of the oracle's K - omega^2 M and N, and the symmetry of
   C diag(1 / area) over the whole matrix; the benchmark's solve as the
   bench times it (alpha = 0, tolerances 1e-5) against LU of the oracle's
@@ -204,16 +204,17 @@ def test_rigid_limit_gives_the_sound_hard_solution(ball):
     plan.close()
 
 
-@pytest.mark.parametrize("n_shell", [5, 6])
-def test_coupling_matrix_elastic_sphere_benchmark(n_shell):
-    """5 shells: the benchmark's body; 6 shells: 11559 unknowns, near the
-    size limit (ragged last panels of 33 and 39 columns)."""
+@pytest.mark.parametrize("level,n_shell", [(3, 5), (3, 6), (4, 3)])
+def test_coupling_matrix_elastic_sphere_benchmark(level, n_shell):
+    """1280 triangles and 5 shells: the benchmark's body (9633 unknowns);
+    6 shells: 11559 unknowns; 5120 triangles and 3 shells: 23061 unknowns,
+    near the size limit (ragged last panels of 33, 39 and 21 columns)."""
     import dataclasses
 
     import scipy.sparse as sps
     import scipy.sparse.linalg as spla
     bem = _lib()
-    E = dataclasses.replace(ELASTIC_SPHERE, n_shell=n_shell)
+    E = dataclasses.replace(ELASTIC_SPHERE, level=level, n_shell=n_shell)
     nodes, tets, V, T = E.mesh()
     _log(f"case: elastic sphere, {len(nodes)} nodes ({3 * len(nodes)} unknowns), "
          f"{len(T)} boundary triangles")
@@ -365,7 +366,7 @@ def test_bad_coupling_inputs_are_rejected(ball):
         bem.Coupling(plan, nodes, tets, T, 20.0, -1.0, 1.5, 1.0, K_WAVE)
     with pytest.raises(bem.BemError):
         bem.Coupling(plan, nodes, tets, T, 20.0, 10.0, 1.5, 1.0, 0.0)
-    big, btets, _, _ = ball_mesh(3, 8)     # 3 x 5137 unknowns > BEM_FEM_MAX_DOF
+    big, btets, _, _ = ball_mesh(4, 4)     # 3 x 10249 unknowns > BEM_FEM_MAX_DOF
     with pytest.raises(bem.BemError):
         bem.Coupling(plan, big, btets, T, 20.0, 10.0, 1.5, 1.0, K_WAVE)
     plan.close()
