@@ -711,6 +711,30 @@ int bem_coupling_create(bem_plan* plan, int prob, const double* nodes, int64_t n
     if (tets[i] < 0 || tets[i] >= n_nodes) return fail(BEM_E_INVALID, "tetrahedron node out of range");
   for (int64_t i = 0; i < 3 * P->n; ++i)
     if (tri[i] < 0 || tri[i] >= n_nodes) return fail(BEM_E_INVALID, "triangle node out of range");
+  // degenerate elements would reach the device as a zero Jacobian
+  auto sub = [&](int32_t a, int32_t b, double* d) {
+    for (int c = 0; c < 3; ++c) d[c] = nodes[3 * (int64_t)b + c] - nodes[3 * (int64_t)a + c];
+  };
+  for (int64_t e = 0; e < n_tets; ++e) {
+    const int32_t* t = tets + 4 * e;
+    double u[3], v[3], w[3];
+    sub(t[0], t[1], u);
+    sub(t[0], t[2], v);
+    sub(t[0], t[3], w);
+    const double det = u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) +
+                       u[2] * (v[0] * w[1] - v[1] * w[0]);
+    if (!(std::fabs(det) > 0.0)) return fail(BEM_E_INVALID, "tetrahedron of zero volume");
+  }
+  for (int64_t j = 0; j < P->n; ++j) {
+    const int32_t* t = tri + 3 * j;
+    double u[3], v[3];
+    sub(t[0], t[1], u);
+    sub(t[0], t[2], v);
+    const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2],
+                 cz = u[0] * v[1] - u[1] * v[0];
+    if (!(cx * cx + cy * cy + cz * cz > 0.0))
+      return fail(BEM_E_INVALID, "boundary triangle of zero area");
+  }
   hipStream_t s = (hipStream_t)stream;
   bem_coupling* c = new bem_coupling();
   c->P = P;

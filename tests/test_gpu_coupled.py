@@ -364,6 +364,14 @@ def test_bad_coupling_inputs_are_rejected(ball):
         bem.Coupling(plan, nodes, bad, T, 20.0, 10.0, 1.5, 1.0, K_WAVE)
     with pytest.raises(bem.BemError):
         bem.Coupling(plan, nodes, tets, T, 20.0, -1.0, 1.5, 1.0, K_WAVE)
+    flat = tets.copy()
+    flat[0, 1] = flat[0, 0]                # a tetrahedron of zero volume
+    with pytest.raises(bem.BemError, match="zero volume"):
+        bem.Coupling(plan, nodes, flat, T, 20.0, 10.0, 1.5, 1.0, K_WAVE)
+    thin = T.copy()
+    thin[0, 2] = thin[0, 1]                # a boundary triangle of zero area
+    with pytest.raises(bem.BemError, match="zero area"):
+        bem.Coupling(plan, nodes, tets, thin, 20.0, 10.0, 1.5, 1.0, K_WAVE)
     with pytest.raises(bem.BemError):
         bem.Coupling(plan, nodes, tets, T, 20.0, 10.0, 1.5, 1.0, 0.0)
     big, btets, _, _ = ball_mesh(4, 4)     # 3 x 10249 unknowns > BEM_FEM_MAX_DOF
