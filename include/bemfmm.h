@@ -499,7 +499,8 @@ int bem_profile_stop(bem_plan* plan, int prob, double* ms, int32_t* calls);
  * bytes, only during creation).  The coupling keeps a pointer to its plan's
  * problem: destroy it before the plan.  Products and solves on one coupling
  * share a work vector, so calls on different streams must not overlap.
- * BEM_E_INVALID for a bad plan, problem, material or size, or a mesh with
+ * BEM_E_INVALID for a bad plan, problem (more than 65535 triangles),
+ * material or size, or a mesh with
  * an index out of range, a tetrahedron of zero volume or a boundary
  * triangle of zero area; BEM_E_NAN
  * when K - omega^2 M is singular to working precision (omega^2 an eigenvalue

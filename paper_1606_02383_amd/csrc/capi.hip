@@ -698,6 +698,8 @@ int bem_coupling_create(bem_plan* plan, int prob, const double* nodes, int64_t n
   *out = nullptr;
   if (!nodes || !tets || !tri || n_nodes < 4 || n_tets < 1)
     return fail(BEM_E_INVALID, "empty or missing solid mesh");
+  if (P->n > 65535)  // dense C and C^T (16 n_tri^2 bytes); one launch row per triangle
+    return fail(BEM_E_INVALID, "problem too large for a dense coupling matrix (n_tri > 65535)");
   if (3 * n_nodes > BEM_FEM_MAX_DOF)
     return fail(BEM_E_INVALID, "solid mesh too large for the dense factorisation (3 n_nodes > " +
                                    std::to_string(BEM_FEM_MAX_DOF) + ")");

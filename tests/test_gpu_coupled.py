@@ -354,6 +354,18 @@ def test_coupling_on_the_second_problem_of_a_plan(ball):
     plan.close()
 
 
+def test_coupling_rejects_a_boundary_beyond_the_dense_limit():
+    """More than 65535 boundary triangles (the 81920-element sphere): the
+    dense C and C^T would need 107 GB; refused before any device work."""
+    bem = _lib()
+    from workloads import icosphere
+    V6, T6 = icosphere(6)
+    plan = bem.Plan(bem.Problem(V6, T6, 1.0))
+    with pytest.raises(bem.BemError, match="65535"):
+        bem.Coupling(plan, V6, np.array([[0, 1, 2, 3]]), T6, 20.0, 10.0, 1.5, 1.0, 1.0)
+    plan.close()
+
+
 def test_bad_coupling_inputs_are_rejected(ball):
     bem = _lib()
     nodes, tets, V, T, g, C = ball
