@@ -42,6 +42,8 @@ static void destroy_problem(Problem* P) {
   P->f32.ops.release();
   P->f64.leafops.release();
   P->f32.leafops.release();
+  P->f64.release_tcache();
+  P->f32.release_tcache();
   P->arena.release();
   delete P;
 }
@@ -376,6 +378,8 @@ int calibrate_orders(Problem& P, hipStream_t s) {
   int r = calibrate_one<double>(P, P.f64, P.fmm_tol64, true, s);
   if (!r) r = calibrate_one<float>(P, P.f32, P.fmm_tol32, false, s);
   if (!r && !(P.fmm_tol32 > 0) && P.order32_req <= 0) r = cut_far_relative<float>(P, P.f32, s);
+  P.f64.release_tcache();
+  P.f32.release_tcache();
   return r;
 }
 

@@ -449,6 +449,41 @@ static int make_translations(Problem& P, DevArena& keep, int ngroups,
   return 0;
 }
 
+// make_translations into D.ops through the precision's cache: the matrices
+// are a function of the arguments (k is the problem's), so a build whose
+// arguments equal the cached entry's copies that entry instead
+template <typename R>
+static int cached_translations(Problem& P, PrecisionData<R>& D, int key, int ngroups,
+                               const std::vector<double>& tv, int sing, int pin, int pout,
+                               const std::vector<double>& rs, const std::vector<double>& cs,
+                               cplx<R>** mats, DevArena& scratch, hipStream_t s) {
+  auto& e = D.tcache[key];
+  if (!(e.mats && e.ngroups == ngroups && e.sing == sing && e.pin == pin && e.pout == pout &&
+        e.tv == tv && e.rs == rs && e.cs == cs)) {
+    e.arena.release();
+    e.mats = nullptr;
+    e.ngroups = -1;
+    int r = make_translations<R>(P, e.arena, ngroups, tv, sing, pin, pout, rs, cs, &e.mats,
+                                 scratch, s);
+    if (r) {
+      e.arena.release();
+      e.mats = nullptr;
+      return r;
+    }
+    e.ngroups = ngroups;
+    e.sing = sing;
+    e.pin = pin;
+    e.pout = pout;
+    e.tv = tv;
+    e.rs = rs;
+    e.cs = cs;
+  }
+  const int64_t cnt = (int64_t)ngroups * (pin + 1) * (pin + 1) * (pout + 1) * (pout + 1);
+  ARENA_ALLOC(D.ops, *mats, cnt);
+  BEM_HIP_TRY(hipMemcpyAsync(*mats, e.mats, sizeof(cplx<R>) * cnt, hipMemcpyDeviceToDevice, s));
+  return 0;
+}
+
 // Expansion order of a level: ceil(k sqrt(3) h) + extra, at least `base`;
 // req > 0 fixes it, req < 0 replaces the minimum by -req.
 // shift (calibration) moves both terms; the result lies in [1, pmax].
@@ -821,7 +856,7 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     if (ns > 0) {
       // L~ = f_n' (S|R) M~ f_n  (locals times f, multipoles over f)
       std::vector<double> rs = coef_scale(p, k * P.h[l], +1), cs = coef_scale(p, k * P.h[l], +1);
-      r = make_translations<R>(P, D.ops, ns, tv, 1, p, p, rs, cs, &op.mats, scratch, s);
+      r = cached_translations<R>(P, D, 0 * 64 + l, ns, tv, 1, p, p, rs, cs, &op.mats, scratch, s);
       if (r) return r;
       r = cut_far_translations<R>(op, p, D.far_cut, N_OFFSETS, 7, slot, D.ops, scratch, s);
       if (r) return r;
@@ -874,7 +909,8 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     mm.cols = D.ncoef[l];
     mm.n_slots = 8;
     std::vector<double> rs = coef_scale(pp, k * P.h[l - 1], -1), cs = coef_scale(pc, k * P.h[l], +1);
-    int r = make_translations<R>(P, D.ops, 8, tv_m2m, 0, pc, pp, rs, cs, &mm.mats, scratch, s);
+    int r = cached_translations<R>(P, D, 1 * 64 + l, 8, tv_m2m, 0, pc, pp, rs, cs, &mm.mats,
+                                   scratch, s);
     if (r) return r;
     r = finish_grouped<R>(mm, d0, s0, c0, nb, 8, slot, D.ops, scratch, s);
     if (r) return r;
@@ -885,7 +921,8 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     ll.n_slots = 8;
     rs = coef_scale(pc, k * P.h[l], +1);
     cs = coef_scale(pp, k * P.h[l - 1], -1);
-    r = make_translations<R>(P, D.ops, 8, tv_l2l, 0, pp, pc, rs, cs, &ll.mats, scratch, s);
+    r = cached_translations<R>(P, D, 2 * 64 + l, 8, tv_l2l, 0, pp, pc, rs, cs, &ll.mats, scratch,
+                               s);
     if (r) return r;
     r = finish_grouped<R>(ll, s0, d0, c0, nb, 8, slot, D.ops, scratch, s);
     if (r) return r;
@@ -931,7 +968,8 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     mu.cols = D.ncoef[L];
     mu.n_slots = ng;
     std::vector<double> rs = coef_scale(pa, k * P.h[a], -1), cs = coef_scale(pL, k * P.h[L], +1);
-    int r = make_translations<R>(P, D.ops, ng, tv_up, 0, pL, pa, rs, cs, &mu.mats, scratch, s);
+    int r = cached_translations<R>(P, D, 3 * 64 + a, ng, tv_up, 0, pL, pa, rs, cs, &mu.mats,
+                                   scratch, s);
     if (r) return r;
     // few pairs per position code: 16-pair tiles (all depths share a launch)
     r = finish_grouped<R>(mu, d0, s0, c0, nb, ng, slot, D.ops, scratch, s, 16);
@@ -942,7 +980,8 @@ static int build_precision(Problem& P, PrecisionData<R>& D, bool is64, DevArena&
     ld.n_slots = ng;
     rs = coef_scale(pL, k * P.h[L], +1);
     cs = coef_scale(pa, k * P.h[a], -1);
-    r = make_translations<R>(P, D.ops, ng, tv_down, 0, pa, pL, rs, cs, &ld.mats, scratch, s);
+    r = cached_translations<R>(P, D, 4 * 64 + a, ng, tv_down, 0, pa, pL, rs, cs, &ld.mats,
+                               scratch, s);
     if (r) return r;
     r = finish_grouped<R>(ld, s0, d0, c0, nb, ng, slot, D.ops, scratch, s, 16);
     if (r) return r;

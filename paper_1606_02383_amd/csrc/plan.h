@@ -5,6 +5,7 @@
 
 #include <array>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -165,6 +166,21 @@ struct PrecisionData {
   // rebuilds while that order stays (leaf_order: the order they hold)
   DevArena leafops;
   int leaf_order = -1;
+  // translation matrices of the last build, per operator set (key: kind and
+  // level), with everything they are made from: a rebuild whose inputs match
+  // (the far-cut trials of the calibration) copies them instead of
+  // recomputing; released once the calibration ends
+  struct TransCacheEntry {
+    int ngroups = -1, sing = -1, pin = -1, pout = -1;
+    std::vector<double> tv, rs, cs;
+    DevArena arena;
+    cplx<R>* mats = nullptr;
+  };
+  std::map<int, TransCacheEntry> tcache;
+  void release_tcache() {
+    for (auto& kv : tcache) kv.second.arena.release();
+    tcache.clear();
+  }
   int shift = 0;       // order shifts applied to the level rule (calibration):
   int shift_c = 0;     //   the leaf level's and the coarser levels'
   // orders dropped from the multipole side of M2L translations across three
